@@ -1,0 +1,179 @@
+/*
+ * mpfc.h -- C ABI of libmpfc.so: the implicit time step of the two
+ * energy-stable convex-splitting schemes for the modified phase field crystal
+ * (MPFC) equation, solved by nonlinear FAS multigrid on one AMD Instinct
+ * MI355X (gfx950) GPU.
+ *
+ * Paper: Baskaran, Zhou, Hu, Wang, Wise, Lowengrub, "Energy stable and
+ * efficient finite-difference nonlinear multigrid schemes for the modified
+ * phase field crystal equation".
+ *
+ * The problem (Sec. 3.1, Sec. 3.2, App. B): given phi^k, psi^k (and phi^{k-1}
+ * for the second-order scheme) on a periodic m x n cell-centred grid with
+ * spacing h, find phi^{k+1}, mu, kappa solving N(u) = S (App. B.1, B.2) and
+ * then psi^{k+1} (eq. discrete_1_b or discrete_2_b).
+ *
+ * Conventions for every entry point:
+ *  - Grid functions are contiguous arrays of m*n values, row-major with x
+ *    fastest: cell (i, j) at index j*m + i.  m and n are powers of two.
+ *  - Pointers named d_* are device pointers (hipMalloc'd or from a PyTorch
+ *    tensor), owned by the caller, and must stay valid until the call
+ *    returns.  Pointers named h_* are host pointers owned by the caller.
+ *  - `stream` is a hipStream_t (NULL = default stream) passed as void*;
+ *    all device work of a call is ordered on it.
+ *  - Return value: 0 (MPFC_OK) or a negative MPFC_E* code; no exception
+ *    crosses the ABI.  Argument errors are detected on the host before any
+ *    HIP call.  mpfc_strerror() names a code; mpfc_last_error() gives the
+ *    detail of the last failure on the calling thread.
+ */
+#ifndef MPFC_H
+#define MPFC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPFC_VERSION 1
+
+enum {
+    MPFC_OK = 0,
+    MPFC_EINVAL = -1,        /* invalid argument (checked on the host) */
+    MPFC_ENOTCONVERGED = -2, /* cycle limit reached; outputs hold the last iterate */
+    MPFC_ENONFINITE = -3,    /* NaN/Inf residual; outputs hold the last iterate */
+    MPFC_EDIVERGED = -4,     /* residual grew by the divergence factor */
+    MPFC_ENOMEM = -5,        /* device allocation failed */
+    MPFC_EHIP = -6           /* a HIP runtime call failed */
+};
+
+enum { MPFC_FP64 = 0, MPFC_MIXED = 1 };                           /* precision */
+enum { MPFC_GUESS_PREV = 0, MPFC_GUESS_EXTRAP = 1 };              /* initial guess */
+enum { MPFC_NEWTON = 0, MPFC_PICARD = 1 };                        /* linearisation */
+
+/* Model and discretisation (Sec. 2, Sec. 3): alpha = 1 - eps; dt is the time
+ * step s.  scheme 1: first-order convex splitting (Sec. 3.1); scheme 2:
+ * second-order scheme (Sec. 3.2).  Requires h > 0, dt > 0, M > 0, beta >= 0,
+ * eps <= 1. */
+typedef struct {
+    double eps, beta, M, h, dt;
+    int scheme;
+} mpfc_params;
+
+/* Solver options.  nu1/nu2: pre/post red-black smoothing passes per level
+ * (App. B "l_max"); tol: stop when the finest residual norm
+ * sqrt(h^2 sum_c sum_ij r_c^2) <= tol; max_cycles: V-cycle limit;
+ * coarsest: side of the coarsest grid (2 or 4; the coarsest grid is solved
+ * by dense Newton and must hold at most 16 cells); energy: 1 to compute the
+ * energies of Sec. 3 after each step; diverge: factor of residual growth
+ * over the initial residual reported as MPFC_EDIVERGED. */
+typedef struct {
+    int nu1, nu2, max_cycles;
+    double tol;
+    int precision, guess, linearization;
+    int coarsest;
+    int energy;
+    double diverge;
+} mpfc_opts;
+
+/* Per-step report.  residual_history is a caller-owned host array of
+ * max_cycles + 1 doubles (may be NULL): entry 0 is the norm of the initial
+ * guess's residual, entry k the norm after V-cycle k.  Energies (Sec. 3):
+ * energy_F = F(phi^{k+1}) (eq. discrete_energy_PFC), energy_pseudo =
+ * F + ||psi^{k+1}||_{-1}^2/(2M) (eq. discrete_energy_MPFC), energy_mod =
+ * energy_pseudo + ||grad_h(phi^{k+1} - phi^k)||^2/2 (eq. energy_numer),
+ * mass = h^2 sum phi^{k+1}. */
+typedef struct {
+    double energy_F, energy_pseudo, energy_mod, mass;
+    double residual;     /* last residual norm */
+    int n_cycles;        /* V-cycles run */
+    int status;          /* return code of the step */
+    int outer_iters;     /* mixed precision: FP64 defect-correction iterations */
+    int pad;
+    double *residual_history;
+} mpfc_info;
+
+typedef struct mpfc_ctx mpfc_ctx;
+
+/* Default options: V(2,2), tol 1e-10, 100 cycles, FP64, extrapolated guess,
+ * Newton linearisation, coarsest 2, energies on, divergence factor 1e8. */
+void mpfc_default_opts(mpfc_opts *o);
+
+/* Host-only validation of a configuration (no HIP call). */
+int mpfc_validate(int m, int n, const mpfc_params *p, const mpfc_opts *o);
+
+/* Create a solver context for an m x n grid: allocates the multigrid level
+ * hierarchy and all workspace on the current HIP device.  *out receives the
+ * context (owned by the caller, released by mpfc_destroy).  `stream` orders
+ * all later work of the context. */
+int mpfc_create(mpfc_ctx **out, int m, int n, const mpfc_params *p, const mpfc_opts *o,
+                void *stream);
+
+/* One time step (Sec. 3.1 / 3.2 with App. B).
+ *   d_phi_n    phi^k (read)
+ *   d_phi_nm1  phi^{k-1} (read; scheme 2 only; NULL means phi^{k-1} = phi^k,
+ *              the start-up rule of Sec. 3.2)
+ *   d_psi      psi^k on entry, psi^{k+1} on return (required: for scheme 2
+ *              psi carries the history of the run, eq. discrete_2_b; the
+ *              first step uses psi^0 = 0)
+ *   d_phi_np1  phi^{k+1} (written; must not alias the inputs)
+ *   d_mu, d_kappa  optional outputs (NULL to skip): mu^{k+1} (mu^{k+1/2} for
+ *              scheme 2) and kappa
+ *   h_info     optional report (NULL to skip).
+ * Returns after the final residual readback (the outputs are complete on the
+ * context's stream).  On MPFC_ENOTCONVERGED / ENONFINITE / EDIVERGED the
+ * outputs hold the last iterate and psi is still updated from it. */
+int mpfc_step(mpfc_ctx *ctx, const double *d_phi_n, const double *d_phi_nm1, double *d_psi,
+              double *d_phi_np1, double *d_mu, double *d_kappa, mpfc_info *h_info);
+
+/* Energies of a state (Sec. 3; App. A "-1" norm with a mean-zero periodic
+ * Poisson solve): out[0..3] = F(phi), F + ||psi||_{-1}^2/(2M),
+ * that + ||grad_h(phi - phi_prev)||^2/2, h^2 sum phi.  d_phi_prev may be NULL
+ * (then the last term is 0). */
+int mpfc_energies(mpfc_ctx *ctx, const double *d_phi, const double *d_phi_prev,
+                  const double *d_psi, double *h_out);
+
+void mpfc_destroy(mpfc_ctx *ctx);
+const char *mpfc_strerror(int code);
+const char *mpfc_last_error(void);
+int mpfc_version(void);
+
+/* ---- Operator-level entry points (one operation of the V-cycle each) ----
+ * Same operators as mpfc_step uses, on caller-provided FP64 device arrays;
+ * c is s M/(beta + 1/s) (scheme 1) or s M/(beta + 2/s) (scheme 2), alpha =
+ * 1 - eps.  d_phik is phi^k on this grid (scheme 2; ignored for scheme 1). */
+
+/* `sweeps` red-black nonlinear Gauss-Seidel passes (App. B), red
+ * ((i+j) even) first, Newton (linearization 0) or Picard (1) local
+ * linearisation, in place on (d_phi, d_mu, d_kappa). */
+int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double c, double alpha,
+                   const double *d_phik, double *d_phi, double *d_mu, double *d_kappa,
+                   const double *d_f1, const double *d_f2, const double *d_f3, int sweeps,
+                   void *stream);
+
+/* r = f - N(u) (App. B), three output arrays. */
+int mpfc_op_residual(int scheme, int m, int n, double h, double c, double alpha,
+                     const double *d_phik, const double *d_phi, const double *d_mu,
+                     const double *d_kappa, const double *d_f1, const double *d_f2,
+                     const double *d_f3, double *d_r1, double *d_r2, double *d_r3, void *stream);
+
+/* Source S of the step (App. B.1 / B.2) from phi^k, phi^{k-1}, psi^k. */
+int mpfc_op_source(const mpfc_params *p, int m, int n, const double *d_phik,
+                   const double *d_phikm1, const double *d_psik, double *d_S1, double *d_S2,
+                   double *d_S3, void *stream);
+
+/* Average of the 2x2 fine cells under each coarse cell: (m/2) x (n/2) out. */
+int mpfc_op_restrict(int m, int n, const double *d_fine, double *d_coarse, void *stream);
+
+/* FAS coarse-grid correction of the three fields of u (m x n):
+ * u_c += P (uH_c - vH_c), P bilinear (weights 9/16, 3/16, 3/16, 1/16 of the
+ * four nearest coarse cells), uH and vH on the (m/2) x (n/2) grid. */
+int mpfc_op_prolong_correct(int m, int n, const double *d_uH0, const double *d_uH1,
+                            const double *d_uH2, const double *d_vH0, const double *d_vH1,
+                            const double *d_vH2, double *d_u0, double *d_u1, double *d_u2,
+                            void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPFC_H */

@@ -1,0 +1,112 @@
+"""ctypes binding of libmpfc.so (argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/mpfc.h under the
+same name.  Device arrays are passed as raw pointers (for example
+``tensor.data_ptr()`` of a PyTorch CUDA/ROCm tensor); the stream is a
+hipStream_t handle as an integer (``torch.cuda.current_stream().cuda_stream``).
+
+The library must have been built (``python -m paper_1208_2643_amd.build`` or
+``__graft_entry__.build()``); importing fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libmpfc.so")
+
+MPFC_OK = 0
+MPFC_EINVAL = -1
+MPFC_ENOTCONVERGED = -2
+MPFC_ENONFINITE = -3
+MPFC_EDIVERGED = -4
+MPFC_ENOMEM = -5
+MPFC_EHIP = -6
+
+MPFC_FP64, MPFC_MIXED = 0, 1
+MPFC_GUESS_PREV, MPFC_GUESS_EXTRAP = 0, 1
+MPFC_NEWTON, MPFC_PICARD = 0, 1
+
+
+class mpfc_params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("beta", ctypes.c_double), ("M", ctypes.c_double),
+                ("h", ctypes.c_double), ("dt", ctypes.c_double), ("scheme", ctypes.c_int)]
+
+
+class mpfc_opts(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("max_cycles", ctypes.c_int),
+                ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("guess", ctypes.c_int),
+                ("linearization", ctypes.c_int), ("coarsest", ctypes.c_int),
+                ("energy", ctypes.c_int), ("diverge", ctypes.c_double)]
+
+
+class mpfc_info(ctypes.Structure):
+    _fields_ = [("energy_F", ctypes.c_double), ("energy_pseudo", ctypes.c_double),
+                ("energy_mod", ctypes.c_double), ("mass", ctypes.c_double),
+                ("residual", ctypes.c_double), ("n_cycles", ctypes.c_int),
+                ("status", ctypes.c_int), ("outer_iters", ctypes.c_int), ("pad", ctypes.c_int),
+                ("residual_history", ctypes.POINTER(ctypes.c_double))]
+
+
+class MpfcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mpfc error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+
+# name -> (restype, argtypes); every symbol declared in include/mpfc.h
+SIGNATURES = {
+    "mpfc_default_opts": (None, [ctypes.POINTER(mpfc_opts)]),
+    "mpfc_validate": (_i, [_i, _i, ctypes.POINTER(mpfc_params), ctypes.POINTER(mpfc_opts)]),
+    "mpfc_create": (_i, [ctypes.POINTER(_vp), _i, _i, ctypes.POINTER(mpfc_params),
+                         ctypes.POINTER(mpfc_opts), _vp]),
+    "mpfc_step": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(mpfc_info)]),
+    "mpfc_energies": (_i, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "mpfc_destroy": (None, [_vp]),
+    "mpfc_strerror": (ctypes.c_char_p, [_i]),
+    "mpfc_last_error": (ctypes.c_char_p, []),
+    "mpfc_version": (_i, []),
+    "mpfc_op_smooth": (_i, [_i, _i, _i, _i, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i,
+                            _vp]),
+    "mpfc_op_residual": (_i, [_i, _i, _i, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                              _vp, _vp, _vp]),
+    "mpfc_op_source": (_i, [ctypes.POINTER(mpfc_params), _i, _i, _vp, _vp, _vp, _vp, _vp, _vp,
+                            _vp]),
+    "mpfc_op_restrict": (_i, [_i, _i, _vp, _vp, _vp]),
+    "mpfc_op_prolong_correct": (_i, [_i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+}
+
+
+def load():
+    """Load libmpfc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"{LIBPATH} is missing: build it with `python -m paper_1208_2643_amd.build`")
+    lib = ctypes.CDLL(LIBPATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc: int, allow=()):
+    if rc != MPFC_OK and rc not in allow:
+        lib = load()
+        raise MpfcError(rc, f"{lib.mpfc_strerror(rc).decode()}: {lib.mpfc_last_error().decode()}")
+    return rc
+
+
+def default_opts() -> mpfc_opts:
+    o = mpfc_opts()
+    load().mpfc_default_opts(ctypes.byref(o))
+    return o

@@ -1,0 +1,185 @@
+"""Python front end of libmpfc: PyTorch supplies device memory and the stream.
+
+``Stepper`` wraps one solver context (one grid size and parameter set) and
+advances the state (phi^k, phi^{k-1}, psi^k) of either convex-splitting scheme
+by one implicit step per call; all arithmetic runs in the library's HIP
+kernels.  There is no CPU fallback: without a GPU or without the built
+library these calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class Params:
+    """Model/discretisation parameters (Sec. 2-3): alpha = 1 - eps."""
+    eps: float
+    beta: float
+    M: float
+    h: float
+    dt: float
+    scheme: int
+
+    def c(self) -> L.mpfc_params:
+        return L.mpfc_params(self.eps, self.beta, self.M, self.h, self.dt, self.scheme)
+
+
+@dataclass
+class StepInfo:
+    status: int
+    n_cycles: int
+    residual: float
+    history: np.ndarray
+    energy_F: float
+    energy_pseudo: float
+    energy_mod: float
+    mass: float
+    outer_iters: int
+
+
+def make_opts(**kw) -> L.mpfc_opts:
+    o = L.default_opts()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Stepper:
+    """One solver context for an n x m grid (tensors of shape (n, m), x fastest)."""
+
+    def __init__(self, m: int, n: int, params: Params, stream=None, **opts):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libmpfc needs a HIP GPU; none is visible")
+        self.lib = L.load()
+        self.m, self.n = m, n
+        self.params = params
+        self.opts = make_opts(**opts)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        ctx = ctypes.c_void_p()
+        L.check(self.lib.mpfc_create(ctypes.byref(ctx), m, n, ctypes.byref(params.c()),
+                                     ctypes.byref(self.opts), _stream(self.stream)))
+        self.ctx = ctx
+        self._hist = np.zeros(self.opts.max_cycles + 1)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.mpfc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, phi_n, phi_nm1, psi, phi_np1=None, mu=None, kappa=None, allow_fail=False):
+        """Advance one step.  psi is updated in place to psi^{k+1}; returns
+        (phi_np1, StepInfo)."""
+        if phi_np1 is None:
+            phi_np1 = torch.empty_like(phi_n)
+        info = L.mpfc_info()
+        info.residual_history = self._hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        rc = self.lib.mpfc_step(self.ctx, _ptr(phi_n), _ptr(phi_nm1), _ptr(psi), _ptr(phi_np1),
+                                _ptr(mu), _ptr(kappa), ctypes.byref(info))
+        allow = (L.MPFC_ENOTCONVERGED, L.MPFC_ENONFINITE, L.MPFC_EDIVERGED) if allow_fail else ()
+        L.check(rc, allow)
+        si = StepInfo(rc, info.n_cycles, info.residual, self._hist[: info.n_cycles + 1].copy(),
+                      info.energy_F, info.energy_pseudo, info.energy_mod, info.mass,
+                      info.outer_iters)
+        return phi_np1, si
+
+    def energies(self, phi, phi_prev, psi):
+        out = (ctypes.c_double * 4)()
+        L.check(self.lib.mpfc_energies(self.ctx, _ptr(phi), _ptr(phi_prev), _ptr(psi), out))
+        return np.array(out[:])
+
+
+def run(stepper: Stepper, phi0: torch.Tensor, steps: int, record=None):
+    """Run `steps` steps from phi^0 with psi^0 = 0 and phi^{-1} = phi^0."""
+    phi = phi0.clone()
+    prev = phi0.clone()
+    psi = torch.zeros_like(phi0)
+    nxt = torch.empty_like(phi0)
+    infos = []
+    for _ in range(steps):
+        _, info = stepper.step(phi, prev, psi, nxt)
+        infos.append(info)
+        if record is not None:
+            record(phi, nxt, psi, info)
+        prev, phi, nxt = phi, nxt, prev
+    return phi, prev, psi, infos
+
+
+# ---- operator-level wrappers (one V-cycle operation each) -------------------
+def coefficients(p: Params):
+    q = 1.0 if p.scheme == 1 else 2.0
+    return p.dt * p.M / (p.beta + q / p.dt), q / (p.beta + q / p.dt)
+
+
+def op_smooth(p: Params, u, f, phik=None, sweeps=1, newton=True, h=None):
+    lib = L.load()
+    phi, mu, ka = u
+    n, m = phi.shape
+    c, _ = coefficients(p)
+    L.check(lib.mpfc_op_smooth(p.scheme, 0 if newton else 1, m, n, p.h if h is None else h, c,
+                               1.0 - p.eps, _ptr(phik), _ptr(phi), _ptr(mu), _ptr(ka),
+                               _ptr(f[0]), _ptr(f[1]), _ptr(f[2]), sweeps, _stream()))
+
+
+def op_residual(p: Params, u, f, phik=None, h=None):
+    lib = L.load()
+    phi, mu, ka = u
+    n, m = phi.shape
+    c, _ = coefficients(p)
+    r = [torch.empty_like(phi) for _ in range(3)]
+    L.check(lib.mpfc_op_residual(p.scheme, m, n, p.h if h is None else h, c, 1.0 - p.eps,
+                                 _ptr(phik), _ptr(phi), _ptr(mu), _ptr(ka), _ptr(f[0]),
+                                 _ptr(f[1]), _ptr(f[2]), _ptr(r[0]), _ptr(r[1]), _ptr(r[2]),
+                                 _stream()))
+    return r
+
+
+def op_source(p: Params, phik, phikm1, psik):
+    lib = L.load()
+    n, m = phik.shape
+    S = [torch.empty_like(phik) for _ in range(3)]
+    L.check(lib.mpfc_op_source(ctypes.byref(p.c()), m, n, _ptr(phik), _ptr(phikm1), _ptr(psik),
+                               _ptr(S[0]), _ptr(S[1]), _ptr(S[2]), _stream()))
+    return S
+
+
+def op_restrict(fine):
+    lib = L.load()
+    n, m = fine.shape
+    out = torch.empty((n // 2, m // 2), dtype=fine.dtype, device=fine.device)
+    L.check(lib.mpfc_op_restrict(m, n, _ptr(fine), _ptr(out), _stream()))
+    return out
+
+
+def op_prolong_correct(uH, vH, u):
+    lib = L.load()
+    n, m = u[0].shape
+    L.check(lib.mpfc_op_prolong_correct(m, n, *[_ptr(x) for x in uH], *[_ptr(x) for x in vH],
+                                        *[_ptr(x) for x in u], _stream()))

@@ -1,0 +1,525 @@
+// Device kernels of the MPFC nonlinear FAS multigrid time step, for gfx950.
+//
+// One implicit step of either convex-splitting scheme (first order: Sec. 3.1,
+// second order: Sec. 3.2) is the solve of N(u) = S for u = (phi, mu, kappa)
+// on a periodic cell-centred grid (App. B.1 / B.2), followed by the psi update
+// (eqs. discrete_1_b / discrete_2_b).  Storage: every field is an m x n array,
+// row-major with x fastest (index j*m + i); periodic ghosts (App. A) are index
+// wrap-arounds, so m and n are powers of two and wrapping is a bit mask.
+//
+// Kernels are templated on the arithmetic type T (double, or float for the
+// inner cycles of mixed precision) and on the scheme.  DEFECT = true selects
+// the correction equation used by mixed precision: the unknown is a
+// correction e to a base state u_b held as a coefficient field, and the
+// nonlinear term is g(phi_b + e) - g(phi_b) written in factored form, so no
+// cancellation happens in low precision.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpfc {
+
+// Stop/bookkeeping state of the cycle loop, kept on the device so that the
+// loop can run without a host round trip per kernel.
+struct CycleState {
+    double acc;          // residual-norm accumulator (sum of r^2)
+    unsigned int blocks; // blocks that have added to acc
+    int count;           // norms recorded so far (entries of hist)
+    int status;          // 0 running, 1 converged, 2 cycle limit, 3 non-finite, 4 diverged
+    int done;            // status != 0; every cycle kernel returns at once when set
+    int pad0, pad1;
+};
+
+enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXCYC = 2, ST_NONFINITE = 3, ST_DIVERGED = 4 };
+
+__device__ __forceinline__ bool stopped(const CycleState* st) {
+    return st != nullptr && st->done != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Nonlinear term of N^(2) (App. B.1: phi^3; App. B.2: chi(phi, phi^k)(phi + phi^k)/2
+// with chi(a, b) = (a^2 + b^2)/2) and its derivative.  In DEFECT mode v is a
+// correction to the base value pb and the value is g(pb + v) - g(pb).
+template <typename T, int SCHEME, bool DEFECT>
+__device__ __forceinline__ T nl_value(T v, T pb, T xk) {
+    if constexpr (!DEFECT) {
+        if constexpr (SCHEME == 1) return v * v * v;
+        else return T(0.25) * (v * v + xk * xk) * (v + xk);
+    } else {
+        if constexpr (SCHEME == 1) {
+            // (pb+v)^3 - pb^3 = v (3 pb^2 + 3 pb v + v^2)
+            return v * (T(3) * pb * pb + T(3) * pb * v + v * v);
+        } else {
+            // [((pb+v)^2 + xk^2)(pb+v+xk) - (pb^2 + xk^2)(pb+xk)]/4
+            //   = v [3 pb^2 + 2 pb xk + xk^2 + v (3 pb + xk) + v^2]/4
+            return T(0.25) * v *
+                   (T(3) * pb * pb + T(2) * pb * xk + xk * xk + v * (T(3) * pb + xk) + v * v);
+        }
+    }
+}
+
+// d/dv of the nonlinear term (Newton) or the Picard coefficient, both taken
+// at the full value x = pb + v.
+template <typename T, int SCHEME, bool NEWTON>
+__device__ __forceinline__ T nl_lin(T x, T xk) {
+    if constexpr (SCHEME == 1) {
+        return NEWTON ? T(3) * x * x : x * x;
+    } else {
+        if constexpr (NEWTON) return T(0.25) * (T(3) * x * x + T(2) * x * xk + xk * xk);
+        else return T(0.25) * (x * x + xk * xk);  // chi(x, xk)/2
+    }
+}
+
+// Per-level operator constants.
+template <typename T>
+struct LevelOp {
+    T ih2;   // 1/h^2
+    T c;     // s M/(beta + 1/s) or s M/(beta + 2/s)
+    T al;    // alpha (scheme 1) or alpha/2 (scheme 2)
+    T e;     // 1 (scheme 1) or 1/2 (scheme 2): N^(3) = kappa - e Lap phi
+};
+
+struct Grid {
+    int m, n;       // powers of two
+    int lm, ln;     // log2 m, log2 n
+};
+
+__device__ __forceinline__ int wrapx(int i, const Grid& g) { return i & (g.m - 1); }
+__device__ __forceinline__ int wrapy(int j, const Grid& g) { return j & (g.n - 1); }
+__device__ __forceinline__ size_t at(int i, int j, const Grid& g) {
+    return ((size_t)j << g.lm) + (size_t)i;
+}
+
+// Sum of the four neighbours of (i, j).
+template <typename T>
+__device__ __forceinline__ T nsum(const T* __restrict__ f, int i, int j, const Grid& g) {
+    const int ip = wrapx(i + 1, g), im = wrapx(i - 1, g);
+    const int jp = wrapy(j + 1, g), jm = wrapy(j - 1, g);
+    return (f[at(ip, j, g)] + f[at(im, j, g)]) + (f[at(i, jp, g)] + f[at(i, jm, g)]);
+}
+
+// Fields of one level.
+template <typename T>
+struct Fields {
+    T* phi; T* mu; T* ka;          // unknown u (in DEFECT mode: the correction)
+    const T* f1; const T* f2; const T* f3;  // right-hand side (S, or FAS coarse RHS)
+    const T* phik;                 // phi^k on this level (scheme 2), else null
+    const T* base;                 // base phi (DEFECT mode), else null
+};
+
+// r = f - N(u) at one cell.
+template <typename T, int SCHEME, bool DEFECT>
+__device__ __forceinline__ void residual_at(const Fields<T>& F, const LevelOp<T>& op,
+                                            const Grid& g, int i, int j, T& r1, T& r2, T& r3) {
+    const size_t q = at(i, j, g);
+    const T x = F.phi[q], y = F.mu[q], z = F.ka[q];
+    const T xk = (SCHEME == 2) ? F.phik[q] : T(0);
+    const T pb = DEFECT ? F.base[q] : T(0);
+    const T lphi = (nsum(F.phi, i, j, g) - T(4) * x) * op.ih2;
+    const T lmu = (nsum(F.mu, i, j, g) - T(4) * y) * op.ih2;
+    const T lka = (nsum(F.ka, i, j, g) - T(4) * z) * op.ih2;
+    r1 = F.f1[q] - (x - op.c * lmu);
+    r2 = F.f2[q] - (y - nl_value<T, SCHEME, DEFECT>(x, pb, xk) - op.al * x - lka);
+    r3 = F.f3[q] - (z - op.e * lphi);
+}
+
+// Nonlinear collective Gauss-Seidel update of one cell (App. B): the 3x3
+// system J_loc * delta = r, J_loc = [[1, a, 0], [-d, 1, b], [ec, 0, 1]],
+// a = 4c/h^2, b = 4/h^2, ec = 4e/h^2, d = al + linearised nonlinear
+// coefficient, solved by elimination (equivalent to Cramer's rule; one
+// division).
+template <typename T, int SCHEME, bool NEWTON, bool DEFECT>
+__device__ __forceinline__ void relax_at(const Fields<T>& F, const LevelOp<T>& op, const Grid& g,
+                                         int i, int j) {
+    T r1, r2, r3;
+    residual_at<T, SCHEME, DEFECT>(F, op, g, i, j, r1, r2, r3);
+    const size_t q = at(i, j, g);
+    const T x = F.phi[q];
+    const T xk = (SCHEME == 2) ? F.phik[q] : T(0);
+    const T pb = DEFECT ? F.base[q] : T(0);
+    const T d = op.al + nl_lin<T, SCHEME, NEWTON>(pb + x, xk);
+    const T a = T(4) * op.c * op.ih2, b = T(4) * op.ih2, ec = T(4) * op.e * op.ih2;
+    const T det = T(1) + a * d + a * b * ec;
+    const T dm = (r2 + (d + b * ec) * r1 - b * r3) / det;
+    const T dx = r1 - a * dm;
+    const T dk = r3 - ec * dx;
+    F.phi[q] = x + dx;
+    F.mu[q] += dm;
+    F.ka[q] += dk;
+}
+
+// ---------------------------------------------------------------------------
+// One colour of a red-black sweep, in place (cells of one colour couple only
+// to the other colour).  colour = (i + j) & 1, red = 0.  Thread (k, j)
+// handles cell i = 2k + ((j + colour) & 1).
+template <typename T, int SCHEME, bool NEWTON, bool DEFECT>
+__global__ void __launch_bounds__(256) k_smooth_color(Fields<T> F, LevelOp<T> op, Grid g,
+                                                      int colour, const CycleState* st) {
+    if (stopped(st)) return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (k >= (g.m >> 1) || j >= g.n) return;
+    const int i = 2 * k + ((j + colour) & 1);
+    relax_at<T, SCHEME, NEWTON, DEFECT>(F, op, g, i, j);
+}
+
+// r = f - N(u) on every cell (operator-level entry point).
+template <typename T, int SCHEME, bool DEFECT>
+__global__ void __launch_bounds__(256) k_residual_field(Fields<T> F, LevelOp<T> op, Grid g, T* r0,
+                                                        T* r1, T* r2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.m || j >= g.n) return;
+    T a, b, c;
+    residual_at<T, SCHEME, DEFECT>(F, op, g, i, j, a, b, c);
+    const size_t q = at(i, j, g);
+    r0[q] = a; r1[q] = b; r2[q] = c;
+}
+
+// ---------------------------------------------------------------------------
+// Residual on the fine grid, restricted with the 2x2 average, together with
+// the restriction of u (FAS): uH = vH = R u, fH = R r.  One thread per coarse
+// cell.
+template <typename T, int SCHEME, bool DEFECT>
+__global__ void __launch_bounds__(256) k_resid_restrict(Fields<T> F, LevelOp<T> op, Grid g,
+                                                        T* uH0, T* uH1, T* uH2, T* vH0, T* vH1,
+                                                        T* vH2, T* fH0, T* fH1, T* fH2,
+                                                        const CycleState* st) {
+    if (stopped(st)) return;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int mc = g.m >> 1, nc = g.n >> 1;
+    if (I >= mc || J >= nc) return;
+    T s0 = 0, s1 = 0, s2 = 0, t0 = 0, t1 = 0, t2 = 0;
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+        for (int di = 0; di < 2; ++di) {
+            const int i = 2 * I + di, j = 2 * J + dj;
+            T r1, r2, r3;
+            residual_at<T, SCHEME, DEFECT>(F, op, g, i, j, r1, r2, r3);
+            const size_t q = at(i, j, g);
+            s0 += F.phi[q]; s1 += F.mu[q]; s2 += F.ka[q];
+            t0 += r1; t1 += r2; t2 += r3;
+        }
+    const size_t Q = (size_t)J * mc + I;
+    const T qt = T(0.25);
+    uH0[Q] = vH0[Q] = qt * s0;
+    uH1[Q] = vH1[Q] = qt * s1;
+    uH2[Q] = vH2[Q] = qt * s2;
+    fH0[Q] = qt * t0; fH1[Q] = qt * t1; fH2[Q] = qt * t2;
+}
+
+// FAS coarse right-hand side: f_H = N_H(u_H) + (R r), with R r already in f_H.
+template <typename T, int SCHEME, bool DEFECT>
+__global__ void __launch_bounds__(256) k_coarse_rhs(Fields<T> F, LevelOp<T> op, Grid g,
+                                                    T* f0, T* f1, T* f2, const CycleState* st) {
+    if (stopped(st)) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.m || j >= g.n) return;
+    const size_t q = at(i, j, g);
+    const T x = F.phi[q], y = F.mu[q], z = F.ka[q];
+    const T xk = (SCHEME == 2) ? F.phik[q] : T(0);
+    const T pb = DEFECT ? F.base[q] : T(0);
+    const T lphi = (nsum(F.phi, i, j, g) - T(4) * x) * op.ih2;
+    const T lmu = (nsum(F.mu, i, j, g) - T(4) * y) * op.ih2;
+    const T lka = (nsum(F.ka, i, j, g) - T(4) * z) * op.ih2;
+    f0[q] += x - op.c * lmu;
+    f1[q] += y - nl_value<T, SCHEME, DEFECT>(x, pb, xk) - op.al * x - lka;
+    f2[q] += z - op.e * lphi;
+}
+
+// Coarse-grid correction u_h += P (u_H - v_H), bilinear: a fine cell takes
+// 9/16 of its coarse parent, 3/16 of the coarse neighbours on its two outer
+// sides and 1/16 of the diagonal one.  One thread per fine cell.
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong_correct(T* u0, T* u1, T* u2, Grid g,
+                                                         const T* __restrict__ uH0,
+                                                         const T* __restrict__ uH1,
+                                                         const T* __restrict__ uH2,
+                                                         const T* __restrict__ vH0,
+                                                         const T* __restrict__ vH1,
+                                                         const T* __restrict__ vH2,
+                                                         const CycleState* st) {
+    if (stopped(st)) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.m || j >= g.n) return;
+    const int mc = g.m >> 1, nc = g.n >> 1;
+    const int I = i >> 1, J = j >> 1;
+    const int Is = ((i & 1) ? I + 1 : I - 1) & (mc - 1);
+    const int Js = ((j & 1) ? J + 1 : J - 1) & (nc - 1);
+    const size_t a = (size_t)J * mc + I, b = (size_t)J * mc + Is;
+    const size_t c = (size_t)Js * mc + I, d = (size_t)Js * mc + Is;
+    const size_t q = at(i, j, g);
+    const T w9 = T(9) / T(16), w3 = T(3) / T(16), w1 = T(1) / T(16);
+    u0[q] += w9 * (uH0[a] - vH0[a]) + w3 * ((uH0[b] - vH0[b]) + (uH0[c] - vH0[c])) +
+             w1 * (uH0[d] - vH0[d]);
+    u1[q] += w9 * (uH1[a] - vH1[a]) + w3 * ((uH1[b] - vH1[b]) + (uH1[c] - vH1[c])) +
+             w1 * (uH1[d] - vH1[d]);
+    u2[q] += w9 * (uH2[a] - vH2[a]) + w3 * ((uH2[b] - vH2[b]) + (uH2[c] - vH2[c])) +
+             w1 * (uH2[d] - vH2[d]);
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide sum of doubles: wave shuffles, then one value per wave in LDS.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) t += red[w];
+    }
+    return t;  // valid in thread 0
+}
+
+// Finest-grid residual norm ||r|| = sqrt(h^2 sum_c sum_ij r_c^2), always in
+// FP64 (the stopping test).  Each block adds its partial sum with one atomic;
+// the last block to finish records the norm in hist[count], updates the
+// status (converged when norm <= tol) and clears the accumulator.
+// When `write` is set the residual is also stored (mixed precision uses it as
+// the right-hand side of the correction equation).
+template <int SCHEME, int NT>
+__global__ void __launch_bounds__(NT) k_resnorm(Fields<double> F, LevelOp<double> op, Grid g,
+                                                double h2, CycleState* st, double* hist,
+                                                double tol, int max_norms, double diverge,
+                                                double* r0, double* r1o, double* r2o) {
+    if (stopped(st)) return;
+    __shared__ double red[NT / 64];
+    __shared__ int last;
+    double acc = 0.0;
+    const size_t total = (size_t)g.m * g.n;
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
+        const int i = (int)(q & (size_t)(g.m - 1));
+        const int j = (int)(q >> g.lm);
+        double a, b, c;
+        residual_at<double, SCHEME, false>(F, op, g, i, j, a, b, c);
+        acc += a * a + b * b + c * c;
+        if (r0) { r0[q] = a; r1o[q] = b; r2o[q] = c; }
+    }
+    const double bs = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) {
+        atomicAdd(&st->acc, bs);
+        __threadfence();
+        const unsigned t = atomicAdd(&st->blocks, 1u);
+        last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        const double s = atomicAdd(&st->acc, 0.0);
+        const double nr = sqrt(h2 * s);
+        const int k = st->count;
+        hist[k] = nr;
+        st->count = k + 1;
+        int status = ST_RUNNING;
+        if (!(nr == nr) || nr > 1.0e300) status = ST_NONFINITE;
+        else if (nr <= tol) status = ST_CONVERGED;
+        else if (k > 0 && nr > diverge * hist[0]) status = ST_DIVERGED;
+        else if (k + 1 >= max_norms) status = ST_MAXCYC;
+        st->status = status;
+        st->done = status != ST_RUNNING;
+        st->acc = 0.0;
+        st->blocks = 0u;
+        __threadfence();
+    }
+}
+
+__global__ void k_state_reset(CycleState* st) {
+    if (threadIdx.x == 0) {
+        st->acc = 0.0; st->blocks = 0u; st->count = 0;
+        st->status = ST_RUNNING; st->done = 0; st->pad0 = st->pad1 = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest grid: Newton's method with the exact Jacobian on all 3 m n
+// unknowns (m n <= 16), each linear system solved by Gaussian elimination
+// with partial pivoting, all in one workgroup of 64 threads.
+constexpr int CMAX = 48;
+
+template <typename T, int SCHEME, bool DEFECT>
+__global__ void __launch_bounds__(64) k_coarsest(Fields<T> F, LevelOp<T> op, Grid g, int maxit,
+                                                 T steptol, const CycleState* st) {
+    if (stopped(st)) return;
+    __shared__ T A[CMAX][CMAX + 1];
+    __shared__ T x[CMAX];
+    __shared__ int piv;
+    __shared__ int conv;
+    const int nc = g.m * g.n, nn = 3 * nc, t = threadIdx.x;
+    for (int it = 0; it < maxit; ++it) {
+        // Row t of the Jacobian and minus the residual.
+        if (t < nn) {
+            for (int cc = 0; cc <= nn; ++cc) A[t][cc] = T(0);
+            const int comp = t / nc, cell = t - comp * nc;
+            const int i = cell & (g.m - 1), j = cell >> g.lm;
+            const int nb[4] = {(int)at(wrapx(i + 1, g), j, g), (int)at(wrapx(i - 1, g), j, g),
+                               (int)at(i, wrapy(j + 1, g), g), (int)at(i, wrapy(j - 1, g), g)};
+            T r1, r2, r3;
+            residual_at<T, SCHEME, DEFECT>(F, op, g, i, j, r1, r2, r3);
+            if (comp == 0) {
+                A[t][cell] += T(1);
+                A[t][nc + cell] += T(4) * op.c * op.ih2;
+                for (int s = 0; s < 4; ++s) A[t][nc + nb[s]] -= op.c * op.ih2;
+                A[t][nn] = r1;
+            } else if (comp == 1) {
+                const T xk = (SCHEME == 2) ? F.phik[cell] : T(0);
+                const T pb = DEFECT ? F.base[cell] : T(0);
+                A[t][cell] -= op.al + nl_lin<T, SCHEME, true>(pb + F.phi[cell], xk);
+                A[t][nc + cell] += T(1);
+                A[t][2 * nc + cell] += T(4) * op.ih2;
+                for (int s = 0; s < 4; ++s) A[t][2 * nc + nb[s]] -= op.ih2;
+                A[t][nn] = r2;
+            } else {
+                A[t][2 * nc + cell] += T(1);
+                A[t][cell] += T(4) * op.e * op.ih2;
+                for (int s = 0; s < 4; ++s) A[t][nb[s]] -= op.e * op.ih2;
+                A[t][nn] = r3;
+            }
+        }
+        __syncthreads();
+        for (int k = 0; k < nn; ++k) {
+            if (t == 0) {
+                int p = k;
+                T best = fabs(A[k][k]);
+                for (int r = k + 1; r < nn; ++r) {
+                    const T v = fabs(A[r][k]);
+                    if (v > best) { best = v; p = r; }
+                }
+                piv = p;
+            }
+            __syncthreads();
+            const int p = piv;
+            if (p != k && t <= nn) {
+                const T tmp = A[k][t]; A[k][t] = A[p][t]; A[p][t] = tmp;
+            }
+            __syncthreads();
+            if (t > k && t < nn) {
+                const T fct = A[t][k] / A[k][k];
+                for (int cc = k; cc <= nn; ++cc) A[t][cc] -= fct * A[k][cc];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            T smax = 0, umax = 0;
+            for (int k = nn - 1; k >= 0; --k) {
+                T s = A[k][nn];
+                for (int cc = k + 1; cc < nn; ++cc) s -= A[k][cc] * x[cc];
+                x[k] = s / A[k][k];
+            }
+            for (int k = 0; k < nc; ++k) {
+                F.phi[k] += x[k];
+                F.mu[k] += x[nc + k];
+                F.ka[k] += x[2 * nc + k];
+                smax = fmax(smax, fmax(fabs(x[k]), fmax(fabs(x[nc + k]), fabs(x[2 * nc + k]))));
+                umax = fmax(umax, fmax(fabs(F.phi[k]), fmax(fabs(F.mu[k]), fabs(F.ka[k]))));
+            }
+            conv = (smax <= steptol * (T(1) + umax));
+            __threadfence();
+        }
+        __syncthreads();
+        if (conv) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step set-up and wrap-up kernels (one thread per cell).
+
+// Source S (App. B.1 / B.2).  d = weight of psi^k.
+template <int SCHEME>
+__global__ void __launch_bounds__(256) k_source(Grid g, double ih2, double d, double alpha,
+                                                const double* __restrict__ phik,
+                                                const double* __restrict__ phikm1,
+                                                const double* __restrict__ psik, double* S1,
+                                                double* S2, double* S3) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.m || j >= g.n) return;
+    const size_t q = at(i, j, g);
+    const double pk = phik[q];
+    const double lk = (nsum(phik, i, j, g) - 4.0 * pk) * ih2;
+    S1[q] = pk + d * psik[q];
+    if constexpr (SCHEME == 1) {
+        S2[q] = 2.0 * lk;
+        S3[q] = 0.0;
+    } else {
+        // 2 Lap((3 phi^k - phi^{k-1})/2) = 3 Lap phi^k - Lap phi^{k-1}
+        const double lkm1 = (nsum(phikm1, i, j, g) - 4.0 * phikm1[q]) * ih2;
+        S2[q] = 0.5 * alpha * pk + (3.0 * lk - lkm1);
+        S3[q] = 0.5 * lk;
+    }
+}
+
+// Initial guess phi^(0): phi^k (mode 0) or 2 phi^k - phi^{k-1} (mode 1).
+__global__ void __launch_bounds__(256) k_guess(Grid g, int mode, const double* __restrict__ phik,
+                                               const double* __restrict__ phikm1, double* phi) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (size_t)g.m * g.n) return;
+    phi[q] = mode == 1 ? 2.0 * phik[q] - phikm1[q] : phik[q];
+}
+
+// Consistent completion of the guess: kappa = S3 + e Lap phi (so N^(3) = S^(3)).
+__global__ void __launch_bounds__(256) k_complete_kappa(Grid g, double ih2, double e,
+                                                        const double* __restrict__ phi,
+                                                        const double* __restrict__ S3,
+                                                        double* ka) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.m || j >= g.n) return;
+    const size_t q = at(i, j, g);
+    ka[q] = S3[q] + e * (nsum(phi, i, j, g) - 4.0 * phi[q]) * ih2;
+}
+
+// ... and mu = S2 + g(phi) + al phi + Lap kappa (so N^(2) = S^(2)).
+template <int SCHEME>
+__global__ void __launch_bounds__(256) k_complete_mu(Grid g, double ih2, double al,
+                                                     const double* __restrict__ phi,
+                                                     const double* __restrict__ phik,
+                                                     const double* __restrict__ ka,
+                                                     const double* __restrict__ S2, double* mu) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.m || j >= g.n) return;
+    const size_t q = at(i, j, g);
+    const double x = phi[q];
+    const double xk = SCHEME == 2 ? phik[q] : 0.0;
+    mu[q] = S2[q] + nl_value<double, SCHEME, false>(x, 0.0, xk) + al * x +
+            (nsum(ka, i, j, g) - 4.0 * ka[q]) * ih2;
+}
+
+// 2x2 average (restriction of phi^k for the scheme-2 coarse operators).
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) k_restrict(Grid g, const TI* __restrict__ f, TO* fc) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int mc = g.m >> 1, nc = g.n >> 1;
+    if (I >= mc || J >= nc) return;
+    const TI s = (f[at(2 * I, 2 * J, g)] + f[at(2 * I + 1, 2 * J, g)]) +
+                 (f[at(2 * I, 2 * J + 1, g)] + f[at(2 * I + 1, 2 * J + 1, g)]);
+    fc[(size_t)J * mc + I] = (TO)(TI(0.25) * s);
+}
+
+// psi^{k+1}: (phi - phi^k)/s (scheme 1, eq. discrete_1_b) or
+// (2/s)(phi - phi^k) - psi^k (scheme 2, eq. discrete_2_b); in place on psi.
+template <int SCHEME>
+__global__ void __launch_bounds__(256) k_psi_update(size_t total, double s,
+                                                    const double* __restrict__ phi,
+                                                    const double* __restrict__ phik, double* psi) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    if constexpr (SCHEME == 1) psi[q] = (phi[q] - phik[q]) / s;
+    else psi[q] = (2.0 / s) * (phi[q] - phik[q]) - psi[q];
+}
+
+}  // namespace mpfc

@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol declared in include/mpfc.h, and rejects invalid configurations
+on the host before any HIP call."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_1208_2643_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "mpfc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpfc_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = declared_symbols()
+    assert "mpfc_step" in names and "mpfc_create" in names
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in L.SIGNATURES, f"binding lacks {name}"
+
+
+def test_version_and_strerror():
+    lib = L.load()
+    assert lib.mpfc_version() == 1
+    for code in range(-6, 1):
+        assert lib.mpfc_strerror(code)
+    assert lib.mpfc_strerror(-99) == b"unknown error"
+
+
+def good():
+    p = L.mpfc_params(0.025, 0.9, 1.0, math.pi / 4, 0.05, 2)
+    o = L.default_opts()
+    return p, o
+
+
+def test_defaults():
+    o = L.default_opts()
+    assert (o.nu1, o.nu2, o.max_cycles, o.tol, o.coarsest) == (2, 2, 100, 1e-10, 2)
+    p, o = good()
+    assert L.load().mpfc_validate(1024, 1024, ctypes.byref(p), ctypes.byref(o)) == 0
+
+
+@pytest.mark.parametrize("field,value", [("dt", 0.0), ("dt", -1.0), ("h", 0.0), ("M", 0.0),
+                                         ("beta", -0.1), ("scheme", 3), ("eps", 1.5),
+                                         ("h", float("nan"))])
+def test_invalid_params_rejected(field, value):
+    p, o = good()
+    setattr(p, field, value)
+    assert L.load().mpfc_validate(64, 64, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
+
+
+@pytest.mark.parametrize("m,n", [(0, 64), (48, 64), (64, 100), (1, 1), (2, 128)])
+def test_invalid_sizes_rejected(m, n):
+    p, o = good()
+    assert L.load().mpfc_validate(m, n, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [("tol", 0.0), ("max_cycles", 0), ("nu1", -1),
+                                         ("coarsest", 3), ("precision", 7), ("guess", 9),
+                                         ("linearization", 5), ("diverge", 0.5)])
+def test_invalid_opts_rejected(field, value):
+    p, o = good()
+    setattr(o, field, value)
+    assert L.load().mpfc_validate(64, 64, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
+
+
+def test_create_rejects_before_any_hip_call():
+    """mpfc_create validates on the host, so it fails cleanly without a GPU."""
+    lib = L.load()
+    p, o = good()
+    p.dt = -1.0
+    ctx = ctypes.c_void_p()
+    assert lib.mpfc_create(ctypes.byref(ctx), 64, 64, ctypes.byref(p), ctypes.byref(o), None) \
+        == L.MPFC_EINVAL
+    assert ctx.value is None
+    assert b"dt" in lib.mpfc_last_error()
+
+
+def test_rectangular_and_small_grids_accepted():
+    lib = L.load()
+    p, o = good()
+    for m, n in [(2, 2), (4, 8), (64, 128), (2048, 2048)]:
+        assert lib.mpfc_validate(m, n, ctypes.byref(p), ctypes.byref(o)) == 0, (m, n)

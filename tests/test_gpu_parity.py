@@ -1,0 +1,258 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+Operator level: each V-cycle operation on the same seeded inputs, element by
+element.  Step level: whole time steps of both schemes against the oracle
+solved to a tighter tolerance; the bar is a relative L2 difference of 1e-10
+(FP64).  Sizes span several workgroups with ragged tails, plus the full
+1024^2 grid of the benchmark workload.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1208_2643_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1208_2643_amd import api  # noqa: E402
+from paper_1208_2643_amd import _lib as L  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relmax(a, b):
+    return float(np.max(np.abs(a - b)) / max(1e-300, np.max(np.abs(b))))
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def both(scheme, **kw):
+    d = dict(eps=0.025, beta=0.9, M=1.0, h=0.5, dt=0.1, scheme=scheme)
+    d.update(kw)
+    return O.Params(**d), api.Params(**d)
+
+
+SIZES = [(8, 8), (64, 32), (128, 256), (32, 512)]
+
+
+def state(m, n, seed):
+    phik = I.noise(m, n, mean=0.1, amp=0.1, seed=seed)
+    phikm1 = I.noise(m, n, mean=0.1, amp=0.1, seed=seed + 1)
+    psik = I.noise(m, n, mean=0.0, amp=0.05, seed=seed + 2)
+    u = [I.noise(m, n, mean=0.1, amp=0.1, seed=seed + 3),
+         I.noise(m, n, mean=0.0, amp=0.2, seed=seed + 4),
+         I.noise(m, n, mean=0.0, amp=0.2, seed=seed + 5)]
+    return phik, phikm1, psik, u
+
+
+# ------------------------------------------------------------ operator level
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("m,n", SIZES)
+def test_source(scheme, m, n):
+    po, pg = both(scheme, h=0.37, dt=0.3)
+    phik, phikm1, psik, _ = state(m, n, 100)
+    ref = O.source(po, phik, phikm1, psik)
+    got = api.op_source(pg, dev(phik), dev(phikm1), dev(psik))
+    for a, b in zip(got, ref):
+        if np.max(np.abs(b)) == 0:
+            assert np.max(np.abs(host(a))) == 0
+        else:
+            assert relmax(host(a), b) <= 1e-14
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("m,n", SIZES)
+def test_residual(scheme, m, n):
+    po, pg = both(scheme, h=0.37, dt=0.3)
+    phik, phikm1, psik, u = state(m, n, 200)
+    f = O.source(po, phik, phikm1, psik)
+    ref = O.residual(po, u, f, phik)
+    got = api.op_residual(pg, [dev(x) for x in u], [dev(x) for x in f], dev(phik))
+    for a, b in zip(got, ref):
+        assert relmax(host(a), b) <= 1e-13
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("newton", [True, False])
+@pytest.mark.parametrize("sweeps", [1, 2])
+@pytest.mark.parametrize("m,n", SIZES)
+def test_smooth(scheme, newton, sweeps, m, n):
+    """Red-black sweeps: GPU and oracle visit cells in the same colour order,
+    so iterates agree up to rounding."""
+    po, pg = both(scheme, h=0.5, dt=0.1)
+    phik, phikm1, psik, u = state(m, n, 300)
+    f = O.source(po, phik, phikm1, psik)
+    ref = O.smooth(po, u, f, phik=phik, sweeps=sweeps, newton=newton)
+    ud = [dev(x) for x in u]
+    api.op_smooth(pg, ud, [dev(x) for x in f], dev(phik), sweeps=sweeps, newton=newton)
+    for a, b in zip(ud, ref):
+        assert relmax(host(a), b) <= 1e-12
+
+
+@pytest.mark.parametrize("m,n", [(4, 4), (64, 32), (128, 256)])
+def test_restrict_and_prolong(m, n):
+    f = I.noise(m, n, mean=0.0, amp=1.0, seed=400)
+    assert relmax(host(api.op_restrict(dev(f))), O.restrict(f)) <= 1e-15
+    uH = [I.noise(m // 2, n // 2, seed=401 + k) for k in range(3)]
+    vH = [I.noise(m // 2, n // 2, seed=404 + k) for k in range(3)]
+    u = [I.noise(m, n, seed=407 + k) for k in range(3)]
+    ud = [dev(x) for x in u]
+    api.op_prolong_correct([dev(x) for x in uH], [dev(x) for x in vH], ud)
+    for k in range(3):
+        ref = O.prolong_add(uH[k] - vH[k], u[k])
+        assert relmax(host(ud[k]), ref) <= 1e-14
+
+
+# ---------------------------------------------------------------- step level
+def run_both(po, pg, phi0, steps, tol_gpu=1e-10, tol_orc=1e-12, **opts):
+    st = api.Stepper(phi0.shape[1], phi0.shape[0], pg, tol=tol_gpu, **opts)
+    phi_g, prev_g, psi_g, infos = api.run(st, dev(phi0), steps)
+    phi_o, prev_o, psi_o, res = O.run(po, phi0, steps, tol=tol_orc, max_cycles=300)
+    assert all(r.cycles >= 0 for r in res)
+    assert all(i.status == 0 for i in infos)
+    return (host(phi_g), host(psi_g), infos), (phi_o, psi_o, res)
+
+
+def test_scheme1_64_ten_steps():
+    """First-order scheme, 64^2, h = 0.5, eps = 0.025, beta = 0.9, M = 1,
+    dt = 0.1, noise initial data, 10 steps of V(2,2) to 1e-10."""
+    po, pg = both(1, h=0.5, dt=0.1)
+    phi0 = I.noise(64, 64, mean=0.07, amp=0.05, seed=1)
+    (pg_, sg, infos), (po_, so, res) = run_both(po, pg, phi0, 10)
+    assert rel_l2(pg_, po_) <= 1e-10
+    assert rel_l2(sg, so) <= 1e-8   # psi = (phi^{k+1} - phi^k)/s amplifies by 1/s
+    for i, r in zip(infos, res):
+        assert abs(i.energy_pseudo - r.energies[1]) <= 1e-9 * abs(r.energies[1])
+        assert abs(i.mass - r.energies[3]) <= 1e-12 * abs(r.energies[3])
+
+
+@pytest.mark.parametrize("N", [32, 128])
+def test_scheme2_crystallites(N):
+    """Second-order scheme with the parameters of the 1024^2 workload
+    (h = pi/4, dt = 0.05) on smaller grids, crystallite initial data."""
+    po, pg = both(2, h=math.pi / 4, dt=0.05)
+    phi0 = I.crystallites(N, N, math.pi / 4, radius_cells=N / 8, seed=2)
+    (pg_, sg, infos), (po_, so, res) = run_both(po, pg, phi0, 6)
+    assert rel_l2(pg_, po_) <= 1e-10
+    assert rel_l2(sg, so) <= 1e-8
+    for i, r in zip(infos, res):
+        assert abs(i.energy_mod - r.energies[2]) <= 1e-9 * abs(r.energies[2])
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_cycle_history_matches_oracle(scheme):
+    """Same guess and same V-cycle components: the GPU's residual history
+    follows the oracle's cycle by cycle."""
+    po, pg = both(scheme, h=math.pi / 4, dt=0.05)
+    phi0 = I.noise(64, 64, mean=0.1, amp=0.1, seed=7)
+    prev = I.noise(64, 64, mean=0.1, amp=0.1, seed=8)
+    st = api.Stepper(64, 64, pg, tol=1e-11, guess=L.MPFC_GUESS_EXTRAP, energy=0)
+    psi = torch.zeros(64, 64, dtype=torch.float64, device=DEV)
+    _, info = st.step(dev(phi0), dev(prev), psi)
+    r = O.step(po, phi0, prev, np.zeros_like(phi0), guess=1, tol=1e-11, energy=False)
+    assert info.n_cycles == r.cycles
+    # relative agreement above the FP64 rounding floor of the residual (~1e-14 here)
+    np.testing.assert_allclose(info.history, r.history, rtol=1e-6, atol=1e-13)
+
+
+def test_full_size_single_step_1024():
+    """One step of the 1024^2 workload (scheme 2, h = pi/4, dt = 0.05,
+    crystallites) in the benchmark's configuration, against the oracle."""
+    N = 1024
+    po, pg = both(2, h=math.pi / 4, dt=0.05)
+    phi0 = I.crystallites(N, N, math.pi / 4, seed=2)
+    st = api.Stepper(N, N, pg, tol=1e-10)
+    psi = torch.zeros(N, N, dtype=torch.float64, device=DEV)
+    phi_g, info = st.step(dev(phi0), dev(phi0), psi)
+    r = O.step(po, phi0, phi0, np.zeros_like(phi0), tol=1e-12, max_cycles=100)
+    assert r.cycles > 0 and info.status == 0
+    assert rel_l2(host(phi_g), r.phi) <= 1e-10
+    assert abs(info.energy_mod - r.energies[2]) <= 1e-9 * abs(r.energies[2])
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_guess_independence_gpu(scheme):
+    """Unique solvability: previous-step and extrapolated guesses give the
+    same phi^{k+1}."""
+    _, pg = both(scheme, h=0.5, dt=2.0)
+    phik = dev(I.noise(64, 64, mean=0.1, amp=0.05, seed=61))
+    phikm1 = dev(I.noise(64, 64, mean=0.1, amp=0.05, seed=62))
+    outs = []
+    for g in (L.MPFC_GUESS_PREV, L.MPFC_GUESS_EXTRAP):
+        st = api.Stepper(64, 64, pg, tol=1e-12, guess=g, max_cycles=300, energy=0)
+        psi = torch.zeros_like(phik)
+        phi, info = st.step(phik, phikm1, psi)
+        assert info.status == 0
+        outs.append(host(phi))
+    assert np.max(np.abs(outs[0] - outs[1])) <= 1e-10
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_mass_and_energy_invariants_gpu(scheme):
+    """Mass conservation and the monotone energy (pseudo energy for scheme 1,
+    modified energy for scheme 2) over a run at a large time step."""
+    _, pg = both(scheme, h=0.5, dt=2.0)
+    phi0 = I.noise(64, 64, mean=0.1, amp=0.05, seed=71)
+    st = api.Stepper(64, 64, pg, tol=1e-11, max_cycles=300)
+    phi, prev, psi, infos = api.run(st, dev(phi0), 8)
+    mass0 = 0.25 * phi0.sum()
+    key = "energy_pseudo" if scheme == 1 else "energy_mod"
+    e = [getattr(i, key) for i in infos]
+    for i in infos:
+        assert abs(i.mass - mass0) <= 1e-10 * abs(mass0)
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(e, e[1:]))
+    assert abs(host(psi).mean()) <= 1e-10
+
+
+def test_status_codes():
+    _, pg = both(2, h=math.pi / 4, dt=0.05)
+    phi0 = I.noise(64, 64, mean=0.1, amp=0.1, seed=81)
+    st = api.Stepper(64, 64, pg, tol=1e-14, max_cycles=1, energy=0)
+    psi = torch.zeros(64, 64, dtype=torch.float64, device=DEV)
+    _, info = st.step(dev(phi0), dev(phi0), psi, allow_fail=True)
+    assert info.status == L.MPFC_ENOTCONVERGED and info.n_cycles == 1
+    bad = phi0.copy()
+    bad[3, 5] = np.nan
+    st2 = api.Stepper(64, 64, pg, energy=0)
+    psi = torch.zeros(64, 64, dtype=torch.float64, device=DEV)
+    _, info = st2.step(dev(bad), dev(bad), psi, allow_fail=True)
+    assert info.status == L.MPFC_ENONFINITE and info.n_cycles == 0
+
+
+def test_constant_state_gpu():
+    _, pg = both(2, h=0.5, dt=0.7)
+    f = dev(np.full((32, 32), 0.23))
+    st = api.Stepper(32, 32, pg, energy=0)
+    psi = torch.zeros_like(f)
+    phi, info = st.step(f, f, psi)
+    assert info.n_cycles == 0
+    assert np.max(np.abs(host(phi) - 0.23)) == 0.0
+
+
+def test_translation_equivariance():
+    """A periodic shift of the input by a non-tile-multiple offset shifts the
+    result (checks the index wrap of every kernel)."""
+    _, pg = both(2, h=math.pi / 4, dt=0.05)
+    phi0 = I.noise(128, 64, mean=0.1, amp=0.1, seed=91)
+    st = api.Stepper(128, 64, pg, tol=1e-12, energy=0)
+    a, _ = st.step(dev(phi0), dev(phi0), torch.zeros(64, 128, dtype=torch.float64, device=DEV))
+    sh = np.roll(phi0, (13, 37), axis=(0, 1))
+    b, _ = st.step(dev(sh), dev(sh), torch.zeros(64, 128, dtype=torch.float64, device=DEV))
+    assert np.max(np.abs(np.roll(host(a), (13, 37), axis=(0, 1)) - host(b))) <= 1e-10
