@@ -1,0 +1,224 @@
+#!/usr/bin/env python
+"""Benchmark: time-steps/s of the MPFC second-order scheme at 1024^2.
+
+Workload (one GPU): second-order convex-splitting scheme, FP64, periodic
+1024 x 1024 grid, h = pi/4, eps = 0.025, beta = 0.9, M = 1, dt = 0.05,
+initial data = 0.07 liquid with three seeded one-mode crystallites (seed 2),
+FAS V(2,2) cycles to a residual norm of 1e-10, energies computed every step.
+A "step" is one whole implicit time step: source, guess, V-cycles to the
+tolerance, psi update and energies, all in the library's HIP kernels.
+
+Prints one JSON line.  `roofline` reports the dominant kernel (finest-level
+red-black smoothing), timed live with HIP events on the library's stream over
+the timed region; `cpu_baseline` times the CPU oracle (test infrastructure)
+on a bounded sample of the same workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-steps/s at 1024² to 1e-10 residual: FP64 MG vs mixed-prec vs learned guess"
+HBM_PEAK_GBPS = 8000.0
+# Algorithmic bytes per finest cell of the two finest-level launches, FP64,
+# scheme 2, V(2,2), per-operation model: one red-black sweep reads u, S, phi^k
+# and writes u (80 B); residual + 2x2 restriction 68 B; prolongation +
+# correction 60 B; residual norm 56 B.
+#   down = 2 sweeps + residual/restriction, up = prolongation + 2 sweeps + norm.
+MODEL_BYTES = {"down": 2 * 80.0 + 68.0, "up": 60.0 + 2 * 80.0 + 56.0}
+# Compulsory traffic of the fused launches: down reads u, S, phi^k (56 B),
+# writes u (24 B) and the coarse u, v, R r (9 quarter fields, 18 B); up reads
+# u, S, phi^k (56 B) and the coarse u, v (6 quarter fields, 12 B), writes u (24 B).
+COMPULSORY_BYTES = {"down": 56.0 + 24.0 + 18.0, "up": 56.0 + 12.0 + 24.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--N", type=int, default=1024, help=argparse.SUPPRESS)
+    ap.add_argument("--no-energy", action="store_true", help="skip the per-step energies")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", type=int, default=1,
+                    help="also time the mixed-precision variant of the workload")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="approximate CPU time budget of the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(params, phi0, tol, budget_s):
+    """The oracle, as it stands, on the same workload from the same initial
+    state: whole steps until about `budget_s` seconds have passed."""
+    import numpy as np
+    import oracle as O
+    p = O.Params(**params)
+    phi, prev, psi = phi0.copy(), phi0.copy(), np.zeros_like(phi0)
+    t0 = time.perf_counter()
+    steps = 0
+    cycles = 0
+    while True:
+        r = O.step(p, phi, prev, psi, guess=1, tol=tol, max_cycles=100, energy=True)
+        steps += 1
+        cycles += max(r.cycles, 0)
+        prev, phi, psi = phi, r.phi, r.psi
+        if time.perf_counter() - t0 >= budget_s or steps >= 20:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": steps / dt, "unit": "time-steps/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {steps} step(s) of the same {phi0.shape[1]}x{phi0.shape[0]} "
+                      f"workload from its initial state ({cycles} V-cycles, energies on), "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; run with --gpus 1 "
+              "(the multi-GPU sharding of the step is a design, not a built path)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1208_2643_amd import api, inputs
+
+    N = args.N
+    params = dict(eps=0.025, beta=0.9, M=1.0, h=math.pi / 4, dt=0.05, scheme=2)
+    tol = 1e-10
+    phi0 = inputs.crystallites(N, N, params["h"], seed=2)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    st = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2,
+                     energy=0 if args.no_energy else 1)
+    phi = torch.from_numpy(phi0).to(dev)
+    prev = phi.clone()
+    psi = torch.zeros_like(phi)
+    nxt = torch.empty_like(phi)
+
+    def one():
+        nonlocal phi, prev, nxt
+        _, info = st.step(phi, prev, psi, nxt)
+        prev, phi, nxt = phi, nxt, prev
+        return info
+
+    for _ in range(args.warmup):
+        one()
+    cycles = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        info = one()
+        cycles.append(info.n_cycles)
+        if (k + 1) % 50 == 0:
+            print(f"[bench] {k + 1}/{args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    steps_per_s = args.steps / elapsed
+    total_cycles = int(sum(cycles))
+
+    # Live per-kernel timing of the two finest-level launches (HIP events on
+    # the library's stream), over a second timed region of the same workload.
+    st.profile(True)
+    for which in (0, 1):
+        st.profile_read(which, reset=True)
+    prof_steps = max(1, min(20, args.steps))
+    for _ in range(prof_steps):
+        one()
+    torch.cuda.synchronize()
+    timing = {}
+    for which, name in ((0, "down"), (1, "up")):
+        ms, launches, cells = st.profile_read(which, reset=True)
+        timing[name] = (ms, launches, cells)
+    st.profile(False)
+    dom = max(timing, key=lambda k: timing[k][0])
+    ms, launches, cells = timing[dom]
+    avg_s = ms / 1e3 / max(1, launches)
+    achieved = MODEL_BYTES[dom] * cells / avg_s / 1e9 if launches else None
+    compulsory = COMPULSORY_BYTES[dom] * cells / avg_s / 1e9 if launches else None
+    kernels = {k: {"avg_launch_us": 1e3 * v[0] / max(1, v[1]), "launches": v[1],
+                   "model_bytes_per_cell": MODEL_BYTES[k],
+                   "compulsory_bytes_per_cell": COMPULSORY_BYTES[k]} for k, v in timing.items()}
+    out = {
+        "metric": METRIC,
+        "value": steps_per_s,
+        "unit": "time-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"MPFC second-order scheme, FP64, {N}x{N} periodic, h=pi/4, eps=0.025, "
+                        "beta=0.9, M=1, dt=0.05, 0.07 liquid + 3 seeded crystallites (seed 2), "
+                        "FAS V(2,2) to residual 1e-10, energies every step"
+                        + (" (energies off)" if args.no_energy else ""),
+            "grid": [N, N], "scheme": 2, "cycle": "V(2,2)", "tol": tol,
+            "precision": "fp64", "guess": "extrapolated",
+        },
+        "roofline": {
+            "kernel": f"k_tile {dom} launch on the finest level (fused red-black passes)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS if achieved else None,
+            "traffic": None,
+            "bytes_per_launch": MODEL_BYTES[dom] * cells,
+            "avg_launch_us": avg_s * 1e6,
+            "compulsory_GBps": compulsory,
+            "frac_compulsory": compulsory / HBM_PEAK_GBPS if compulsory else None,
+            "timed_steps": prof_steps,
+            "kernels": kernels,
+        },
+        "extra": {
+            "vcycles_per_step": total_cycles / args.steps,
+            "unknowns_x_vcycles_per_s": 3.0 * N * N * total_cycles / elapsed,
+            "ms_per_vcycle": 1e3 * elapsed / max(1, total_cycles),
+        },
+    }
+    # The same workload with mixed precision (FP32 correction cycles inside
+    # FP64 defect correction), timed over its own region.
+    if args.variants:
+        out["variants"] = {"fp64": {"time_steps_per_s": steps_per_s,
+                                    "vcycles_per_step": total_cycles / args.steps}}
+        stm = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2,
+                          energy=0 if args.no_energy else 1, precision=1)
+        p_, q_, s_ = (torch.from_numpy(phi0).to(dev), torch.from_numpy(phi0).to(dev),
+                      torch.zeros_like(phi))
+        n_ = torch.empty_like(phi)
+        for _ in range(args.warmup):
+            stm.step(p_, q_, s_, n_)
+            q_, p_, n_ = p_, n_, q_
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        outer = inner = 0
+        vsteps = max(1, args.steps // 2)
+        for _ in range(vsteps):
+            _, inf = stm.step(p_, q_, s_, n_)
+            q_, p_, n_ = p_, n_, q_
+            outer += inf.outer_iters
+            inner += inf.n_cycles
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        out["variants"]["mixed"] = {"time_steps_per_s": vsteps / el, "steps": vsteps,
+                                    "outer_per_step": outer / vsteps,
+                                    "fp32_vcycles_per_step": inner / vsteps}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(params, phi0, tol, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

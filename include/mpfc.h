@@ -61,12 +61,18 @@ typedef struct {
 } mpfc_params;
 
 /* Solver options.  nu1/nu2: pre/post red-black smoothing passes per level
- * (App. B "l_max"); tol: stop when the finest residual norm
+ * (App. B "l_max"), each in [0, 4]; tol: stop when the finest residual norm
  * sqrt(h^2 sum_c sum_ij r_c^2) <= tol; max_cycles: V-cycle limit;
- * coarsest: side of the coarsest grid (2 or 4; the coarsest grid is solved
- * by dense Newton and must hold at most 16 cells); energy: 1 to compute the
- * energies of Sec. 3 after each step; diverge: factor of residual growth
- * over the initial residual reported as MPFC_EDIVERGED. */
+ * coarsest: smaller side of the coarsest grid, must be 2 (the coarsest grid,
+ * 2x2 or 2x4 cells, so m/n or n/m is at most 2, is solved directly by
+ * Newton's method); energy: 1 to compute the energies of Sec. 3 after each
+ * step; diverge: factor of residual growth over the initial residual
+ * reported as MPFC_EDIVERGED.
+ * precision = MPFC_MIXED: FP64 outer defect correction (FP64 finest residual,
+ * norm and stopping test; u updated in FP64) around inner_cycles FP32 FAS
+ * V-cycles per outer iteration on the correction equation N(u+e) - N(u) = r,
+ * whose nonlinear difference is evaluated in factored form; max_cycles then
+ * limits the outer iterations. */
 typedef struct {
     int nu1, nu2, max_cycles;
     double tol;
@@ -74,6 +80,7 @@ typedef struct {
     int coarsest;
     int energy;
     double diverge;
+    int inner_cycles;
 } mpfc_opts;
 
 /* Per-step report.  residual_history is a caller-owned host array of
@@ -133,6 +140,19 @@ int mpfc_step(mpfc_ctx *ctx, const double *d_phi_n, const double *d_phi_nm1, dou
 int mpfc_energies(mpfc_ctx *ctx, const double *d_phi, const double *d_phi_prev,
                   const double *d_psi, double *h_out);
 
+/* Live timing of the two finest-level launches of each V-cycle (the dominant
+ * kernels of the step) with HIP events on the context's stream:
+ * which = 0: the down launch (nu1 red-black passes of the App. B smoother,
+ * residual, restriction); which = 1: the up launch (coarse-grid correction,
+ * nu2 passes, residual norm).  what = 1 enables, 0 disables; while enabled
+ * the cycles are launched one by one instead of as a captured graph.
+ * mpfc_prof_read returns, since the last reset, the summed event-to-event
+ * duration in milliseconds, the number of launches timed and the cells of
+ * the finest grid each launch covers. */
+int mpfc_prof_enable(mpfc_ctx *ctx, int what);
+int mpfc_prof_read(mpfc_ctx *ctx, int which, double *h_total_ms, long long *h_launches,
+                   long long *h_cells_per_launch, int reset);
+
 void mpfc_destroy(mpfc_ctx *ctx);
 const char *mpfc_strerror(int code);
 const char *mpfc_last_error(void);
@@ -145,7 +165,8 @@ int mpfc_version(void);
 
 /* `sweeps` red-black nonlinear Gauss-Seidel passes (App. B), red
  * ((i+j) even) first, Newton (linearization 0) or Picard (1) local
- * linearisation, in place on (d_phi, d_mu, d_kappa). */
+ * linearisation, in place on (d_phi, d_mu, d_kappa); m, n >= 4.  Runs the
+ * fused tile kernel of the V-cycle and allocates a scratch copy of u. */
 int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double c, double alpha,
                    const double *d_phik, double *d_phi, double *d_mu, double *d_kappa,
                    const double *d_f1, const double *d_f2, const double *d_f3, int sweeps,
@@ -164,14 +185,6 @@ int mpfc_op_source(const mpfc_params *p, int m, int n, const double *d_phik,
 
 /* Average of the 2x2 fine cells under each coarse cell: (m/2) x (n/2) out. */
 int mpfc_op_restrict(int m, int n, const double *d_fine, double *d_coarse, void *stream);
-
-/* FAS coarse-grid correction of the three fields of u (m x n):
- * u_c += P (uH_c - vH_c), P bilinear (weights 9/16, 3/16, 3/16, 1/16 of the
- * four nearest coarse cells), uH and vH on the (m/2) x (n/2) grid. */
-int mpfc_op_prolong_correct(int m, int n, const double *d_uH0, const double *d_uH1,
-                            const double *d_uH2, const double *d_vH0, const double *d_vH1,
-                            const double *d_vH2, double *d_u0, double *d_u1, double *d_u2,
-                            void *stream);
 
 #ifdef __cplusplus
 }

@@ -88,6 +88,7 @@ def load():
         "orc_step": (i, [P, i, i, i, _dp, _dp, _dp, i, i, i, i, d, i,
                          _dp, _dp, _dp, _dp, _dp, _dp]),
         "orc_version": (i, []),
+        "orc_num_threads": (i, []),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -95,6 +96,10 @@ def load():
         f.argtypes = args
     _lib = lib
     return lib
+
+
+def num_threads() -> int:
+    return load().orc_num_threads()
 
 
 def _arr(a) -> np.ndarray:

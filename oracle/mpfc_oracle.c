@@ -41,6 +41,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define IX(i, j, m) ((size_t)(j) * (size_t)(m) + (size_t)(i))
 
@@ -707,3 +710,12 @@ int orc_step(const orc_model *p, int newton, int m, int n, const double *phik,
 }
 
 int orc_version(void) { return 1; }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

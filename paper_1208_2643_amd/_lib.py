@@ -38,7 +38,8 @@ class mpfc_opts(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("max_cycles", ctypes.c_int),
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("guess", ctypes.c_int),
                 ("linearization", ctypes.c_int), ("coarsest", ctypes.c_int),
-                ("energy", ctypes.c_int), ("diverge", ctypes.c_double)]
+                ("energy", ctypes.c_int), ("diverge", ctypes.c_double),
+                ("inner_cycles", ctypes.c_int)]
 
 
 class mpfc_info(ctypes.Structure):
@@ -68,6 +69,9 @@ SIGNATURES = {
                          ctypes.POINTER(mpfc_opts), _vp]),
     "mpfc_step": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(mpfc_info)]),
     "mpfc_energies": (_i, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "mpfc_prof_enable": (_i, [_vp, _i]),
+    "mpfc_prof_read": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong),
+                            ctypes.POINTER(ctypes.c_longlong), _i]),
     "mpfc_destroy": (None, [_vp]),
     "mpfc_strerror": (ctypes.c_char_p, [_i]),
     "mpfc_last_error": (ctypes.c_char_p, []),
@@ -79,7 +83,6 @@ SIGNATURES = {
     "mpfc_op_source": (_i, [ctypes.POINTER(mpfc_params), _i, _i, _vp, _vp, _vp, _vp, _vp, _vp,
                             _vp]),
     "mpfc_op_restrict": (_i, [_i, _i, _vp, _vp, _vp]),
-    "mpfc_op_prolong_correct": (_i, [_i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
 }
 
 

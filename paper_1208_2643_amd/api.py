@@ -110,6 +110,17 @@ class Stepper:
                       info.outer_iters)
         return phi_np1, si
 
+    def profile(self, on: bool = True):
+        """Time the two finest-level launches of every V-cycle with HIP events."""
+        L.check(self.lib.mpfc_prof_enable(self.ctx, 1 if on else 0))
+
+    def profile_read(self, which: int, reset: bool = True):
+        """(total ms, launches, finest cells) of the timed down (0) or up (1) launches."""
+        ms, n, cells = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_longlong()
+        L.check(self.lib.mpfc_prof_read(self.ctx, which, ctypes.byref(ms), ctypes.byref(n),
+                                        ctypes.byref(cells), 1 if reset else 0))
+        return ms.value, n.value, cells.value
+
     def energies(self, phi, phi_prev, psi):
         out = (ctypes.c_double * 4)()
         L.check(self.lib.mpfc_energies(self.ctx, _ptr(phi), _ptr(phi_prev), _ptr(psi), out))
@@ -176,10 +187,3 @@ def op_restrict(fine):
     out = torch.empty((n // 2, m // 2), dtype=fine.dtype, device=fine.device)
     L.check(lib.mpfc_op_restrict(m, n, _ptr(fine), _ptr(out), _stream()))
     return out
-
-
-def op_prolong_correct(uH, vH, u):
-    lib = L.load()
-    n, m = u[0].shape
-    L.check(lib.mpfc_op_prolong_correct(m, n, *[_ptr(x) for x in uH], *[_ptr(x) for x in vH],
-                                        *[_ptr(x) for x in u], _stream()))

@@ -148,21 +148,6 @@ __device__ __forceinline__ void relax_at(const Fields<T>& F, const LevelOp<T>& o
     F.ka[q] += dk;
 }
 
-// ---------------------------------------------------------------------------
-// One colour of a red-black sweep, in place (cells of one colour couple only
-// to the other colour).  colour = (i + j) & 1, red = 0.  Thread (k, j)
-// handles cell i = 2k + ((j + colour) & 1).
-template <typename T, int SCHEME, bool NEWTON, bool DEFECT>
-__global__ void __launch_bounds__(256) k_smooth_color(Fields<T> F, LevelOp<T> op, Grid g,
-                                                      int colour, const CycleState* st) {
-    if (stopped(st)) return;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (k >= (g.m >> 1) || j >= g.n) return;
-    const int i = 2 * k + ((j + colour) & 1);
-    relax_at<T, SCHEME, NEWTON, DEFECT>(F, op, g, i, j);
-}
-
 // r = f - N(u) on every cell (operator-level entry point).
 template <typename T, int SCHEME, bool DEFECT>
 __global__ void __launch_bounds__(256) k_residual_field(Fields<T> F, LevelOp<T> op, Grid g, T* r0,
@@ -174,92 +159,6 @@ __global__ void __launch_bounds__(256) k_residual_field(Fields<T> F, LevelOp<T> 
     residual_at<T, SCHEME, DEFECT>(F, op, g, i, j, a, b, c);
     const size_t q = at(i, j, g);
     r0[q] = a; r1[q] = b; r2[q] = c;
-}
-
-// ---------------------------------------------------------------------------
-// Residual on the fine grid, restricted with the 2x2 average, together with
-// the restriction of u (FAS): uH = vH = R u, fH = R r.  One thread per coarse
-// cell.
-template <typename T, int SCHEME, bool DEFECT>
-__global__ void __launch_bounds__(256) k_resid_restrict(Fields<T> F, LevelOp<T> op, Grid g,
-                                                        T* uH0, T* uH1, T* uH2, T* vH0, T* vH1,
-                                                        T* vH2, T* fH0, T* fH1, T* fH2,
-                                                        const CycleState* st) {
-    if (stopped(st)) return;
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    const int J = blockIdx.y * blockDim.y + threadIdx.y;
-    const int mc = g.m >> 1, nc = g.n >> 1;
-    if (I >= mc || J >= nc) return;
-    T s0 = 0, s1 = 0, s2 = 0, t0 = 0, t1 = 0, t2 = 0;
-#pragma unroll
-    for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-        for (int di = 0; di < 2; ++di) {
-            const int i = 2 * I + di, j = 2 * J + dj;
-            T r1, r2, r3;
-            residual_at<T, SCHEME, DEFECT>(F, op, g, i, j, r1, r2, r3);
-            const size_t q = at(i, j, g);
-            s0 += F.phi[q]; s1 += F.mu[q]; s2 += F.ka[q];
-            t0 += r1; t1 += r2; t2 += r3;
-        }
-    const size_t Q = (size_t)J * mc + I;
-    const T qt = T(0.25);
-    uH0[Q] = vH0[Q] = qt * s0;
-    uH1[Q] = vH1[Q] = qt * s1;
-    uH2[Q] = vH2[Q] = qt * s2;
-    fH0[Q] = qt * t0; fH1[Q] = qt * t1; fH2[Q] = qt * t2;
-}
-
-// FAS coarse right-hand side: f_H = N_H(u_H) + (R r), with R r already in f_H.
-template <typename T, int SCHEME, bool DEFECT>
-__global__ void __launch_bounds__(256) k_coarse_rhs(Fields<T> F, LevelOp<T> op, Grid g,
-                                                    T* f0, T* f1, T* f2, const CycleState* st) {
-    if (stopped(st)) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= g.m || j >= g.n) return;
-    const size_t q = at(i, j, g);
-    const T x = F.phi[q], y = F.mu[q], z = F.ka[q];
-    const T xk = (SCHEME == 2) ? F.phik[q] : T(0);
-    const T pb = DEFECT ? F.base[q] : T(0);
-    const T lphi = (nsum(F.phi, i, j, g) - T(4) * x) * op.ih2;
-    const T lmu = (nsum(F.mu, i, j, g) - T(4) * y) * op.ih2;
-    const T lka = (nsum(F.ka, i, j, g) - T(4) * z) * op.ih2;
-    f0[q] += x - op.c * lmu;
-    f1[q] += y - nl_value<T, SCHEME, DEFECT>(x, pb, xk) - op.al * x - lka;
-    f2[q] += z - op.e * lphi;
-}
-
-// Coarse-grid correction u_h += P (u_H - v_H), bilinear: a fine cell takes
-// 9/16 of its coarse parent, 3/16 of the coarse neighbours on its two outer
-// sides and 1/16 of the diagonal one.  One thread per fine cell.
-template <typename T>
-__global__ void __launch_bounds__(256) k_prolong_correct(T* u0, T* u1, T* u2, Grid g,
-                                                         const T* __restrict__ uH0,
-                                                         const T* __restrict__ uH1,
-                                                         const T* __restrict__ uH2,
-                                                         const T* __restrict__ vH0,
-                                                         const T* __restrict__ vH1,
-                                                         const T* __restrict__ vH2,
-                                                         const CycleState* st) {
-    if (stopped(st)) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= g.m || j >= g.n) return;
-    const int mc = g.m >> 1, nc = g.n >> 1;
-    const int I = i >> 1, J = j >> 1;
-    const int Is = ((i & 1) ? I + 1 : I - 1) & (mc - 1);
-    const int Js = ((j & 1) ? J + 1 : J - 1) & (nc - 1);
-    const size_t a = (size_t)J * mc + I, b = (size_t)J * mc + Is;
-    const size_t c = (size_t)Js * mc + I, d = (size_t)Js * mc + Is;
-    const size_t q = at(i, j, g);
-    const T w9 = T(9) / T(16), w3 = T(3) / T(16), w1 = T(1) / T(16);
-    u0[q] += w9 * (uH0[a] - vH0[a]) + w3 * ((uH0[b] - vH0[b]) + (uH0[c] - vH0[c])) +
-             w1 * (uH0[d] - vH0[d]);
-    u1[q] += w9 * (uH1[a] - vH1[a]) + w3 * ((uH1[b] - vH1[b]) + (uH1[c] - vH1[c])) +
-             w1 * (uH1[d] - vH1[d]);
-    u2[q] += w9 * (uH2[a] - vH2[a]) + w3 * ((uH2[b] - vH2[b]) + (uH2[c] - vH2[c])) +
-             w1 * (uH2[d] - vH2[d]);
 }
 
 // ---------------------------------------------------------------------------
@@ -336,100 +235,93 @@ __global__ void __launch_bounds__(NT) k_resnorm(Fields<double> F, LevelOp<double
     }
 }
 
+// Mixed precision, outer FP64 defect-correction step on the finest grid:
+// u += e (the FP32 correction), then r = S - N(u) in FP64 with its norm (the
+// stopping test, same bookkeeping as k_resnorm), and the inputs of the next
+// FP32 correction solve: r rounded to FP32, the base phi rounded to FP32, and
+// e reset to zero.  `add` = 0 skips the update (first residual of a step).
+// One thread per cell; the update of a cell's neighbours is recomputed from
+// u + e, so no other thread's write is read.
+template <int SCHEME, int NT>
+__global__ void __launch_bounds__(NT) k_defect(Fields<double> F, LevelOp<double> op, Grid g,
+                                               double h2, CycleState* st, double* hist,
+                                               double tol, int max_norms, double diverge,
+                                               const float* __restrict__ e0,
+                                               const float* __restrict__ e1,
+                                               const float* __restrict__ e2, int add,
+                                               double* un0, double* un1, double* un2,
+                                               float* r0, float* r1, float* r2, float* pbase) {
+    if (stopped(st)) return;
+    __shared__ double red[NT / 64];
+    __shared__ int last;
+    double acc = 0.0;
+    const size_t total = (size_t)g.m * g.n;
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
+        const int i = (int)(q & (size_t)(g.m - 1));
+        const int j = (int)(q >> g.lm);
+        const size_t nb[4] = {at(wrapx(i + 1, g), j, g), at(wrapx(i - 1, g), j, g),
+                              at(i, wrapy(j + 1, g), g), at(i, wrapy(j - 1, g), g)};
+        auto val = [&](const double* u, const float* e, size_t k) {
+            return add ? u[k] + (double)e[k] : u[k];
+        };
+        const double x = val(F.phi, e0, q), y = val(F.mu, e1, q), z = val(F.ka, e2, q);
+        double sx = 0, sy = 0, sz = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sx += val(F.phi, e0, nb[k]);
+            sy += val(F.mu, e1, nb[k]);
+            sz += val(F.ka, e2, nb[k]);
+        }
+        const double xk = SCHEME == 2 ? F.phik[q] : 0.0;
+        const double lphi = (sx - 4.0 * x) * op.ih2;
+        const double lmu = (sy - 4.0 * y) * op.ih2;
+        const double lka = (sz - 4.0 * z) * op.ih2;
+        const double a = F.f1[q] - (x - op.c * lmu);
+        const double b = F.f2[q] - (y - nl_value<double, SCHEME, false>(x, 0.0, xk) - op.al * x - lka);
+        const double c = F.f3[q] - (z - op.e * lphi);
+        acc += a * a + b * b + c * c;
+        un0[q] = x; un1[q] = y; un2[q] = z;
+        r0[q] = (float)a; r1[q] = (float)b; r2[q] = (float)c;
+        pbase[q] = (float)x;
+    }
+    const double bs = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) {
+        atomicAdd(&st->acc, bs);
+        __threadfence();
+        const unsigned t = atomicAdd(&st->blocks, 1u);
+        last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        const double s = atomicAdd(&st->acc, 0.0);
+        const double nr = sqrt(h2 * s);
+        const int k = st->count;
+        hist[k] = nr;
+        st->count = k + 1;
+        int status = ST_RUNNING;
+        if (!(nr == nr) || nr > 1.0e300) status = ST_NONFINITE;
+        else if (nr <= tol) status = ST_CONVERGED;
+        else if (k > 0 && nr > diverge * hist[0]) status = ST_DIVERGED;
+        else if (k + 1 >= max_norms) status = ST_MAXCYC;
+        st->status = status;
+        st->done = status != ST_RUNNING;
+        st->acc = 0.0;
+        st->blocks = 0u;
+        __threadfence();
+    }
+}
+
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) k_convert(const TI* __restrict__ a, TO* b, size_t n) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) b[q] = (TO)a[q];
+}
+
 __global__ void k_state_reset(CycleState* st) {
     if (threadIdx.x == 0) {
         st->acc = 0.0; st->blocks = 0u; st->count = 0;
         st->status = ST_RUNNING; st->done = 0; st->pad0 = st->pad1 = 0;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Coarsest grid: Newton's method with the exact Jacobian on all 3 m n
-// unknowns (m n <= 16), each linear system solved by Gaussian elimination
-// with partial pivoting, all in one workgroup of 64 threads.
-constexpr int CMAX = 48;
-
-template <typename T, int SCHEME, bool DEFECT>
-__global__ void __launch_bounds__(64) k_coarsest(Fields<T> F, LevelOp<T> op, Grid g, int maxit,
-                                                 T steptol, const CycleState* st) {
-    if (stopped(st)) return;
-    __shared__ T A[CMAX][CMAX + 1];
-    __shared__ T x[CMAX];
-    __shared__ int piv;
-    __shared__ int conv;
-    const int nc = g.m * g.n, nn = 3 * nc, t = threadIdx.x;
-    for (int it = 0; it < maxit; ++it) {
-        // Row t of the Jacobian and minus the residual.
-        if (t < nn) {
-            for (int cc = 0; cc <= nn; ++cc) A[t][cc] = T(0);
-            const int comp = t / nc, cell = t - comp * nc;
-            const int i = cell & (g.m - 1), j = cell >> g.lm;
-            const int nb[4] = {(int)at(wrapx(i + 1, g), j, g), (int)at(wrapx(i - 1, g), j, g),
-                               (int)at(i, wrapy(j + 1, g), g), (int)at(i, wrapy(j - 1, g), g)};
-            T r1, r2, r3;
-            residual_at<T, SCHEME, DEFECT>(F, op, g, i, j, r1, r2, r3);
-            if (comp == 0) {
-                A[t][cell] += T(1);
-                A[t][nc + cell] += T(4) * op.c * op.ih2;
-                for (int s = 0; s < 4; ++s) A[t][nc + nb[s]] -= op.c * op.ih2;
-                A[t][nn] = r1;
-            } else if (comp == 1) {
-                const T xk = (SCHEME == 2) ? F.phik[cell] : T(0);
-                const T pb = DEFECT ? F.base[cell] : T(0);
-                A[t][cell] -= op.al + nl_lin<T, SCHEME, true>(pb + F.phi[cell], xk);
-                A[t][nc + cell] += T(1);
-                A[t][2 * nc + cell] += T(4) * op.ih2;
-                for (int s = 0; s < 4; ++s) A[t][2 * nc + nb[s]] -= op.ih2;
-                A[t][nn] = r2;
-            } else {
-                A[t][2 * nc + cell] += T(1);
-                A[t][cell] += T(4) * op.e * op.ih2;
-                for (int s = 0; s < 4; ++s) A[t][nb[s]] -= op.e * op.ih2;
-                A[t][nn] = r3;
-            }
-        }
-        __syncthreads();
-        for (int k = 0; k < nn; ++k) {
-            if (t == 0) {
-                int p = k;
-                T best = fabs(A[k][k]);
-                for (int r = k + 1; r < nn; ++r) {
-                    const T v = fabs(A[r][k]);
-                    if (v > best) { best = v; p = r; }
-                }
-                piv = p;
-            }
-            __syncthreads();
-            const int p = piv;
-            if (p != k && t <= nn) {
-                const T tmp = A[k][t]; A[k][t] = A[p][t]; A[p][t] = tmp;
-            }
-            __syncthreads();
-            if (t > k && t < nn) {
-                const T fct = A[t][k] / A[k][k];
-                for (int cc = k; cc <= nn; ++cc) A[t][cc] -= fct * A[k][cc];
-            }
-            __syncthreads();
-        }
-        if (t == 0) {
-            T smax = 0, umax = 0;
-            for (int k = nn - 1; k >= 0; --k) {
-                T s = A[k][nn];
-                for (int cc = k + 1; cc < nn; ++cc) s -= A[k][cc] * x[cc];
-                x[k] = s / A[k][k];
-            }
-            for (int k = 0; k < nc; ++k) {
-                F.phi[k] += x[k];
-                F.mu[k] += x[nc + k];
-                F.ka[k] += x[2 * nc + k];
-                smax = fmax(smax, fmax(fabs(x[k]), fmax(fabs(x[nc + k]), fabs(x[2 * nc + k]))));
-                umax = fmax(umax, fmax(fabs(F.phi[k]), fmax(fabs(F.mu[k]), fabs(F.ka[k]))));
-            }
-            conv = (smax <= steptol * (T(1) + umax));
-            __threadfence();
-        }
-        __syncthreads();
-        if (conv) break;
     }
 }
 
@@ -442,12 +334,13 @@ __global__ void __launch_bounds__(256) k_source(Grid g, double ih2, double d, do
                                                 const double* __restrict__ phik,
                                                 const double* __restrict__ phikm1,
                                                 const double* __restrict__ psik, double* S1,
-                                                double* S2, double* S3) {
+                                                double* S2, double* S3, double* phik_copy) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.m || j >= g.n) return;
     const size_t q = at(i, j, g);
     const double pk = phik[q];
+    if (phik_copy) phik_copy[q] = pk;
     const double lk = (nsum(phik, i, j, g) - 4.0 * pk) * ih2;
     S1[q] = pk + d * psik[q];
     if constexpr (SCHEME == 1) {
@@ -512,14 +405,18 @@ __global__ void __launch_bounds__(256) k_restrict(Grid g, const TI* __restrict__
 
 // psi^{k+1}: (phi - phi^k)/s (scheme 1, eq. discrete_1_b) or
 // (2/s)(phi - phi^k) - psi^k (scheme 2, eq. discrete_2_b); in place on psi.
+// phi is also copied to phi_out (the caller's phi^{k+1}).
 template <int SCHEME>
 __global__ void __launch_bounds__(256) k_psi_update(size_t total, double s,
                                                     const double* __restrict__ phi,
-                                                    const double* __restrict__ phik, double* psi) {
+                                                    const double* __restrict__ phik, double* psi,
+                                                    double* phi_out) {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= total) return;
-    if constexpr (SCHEME == 1) psi[q] = (phi[q] - phik[q]) / s;
-    else psi[q] = (2.0 / s) * (phi[q] - phik[q]) - psi[q];
+    const double x = phi[q];
+    if constexpr (SCHEME == 1) psi[q] = (x - phik[q]) / s;
+    else psi[q] = (2.0 / s) * (x - phik[q]) - psi[q];
+    phi_out[q] = x;
 }
 
 }  // namespace mpfc

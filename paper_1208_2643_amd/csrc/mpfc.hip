@@ -4,15 +4,20 @@
 // A step of either convex-splitting scheme (Sec. 3.1, 3.2) solves N(u) = S
 // (App. B.1, B.2) by FAS V(nu1, nu2) cycles: red-black nonlinear Gauss-Seidel
 // smoothing, residual and 2x2-average restriction, FAS coarse right-hand
-// side, dense Newton on the coarsest grid, bilinear prolongation of the
-// coarse-grid correction.  The cycle loop is stopped by a device-side test on
-// the finest residual norm; the host reads back one small status record per
-// cycle.  Afterwards psi is updated (eqs. discrete_1_b / discrete_2_b) and,
-// optionally, the energies of Sec. 3 are computed.
+// side, direct solve on the coarsest grid, bilinear prolongation of the
+// coarse-grid correction.  Levels above 32x32 cells take two fused tile
+// launches per cycle (tiles.hpp); all smaller levels take one persistent
+// launch.  One V-cycle is captured once into a hipGraph and replayed.  The
+// stopping test runs on the device (the finest up-launch records the
+// residual norm and raises a stop flag that every later kernel checks), so
+// the host only reads back a small status record per cycle.  Afterwards psi
+// is updated (eqs. discrete_1_b / discrete_2_b) and the energies of Sec. 3
+// are computed, the -1 norm with the same multigrid on the Poisson problem.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -21,6 +26,7 @@
 #include "../../include/mpfc.h"
 #include "kernels.hpp"
 #include "poisson.hpp"
+#include "tiles.hpp"
 
 using namespace mpfc;
 
@@ -46,6 +52,7 @@ int ilog2(int v) {
     while ((1 << l) < v) ++l;
     return l;
 }
+int round_even(int v) { return (v + 1) & ~1; }
 
 Grid make_grid(int m, int n) { return Grid{m, n, ilog2(m), ilog2(n)}; }
 
@@ -58,15 +65,27 @@ unsigned red_blocks(size_t total) {
     return (unsigned)(b < 1024 ? b : 1024);
 }
 
+// Tile shapes (interior TX x TY, largest halo HMAX) instantiated for the
+// tiled levels.  Variant 0 serves halos up to 6 (nu <= 2), variant 1 up to 10.
+struct TileShape { int tx, ty, hmax; };
+constexpr TileShape kShapes[] = {{64, 32, 6}, {64, 16, 10}};
+
 struct Level {
     int m = 0, n = 0;
     double h = 0;
     Grid g{};
-    double *phi = nullptr, *mu = nullptr, *ka = nullptr;
-    double *v0 = nullptr, *v1 = nullptr, *v2 = nullptr;
-    double *f0 = nullptr, *f1 = nullptr, *f2 = nullptr;
-    double* phik = nullptr;
-    double *w = nullptr, *b = nullptr;  // Poisson correction and right-hand side
+    bool tiled = false;     // more than CP_CELLS cells: fused tile launches
+    // MPFC system
+    double* u[2][3] = {};   // ping-pong; u[0] holds the iterate between cycles
+    double* v[3] = {};      // restricted iterate (coarse levels)
+    double* f[3] = {};      // complete right-hand side (finest: S)
+    double* rr[3] = {};     // restricted residual (coarse levels)
+    double* xk = nullptr;   // phi^k on this level (scheme 2)
+    // Poisson problem of the -1 norm
+    double* w[2] = {};
+    double* pv = nullptr;
+    double* pf = nullptr;   // finest: b = psi - mean(psi)
+    double* prr = nullptr;
 };
 
 }  // namespace
@@ -78,7 +97,8 @@ struct mpfc_ctx {
     hipStream_t stream = nullptr;
     double c = 0, d = 0, alpha = 0;
     std::vector<Level> L;
-    double *mu_int = nullptr, *ka_int = nullptr;
+    int Lp = 0;                 // first level handled by the persistent kernel
+    double* phik = nullptr;     // copy of phi^k (finest)
     CycleState* st = nullptr;   // nonlinear cycle state
     double* hist = nullptr;     // device residual history
     CycleState* pst = nullptr;  // Poisson cycle state
@@ -86,14 +106,38 @@ struct mpfc_ctx {
     double* acc = nullptr;      // reduction accumulators
     double* G = nullptr;        // coarsest Poisson Green's matrix
     int have_w = 0;
+    int poisson_cycles = 3;
     void* arena = nullptr;
     size_t arena_bytes = 0;
     CycleState* host_st = nullptr;  // pinned readback
     double* host_buf = nullptr;     // pinned readback (history / sums)
+    // hipGraphs of one V-cycle (MPFC, Poisson); rebuilt when profiling toggles
+    bool use_graph = true;
+    hipGraphExec_t gx_mpfc = nullptr, gx_poisson = nullptr;
+    hipStream_t cap_stream = nullptr;  // capture only (the caller's stream may be the null stream)
+    // live timing of the finest-level launches (HIP events on `stream`)
+    int prof = 0;
+    hipEvent_t ev[4] = {};
+    double prof_ms[2] = {0, 0};       // finest down, finest up
+    long long prof_launches[2] = {0, 0};
+    // mixed precision: FP32 correction cycles inside FP64 defect correction
+    struct FLevel {
+        float* e[2][3] = {};  // correction, ping-pong
+        float* v[3] = {};
+        float* f[3] = {};     // finest: FP64 residual rounded to FP32
+        float* rr[3] = {};
+        float* xk = nullptr;  // phi^k (FP32) on this level
+        float* pb = nullptr;  // base phi (FP32) on this level
+    };
+    std::vector<FLevel> FL;
+    int inner_cycles = 3;
+    int mp_cur = 0;                        // FP64 copy of u holding the iterate
+    hipGraphExec_t gx_mixed[2] = {};       // one outer iteration, from copy 0 / copy 1
 };
 
 namespace {
 
+// ---- operators per level --------------------------------------------------------
 LevelOp<double> level_op(const mpfc_ctx* C, const Level& lv) {
     LevelOp<double> op;
     op.ih2 = 1.0 / (lv.h * lv.h);
@@ -103,53 +147,156 @@ LevelOp<double> level_op(const mpfc_ctx* C, const Level& lv) {
     return op;
 }
 
-Fields<double> level_fields(const Level& lv) {
+template <class Op>
+Op make_op(const mpfc_ctx* C, const Level& lv) {
+    if constexpr (Op::NF == 3) {
+        Op o;
+        o.op = level_op(C, lv);
+        return o;
+    } else {
+        Op o;
+        o.ih2 = 1.0 / (lv.h * lv.h);
+        o.h2 = lv.h * lv.h;
+        return o;
+    }
+}
+
+Fields<double> finest_fields(const mpfc_ctx* C) {
+    const Level& lv = C->L[0];
     Fields<double> F;
-    F.phi = lv.phi; F.mu = lv.mu; F.ka = lv.ka;
-    F.f1 = lv.f0; F.f2 = lv.f1; F.f3 = lv.f2;
-    F.phik = lv.phik;
+    F.phi = lv.u[0][0]; F.mu = lv.u[0][1]; F.ka = lv.u[0][2];
+    F.f1 = lv.f[0]; F.f2 = lv.f[1]; F.f3 = lv.f[2];
+    F.phik = C->p.scheme == 2 ? C->phik : nullptr;
     F.base = nullptr;
     return F;
 }
 
-// ---- templated launchers ---------------------------------------------------
-template <int S, bool NW>
-void launch_smooth(const mpfc_ctx* C, const Level& lv, int sweeps, const CycleState* st,
-                   hipStream_t s) {
-    const Fields<double> F = level_fields(lv);
-    const LevelOp<double> op = level_op(C, lv);
-    const dim3 gr = grid2(lv.m / 2, lv.n);
-    for (int k = 0; k < sweeps; ++k)
-        for (int colour = 0; colour < 2; ++colour)
-            hipLaunchKernelGGL((k_smooth_color<double, S, NW, false>), gr, B2, 0, s, F, op, lv.g,
-                               colour, st);
+// ---- launches -----------------------------------------------------------------------
+template <class Op, bool UP>
+void launch_tile(const Op& op, const TileArgs<typename Op::real>& A, int shape,
+                 const CycleState* stop, hipStream_t s) {
+    const dim3 grid(A.g.m / A.tx, A.g.n / A.ty);
+    if (shape == 0)
+        hipLaunchKernelGGL((k_tile<Op, 64, 32, 6, UP>), grid, dim3(256), 0, s, op, A, stop);
+    else
+        hipLaunchKernelGGL((k_tile<Op, 64, 16, 10, UP>), grid, dim3(256), 0, s, op, A, stop);
 }
 
-void smooth(const mpfc_ctx* C, const Level& lv, int sweeps, const CycleState* st, hipStream_t s) {
-    const bool nw = C->o.linearization == MPFC_NEWTON;
-    if (C->p.scheme == 1) {
-        if (nw) launch_smooth<1, true>(C, lv, sweeps, st, s);
-        else launch_smooth<1, false>(C, lv, sweeps, st, s);
-    } else {
-        if (nw) launch_smooth<2, true>(C, lv, sweeps, st, s);
-        else launch_smooth<2, false>(C, lv, sweeps, st, s);
+int pick_shape(int H) { return H <= kShapes[0].hmax ? 0 : 1; }
+
+void tile_dims(const Level& lv, int shape, int& tx, int& ty) {
+    tx = lv.m < kShapes[shape].tx ? lv.m : kShapes[shape].tx;
+    ty = lv.n < kShapes[shape].ty ? lv.n : kShapes[shape].ty;
+}
+
+CoarseGeom coarse_geom(const mpfc_ctx* C) {
+    CoarseGeom G{};
+    G.nlev = (int)C->L.size() - C->Lp;
+    int off = 0;
+    for (int k = 0; k < G.nlev; ++k) {
+        const Level& lv = C->L[C->Lp + k];
+        G.m[k] = lv.m; G.n[k] = lv.n; G.lm[k] = lv.g.lm;
+        G.off[k] = off;
+        off += lv.m * lv.n;
+    }
+    return G;
+}
+
+void prof_mark(mpfc_ctx* C, int which, hipStream_t s) {
+    (void)hipEventRecord(C->ev[which], s);
+}
+
+void prof_collect(mpfc_ctx* C) {
+    for (int k = 0; k < 2; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, C->ev[2 * k], C->ev[2 * k + 1]) == hipSuccess) {
+            C->prof_ms[k] += ms;
+            C->prof_launches[k] += 1;
+        }
     }
 }
 
-template <int S>
-void launch_restrict_pair(const mpfc_ctx* C, const Level& A, const Level& Bc, const CycleState* st,
-                          hipStream_t s) {
-    hipLaunchKernelGGL((k_resid_restrict<double, S, false>), grid2(Bc.m, Bc.n), B2, 0, s,
-                       level_fields(A), level_op(C, A), A.g, Bc.phi, Bc.mu, Bc.ka, Bc.v0, Bc.v1,
-                       Bc.v2, Bc.f0, Bc.f1, Bc.f2, st);
-    hipLaunchKernelGGL((k_coarse_rhs<double, S, false>), grid2(Bc.m, Bc.n), B2, 0, s,
-                       level_fields(Bc), level_op(C, Bc), Bc.g, Bc.f0, Bc.f1, Bc.f2, st);
-}
-
-template <int S>
-void launch_coarsest(const mpfc_ctx* C, const Level& lv, const CycleState* st, hipStream_t s) {
-    hipLaunchKernelGGL((k_coarsest<double, S, false>), dim3(1), dim3(64), 0, s, level_fields(lv),
-                       level_op(C, lv), lv.g, 30, 1e-15, st);
+// One FAS V-cycle of the MPFC system on all levels.
+template <class Op>
+void vcycle_mpfc_t(mpfc_ctx* C, hipStream_t s) {
+    const int nl = (int)C->L.size(), Lp = C->Lp;
+    const CycleState* stop = C->st;
+    const int nsw1 = 2 * C->o.nu1, nsw2 = 2 * C->o.nu2;
+    for (int l = 0; l < Lp; ++l) {
+        const Level& A = C->L[l];
+        const Level& B = C->L[l + 1];
+        TileArgs<double> T{};
+        T.g = A.g;
+        for (int f = 0; f < 3; ++f) {
+            T.uin[f] = A.u[0][f];
+            T.uout[f] = A.u[1][f];
+            T.f[f] = l == 0 ? A.f[f] : A.rr[f];
+            T.fout[f] = A.f[f];
+            T.uH[f] = B.u[0][f];
+            T.vH[f] = B.v[f];
+            T.rH[f] = B.rr[f];
+        }
+        T.xk = A.xk;
+        T.complete_f = l > 0;
+        T.nsweep = nsw1;
+        T.H = round_even(nsw1 + 1);
+        const int shape = pick_shape(T.H);
+        tile_dims(A, shape, T.tx, T.ty);
+        if (l == 0 && C->prof) prof_mark(C, 0, s);
+        launch_tile<Op, false>(make_op<Op>(C, A), T, shape, stop, s);
+        if (l == 0 && C->prof) prof_mark(C, 1, s);
+    }
+    if (Lp < nl) {
+        const Level& top = C->L[Lp];
+        CoarseArgs<double> A{};
+        A.geo = coarse_geom(C);
+        for (int f = 0; f < 3; ++f) {
+            A.u[f] = top.u[0][f];
+            A.rr[f] = Lp > 0 ? top.rr[f] : top.f[f];
+        }
+        A.xk = top.xk;
+        A.h_top = top.h;
+        A.nsw1 = nsw1;
+        A.nsw2 = nsw2;
+        A.complete_top = Lp > 0;
+        A.newton_maxit = 30;
+        A.newton_tol = 1e-15;
+        const Level& cl = C->L[nl - 1];
+        if (cl.m * cl.n == 4)
+            hipLaunchKernelGGL((k_coarse_persistent<Op, 256, 4>), dim3(1), dim3(256), 0, s,
+                               make_op<Op>(C, top), A, stop);
+        else
+            hipLaunchKernelGGL((k_coarse_persistent<Op, 256, 8>), dim3(1), dim3(256), 0, s,
+                               make_op<Op>(C, top), A, stop);
+    }
+    for (int l = Lp - 1; l >= 0; --l) {
+        const Level& A = C->L[l];
+        const Level& B = C->L[l + 1];
+        TileArgs<double> T{};
+        T.g = A.g;
+        for (int f = 0; f < 3; ++f) {
+            T.uin[f] = A.u[1][f];
+            T.uout[f] = A.u[0][f];
+            T.f[f] = A.f[f];
+            T.cuH[f] = B.u[0][f];
+            T.cvH[f] = B.v[f];
+        }
+        T.xk = A.xk;
+        T.nsweep = nsw2;
+        T.norm = l == 0;
+        T.H = l == 0 ? round_even(nsw2 + 1) : nsw2;
+        T.nst = C->st;
+        T.hist = C->hist;
+        T.tol = C->o.tol;
+        T.diverge = C->o.diverge;
+        T.h2 = A.h * A.h;
+        T.max_norms = C->o.max_cycles + 1;
+        const int shape = pick_shape(T.H);
+        tile_dims(A, shape, T.tx, T.ty);
+        if (l == 0 && C->prof) prof_mark(C, 2, s);
+        launch_tile<Op, true>(make_op<Op>(C, A), T, shape, stop, s);
+        if (l == 0 && C->prof) prof_mark(C, 3, s);
+    }
 }
 
 void resnorm(mpfc_ctx* C, hipStream_t s) {
@@ -159,33 +306,270 @@ void resnorm(mpfc_ctx* C, hipStream_t s) {
     const int max_norms = C->o.max_cycles + 1;
     if (C->p.scheme == 1)
         hipLaunchKernelGGL((k_resnorm<1, NT>), dim3(red_blocks(total)), dim3(NT), 0, s,
-                           level_fields(lv), level_op(C, lv), lv.g, h2, C->st, C->hist, C->o.tol,
+                           finest_fields(C), level_op(C, lv), lv.g, h2, C->st, C->hist, C->o.tol,
                            max_norms, C->o.diverge, nullptr, nullptr, nullptr);
     else
         hipLaunchKernelGGL((k_resnorm<2, NT>), dim3(red_blocks(total)), dim3(NT), 0, s,
-                           level_fields(lv), level_op(C, lv), lv.g, h2, C->st, C->hist, C->o.tol,
+                           finest_fields(C), level_op(C, lv), lv.g, h2, C->st, C->hist, C->o.tol,
                            max_norms, C->o.diverge, nullptr, nullptr, nullptr);
 }
 
-// One FAS V(nu1, nu2) cycle on all levels, then the finest residual norm.
-void vcycle(mpfc_ctx* C, hipStream_t s) {
-    const int nl = (int)C->L.size();
-    const CycleState* st = C->st;
-    for (int l = 0; l < nl - 1; ++l) {
-        smooth(C, C->L[l], C->o.nu1, st, s);
-        if (C->p.scheme == 1) launch_restrict_pair<1>(C, C->L[l], C->L[l + 1], st, s);
-        else launch_restrict_pair<2>(C, C->L[l], C->L[l + 1], st, s);
-    }
-    if (C->p.scheme == 1) launch_coarsest<1>(C, C->L[nl - 1], st, s);
-    else launch_coarsest<2>(C, C->L[nl - 1], st, s);
-    for (int l = nl - 2; l >= 0; --l) {
+// ---- mixed precision ---------------------------------------------------------------
+// One FP32 FAS V-cycle on the correction equation N(u + e) - N(u) = r (DEFECT
+// operators: the base phi of every level is a coefficient field).
+template <class Op>
+void vcycle_inner_t(mpfc_ctx* C, hipStream_t s) {
+    using T = float;
+    const int nl = (int)C->L.size(), Lp = C->Lp;
+    const CycleState* stop = C->st;
+    const int nsw1 = 2 * C->o.nu1, nsw2 = 2 * C->o.nu2;
+    auto op_of = [&](const Level& lv) {
+        Op o;
+        o.op.ih2 = (T)(1.0 / (lv.h * lv.h));
+        o.op.c = (T)C->c;
+        o.op.al = (T)(C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha);
+        o.op.e = (T)(C->p.scheme == 1 ? 1.0 : 0.5);
+        return o;
+    };
+    for (int l = 0; l < Lp; ++l) {
         const Level& A = C->L[l];
-        const Level& Bc = C->L[l + 1];
-        hipLaunchKernelGGL((k_prolong_correct<double>), grid2(A.m, A.n), B2, 0, s, A.phi, A.mu,
-                           A.ka, A.g, Bc.phi, Bc.mu, Bc.ka, Bc.v0, Bc.v1, Bc.v2, st);
-        smooth(C, A, C->o.nu2, st, s);
+        const auto& FA = C->FL[l];
+        const auto& FB = C->FL[l + 1];
+        TileArgs<T> Tg{};
+        Tg.g = A.g;
+        for (int f = 0; f < 3; ++f) {
+            Tg.uin[f] = FA.e[0][f];
+            Tg.uout[f] = FA.e[1][f];
+            Tg.f[f] = l == 0 ? FA.f[f] : FA.rr[f];
+            Tg.fout[f] = FA.f[f];
+            Tg.uH[f] = FB.e[0][f];
+            Tg.vH[f] = FB.v[f];
+            Tg.rH[f] = FB.rr[f];
+        }
+        Tg.xk = FA.xk;
+        Tg.pb = FA.pb;
+        Tg.complete_f = l > 0;
+        Tg.nsweep = nsw1;
+        Tg.H = round_even(nsw1 + 1);
+        const int shape = pick_shape(Tg.H);
+        tile_dims(A, shape, Tg.tx, Tg.ty);
+        launch_tile<Op, false>(op_of(A), Tg, shape, stop, s);
     }
-    resnorm(C, s);
+    if (Lp < nl) {
+        const Level& top = C->L[Lp];
+        const auto& FT = C->FL[Lp];
+        CoarseArgs<T> A{};
+        A.geo = coarse_geom(C);
+        for (int f = 0; f < 3; ++f) {
+            A.u[f] = FT.e[0][f];
+            A.rr[f] = Lp > 0 ? FT.rr[f] : FT.f[f];
+        }
+        A.xk = FT.xk;
+        A.pb = FT.pb;
+        A.h_top = (T)top.h;
+        A.nsw1 = nsw1;
+        A.nsw2 = nsw2;
+        A.complete_top = Lp > 0;
+        A.newton_maxit = 20;
+        A.newton_tol = 1e-6f;
+        const Level& cl = C->L[nl - 1];
+        if (cl.m * cl.n == 4)
+            hipLaunchKernelGGL((k_coarse_persistent<Op, 256, 4>), dim3(1), dim3(256), 0, s,
+                               op_of(top), A, stop);
+        else
+            hipLaunchKernelGGL((k_coarse_persistent<Op, 256, 8>), dim3(1), dim3(256), 0, s,
+                               op_of(top), A, stop);
+    }
+    for (int l = Lp - 1; l >= 0; --l) {
+        const Level& A = C->L[l];
+        const auto& FA = C->FL[l];
+        const auto& FB = C->FL[l + 1];
+        TileArgs<T> Tg{};
+        Tg.g = A.g;
+        for (int f = 0; f < 3; ++f) {
+            Tg.uin[f] = FA.e[1][f];
+            Tg.uout[f] = FA.e[0][f];
+            Tg.f[f] = FA.f[f];
+            Tg.cuH[f] = FB.e[0][f];
+            Tg.cvH[f] = FB.v[f];
+        }
+        Tg.xk = FA.xk;
+        Tg.pb = FA.pb;
+        Tg.nsweep = nsw2;
+        Tg.norm = 0;
+        Tg.H = nsw2;
+        const int shape = pick_shape(Tg.H);
+        tile_dims(A, shape, Tg.tx, Tg.ty);
+        launch_tile<Op, true>(op_of(A), Tg, shape, stop, s);
+    }
+}
+
+// FP64 defect step on the finest grid: u[to] = u[from] + e (add) or u[from],
+// r = S - N(u[to]) with its norm (stopping test), r and base phi to FP32.
+void defect(mpfc_ctx* C, int from, int add, hipStream_t s) {
+    const Level& F0 = C->L[0];
+    const auto& FF = C->FL[0];
+    const size_t total = (size_t)F0.m * F0.n;
+    Fields<double> F;
+    F.phi = F0.u[from][0]; F.mu = F0.u[from][1]; F.ka = F0.u[from][2];
+    F.f1 = F0.f[0]; F.f2 = F0.f[1]; F.f3 = F0.f[2];
+    F.phik = C->p.scheme == 2 ? C->phik : nullptr;
+    F.base = nullptr;
+    const int to = from ^ 1;
+    const int max_norms = C->o.max_cycles + 1;
+    auto kern = C->p.scheme == 1 ? k_defect<1, NT> : k_defect<2, NT>;
+    hipLaunchKernelGGL(kern, dim3(red_blocks(total)), dim3(NT), 0, s, F, level_op(C, F0), F0.g,
+                       F0.h * F0.h, C->st, C->hist, C->o.tol, max_norms, C->o.diverge,
+                       FF.e[0][0], FF.e[0][1], FF.e[0][2], add, F0.u[to][0], F0.u[to][1],
+                       F0.u[to][2], FF.f[0], FF.f[1], FF.f[2], FF.pb);
+}
+
+// One outer iteration of mixed precision starting from FP64 copy `from`:
+// e = 0, base-phi pyramid, `inner_cycles` FP32 V-cycles, then the FP64 defect
+// step into the other copy.
+void outer_mixed(mpfc_ctx* C, int from, hipStream_t s) {
+    const int nl = (int)C->L.size();
+    const auto& FF = C->FL[0];
+    const size_t total = (size_t)C->m * C->n;
+    for (int f = 0; f < 3; ++f)
+        hipLaunchKernelGGL((k_fill<float>), grid1(total), dim3(256), 0, s, FF.e[0][f], total, 0.f);
+    for (int l = 1; l < nl; ++l)
+        hipLaunchKernelGGL((k_restrict<float, float>), grid2(C->L[l].m, C->L[l].n), B2, 0, s,
+                           C->L[l - 1].g, C->FL[l - 1].pb, C->FL[l].pb);
+    const bool nw = C->o.linearization == MPFC_NEWTON;
+    for (int k = 0; k < C->inner_cycles; ++k) {
+        if (C->p.scheme == 1) {
+            if (nw) vcycle_inner_t<MpfcOp<float, 1, true, true>>(C, s);
+            else vcycle_inner_t<MpfcOp<float, 1, false, true>>(C, s);
+        } else {
+            if (nw) vcycle_inner_t<MpfcOp<float, 2, true, true>>(C, s);
+            else vcycle_inner_t<MpfcOp<float, 2, false, true>>(C, s);
+        }
+    }
+    defect(C, from, 1, s);
+}
+
+void vcycle_mpfc(mpfc_ctx* C, hipStream_t s) {
+    const bool nw = C->o.linearization == MPFC_NEWTON;
+    if (C->p.scheme == 1) {
+        if (nw) vcycle_mpfc_t<MpfcOp<double, 1, true, false>>(C, s);
+        else vcycle_mpfc_t<MpfcOp<double, 1, false, false>>(C, s);
+    } else {
+        if (nw) vcycle_mpfc_t<MpfcOp<double, 2, true, false>>(C, s);
+        else vcycle_mpfc_t<MpfcOp<double, 2, false, false>>(C, s);
+    }
+    if (C->Lp == 0) resnorm(C, s);
+}
+
+// One V-cycle of the Poisson problem -Lap_h w = b (same structure, scalar).
+void vcycle_poisson(mpfc_ctx* C, hipStream_t s) {
+    using Op = PoissonOp<double>;
+    const int nl = (int)C->L.size(), Lp = C->Lp;
+    const CycleState* stop = C->pst;
+    for (int l = 0; l < Lp; ++l) {
+        const Level& A = C->L[l];
+        const Level& B = C->L[l + 1];
+        TileArgs<double> T{};
+        T.g = A.g;
+        T.uin[0] = A.w[0]; T.uout[0] = A.w[1];
+        T.f[0] = l == 0 ? A.pf : A.prr;
+        T.fout[0] = A.pf;
+        T.uH[0] = B.w[0]; T.vH[0] = B.pv; T.rH[0] = B.prr;
+        T.complete_f = l > 0;
+        T.nsweep = 4;
+        T.H = 6;
+        tile_dims(A, 0, T.tx, T.ty);
+        launch_tile<Op, false>(make_op<Op>(C, A), T, 0, stop, s);
+    }
+    if (Lp < nl) {
+        const Level& top = C->L[Lp];
+        CoarseArgs<double> A{};
+        A.geo = coarse_geom(C);
+        A.u[0] = top.w[0];
+        A.rr[0] = Lp > 0 ? top.prr : top.pf;
+        A.h_top = top.h;
+        A.nsw1 = 4;
+        A.nsw2 = 4;
+        A.complete_top = Lp > 0;
+        A.G = C->G;
+        hipLaunchKernelGGL((k_coarse_persistent<Op, 256, 4>), dim3(1), dim3(256), 0, s,
+                           make_op<Op>(C, top), A, stop);
+    }
+    for (int l = Lp - 1; l >= 0; --l) {
+        const Level& A = C->L[l];
+        const Level& B = C->L[l + 1];
+        TileArgs<double> T{};
+        T.g = A.g;
+        T.uin[0] = A.w[1]; T.uout[0] = A.w[0];
+        T.f[0] = A.pf;
+        T.cuH[0] = B.w[0]; T.cvH[0] = B.pv;
+        T.nsweep = 4;
+        T.norm = l == 0;
+        T.H = l == 0 ? 6 : 4;
+        T.nst = C->pst;
+        T.hist = C->phist;
+        T.tol = 0.0;   // the host compares with rtol * ||b||
+        T.diverge = 1e300;
+        T.h2 = 1.0;    // plain l2 norm of the Poisson residual
+        T.max_norms = 60;
+        tile_dims(A, 0, T.tx, T.ty);
+        launch_tile<Op, true>(make_op<Op>(C, A), T, 0, stop, s);
+    }
+    if (Lp == 0) {
+        const Level& F0 = C->L[0];
+        hipLaunchKernelGGL((k_p_resnorm<NT>), dim3(red_blocks((size_t)F0.m * F0.n)), dim3(NT), 0,
+                           s, F0.w[0], F0.pf, F0.g, 1.0 / (F0.h * F0.h), C->pst, C->phist,
+                           C->acc + 9, 0.0, 60);
+    }
+}
+
+// What one replayable unit of work is.
+enum CycleKind { CYC_MPFC = 0, CYC_POISSON = 1, CYC_MIXED0 = 2, CYC_MIXED1 = 3 };
+
+void enqueue(mpfc_ctx* C, int kind, hipStream_t s) {
+    switch (kind) {
+        case CYC_MPFC: vcycle_mpfc(C, s); break;
+        case CYC_POISSON: vcycle_poisson(C, s); break;
+        case CYC_MIXED0: outer_mixed(C, 0, s); break;
+        default: outer_mixed(C, 1, s); break;
+    }
+}
+
+// Replay one unit (a V-cycle, or one mixed-precision outer iteration) from a
+// graph captured on first use; launched directly while profiling.
+int run_cycle(mpfc_ctx* C, int kind) {
+    hipStream_t s = C->stream;
+    if (!C->use_graph || C->prof) {
+        enqueue(C, kind, s);
+        HIP_TRY(hipGetLastError());
+        return MPFC_OK;
+    }
+    hipGraphExec_t& gx = kind == CYC_MPFC ? C->gx_mpfc
+                         : kind == CYC_POISSON ? C->gx_poisson
+                                               : C->gx_mixed[kind - CYC_MIXED0];
+    if (!gx) {
+        // Record the launches on a context-owned stream (nothing executes while
+        // capturing), then replay the graph on the caller's stream.
+        if (!C->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&C->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(C->cap_stream, hipStreamCaptureModeThreadLocal));
+        enqueue(C, kind, C->cap_stream);
+        hipError_t le = hipGetLastError();
+        hipError_t ce = hipStreamEndCapture(C->cap_stream, &g);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(MPFC_EHIP, std::string("graph capture: ") +
+                                       hipGetErrorString(le != hipSuccess ? le : ce));
+        }
+        hipError_t ie = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            gx = nullptr;
+            return fail(MPFC_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+        }
+    }
+    HIP_TRY(hipGraphLaunch(gx, s));
+    return MPFC_OK;
 }
 
 // Periodic mean-zero Green's matrix of -Lap_h on an m x n grid of spacing h,
@@ -222,12 +606,12 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
     if (!is_pow2(m) || !is_pow2(n) || m < 2 || n < 2)
         return fail(MPFC_EINVAL, "m and n must be powers of two >= 2");
     if ((long long)m * n > (1LL << 28)) return fail(MPFC_EINVAL, "grid too large (m*n > 2^28)");
-    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 || o->nu1 > 8 || o->nu2 > 8)
-        return fail(MPFC_EINVAL, "nu1, nu2 must be in [0, 8] with nu1 + nu2 >= 1");
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 || o->nu1 > 4 || o->nu2 > 4)
+        return fail(MPFC_EINVAL, "nu1, nu2 must be in [0, 4] with nu1 + nu2 >= 1");
     if (o->max_cycles < 1 || o->max_cycles > 100000)
         return fail(MPFC_EINVAL, "max_cycles must be in [1, 100000]");
     if (!(o->tol > 0)) return fail(MPFC_EINVAL, "tol must be > 0");
-    if (!(o->coarsest == 2 || o->coarsest == 4)) return fail(MPFC_EINVAL, "coarsest must be 2 or 4");
+    if (o->coarsest != 2) return fail(MPFC_EINVAL, "coarsest must be 2");
     if (!(o->precision == MPFC_FP64 || o->precision == MPFC_MIXED))
         return fail(MPFC_EINVAL, "precision must be MPFC_FP64 or MPFC_MIXED");
     if (!(o->guess == MPFC_GUESS_PREV || o->guess == MPFC_GUESS_EXTRAP))
@@ -235,11 +619,22 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
     if (!(o->linearization == MPFC_NEWTON || o->linearization == MPFC_PICARD))
         return fail(MPFC_EINVAL, "unknown linearization");
     if (!(o->diverge > 1.0)) return fail(MPFC_EINVAL, "diverge must be > 1");
+    if (o->inner_cycles < 1 || o->inner_cycles > 16)
+        return fail(MPFC_EINVAL, "inner_cycles must be in [1, 16]");
     // coarsest grid: coarsen while the smaller side exceeds `coarsest`
     int mm = m, nn = n;
     while ((mm < nn ? mm : nn) > o->coarsest) { mm /= 2; nn /= 2; }
-    if (mm * nn > CMAX / 3)
-        return fail(MPFC_EINVAL, "aspect ratio too large: coarsest grid exceeds 16 cells");
+    if (mm * nn > 8)
+        return fail(MPFC_EINVAL, "aspect ratio above 2: the coarsest grid must be 2x2 or 2x4");
+    // the levels of at most 32x32 cells must fit the persistent kernel
+    int cells = 0;
+    mm = m; nn = n;
+    for (;;) {
+        if (mm * nn <= CP_CELLS) cells += mm * nn;
+        if ((mm < nn ? mm : nn) <= o->coarsest) break;
+        mm /= 2; nn /= 2;
+    }
+    if (cells > CP_TOTAL) return fail(MPFC_EINVAL, "internal: coarse levels exceed the LDS budget");
     return MPFC_OK;
 }
 
@@ -253,58 +648,64 @@ int status_code(int st) {
     }
 }
 
-// Energies of (phi, phi_prev, psi) into out[0..3].
+// Energies of (phi, phi_prev, psi) into out[0..3].  When `mu` is given (the
+// step's chemical potential) the previous Poisson solution is first advanced
+// by the scheme's own relation between psi^{k+1}, psi^k and Lap mu, which
+// leaves only the solver residual for the Poisson cycles to remove.
 int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, const double* psi,
-                     double* out) {
+                     const double* mu, double* out) {
     hipStream_t s = C->stream;
-    const Level& F0 = C->L[0];
+    Level& F0 = C->L[0];
     const size_t total = (size_t)C->m * C->n;
     const unsigned rb = red_blocks(total);
-    const int nl = (int)C->L.size();
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, C->acc, 16);
     hipLaunchKernelGGL((k_sum<NT>), dim3(rb), dim3(NT), 0, s, psi, total, C->acc + 8);
-    hipLaunchKernelGGL((k_p_rhs<NT>), dim3(rb), dim3(NT), 0, s, psi, total, C->acc + 8, F0.b,
+    hipLaunchKernelGGL((k_p_rhs<NT>), dim3(rb), dim3(NT), 0, s, psi, total, C->acc + 8, F0.pf,
                        C->acc + 9);
-    if (!C->have_w)
-        hipLaunchKernelGGL((k_fill<double>), grid1(total), dim3(256), 0, s, F0.w, total, 0.0);
-    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->pst);
-    const int pmax = 60;
-    const double rtol = 1e-13;
-    const double ih2_0 = 1.0 / (F0.h * F0.h);
-    hipLaunchKernelGGL((k_p_resnorm<NT>), dim3(rb), dim3(NT), 0, s, F0.w, F0.b, F0.g, ih2_0,
-                       C->pst, C->phist, C->acc + 9, rtol, pmax);
-    for (int cyc = 0; cyc < pmax; ++cyc) {
-        for (int l = 0; l < nl - 1; ++l) {
-            const Level& A = C->L[l];
-            const Level& Bc = C->L[l + 1];
-            for (int sw = 0; sw < 2; ++sw)
-                for (int colour = 0; colour < 2; ++colour)
-                    hipLaunchKernelGGL(k_p_smooth_color, grid2(A.m / 2, A.n), B2, 0, s, A.w, A.b,
-                                       A.g, A.h * A.h, colour, C->pst);
-            hipLaunchKernelGGL(k_p_resid_restrict, grid2(Bc.m, Bc.n), B2, 0, s, A.w, A.b, A.g,
-                               1.0 / (A.h * A.h), Bc.w, Bc.b, C->pst);
-        }
-        const Level& Cl = C->L[nl - 1];
-        hipLaunchKernelGGL(k_p_coarsest, dim3(1), dim3(64), 0, s, Cl.w, Cl.b, C->G, Cl.m * Cl.n,
-                           C->pst);
-        for (int l = nl - 2; l >= 0; --l) {
-            const Level& A = C->L[l];
-            hipLaunchKernelGGL(k_p_prolong, grid2(A.m, A.n), B2, 0, s, A.w, A.g, C->L[l + 1].w,
-                               C->pst);
-            for (int sw = 0; sw < 2; ++sw)
-                for (int colour = 0; colour < 2; ++colour)
-                    hipLaunchKernelGGL(k_p_smooth_color, grid2(A.m / 2, A.n), B2, 0, s, A.w, A.b,
-                                       A.g, A.h * A.h, colour, C->pst);
-        }
-        hipLaunchKernelGGL((k_p_resnorm<NT>), dim3(rb), dim3(NT), 0, s, F0.w, F0.b, F0.g, ih2_0,
-                           C->pst, C->phist, C->acc + 9, rtol, pmax);
-        HIP_TRY(hipMemcpyAsync(C->host_st, C->pst, sizeof(CycleState), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (C->host_st->done) break;
+    if (!C->have_w) {
+        hipLaunchKernelGGL((k_fill<double>), grid1(total), dim3(256), 0, s, F0.w[0], total, 0.0);
+    } else if (mu) {
+        const double sb = C->p.dt * C->p.beta, sM = C->p.dt * C->p.M;
+        double a, b;
+        if (C->p.scheme == 1) { a = 1.0 / (1.0 + sb); b = sM / (1.0 + sb); }
+        else { a = (1.0 - 0.5 * sb) / (1.0 + 0.5 * sb); b = sM / (1.0 + 0.5 * sb); }
+        hipLaunchKernelGGL((k_sum<NT>), dim3(rb), dim3(NT), 0, s, mu, total, C->acc + 10);
+        hipLaunchKernelGGL((k_w_advance), grid1(total), dim3(256), 0, s, F0.w[0], mu, total, a, b,
+                           C->acc + 10);
     }
+    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->pst);
+    HIP_TRY(hipGetLastError());
+    int ran = 0;
+    for (int k = 0; k < C->poisson_cycles; ++k, ++ran) {
+        int rc = run_cycle(C, CYC_POISSON);
+        if (rc) return rc;
+    }
+    double res = 0.0, bn = 0.0, prev_res = 1e300;
+    bool ok = false;
+    for (;;) {
+        HIP_TRY(hipMemcpyAsync(C->host_buf, C->acc, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(C->host_st, C->pst, sizeof(CycleState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(C->host_buf + 16, C->phist, 64 * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const int cnt = C->host_st->count;
+        res = cnt > 0 ? C->host_buf[16 + cnt - 1] : 1e300;
+        prev_res = cnt > 1 ? C->host_buf[16 + cnt - 2] : 1e300;
+        bn = std::sqrt(C->host_buf[9]);
+        // converged, or stalled at the rounding floor of the Poisson operator
+        ok = res <= 1e-11 * bn || bn == 0.0 || (res <= 1e-8 * bn && res > 0.5 * prev_res);
+        if (ok || C->host_st->done || ran >= 50) break;
+        int rc = run_cycle(C, CYC_POISSON);
+        if (rc) return rc;
+        ++ran;
+    }
+    // keep the number of warm cycles just large enough
+    if (ran > C->poisson_cycles) C->poisson_cycles = ran < 8 ? ran : 8;
+    else if (ran == C->poisson_cycles && C->poisson_cycles > 1 && res <= 1e-3 * 1e-11 * bn)
+        C->poisson_cycles -= 1;
     C->have_w = 1;
-    hipLaunchKernelGGL((k_energy_terms<NT>), dim3(rb), dim3(NT), 0, s, F0.g, ih2_0, phi, phiprev,
-                       F0.b, F0.w, C->acc);
+    hipLaunchKernelGGL((k_energy_terms<NT>), dim3(rb), dim3(NT), 0, s, F0.g, 1.0 / (F0.h * F0.h),
+                       phi, phiprev, F0.pf, F0.w[0], C->acc);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(C->host_buf, C->acc, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -316,8 +717,7 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
     out[1] = Fe + nm1 / (2.0 * C->p.M);
     out[2] = out[1] + 0.5 * a[5];
     out[3] = h2 * a[4];
-    if (C->host_st->status == ST_NONFINITE)
-        return fail(MPFC_ENONFINITE, "non-finite residual in the Poisson solve of the -1 norm");
+    if (!ok) return fail(MPFC_ENOTCONVERGED, "Poisson solve of the -1 norm did not converge");
     return MPFC_OK;
 }
 
@@ -336,6 +736,7 @@ void mpfc_default_opts(mpfc_opts* o) {
     o->coarsest = 2;
     o->energy = 1;
     o->diverge = 1e8;
+    o->inner_cycles = 3;
 }
 
 int mpfc_validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
@@ -359,14 +760,31 @@ const char* mpfc_strerror(int code) {
 
 const char* mpfc_last_error(void) { return g_last_error.c_str(); }
 
+int mpfc_prof_enable(mpfc_ctx* C, int what) {
+    if (!C || what < 0 || what > 1) return fail(MPFC_EINVAL, "mpfc_prof_enable: bad arguments");
+    if (what && !C->ev[0])
+        for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&C->ev[k]));
+    C->prof = what;
+    return MPFC_OK;
+}
+
+int mpfc_prof_read(mpfc_ctx* C, int which, double* total_ms, long long* launches,
+                   long long* cells, int reset) {
+    if (!C || !total_ms || !launches || !cells || which < 0 || which > 1)
+        return fail(MPFC_EINVAL, "mpfc_prof_read: bad arguments");
+    *total_ms = C->prof_ms[which];
+    *launches = C->prof_launches[which];
+    *cells = (long long)C->m * C->n;
+    if (reset) { C->prof_ms[which] = 0.0; C->prof_launches[which] = 0; }
+    return MPFC_OK;
+}
+
 int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_opts* o,
                 void* stream) {
     if (!out) return fail(MPFC_EINVAL, "out is NULL");
     *out = nullptr;
     int rc = validate(m, n, p, o);
     if (rc) return rc;
-    if (o->precision != MPFC_FP64)
-        return fail(MPFC_EINVAL, "mixed precision is not available in this build");
     mpfc_ctx* C = new (std::nothrow) mpfc_ctx();
     if (!C) return fail(MPFC_ENOMEM, "host allocation failed");
     C->m = m; C->n = n; C->p = *p; C->o = *o;
@@ -375,6 +793,10 @@ int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_o
     const double q = p->scheme == 1 ? 1.0 : 2.0;
     C->c = p->dt * p->M / (p->beta + q / p->dt);
     C->d = q / (p->beta + q / p->dt);
+    const char* ng = std::getenv("MPFC_NO_GRAPH");
+    C->use_graph = !(ng && ng[0] == '1');
+    C->inner_cycles = o->inner_cycles;
+    const bool mixed = o->precision == MPFC_MIXED;
     // level hierarchy
     {
         int mm = m, nn = n;
@@ -382,16 +804,18 @@ int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_o
         for (;;) {
             Level lv;
             lv.m = mm; lv.n = nn; lv.h = h; lv.g = make_grid(mm, nn);
+            lv.tiled = (long long)mm * nn > CP_CELLS;
             C->L.push_back(lv);
             if ((mm < nn ? mm : nn) <= o->coarsest) break;
             mm /= 2; nn /= 2; h *= 2.0;
         }
     }
     const int nl = (int)C->L.size();
+    C->Lp = nl;
+    for (int l = 0; l < nl; ++l)
+        if (!C->L[l].tiled) { C->Lp = l; break; }
     // Arena layout in doubles, every piece 256-byte aligned: the same function
     // sizes the arena (base == nullptr) and then assigns the pointers.
-    auto fieldsz = [](const Level& lv) { return (size_t)lv.m * lv.n; };
-    const size_t N0 = fieldsz(C->L[0]);
     const Level& Lc = C->L[nl - 1];
     const size_t nG = (size_t)(Lc.m * Lc.n) * (Lc.m * Lc.n);
     auto layout = [&](double* base) {
@@ -401,22 +825,44 @@ int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_o
             off += (cnt + 31) & ~(size_t)31;
             return r;
         };
-        Level& F0 = C->L[0];
-        F0.f0 = take(N0); F0.f1 = take(N0); F0.f2 = take(N0);
-        C->mu_int = take(N0); C->ka_int = take(N0);
-        F0.w = take(N0); F0.b = take(N0);
-        for (int l = 1; l < nl; ++l) {
+        for (int l = 0; l < nl; ++l) {
             Level& lv = C->L[l];
-            const size_t Nl = fieldsz(lv);
-            lv.phi = take(Nl); lv.mu = take(Nl); lv.ka = take(Nl);
-            lv.v0 = take(Nl); lv.v1 = take(Nl); lv.v2 = take(Nl);
-            lv.f0 = take(Nl); lv.f1 = take(Nl); lv.f2 = take(Nl);
-            lv.phik = take(Nl);
-            lv.w = take(Nl); lv.b = take(Nl);
+            const size_t Nl = (size_t)lv.m * lv.n;
+            for (int f = 0; f < 3; ++f) {
+                lv.u[0][f] = take(Nl);
+                lv.u[1][f] = (l < C->Lp || (l == 0 && mixed)) ? take(Nl) : nullptr;
+                lv.f[f] = take(Nl);
+                lv.v[f] = l > 0 ? take(Nl) : nullptr;
+                lv.rr[f] = l > 0 ? take(Nl) : nullptr;
+            }
+            lv.xk = (p->scheme == 2) ? take(Nl) : nullptr;
+            lv.w[0] = take(Nl);
+            lv.w[1] = (l < C->Lp) ? take(Nl) : nullptr;
+            lv.pf = take(Nl);
+            lv.pv = l > 0 ? take(Nl) : nullptr;
+            lv.prr = l > 0 ? take(Nl) : nullptr;
+        }
+        C->phik = C->L[0].xk ? C->L[0].xk : take((size_t)m * n);
+        if (mixed) {
+            auto take_f = [&](size_t cnt) { return (float*)take((cnt + 1) / 2); };
+            C->FL.assign(nl, mpfc_ctx::FLevel{});
+            for (int l = 0; l < nl; ++l) {
+                auto& F = C->FL[l];
+                const size_t Nl = (size_t)C->L[l].m * C->L[l].n;
+                for (int f = 0; f < 3; ++f) {
+                    F.e[0][f] = take_f(Nl);
+                    F.e[1][f] = l < C->Lp ? take_f(Nl) : nullptr;
+                    F.v[f] = l > 0 ? take_f(Nl) : nullptr;
+                    F.f[f] = take_f(Nl);
+                    F.rr[f] = l > 0 ? take_f(Nl) : nullptr;
+                }
+                F.xk = p->scheme == 2 ? take_f(Nl) : nullptr;
+                F.pb = take_f(Nl);
+            }
         }
         C->G = take(nG);
         C->hist = take(o->max_cycles + 1 + 8);
-        C->phist = take(o->max_cycles + 1 + 8);
+        C->phist = take(64);
         C->acc = take(64);
         C->st = (CycleState*)take(16);
         C->pst = (CycleState*)take(16);
@@ -433,7 +879,7 @@ int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_o
     green_matrix(Lc.m, Lc.n, Lc.h, G);
     e = hipHostMalloc((void**)&C->host_st, sizeof(CycleState) * 2, hipHostMallocDefault);
     if (e == hipSuccess)
-        e = hipHostMalloc((void**)&C->host_buf, sizeof(double) * (size_t)(o->max_cycles + 64),
+        e = hipHostMalloc((void**)&C->host_buf, sizeof(double) * (size_t)(o->max_cycles + 128),
                           hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipMemcpy(C->G, G.data(), nG * sizeof(double), hipMemcpyHostToDevice);
@@ -447,6 +893,13 @@ int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_o
 
 void mpfc_destroy(mpfc_ctx* C) {
     if (!C) return;
+    if (C->gx_mpfc) (void)hipGraphExecDestroy(C->gx_mpfc);
+    if (C->gx_poisson) (void)hipGraphExecDestroy(C->gx_poisson);
+    for (hipGraphExec_t g : C->gx_mixed)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (C->cap_stream) (void)hipStreamDestroy(C->cap_stream);
+    for (hipEvent_t e : C->ev)
+        if (e) (void)hipEventDestroy(e);
     if (C->arena) (void)hipFree(C->arena);
     if (C->host_st) (void)hipHostFree(C->host_st);
     if (C->host_buf) (void)hipHostFree(C->host_buf);
@@ -463,70 +916,91 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     hipStream_t s = C->stream;
     const int nl = (int)C->L.size();
     Level& F0 = C->L[0];
-    F0.phi = phi_np1;
-    F0.mu = mu_out ? mu_out : C->mu_int;
-    F0.ka = ka_out ? ka_out : C->ka_int;
-    F0.phik = C->p.scheme == 2 ? const_cast<double*>(phi_n) : nullptr;
+    const Grid g0 = F0.g;
     const size_t total = (size_t)C->m * C->n;
     const double ih2 = 1.0 / (F0.h * F0.h);
-    // source, phi^k pyramid, guess and its completion
+    double* phi = F0.u[0][0];
+    double* mu = F0.u[0][1];
+    double* ka = F0.u[0][2];
+    // source (also copies phi^k), phi^k pyramid, guess and its completion
     if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_source<1>), grid2(C->m, C->n), B2, 0, s, F0.g, ih2, C->d, C->alpha,
-                           phi_n, phi_nm1, psi, F0.f0, F0.f1, F0.f2);
+        hipLaunchKernelGGL((k_source<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
+                           phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik);
     else
-        hipLaunchKernelGGL((k_source<2>), grid2(C->m, C->n), B2, 0, s, F0.g, ih2, C->d, C->alpha,
-                           phi_n, phi_nm1, psi, F0.f0, F0.f1, F0.f2);
+        hipLaunchKernelGGL((k_source<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
+                           phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik);
     if (C->p.scheme == 2)
         for (int l = 1; l < nl; ++l)
             hipLaunchKernelGGL((k_restrict<double, double>), grid2(C->L[l].m, C->L[l].n), B2, 0, s,
-                               C->L[l - 1].g, C->L[l - 1].phik, C->L[l].phik);
-    else
-        for (int l = 1; l < nl; ++l) C->L[l].phik = nullptr;
-    hipLaunchKernelGGL(k_guess, grid1(total), dim3(256), 0, s, F0.g,
-                       C->o.guess == MPFC_GUESS_EXTRAP ? 1 : 0, phi_n, phi_nm1, F0.phi);
+                               C->L[l - 1].g, C->L[l - 1].xk, C->L[l].xk);
+    hipLaunchKernelGGL(k_guess, grid1(total), dim3(256), 0, s, g0,
+                       C->o.guess == MPFC_GUESS_EXTRAP ? 1 : 0, phi_n, phi_nm1, phi);
     const double e = C->p.scheme == 1 ? 1.0 : 0.5;
     const double al = C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha;
-    hipLaunchKernelGGL(k_complete_kappa, grid2(C->m, C->n), B2, 0, s, F0.g, ih2, e, F0.phi, F0.f2,
-                       F0.ka);
+    hipLaunchKernelGGL(k_complete_kappa, grid2(C->m, C->n), B2, 0, s, g0, ih2, e, phi, F0.f[2], ka);
     if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_complete_mu<1>), grid2(C->m, C->n), B2, 0, s, F0.g, ih2, al, F0.phi,
-                           F0.phik, F0.ka, F0.f1, F0.mu);
+        hipLaunchKernelGGL((k_complete_mu<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, phi,
+                           C->phik, ka, F0.f[1], mu);
     else
-        hipLaunchKernelGGL((k_complete_mu<2>), grid2(C->m, C->n), B2, 0, s, F0.g, ih2, al, F0.phi,
-                           F0.phik, F0.ka, F0.f1, F0.mu);
+        hipLaunchKernelGGL((k_complete_mu<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, phi,
+                           C->phik, ka, F0.f[1], mu);
     hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->st);
-    resnorm(C, s);
+    const bool mixed = C->o.precision == MPFC_MIXED;
+    int cur = 0;
+    if (!mixed) {
+        resnorm(C, s);
+    } else {
+        // FP32 coefficient pyramids, then the first FP64 defect (copy 0 -> 1)
+        const auto& FF = C->FL[0];
+        if (C->p.scheme == 2) {
+            hipLaunchKernelGGL((k_convert<double, float>), grid1(total), dim3(256), 0, s, C->phik,
+                               FF.xk, total);
+            for (int l = 1; l < nl; ++l)
+                hipLaunchKernelGGL((k_restrict<float, float>), grid2(C->L[l].m, C->L[l].n), B2, 0,
+                                   s, C->L[l - 1].g, C->FL[l - 1].xk, C->FL[l].xk);
+        }
+        defect(C, 0, 0, s);
+        cur = 1;
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(C->host_st, C->st, sizeof(CycleState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (int guard = 0; !C->host_st->done; ++guard) {
         if (guard > C->o.max_cycles + 1)
             return fail(MPFC_EHIP, "internal: cycle state did not advance");
-        vcycle(C, s);
-        HIP_TRY(hipGetLastError());
+        int rc = run_cycle(C, mixed ? CYC_MIXED0 + cur : CYC_MPFC);
+        if (rc) return rc;
+        if (mixed) cur ^= 1;
         HIP_TRY(hipMemcpyAsync(C->host_st, C->st, sizeof(CycleState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (C->prof && C->Lp > 0 && !mixed) prof_collect(C);
     }
     const CycleState fin = *C->host_st;
-    const int ncyc = fin.count - 1;
-    // psi update
+    const int nouter = fin.count - 1;
+    const int ncyc = mixed ? nouter * C->inner_cycles : nouter;
+    phi = F0.u[cur][0];
+    mu = F0.u[cur][1];
+    ka = F0.u[cur][2];
+    // psi update, copy-out of phi^{k+1} (and mu, kappa)
     if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_psi_update<1>), grid1(total), dim3(256), 0, s, total, C->p.dt, F0.phi,
-                           phi_n, psi);
+        hipLaunchKernelGGL((k_psi_update<1>), grid1(total), dim3(256), 0, s, total, C->p.dt, phi,
+                           phi_n, psi, phi_np1);
     else
-        hipLaunchKernelGGL((k_psi_update<2>), grid1(total), dim3(256), 0, s, total, C->p.dt, F0.phi,
-                           phi_n, psi);
+        hipLaunchKernelGGL((k_psi_update<2>), grid1(total), dim3(256), 0, s, total, C->p.dt, phi,
+                           phi_n, psi, phi_np1);
+    if (mu_out) HIP_TRY(hipMemcpyAsync(mu_out, mu, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (ka_out) HIP_TRY(hipMemcpyAsync(ka_out, ka, total * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipGetLastError());
     const int rc = status_code(fin.status);
     double en[4] = {0, 0, 0, 0};
     if (C->o.energy) {
-        const int erc = compute_energies(C, F0.phi, phi_n, psi, en);
-        if (erc && erc != MPFC_ENONFINITE) return erc;
+        const int erc = compute_energies(C, phi, phi_n, psi, mu, en);
+        if (erc && erc != MPFC_ENOTCONVERGED) return erc;
     }
     if (info) {
         info->n_cycles = ncyc;
         info->status = rc;
-        info->outer_iters = 0;
+        info->outer_iters = mixed ? nouter : 0;
         info->energy_F = en[0];
         info->energy_pseudo = en[1];
         info->energy_mod = en[2];
@@ -552,10 +1026,13 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
 int mpfc_energies(mpfc_ctx* C, const double* phi, const double* phi_prev, const double* psi,
                   double* out) {
     if (!C || !phi || !psi || !out) return fail(MPFC_EINVAL, "ctx, phi, psi and out are required");
-    return compute_energies(C, phi, phi_prev, psi, out);
+    return compute_energies(C, phi, phi_prev, psi, nullptr, out);
 }
 
 // ---- operator-level entry points --------------------------------------------
+// Red-black sweeps through the same fused tile kernel the V-cycle uses (down
+// direction without the restriction outputs); a scratch copy keeps the
+// ping-pong between launches.
 int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double c, double alpha,
                    const double* phik, double* phi, double* mu, double* ka, const double* f1,
                    const double* f2, const double* f3, int sweeps, void* stream) {
@@ -563,17 +1040,58 @@ int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double
         sweeps < 0 || !(h > 0) || !phi || !mu || !ka || !f1 || !f2 || !f3 ||
         (scheme == 2 && !phik))
         return fail(MPFC_EINVAL, "mpfc_op_smooth: bad arguments");
-    mpfc_ctx C;
-    C.p.scheme = scheme;
-    C.c = c; C.alpha = alpha;
-    C.o.linearization = linearization;
+    if (m < 4 || n < 4) return fail(MPFC_EINVAL, "mpfc_op_smooth: m, n >= 4");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = (size_t)m * n;
+    double* tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, 3 * N * sizeof(double) + 3 * (N / 4 + 1) * sizeof(double)));
+    double* cz = tmp + 3 * N;  // coarse outputs land here and are discarded
+    double* a[3] = {phi, mu, ka};
+    double* b[3] = {tmp, tmp + N, tmp + 2 * N};
+    LevelOp<double> lop;
+    lop.ih2 = 1.0 / (h * h); lop.c = c;
+    lop.al = scheme == 1 ? alpha : 0.5 * alpha;
+    lop.e = scheme == 1 ? 1.0 : 0.5;
     Level lv;
-    lv.m = m; lv.n = n; lv.h = h; lv.g = make_grid(m, n);
-    lv.phi = phi; lv.mu = mu; lv.ka = ka;
-    lv.f0 = const_cast<double*>(f1); lv.f1 = const_cast<double*>(f2); lv.f2 = const_cast<double*>(f3);
-    lv.phik = const_cast<double*>(phik);
-    smooth(&C, lv, sweeps, nullptr, (hipStream_t)stream);
+    lv.m = m; lv.n = n; lv.g = make_grid(m, n);
+    int done = 0;
+    while (done < sweeps) {
+        const int k = (sweeps - done) >= 2 ? 2 : 1;
+        TileArgs<double> T{};
+        T.g = lv.g;
+        for (int f = 0; f < 3; ++f) {
+            T.uin[f] = a[f]; T.uout[f] = b[f];
+            T.uH[f] = cz; T.vH[f] = cz; T.rH[f] = cz;
+        }
+        T.f[0] = f1; T.f[1] = f2; T.f[2] = f3;
+        T.xk = phik;
+        T.nsweep = 2 * k;
+        T.H = round_even(2 * k + 1);
+        T.complete_f = 0;
+        T.norm = 0;
+        tile_dims(lv, 0, T.tx, T.ty);
+        if (scheme == 1) {
+            MpfcOp<double, 1, true, false> on{lop};
+            MpfcOp<double, 1, false, false> op{lop};
+            if (linearization == MPFC_NEWTON) launch_tile<decltype(on), false>(on, T, 0, nullptr, s);
+            else launch_tile<decltype(op), false>(op, T, 0, nullptr, s);
+        } else {
+            MpfcOp<double, 2, true, false> on{lop};
+            MpfcOp<double, 2, false, false> op{lop};
+            if (linearization == MPFC_NEWTON) launch_tile<decltype(on), false>(on, T, 0, nullptr, s);
+            else launch_tile<decltype(op), false>(op, T, 0, nullptr, s);
+        }
+        for (int f = 0; f < 3; ++f) { double* t = a[f]; a[f] = b[f]; b[f] = t; }
+        done += k;
+    }
+    if (a[0] != phi)
+        for (int f = 0; f < 3; ++f) {
+            double* dst = f == 0 ? phi : (f == 1 ? mu : ka);
+            HIP_TRY(hipMemcpyAsync(dst, a[f], N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipFree(tmp));
     return MPFC_OK;
 }
 
@@ -616,10 +1134,10 @@ int mpfc_op_source(const mpfc_params* p, int m, int n, const double* phik, const
     hipStream_t s = (hipStream_t)stream;
     if (p->scheme == 1)
         hipLaunchKernelGGL((k_source<1>), grid2(m, n), B2, 0, s, g, 1.0 / (p->h * p->h), d,
-                           1.0 - p->eps, phik, phikm1, psik, S1, S2, S3);
+                           1.0 - p->eps, phik, phikm1, psik, S1, S2, S3, nullptr);
     else
         hipLaunchKernelGGL((k_source<2>), grid2(m, n), B2, 0, s, g, 1.0 / (p->h * p->h), d,
-                           1.0 - p->eps, phik, phikm1, psik, S1, S2, S3);
+                           1.0 - p->eps, phik, phikm1, psik, S1, S2, S3, nullptr);
     HIP_TRY(hipGetLastError());
     return MPFC_OK;
 }
@@ -629,18 +1147,6 @@ int mpfc_op_restrict(int m, int n, const double* fine, double* coarse, void* str
         return fail(MPFC_EINVAL, "mpfc_op_restrict: bad arguments");
     hipLaunchKernelGGL((k_restrict<double, double>), grid2(m / 2, n / 2), B2, 0,
                        (hipStream_t)stream, make_grid(m, n), fine, coarse);
-    HIP_TRY(hipGetLastError());
-    return MPFC_OK;
-}
-
-int mpfc_op_prolong_correct(int m, int n, const double* uH0, const double* uH1,
-                            const double* uH2, const double* vH0, const double* vH1,
-                            const double* vH2, double* u0, double* u1, double* u2, void* stream) {
-    if (!is_pow2(m) || !is_pow2(n) || m < 4 || n < 4 || !uH0 || !uH1 || !uH2 || !vH0 || !vH1 ||
-        !vH2 || !u0 || !u1 || !u2)
-        return fail(MPFC_EINVAL, "mpfc_op_prolong_correct: bad arguments");
-    hipLaunchKernelGGL((k_prolong_correct<double>), grid2(m, n), B2, 0, (hipStream_t)stream, u0,
-                       u1, u2, make_grid(m, n), uH0, uH1, uH2, vH0, vH1, vH2, nullptr);
     HIP_TRY(hipGetLastError());
     return MPFC_OK;
 }

@@ -63,83 +63,18 @@ __global__ void __launch_bounds__(NT) k_p_rhs(const double* __restrict__ psi, si
     block_atomic_add<NT>(s, red, acc);
 }
 
-// One colour of red-black Gauss-Seidel for -Lap_h w = b:
-// w_ij = (h^2 b_ij + sum of neighbours)/4.
-__global__ void __launch_bounds__(256) k_p_smooth_color(double* w, const double* __restrict__ b,
-                                                        Grid g, double h2, int colour,
-                                                        const CycleState* st) {
-    if (stopped(st)) return;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (k >= (g.m >> 1) || j >= g.n) return;
-    const int i = 2 * k + ((j + colour) & 1);
-    const size_t q = at(i, j, g);
-    w[q] = 0.25 * (h2 * b[q] + nsum(w, i, j, g));
-}
-
-// bH = 2x2 average of the residual b + Lap_h w; wH = 0.
-__global__ void __launch_bounds__(256) k_p_resid_restrict(const double* __restrict__ w,
-                                                          const double* __restrict__ b, Grid g,
-                                                          double ih2, double* wH, double* bH,
-                                                          const CycleState* st) {
-    if (stopped(st)) return;
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    const int J = blockIdx.y * blockDim.y + threadIdx.y;
-    const int mc = g.m >> 1, nc = g.n >> 1;
-    if (I >= mc || J >= nc) return;
-    double s = 0.0;
-#pragma unroll
-    for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-        for (int di = 0; di < 2; ++di) {
-            const int i = 2 * I + di, j = 2 * J + dj;
-            const size_t q = at(i, j, g);
-            s += b[q] + (nsum(w, i, j, g) - 4.0 * w[q]) * ih2;
-        }
-    const size_t Q = (size_t)J * mc + I;
-    bH[Q] = 0.25 * s;
-    wH[Q] = 0.0;
-}
-
-// w += bilinear interpolation of wH.
-__global__ void __launch_bounds__(256) k_p_prolong(double* w, Grid g, const double* __restrict__ wH,
-                                                   const CycleState* st) {
-    if (stopped(st)) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= g.m || j >= g.n) return;
-    const int mc = g.m >> 1, nc = g.n >> 1;
-    const int I = i >> 1, J = j >> 1;
-    const int Is = ((i & 1) ? I + 1 : I - 1) & (mc - 1);
-    const int Js = ((j & 1) ? J + 1 : J - 1) & (nc - 1);
-    w[at(i, j, g)] += (9.0 * wH[(size_t)J * mc + I] +
-                       3.0 * (wH[(size_t)J * mc + Is] + wH[(size_t)Js * mc + I]) +
-                       wH[(size_t)Js * mc + Is]) / 16.0;
-}
-
-// Coarsest grid: w = G b with G the mean-zero periodic Green's matrix of
-// -Lap_h (computed on the host).  b is projected to mean zero first (it is
-// mean-zero up to rounding).
-__global__ void __launch_bounds__(64) k_p_coarsest(double* w, const double* __restrict__ b,
-                                                   const double* __restrict__ G, int ncell,
-                                                   const CycleState* st) {
-    if (stopped(st)) return;
-    __shared__ double bs[64];
-    __shared__ double mean;
-    const int t = threadIdx.x;
-    if (t < ncell) bs[t] = b[t];
-    __syncthreads();
-    if (t == 0) {
-        double s = 0.0;
-        for (int k = 0; k < ncell; ++k) s += bs[k];
-        mean = s / ncell;
-    }
-    __syncthreads();
-    if (t < ncell) {
-        double s = 0.0;
-        for (int k = 0; k < ncell; ++k) s += G[t * ncell + k] * (bs[k] - mean);
-        w[t] = s;
-    }
+// Advance the Poisson solution across a time step.  With -Lap_h w^k = psi^k,
+// the scheme's psi equation (eq. scheme1_1 or mpfc_scheme2_1 with the psi
+// update) gives -Lap_h w^{k+1} = psi^{k+1} for w^{k+1} = a w^k - b (mu - mean mu),
+// a = 1/(1 + s beta), b = s M/(1 + s beta) (scheme 1) or a = (1 - s beta/2)/
+// (1 + s beta/2), b = s M/(1 + s beta/2) (scheme 2), up to the step's residual.
+__global__ void __launch_bounds__(256) k_w_advance(double* w, const double* __restrict__ mu,
+                                                   size_t total, double a, double b,
+                                                   const double* __restrict__ musum) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const double mean = musum[0] / (double)total;
+    w[q] = a * w[q] - b * (mu[q] - mean);
 }
 
 // Finest-grid Poisson residual norm with the same last-block bookkeeping as

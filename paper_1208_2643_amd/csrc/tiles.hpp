@@ -1,0 +1,721 @@
+// Fused, LDS-tiled FAS V-cycle kernels for gfx950.
+//
+// Each multigrid level above 32x32 cells costs two launches per V-cycle:
+//   down: complete the FAS right-hand side, nu1 red-black nonlinear
+//         Gauss-Seidel passes (App. B smoother), write u, then the residual
+//         and its 2x2-average restriction together with the restriction of u
+//         onto the next level (one read of the level, one write);
+//   up:   load u with the bilinear coarse-grid correction applied, nu2
+//         passes, write u; on the finest level also the residual norm of the
+//         stopping test.
+// All levels of at most 32x32 cells run in one persistent single-workgroup
+// kernel that keeps them in LDS and solves the coarsest grid directly.
+//
+// Tiles.  A workgroup owns a tx x ty interior tile and loads it with a halo
+// of H cells (periodic wrap) into LDS.  After p half-sweeps the cells at
+// distance >= p from the loaded border hold exactly the values of a global
+// red-black sweep (a red cell only reads black neighbours and vice versa), so
+// H >= number of half-sweeps (+1 when a residual follows) makes the interior
+// exact.  Output goes to a second buffer (ping-pong), so neighbouring tiles
+// always read the values from before the launch.  H is even, so the loaded
+// region starts on an even global index: 2x2 blocks of the loaded region are
+// exactly the fine cells under one coarse cell.
+//
+// Threads own 2x2 blocks of the loaded region: both red cells of a block in
+// red passes, both black cells in black passes, all four for the residual,
+// restriction and prolongation.  Right-hand side and phi^k of owned cells
+// live in registers.  LDS holds the unknowns split by colour: U[f][c][y][x/2]
+// with c = (x + y) & 1, so a thread's own cells and all neighbours of one
+// colour are contiguous across lanes (no bank conflicts on 8-byte accesses).
+#pragma once
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace mpfc {
+
+// ---------------------------------------------------------------------------
+// Cell operators.  ns[f] is the sum of the four neighbours of field f.
+
+// MPFC system N(u) = f (App. B.1 / B.2), optionally in correction (DEFECT) form.
+template <typename T, int SCHEME, bool NEWTON, bool DEFECT>
+struct MpfcOp {
+    using real = T;
+    static constexpr int NF = 3;
+    static constexpr bool XK = SCHEME == 2;
+    static constexpr bool PB = DEFECT;
+    LevelOp<T> op;
+
+    __device__ __forceinline__ void apply(const T* u, const T* ns, T xk, T pb, T* N) const {
+        const T lphi = (ns[0] - T(4) * u[0]) * op.ih2;
+        const T lmu = (ns[1] - T(4) * u[1]) * op.ih2;
+        const T lka = (ns[2] - T(4) * u[2]) * op.ih2;
+        N[0] = u[0] - op.c * lmu;
+        N[1] = u[1] - nl_value<T, SCHEME, DEFECT>(u[0], pb, xk) - op.al * u[0] - lka;
+        N[2] = u[2] - op.e * lphi;
+    }
+    // Collective update of one cell: J_loc delta = f - N(u) (see relax_at).
+    __device__ __forceinline__ void relax(T* u, const T* ns, const T* f, T xk, T pb) const {
+        T N[3];
+        apply(u, ns, xk, pb, N);
+        const T r1 = f[0] - N[0], r2 = f[1] - N[1], r3 = f[2] - N[2];
+        const T d = op.al + nl_lin<T, SCHEME, NEWTON>(pb + u[0], xk);
+        const T a = T(4) * op.c * op.ih2, b = T(4) * op.ih2, ec = T(4) * op.e * op.ih2;
+        const T det = T(1) + a * d + a * b * ec;
+        const T dm = (r2 + (d + b * ec) * r1 - b * r3) / det;
+        const T dx = r1 - a * dm;
+        const T dk = r3 - ec * dx;
+        u[0] += dx;
+        u[1] += dm;
+        u[2] += dk;
+    }
+};
+
+// Periodic Poisson problem -Lap_h w = b (App. A "-1" norm), same interface.
+template <typename T>
+struct PoissonOp {
+    using real = T;
+    static constexpr int NF = 1;
+    static constexpr bool XK = false;
+    static constexpr bool PB = false;
+    T ih2, h2;
+    __device__ __forceinline__ void apply(const T* u, const T* ns, T, T, T* N) const {
+        N[0] = (T(4) * u[0] - ns[0]) * ih2;
+    }
+    __device__ __forceinline__ void relax(T* u, const T* ns, const T* f, T, T) const {
+        u[0] = T(0.25) * (h2 * f[0] + ns[0]);
+    }
+};
+
+// ---------------------------------------------------------------------------
+template <typename T>
+struct TileArgs {
+    Grid g;                 // this level
+    const T* uin[3];        // u before the launch
+    T* uout[3];             // u after the launch (interior cells)
+    const T* f[3];          // right-hand side: complete (finest down, every up) or the
+                            // restricted residual R r (coarse down, completed in-kernel)
+    T* fout[3];             // coarse down: completed right-hand side f = R r + N(u)
+    const T* xk;            // phi^k on this level (scheme 2)
+    const T* pb;            // base phi (correction form)
+    T* uH[3]; T* vH[3]; T* rH[3];          // down: restricted u (twice) and residual
+    const T* cuH[3]; const T* cvH[3];      // up: coarse u after and before its solve
+    int complete_f;         // down on a coarse level
+    int nsweep;             // red-black half-sweeps (2 nu)
+    int H;                  // halo (even)
+    int tx, ty;             // interior tile (even, divides m, n)
+    // residual norm (finest up): h^2-weighted, FP64, last-block finalizer
+    int norm;
+    CycleState* nst;
+    double* hist;
+    double tol, diverge, h2;
+    int max_norms;
+};
+
+template <typename T>
+__device__ __forceinline__ T bilinear(const T* __restrict__ uH, const T* __restrict__ vH, int I,
+                                      int J, int Is, int Js, int mc) {
+    const size_t a = (size_t)J * mc + I, b = (size_t)J * mc + Is;
+    const size_t c = (size_t)Js * mc + I, d = (size_t)Js * mc + Is;
+    return T(9.0 / 16.0) * (uH[a] - vH[a]) +
+           T(3.0 / 16.0) * ((uH[b] - vH[b]) + (uH[c] - vH[c])) +
+           T(1.0 / 16.0) * (uH[d] - vH[d]);
+}
+
+__device__ __forceinline__ void finalize_norm(CycleState* st, double* hist, double nr, double tol,
+                                              int max_norms, double diverge) {
+    const int k = st->count;
+    hist[k] = nr;
+    st->count = k + 1;
+    int status = ST_RUNNING;
+    if (!(nr == nr) || nr > 1.0e300) status = ST_NONFINITE;
+    else if (nr <= tol) status = ST_CONVERGED;
+    else if (k > 0 && nr > diverge * hist[0]) status = ST_DIVERGED;
+    else if (k + 1 >= max_norms) status = ST_MAXCYC;
+    st->status = status;
+    st->done = status != ST_RUNNING;
+    st->acc = 0.0;
+    st->blocks = 0u;
+}
+
+// One tile kernel for both directions.  Grid: (m / tx, n / ty), 256 threads.
+template <class Op, int TX, int TY, int HMAX, bool UP>
+__global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real> A,
+                                              const CycleState* stop) {
+    using T = typename Op::real;
+    constexpr int NF = Op::NF;
+    constexpr int NT = 256;
+    constexpr int LX2M = (TX + 2 * HMAX) / 2;
+    constexpr int LYM = TY + 2 * HMAX;
+    constexpr int SL = (LX2M * (LYM / 2) + NT - 1) / NT;  // owned blocks per thread
+    __shared__ T U[NF][2][LYM][LX2M];
+    __shared__ double red[NT / 64];
+    __shared__ int last;
+    if (stopped(stop)) return;
+
+    const Grid g = A.g;
+    const int H = A.H, tx = A.tx, ty = A.ty;
+    const int LX = tx + 2 * H, LY = ty + 2 * H, LX2 = LX >> 1;
+    const int nblk = LX2 * (LY >> 1);
+    const int x0 = (int)blockIdx.x * tx - H, y0 = (int)blockIdx.y * ty - H;
+    const int t = threadIdx.x;
+
+    // 1. u (tile + halo) into LDS, coalesced along rows.
+    for (int q = t; q < LX * LY; q += NT) {
+        const int y = q / LX, x = q - y * LX;
+        const size_t gq = at((x0 + x) & (g.m - 1), (y0 + y) & (g.n - 1), g);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) U[f][(x + y) & 1][y][x >> 1] = A.uin[f][gq];
+    }
+    __syncthreads();
+
+    // 2. per owned block: right-hand side and coefficients of its four cells
+    //    (cell order: (0,0) (1,1) red, (1,0) (0,1) black).
+    T fr[SL][4][NF];
+    T xkr[SL][4];
+    T pbr[SL][4];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int b = t + s * NT;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) fr[s][c][f] = T(0);
+            xkr[s][c] = T(0);
+            pbr[s][c] = T(0);
+        }
+        if (b >= nblk) continue;
+        const int by = b / LX2, bx = b - by * LX2;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
+            const int x = 2 * bx + dx, y = 2 * by + dy;
+            if (x < 1 || y < 1 || x >= LX - 1 || y >= LY - 1) continue;  // never updated
+            const size_t gq = at((x0 + x) & (g.m - 1), (y0 + y) & (g.n - 1), g);
+            if constexpr (Op::XK) xkr[s][c] = A.xk[gq];
+            if constexpr (Op::PB) pbr[s][c] = A.pb[gq];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) fr[s][c][f] = A.f[f][gq];
+        }
+    }
+
+    // 3. up: add the coarse-grid correction P(uH - vH) to every loaded cell.
+    if constexpr (UP) {
+        const int mc = g.m >> 1, nc = g.n >> 1;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const int b = t + s * NT;
+            if (b >= nblk) continue;
+            const int by = b / LX2, bx = b - by * LX2;
+            const int I = ((x0 + 2 * bx) & (g.m - 1)) >> 1;
+            const int J = ((y0 + 2 * by) & (g.n - 1)) >> 1;
+            const int Im = (I - 1) & (mc - 1), Ip = (I + 1) & (mc - 1);
+            const int Jm = (J - 1) & (nc - 1), Jp = (J + 1) & (nc - 1);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
+                const int x = 2 * bx + dx, y = 2 * by + dy;
+                const int Is = dx ? Ip : Im, Js = dy ? Jp : Jm;
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+                    U[f][(x + y) & 1][y][x >> 1] += bilinear<T>(A.cuH[f], A.cvH[f], I, J, Is, Js, mc);
+            }
+        }
+        __syncthreads();
+    }
+
+    // 3'. coarse down: f = R r + N(u) at every cell that can be updated.
+    if (!UP && A.complete_f) {
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const int b = t + s * NT;
+            if (b >= nblk) continue;
+            const int by = b / LX2, bx = b - by * LX2;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
+                const int x = 2 * bx + dx, y = 2 * by + dy;
+                if (x < 1 || y < 1 || x >= LX - 1 || y >= LY - 1) continue;
+                const int col = (x + y) & 1, oc = col ^ 1, k = x >> 1;
+                const int ke = (x + 1) >> 1, kw = (x - 1) >> 1;
+                T u[NF], ns[NF], N[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    u[f] = U[f][col][y][k];
+                    ns[f] = (U[f][oc][y][ke] + U[f][oc][y][kw]) +
+                            (U[f][oc][y + 1][k] + U[f][oc][y - 1][k]);
+                }
+                op.apply(u, ns, xkr[s][c], pbr[s][c], N);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) fr[s][c][f] += N[f];
+            }
+        }
+    }
+
+    // 4. red-black passes; pass p is exact on cells at distance >= p.  The
+    //    colour is a compile-time constant inside `pass`, so the per-cell
+    //    register arrays are indexed statically.
+    auto pass = [&](auto colc, int p) {
+        constexpr int colour = decltype(colc)::value;
+        constexpr int oc = colour ^ 1;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const int b = t + s * NT;
+            if (b >= nblk) continue;
+            const int by = b / LX2, bx = b - by * LX2;
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+                const int c = colour == 0 ? cc : 2 + cc;
+                const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
+                const int x = 2 * bx + dx, y = 2 * by + dy;
+                if (x < p || y < p || x >= LX - p || y >= LY - p) continue;
+                const int k = x >> 1, ke = (x + 1) >> 1, kw = (x - 1) >> 1;
+                T u[NF], ns[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    u[f] = U[f][colour][y][k];
+                    ns[f] = (U[f][oc][y][ke] + U[f][oc][y][kw]) +
+                            (U[f][oc][y + 1][k] + U[f][oc][y - 1][k]);
+                }
+                op.relax(u, ns, fr[s][c], xkr[s][c], pbr[s][c]);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) U[f][colour][y][k] = u[f];
+            }
+        }
+    };
+    for (int p = 1; p <= A.nsweep; ++p) {
+        if (((p - 1) & 1) == 0) pass(std::integral_constant<int, 0>{}, p);
+        else pass(std::integral_constant<int, 1>{}, p);
+        __syncthreads();
+    }
+
+    // 5. interior u back to global memory, coalesced along rows.
+    const int gx0 = (int)blockIdx.x * tx, gy0 = (int)blockIdx.y * ty;
+    for (int q = t; q < tx * ty; q += NT) {
+        const int yi = q / tx, xi = q - yi * tx;
+        const int x = xi + H, y = yi + H;
+        const size_t gq = at(gx0 + xi, gy0 + yi, g);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) A.uout[f][gq] = U[f][(x + y) & 1][y][x >> 1];
+    }
+
+    // 6. interior blocks: residual; down restricts it (and u), finest up sums r^2.
+    double acc = 0.0;
+    const int mc = g.m >> 1;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int b = t + s * NT;
+        if (b >= nblk) continue;
+        const int by = b / LX2, bx = b - by * LX2;
+        if (2 * bx < H || 2 * bx >= H + tx || 2 * by < H || 2 * by >= H + ty) continue;
+        if (UP && !A.norm) continue;
+        T su[NF], sr[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) { su[f] = T(0); sr[f] = T(0); }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
+            const int x = 2 * bx + dx, y = 2 * by + dy;
+            const int col = (x + y) & 1, oc = col ^ 1, k = x >> 1;
+            const int ke = (x + 1) >> 1, kw = (x - 1) >> 1;
+            T u[NF], ns[NF], N[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                u[f] = U[f][col][y][k];
+                ns[f] = (U[f][oc][y][ke] + U[f][oc][y][kw]) +
+                        (U[f][oc][y + 1][k] + U[f][oc][y - 1][k]);
+            }
+            op.apply(u, ns, xkr[s][c], pbr[s][c], N);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const T r = fr[s][c][f] - N[f];
+                su[f] += u[f];
+                sr[f] += r;
+                acc += (double)r * (double)r;
+            }
+        }
+        if constexpr (!UP) {
+            const int I = (gx0 + 2 * bx - H) >> 1, J = (gy0 + 2 * by - H) >> 1;
+            const size_t Q = (size_t)J * mc + I;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const T avg = T(0.25) * su[f];
+                A.uH[f][Q] = avg;
+                A.vH[f][Q] = avg;
+                A.rH[f][Q] = T(0.25) * sr[f];
+            }
+        }
+    }
+    if constexpr (!UP) {
+        // completed coarse-level right-hand side for the up launch
+        if (A.complete_f) {
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                const int b = t + s * NT;
+                if (b >= nblk) continue;
+                const int by = b / LX2, bx = b - by * LX2;
+                if (2 * bx < H || 2 * bx >= H + tx || 2 * by < H || 2 * by >= H + ty) continue;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
+                    const size_t gq = at(gx0 + 2 * bx - H + dx, gy0 + 2 * by - H + dy, g);
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) A.fout[f][gq] = fr[s][c][f];
+                }
+            }
+        }
+    } else {
+        if (A.norm) {
+            const double bs = block_sum<NT>(acc, red);
+            if (t == 0) {
+                atomicAdd(&A.nst->acc, bs);
+                __threadfence();
+                const unsigned done = atomicAdd(&A.nst->blocks, 1u);
+                last = (done == gridDim.x * gridDim.y - 1);
+            }
+            __syncthreads();
+            if (last && t == 0) {
+                __threadfence();
+                const double tot = atomicAdd(&A.nst->acc, 0.0);
+                finalize_norm(A.nst, A.hist, sqrt(A.h2 * tot), A.tol, A.max_norms, A.diverge);
+                __threadfence();
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent kernel: every level of at most CP_CELLS cells, in LDS, one
+// workgroup.  Same V(nu1, nu2) cycle as the tiled levels; the coarsest grid is
+// solved directly (CoarseSolve).
+constexpr int CP_CELLS = 1024;  // largest level handled here (32 x 32)
+constexpr int CP_TOTAL = 1368;  // cells of all its levels (1024 + 256 + 64 + 16 + 4, padded)
+constexpr int CP_MAXLEV = 12;
+
+struct CoarseGeom {
+    int nlev;             // levels in this kernel (top first)
+    int m[CP_MAXLEV], n[CP_MAXLEV], lm[CP_MAXLEV];
+    int off[CP_MAXLEV];   // cell offset of each level in the LDS arrays
+};
+
+template <typename T>
+struct CoarseArgs {
+    CoarseGeom geo;
+    T* u[3];              // top level u (in/out, global)
+    const T* rr[3];       // top level restricted residual R r (global)
+    const T* xk;          // phi^k on the top level (global)
+    const T* pb;          // base phi on the top level (global)
+    T h_top;              // spacing of the top level
+    int nsw1, nsw2;       // half-sweeps down / up
+    int complete_top;     // 1: rr holds R r (add N(u)); 0: rr is already the full f
+    const double* G;      // Poisson: Green's matrix of the coarsest grid
+    int newton_maxit;
+    T newton_tol;
+};
+
+// Coarsest grid, MPFC: eliminate kappa and mu (kappa = f3 + e Lap phi,
+// mu = f2 + g(phi) + al phi + Lap kappa) and solve the remaining equation
+//   phi - c Lap(g(phi) + al phi + e Lap^2 phi) = f1 + c Lap(f2 + Lap f3)
+// by Newton with Gaussian elimination (NC <= 16 unknowns), one thread.  Its
+// solution is the unique solution of the three-field system.
+template <class Op, int NC>
+__device__ void coarse_solve_mpfc(const Op& op, typename Op::real* phi, typename Op::real* mu,
+                                  typename Op::real* ka, const typename Op::real* f,
+                                  const typename Op::real* xk, const typename Op::real* pb,
+                                  int m, int n, int maxit, typename Op::real tol) {
+    constexpr int ncell = NC;
+    using T = typename Op::real;
+    // Laplacian matrix of the periodic m x n grid (entries accumulate, so a
+    // 2-cell direction couples each cell twice to its one neighbour).
+    T L[NC][NC];
+    for (int a = 0; a < NC; ++a)
+        for (int b = 0; b < NC; ++b) L[a][b] = T(0);
+    for (int q = 0; q < ncell; ++q) {
+        const int i = q % m, j = q / m;
+        const int nb[4] = {((i + 1) % m) + j * m, ((i - 1 + m) % m) + j * m,
+                           i + ((j + 1) % n) * m, i + ((j - 1 + n) % n) * m};
+        L[q][q] -= T(4) * op.op.ih2;
+        for (int s = 0; s < 4; ++s) L[q][nb[s]] += op.op.ih2;
+    }
+    const T* f1 = f;
+    const T* f2 = f + ncell;
+    const T* f3 = f + 2 * ncell;
+    T rhs[NC], t1[NC], L2[NC][NC];
+    // rhs = f1 + c Lap(f2 + Lap f3)
+    for (int a = 0; a < NC; ++a) {
+        T s = 0;
+        for (int b = 0; b < ncell; ++b) s += L[a][b] * f3[b];
+        t1[a] = f2[a] + s;
+    }
+    for (int a = 0; a < ncell; ++a) {
+        T s = 0;
+        for (int b = 0; b < ncell; ++b) s += L[a][b] * t1[b];
+        rhs[a] = f1[a] + op.op.c * s;
+    }
+    // L2 = Lap^2
+    for (int a = 0; a < ncell; ++a)
+        for (int b = 0; b < ncell; ++b) {
+            T s = 0;
+            for (int k = 0; k < ncell; ++k) s += L[a][k] * L[k][b];
+            L2[a][b] = s;
+        }
+    T x[NC];
+    for (int a = 0; a < ncell; ++a) x[a] = phi[a];
+    for (int it = 0; it < maxit; ++it) {
+        // residual R = x - c Lap(g(x) + al x + e Lap^2 x) - rhs, Jacobian J
+        T w[NC], d[NC], R[NC], J[NC][NC + 1];
+        for (int a = 0; a < ncell; ++a) {
+            const T xa = x[a];
+            const T xka = Op::XK ? xk[a] : T(0);
+            const T pba = Op::PB ? pb[a] : T(0);
+            T s = 0;
+            for (int b = 0; b < ncell; ++b) s += L2[a][b] * x[b];
+            w[a] = nl_value<T, (Op::XK ? 2 : 1), Op::PB>(xa, pba, xka) + op.op.al * xa + op.op.e * s;
+            d[a] = nl_lin<T, (Op::XK ? 2 : 1), true>(pba + xa, xka) + op.op.al;
+        }
+        for (int a = 0; a < ncell; ++a) {
+            T s = 0;
+            for (int b = 0; b < ncell; ++b) s += L[a][b] * w[b];
+            R[a] = x[a] - op.op.c * s - rhs[a];
+        }
+        // J = I - c Lap (diag(d) + e Lap^2)
+        for (int a = 0; a < ncell; ++a) {
+            for (int b = 0; b < ncell; ++b) {
+                const T v = L[a][b] * d[b] + op.op.e * [&] {
+                    T s = 0;
+                    for (int k = 0; k < ncell; ++k) s += L[a][k] * L2[k][b];
+                    return s;
+                }();
+                J[a][b] = (a == b ? T(1) : T(0)) - op.op.c * v;
+            }
+            J[a][ncell] = -R[a];
+        }
+        // Gaussian elimination with partial pivoting
+        for (int k = 0; k < ncell; ++k) {
+            int p = k;
+            T best = fabs(J[k][k]);
+            for (int r = k + 1; r < ncell; ++r)
+                if (fabs(J[r][k]) > best) { best = fabs(J[r][k]); p = r; }
+            if (p != k)
+                for (int cc = 0; cc <= ncell; ++cc) {
+                    const T tmp = J[k][cc]; J[k][cc] = J[p][cc]; J[p][cc] = tmp;
+                }
+            for (int r = k + 1; r < ncell; ++r) {
+                const T fct = J[r][k] / J[k][k];
+                for (int cc = k; cc <= ncell; ++cc) J[r][cc] -= fct * J[k][cc];
+            }
+        }
+        T smax = 0, xmax = 0;
+        for (int k = ncell - 1; k >= 0; --k) {
+            T s = J[k][ncell];
+            for (int cc = k + 1; cc < ncell; ++cc) s -= J[k][cc] * t1[cc];
+            t1[k] = s / J[k][k];
+        }
+        for (int a = 0; a < ncell; ++a) {
+            x[a] += t1[a];
+            smax = fmax(smax, fabs(t1[a]));
+            xmax = fmax(xmax, fabs(x[a]));
+        }
+        if (smax <= tol * (T(1) + xmax)) break;
+    }
+    // recover kappa and mu
+    for (int a = 0; a < ncell; ++a) {
+        T s = 0;
+        for (int b = 0; b < ncell; ++b) s += L[a][b] * x[b];
+        ka[a] = f3[a] + op.op.e * s;
+    }
+    for (int a = 0; a < ncell; ++a) {
+        T s = 0;
+        for (int b = 0; b < ncell; ++b) s += L[a][b] * ka[b];
+        const T xka = Op::XK ? xk[a] : T(0);
+        const T pba = Op::PB ? pb[a] : T(0);
+        mu[a] = f2[a] + nl_value<T, (Op::XK ? 2 : 1), Op::PB>(x[a], pba, xka) + op.op.al * x[a] + s;
+        phi[a] = x[a];
+    }
+}
+
+// Coarsest grid, Poisson: w = G f + mean(v) (the mean of w is free; keep the
+// correction mean-free).  One thread per cell.
+template <typename T>
+__device__ void coarse_solve_poisson(T* w, const T* f, const T* v, const double* G, int ncell) {
+    const int t = threadIdx.x;
+    __shared__ T mv;
+    if (t == 0) {
+        T s = 0;
+        for (int k = 0; k < ncell; ++k) s += v[k];
+        mv = s / T(ncell);
+    }
+    __syncthreads();
+    if (t < ncell) {
+        T s = 0;
+        for (int k = 0; k < ncell; ++k) s += (T)G[t * ncell + k] * f[k];
+        w[t] = s + mv;
+    }
+}
+
+template <class Op, int NTP, int NC>
+__global__ void __launch_bounds__(NTP) k_coarse_persistent(Op op_top, CoarseArgs<typename Op::real> A,
+                                                           const CycleState* stop) {
+    using T = typename Op::real;
+    constexpr int NF = Op::NF;
+    __shared__ T Su[NF][CP_TOTAL];
+    __shared__ T Sf[NF][CP_TOTAL];
+    __shared__ T Sv[NF][CP_TOTAL];
+    __shared__ T Sxk[Op::XK ? CP_TOTAL : 1];
+    __shared__ T Spb[Op::PB ? CP_TOTAL : 1];
+    if (stopped(stop)) return;
+    const int t = threadIdx.x;
+    const CoarseGeom& G = A.geo;
+    const int m0 = G.m[0], n0 = G.n[0], N0 = m0 * n0;
+    // load the top level
+    for (int q = t; q < N0; q += NTP) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            Su[f][q] = A.u[f][q];
+            Sf[f][q] = A.rr[f][q];
+        }
+        if constexpr (Op::XK) Sxk[q] = A.xk[q];
+        if constexpr (Op::PB) Spb[q] = A.pb[q];
+    }
+    __syncthreads();
+    // coefficient pyramids (2x2 averages)
+    for (int l = 1; l < G.nlev; ++l) {
+        const int mf = G.m[l - 1], mcv = G.m[l], nc = G.n[l];
+        for (int q = t; q < mcv * nc; q += NTP) {
+            const int I = q % mcv, J = q / mcv;
+            const int a = G.off[l - 1] + 2 * J * mf + 2 * I;
+            if constexpr (Op::XK)
+                Sxk[G.off[l] + q] = T(0.25) * ((Sxk[a] + Sxk[a + 1]) + (Sxk[a + mf] + Sxk[a + mf + 1]));
+            if constexpr (Op::PB)
+                Spb[G.off[l] + q] = T(0.25) * ((Spb[a] + Spb[a + 1]) + (Spb[a + mf] + Spb[a + mf + 1]));
+        }
+        __syncthreads();
+    }
+    auto opl = [&](int l) {
+        Op o = op_top;
+        const T s = T(1 << l);
+        if constexpr (NF == 3) o.op.ih2 = op_top.op.ih2 / (s * s);
+        else { o.ih2 = op_top.ih2 / (s * s); o.h2 = op_top.h2 * (s * s); }
+        return o;
+    };
+    auto nsum_l = [&](const T* a, int q, int m, int n) {
+        const int i = q % m, j = q / m;
+        return (a[((i + 1) & (m - 1)) + j * m] + a[((i - 1) & (m - 1)) + j * m]) +
+               (a[i + ((j + 1) & (n - 1)) * m] + a[i + ((j - 1) & (n - 1)) * m]);
+    };
+    auto complete_rhs = [&](int l) {
+        const Op o = opl(l);
+        const int m = G.m[l], n = G.n[l], off = G.off[l];
+        for (int q = t; q < m * n; q += NTP) {
+            T u[NF], ns[NF], N[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) { u[f] = Su[f][off + q]; ns[f] = nsum_l(&Su[f][off], q, m, n); }
+            o.apply(u, ns, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0), N);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) Sf[f][off + q] += N[f];
+        }
+        __syncthreads();
+    };
+    auto sweeps = [&](int l, int nsw) {
+        const Op o = opl(l);
+        const int m = G.m[l], n = G.n[l], off = G.off[l];
+        for (int p = 0; p < nsw; ++p) {
+            const int colour = p & 1;
+            for (int q2 = t; q2 < (m * n) / 2; q2 += NTP) {
+                const int j = q2 / (m >> 1), k = q2 - j * (m >> 1);
+                const int i = 2 * k + ((j + colour) & 1);
+                const int q = j * m + i;
+                T u[NF], ns[NF], fv[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    u[f] = Su[f][off + q];
+                    ns[f] = nsum_l(&Su[f][off], q, m, n);
+                    fv[f] = Sf[f][off + q];
+                }
+                o.relax(u, ns, fv, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0));
+#pragma unroll
+                for (int f = 0; f < NF; ++f) Su[f][off + q] = u[f];
+            }
+            __syncthreads();
+        }
+    };
+    const int L = G.nlev;
+    // down
+    if (A.complete_top) complete_rhs(0);
+    for (int l = 0; l < L - 1; ++l) {
+        sweeps(l, A.nsw1);
+        const Op o = opl(l);
+        const int m = G.m[l], n = G.n[l], off = G.off[l];
+        const int mc = G.m[l + 1], nc = G.n[l + 1], offc = G.off[l + 1];
+        for (int Q = t; Q < mc * nc; Q += NTP) {
+            const int I = Q % mc, J = Q / mc;
+            T su[NF], sr[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) { su[f] = T(0); sr[f] = T(0); }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int q = (2 * J + (c >> 1)) * m + 2 * I + (c & 1);
+                T u[NF], ns[NF], N[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) { u[f] = Su[f][off + q]; ns[f] = nsum_l(&Su[f][off], q, m, n); }
+                o.apply(u, ns, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0), N);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) { su[f] += u[f]; sr[f] += Sf[f][off + q] - N[f]; }
+            }
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                Su[f][offc + Q] = T(0.25) * su[f];
+                Sv[f][offc + Q] = T(0.25) * su[f];
+                Sf[f][offc + Q] = T(0.25) * sr[f];
+            }
+        }
+        __syncthreads();
+        complete_rhs(l + 1);
+    }
+    // coarsest
+    {
+        const int l = L - 1, off = G.off[l], nc = G.m[l] * G.n[l];
+        if constexpr (NF == 3) {
+            // the host launches the instantiation whose NC equals the coarsest cell count
+            if (t == 0 && nc == NC) {
+                const Op o = opl(l);
+                T fbuf[3 * NC];
+#pragma unroll
+                for (int q = 0; q < NC; ++q) {
+                    fbuf[q] = Sf[0][off + q];
+                    fbuf[NC + q] = Sf[1][off + q];
+                    fbuf[2 * NC + q] = Sf[2][off + q];
+                }
+                T* xkp = Op::XK ? &Sxk[off] : nullptr;
+                T* pbp = Op::PB ? &Spb[off] : nullptr;
+                coarse_solve_mpfc<Op, NC>(o, &Su[0][off], &Su[1][off], &Su[2][off], fbuf, xkp, pbp,
+                                          G.m[l], G.n[l], A.newton_maxit, A.newton_tol);
+            }
+        } else {
+            coarse_solve_poisson<T>(&Su[0][off], &Sf[0][off], &Sv[0][off], A.G, nc);
+        }
+        __syncthreads();
+    }
+    // up
+    for (int l = L - 2; l >= 0; --l) {
+        const int m = G.m[l], n = G.n[l], off = G.off[l];
+        const int mc = G.m[l + 1], nc = G.n[l + 1], offc = G.off[l + 1];
+        for (int q = t; q < m * n; q += NTP) {
+            const int i = q % m, j = q / m, I = i >> 1, J = j >> 1;
+            const int Is = ((i & 1) ? I + 1 : I - 1) & (mc - 1);
+            const int Js = ((j & 1) ? J + 1 : J - 1) & (nc - 1);
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                Su[f][off + q] += bilinear<T>(&Su[f][offc], &Sv[f][offc], I, J, Is, Js, mc);
+        }
+        __syncthreads();
+        sweeps(l, A.nsw2);
+    }
+    // top level back to global memory
+    for (int q = t; q < N0; q += NTP) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) A.u[f][q] = Su[f][q];
+    }
+}
+
+}  // namespace mpfc

@@ -58,7 +58,7 @@ def test_invalid_params_rejected(field, value):
     assert L.load().mpfc_validate(64, 64, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
 
 
-@pytest.mark.parametrize("m,n", [(0, 64), (48, 64), (64, 100), (1, 1), (2, 128)])
+@pytest.mark.parametrize("m,n", [(0, 64), (48, 64), (64, 100), (1, 1), (2, 128), (64, 256)])
 def test_invalid_sizes_rejected(m, n):
     p, o = good()
     assert L.load().mpfc_validate(m, n, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
@@ -88,5 +88,5 @@ def test_create_rejects_before_any_hip_call():
 def test_rectangular_and_small_grids_accepted():
     lib = L.load()
     p, o = good()
-    for m, n in [(2, 2), (4, 8), (64, 128), (2048, 2048)]:
+    for m, n in [(2, 2), (4, 8), (64, 128), (2048, 2048), (128, 64)]:
         assert lib.mpfc_validate(m, n, ctypes.byref(p), ctypes.byref(o)) == 0, (m, n)
