@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--N", type=int, default=1024, help=argparse.SUPPRESS)
     ap.add_argument("--no-energy", action="store_true", help="skip the per-step energies")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 128 MiB device copy (counter calibration)")
     ap.add_argument("--variants", type=int, default=1,
                     help="also time the mixed-precision variant of the workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -90,6 +92,15 @@ def main():
     import torch
     from paper_1208_2643_amd import api, inputs
 
+    if args.calib_copy:
+        # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
+        # calibrate the HBM byte counters (128 MiB read, 128 MiB written).
+        a = torch.ones(16 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     N = args.N
     params = dict(eps=0.025, beta=0.9, M=1.0, h=math.pi / 4, dt=0.05, scheme=2)
     tol = 1e-10

@@ -17,6 +17,8 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are disabled for every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # hardware FP64 atomic add (all atomics target coarse-grained hipMalloc memory)
+    "-munsafe-fp-atomics",
     "-I", os.path.join(ROOT, "include"),
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]

@@ -183,20 +183,45 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return t;  // valid in thread 0
 }
 
-// Finest-grid residual norm ||r|| = sqrt(h^2 sum_c sum_ij r_c^2), always in
-// FP64 (the stopping test).  Each block adds its partial sum with one atomic;
-// the last block to finish records the norm in hist[count], updates the
-// status (converged when norm <= tol) and clears the accumulator.
-// When `write` is set the residual is also stored (mixed precision uses it as
-// the right-hand side of the correction equation).
-template <int SCHEME, int NT>
-__global__ void __launch_bounds__(NT) k_resnorm(Fields<double> F, LevelOp<double> op, Grid g,
-                                                double h2, CycleState* st, double* hist,
-                                                double tol, int max_norms, double diverge,
-                                                double* r0, double* r1o, double* r2o) {
+// Stop test after a norm: every block of the producing kernel wrote the sum
+// of its squares to part[b]; one block adds them in a fixed order, records
+// ||r|| = sqrt(h2 * sum) in hist[count] and sets the status: converged when
+// ||r|| <= tol, non-finite, diverged (growth by `diverge` over hist[0]) or the
+// cycle limit.  No atomics and no device-wide fences are involved, and the
+// norm is deterministic.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_norm_finalize(const double* __restrict__ part, int nparts,
+                                                      CycleState* st, double* hist, double h2,
+                                                      double tol, int max_norms, double diverge) {
     if (stopped(st)) return;
     __shared__ double red[NT / 64];
-    __shared__ int last;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += NT) s += part[b];
+    const double tot = block_sum<NT>(s, red);
+    if (threadIdx.x == 0) {
+        const double nr = sqrt(h2 * tot);
+        const int k = st->count;
+        hist[k] = nr;
+        st->count = k + 1;
+        int status = ST_RUNNING;
+        if (!(nr == nr) || nr > 1.0e300) status = ST_NONFINITE;
+        else if (nr <= tol) status = ST_CONVERGED;
+        else if (k > 0 && nr > diverge * hist[0]) status = ST_DIVERGED;
+        else if (k + 1 >= max_norms) status = ST_MAXCYC;
+        st->status = status;
+        st->done = status != ST_RUNNING;
+    }
+}
+
+// Finest-grid residual sum of squares sum_c sum_ij r_c^2 (FP64, the stopping
+// test; k_norm_finalize turns the per-block sums into the norm).  With r0
+// non-null the residual is also stored.
+template <int SCHEME, int NT>
+__global__ void __launch_bounds__(NT) k_resnorm(Fields<double> F, LevelOp<double> op, Grid g,
+                                                const CycleState* st, double* part, double* r0,
+                                                double* r1o, double* r2o) {
+    if (stopped(st)) return;
+    __shared__ double red[NT / 64];
     double acc = 0.0;
     const size_t total = (size_t)g.m * g.n;
     for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
@@ -208,31 +233,7 @@ __global__ void __launch_bounds__(NT) k_resnorm(Fields<double> F, LevelOp<double
         if (r0) { r0[q] = a; r1o[q] = b; r2o[q] = c; }
     }
     const double bs = block_sum<NT>(acc, red);
-    if (threadIdx.x == 0) {
-        atomicAdd(&st->acc, bs);
-        __threadfence();
-        const unsigned t = atomicAdd(&st->blocks, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        const double s = atomicAdd(&st->acc, 0.0);
-        const double nr = sqrt(h2 * s);
-        const int k = st->count;
-        hist[k] = nr;
-        st->count = k + 1;
-        int status = ST_RUNNING;
-        if (!(nr == nr) || nr > 1.0e300) status = ST_NONFINITE;
-        else if (nr <= tol) status = ST_CONVERGED;
-        else if (k > 0 && nr > diverge * hist[0]) status = ST_DIVERGED;
-        else if (k + 1 >= max_norms) status = ST_MAXCYC;
-        st->status = status;
-        st->done = status != ST_RUNNING;
-        st->acc = 0.0;
-        st->blocks = 0u;
-        __threadfence();
-    }
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;  // summed by k_norm_finalize
 }
 
 // Mixed precision, outer FP64 defect-correction step on the finest grid:
@@ -244,8 +245,7 @@ __global__ void __launch_bounds__(NT) k_resnorm(Fields<double> F, LevelOp<double
 // u + e, so no other thread's write is read.
 template <int SCHEME, int NT>
 __global__ void __launch_bounds__(NT) k_defect(Fields<double> F, LevelOp<double> op, Grid g,
-                                               double h2, CycleState* st, double* hist,
-                                               double tol, int max_norms, double diverge,
+                                               const CycleState* st, double* part,
                                                const float* __restrict__ e0,
                                                const float* __restrict__ e1,
                                                const float* __restrict__ e2, int add,
@@ -253,7 +253,6 @@ __global__ void __launch_bounds__(NT) k_defect(Fields<double> F, LevelOp<double>
                                                float* r0, float* r1, float* r2, float* pbase) {
     if (stopped(st)) return;
     __shared__ double red[NT / 64];
-    __shared__ int last;
     double acc = 0.0;
     const size_t total = (size_t)g.m * g.n;
     for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
@@ -285,31 +284,7 @@ __global__ void __launch_bounds__(NT) k_defect(Fields<double> F, LevelOp<double>
         pbase[q] = (float)x;
     }
     const double bs = block_sum<NT>(acc, red);
-    if (threadIdx.x == 0) {
-        atomicAdd(&st->acc, bs);
-        __threadfence();
-        const unsigned t = atomicAdd(&st->blocks, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        const double s = atomicAdd(&st->acc, 0.0);
-        const double nr = sqrt(h2 * s);
-        const int k = st->count;
-        hist[k] = nr;
-        st->count = k + 1;
-        int status = ST_RUNNING;
-        if (!(nr == nr) || nr > 1.0e300) status = ST_NONFINITE;
-        else if (nr <= tol) status = ST_CONVERGED;
-        else if (k > 0 && nr > diverge * hist[0]) status = ST_DIVERGED;
-        else if (k + 1 >= max_norms) status = ST_MAXCYC;
-        st->status = status;
-        st->done = status != ST_RUNNING;
-        st->acc = 0.0;
-        st->blocks = 0u;
-        __threadfence();
-    }
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;  // summed by k_norm_finalize
 }
 
 template <typename TI, typename TO>

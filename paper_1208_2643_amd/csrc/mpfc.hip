@@ -62,19 +62,24 @@ dim3 grid2(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); }
 dim3 grid1(size_t total) { return dim3((unsigned)((total + 255) / 256)); }
 unsigned red_blocks(size_t total) {
     size_t b = (total + NT - 1) / NT;
-    return (unsigned)(b < 1024 ? b : 1024);
+    return (unsigned)(b < 256 ? b : 256);  // one workgroup per CU: few atomics per reduction
 }
 
 // Tile shapes (interior TX x TY, largest halo HMAX) instantiated for the
 // tiled levels.  Variant 0 serves halos up to 6 (nu <= 2), variant 1 up to 10.
 struct TileShape { int tx, ty, hmax; };
-constexpr TileShape kShapes[] = {{64, 32, 6}, {64, 16, 10}};
+constexpr TileShape kShapes[] = {{64, 32, 6},  {32, 32, 6},  {32, 16, 6}, {16, 16, 6},
+                                 {64, 16, 10}, {32, 16, 10}, {16, 16, 10}};
+constexpr int kNumShapes = 7;
+// Launch kinds that carry a tuned shape per level.
+enum { SH_DN = 0, SH_UP = 1, SH_DN32 = 2, SH_UP32 = 3, SH_PDN = 4, SH_PUP = 5, SH_KINDS = 6 };
 
 struct Level {
     int m = 0, n = 0;
     double h = 0;
     Grid g{};
     bool tiled = false;     // more than CP_CELLS cells: fused tile launches
+    int shape[SH_KINDS] = {-1, -1, -1, -1, -1, -1};  // tile shape per launch kind (tuned)
     // MPFC system
     double* u[2][3] = {};   // ping-pong; u[0] holds the iterate between cycles
     double* v[3] = {};      // restricted iterate (coarse levels)
@@ -103,7 +108,9 @@ struct mpfc_ctx {
     double* hist = nullptr;     // device residual history
     CycleState* pst = nullptr;  // Poisson cycle state
     double* phist = nullptr;
-    double* acc = nullptr;      // reduction accumulators
+    double* acc = nullptr;      // reduction results
+    double* part = nullptr;     // per-block partial sums of the reductions
+    int nparts = 0;
     double* G = nullptr;        // coarsest Poisson Green's matrix
     int have_w = 0;
     int poisson_cycles = 3;
@@ -175,14 +182,29 @@ Fields<double> finest_fields(const mpfc_ctx* C) {
 template <class Op, bool UP>
 void launch_tile(const Op& op, const TileArgs<typename Op::real>& A, int shape,
                  const CycleState* stop, hipStream_t s) {
-    const dim3 grid(A.g.m / A.tx, A.g.n / A.ty);
-    if (shape == 0)
-        hipLaunchKernelGGL((k_tile<Op, 64, 32, 6, UP>), grid, dim3(256), 0, s, op, A, stop);
-    else
-        hipLaunchKernelGGL((k_tile<Op, 64, 16, 10, UP>), grid, dim3(256), 0, s, op, A, stop);
+    const dim3 grid(A.g.m / A.tx, A.g.n / A.ty), blk(256);
+    switch (shape) {
+        case 0: hipLaunchKernelGGL((k_tile<Op, 64, 32, 6, UP>), grid, blk, 0, s, op, A, stop); break;
+        case 1: hipLaunchKernelGGL((k_tile<Op, 32, 32, 6, UP>), grid, blk, 0, s, op, A, stop); break;
+        case 2: hipLaunchKernelGGL((k_tile<Op, 32, 16, 6, UP>), grid, blk, 0, s, op, A, stop); break;
+        case 3: hipLaunchKernelGGL((k_tile<Op, 16, 16, 6, UP>), grid, blk, 0, s, op, A, stop); break;
+        case 4: hipLaunchKernelGGL((k_tile<Op, 64, 16, 10, UP>), grid, blk, 0, s, op, A, stop); break;
+        case 5: hipLaunchKernelGGL((k_tile<Op, 32, 16, 10, UP>), grid, blk, 0, s, op, A, stop); break;
+        default: hipLaunchKernelGGL((k_tile<Op, 16, 16, 10, UP>), grid, blk, 0, s, op, A, stop); break;
+    }
 }
 
-int pick_shape(int H) { return H <= kShapes[0].hmax ? 0 : 1; }
+// First shape whose halo allowance covers H (used until the autotuner has run).
+int pick_shape(int H) {
+    for (int k = 0; k < kNumShapes; ++k)
+        if (H <= kShapes[k].hmax) return k;
+    return kNumShapes - 1;
+}
+
+int level_shape(const Level& lv, int kind, int H) {
+    const int k = lv.shape[kind];
+    return (k >= 0 && H <= kShapes[k].hmax) ? k : pick_shape(H);
+}
 
 void tile_dims(const Level& lv, int shape, int& tx, int& ty) {
     tx = lv.m < kShapes[shape].tx ? lv.m : kShapes[shape].tx;
@@ -216,13 +238,16 @@ void prof_collect(mpfc_ctx* C) {
     }
 }
 
-// One FAS V-cycle of the MPFC system on all levels.
+// One FAS V-cycle of the MPFC system on all levels.  With `only` >= 0 just
+// the down (only_up = 0) or up (1) launch of that level is issued, without
+// the stop flag or the norm (used by the tile autotuner).
 template <class Op>
-void vcycle_mpfc_t(mpfc_ctx* C, hipStream_t s) {
+void vcycle_mpfc_t(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) {
     const int nl = (int)C->L.size(), Lp = C->Lp;
-    const CycleState* stop = C->st;
+    const CycleState* stop = only >= 0 ? nullptr : C->st;
     const int nsw1 = 2 * C->o.nu1, nsw2 = 2 * C->o.nu2;
     for (int l = 0; l < Lp; ++l) {
+        if (only >= 0 && (l != only || only_up)) continue;
         const Level& A = C->L[l];
         const Level& B = C->L[l + 1];
         TileArgs<double> T{};
@@ -240,13 +265,13 @@ void vcycle_mpfc_t(mpfc_ctx* C, hipStream_t s) {
         T.complete_f = l > 0;
         T.nsweep = nsw1;
         T.H = round_even(nsw1 + 1);
-        const int shape = pick_shape(T.H);
+        const int shape = level_shape(A, SH_DN, T.H);
         tile_dims(A, shape, T.tx, T.ty);
         if (l == 0 && C->prof) prof_mark(C, 0, s);
         launch_tile<Op, false>(make_op<Op>(C, A), T, shape, stop, s);
         if (l == 0 && C->prof) prof_mark(C, 1, s);
     }
-    if (Lp < nl) {
+    if (Lp < nl && only < 0) {
         const Level& top = C->L[Lp];
         CoarseArgs<double> A{};
         A.geo = coarse_geom(C);
@@ -263,13 +288,14 @@ void vcycle_mpfc_t(mpfc_ctx* C, hipStream_t s) {
         A.newton_tol = 1e-15;
         const Level& cl = C->L[nl - 1];
         if (cl.m * cl.n == 4)
-            hipLaunchKernelGGL((k_coarse_persistent<Op, 256, 4>), dim3(1), dim3(256), 0, s,
+            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4>), dim3(1), dim3(CP_THREADS), 0, s,
                                make_op<Op>(C, top), A, stop);
         else
-            hipLaunchKernelGGL((k_coarse_persistent<Op, 256, 8>), dim3(1), dim3(256), 0, s,
+            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 8>), dim3(1), dim3(CP_THREADS), 0, s,
                                make_op<Op>(C, top), A, stop);
     }
     for (int l = Lp - 1; l >= 0; --l) {
+        if (only >= 0 && (l != only || !only_up)) continue;
         const Level& A = C->L[l];
         const Level& B = C->L[l + 1];
         TileArgs<double> T{};
@@ -283,19 +309,19 @@ void vcycle_mpfc_t(mpfc_ctx* C, hipStream_t s) {
         }
         T.xk = A.xk;
         T.nsweep = nsw2;
-        T.norm = l == 0;
+        T.norm = l == 0 && only < 0;
         T.H = l == 0 ? round_even(nsw2 + 1) : nsw2;
-        T.nst = C->st;
-        T.hist = C->hist;
-        T.tol = C->o.tol;
-        T.diverge = C->o.diverge;
-        T.h2 = A.h * A.h;
-        T.max_norms = C->o.max_cycles + 1;
-        const int shape = pick_shape(T.H);
+        T.part = C->part;
+        const int shape = level_shape(A, SH_UP, T.H);
         tile_dims(A, shape, T.tx, T.ty);
         if (l == 0 && C->prof) prof_mark(C, 2, s);
         launch_tile<Op, true>(make_op<Op>(C, A), T, shape, stop, s);
         if (l == 0 && C->prof) prof_mark(C, 3, s);
+        if (T.norm) {
+            const int nb = (A.m / T.tx) * (A.n / T.ty);
+            hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, nb, C->st,
+                               C->hist, A.h * A.h, C->o.tol, C->o.max_cycles + 1, C->o.diverge);
+        }
     }
 }
 
@@ -304,24 +330,25 @@ void resnorm(mpfc_ctx* C, hipStream_t s) {
     const size_t total = (size_t)lv.m * lv.n;
     const double h2 = lv.h * lv.h;
     const int max_norms = C->o.max_cycles + 1;
+    const unsigned nb = red_blocks(total);
     if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_resnorm<1, NT>), dim3(red_blocks(total)), dim3(NT), 0, s,
-                           finest_fields(C), level_op(C, lv), lv.g, h2, C->st, C->hist, C->o.tol,
-                           max_norms, C->o.diverge, nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL((k_resnorm<1, NT>), dim3(nb), dim3(NT), 0, s, finest_fields(C),
+                           level_op(C, lv), lv.g, C->st, C->part, nullptr, nullptr, nullptr);
     else
-        hipLaunchKernelGGL((k_resnorm<2, NT>), dim3(red_blocks(total)), dim3(NT), 0, s,
-                           finest_fields(C), level_op(C, lv), lv.g, h2, C->st, C->hist, C->o.tol,
-                           max_norms, C->o.diverge, nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL((k_resnorm<2, NT>), dim3(nb), dim3(NT), 0, s, finest_fields(C),
+                           level_op(C, lv), lv.g, C->st, C->part, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)nb, C->st,
+                       C->hist, h2, C->o.tol, max_norms, C->o.diverge);
 }
 
 // ---- mixed precision ---------------------------------------------------------------
 // One FP32 FAS V-cycle on the correction equation N(u + e) - N(u) = r (DEFECT
 // operators: the base phi of every level is a coefficient field).
 template <class Op>
-void vcycle_inner_t(mpfc_ctx* C, hipStream_t s) {
+void vcycle_inner_t(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) {
     using T = float;
     const int nl = (int)C->L.size(), Lp = C->Lp;
-    const CycleState* stop = C->st;
+    const CycleState* stop = only >= 0 ? nullptr : C->st;
     const int nsw1 = 2 * C->o.nu1, nsw2 = 2 * C->o.nu2;
     auto op_of = [&](const Level& lv) {
         Op o;
@@ -332,6 +359,7 @@ void vcycle_inner_t(mpfc_ctx* C, hipStream_t s) {
         return o;
     };
     for (int l = 0; l < Lp; ++l) {
+        if (only >= 0 && (l != only || only_up)) continue;
         const Level& A = C->L[l];
         const auto& FA = C->FL[l];
         const auto& FB = C->FL[l + 1];
@@ -351,11 +379,11 @@ void vcycle_inner_t(mpfc_ctx* C, hipStream_t s) {
         Tg.complete_f = l > 0;
         Tg.nsweep = nsw1;
         Tg.H = round_even(nsw1 + 1);
-        const int shape = pick_shape(Tg.H);
+        const int shape = level_shape(A, SH_DN32, Tg.H);
         tile_dims(A, shape, Tg.tx, Tg.ty);
         launch_tile<Op, false>(op_of(A), Tg, shape, stop, s);
     }
-    if (Lp < nl) {
+    if (Lp < nl && only < 0) {
         const Level& top = C->L[Lp];
         const auto& FT = C->FL[Lp];
         CoarseArgs<T> A{};
@@ -374,13 +402,14 @@ void vcycle_inner_t(mpfc_ctx* C, hipStream_t s) {
         A.newton_tol = 1e-6f;
         const Level& cl = C->L[nl - 1];
         if (cl.m * cl.n == 4)
-            hipLaunchKernelGGL((k_coarse_persistent<Op, 256, 4>), dim3(1), dim3(256), 0, s,
+            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4>), dim3(1), dim3(CP_THREADS), 0, s,
                                op_of(top), A, stop);
         else
-            hipLaunchKernelGGL((k_coarse_persistent<Op, 256, 8>), dim3(1), dim3(256), 0, s,
+            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 8>), dim3(1), dim3(CP_THREADS), 0, s,
                                op_of(top), A, stop);
     }
     for (int l = Lp - 1; l >= 0; --l) {
+        if (only >= 0 && (l != only || !only_up)) continue;
         const Level& A = C->L[l];
         const auto& FA = C->FL[l];
         const auto& FB = C->FL[l + 1];
@@ -398,7 +427,7 @@ void vcycle_inner_t(mpfc_ctx* C, hipStream_t s) {
         Tg.nsweep = nsw2;
         Tg.norm = 0;
         Tg.H = nsw2;
-        const int shape = pick_shape(Tg.H);
+        const int shape = level_shape(A, SH_UP32, Tg.H);
         tile_dims(A, shape, Tg.tx, Tg.ty);
         launch_tile<Op, true>(op_of(A), Tg, shape, stop, s);
     }
@@ -418,10 +447,12 @@ void defect(mpfc_ctx* C, int from, int add, hipStream_t s) {
     const int to = from ^ 1;
     const int max_norms = C->o.max_cycles + 1;
     auto kern = C->p.scheme == 1 ? k_defect<1, NT> : k_defect<2, NT>;
-    hipLaunchKernelGGL(kern, dim3(red_blocks(total)), dim3(NT), 0, s, F, level_op(C, F0), F0.g,
-                       F0.h * F0.h, C->st, C->hist, C->o.tol, max_norms, C->o.diverge,
+    const unsigned nb = red_blocks(total);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(NT), 0, s, F, level_op(C, F0), F0.g, C->st, C->part,
                        FF.e[0][0], FF.e[0][1], FF.e[0][2], add, F0.u[to][0], F0.u[to][1],
                        F0.u[to][2], FF.f[0], FF.f[1], FF.f[2], FF.pb);
+    hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)nb, C->st,
+                       C->hist, F0.h * F0.h, C->o.tol, max_norms, C->o.diverge);
 }
 
 // One outer iteration of mixed precision starting from FP64 copy `from`:
@@ -462,11 +493,12 @@ void vcycle_mpfc(mpfc_ctx* C, hipStream_t s) {
 }
 
 // One V-cycle of the Poisson problem -Lap_h w = b (same structure, scalar).
-void vcycle_poisson(mpfc_ctx* C, hipStream_t s) {
+void vcycle_poisson(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) {
     using Op = PoissonOp<double>;
     const int nl = (int)C->L.size(), Lp = C->Lp;
-    const CycleState* stop = C->pst;
+    const CycleState* stop = only >= 0 ? nullptr : C->pst;
     for (int l = 0; l < Lp; ++l) {
+        if (only >= 0 && (l != only || only_up)) continue;
         const Level& A = C->L[l];
         const Level& B = C->L[l + 1];
         TileArgs<double> T{};
@@ -478,10 +510,11 @@ void vcycle_poisson(mpfc_ctx* C, hipStream_t s) {
         T.complete_f = l > 0;
         T.nsweep = 4;
         T.H = 6;
-        tile_dims(A, 0, T.tx, T.ty);
-        launch_tile<Op, false>(make_op<Op>(C, A), T, 0, stop, s);
+        const int shape = level_shape(A, SH_PDN, T.H);
+        tile_dims(A, shape, T.tx, T.ty);
+        launch_tile<Op, false>(make_op<Op>(C, A), T, shape, stop, s);
     }
-    if (Lp < nl) {
+    if (Lp < nl && only < 0) {
         const Level& top = C->L[Lp];
         CoarseArgs<double> A{};
         A.geo = coarse_geom(C);
@@ -492,10 +525,11 @@ void vcycle_poisson(mpfc_ctx* C, hipStream_t s) {
         A.nsw2 = 4;
         A.complete_top = Lp > 0;
         A.G = C->G;
-        hipLaunchKernelGGL((k_coarse_persistent<Op, 256, 4>), dim3(1), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4>), dim3(1), dim3(CP_THREADS), 0, s,
                            make_op<Op>(C, top), A, stop);
     }
     for (int l = Lp - 1; l >= 0; --l) {
+        if (only >= 0 && (l != only || !only_up)) continue;
         const Level& A = C->L[l];
         const Level& B = C->L[l + 1];
         TileArgs<double> T{};
@@ -504,22 +538,26 @@ void vcycle_poisson(mpfc_ctx* C, hipStream_t s) {
         T.f[0] = A.pf;
         T.cuH[0] = B.w[0]; T.cvH[0] = B.pv;
         T.nsweep = 4;
-        T.norm = l == 0;
+        T.norm = l == 0 && only < 0;
         T.H = l == 0 ? 6 : 4;
-        T.nst = C->pst;
-        T.hist = C->phist;
-        T.tol = 0.0;   // the host compares with rtol * ||b||
-        T.diverge = 1e300;
-        T.h2 = 1.0;    // plain l2 norm of the Poisson residual
-        T.max_norms = 60;
-        tile_dims(A, 0, T.tx, T.ty);
-        launch_tile<Op, true>(make_op<Op>(C, A), T, 0, stop, s);
+        T.part = C->part;
+        const int shape = level_shape(A, SH_PUP, T.H);
+        tile_dims(A, shape, T.tx, T.ty);
+        launch_tile<Op, true>(make_op<Op>(C, A), T, shape, stop, s);
+        if (T.norm) {
+            // plain l2 norm; the host compares it with ||b|| (tol 0 never stops)
+            const int nb = (A.m / T.tx) * (A.n / T.ty);
+            hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, nb, C->pst,
+                               C->phist, 1.0, 0.0, 60, 1e300);
+        }
     }
-    if (Lp == 0) {
+    if (Lp == 0 && only < 0) {
         const Level& F0 = C->L[0];
-        hipLaunchKernelGGL((k_p_resnorm<NT>), dim3(red_blocks((size_t)F0.m * F0.n)), dim3(NT), 0,
-                           s, F0.w[0], F0.pf, F0.g, 1.0 / (F0.h * F0.h), C->pst, C->phist,
-                           C->acc + 9, 0.0, 60);
+        const unsigned nb = red_blocks((size_t)F0.m * F0.n);
+        hipLaunchKernelGGL((k_p_resnorm<NT>), dim3(nb), dim3(NT), 0, s, F0.w[0], F0.pf, F0.g,
+                           1.0 / (F0.h * F0.h), C->pst, C->part);
+        hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)nb,
+                           C->pst, C->phist, 1.0, 0.0, 60, 1e300);
     }
 }
 
@@ -569,6 +607,89 @@ int run_cycle(mpfc_ctx* C, int kind) {
         }
     }
     HIP_TRY(hipGraphLaunch(gx, s));
+    return MPFC_OK;
+}
+
+// ---- tile-shape autotuner ----------------------------------------------------------
+// For every level with tile launches and every launch kind, time each tile
+// shape whose halo allowance fits (one warm launch, then `reps` launches
+// between two events) and keep the fastest.  The iterates do not depend on
+// the shape (each cell's update is the same arithmetic in every tiling), so
+// tuning changes speed only.  MPFC_TILE_SHAPE=<k> forces shape k instead.
+template <class Fn>
+int tune_one(mpfc_ctx* C, Level& lv, int kind, int H, Fn&& launch) {
+    hipStream_t s = C->stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_k = pick_shape(H);
+    const int reps = 3;
+    for (int k = 0; k < kNumShapes; ++k) {
+        if (H > kShapes[k].hmax) continue;
+        lv.shape[kind] = k;
+        launch();
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch();
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; best_k = k; }
+    }
+    lv.shape[kind] = best_k;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return MPFC_OK;
+}
+
+int autotune(mpfc_ctx* C) {
+    const char* forced = std::getenv("MPFC_TILE_SHAPE");
+    if (forced && forced[0]) {
+        const int k = std::atoi(forced);
+        if (k < 0 || k >= kNumShapes) return fail(MPFC_EINVAL, "MPFC_TILE_SHAPE out of range");
+        for (auto& lv : C->L)
+            for (int kind = 0; kind < SH_KINDS; ++kind) lv.shape[kind] = k;
+        return MPFC_OK;
+    }
+    hipStream_t s = C->stream;
+    const bool nw = C->o.linearization == MPFC_NEWTON;
+    const int Hd = round_even(2 * C->o.nu1 + 1), Hu = round_even(2 * C->o.nu2 + 1);
+    for (int l = 0; l < C->Lp; ++l) {
+        Level& lv = C->L[l];
+        for (int up = 0; up < 2; ++up) {
+            const int H = up ? (l == 0 ? Hu : 2 * C->o.nu2) : Hd;
+            int rc = tune_one(C, lv, up ? SH_UP : SH_DN, H, [&] {
+                if (C->p.scheme == 1) {
+                    if (nw) vcycle_mpfc_t<MpfcOp<double, 1, true, false>>(C, s, l, up);
+                    else vcycle_mpfc_t<MpfcOp<double, 1, false, false>>(C, s, l, up);
+                } else {
+                    if (nw) vcycle_mpfc_t<MpfcOp<double, 2, true, false>>(C, s, l, up);
+                    else vcycle_mpfc_t<MpfcOp<double, 2, false, false>>(C, s, l, up);
+                }
+            });
+            if (rc) return rc;
+            if (C->o.precision == MPFC_MIXED) {
+                const int H32 = up ? 2 * C->o.nu2 : Hd;
+                rc = tune_one(C, lv, up ? SH_UP32 : SH_DN32, H32, [&] {
+                    if (C->p.scheme == 1) {
+                        if (nw) vcycle_inner_t<MpfcOp<float, 1, true, true>>(C, s, l, up);
+                        else vcycle_inner_t<MpfcOp<float, 1, false, true>>(C, s, l, up);
+                    } else {
+                        if (nw) vcycle_inner_t<MpfcOp<float, 2, true, true>>(C, s, l, up);
+                        else vcycle_inner_t<MpfcOp<float, 2, false, true>>(C, s, l, up);
+                    }
+                });
+                if (rc) return rc;
+            }
+            if (C->o.energy) {
+                rc = tune_one(C, lv, up ? SH_PUP : SH_PDN, up ? (l == 0 ? 6 : 4) : 6,
+                              [&] { vcycle_poisson(C, s, l, up); });
+                if (rc) return rc;
+            }
+        }
+    }
+    HIP_TRY(hipGetLastError());
     return MPFC_OK;
 }
 
@@ -658,10 +779,11 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
     Level& F0 = C->L[0];
     const size_t total = (size_t)C->m * C->n;
     const unsigned rb = red_blocks(total);
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, C->acc, 16);
-    hipLaunchKernelGGL((k_sum<NT>), dim3(rb), dim3(NT), 0, s, psi, total, C->acc + 8);
+    hipLaunchKernelGGL((k_sum<NT>), dim3(rb), dim3(NT), 0, s, psi, total, C->part);
+    hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 1, C->acc + 8);
     hipLaunchKernelGGL((k_p_rhs<NT>), dim3(rb), dim3(NT), 0, s, psi, total, C->acc + 8, F0.pf,
-                       C->acc + 9);
+                       C->part);
+    hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 1, C->acc + 9);
     if (!C->have_w) {
         hipLaunchKernelGGL((k_fill<double>), grid1(total), dim3(256), 0, s, F0.w[0], total, 0.0);
     } else if (mu) {
@@ -669,7 +791,9 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
         double a, b;
         if (C->p.scheme == 1) { a = 1.0 / (1.0 + sb); b = sM / (1.0 + sb); }
         else { a = (1.0 - 0.5 * sb) / (1.0 + 0.5 * sb); b = sM / (1.0 + 0.5 * sb); }
-        hipLaunchKernelGGL((k_sum<NT>), dim3(rb), dim3(NT), 0, s, mu, total, C->acc + 10);
+        hipLaunchKernelGGL((k_sum<NT>), dim3(rb), dim3(NT), 0, s, mu, total, C->part);
+        hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 1,
+                           C->acc + 10);
         hipLaunchKernelGGL((k_w_advance), grid1(total), dim3(256), 0, s, F0.w[0], mu, total, a, b,
                            C->acc + 10);
     }
@@ -705,7 +829,8 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
         C->poisson_cycles -= 1;
     C->have_w = 1;
     hipLaunchKernelGGL((k_energy_terms<NT>), dim3(rb), dim3(NT), 0, s, F0.g, 1.0 / (F0.h * F0.h),
-                       phi, phiprev, F0.pf, F0.w[0], C->acc);
+                       phi, phiprev, F0.pf, F0.w[0], C->part);
+    hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 8, C->acc);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(C->host_buf, C->acc, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -864,6 +989,8 @@ int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_o
         C->hist = take(o->max_cycles + 1 + 8);
         C->phist = take(64);
         C->acc = take(64);
+        C->nparts = (int)((size_t)m * n / 256 > 4096 ? (size_t)m * n / 256 : 4096);
+        C->part = take((size_t)C->nparts);
         C->st = (CycleState*)take(16);
         C->pst = (CycleState*)take(16);
         return off;
@@ -881,11 +1008,23 @@ int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_o
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&C->host_buf, sizeof(double) * (size_t)(o->max_cycles + 128),
                           hipHostMallocDefault);
+    // zero the whole arena once (the autotuner runs the tile kernels on it)
+    if (e == hipSuccess) e = hipMemsetAsync(C->arena, 0, C->arena_bytes, C->stream);
     if (e == hipSuccess)
-        e = hipMemcpy(C->G, G.data(), nG * sizeof(double), hipMemcpyHostToDevice);
+        e = hipMemcpyAsync(C->G, G.data(), nG * sizeof(double), hipMemcpyHostToDevice, C->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(C->stream);
     if (e != hipSuccess) {
         mpfc_destroy(C);
         return fail(MPFC_EHIP, std::string("context setup: ") + hipGetErrorString(e));
+    }
+    rc = autotune(C);
+    if (rc == MPFC_OK) {
+        e = hipStreamSynchronize(C->stream);
+        if (e != hipSuccess) rc = fail(MPFC_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+    }
+    if (rc) {
+        mpfc_destroy(C);
+        return rc;
     }
     *out = C;
     return MPFC_OK;

@@ -104,12 +104,9 @@ struct TileArgs {
     int nsweep;             // red-black half-sweeps (2 nu)
     int H;                  // halo (even)
     int tx, ty;             // interior tile (even, divides m, n)
-    // residual norm (finest up): h^2-weighted, FP64, last-block finalizer
+    // residual norm (finest up): per-block FP64 sums of r^2 into part[]
     int norm;
-    CycleState* nst;
-    double* hist;
-    double tol, diverge, h2;
-    int max_norms;
+    double* part;
 };
 
 template <typename T>
@@ -120,22 +117,6 @@ __device__ __forceinline__ T bilinear(const T* __restrict__ uH, const T* __restr
     return T(9.0 / 16.0) * (uH[a] - vH[a]) +
            T(3.0 / 16.0) * ((uH[b] - vH[b]) + (uH[c] - vH[c])) +
            T(1.0 / 16.0) * (uH[d] - vH[d]);
-}
-
-__device__ __forceinline__ void finalize_norm(CycleState* st, double* hist, double nr, double tol,
-                                              int max_norms, double diverge) {
-    const int k = st->count;
-    hist[k] = nr;
-    st->count = k + 1;
-    int status = ST_RUNNING;
-    if (!(nr == nr) || nr > 1.0e300) status = ST_NONFINITE;
-    else if (nr <= tol) status = ST_CONVERGED;
-    else if (k > 0 && nr > diverge * hist[0]) status = ST_DIVERGED;
-    else if (k + 1 >= max_norms) status = ST_MAXCYC;
-    st->status = status;
-    st->done = status != ST_RUNNING;
-    st->acc = 0.0;
-    st->blocks = 0u;
 }
 
 // One tile kernel for both directions.  Grid: (m / tx, n / ty), 256 threads.
@@ -149,8 +130,8 @@ __global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real>
     constexpr int LYM = TY + 2 * HMAX;
     constexpr int SL = (LX2M * (LYM / 2) + NT - 1) / NT;  // owned blocks per thread
     __shared__ T U[NF][2][LYM][LX2M];
+    __shared__ T E[UP ? NF : 1][UP ? LYM / 2 + 2 : 1][UP ? LX2M + 2 : 1];  // up: uH - vH
     __shared__ double red[NT / 64];
-    __shared__ int last;
     if (stopped(stop)) return;
 
     const Grid g = A.g;
@@ -200,25 +181,36 @@ __global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real>
     }
 
     // 3. up: add the coarse-grid correction P(uH - vH) to every loaded cell.
+    //    uH - vH over the tile's coarse footprint (one coarse cell of margin)
+    //    is staged in LDS first, read coalesced.
     if constexpr (UP) {
         const int mc = g.m >> 1, nc = g.n >> 1;
+        const int CX = LX2 + 2, CY = (LY >> 1) + 2;
+        const int cx0 = (x0 >> 1) - 1, cy0 = (y0 >> 1) - 1;
+        for (int q = t; q < CX * CY; q += NT) {
+            const int cy = q / CX, cx = q - cy * CX;
+            const size_t gq = (size_t)((cy0 + cy) & (nc - 1)) * mc + ((cx0 + cx) & (mc - 1));
+#pragma unroll
+            for (int f = 0; f < NF; ++f) E[f][cy][cx] = A.cuH[f][gq] - A.cvH[f][gq];
+        }
+        __syncthreads();
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             const int b = t + s * NT;
             if (b >= nblk) continue;
             const int by = b / LX2, bx = b - by * LX2;
-            const int I = ((x0 + 2 * bx) & (g.m - 1)) >> 1;
-            const int J = ((y0 + 2 * by) & (g.n - 1)) >> 1;
-            const int Im = (I - 1) & (mc - 1), Ip = (I + 1) & (mc - 1);
-            const int Jm = (J - 1) & (nc - 1), Jp = (J + 1) & (nc - 1);
+            const int cx = bx + 1, cy = by + 1;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
                 const int x = 2 * bx + dx, y = 2 * by + dy;
-                const int Is = dx ? Ip : Im, Js = dy ? Jp : Jm;
+                const int sx = dx ? cx + 1 : cx - 1, sy = dy ? cy + 1 : cy - 1;
 #pragma unroll
                 for (int f = 0; f < NF; ++f)
-                    U[f][(x + y) & 1][y][x >> 1] += bilinear<T>(A.cuH[f], A.cvH[f], I, J, Is, Js, mc);
+                    U[f][(x + y) & 1][y][x >> 1] +=
+                        T(9.0 / 16.0) * E[f][cy][cx] +
+                        T(3.0 / 16.0) * (E[f][cy][sx] + E[f][sy][cx]) +
+                        T(1.0 / 16.0) * E[f][sy][sx];
             }
         }
         __syncthreads();
@@ -366,20 +358,9 @@ __global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real>
         }
     } else {
         if (A.norm) {
+            // per-block sum of r^2; k_norm_finalize adds them and decides
             const double bs = block_sum<NT>(acc, red);
-            if (t == 0) {
-                atomicAdd(&A.nst->acc, bs);
-                __threadfence();
-                const unsigned done = atomicAdd(&A.nst->blocks, 1u);
-                last = (done == gridDim.x * gridDim.y - 1);
-            }
-            __syncthreads();
-            if (last && t == 0) {
-                __threadfence();
-                const double tot = atomicAdd(&A.nst->acc, 0.0);
-                finalize_norm(A.nst, A.hist, sqrt(A.h2 * tot), A.tol, A.max_norms, A.diverge);
-                __threadfence();
-            }
+            if (t == 0) A.part[blockIdx.y * gridDim.x + blockIdx.x] = bs;
         }
     }
 }
@@ -391,6 +372,7 @@ __global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real>
 constexpr int CP_CELLS = 1024;  // largest level handled here (32 x 32)
 constexpr int CP_TOTAL = 1368;  // cells of all its levels (1024 + 256 + 64 + 16 + 4, padded)
 constexpr int CP_MAXLEV = 12;
+constexpr int CP_THREADS = 512;  // threads of the persistent workgroup
 
 struct CoarseGeom {
     int nlev;             // levels in this kernel (top first)
