@@ -37,6 +37,21 @@ MODEL_BYTES = {"down": 2 * 80.0 + 68.0, "up": 60.0 + 2 * 80.0 + 56.0}
 # writes u (24 B) and the coarse u, v, R r (9 quarter fields, 18 B); up reads
 # u, S, phi^k (56 B) and the coarse u, v (6 quarter fields, 12 B), writes u (24 B).
 COMPULSORY_BYTES = {"down": 56.0 + 24.0 + 18.0, "up": 56.0 + 12.0 + 24.0}
+# HBM bytes per finest-level launch measured with rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by a 128 MiB copy), valid only for the kernel sources
+# they were measured on (hash of paper_1208_2643_amd/csrc/*).
+MEASURED_TRAFFIC = {"src": "c0d5372ce39ed118", "up": 107387244.0, "down": 112928009.0}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    import glob
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1208_2643_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -185,7 +200,8 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS if achieved else None,
-            "traffic": None,
+            "traffic": (MEASURED_TRAFFIC[dom] if kernel_source_hash() == MEASURED_TRAFFIC["src"]
+                        else None),
             "bytes_per_launch": MODEL_BYTES[dom] * cells,
             "avg_launch_us": avg_s * 1e6,
             "compulsory_GBps": compulsory,

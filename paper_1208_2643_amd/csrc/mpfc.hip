@@ -138,7 +138,7 @@ struct mpfc_ctx {
     };
     std::vector<FLevel> FL;
     int inner_cycles = 3;
-    int mp_cur = 0;                        // FP64 copy of u holding the iterate
+    int pred_units = 4;                    // cycles (outer iterations) the last step needed
     hipGraphExec_t gx_mixed[2] = {};       // one outer iteration, from copy 0 / copy 1
 };
 
@@ -1104,12 +1104,21 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(C->host_st, C->st, sizeof(CycleState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    for (int guard = 0; !C->host_st->done; ++guard) {
-        if (guard > C->o.max_cycles + 1)
+    // Cycles are enqueued speculatively: the first batch is one less than the
+    // previous step needed, then one at a time.  A cycle enqueued after the
+    // stop flag was raised exits at once in every kernel, so speculation only
+    // costs launches, never changes the result.  (Mixed precision: outer
+    // iteration k reads FP64 copy 1 ^ (k & 1).)
+    int launched = 0;
+    int batch = C->prof ? 1 : (C->pred_units > 1 ? C->pred_units - 1 : 1);
+    while (!C->host_st->done) {
+        if (launched > C->o.max_cycles + 1)
             return fail(MPFC_EHIP, "internal: cycle state did not advance");
-        int rc = run_cycle(C, mixed ? CYC_MIXED0 + cur : CYC_MPFC);
-        if (rc) return rc;
-        if (mixed) cur ^= 1;
+        for (int b = 0; b < batch; ++b, ++launched) {
+            int rc = run_cycle(C, mixed ? CYC_MIXED0 + (1 ^ (launched & 1)) : CYC_MPFC);
+            if (rc) return rc;
+        }
+        batch = 1;
         HIP_TRY(hipMemcpyAsync(C->host_st, C->st, sizeof(CycleState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (C->prof && C->Lp > 0 && !mixed) prof_collect(C);
@@ -1117,6 +1126,8 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     const CycleState fin = *C->host_st;
     const int nouter = fin.count - 1;
     const int ncyc = mixed ? nouter * C->inner_cycles : nouter;
+    C->pred_units = nouter > 0 ? nouter : 1;
+    if (mixed) cur = 1 ^ (nouter & 1);
     phi = F0.u[cur][0];
     mu = F0.u[cur][1];
     ka = F0.u[cur][2];

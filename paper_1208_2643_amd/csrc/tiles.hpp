@@ -138,7 +138,21 @@ __global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real>
     const int H = A.H, tx = A.tx, ty = A.ty;
     const int LX = tx + 2 * H, LY = ty + 2 * H, LX2 = LX >> 1;
     const int nblk = LX2 * (LY >> 1);
-    const int x0 = (int)blockIdx.x * tx - H, y0 = (int)blockIdx.y * ty - H;
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs,
+    // each with its own L2.  Workgroup b (on XCD b % 8) takes tile
+    // (b % 8) * (tiles / 8) + b / 8, so every XCD sweeps one contiguous strip
+    // of tiles and the halos it re-reads are mostly in its own L2.
+    int tbx = blockIdx.x, tby = blockIdx.y;
+    {
+        const int nt = gridDim.x * gridDim.y;
+        if ((nt & 7) == 0) {
+            const int b = blockIdx.y * gridDim.x + blockIdx.x;
+            const int tl = (b & 7) * (nt >> 3) + (b >> 3);
+            tby = tl / gridDim.x;
+            tbx = tl - tby * gridDim.x;
+        }
+    }
+    const int x0 = tbx * tx - H, y0 = tby * ty - H;
     const int t = threadIdx.x;
 
     // 1. u (tile + halo) into LDS, coalesced along rows.
@@ -282,7 +296,7 @@ __global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real>
     }
 
     // 5. interior u back to global memory, coalesced along rows.
-    const int gx0 = (int)blockIdx.x * tx, gy0 = (int)blockIdx.y * ty;
+    const int gx0 = tbx * tx, gy0 = tby * ty;
     for (int q = t; q < tx * ty; q += NT) {
         const int yi = q / tx, xi = q - yi * tx;
         const int x = xi + H, y = yi + H;
