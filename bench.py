@@ -66,6 +66,8 @@ def parse():
                     help="first run a plain 128 MiB device copy (counter calibration)")
     ap.add_argument("--variants", type=int, default=1,
                     help="also time the mixed-precision variant of the workload")
+    ap.add_argument("--batch-steps", type=int, default=50,
+                    help="steps of the 64-simulation batched variant (0 skips it)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
@@ -94,6 +96,46 @@ def cpu_baseline(params, phi0, tol, budget_s):
             "sample": f"first {steps} step(s) of the same {phi0.shape[1]}x{phi0.shape[0]} "
                       f"workload from its initial state ({cycles} V-cycles, energies on), "
                       f"{dt:.1f} s wall"}
+
+
+def bench_batch(api, inputs, torch, dev, steps, warmup):
+    specs = inputs.batch(64)
+    sims = [(sp.N, sp.N, api.Params(eps=sp.eps, beta=sp.beta, M=1.0, h=math.pi / 4, dt=0.05,
+                                    scheme=2)) for sp in specs]
+    t_create = time.perf_counter()
+    b = api.Batch(sims, nu1=2, nu2=2, tol=1e-10, precision=1)
+    t_create = time.perf_counter() - t_create
+    phi = [torch.from_numpy(sp.phi0).to(dev) for sp in specs]
+    prev = [t.clone() for t in phi]
+    psi = [torch.zeros_like(t) for t in phi]
+    nxt = [torch.empty_like(t) for t in phi]
+    cells = [sp.N * sp.N for sp in specs]
+
+    def one():
+        nonlocal phi, prev, nxt
+        infos = b.step(phi, prev, psi, nxt, history=False)
+        prev, phi, nxt = phi, nxt, prev
+        return infos
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    work = 0.0
+    outer = 0
+    for k in range(steps):
+        infos = one()
+        work += sum(3.0 * c * i.n_cycles for c, i in zip(cells, infos))
+        outer += max(i.outer_iters for i in infos)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    b.close()
+    return {"simulations": len(sims), "steps": steps, "sim_steps_per_s": len(sims) * steps / el,
+            "batch_steps_per_s": steps / el, "cells": int(sum(cells)),
+            "unknowns_x_fp32_vcycles_per_s": work / el,
+            "max_outer_per_step": outer / steps, "create_s": t_create,
+            "precision": "mixed (FP32 correction cycles, FP64 defect correction)",
+            "sizes": {str(n): sum(1 for sp in specs if sp.N == n) for n in (128, 256, 512, 1024)}}
 
 
 def main():
@@ -242,6 +284,12 @@ def main():
         out["variants"]["mixed"] = {"time_steps_per_s": vsteps / el, "steps": vsteps,
                                     "outer_per_step": outer / vsteps,
                                     "fp32_vcycles_per_step": inner / vsteps}
+    # Batched workload: 64 independent simulations, sizes uniform over
+    # {128, ..., 1024}^2, eps / mean phi / beta drawn per simulation, seeded
+    # noise, mixed precision, all advanced together by shared launches.
+    if args.variants and args.batch_steps > 0:
+        out["variants"]["batch64"] = bench_batch(api, inputs, torch, dev, args.batch_steps,
+                                                 args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(params, phi0, tol, args.cpu_seconds)
     print(json.dumps(out), flush=True)

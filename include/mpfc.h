@@ -186,6 +186,47 @@ int mpfc_op_source(const mpfc_params *p, int m, int n, const double *d_phik,
 /* Average of the 2x2 fine cells under each coarse cell: (m/2) x (n/2) out. */
 int mpfc_op_restrict(int m, int n, const double *d_fine, double *d_coarse, void *stream);
 
+/* ---- batched simulations ------------------------------------------------------
+ * Many independent simulations, each with its own grid size and parameters
+ * (same scheme), advanced one time step at a time by shared launches: each
+ * stage of the step (set-up, the tiled levels of one size, the coarse levels,
+ * the residual, the psi update) is one launch over the work of every
+ * simulation, and each simulation stops on its own residual test (Sec. 4's
+ * V-cycle iteration, run per simulation).  A simulation's iterates are those
+ * of a single-grid context with the same options. */
+#define MPFC_BATCH_MAX 4096
+
+typedef struct {
+    int m, n;            /* grid cells in x and y (powers of two, m n > 1024) */
+    mpfc_params p;       /* eps, beta, M, h, dt, scheme (scheme equal across the batch) */
+} mpfc_sim_desc;
+
+typedef struct mpfc_batch mpfc_batch;
+
+/* Create a batch of `nsim` simulations (1 ... MPFC_BATCH_MAX): every one is
+ * validated as by mpfc_validate, and gets its own level hierarchy and
+ * workspace on the current device.  The options apply to all of them; the
+ * energy option is ignored (a batch computes no energies).  Tile shapes are
+ * chosen by timing every launch of the batch at creation.  *out is owned by
+ * the caller and released by mpfc_batch_destroy.  `stream` orders all work. */
+int mpfc_batch_create(mpfc_batch **out, int nsim, const mpfc_sim_desc *sims,
+                      const mpfc_opts *o, void *stream);
+
+/* One time step of every simulation.  Each argument is a host array of nsim
+ * device pointers with the meaning of mpfc_step's argument of that name
+ * (d_phi_nm1 may be NULL, or hold NULL entries: phi^{k-1} = phi^k).
+ * h_infos: NULL, or nsim reports (residual_history honoured per entry;
+ * energies are 0).  Returns MPFC_OK when every simulation converged, else the
+ * status of the first one that did not (all outputs are still written). */
+int mpfc_batch_step(mpfc_batch *b, const double *const *d_phi_n,
+                    const double *const *d_phi_nm1, double *const *d_psi,
+                    double *const *d_phi_np1, mpfc_info *h_infos);
+
+/* Number of simulations (0 for NULL). */
+int mpfc_batch_size(const mpfc_batch *b);
+
+void mpfc_batch_destroy(mpfc_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,13 @@ class mpfc_info(ctypes.Structure):
                 ("residual_history", ctypes.POINTER(ctypes.c_double))]
 
 
+class mpfc_sim_desc(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("n", ctypes.c_int), ("p", mpfc_params)]
+
+
+MPFC_BATCH_MAX = 4096
+
+
 class MpfcError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"mpfc error {code}: {msg}")
@@ -83,6 +90,12 @@ SIGNATURES = {
     "mpfc_op_source": (_i, [ctypes.POINTER(mpfc_params), _i, _i, _vp, _vp, _vp, _vp, _vp, _vp,
                             _vp]),
     "mpfc_op_restrict": (_i, [_i, _i, _vp, _vp, _vp]),
+    "mpfc_batch_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(mpfc_sim_desc),
+                               ctypes.POINTER(mpfc_opts), _vp]),
+    "mpfc_batch_step": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                             ctypes.POINTER(_vp), ctypes.POINTER(mpfc_info)]),
+    "mpfc_batch_size": (_i, [_vp]),
+    "mpfc_batch_destroy": (None, [_vp]),
 }
 
 

@@ -105,7 +105,8 @@ class Stepper:
                                 _ptr(mu), _ptr(kappa), ctypes.byref(info))
         allow = (L.MPFC_ENOTCONVERGED, L.MPFC_ENONFINITE, L.MPFC_EDIVERGED) if allow_fail else ()
         L.check(rc, allow)
-        si = StepInfo(rc, info.n_cycles, info.residual, self._hist[: info.n_cycles + 1].copy(),
+        nh = (info.outer_iters if self.opts.precision == L.MPFC_MIXED else info.n_cycles) + 1
+        si = StepInfo(rc, info.n_cycles, info.residual, self._hist[:nh].copy(),
                       info.energy_F, info.energy_pseudo, info.energy_mod, info.mass,
                       info.outer_iters)
         return phi_np1, si
@@ -125,6 +126,90 @@ class Stepper:
         out = (ctypes.c_double * 4)()
         L.check(self.lib.mpfc_energies(self.ctx, _ptr(phi), _ptr(phi_prev), _ptr(psi), out))
         return np.array(out[:])
+
+
+class Batch:
+    """Many independent simulations advanced together (mpfc_batch_*).
+
+    `sims` is a list of (m, n, Params) with one scheme; every option applies
+    to all of them.  Fields are lists of (n, m) float64 GPU tensors, one per
+    simulation."""
+
+    def __init__(self, sims, stream=None, **opts):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libmpfc needs a HIP GPU; none is visible")
+        self.lib = L.load()
+        self.sims = [(int(m), int(n), p) for m, n, p in sims]
+        self.nsim = len(self.sims)
+        self.opts = make_opts(**opts)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        desc = (L.mpfc_sim_desc * self.nsim)()
+        for k, (m, n, p) in enumerate(self.sims):
+            desc[k].m, desc[k].n, desc[k].p = m, n, p.c()
+        b = ctypes.c_void_p()
+        L.check(self.lib.mpfc_batch_create(ctypes.byref(b), self.nsim, desc,
+                                           ctypes.byref(self.opts), _stream(self.stream)))
+        self.b = b
+        self._hist = np.zeros((self.nsim, self.opts.max_cycles + 1))
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.lib.mpfc_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _arr(self, ts, allow_none=False):
+        if ts is None:
+            if allow_none:
+                return None
+            raise ValueError("a list of tensors is required")
+        if len(ts) != self.nsim:
+            raise ValueError(f"expected {self.nsim} tensors, got {len(ts)}")
+        a = (ctypes.c_void_p * self.nsim)()
+        for k, t in enumerate(ts):
+            m, n, _ = self.sims[k]
+            if t is not None and tuple(t.shape) != (n, m):
+                raise ValueError(f"simulation {k}: expected shape {(n, m)}, got {tuple(t.shape)}")
+            a[k] = _ptr(t).value if t is not None else None
+        return a
+
+    def step(self, phi_n, phi_nm1, psi, phi_np1, allow_fail=False, history=True):
+        """Advance every simulation one step (psi in place); returns a list of StepInfo."""
+        infos = (L.mpfc_info * self.nsim)()
+        if history:
+            for k in range(self.nsim):
+                infos[k].residual_history = self._hist[k].ctypes.data_as(
+                    ctypes.POINTER(ctypes.c_double))
+        rc = self.lib.mpfc_batch_step(self.b, self._arr(phi_n), self._arr(phi_nm1, True),
+                                      self._arr(psi), self._arr(phi_np1), infos)
+        allow = (L.MPFC_ENOTCONVERGED, L.MPFC_ENONFINITE, L.MPFC_EDIVERGED) if allow_fail else ()
+        L.check(rc, allow)
+        out = []
+        for k in range(self.nsim):
+            I = infos[k]
+            hist = self._hist[k][: I.outer_iters + 1 if self.opts.precision == L.MPFC_MIXED
+                                 else I.n_cycles + 1].copy() if history else np.zeros(0)
+            out.append(StepInfo(I.status, I.n_cycles, I.residual, hist, 0.0, 0.0, 0.0, 0.0,
+                                I.outer_iters))
+        return out
+
+
+def run_batch(batch: Batch, phi0s, steps: int):
+    """Run `steps` steps of every simulation from phi^0 (psi^0 = 0, phi^{-1} = phi^0)."""
+    phi = [t.clone() for t in phi0s]
+    prev = [t.clone() for t in phi0s]
+    psi = [torch.zeros_like(t) for t in phi0s]
+    nxt = [torch.empty_like(t) for t in phi0s]
+    infos = []
+    for _ in range(steps):
+        infos.append(batch.step(phi, prev, psi, nxt))
+        prev, phi, nxt = phi, nxt, prev
+    return phi, prev, psi, infos
 
 
 def run(stepper: Stepper, phi0: torch.Tensor, steps: int, record=None):

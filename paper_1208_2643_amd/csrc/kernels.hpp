@@ -22,7 +22,7 @@ namespace mpfc {
 // Stop/bookkeeping state of the cycle loop, kept on the device so that the
 // loop can run without a host round trip per kernel.
 struct CycleState {
-    double acc;          // residual-norm accumulator (sum of r^2)
+    double acc;          // latest residual norm (written with hist[count - 1])
     unsigned int blocks; // blocks that have added to acc
     int count;           // norms recorded so far (entries of hist)
     int status;          // 0 running, 1 converged, 2 cycle limit, 3 non-finite, 4 diverged
@@ -190,10 +190,9 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // cycle limit.  No atomics and no device-wide fences are involved, and the
 // norm is deterministic.
 template <int NT>
-__global__ void __launch_bounds__(NT) k_norm_finalize(const double* __restrict__ part, int nparts,
-                                                      CycleState* st, double* hist, double h2,
-                                                      double tol, int max_norms, double diverge) {
-    if (stopped(st)) return;
+__device__ __forceinline__ void norm_finalize_body(const double* __restrict__ part, int nparts,
+                                                   CycleState* st, double* hist, double h2,
+                                                   double tol, int max_norms, double diverge) {
     __shared__ double red[NT / 64];
     double s = 0.0;
     for (int b = threadIdx.x; b < nparts; b += NT) s += part[b];
@@ -202,6 +201,7 @@ __global__ void __launch_bounds__(NT) k_norm_finalize(const double* __restrict__
         const double nr = sqrt(h2 * tot);
         const int k = st->count;
         hist[k] = nr;
+        st->acc = nr;  // latest norm, read back with the state
         st->count = k + 1;
         int status = ST_RUNNING;
         if (!(nr == nr) || nr > 1.0e300) status = ST_NONFINITE;
@@ -211,6 +211,14 @@ __global__ void __launch_bounds__(NT) k_norm_finalize(const double* __restrict__
         st->status = status;
         st->done = status != ST_RUNNING;
     }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_norm_finalize(const double* __restrict__ part, int nparts,
+                                                      CycleState* st, double* hist, double h2,
+                                                      double tol, int max_norms, double diverge) {
+    if (stopped(st)) return;
+    norm_finalize_body<NT>(part, nparts, st, hist, h2, tol, max_norms, diverge);
 }
 
 // Finest-grid residual sum of squares sum_c sum_ij r_c^2 (FP64, the stopping
@@ -236,13 +244,49 @@ __global__ void __launch_bounds__(NT) k_resnorm(Fields<double> F, LevelOp<double
     if (threadIdx.x == 0) part[blockIdx.x] = bs;  // summed by k_norm_finalize
 }
 
-// Mixed precision, outer FP64 defect-correction step on the finest grid:
-// u += e (the FP32 correction), then r = S - N(u) in FP64 with its norm (the
-// stopping test, same bookkeeping as k_resnorm), and the inputs of the next
-// FP32 correction solve: r rounded to FP32, the base phi rounded to FP32, and
-// e reset to zero.  `add` = 0 skips the update (first residual of a step).
-// One thread per cell; the update of a cell's neighbours is recomputed from
-// u + e, so no other thread's write is read.
+// Mixed precision, outer FP64 defect-correction step on the finest grid, one
+// cell: u_new = u + e (the FP32 correction; `add` = 0 keeps u, for the first
+// residual of a step), r = S - N(u_new) in FP64, and the inputs of the next
+// FP32 correction solve: r rounded to FP32 and the base phi rounded to FP32.
+// The neighbours' u + e are recomputed here, so no other thread's write is
+// read.  Returns the cell's sum of squared residuals (the stopping test).
+template <int SCHEME>
+__device__ __forceinline__ double defect_cell(const Fields<double>& F, const LevelOp<double>& op,
+                                              const Grid& g, const float* __restrict__ e0,
+                                              const float* __restrict__ e1,
+                                              const float* __restrict__ e2, int add, double* un0,
+                                              double* un1, double* un2, float* r0, float* r1,
+                                              float* r2, float* pbase, int i, int j) {
+    const size_t q = at(i, j, g);
+    const size_t nb[4] = {at(wrapx(i + 1, g), j, g), at(wrapx(i - 1, g), j, g),
+                          at(i, wrapy(j + 1, g), g), at(i, wrapy(j - 1, g), g)};
+    auto val = [&](const double* u, const float* e, size_t k) {
+        return add ? u[k] + (double)e[k] : u[k];
+    };
+    const double x = val(F.phi, e0, q), y = val(F.mu, e1, q), z = val(F.ka, e2, q);
+    double sx = 0, sy = 0, sz = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        sx += val(F.phi, e0, nb[k]);
+        sy += val(F.mu, e1, nb[k]);
+        sz += val(F.ka, e2, nb[k]);
+    }
+    const double xk = SCHEME == 2 ? F.phik[q] : 0.0;
+    const double lphi = (sx - 4.0 * x) * op.ih2;
+    const double lmu = (sy - 4.0 * y) * op.ih2;
+    const double lka = (sz - 4.0 * z) * op.ih2;
+    const double a = F.f1[q] - (x - op.c * lmu);
+    const double b = F.f2[q] - (y - nl_value<double, SCHEME, false>(x, 0.0, xk) - op.al * x - lka);
+    const double c = F.f3[q] - (z - op.e * lphi);
+    un0[q] = x; un1[q] = y; un2[q] = z;
+    r0[q] = (float)a; r1[q] = (float)b; r2[q] = (float)c;
+    pbase[q] = (float)x;
+    return a * a + b * b + c * c;
+}
+
+// Whole finest grid, one thread per cell; per-block sums of r^2 into part[]
+// (summed by k_norm_finalize).  The correction e is cleared by the next
+// outer iteration, not here (neighbours still read it).
 template <int SCHEME, int NT>
 __global__ void __launch_bounds__(NT) k_defect(Fields<double> F, LevelOp<double> op, Grid g,
                                                const CycleState* st, double* part,
@@ -255,36 +299,11 @@ __global__ void __launch_bounds__(NT) k_defect(Fields<double> F, LevelOp<double>
     __shared__ double red[NT / 64];
     double acc = 0.0;
     const size_t total = (size_t)g.m * g.n;
-    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
-        const int i = (int)(q & (size_t)(g.m - 1));
-        const int j = (int)(q >> g.lm);
-        const size_t nb[4] = {at(wrapx(i + 1, g), j, g), at(wrapx(i - 1, g), j, g),
-                              at(i, wrapy(j + 1, g), g), at(i, wrapy(j - 1, g), g)};
-        auto val = [&](const double* u, const float* e, size_t k) {
-            return add ? u[k] + (double)e[k] : u[k];
-        };
-        const double x = val(F.phi, e0, q), y = val(F.mu, e1, q), z = val(F.ka, e2, q);
-        double sx = 0, sy = 0, sz = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            sx += val(F.phi, e0, nb[k]);
-            sy += val(F.mu, e1, nb[k]);
-            sz += val(F.ka, e2, nb[k]);
-        }
-        const double xk = SCHEME == 2 ? F.phik[q] : 0.0;
-        const double lphi = (sx - 4.0 * x) * op.ih2;
-        const double lmu = (sy - 4.0 * y) * op.ih2;
-        const double lka = (sz - 4.0 * z) * op.ih2;
-        const double a = F.f1[q] - (x - op.c * lmu);
-        const double b = F.f2[q] - (y - nl_value<double, SCHEME, false>(x, 0.0, xk) - op.al * x - lka);
-        const double c = F.f3[q] - (z - op.e * lphi);
-        acc += a * a + b * b + c * c;
-        un0[q] = x; un1[q] = y; un2[q] = z;
-        r0[q] = (float)a; r1[q] = (float)b; r2[q] = (float)c;
-        pbase[q] = (float)x;
-    }
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT)
+        acc += defect_cell<SCHEME>(F, op, g, e0, e1, e2, add, un0, un1, un2, r0, r1, r2, pbase,
+                                   (int)(q & (size_t)(g.m - 1)), (int)(q >> g.lm));
     const double bs = block_sum<NT>(acc, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = bs;  // summed by k_norm_finalize
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
 }
 
 template <typename TI, typename TO>
@@ -303,16 +322,14 @@ __global__ void k_state_reset(CycleState* st) {
 // ---------------------------------------------------------------------------
 // Step set-up and wrap-up kernels (one thread per cell).
 
-// Source S (App. B.1 / B.2).  d = weight of psi^k.
+// Source S (App. B.1 / B.2) at cell (i, j).  d = weight of psi^k.
 template <int SCHEME>
-__global__ void __launch_bounds__(256) k_source(Grid g, double ih2, double d, double alpha,
-                                                const double* __restrict__ phik,
-                                                const double* __restrict__ phikm1,
-                                                const double* __restrict__ psik, double* S1,
-                                                double* S2, double* S3, double* phik_copy) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= g.m || j >= g.n) return;
+__device__ __forceinline__ void source_cell(const Grid& g, double ih2, double d, double alpha,
+                                            const double* __restrict__ phik,
+                                            const double* __restrict__ phikm1,
+                                            const double* __restrict__ psik, double* S1,
+                                            double* S2, double* S3, double* phik_copy, int i,
+                                            int j) {
     const size_t q = at(i, j, g);
     const double pk = phik[q];
     if (phik_copy) phik_copy[q] = pk;
@@ -329,15 +346,39 @@ __global__ void __launch_bounds__(256) k_source(Grid g, double ih2, double d, do
     }
 }
 
+template <int SCHEME>
+__global__ void __launch_bounds__(256) k_source(Grid g, double ih2, double d, double alpha,
+                                                const double* __restrict__ phik,
+                                                const double* __restrict__ phikm1,
+                                                const double* __restrict__ psik, double* S1,
+                                                double* S2, double* S3, double* phik_copy) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.m || j >= g.n) return;
+    source_cell<SCHEME>(g, ih2, d, alpha, phik, phikm1, psik, S1, S2, S3, phik_copy, i, j);
+}
+
 // Initial guess phi^(0): phi^k (mode 0) or 2 phi^k - phi^{k-1} (mode 1).
+__device__ __forceinline__ double guess_value(int mode, double pk, double pkm1) {
+    return mode == 1 ? 2.0 * pk - pkm1 : pk;
+}
+
 __global__ void __launch_bounds__(256) k_guess(Grid g, int mode, const double* __restrict__ phik,
                                                const double* __restrict__ phikm1, double* phi) {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= (size_t)g.m * g.n) return;
-    phi[q] = mode == 1 ? 2.0 * phik[q] - phikm1[q] : phik[q];
+    phi[q] = guess_value(mode, phik[q], phikm1[q]);
 }
 
 // Consistent completion of the guess: kappa = S3 + e Lap phi (so N^(3) = S^(3)).
+__device__ __forceinline__ void complete_kappa_cell(const Grid& g, double ih2, double e,
+                                                    const double* __restrict__ phi,
+                                                    const double* __restrict__ S3, double* ka,
+                                                    int i, int j) {
+    const size_t q = at(i, j, g);
+    ka[q] = S3[q] + e * (nsum(phi, i, j, g) - 4.0 * phi[q]) * ih2;
+}
+
 __global__ void __launch_bounds__(256) k_complete_kappa(Grid g, double ih2, double e,
                                                         const double* __restrict__ phi,
                                                         const double* __restrict__ S3,
@@ -345,11 +386,24 @@ __global__ void __launch_bounds__(256) k_complete_kappa(Grid g, double ih2, doub
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.m || j >= g.n) return;
-    const size_t q = at(i, j, g);
-    ka[q] = S3[q] + e * (nsum(phi, i, j, g) - 4.0 * phi[q]) * ih2;
+    complete_kappa_cell(g, ih2, e, phi, S3, ka, i, j);
 }
 
 // ... and mu = S2 + g(phi) + al phi + Lap kappa (so N^(2) = S^(2)).
+template <int SCHEME>
+__device__ __forceinline__ void complete_mu_cell(const Grid& g, double ih2, double al,
+                                                 const double* __restrict__ phi,
+                                                 const double* __restrict__ phik,
+                                                 const double* __restrict__ ka,
+                                                 const double* __restrict__ S2, double* mu, int i,
+                                                 int j) {
+    const size_t q = at(i, j, g);
+    const double x = phi[q];
+    const double xk = SCHEME == 2 ? phik[q] : 0.0;
+    mu[q] = S2[q] + nl_value<double, SCHEME, false>(x, 0.0, xk) + al * x +
+            (nsum(ka, i, j, g) - 4.0 * ka[q]) * ih2;
+}
+
 template <int SCHEME>
 __global__ void __launch_bounds__(256) k_complete_mu(Grid g, double ih2, double al,
                                                      const double* __restrict__ phi,
@@ -359,11 +413,7 @@ __global__ void __launch_bounds__(256) k_complete_mu(Grid g, double ih2, double 
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.m || j >= g.n) return;
-    const size_t q = at(i, j, g);
-    const double x = phi[q];
-    const double xk = SCHEME == 2 ? phik[q] : 0.0;
-    mu[q] = S2[q] + nl_value<double, SCHEME, false>(x, 0.0, xk) + al * x +
-            (nsum(ka, i, j, g) - 4.0 * ka[q]) * ih2;
+    complete_mu_cell<SCHEME>(g, ih2, al, phi, phik, ka, S2, mu, i, j);
 }
 
 // 2x2 average (restriction of phi^k for the scheme-2 coarse operators).
@@ -382,16 +432,23 @@ __global__ void __launch_bounds__(256) k_restrict(Grid g, const TI* __restrict__
 // (2/s)(phi - phi^k) - psi^k (scheme 2, eq. discrete_2_b); in place on psi.
 // phi is also copied to phi_out (the caller's phi^{k+1}).
 template <int SCHEME>
+__device__ __forceinline__ void psi_cell(double s, const double* __restrict__ phi,
+                                         const double* __restrict__ phik, double* psi,
+                                         double* phi_out, size_t q) {
+    const double x = phi[q];
+    if constexpr (SCHEME == 1) psi[q] = (x - phik[q]) / s;
+    else psi[q] = (2.0 / s) * (x - phik[q]) - psi[q];
+    phi_out[q] = x;
+}
+
+template <int SCHEME>
 __global__ void __launch_bounds__(256) k_psi_update(size_t total, double s,
                                                     const double* __restrict__ phi,
                                                     const double* __restrict__ phik, double* psi,
                                                     double* phi_out) {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= total) return;
-    const double x = phi[q];
-    if constexpr (SCHEME == 1) psi[q] = (x - phik[q]) / s;
-    else psi[q] = (2.0 / s) * (x - phik[q]) - psi[q];
-    phi_out[q] = x;
+    psi_cell<SCHEME>(s, phi, phik, psi, phi_out, q);
 }
 
 }  // namespace mpfc

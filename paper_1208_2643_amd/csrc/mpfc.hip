@@ -238,6 +238,150 @@ void prof_collect(mpfc_ctx* C) {
     }
 }
 
+// ---- launch arguments of one level (shared by the single and batched paths) ------
+// FP64 MPFC system, down launch of tiled level l: smooth, residual, restrict.
+TileArgs<double> dn_args64(const mpfc_ctx* C, int l) {
+    const Level& A = C->L[l];
+    const Level& B = C->L[l + 1];
+    TileArgs<double> T{};
+    T.g = A.g;
+    for (int f = 0; f < 3; ++f) {
+        T.uin[f] = A.u[0][f];
+        T.uout[f] = A.u[1][f];
+        T.f[f] = l == 0 ? A.f[f] : A.rr[f];
+        T.fout[f] = A.f[f];
+        T.uH[f] = B.u[0][f];
+        T.vH[f] = B.v[f];
+        T.rH[f] = B.rr[f];
+    }
+    T.xk = A.xk;
+    T.complete_f = l > 0;
+    T.nsweep = 2 * C->o.nu1;
+    T.H = round_even(T.nsweep + 1);
+    return T;
+}
+
+// ... up launch: coarse-grid correction, smooth; the finest one also the norm.
+TileArgs<double> up_args64(const mpfc_ctx* C, int l, bool norm) {
+    const Level& A = C->L[l];
+    const Level& B = C->L[l + 1];
+    TileArgs<double> T{};
+    T.g = A.g;
+    for (int f = 0; f < 3; ++f) {
+        T.uin[f] = A.u[1][f];
+        T.uout[f] = A.u[0][f];
+        T.f[f] = A.f[f];
+        T.cuH[f] = B.u[0][f];
+        T.cvH[f] = B.v[f];
+    }
+    T.xk = A.xk;
+    T.nsweep = 2 * C->o.nu2;
+    T.norm = norm;
+    T.H = l == 0 ? round_even(T.nsweep + 1) : T.nsweep;
+    T.part = C->part;
+    return T;
+}
+
+// ... persistent launch: every level from Lp down.
+CoarseArgs<double> coarse_args64(const mpfc_ctx* C) {
+    const Level& top = C->L[C->Lp];
+    CoarseArgs<double> A{};
+    A.geo = coarse_geom(C);
+    for (int f = 0; f < 3; ++f) {
+        A.u[f] = top.u[0][f];
+        A.rr[f] = C->Lp > 0 ? top.rr[f] : top.f[f];
+    }
+    A.xk = top.xk;
+    A.h_top = top.h;
+    A.nsw1 = 2 * C->o.nu1;
+    A.nsw2 = 2 * C->o.nu2;
+    A.complete_top = C->Lp > 0;
+    A.newton_maxit = 30;
+    A.newton_tol = 1e-15;
+    return A;
+}
+
+// FP32 correction equation of mixed precision (same roles, FL buffers).
+template <class Op>
+Op make_op32(const mpfc_ctx* C, const Level& lv) {
+    Op o;
+    o.op.ih2 = (float)(1.0 / (lv.h * lv.h));
+    o.op.c = (float)C->c;
+    o.op.al = (float)(C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha);
+    o.op.e = (float)(C->p.scheme == 1 ? 1.0 : 0.5);
+    return o;
+}
+
+TileArgs<float> dn_args32(const mpfc_ctx* C, int l) {
+    const Level& A = C->L[l];
+    const auto& FA = C->FL[l];
+    const auto& FB = C->FL[l + 1];
+    TileArgs<float> T{};
+    T.g = A.g;
+    for (int f = 0; f < 3; ++f) {
+        T.uin[f] = FA.e[0][f];
+        T.uout[f] = FA.e[1][f];
+        T.f[f] = l == 0 ? FA.f[f] : FA.rr[f];
+        T.fout[f] = FA.f[f];
+        T.uH[f] = FB.e[0][f];
+        T.vH[f] = FB.v[f];
+        T.rH[f] = FB.rr[f];
+    }
+    T.xk = FA.xk;
+    T.pb = FA.pb;
+    T.complete_f = l > 0;
+    T.nsweep = 2 * C->o.nu1;
+    T.H = round_even(T.nsweep + 1);
+    return T;
+}
+
+TileArgs<float> up_args32(const mpfc_ctx* C, int l) {
+    const Level& A = C->L[l];
+    const auto& FA = C->FL[l];
+    const auto& FB = C->FL[l + 1];
+    TileArgs<float> T{};
+    T.g = A.g;
+    for (int f = 0; f < 3; ++f) {
+        T.uin[f] = FA.e[1][f];
+        T.uout[f] = FA.e[0][f];
+        T.f[f] = FA.f[f];
+        T.cuH[f] = FB.e[0][f];
+        T.cvH[f] = FB.v[f];
+    }
+    T.xk = FA.xk;
+    T.pb = FA.pb;
+    T.nsweep = 2 * C->o.nu2;
+    T.norm = 0;
+    T.H = T.nsweep;
+    return T;
+}
+
+CoarseArgs<float> coarse_args32(const mpfc_ctx* C) {
+    const Level& top = C->L[C->Lp];
+    const auto& FT = C->FL[C->Lp];
+    CoarseArgs<float> A{};
+    A.geo = coarse_geom(C);
+    for (int f = 0; f < 3; ++f) {
+        A.u[f] = FT.e[0][f];
+        A.rr[f] = C->Lp > 0 ? FT.rr[f] : FT.f[f];
+    }
+    A.xk = FT.xk;
+    A.pb = FT.pb;
+    A.h_top = (float)top.h;
+    A.nsw1 = 2 * C->o.nu1;
+    A.nsw2 = 2 * C->o.nu2;
+    A.complete_top = C->Lp > 0;
+    A.newton_maxit = 20;
+    A.newton_tol = 1e-6f;
+    return A;
+}
+
+// Coarsest-grid cell count (4 or 8) selects the persistent kernel's direct solve.
+bool coarsest_is_4(const mpfc_ctx* C) {
+    const Level& cl = C->L.back();
+    return cl.m * cl.n == 4;
+}
+
 // One FAS V-cycle of the MPFC system on all levels.  With `only` >= 0 just
 // the down (only_up = 0) or up (1) launch of that level is issued, without
 // the stop flag or the norm (used by the tile autotuner).
@@ -245,26 +389,10 @@ template <class Op>
 void vcycle_mpfc_t(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) {
     const int nl = (int)C->L.size(), Lp = C->Lp;
     const CycleState* stop = only >= 0 ? nullptr : C->st;
-    const int nsw1 = 2 * C->o.nu1, nsw2 = 2 * C->o.nu2;
     for (int l = 0; l < Lp; ++l) {
         if (only >= 0 && (l != only || only_up)) continue;
         const Level& A = C->L[l];
-        const Level& B = C->L[l + 1];
-        TileArgs<double> T{};
-        T.g = A.g;
-        for (int f = 0; f < 3; ++f) {
-            T.uin[f] = A.u[0][f];
-            T.uout[f] = A.u[1][f];
-            T.f[f] = l == 0 ? A.f[f] : A.rr[f];
-            T.fout[f] = A.f[f];
-            T.uH[f] = B.u[0][f];
-            T.vH[f] = B.v[f];
-            T.rH[f] = B.rr[f];
-        }
-        T.xk = A.xk;
-        T.complete_f = l > 0;
-        T.nsweep = nsw1;
-        T.H = round_even(nsw1 + 1);
+        TileArgs<double> T = dn_args64(C, l);
         const int shape = level_shape(A, SH_DN, T.H);
         tile_dims(A, shape, T.tx, T.ty);
         if (l == 0 && C->prof) prof_mark(C, 0, s);
@@ -272,46 +400,19 @@ void vcycle_mpfc_t(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) {
         if (l == 0 && C->prof) prof_mark(C, 1, s);
     }
     if (Lp < nl && only < 0) {
-        const Level& top = C->L[Lp];
-        CoarseArgs<double> A{};
-        A.geo = coarse_geom(C);
-        for (int f = 0; f < 3; ++f) {
-            A.u[f] = top.u[0][f];
-            A.rr[f] = Lp > 0 ? top.rr[f] : top.f[f];
-        }
-        A.xk = top.xk;
-        A.h_top = top.h;
-        A.nsw1 = nsw1;
-        A.nsw2 = nsw2;
-        A.complete_top = Lp > 0;
-        A.newton_maxit = 30;
-        A.newton_tol = 1e-15;
-        const Level& cl = C->L[nl - 1];
-        if (cl.m * cl.n == 4)
-            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4>), dim3(1), dim3(CP_THREADS), 0, s,
-                               make_op<Op>(C, top), A, stop);
+        const CoarseArgs<double> A = coarse_args64(C);
+        const Op op = make_op<Op>(C, C->L[Lp]);
+        if (coarsest_is_4(C))
+            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4>), dim3(1), dim3(CP_THREADS),
+                               0, s, op, A, stop);
         else
-            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 8>), dim3(1), dim3(CP_THREADS), 0, s,
-                               make_op<Op>(C, top), A, stop);
+            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 8>), dim3(1), dim3(CP_THREADS),
+                               0, s, op, A, stop);
     }
     for (int l = Lp - 1; l >= 0; --l) {
         if (only >= 0 && (l != only || !only_up)) continue;
         const Level& A = C->L[l];
-        const Level& B = C->L[l + 1];
-        TileArgs<double> T{};
-        T.g = A.g;
-        for (int f = 0; f < 3; ++f) {
-            T.uin[f] = A.u[1][f];
-            T.uout[f] = A.u[0][f];
-            T.f[f] = A.f[f];
-            T.cuH[f] = B.u[0][f];
-            T.cvH[f] = B.v[f];
-        }
-        T.xk = A.xk;
-        T.nsweep = nsw2;
-        T.norm = l == 0 && only < 0;
-        T.H = l == 0 ? round_even(nsw2 + 1) : nsw2;
-        T.part = C->part;
+        TileArgs<double> T = up_args64(C, l, l == 0 && only < 0);
         const int shape = level_shape(A, SH_UP, T.H);
         tile_dims(A, shape, T.tx, T.ty);
         if (l == 0 && C->prof) prof_mark(C, 2, s);
@@ -346,90 +447,33 @@ void resnorm(mpfc_ctx* C, hipStream_t s) {
 // operators: the base phi of every level is a coefficient field).
 template <class Op>
 void vcycle_inner_t(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) {
-    using T = float;
     const int nl = (int)C->L.size(), Lp = C->Lp;
     const CycleState* stop = only >= 0 ? nullptr : C->st;
-    const int nsw1 = 2 * C->o.nu1, nsw2 = 2 * C->o.nu2;
-    auto op_of = [&](const Level& lv) {
-        Op o;
-        o.op.ih2 = (T)(1.0 / (lv.h * lv.h));
-        o.op.c = (T)C->c;
-        o.op.al = (T)(C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha);
-        o.op.e = (T)(C->p.scheme == 1 ? 1.0 : 0.5);
-        return o;
-    };
     for (int l = 0; l < Lp; ++l) {
         if (only >= 0 && (l != only || only_up)) continue;
         const Level& A = C->L[l];
-        const auto& FA = C->FL[l];
-        const auto& FB = C->FL[l + 1];
-        TileArgs<T> Tg{};
-        Tg.g = A.g;
-        for (int f = 0; f < 3; ++f) {
-            Tg.uin[f] = FA.e[0][f];
-            Tg.uout[f] = FA.e[1][f];
-            Tg.f[f] = l == 0 ? FA.f[f] : FA.rr[f];
-            Tg.fout[f] = FA.f[f];
-            Tg.uH[f] = FB.e[0][f];
-            Tg.vH[f] = FB.v[f];
-            Tg.rH[f] = FB.rr[f];
-        }
-        Tg.xk = FA.xk;
-        Tg.pb = FA.pb;
-        Tg.complete_f = l > 0;
-        Tg.nsweep = nsw1;
-        Tg.H = round_even(nsw1 + 1);
+        TileArgs<float> Tg = dn_args32(C, l);
         const int shape = level_shape(A, SH_DN32, Tg.H);
         tile_dims(A, shape, Tg.tx, Tg.ty);
-        launch_tile<Op, false>(op_of(A), Tg, shape, stop, s);
+        launch_tile<Op, false>(make_op32<Op>(C, A), Tg, shape, stop, s);
     }
     if (Lp < nl && only < 0) {
-        const Level& top = C->L[Lp];
-        const auto& FT = C->FL[Lp];
-        CoarseArgs<T> A{};
-        A.geo = coarse_geom(C);
-        for (int f = 0; f < 3; ++f) {
-            A.u[f] = FT.e[0][f];
-            A.rr[f] = Lp > 0 ? FT.rr[f] : FT.f[f];
-        }
-        A.xk = FT.xk;
-        A.pb = FT.pb;
-        A.h_top = (T)top.h;
-        A.nsw1 = nsw1;
-        A.nsw2 = nsw2;
-        A.complete_top = Lp > 0;
-        A.newton_maxit = 20;
-        A.newton_tol = 1e-6f;
-        const Level& cl = C->L[nl - 1];
-        if (cl.m * cl.n == 4)
-            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4>), dim3(1), dim3(CP_THREADS), 0, s,
-                               op_of(top), A, stop);
+        const CoarseArgs<float> A = coarse_args32(C);
+        const Op op = make_op32<Op>(C, C->L[Lp]);
+        if (coarsest_is_4(C))
+            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4>), dim3(1), dim3(CP_THREADS),
+                               0, s, op, A, stop);
         else
-            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 8>), dim3(1), dim3(CP_THREADS), 0, s,
-                               op_of(top), A, stop);
+            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 8>), dim3(1), dim3(CP_THREADS),
+                               0, s, op, A, stop);
     }
     for (int l = Lp - 1; l >= 0; --l) {
         if (only >= 0 && (l != only || !only_up)) continue;
         const Level& A = C->L[l];
-        const auto& FA = C->FL[l];
-        const auto& FB = C->FL[l + 1];
-        TileArgs<T> Tg{};
-        Tg.g = A.g;
-        for (int f = 0; f < 3; ++f) {
-            Tg.uin[f] = FA.e[1][f];
-            Tg.uout[f] = FA.e[0][f];
-            Tg.f[f] = FA.f[f];
-            Tg.cuH[f] = FB.e[0][f];
-            Tg.cvH[f] = FB.v[f];
-        }
-        Tg.xk = FA.xk;
-        Tg.pb = FA.pb;
-        Tg.nsweep = nsw2;
-        Tg.norm = 0;
-        Tg.H = nsw2;
+        TileArgs<float> Tg = up_args32(C, l);
         const int shape = level_shape(A, SH_UP32, Tg.H);
         tile_dims(A, shape, Tg.tx, Tg.ty);
-        launch_tile<Op, true>(op_of(A), Tg, shape, stop, s);
+        launch_tile<Op, true>(make_op32<Op>(C, A), Tg, shape, stop, s);
     }
 }
 
@@ -846,6 +890,72 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
     return MPFC_OK;
 }
 
+// ---- one step, split for reuse by the batched path -------------------------------
+// Source (also copies phi^k), phi^k pyramid, guess and its completion, stop
+// state reset and the first residual norm (FP64), or for mixed precision the
+// FP32 coefficient pyramids and the first FP64 defect (copy 0 -> 1).
+int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const double* psi,
+                  hipStream_t s) {
+    const int nl = (int)C->L.size();
+    Level& F0 = C->L[0];
+    const Grid g0 = F0.g;
+    const size_t total = (size_t)C->m * C->n;
+    const double ih2 = 1.0 / (F0.h * F0.h);
+    double* phi = F0.u[0][0];
+    double* mu = F0.u[0][1];
+    double* ka = F0.u[0][2];
+    if (C->p.scheme == 1)
+        hipLaunchKernelGGL((k_source<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
+                           phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik);
+    else
+        hipLaunchKernelGGL((k_source<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
+                           phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik);
+    if (C->p.scheme == 2)
+        for (int l = 1; l < nl; ++l)
+            hipLaunchKernelGGL((k_restrict<double, double>), grid2(C->L[l].m, C->L[l].n), B2, 0, s,
+                               C->L[l - 1].g, C->L[l - 1].xk, C->L[l].xk);
+    hipLaunchKernelGGL(k_guess, grid1(total), dim3(256), 0, s, g0,
+                       C->o.guess == MPFC_GUESS_EXTRAP ? 1 : 0, phi_n, phi_nm1, phi);
+    const double e = C->p.scheme == 1 ? 1.0 : 0.5;
+    const double al = C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha;
+    hipLaunchKernelGGL(k_complete_kappa, grid2(C->m, C->n), B2, 0, s, g0, ih2, e, phi, F0.f[2], ka);
+    if (C->p.scheme == 1)
+        hipLaunchKernelGGL((k_complete_mu<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, phi,
+                           C->phik, ka, F0.f[1], mu);
+    else
+        hipLaunchKernelGGL((k_complete_mu<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, phi,
+                           C->phik, ka, F0.f[1], mu);
+    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->st);
+    if (C->o.precision != MPFC_MIXED) {
+        resnorm(C, s);
+    } else {
+        const auto& FF = C->FL[0];
+        if (C->p.scheme == 2) {
+            hipLaunchKernelGGL((k_convert<double, float>), grid1(total), dim3(256), 0, s, C->phik,
+                               FF.xk, total);
+            for (int l = 1; l < nl; ++l)
+                hipLaunchKernelGGL((k_restrict<float, float>), grid2(C->L[l].m, C->L[l].n), B2, 0,
+                                   s, C->L[l - 1].g, C->FL[l - 1].xk, C->FL[l].xk);
+        }
+        defect(C, 0, 0, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return MPFC_OK;
+}
+
+// psi update from FP64 copy `cur` and copy-out of phi^{k+1}.
+void step_epilogue(mpfc_ctx* C, int cur, const double* phi_n, double* psi, double* phi_np1,
+                   hipStream_t s) {
+    const size_t total = (size_t)C->m * C->n;
+    const double* phi = C->L[0].u[cur][0];
+    if (C->p.scheme == 1)
+        hipLaunchKernelGGL((k_psi_update<1>), grid1(total), dim3(256), 0, s, total, C->p.dt, phi,
+                           phi_n, psi, phi_np1);
+    else
+        hipLaunchKernelGGL((k_psi_update<2>), grid1(total), dim3(256), 0, s, total, C->p.dt, phi,
+                           phi_n, psi, phi_np1);
+}
+
 }  // namespace
 
 // ============================================================================
@@ -904,8 +1014,10 @@ int mpfc_prof_read(mpfc_ctx* C, int which, double* total_ms, long long* launches
     return MPFC_OK;
 }
 
-int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_opts* o,
-                void* stream) {
+// Context of one grid; `tune` = false skips the tile autotuner (the batched
+// path tunes its own launches).
+static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_opts* o,
+                      void* stream, bool tune) {
     if (!out) return fail(MPFC_EINVAL, "out is NULL");
     *out = nullptr;
     int rc = validate(m, n, p, o);
@@ -1017,7 +1129,7 @@ int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_o
         mpfc_destroy(C);
         return fail(MPFC_EHIP, std::string("context setup: ") + hipGetErrorString(e));
     }
-    rc = autotune(C);
+    rc = tune ? autotune(C) : MPFC_OK;
     if (rc == MPFC_OK) {
         e = hipStreamSynchronize(C->stream);
         if (e != hipSuccess) rc = fail(MPFC_EHIP, std::string("autotune: ") + hipGetErrorString(e));
@@ -1028,6 +1140,11 @@ int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_o
     }
     *out = C;
     return MPFC_OK;
+}
+
+int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_opts* o,
+                void* stream) {
+    return create_ctx(out, m, n, p, o, stream, true);
 }
 
 void mpfc_destroy(mpfc_ctx* C) {
@@ -1053,55 +1170,11 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
         return fail(MPFC_EINVAL, "phi_np1 must not alias an input");
     if (!phi_nm1) phi_nm1 = phi_n;
     hipStream_t s = C->stream;
-    const int nl = (int)C->L.size();
     Level& F0 = C->L[0];
-    const Grid g0 = F0.g;
     const size_t total = (size_t)C->m * C->n;
-    const double ih2 = 1.0 / (F0.h * F0.h);
-    double* phi = F0.u[0][0];
-    double* mu = F0.u[0][1];
-    double* ka = F0.u[0][2];
-    // source (also copies phi^k), phi^k pyramid, guess and its completion
-    if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_source<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
-                           phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik);
-    else
-        hipLaunchKernelGGL((k_source<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
-                           phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik);
-    if (C->p.scheme == 2)
-        for (int l = 1; l < nl; ++l)
-            hipLaunchKernelGGL((k_restrict<double, double>), grid2(C->L[l].m, C->L[l].n), B2, 0, s,
-                               C->L[l - 1].g, C->L[l - 1].xk, C->L[l].xk);
-    hipLaunchKernelGGL(k_guess, grid1(total), dim3(256), 0, s, g0,
-                       C->o.guess == MPFC_GUESS_EXTRAP ? 1 : 0, phi_n, phi_nm1, phi);
-    const double e = C->p.scheme == 1 ? 1.0 : 0.5;
-    const double al = C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha;
-    hipLaunchKernelGGL(k_complete_kappa, grid2(C->m, C->n), B2, 0, s, g0, ih2, e, phi, F0.f[2], ka);
-    if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_complete_mu<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, phi,
-                           C->phik, ka, F0.f[1], mu);
-    else
-        hipLaunchKernelGGL((k_complete_mu<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, phi,
-                           C->phik, ka, F0.f[1], mu);
-    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->st);
     const bool mixed = C->o.precision == MPFC_MIXED;
-    int cur = 0;
-    if (!mixed) {
-        resnorm(C, s);
-    } else {
-        // FP32 coefficient pyramids, then the first FP64 defect (copy 0 -> 1)
-        const auto& FF = C->FL[0];
-        if (C->p.scheme == 2) {
-            hipLaunchKernelGGL((k_convert<double, float>), grid1(total), dim3(256), 0, s, C->phik,
-                               FF.xk, total);
-            for (int l = 1; l < nl; ++l)
-                hipLaunchKernelGGL((k_restrict<float, float>), grid2(C->L[l].m, C->L[l].n), B2, 0,
-                                   s, C->L[l - 1].g, C->FL[l - 1].xk, C->FL[l].xk);
-        }
-        defect(C, 0, 0, s);
-        cur = 1;
-    }
-    HIP_TRY(hipGetLastError());
+    int rc0 = step_prologue(C, phi_n, phi_nm1, psi, s);
+    if (rc0) return rc0;
     HIP_TRY(hipMemcpyAsync(C->host_st, C->st, sizeof(CycleState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     // Cycles are enqueued speculatively: the first batch is one less than the
@@ -1127,17 +1200,11 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     const int nouter = fin.count - 1;
     const int ncyc = mixed ? nouter * C->inner_cycles : nouter;
     C->pred_units = nouter > 0 ? nouter : 1;
-    if (mixed) cur = 1 ^ (nouter & 1);
-    phi = F0.u[cur][0];
-    mu = F0.u[cur][1];
-    ka = F0.u[cur][2];
-    // psi update, copy-out of phi^{k+1} (and mu, kappa)
-    if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_psi_update<1>), grid1(total), dim3(256), 0, s, total, C->p.dt, phi,
-                           phi_n, psi, phi_np1);
-    else
-        hipLaunchKernelGGL((k_psi_update<2>), grid1(total), dim3(256), 0, s, total, C->p.dt, phi,
-                           phi_n, psi, phi_np1);
+    const int cur = mixed ? 1 ^ (nouter & 1) : 0;
+    double* phi = F0.u[cur][0];
+    double* mu = F0.u[cur][1];
+    double* ka = F0.u[cur][2];
+    step_epilogue(C, cur, phi_n, psi, phi_np1, s);
     if (mu_out) HIP_TRY(hipMemcpyAsync(mu_out, mu, total * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (ka_out) HIP_TRY(hipMemcpyAsync(ka_out, ka, total * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipGetLastError());
@@ -1302,3 +1369,5 @@ int mpfc_op_restrict(int m, int n, const double* fine, double* coarse, void* str
 }
 
 }  // extern "C"
+
+#include "batch_host.hpp"

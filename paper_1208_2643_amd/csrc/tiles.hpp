@@ -119,10 +119,19 @@ __device__ __forceinline__ T bilinear(const T* __restrict__ uH, const T* __restr
            T(1.0 / 16.0) * (uH[d] - vH[d]);
 }
 
-// One tile kernel for both directions.  Grid: (m / tx, n / ty), 256 threads.
+// XCD-aware order of nt work items: workgroups are dealt round-robin to the 8
+// XCDs, each with its own L2.  Workgroup b (on XCD b % 8) takes item
+// (b % 8) * (nt / 8) + b / 8, so every XCD sweeps one contiguous strip of
+// tiles and the halos it re-reads are mostly in its own L2.
+__device__ __forceinline__ int xcd_item(int b, int nt) {
+    return (nt & 7) == 0 ? (b & 7) * (nt >> 3) + (b >> 3) : b;
+}
+
+// Body of one tile launch (one workgroup, 256 threads) on tile (tbx, tby).
+// `pslot` is where the workgroup's residual sum goes in A.part.
 template <class Op, int TX, int TY, int HMAX, bool UP>
-__global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real> A,
-                                              const CycleState* stop) {
+__device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename Op::real>& A,
+                                          const CycleState* stop, int tbx, int tby, int pslot) {
     using T = typename Op::real;
     constexpr int NF = Op::NF;
     constexpr int NT = 256;
@@ -138,20 +147,6 @@ __global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real>
     const int H = A.H, tx = A.tx, ty = A.ty;
     const int LX = tx + 2 * H, LY = ty + 2 * H, LX2 = LX >> 1;
     const int nblk = LX2 * (LY >> 1);
-    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs,
-    // each with its own L2.  Workgroup b (on XCD b % 8) takes tile
-    // (b % 8) * (tiles / 8) + b / 8, so every XCD sweeps one contiguous strip
-    // of tiles and the halos it re-reads are mostly in its own L2.
-    int tbx = blockIdx.x, tby = blockIdx.y;
-    {
-        const int nt = gridDim.x * gridDim.y;
-        if ((nt & 7) == 0) {
-            const int b = blockIdx.y * gridDim.x + blockIdx.x;
-            const int tl = (b & 7) * (nt >> 3) + (b >> 3);
-            tby = tl / gridDim.x;
-            tbx = tl - tby * gridDim.x;
-        }
-    }
     const int x0 = tbx * tx - H, y0 = tby * ty - H;
     const int t = threadIdx.x;
 
@@ -374,9 +369,47 @@ __global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real>
         if (A.norm) {
             // per-block sum of r^2; k_norm_finalize adds them and decides
             const double bs = block_sum<NT>(acc, red);
-            if (t == 0) A.part[blockIdx.y * gridDim.x + blockIdx.x] = bs;
+            if (t == 0) A.part[pslot] = bs;
         }
     }
+}
+
+// One level of one grid.  Grid: (m / tx, n / ty) workgroups of 256 threads.
+template <class Op, int TX, int TY, int HMAX, bool UP>
+__global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real> A,
+                                              const CycleState* stop) {
+    const int nt = gridDim.x * gridDim.y;
+    const int tl = xcd_item(blockIdx.y * gridDim.x + blockIdx.x, nt);
+    const int tby = tl / gridDim.x, tbx = tl - tby * gridDim.x;
+    tile_body<Op, TX, TY, HMAX, UP>(op, A, stop, tbx, tby, tl);
+}
+
+// Batched launch: one level of many independent grids.  Each (grid, level)
+// has its own arguments, operator constants and stop flag; the work list
+// holds one entry per tile.
+template <class Op>
+struct BatchTile {
+    Op op;
+    TileArgs<typename Op::real> A;
+    const CycleState* stop;
+    int part_off;         // first slot of this grid's residual sums in A.part
+    int ntx;              // tiles in x
+};
+
+struct BatchItem {
+    int arg;              // index into the BatchTile array
+    int tile;             // linear tile index within that grid level
+};
+
+template <class Op, int TX, int TY, int HMAX, bool UP>
+__global__ void __launch_bounds__(256) k_tile_batched(const BatchTile<Op>* __restrict__ args,
+                                                      const BatchItem* __restrict__ items,
+                                                      int nitems) {
+    const int b = xcd_item(blockIdx.x, nitems);
+    const BatchItem it = items[b];
+    const BatchTile<Op>& BA = args[it.arg];
+    const int tby = it.tile / BA.ntx, tbx = it.tile - tby * BA.ntx;
+    tile_body<Op, TX, TY, HMAX, UP>(BA.op, BA.A, BA.stop, tbx, tby, BA.part_off + it.tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -550,8 +583,35 @@ __device__ void coarse_solve_poisson(T* w, const T* f, const T* v, const double*
 }
 
 template <class Op, int NTP, int NC>
+__device__ __forceinline__ void coarse_body(const Op& op_top,
+                                            const CoarseArgs<typename Op::real>& A,
+                                            const CycleState* stop);
+
+template <class Op, int NTP, int NC>
 __global__ void __launch_bounds__(NTP) k_coarse_persistent(Op op_top, CoarseArgs<typename Op::real> A,
                                                            const CycleState* stop) {
+    coarse_body<Op, NTP, NC>(op_top, A, stop);
+}
+
+// Batched: workgroup b runs the coarse levels of grid b.
+template <class Op>
+struct BatchCoarse {
+    Op op;
+    CoarseArgs<typename Op::real> A;
+    const CycleState* stop;
+};
+
+template <class Op, int NTP, int NC>
+__global__ void __launch_bounds__(NTP) k_coarse_persistent_batched(
+    const BatchCoarse<Op>* __restrict__ args) {
+    const BatchCoarse<Op>& B = args[blockIdx.x];
+    coarse_body<Op, NTP, NC>(B.op, B.A, B.stop);
+}
+
+template <class Op, int NTP, int NC>
+__device__ __forceinline__ void coarse_body(const Op& op_top,
+                                            const CoarseArgs<typename Op::real>& A,
+                                            const CycleState* stop) {
     using T = typename Op::real;
     constexpr int NF = Op::NF;
     __shared__ T Su[NF][CP_TOTAL];

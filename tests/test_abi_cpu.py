@@ -90,3 +90,36 @@ def test_rectangular_and_small_grids_accepted():
     p, o = good()
     for m, n in [(2, 2), (4, 8), (64, 128), (2048, 2048), (128, 64)]:
         assert lib.mpfc_validate(m, n, ctypes.byref(p), ctypes.byref(o)) == 0, (m, n)
+
+
+def _descs(shapes, schemes=None):
+    d = (L.mpfc_sim_desc * len(shapes))()
+    for k, (m, n) in enumerate(shapes):
+        d[k].m, d[k].n = m, n
+        d[k].p = L.mpfc_params(0.025, 0.9, 1.0, math.pi / 4, 0.05,
+                               schemes[k] if schemes else 2)
+    return d
+
+
+@pytest.mark.parametrize("shapes,schemes,nsim", [
+    ([(64, 64), (128, 128)], [1, 2], 2),      # mixed schemes
+    ([(64, 64), (32, 32)], None, 2),          # a grid of 1024 cells
+    ([(64, 64), (48, 64)], None, 2),          # not a power of two
+    ([(64, 64)], None, 0),                    # empty batch
+    ([(64, 64)], None, L.MPFC_BATCH_MAX + 1),  # too many
+])
+def test_batch_create_rejects_before_any_hip_call(shapes, schemes, nsim):
+    lib = L.load()
+    o = L.default_opts()
+    d = _descs(shapes, schemes)
+    b = ctypes.c_void_p()
+    assert lib.mpfc_batch_create(ctypes.byref(b), nsim, d, ctypes.byref(o), None) == L.MPFC_EINVAL
+    assert not b.value
+    assert lib.mpfc_last_error()
+
+
+def test_batch_null_handles():
+    lib = L.load()
+    assert lib.mpfc_batch_size(None) == 0
+    lib.mpfc_batch_destroy(None)
+    assert lib.mpfc_batch_step(None, None, None, None, None, None) == L.MPFC_EINVAL

@@ -1,0 +1,156 @@
+"""Batched simulations (mpfc_batch_*) against single-grid contexts and the
+oracle.
+
+A simulation in a batch runs the same per-cell arithmetic as a single-grid
+context with the same options, so its states match that context's to
+rounding (1e-12 relative), its cycle counts match exactly, and the small
+members are also checked against the oracle at the parity bar (1e-10 FP64,
+1e-9 mixed precision).  Buffers rotate between steps, so the device table of
+the caller's pointers is exercised on every graph replay.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1208_2643_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1208_2643_amd import api  # noqa: E402
+from paper_1208_2643_amd import _lib as L  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# uneven members: sizes, aspect ratios, parameters
+MEMBERS = [
+    (64, 64, dict(eps=0.025, beta=0.9, M=1.0, h=math.pi / 4, dt=0.05), 0.07, 11),
+    (128, 64, dict(eps=0.1, beta=1.5, M=1.0, h=math.pi / 4, dt=0.05), 0.15, 12),
+    (64, 128, dict(eps=0.25, beta=0.6, M=0.8, h=math.pi / 4, dt=0.04), 0.25, 13),
+    (256, 256, dict(eps=0.05, beta=1.2, M=1.0, h=0.7, dt=0.05), 0.1, 14),
+]
+
+
+def members(scheme, which=None):
+    out = []
+    for k, (m, n, d, mean, seed) in enumerate(MEMBERS):
+        if which is not None and k not in which:
+            continue
+        p = api.Params(scheme=scheme, **d)
+        phi0 = I.noise(m, n, mean=mean, amp=0.05, seed=seed)
+        out.append((m, n, p, phi0))
+    return out
+
+
+def run_single(m, n, p, phi0, steps, **opts):
+    st = api.Stepper(m, n, p, energy=0, **opts)
+    phi, prev, psi, infos = api.run(st, dev(phi0), steps)
+    st.close()
+    return host(phi), host(psi), [i.n_cycles for i in infos]
+
+
+@pytest.mark.parametrize("scheme,precision,lin", [(2, L.MPFC_FP64, L.MPFC_NEWTON),
+                                                  (1, L.MPFC_FP64, L.MPFC_NEWTON),
+                                                  (2, L.MPFC_MIXED, L.MPFC_NEWTON),
+                                                  (1, L.MPFC_MIXED, L.MPFC_PICARD)])
+def test_batch_matches_single_contexts(scheme, precision, lin):
+    sims = members(scheme)
+    steps = 3
+    b = api.Batch([(m, n, p) for m, n, p, _ in sims], precision=precision, linearization=lin)
+    phi_b, _, psi_b, infos = api.run_batch(b, [dev(x) for *_, x in sims], steps)
+    b.close()
+    for k, (m, n, p, phi0) in enumerate(sims):
+        phi_s, psi_s, cyc_s = run_single(m, n, p, phi0, steps, precision=precision,
+                                         linearization=lin)
+        assert rel_l2(host(phi_b[k]), phi_s) <= 1e-12, k
+        assert rel_l2(host(psi_b[k]), psi_s) <= 1e-10, k
+        assert [infos[t][k].n_cycles for t in range(steps)] == cyc_s, k
+        for t in range(steps):
+            assert infos[t][k].status == 0
+            assert infos[t][k].residual <= 1e-10
+
+
+@pytest.mark.parametrize("precision,bar", [(L.MPFC_FP64, 1e-10), (L.MPFC_MIXED, 1e-9)])
+def test_batch_matches_oracle(precision, bar):
+    """The two small members against the FP64 oracle solved to 1e-12."""
+    sims = members(2, which=(0, 1))
+    steps = 2
+    b = api.Batch([(m, n, p) for m, n, p, _ in sims], precision=precision)
+    phi_b, _, psi_b, infos = api.run_batch(b, [dev(x) for *_, x in sims], steps)
+    b.close()
+    for k, (m, n, p, phi0) in enumerate(sims):
+        po = O.Params(eps=p.eps, beta=p.beta, M=p.M, h=p.h, dt=p.dt, scheme=p.scheme)
+        phi_o, _, psi_o, _ = O.run(po, phi0, steps, tol=1e-12, max_cycles=300)
+        assert rel_l2(host(phi_b[k]), phi_o) <= bar, k
+        assert rel_l2(host(psi_b[k]), psi_o) <= 1e3 * bar, k
+
+
+def test_batch_members_stop_independently():
+    """A member whose step is already solved by its initial guess (a constant
+    state) stops after zero cycles while the others go on; it and they still
+    match their single-context results."""
+    sims = members(2, which=(1, 3))
+    m, n, p, _ = sims[0]
+    sims[0] = (m, n, p, np.full((n, m), 0.2))
+    b = api.Batch([(m, n, p) for m, n, p, _ in sims])
+    phi_b, _, _, infos = api.run_batch(b, [dev(x) for *_, x in sims], 2)
+    b.close()
+    assert infos[0][0].n_cycles == 0 and infos[0][1].n_cycles > 0
+    for k, (m, n, p, phi0) in enumerate(sims):
+        phi_s, _, cyc = run_single(m, n, p, phi0, 2)
+        assert rel_l2(host(phi_b[k]), phi_s) <= 1e-12
+        assert [infos[t][k].n_cycles for t in range(2)] == cyc
+
+
+def test_batch_history_and_rejections():
+    sims = members(2, which=(0, 1))
+    b = api.Batch([(m, n, p) for m, n, p, _ in sims])
+    phi = [dev(x) for *_, x in sims]
+    psi = [torch.zeros_like(x) for x in phi]
+    out = [torch.empty_like(x) for x in phi]
+    infos = b.step(phi, None, psi, out)
+    for inf in infos:
+        h = inf.history
+        assert len(h) == inf.n_cycles + 1 and h[-1] == inf.residual and h[-1] <= 1e-10
+        assert h[-1] < 1e-3 * h[0]
+    with pytest.raises(L.MpfcError):
+        b.step(phi, None, psi, phi)  # phi_np1 aliases phi_n
+    b.close()
+
+
+def test_full_batch_workload_sampled():
+    """The 64-member workload (sizes 128^2 ... 1024^2, mixed precision), one
+    step; the largest and the smallest member against single contexts."""
+    specs = I.batch(64)
+    sims = [(sp.N, sp.N, api.Params(eps=sp.eps, beta=sp.beta, M=1.0, h=math.pi / 4, dt=0.05,
+                                    scheme=2)) for sp in specs]
+    b = api.Batch(sims, precision=L.MPFC_MIXED)
+    phi0 = [dev(sp.phi0) for sp in specs]
+    phi_b, _, _, infos = api.run_batch(b, phi0, 1)
+    b.close()
+    assert all(i.status == 0 and i.residual <= 1e-10 for i in infos[0])
+    sizes = [sp.N for sp in specs]
+    for k in (int(np.argmax(sizes)), int(np.argmin(sizes))):
+        m, n, p = sims[k]
+        phi_s, _, cyc = run_single(m, n, p, specs[k].phi0, 1, precision=L.MPFC_MIXED)
+        assert rel_l2(host(phi_b[k]), phi_s) <= 1e-12
+        assert infos[0][k].n_cycles == cyc[0]
