@@ -48,7 +48,8 @@ enum {
 };
 
 enum { MPFC_FP64 = 0, MPFC_MIXED = 1 };                           /* precision */
-enum { MPFC_GUESS_PREV = 0, MPFC_GUESS_EXTRAP = 1 };              /* initial guess */
+enum { MPFC_GUESS_PREV = 0, MPFC_GUESS_EXTRAP = 1,                 /* initial guess */
+       MPFC_GUESS_CNN = 2 /* learned, with the extrapolated guess as fallback (mpfc_cnn_load) */ };
 enum { MPFC_NEWTON = 0, MPFC_PICARD = 1 };                        /* linearisation */
 
 /* Model and discretisation (Sec. 2, Sec. 3): alpha = 1 - eps; dt is the time
@@ -226,6 +227,65 @@ int mpfc_batch_step(mpfc_batch *b, const double *const *d_phi_n,
 int mpfc_batch_size(const mpfc_batch *b);
 
 void mpfc_batch_destroy(mpfc_batch *b);
+
+/* ---- learned initial guess -------------------------------------------------------
+ * Each step has exactly one solution (Sec. 3, unique solvability), so its
+ * initial guess is free; a better one only saves V-cycles.  The learned guess
+ * is a periodic convolutional network (four 3x3 layers, 2 -> 32 -> 32 -> 32 -> 1
+ * channels, tanh-form GELU after the first three; BF16 weights and
+ * activations on the matrix cores, FP32 accumulation):
+ *   inputs  x0 = in_scale phi^n, x1 = (phi^n - phi^{n-1}) / sigma1, sigma1 the
+ *           rms of phi^n - phi^{n-1} (x1 = 0 when sigma1 = 0);
+ *   output  delta; guess = 2 phi^n - phi^{n-1} + c, c = out_scale sigma1 delta
+ *           minus its mean (the guess keeps the mass of the extrapolation).
+ * In a step with guess mode MPFC_GUESS_CNN both the learned and the
+ * extrapolated guess are completed (mu, kappa as for any guess) and the one
+ * with the smaller FP64 residual starts the V-cycles (fallback).
+ *
+ * Blob (host float32, mpfc_cnn_blob_size() values): header [1, 2, 32, 4,
+ * in_scale, out_scale, 0, 0], then per layer W[ky][kx][ci][co] (ky, kx = 0..2
+ * for offsets -1..1 in y and x) and b[co]: W1 (3,3,2,32), b1 (32),
+ * W2 (3,3,32,32), b2, W3 (3,3,32,32), b3, W4 (3,3,32,1), b4 (1).  Grids must be
+ * powers of two of at least 16 x 16. */
+int mpfc_cnn_blob_size(void);
+
+/* Copy a network into the context (device memory of its own, freed with the
+ * context); also resets the counters below.  EINVAL on a malformed blob. */
+int mpfc_cnn_load(mpfc_ctx *ctx, const float *h_blob, size_t count);
+
+/* Steps that started from the learned guess, and fallbacks to extrapolation. */
+int mpfc_cnn_counts(mpfc_ctx *ctx, long long *used, long long *fallbacks);
+
+typedef struct {
+    float lr, beta1, beta2, eps;   /* Adam (Kingma and Ba, 2015) */
+} mpfc_cnn_hparams;
+
+typedef struct mpfc_cnn_trainer mpfc_cnn_trainer;
+
+/* Trainer for batches of `batch` samples of an m x n grid, starting from
+ * h_blob (FP32 master weights on the device, BF16 copies for the kernels).
+ * Loss: mean over every pixel of the batch of (delta - t)^2 with
+ * t = (phi^{n+1} - 2 phi^n + phi^{n-1}) / (out_scale sigma1). */
+int mpfc_cnn_trainer_create(mpfc_cnn_trainer **out, int m, int n, int batch,
+                            const float *h_blob, size_t count, const mpfc_cnn_hparams *hp,
+                            void *stream);
+
+/* Forward and backward pass over one batch (host arrays of `batch` device
+ * pointers to m x n FP64 fields); `update` != 0 then takes one Adam step.
+ * h_loss: the loss before the update; h_grad: NULL or mpfc_cnn_blob_size() - 8
+ * floats receiving the gradient in blob order. */
+int mpfc_cnn_train_step(mpfc_cnn_trainer *t, const double *const *d_phi_nm1,
+                        const double *const *d_phi_n, const double *const *d_phi_np1,
+                        int update, double *h_loss, float *h_grad);
+
+/* Mean-corrected learned guesses of a batch with the current weights. */
+int mpfc_cnn_predict(mpfc_cnn_trainer *t, const double *const *d_phi_nm1,
+                     const double *const *d_phi_n, double *const *d_guess);
+
+/* Current weights as a blob (count = mpfc_cnn_blob_size()). */
+int mpfc_cnn_trainer_blob(mpfc_cnn_trainer *t, float *h_blob, size_t count);
+
+void mpfc_cnn_trainer_destroy(mpfc_cnn_trainer *t);
 
 #ifdef __cplusplus
 }

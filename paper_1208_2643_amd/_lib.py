@@ -25,7 +25,7 @@ MPFC_ENOMEM = -5
 MPFC_EHIP = -6
 
 MPFC_FP64, MPFC_MIXED = 0, 1
-MPFC_GUESS_PREV, MPFC_GUESS_EXTRAP = 0, 1
+MPFC_GUESS_PREV, MPFC_GUESS_EXTRAP, MPFC_GUESS_CNN = 0, 1, 2
 MPFC_NEWTON, MPFC_PICARD = 0, 1
 
 
@@ -55,6 +55,11 @@ class mpfc_sim_desc(ctypes.Structure):
 
 
 MPFC_BATCH_MAX = 4096
+
+
+class mpfc_cnn_hparams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
 
 
 class MpfcError(RuntimeError):
@@ -96,6 +101,18 @@ SIGNATURES = {
                              ctypes.POINTER(_vp), ctypes.POINTER(mpfc_info)]),
     "mpfc_batch_size": (_i, [_vp]),
     "mpfc_batch_destroy": (None, [_vp]),
+    "mpfc_cnn_blob_size": (_i, []),
+    "mpfc_cnn_load": (_i, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
+    "mpfc_cnn_counts": (_i, [_vp, ctypes.POINTER(ctypes.c_longlong),
+                             ctypes.POINTER(ctypes.c_longlong)]),
+    "mpfc_cnn_trainer_create": (_i, [ctypes.POINTER(_vp), _i, _i, _i, ctypes.POINTER(ctypes.c_float),
+                                     ctypes.c_size_t, ctypes.POINTER(mpfc_cnn_hparams), _vp]),
+    "mpfc_cnn_train_step": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                 _i, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_float)]),
+    "mpfc_cnn_predict": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "mpfc_cnn_trainer_blob": (_i, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
+    "mpfc_cnn_trainer_destroy": (None, [_vp]),
 }
 
 

@@ -122,6 +122,18 @@ class Stepper:
                                         ctypes.byref(cells), 1 if reset else 0))
         return ms.value, n.value, cells.value
 
+    def load_cnn(self, blob):
+        """Load a learned-guess network (float32 blob); used when guess=MPFC_GUESS_CNN."""
+        b = np.ascontiguousarray(blob, dtype=np.float32)
+        L.check(self.lib.mpfc_cnn_load(self.ctx, b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                       b.size))
+
+    def cnn_counts(self):
+        """(steps started from the learned guess, fallbacks to extrapolation)."""
+        u, f = ctypes.c_longlong(), ctypes.c_longlong()
+        L.check(self.lib.mpfc_cnn_counts(self.ctx, ctypes.byref(u), ctypes.byref(f)))
+        return u.value, f.value
+
     def energies(self, phi, phi_prev, psi):
         out = (ctypes.c_double * 4)()
         L.check(self.lib.mpfc_energies(self.ctx, _ptr(phi), _ptr(phi_prev), _ptr(psi), out))
@@ -197,6 +209,65 @@ class Batch:
             out.append(StepInfo(I.status, I.n_cycles, I.residual, hist, 0.0, 0.0, 0.0, 0.0,
                                 I.outer_iters))
         return out
+
+
+def _ptrs(ts):
+    a = (ctypes.c_void_p * len(ts))()
+    for k, t in enumerate(ts):
+        a[k] = _ptr(t).value
+    return a
+
+
+class CnnTrainer:
+    """GPU trainer of the learned-guess network (mpfc_cnn_*): batches of
+    `batch` samples (phi^{n-1}, phi^n, phi^{n+1}) of an (n, m) grid."""
+
+    def __init__(self, m: int, n: int, batch: int, blob, lr=1e-3, beta1=0.9, beta2=0.999,
+                 eps=1e-8, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libmpfc needs a HIP GPU; none is visible")
+        self.lib = L.load()
+        self.m, self.n, self.batch = m, n, batch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        b = np.ascontiguousarray(blob, dtype=np.float32)
+        hp = L.mpfc_cnn_hparams(lr, beta1, beta2, eps)
+        t = ctypes.c_void_p()
+        L.check(self.lib.mpfc_cnn_trainer_create(
+            ctypes.byref(t), m, n, batch, b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), b.size,
+            ctypes.byref(hp), _stream(self.stream)))
+        self.t = t
+        self.nparams = self.lib.mpfc_cnn_blob_size() - 8
+
+    def close(self):
+        if getattr(self, "t", None):
+            self.lib.mpfc_cnn_trainer_destroy(self.t)
+            self.t = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, pm1, p0, pp1, update=True, grad=False):
+        """Loss before the step (and the gradient, float32, blob order)."""
+        loss = ctypes.c_double()
+        g = np.zeros(self.nparams, dtype=np.float32) if grad else None
+        L.check(self.lib.mpfc_cnn_train_step(
+            self.t, _ptrs(pm1), _ptrs(p0), _ptrs(pp1), 1 if update else 0, ctypes.byref(loss),
+            g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if grad else None))
+        return (loss.value, g) if grad else loss.value
+
+    def predict(self, pm1, p0):
+        out = [torch.empty_like(t) for t in p0]
+        L.check(self.lib.mpfc_cnn_predict(self.t, _ptrs(pm1), _ptrs(p0), _ptrs(out)))
+        return out
+
+    def blob(self):
+        b = np.zeros(self.nparams + 8, dtype=np.float32)
+        L.check(self.lib.mpfc_cnn_trainer_blob(self.t, b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                               b.size))
+        return b
 
 
 def run_batch(batch: Batch, phi0s, steps: int):

@@ -494,6 +494,8 @@ int mpfc_batch_create(mpfc_batch** out, int nsim, const mpfc_sim_desc* sims, con
     *out = nullptr;
     if (nsim < 1 || nsim > MPFC_BATCH_MAX) return fail(MPFC_EINVAL, "nsim out of range");
     if (!sims || !o) return fail(MPFC_EINVAL, "sims and opts are required");
+    if (o->guess == MPFC_GUESS_CNN)
+        return fail(MPFC_EINVAL, "the learned guess is not available in a batch");
     for (int s = 0; s < nsim; ++s) {
         int rc = validate(sims[s].m, sims[s].n, &sims[s].p, o);
         if (rc) {

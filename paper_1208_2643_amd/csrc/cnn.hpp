@@ -1,0 +1,626 @@
+// Learned initial guess: a small periodic convolutional network, inference
+// and training kernels for gfx950 (BF16 operands on the matrix cores, FP32
+// accumulation).
+//
+// The step's initial guess is free (each step has exactly one solution, Sec. 3
+// unique-solvability theorems), so a predictor may supply it:
+//   x0 = in_scale * phi^n, x1 = (phi^n - phi^{n-1}) / sigma1 (sigma1 = rms of
+//   the difference; x1 = 0 when it vanishes), four 3x3 periodic convolutions
+//   2 -> 32 -> 32 -> 32 -> 1 with tanh-form GELU after the first three, and the
+//   guess 2 phi^n - phi^{n-1} + c with c = out_scale * sigma1 * delta minus its
+//   mean (the guess keeps the mass of the extrapolation).
+//
+// Layouts.  Activations are BF16 (stored as uint16 bit patterns), NHWC with
+// 32 channels: act[(s * NP + p) * 32 + c], p = y * m + x.  Parameters are an
+// FP32 vector in blob order (W1 [3][3][2][32], b1, W2 [3][3][32][32], b2, W3,
+// b3, W4 [3][3][32], b4).  A convolution is a GEMM per tap with the output
+// channels as M (two 16-row tiles), 16 pixels of a tile row as N and the input
+// channels as K; its weight operand is kept in registers as per-lane fragments
+// prepared from the FP32 master weights (k_cnn_prepare).  Layer 1 gathers its
+// 18 taps x channels into one K = 32 operand (im2col in LDS).
+//
+// MFMA v_mfma_f32_16x16x16bf16_1k operand layout (lane l, g = l / 16,
+// c = l % 16): A[m = c][k = 4g + i], B[k = 4g + i][n = c], D[m = 4g + i][n = c].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace mpfc {
+
+typedef short cnn_v4s __attribute__((ext_vector_type(4)));
+typedef float cnn_v4f __attribute__((ext_vector_type(4)));
+
+constexpr int CNN_CH = 32;
+constexpr int CNN_TILE = 16;
+constexpr int CNN_HALO = 18;
+constexpr int CNN_PX = 36;           // LDS stride of one pixel (32 channels + 4 pad)
+constexpr int CNN_NFRAG1 = 4;        // layer 1: K = 32 (2 chunks) x 2 M tiles
+constexpr int CNN_NFRAG = 36;        // 9 taps x 2 K chunks x 2 M tiles
+// parameter offsets in the FP32 vector (blob order, no header)
+constexpr int CNN_W1 = 0, CNN_B1 = 576, CNN_W2 = 608, CNN_B2 = 9824, CNN_W3 = 9856,
+              CNN_B3 = 19072, CNN_W4 = 19104, CNN_B4 = 19392, CNN_NPARAM = 19393;
+constexpr int CNN_SEG1 = 18 * 32 + 32;   // layer-1 gradient segment (W1, b1)
+constexpr int CNN_SEG = 9 * 32 * 32 + 32;  // layers 2, 3 (W, b)
+constexpr int CNN_SEG4 = 9 * 32 + 1;     // layer 4 (W4, b4)
+
+// Fields of one sample: the guess reads phi^{n-1}, phi^n; training also phi^{n+1};
+// `out` receives the guess (inference).
+struct CnnSample {
+    const double* pm1;
+    const double* p0;
+    const double* pp1;
+    double* out;
+};
+
+// Round to nearest even; NaN stays NaN.
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float gelu_f(float x) {
+    const float u = 0.7978845608028654f * (x + 0.044715f * x * x * x);
+    return 0.5f * x * (1.0f + tanhf(u));
+}
+__device__ __forceinline__ float gelu_grad_f(float x) {
+    const float u = 0.7978845608028654f * (x + 0.044715f * x * x * x);
+    const float t = tanhf(u);
+    return 0.5f * (1.0f + t) +
+           0.5f * x * (1.0f - t * t) * 0.7978845608028654f * (1.0f + 0.134145f * x * x);
+}
+
+// Halo tile (18 x 18 pixels, 32 channels) of an NHWC activation into LDS
+// (pixel stride CNN_PX), periodic wrap.  Uses every thread of the block.
+__device__ __forceinline__ void cnn_load_halo(const uint16_t* __restrict__ act, size_t base,
+                                              int x0, int y0, int m, int n, uint16_t* lds) {
+    for (int c = threadIdx.x; c < CNN_HALO * CNN_HALO * 4; c += blockDim.x) {
+        const int pi = c >> 2, part = c & 3;
+        const int ty = pi / CNN_HALO, tx = pi - ty * CNN_HALO;
+        const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (m - 1);
+        const uint4 v = *(const uint4*)(act + (base + (size_t)gy * m + gx) * CNN_CH + part * 8);
+        uint2* d = (uint2*)(lds + pi * CNN_PX + part * 8);
+        d[0] = make_uint2(v.x, v.y);
+        d[1] = make_uint2(v.z, v.w);
+    }
+}
+
+// Layer-1 inputs of an 18 x 18 halo tile as BF16 bits: xs[0][.] = in_scale *
+// phi^n, xs[1][.] = (phi^n - phi^{n-1}) * inv_sigma1.
+__device__ __forceinline__ void cnn_load_inputs(const CnnSample& S, double in_scale,
+                                                double inv_sigma1, int x0, int y0, int m, int n,
+                                                uint16_t (*xs)[CNN_HALO * CNN_HALO]) {
+    for (int t = threadIdx.x; t < CNN_HALO * CNN_HALO; t += blockDim.x) {
+        const int ty = t / CNN_HALO, tx = t - ty * CNN_HALO;
+        const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (m - 1);
+        const size_t q = (size_t)gy * m + gx;
+        const double v0 = S.p0[q], v1 = S.pm1[q];
+        xs[0][t] = bf16_bits((float)(in_scale * v0));
+        xs[1][t] = bf16_bits((float)((v0 - v1) * inv_sigma1));
+    }
+}
+
+// im2col value k (k = tap * 2 + channel, 0 for k >= 18) of tile pixel (ty, tx).
+__device__ __forceinline__ uint16_t cnn_im2col(const uint16_t (*xs)[CNN_HALO * CNN_HALO], int k,
+                                               int ty, int tx) {
+    if (k >= 18) return 0;
+    const int tap = k >> 1, ky = tap / 3, kx = tap - 3 * ky;
+    return xs[k & 1][(ty + ky) * CNN_HALO + tx + kx];
+}
+
+struct CnnConvArgs {
+    int m, n;
+    const uint16_t* in;        // NHWC input (layers 2, 3 forward; backward data)
+    const CnnSample* smp;      // layer 1: fields of every sample
+    const double* sc;          // per sample: inv_sigma1, sigma_out, inv_sigma_out, 0
+    double in_scale;
+    const uint16_t* wfrag;     // weight fragments
+    const float* bias;         // forward
+    uint16_t* out;             // NHWC output
+    uint16_t* zout;            // forward: pre-activations (nullable)
+    const uint16_t* zprev;     // backward data: pre-activations of the layer below
+};
+
+enum { CNN_FWD = 0, CNN_BWD = 1 };
+
+// One 3x3 convolution layer with 32 output channels on a 16 x 16 tile of one
+// sample.  FWD: out = gelu(conv(in) + b) (and z = conv(in) + b when zout is set).
+// BWD (transposed, flipped weights): out = conv(in) * gelu'(zprev).
+// Grid (m / 16, n / 16, samples), 256 threads; wave w computes tile rows
+// 4w ... 4w + 3.
+template <bool IM2COL, int MODE>
+__global__ void __launch_bounds__(256) k_cnn_conv(CnnConvArgs A) {
+    constexpr int NFR = IM2COL ? CNN_NFRAG1 : CNN_NFRAG;
+    constexpr int LDS_N = IM2COL ? CNN_TILE * CNN_TILE * CNN_PX : CNN_HALO * CNN_HALO * CNN_PX;
+    __shared__ __align__(16) uint16_t lds[LDS_N];
+    __shared__ uint16_t xs[IM2COL ? 2 : 1][IM2COL ? CNN_HALO * CNN_HALO : 1];
+    const int m = A.m, n = A.n;
+    const size_t NP = (size_t)m * n;
+    const int s = blockIdx.z;
+    const int x0 = blockIdx.x * CNN_TILE, y0 = blockIdx.y * CNN_TILE;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c16 = lane & 15;
+    cnn_v4s af[NFR];
+#pragma unroll
+    for (int f = 0; f < NFR; ++f) af[f] = *(const cnn_v4s*)(A.wfrag + ((size_t)f * 64 + lane) * 4);
+    if constexpr (IM2COL) {
+        const CnnSample S = A.smp[s];
+        cnn_load_inputs(S, A.in_scale, A.sc[4 * s + 0], x0, y0, m, n, xs);
+        __syncthreads();
+        {
+            const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
+            for (int k = 0; k < 32; ++k) lds[t * CNN_PX + k] = cnn_im2col(xs, k, ty, tx);
+        }
+    } else {
+        cnn_load_halo(A.in, (size_t)s * NP, x0, y0, m, n, lds);
+    }
+    __syncthreads();
+    cnn_v4f acc[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) acc[r][mt] = cnn_v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = wave * 4 + r;
+        if constexpr (IM2COL) {
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc) {
+                const cnn_v4s b = *(const cnn_v4s*)(lds + (row * CNN_TILE + c16) * CNN_PX + kc * 16 + 4 * g);
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt)
+                    acc[r][mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[kc * 2 + mt], b,
+                                                                          acc[r][mt], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+#pragma unroll
+                for (int kc = 0; kc < 2; ++kc) {
+                    const cnn_v4s b = *(const cnn_v4s*)(lds + ((row + ky) * CNN_HALO + c16 + kx) * CNN_PX +
+                                                        kc * 16 + 4 * g);
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt)
+                        acc[r][mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                            af[(tap * 2 + kc) * 2 + mt], b, acc[r][mt], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // epilogue: lane holds channels mt * 16 + 4g .. + 3 of pixel (row, c16)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = wave * 4 + r;
+        const size_t q = (size_t)s * NP + (size_t)(y0 + row) * m + x0 + c16;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const int co = mt * 16 + 4 * g;
+            uint16_t o[4];
+            if constexpr (MODE == CNN_FWD) {
+                uint16_t zb[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float z = acc[r][mt][i] + A.bias[co + i];
+                    zb[i] = bf16_bits(z);
+                    o[i] = bf16_bits(gelu_f(z));
+                }
+                if (A.zout)
+                    *(uint2*)(A.zout + q * CNN_CH + co) =
+                        make_uint2((uint32_t)zb[0] | ((uint32_t)zb[1] << 16),
+                                   (uint32_t)zb[2] | ((uint32_t)zb[3] << 16));
+            } else {
+                const uint2 zp = *(const uint2*)(A.zprev + q * CNN_CH + co);
+                const uint16_t zv[4] = {(uint16_t)(zp.x & 0xffff), (uint16_t)(zp.x >> 16),
+                                        (uint16_t)(zp.y & 0xffff), (uint16_t)(zp.y >> 16)};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = bf16_bits(acc[r][mt][i] * gelu_grad_f(bf16_val(zv[i])));
+            }
+            *(uint2*)(A.out + q * CNN_CH + co) = make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16),
+                                                           (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+        }
+    }
+}
+
+struct CnnOutArgs {
+    int m, n;
+    const uint16_t* in;        // a3 (NHWC)
+    const CnnSample* smp;
+    const double* sc;
+    const float* w4;           // [tap][ci], BF16-rounded values
+    const float* b4;
+    float* gd;                 // training: d loss / d delta
+    double* part;              // per block and sample: sum of the correction / of err^2
+    double gscale;             // training: 2 / (pixels of the batch)
+};
+
+// Output layer (32 -> 1) on a 16 x 16 tile, one thread per pixel.
+// Inference: guess = 2 phi^n - phi^{n-1} + sigma_out * delta into smp.out and
+// the block's sum of the correction.  Training: err = delta - target,
+// gd = gscale * err and the block's sum of err^2.  part[blk * samples + s].
+template <bool TRAIN>
+__global__ void __launch_bounds__(256) k_cnn_out(CnnOutArgs A) {
+    __shared__ __align__(16) uint16_t lds[CNN_HALO * CNN_HALO * CNN_PX];
+    __shared__ float w4s[9 * CNN_CH];
+    __shared__ double red[4];
+    const int m = A.m, n = A.n;
+    const size_t NP = (size_t)m * n;
+    const int s = blockIdx.z;
+    const int x0 = blockIdx.x * CNN_TILE, y0 = blockIdx.y * CNN_TILE;
+    for (int k = threadIdx.x; k < 9 * CNN_CH; k += 256) w4s[k] = A.w4[k];
+    cnn_load_halo(A.in, (size_t)s * NP, x0, y0, m, n, lds);
+    __syncthreads();
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    float d = A.b4[0];
+    for (int tap = 0; tap < 9; ++tap) {
+        const int ky = tap / 3, kx = tap - 3 * ky;
+        const uint16_t* a = lds + ((ty + ky) * CNN_HALO + tx + kx) * CNN_PX;
+#pragma unroll
+        for (int c = 0; c < CNN_CH; c += 4) {
+            const uint2 v = *(const uint2*)(a + c);
+            d += w4s[tap * CNN_CH + c] * bf16_val((uint16_t)(v.x & 0xffff)) +
+                 w4s[tap * CNN_CH + c + 1] * bf16_val((uint16_t)(v.x >> 16)) +
+                 w4s[tap * CNN_CH + c + 2] * bf16_val((uint16_t)(v.y & 0xffff)) +
+                 w4s[tap * CNN_CH + c + 3] * bf16_val((uint16_t)(v.y >> 16));
+        }
+    }
+    const CnnSample S = A.smp[s];
+    const size_t q = (size_t)(y0 + ty) * m + x0 + tx;
+    double acc;
+    if constexpr (!TRAIN) {
+        const double corr = A.sc[4 * s + 1] * (double)d;
+        S.out[q] = 2.0 * S.p0[q] - S.pm1[q] + corr;
+        acc = corr;
+    } else {
+        const double t = (S.pp1[q] - 2.0 * S.p0[q] + S.pm1[q]) * A.sc[4 * s + 2];
+        const double err = (double)d - t;
+        A.gd[(size_t)s * NP + q] = (float)(A.gscale * err);
+        acc = err * err;
+    }
+    const double bs = block_sum<256>(acc, red);
+    if (threadIdx.x == 0)
+        A.part[(size_t)(blockIdx.y * gridDim.x + blockIdx.x) * gridDim.z + s] = bs;
+}
+
+// Per-sample scale factors from the sums of (phi^n - phi^{n-1})^2.
+__global__ void k_cnn_scales(const double* __restrict__ sums, int samples, double npix,
+                             double out_scale, double* sc) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= samples) return;
+    const double sig = sqrt(sums[s] / npix);
+    const double so = out_scale * sig;
+    sc[4 * s + 0] = sig > 0.0 ? 1.0 / sig : 0.0;
+    sc[4 * s + 1] = so;
+    sc[4 * s + 2] = so > 0.0 ? 1.0 / so : 0.0;
+    sc[4 * s + 3] = 0.0;
+}
+
+// part[blk * samples + s] = block's share of sum (phi^n - phi^{n-1})^2 of sample s.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_cnn_sigma(const CnnSample* __restrict__ smp, size_t npix,
+                                                  double* part) {
+    __shared__ double red[NT / 64];
+    const int s = blockIdx.y;
+    const CnnSample S = smp[s];
+    double acc = 0.0;
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < npix; q += (size_t)gridDim.x * NT) {
+        const double d = S.p0[q] - S.pm1[q];
+        acc += d * d;
+    }
+    const double bs = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * gridDim.y + s] = bs;
+}
+
+// Mean correction of the guesses: out -= sums[s] / npix.
+__global__ void __launch_bounds__(256) k_cnn_shift(const CnnSample* __restrict__ smp, size_t npix,
+                                                   const double* __restrict__ sums) {
+    const int s = blockIdx.y;
+    const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= npix) return;
+    smp[s].out[q] -= sums[s] / (double)npix;
+}
+
+struct CnnOutBwdArgs {
+    int m, n;
+    const float* gd;           // d loss / d delta
+    const float* w4;
+    const uint16_t* z3;        // pre-activations of layer 3
+    uint16_t* out;             // d loss / d z3
+};
+
+// dz3[p][c] = gelu'(z3[p][c]) * sum_tap w4[tap][c] gd[p - offset(tap)].
+__global__ void __launch_bounds__(256) k_cnn_out_bwd(CnnOutBwdArgs A) {
+    __shared__ float gs[CNN_HALO * CNN_HALO];
+    __shared__ float w4s[9 * CNN_CH];
+    const int m = A.m, n = A.n;
+    const size_t NP = (size_t)m * n;
+    const int s = blockIdx.z;
+    const int x0 = blockIdx.x * CNN_TILE, y0 = blockIdx.y * CNN_TILE;
+    for (int k = threadIdx.x; k < 9 * CNN_CH; k += 256) w4s[k] = A.w4[k];
+    for (int t = threadIdx.x; t < CNN_HALO * CNN_HALO; t += 256) {
+        const int ty = t / CNN_HALO, tx = t - ty * CNN_HALO;
+        const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (m - 1);
+        gs[t] = A.gd[(size_t)s * NP + (size_t)gy * m + gx];
+    }
+    __syncthreads();
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    float gn[9];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int ky = tap / 3, kx = tap - 3 * ky;
+        gn[tap] = gs[(ty + 2 - ky) * CNN_HALO + tx + 2 - kx];
+    }
+    const size_t q = (size_t)s * NP + (size_t)(y0 + ty) * m + x0 + tx;
+    for (int c = 0; c < CNN_CH; c += 4) {
+        const uint2 zp = *(const uint2*)(A.z3 + q * CNN_CH + c);
+        const uint16_t zv[4] = {(uint16_t)(zp.x & 0xffff), (uint16_t)(zp.x >> 16),
+                                (uint16_t)(zp.y & 0xffff), (uint16_t)(zp.y >> 16)};
+        uint16_t o[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float a = 0.f;
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) a += w4s[tap * CNN_CH + c + i] * gn[tap];
+            o[i] = bf16_bits(a * gelu_grad_f(bf16_val(zv[i])));
+        }
+        *(uint2*)(A.out + q * CNN_CH + c) = make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16),
+                                                      (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+    }
+}
+
+struct CnnWgradArgs {
+    int m, n, samples;
+    const uint16_t* in;        // a_{L-1} (layers 2, 3)
+    const CnnSample* smp;      // layer 1
+    const double* sc;
+    double in_scale;
+    const uint16_t* dz;        // d loss / d z_L
+    float* part;               // [block][segment]
+};
+
+// Weight and bias gradients of a 32-output convolution layer:
+// dW[tap][ci][co] = sum_p a[p + offset(tap)][ci] dz[p][co], db[co] = sum_p dz[p][co],
+// as MFMA GEMMs over the pixels (K) of 16 x 16 tiles; every block loops over
+// tiles and writes its partial sums (reduced in a fixed order by k_cnn_reduce).
+// Both operands are staged in LDS with the pixel index fastest.
+template <bool IM2COL>
+__global__ void __launch_bounds__(256) k_cnn_wgrad(CnnWgradArgs A) {
+    constexpr int AR = IM2COL ? CNN_TILE : CNN_HALO;   // rows of the A tile
+    constexpr int RS = 20;                             // LDS row stride (pixels)
+    constexpr int NCB = IM2COL ? 1 : 9;                // (tap, mt, nt) combos per wave
+    constexpr int SEG = IM2COL ? CNN_SEG1 : CNN_SEG;
+    __shared__ __align__(16) uint16_t la[32 * AR * RS];
+    __shared__ __align__(16) uint16_t lb[32 * CNN_TILE * RS];
+    __shared__ uint16_t xs[IM2COL ? 2 : 1][IM2COL ? CNN_HALO * CNN_HALO : 1];
+    const int m = A.m, n = A.n;
+    const size_t NP = (size_t)m * n;
+    const int tx_n = m / CNN_TILE, ty_n = n / CNN_TILE;
+    const int ntiles = tx_n * ty_n * A.samples;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c16 = lane & 15;
+    cnn_v4f acc[NCB];
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) acc[j] = cnn_v4f{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+    for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+        const int s = tl / (tx_n * ty_n);
+        const int rem = tl - s * tx_n * ty_n;
+        const int by = rem / tx_n, bx = rem - by * tx_n;
+        const int x0 = bx * CNN_TILE, y0 = by * CNN_TILE;
+        __syncthreads();  // previous tile's LDS reads are done
+        if constexpr (IM2COL) {
+            cnn_load_inputs(A.smp[s], A.in_scale, A.sc[4 * s + 0], x0, y0, m, n, xs);
+            __syncthreads();
+            const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
+            for (int k = 0; k < 32; ++k) la[(k * CNN_TILE + ty) * RS + tx] = cnn_im2col(xs, k, ty, tx);
+        } else {
+            for (int c = threadIdx.x; c < CNN_HALO * CNN_HALO * 4; c += 256) {
+                const int pi = c >> 2, part = c & 3;
+                const int ty = pi / CNN_HALO, tx = pi - ty * CNN_HALO;
+                const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (m - 1);
+                const uint4 v = *(const uint4*)(A.in + ((size_t)s * NP + (size_t)gy * m + gx) * CNN_CH + part * 8);
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    la[((part * 8 + j) * CNN_HALO + ty) * RS + tx] =
+                        (uint16_t)((w[j >> 1] >> ((j & 1) * 16)) & 0xffff);
+            }
+        }
+        for (int c = threadIdx.x; c < CNN_TILE * CNN_TILE * 4; c += 256) {
+            const int pi = c >> 2, part = c & 3;
+            const int ty = pi >> 4, tx = pi & 15;
+            const uint4 v = *(const uint4*)(A.dz + ((size_t)s * NP + (size_t)(y0 + ty) * m + x0 + tx) * CNN_CH + part * 8);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                lb[((part * 8 + j) * CNN_TILE + ty) * RS + tx] = (uint16_t)((w[j >> 1] >> ((j & 1) * 16)) & 0xffff);
+        }
+        __syncthreads();
+        if (threadIdx.x < 32) {
+            float sb = 0.f;
+            for (int y = 0; y < CNN_TILE; ++y)
+                for (int x = 0; x < CNN_TILE; ++x) sb += bf16_val(lb[(threadIdx.x * CNN_TILE + y) * RS + x]);
+            bacc += sb;
+        }
+        for (int y = 0; y < CNN_TILE; ++y) {
+#pragma unroll
+            for (int j = 0; j < NCB; ++j) {
+                const int cb = wave * NCB + j;
+                int tap, mt, nt;
+                if constexpr (IM2COL) { tap = 0; mt = cb >> 1; nt = cb & 1; }
+                else { tap = cb >> 2; mt = (cb >> 1) & 1; nt = cb & 1; }
+                const int ky = tap / 3, kx = tap - 3 * ky;
+                const int row = mt * 16 + c16;
+                cnn_v4s a;
+                const uint16_t* pa = la + (row * AR + y + (IM2COL ? 0 : ky)) * RS + 4 * g + (IM2COL ? 0 : kx);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = (short)pa[i];
+                const cnn_v4s b = *(const cnn_v4s*)(lb + ((nt * 16 + c16) * CNN_TILE + y) * RS + 4 * g);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+            }
+        }
+    }
+    float* out = A.part + (size_t)blockIdx.x * SEG;
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) {
+        const int cb = wave * NCB + j;
+        int tap, mt, nt;
+        if constexpr (IM2COL) { tap = 0; mt = cb >> 1; nt = cb & 1; }
+        else { tap = cb >> 2; mt = (cb >> 1) & 1; nt = cb & 1; }
+        const int co = nt * 16 + c16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ci = mt * 16 + 4 * g + i;
+            if constexpr (IM2COL) {
+                if (ci < 18) out[ci * CNN_CH + co] = acc[j][i];
+            } else {
+                out[(tap * CNN_CH + ci) * CNN_CH + co] = acc[j][i];
+            }
+        }
+    }
+    if (threadIdx.x < 32) out[SEG - 32 + threadIdx.x] = bacc;
+}
+
+struct CnnW4Args {
+    int m, n, samples;
+    const uint16_t* in;        // a3
+    const float* gd;
+    float* part;               // [block][CNN_SEG4]
+};
+
+// Gradients of the output layer: dW4[tap][c] = sum_p a3[p + offset(tap)][c] gd[p],
+// db4 = sum_p gd[p]; per-block partial sums over a strided set of tiles.
+__global__ void __launch_bounds__(256) k_cnn_w4grad(CnnW4Args A) {
+    __shared__ __align__(16) uint16_t lds[CNN_HALO * CNN_HALO * CNN_PX];
+    __shared__ float gs[CNN_TILE * CNN_TILE];
+    const int m = A.m, n = A.n;
+    const size_t NP = (size_t)m * n;
+    const int tx_n = m / CNN_TILE, ty_n = n / CNN_TILE;
+    const int ntiles = tx_n * ty_n * A.samples;
+    float acc[2] = {0.f, 0.f};
+    for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+        const int s = tl / (tx_n * ty_n);
+        const int rem = tl - s * tx_n * ty_n;
+        const int by = rem / tx_n, bx = rem - by * tx_n;
+        const int x0 = bx * CNN_TILE, y0 = by * CNN_TILE;
+        __syncthreads();
+        cnn_load_halo(A.in, (size_t)s * NP, x0, y0, m, n, lds);
+        {
+            const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+            gs[threadIdx.x] = A.gd[(size_t)s * NP + (size_t)(y0 + ty) * m + x0 + tx];
+        }
+        __syncthreads();
+        for (int k = 0; k < 2; ++k) {
+            const int o = threadIdx.x + 256 * k;
+            if (o >= CNN_SEG4) break;
+            float sum = 0.f;
+            if (o < 9 * CNN_CH) {
+                const int tap = o / CNN_CH, c = o - tap * CNN_CH;
+                const int ky = tap / 3, kx = tap - 3 * ky;
+                for (int y = 0; y < CNN_TILE; ++y)
+                    for (int x = 0; x < CNN_TILE; ++x)
+                        sum += bf16_val(lds[((y + ky) * CNN_HALO + x + kx) * CNN_PX + c]) * gs[y * CNN_TILE + x];
+            } else {
+                for (int p = 0; p < CNN_TILE * CNN_TILE; ++p) sum += gs[p];
+            }
+            acc[k] += sum;
+        }
+    }
+    for (int k = 0; k < 2; ++k) {
+        const int o = threadIdx.x + 256 * k;
+        if (o < CNN_SEG4) A.part[(size_t)blockIdx.x * CNN_SEG4 + o] = acc[k];
+    }
+}
+
+// out[i] = sum over blocks b (in order) of part[b * seg + i].
+__global__ void __launch_bounds__(256) k_cnn_reduce(const float* __restrict__ part, int nblk,
+                                                    int seg, float* out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= seg) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * seg + i];
+    out[i] = s;
+}
+
+// Adam on the FP32 master parameters (Kingma and Ba, 2015); c1, c2 are the
+// bias corrections 1 / (1 - beta^t).
+__global__ void __launch_bounds__(256) k_cnn_adam(float* theta, const float* __restrict__ grad,
+                                                  float* mom, float* vel, int count, float lr,
+                                                  float b1, float b2, float eps, float c1,
+                                                  float c2) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const float gr = grad[i];
+    const float m1 = b1 * mom[i] + (1.f - b1) * gr;
+    const float v1 = b2 * vel[i] + (1.f - b2) * gr * gr;
+    mom[i] = m1;
+    vel[i] = v1;
+    theta[i] -= lr * (m1 * c1) / (sqrtf(v1 * c2) + eps);
+}
+
+// Per-lane weight fragments (BF16) from the FP32 parameters:
+//   f1: layer 1, [kc][mt][lane][4], A[co][k] = W1[k / 2][k % 2][co] (0 for k >= 18);
+//   f2, f3: layers 2, 3 forward, [tap][kc][mt][lane][4], A[co][ci] = W[tap][ci][co];
+//   r2, r3: backward data, A[co'][ci'] = W[8 - tap][co'][ci'] (flipped taps, swapped channels);
+//   w4: output-layer weights rounded to BF16 (as floats).
+struct CnnFrags {
+    uint16_t* f1;
+    uint16_t* f2;
+    uint16_t* f3;
+    uint16_t* r2;
+    uint16_t* r3;
+    float* w4;
+};
+
+__global__ void __launch_bounds__(256) k_cnn_prepare(const float* __restrict__ th, CnnFrags F) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    constexpr int N1 = CNN_NFRAG1 * 256, N2 = CNN_NFRAG * 256;
+    if (e < N1) {
+        const int f = e >> 8, lane = (e >> 2) & 63, i = e & 3;
+        const int kc = f >> 1, mt = f & 1;
+        const int co = mt * 16 + (lane & 15), k = kc * 16 + 4 * (lane >> 4) + i;
+        F.f1[e] = k < 18 ? bf16_bits(th[CNN_W1 + k * CNN_CH + co]) : (uint16_t)0;
+        return;
+    }
+    int r = e - N1;
+    if (r < 4 * N2) {
+        const int which = r / N2;
+        r -= which * N2;
+        const int f = r >> 8, lane = (r >> 2) & 63, i = r & 3;
+        const int tap = f >> 2, kc = (f >> 1) & 1, mt = f & 1;
+        const int a = mt * 16 + (lane & 15), b = kc * 16 + 4 * (lane >> 4) + i;
+        const int base = (which & 1) ? CNN_W3 : CNN_W2;
+        uint16_t* dst = which == 0 ? F.f2 : which == 1 ? F.f3 : which == 2 ? F.r2 : F.r3;
+        // forward: co = a, ci = b; backward: co' = a (an input channel of W), ci' = b
+        const float v = which < 2 ? th[base + (tap * CNN_CH + b) * CNN_CH + a]
+                                  : th[base + ((8 - tap) * CNN_CH + a) * CNN_CH + b];
+        dst[r] = bf16_bits(v);
+        return;
+    }
+    r -= 4 * N2;
+    if (r < 9 * CNN_CH) F.w4[r] = bf16_val(bf16_bits(th[CNN_W4 + r]));
+}
+
+// Candidate choice of the step's initial guess: if the learned guess (copy 1)
+// has the smaller FP64 residual, copy it over the extrapolated one (copy 0).
+// counts[0] counts the steps that used it, counts[1] the fallbacks.
+__global__ void __launch_bounds__(256) k_cnn_pick(const double* __restrict__ r2, size_t total,
+                                                  double* u0a, double* u0b, double* u0c,
+                                                  const double* __restrict__ u1a,
+                                                  const double* __restrict__ u1b,
+                                                  const double* __restrict__ u1c,
+                                                  unsigned long long* counts) {
+    const bool use = r2[0] < r2[1];
+    const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (q == 0) counts[use ? 0 : 1] += 1ull;
+    if (!use || q >= total) return;
+    u0a[q] = u1a[q];
+    u0b[q] = u1b[q];
+    u0c[q] = u1c[q];
+}
+
+}  // namespace mpfc

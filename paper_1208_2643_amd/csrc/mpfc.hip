@@ -93,6 +93,9 @@ struct Level {
     double* prr = nullptr;
 };
 
+struct CnnNet;               // learned-guess network (defined with its kernels)
+void cnn_free(CnnNet* net);
+
 }  // namespace
 
 struct mpfc_ctx {
@@ -140,6 +143,10 @@ struct mpfc_ctx {
     int inner_cycles = 3;
     int pred_units = 4;                    // cycles (outer iterations) the last step needed
     hipGraphExec_t gx_mixed[2] = {};       // one outer iteration, from copy 0 / copy 1
+    // learned initial guess (guess mode MPFC_GUESS_CNN)
+    CnnNet* cnn = nullptr;
+    double* cnn_r2 = nullptr;              // squared residual norms: [0] learned, [1] extrapolated
+    unsigned long long* cnn_counts = nullptr;  // [0] steps that used the learned guess, [1] fallbacks
 };
 
 namespace {
@@ -779,7 +786,8 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
     if (o->coarsest != 2) return fail(MPFC_EINVAL, "coarsest must be 2");
     if (!(o->precision == MPFC_FP64 || o->precision == MPFC_MIXED))
         return fail(MPFC_EINVAL, "precision must be MPFC_FP64 or MPFC_MIXED");
-    if (!(o->guess == MPFC_GUESS_PREV || o->guess == MPFC_GUESS_EXTRAP))
+    if (!(o->guess == MPFC_GUESS_PREV || o->guess == MPFC_GUESS_EXTRAP ||
+          o->guess == MPFC_GUESS_CNN))
         return fail(MPFC_EINVAL, "unknown guess mode");
     if (!(o->linearization == MPFC_NEWTON || o->linearization == MPFC_PICARD))
         return fail(MPFC_EINVAL, "unknown linearization");
@@ -890,6 +898,10 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
     return MPFC_OK;
 }
 
+int cnn_candidate(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, hipStream_t s);
+void residual_sq(mpfc_ctx* C, int k, double* out, hipStream_t s);
+void cnn_choose(mpfc_ctx* C, hipStream_t s);
+
 // ---- one step, split for reuse by the batched path -------------------------------
 // Source (also copies phi^k), phi^k pyramid, guess and its completion, stop
 // state reset and the first residual norm (FP64), or for mixed precision the
@@ -914,8 +926,15 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
         for (int l = 1; l < nl; ++l)
             hipLaunchKernelGGL((k_restrict<double, double>), grid2(C->L[l].m, C->L[l].n), B2, 0, s,
                                C->L[l - 1].g, C->L[l - 1].xk, C->L[l].xk);
+    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->st);
+    const bool learned = C->o.guess == MPFC_GUESS_CNN;
+    if (learned) {
+        int rc = cnn_candidate(C, phi_n, phi_nm1, s);
+        if (rc) return rc;
+        residual_sq(C, 1, C->cnn_r2, s);
+    }
     hipLaunchKernelGGL(k_guess, grid1(total), dim3(256), 0, s, g0,
-                       C->o.guess == MPFC_GUESS_EXTRAP ? 1 : 0, phi_n, phi_nm1, phi);
+                       C->o.guess == MPFC_GUESS_PREV ? 0 : 1, phi_n, phi_nm1, phi);
     const double e = C->p.scheme == 1 ? 1.0 : 0.5;
     const double al = C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha;
     hipLaunchKernelGGL(k_complete_kappa, grid2(C->m, C->n), B2, 0, s, g0, ih2, e, phi, F0.f[2], ka);
@@ -925,7 +944,7 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
     else
         hipLaunchKernelGGL((k_complete_mu<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, phi,
                            C->phik, ka, F0.f[1], mu);
-    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->st);
+    if (learned) cnn_choose(C, s);
     if (C->o.precision != MPFC_MIXED) {
         resnorm(C, s);
     } else {
@@ -1105,6 +1124,8 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
         C->part = take((size_t)C->nparts);
         C->st = (CycleState*)take(16);
         C->pst = (CycleState*)take(16);
+        C->cnn_r2 = take(8);
+        C->cnn_counts = (unsigned long long*)take(8);
         return off;
     };
     C->arena_bytes = layout(nullptr) * sizeof(double);
@@ -1156,6 +1177,7 @@ void mpfc_destroy(mpfc_ctx* C) {
     if (C->cap_stream) (void)hipStreamDestroy(C->cap_stream);
     for (hipEvent_t e : C->ev)
         if (e) (void)hipEventDestroy(e);
+    if (C->cnn) cnn_free(C->cnn);
     if (C->arena) (void)hipFree(C->arena);
     if (C->host_st) (void)hipHostFree(C->host_st);
     if (C->host_buf) (void)hipHostFree(C->host_buf);
@@ -1169,6 +1191,8 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     if (phi_np1 == phi_n || phi_np1 == phi_nm1 || phi_np1 == psi)
         return fail(MPFC_EINVAL, "phi_np1 must not alias an input");
     if (!phi_nm1) phi_nm1 = phi_n;
+    if (C->o.guess == MPFC_GUESS_CNN && !C->cnn)
+        return fail(MPFC_EINVAL, "guess mode MPFC_GUESS_CNN needs a network (mpfc_cnn_load)");
     hipStream_t s = C->stream;
     Level& F0 = C->L[0];
     const size_t total = (size_t)C->m * C->n;
@@ -1371,3 +1395,4 @@ int mpfc_op_restrict(int m, int n, const double* fine, double* coarse, void* str
 }  // extern "C"
 
 #include "batch_host.hpp"
+#include "cnn_host.hpp"

@@ -1,0 +1,166 @@
+"""The learned initial guess on the GPU (BF16 matrix-core kernels) against the
+FP64 CPU reference network (oracle/cnn.py), and inside the time step.
+
+Bars: BF16 operands carry 8 significant bits, so forward outputs and
+gradients agree with the FP64 reference to about 1e-2 relative (the tests use
+3e-2 for outputs and 5e-2 per gradient array); Adam runs in FP32 and matches
+the reference update of the same gradient to 1e-5.  Inside the step the
+solution does not depend on the guess (Sec. 3, unique solvability), so a step
+from the learned guess must agree with one from extrapolation to the solver
+tolerance, and a network that cannot beat extrapolation must fall back to it
+exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cnn as N
+from paper_1208_2643_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1208_2643_amd import api  # noqa: E402
+from paper_1208_2643_amd import _lib as L  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def samples(m, n, count, seed):
+    out = []
+    for k in range(count):
+        a = I.noise(m, n, mean=0.1, amp=0.1, seed=seed + 3 * k)
+        b = a + I.noise(m, n, mean=0.0, amp=0.01, seed=seed + 3 * k + 1)
+        c = 2 * b - a + I.noise(m, n, mean=0.0, amp=0.002, seed=seed + 3 * k + 2)
+        out.append((a, b, c))
+    return out
+
+
+def make_blob(seed=3):
+    """Hidden and output weights all random, small random biases."""
+    blob = N.init_blob(seed, zero_last=False)
+    rng = np.random.default_rng(seed + 100)
+    off = N.HEADER
+    for name, shape in N.layout():
+        cnt = int(np.prod(shape))
+        if name.startswith("b"):
+            blob[off:off + cnt] = rng.uniform(-0.1, 0.1, cnt)
+        off += cnt
+    blob[5] = 0.5  # out_scale
+    return blob
+
+
+M, NN, B = 32, 64, 2
+
+
+def test_predict_matches_oracle():
+    blob = make_blob()
+    S = samples(M, NN, B, 10)
+    tr = api.CnnTrainer(M, NN, B, blob)
+    got = tr.predict([dev(s[0]) for s in S], [dev(s[1]) for s in S])
+    tr.close()
+    for k, (a, b, _) in enumerate(S):
+        ref = N.guess(blob, a, b)
+        g = host(got[k])
+        # the learned correction (the part the network adds to extrapolation)
+        assert rel(g - (2 * b - a), ref - (2 * b - a)) <= 3e-2, k
+        assert abs(np.mean(g) - np.mean(2 * b - a)) < 1e-14
+
+
+def test_gradients_match_oracle():
+    blob = make_blob(4)
+    S = samples(M, NN, B, 20)
+    tr = api.CnnTrainer(M, NN, B, blob)
+    loss, g = tr.step([dev(s[0]) for s in S], [dev(s[1]) for s in S], [dev(s[2]) for s in S],
+                      update=False, grad=True)
+    tr.close()
+    lref, gref = N.loss_and_grad(blob, S)
+    assert abs(loss - lref) <= 3e-2 * lref
+    off = 0
+    for name, shape in N.layout():
+        cnt = int(np.prod(shape))
+        assert rel(g[off:off + cnt], gref[off:off + cnt]) <= 5e-2, name
+        off += cnt
+
+
+def test_adam_matches_oracle_on_gpu_gradients():
+    blob = make_blob(5)
+    S = samples(M, NN, B, 30)
+    lr = 3e-3
+    tr = api.CnnTrainer(M, NN, B, blob, lr=lr)
+    args = ([dev(s[0]) for s in S], [dev(s[1]) for s in S], [dev(s[2]) for s in S])
+    theta = blob[N.HEADER:].astype(np.float64)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    for t in (1, 2):
+        _, g = tr.step(*args, update=True, grad=True)
+        theta, m, v = N.adam(theta, g.astype(np.float64), m, v, t, lr)
+        got = tr.blob()[N.HEADER:].astype(np.float64)
+        assert np.max(np.abs(got - theta)) <= 1e-5 * max(1.0, np.max(np.abs(theta)))
+    tr.close()
+
+
+def test_training_reduces_loss():
+    blob = N.init_blob(6)
+    S = samples(M, NN, B, 40)
+    tr = api.CnnTrainer(M, NN, B, blob, lr=3e-3)
+    args = ([dev(s[0]) for s in S], [dev(s[1]) for s in S], [dev(s[2]) for s in S])
+    first = tr.step(*args)
+    for _ in range(60):
+        last = tr.step(*args)
+    tr.close()
+    assert last < 0.5 * first
+
+
+def crystal_run(stepper, steps, seed=5, N_=64):
+    phi0 = I.crystallites(N_, N_, math.pi / 4, count=2, radius_cells=8, seed=seed)
+    return api.run(stepper, dev(phi0), steps)
+
+
+PARAMS = dict(eps=0.025, beta=0.9, M=1.0, h=math.pi / 4, dt=0.05, scheme=2)
+
+
+def test_fallback_is_exact():
+    """A network whose output is zero reproduces extrapolation and counts
+    every step as a fallback; a NaN network too; the states are bitwise those
+    of the extrapolated guess."""
+    p = api.Params(**PARAMS)
+    ref = api.Stepper(64, 64, p, energy=0, guess=L.MPFC_GUESS_EXTRAP)
+    phi_r, _, _, inf_r = crystal_run(ref, 4)
+    for kind in ("zero", "nan"):
+        blob = N.init_blob(7, zero_last=True)
+        if kind == "nan":
+            blob[N.HEADER + 700] = np.nan
+        st = api.Stepper(64, 64, p, energy=0, guess=L.MPFC_GUESS_CNN)
+        st.load_cnn(blob)
+        phi, _, _, inf = crystal_run(st, 4)
+        used, fb = st.cnn_counts()
+        assert (used, fb) == (0, 4), kind
+        assert np.array_equal(host(phi), host(phi_r)), kind
+        assert [i.n_cycles for i in inf] == [i.n_cycles for i in inf_r]
+
+
+def test_learned_guess_requires_a_network():
+    st = api.Stepper(64, 64, api.Params(**PARAMS), energy=0, guess=L.MPFC_GUESS_CNN)
+    x = dev(np.full((64, 64), 0.1))
+    with pytest.raises(L.MpfcError):
+        st.step(x, x, torch.zeros_like(x), torch.empty_like(x))
+    with pytest.raises(L.MpfcError):
+        st.load_cnn(np.zeros(10, dtype=np.float32))
