@@ -66,6 +66,8 @@ def parse():
                     help="first run a plain 128 MiB device copy (counter calibration)")
     ap.add_argument("--variants", type=int, default=1,
                     help="also time the mixed-precision variant of the workload")
+    ap.add_argument("--learned-steps", type=int, default=500,
+                    help="steps of the learned-guess comparison (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=50,
                     help="steps of the 64-simulation batched variant (0 skips it)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -96,6 +98,59 @@ def cpu_baseline(params, phi0, tol, budget_s):
             "sample": f"first {steps} step(s) of the same {phi0.shape[1]}x{phi0.shape[0]} "
                       f"workload from its initial state ({cycles} V-cycles, energies on), "
                       f"{dt:.1f} s wall"}
+
+
+def bench_learned(api, inputs, torch, dev, params, tol, steps, warmup, N):
+    from paper_1208_2643_amd import guess_net
+    if not os.path.exists(guess_net.DEFAULT_WEIGHTS):
+        return {"skipped": f"no trained network at {guess_net.DEFAULT_WEIGHTS}"}
+    blob = guess_net.load()
+    phi0 = inputs.crystallites(N, N, params["h"], seed=5)
+    res = {"workload": f"{N}x{N}, second-order scheme, crystallites seed 5, {steps} steps, "
+                       "FP64 V(2,2) to 1e-10, energies off",
+           "network": guess_net.meta().get("validation_loss") if os.path.exists(
+               guess_net.DEFAULT_WEIGHTS + ".json") else None}
+    finals = {}
+    for name, guess in (("extrapolated", 1), ("learned", 2)):
+        st = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2, energy=0, guess=guess)
+        if guess == 2:
+            st.load_cnn(blob)
+        phi = torch.from_numpy(phi0).to(dev)
+        prev = phi.clone()
+        psi = torch.zeros_like(phi)
+        nxt = torch.empty_like(phi)
+        # warm-up steps restart from the initial state afterwards
+        for _ in range(warmup):
+            st.step(phi, prev, psi, nxt)
+        phi = torch.from_numpy(phi0).to(dev)
+        prev = phi.clone()
+        psi.zero_()
+        if guess == 2:
+            st.load_cnn(blob)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cycles = 0
+        r0 = []
+        for _ in range(steps):
+            _, info = st.step(phi, prev, psi, nxt)
+            cycles += info.n_cycles
+            r0.append(info.history[0])
+            prev, phi, nxt = phi, nxt, prev
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        entry = {"time_steps_per_s": steps / el, "vcycles_per_step": cycles / steps,
+                 "median_initial_residual": float(sorted(r0)[len(r0) // 2])}
+        if guess == 2:
+            used, fb = st.cnn_counts()
+            entry["steps_from_learned_guess"] = used
+            entry["fallbacks"] = fb
+        finals[name] = phi.double().cpu()
+        res[name] = entry
+        st.close()
+    d = (finals["learned"] - finals["extrapolated"]).norm() / finals["extrapolated"].norm()
+    res["final_state_rel_l2_difference"] = float(d)
+    res["speedup"] = res["learned"]["time_steps_per_s"] / res["extrapolated"]["time_steps_per_s"]
+    return res
 
 
 def bench_batch(api, inputs, torch, dev, steps, warmup):
@@ -284,6 +339,12 @@ def main():
         out["variants"]["mixed"] = {"time_steps_per_s": vsteps / el, "steps": vsteps,
                                     "outer_per_step": outer / vsteps,
                                     "fp32_vcycles_per_step": inner / vsteps}
+    # Learned initial guess (the committed trained network) against the
+    # extrapolated guess on the same evaluation input: 1024^2, the parameters
+    # above, crystallites from seed 5, `learned_steps` steps each.
+    if args.variants and args.learned_steps > 0:
+        out["variants"]["learned"] = bench_learned(api, inputs, torch, dev, params, tol,
+                                                   args.learned_steps, args.warmup, N)
     # Batched workload: 64 independent simulations, sizes uniform over
     # {128, ..., 1024}^2, eps / mean phi / beta drawn per simulation, seeded
     # noise, mixed precision, all advanced together by shared launches.

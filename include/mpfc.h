@@ -282,6 +282,9 @@ int mpfc_cnn_train_step(mpfc_cnn_trainer *t, const double *const *d_phi_nm1,
 int mpfc_cnn_predict(mpfc_cnn_trainer *t, const double *const *d_phi_nm1,
                      const double *const *d_phi_n, double *const *d_guess);
 
+/* Learning rate of the following Adam steps (a schedule is the caller's). */
+int mpfc_cnn_trainer_set_lr(mpfc_cnn_trainer *t, float lr);
+
 /* Current weights as a blob (count = mpfc_cnn_blob_size()). */
 int mpfc_cnn_trainer_blob(mpfc_cnn_trainer *t, float *h_blob, size_t count);
 

@@ -113,6 +113,7 @@ SIGNATURES = {
     "mpfc_cnn_predict": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "mpfc_cnn_trainer_blob": (_i, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
     "mpfc_cnn_trainer_destroy": (None, [_vp]),
+    "mpfc_cnn_trainer_set_lr": (_i, [_vp, ctypes.c_float]),
 }
 
 

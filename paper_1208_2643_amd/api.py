@@ -258,6 +258,9 @@ class CnnTrainer:
             g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if grad else None))
         return (loss.value, g) if grad else loss.value
 
+    def set_lr(self, lr: float):
+        L.check(self.lib.mpfc_cnn_trainer_set_lr(self.t, lr))
+
     def predict(self, pm1, p0):
         out = [torch.empty_like(t) for t in p0]
         L.check(self.lib.mpfc_cnn_predict(self.t, _ptrs(pm1), _ptrs(p0), _ptrs(out)))

@@ -17,7 +17,8 @@
 // channels as M (two 16-row tiles), 16 pixels of a tile row as N and the input
 // channels as K; its weight operand is kept in registers as per-lane fragments
 // prepared from the FP32 master weights (k_cnn_prepare).  Layer 1 gathers its
-// 18 taps x channels into one K = 32 operand (im2col in LDS).
+// 18 taps x channels, each input split into a BF16 hi and lo part, into one
+// K = 48 operand (im2col in LDS).
 //
 // MFMA v_mfma_f32_16x16x16bf16_1k operand layout (lane l, g = l / 16,
 // c = l % 16): A[m = c][k = 4g + i], B[k = 4g + i][n = c], D[m = 4g + i][n = c].
@@ -36,7 +37,7 @@ constexpr int CNN_CH = 32;
 constexpr int CNN_TILE = 16;
 constexpr int CNN_HALO = 18;
 constexpr int CNN_PX = 36;           // LDS stride of one pixel (32 channels + 4 pad)
-constexpr int CNN_NFRAG1 = 4;        // layer 1: K = 32 (2 chunks) x 2 M tiles
+constexpr int CNN_NFRAG1 = 6;        // layer 1: K = 48 (3 chunks) x 2 M tiles
 constexpr int CNN_NFRAG = 36;        // 9 taps x 2 K chunks x 2 M tiles
 // parameter offsets in the FP32 vector (blob order, no header)
 constexpr int CNN_W1 = 0, CNN_B1 = 576, CNN_W2 = 608, CNN_B2 = 9824, CNN_W3 = 9856,
@@ -54,24 +55,23 @@ struct CnnSample {
     double* out;
 };
 
-// Round to nearest even; NaN stays NaN.
+// FP32 -> BF16 (hardware conversion: round to nearest even, NaN kept).
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 __device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-__device__ __forceinline__ float gelu_f(float x) {
+// tanh-form GELU, evaluated through the identity (1 + tanh u) / 2 = 1 / (1 + e^{-2u}):
+// gelu(x) = x s, s = 1 / (1 + e^{-2u}), u = sqrt(2/pi) (x + 0.044715 x^3);
+// gelu'(x) = s + 2 x s (1 - s) u'(x).
+__device__ __forceinline__ float gelu_sig(float x) {
     const float u = 0.7978845608028654f * (x + 0.044715f * x * x * x);
-    return 0.5f * x * (1.0f + tanhf(u));
+    return __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));
 }
+__device__ __forceinline__ float gelu_f(float x) { return x * gelu_sig(x); }
 __device__ __forceinline__ float gelu_grad_f(float x) {
-    const float u = 0.7978845608028654f * (x + 0.044715f * x * x * x);
-    const float t = tanhf(u);
-    return 0.5f * (1.0f + t) +
-           0.5f * x * (1.0f - t * t) * 0.7978845608028654f * (1.0f + 0.134145f * x * x);
+    const float s = gelu_sig(x);
+    return s + 2.0f * x * s * (1.0f - s) * 0.7978845608028654f * (1.0f + 0.134145f * x * x);
 }
 
 // Halo tile (18 x 18 pixels, 32 channels) of an NHWC activation into LDS
@@ -89,8 +89,10 @@ __device__ __forceinline__ void cnn_load_halo(const uint16_t* __restrict__ act, 
     }
 }
 
-// Layer-1 inputs of an 18 x 18 halo tile as BF16 bits: xs[0][.] = in_scale *
-// phi^n, xs[1][.] = (phi^n - phi^{n-1}) * inv_sigma1.
+// Layer-1 inputs of an 18 x 18 halo tile as BF16 pairs (hi, lo = the BF16
+// rounding of what hi leaves), so that the first layer sees its inputs to about
+// 16 significant bits: xs[c] and xs[2 + c] for x0 = in_scale * phi^n and
+// x1 = (phi^n - phi^{n-1}) * inv_sigma1.
 __device__ __forceinline__ void cnn_load_inputs(const CnnSample& S, double in_scale,
                                                 double inv_sigma1, int x0, int y0, int m, int n,
                                                 uint16_t (*xs)[CNN_HALO * CNN_HALO]) {
@@ -99,17 +101,25 @@ __device__ __forceinline__ void cnn_load_inputs(const CnnSample& S, double in_sc
         const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (m - 1);
         const size_t q = (size_t)gy * m + gx;
         const double v0 = S.p0[q], v1 = S.pm1[q];
-        xs[0][t] = bf16_bits((float)(in_scale * v0));
-        xs[1][t] = bf16_bits((float)((v0 - v1) * inv_sigma1));
+        const float a = (float)(in_scale * v0), b = (float)((v0 - v1) * inv_sigma1);
+        const uint16_t ah = bf16_bits(a), bh = bf16_bits(b);
+        xs[0][t] = ah;
+        xs[1][t] = bh;
+        xs[2][t] = bf16_bits(a - bf16_val(ah));
+        xs[3][t] = bf16_bits(b - bf16_val(bh));
     }
 }
 
-// im2col value k (k = tap * 2 + channel, 0 for k >= 18) of tile pixel (ty, tx).
+// im2col value k of tile pixel (ty, tx): k = part * 18 + tap * 2 + channel for
+// the hi (part 0) and lo (part 1) inputs, 0 for k >= 36.
+constexpr int CNN_K1 = 48;        // layer-1 K (36 used), 3 chunks of 16
+constexpr int CNN_PX1 = 52;       // LDS stride of one im2col pixel
 __device__ __forceinline__ uint16_t cnn_im2col(const uint16_t (*xs)[CNN_HALO * CNN_HALO], int k,
                                                int ty, int tx) {
-    if (k >= 18) return 0;
-    const int tap = k >> 1, ky = tap / 3, kx = tap - 3 * ky;
-    return xs[k & 1][(ty + ky) * CNN_HALO + tx + kx];
+    if (k >= 36) return 0;
+    const int part = k >= 18 ? 1 : 0, kk = k - 18 * part;
+    const int tap = kk >> 1, ky = tap / 3, kx = tap - 3 * ky;
+    return xs[2 * part + (kk & 1)][(ty + ky) * CNN_HALO + tx + kx];
 }
 
 struct CnnConvArgs {
@@ -135,9 +145,9 @@ enum { CNN_FWD = 0, CNN_BWD = 1 };
 template <bool IM2COL, int MODE>
 __global__ void __launch_bounds__(256) k_cnn_conv(CnnConvArgs A) {
     constexpr int NFR = IM2COL ? CNN_NFRAG1 : CNN_NFRAG;
-    constexpr int LDS_N = IM2COL ? CNN_TILE * CNN_TILE * CNN_PX : CNN_HALO * CNN_HALO * CNN_PX;
+    constexpr int LDS_N = IM2COL ? CNN_TILE * CNN_TILE * CNN_PX1 : CNN_HALO * CNN_HALO * CNN_PX;
     __shared__ __align__(16) uint16_t lds[LDS_N];
-    __shared__ uint16_t xs[IM2COL ? 2 : 1][IM2COL ? CNN_HALO * CNN_HALO : 1];
+    __shared__ uint16_t xs[IM2COL ? 4 : 1][IM2COL ? CNN_HALO * CNN_HALO : 1];
     const int m = A.m, n = A.n;
     const size_t NP = (size_t)m * n;
     const int s = blockIdx.z;
@@ -153,7 +163,7 @@ __global__ void __launch_bounds__(256) k_cnn_conv(CnnConvArgs A) {
         __syncthreads();
         {
             const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
-            for (int k = 0; k < 32; ++k) lds[t * CNN_PX + k] = cnn_im2col(xs, k, ty, tx);
+            for (int k = 0; k < CNN_K1; ++k) lds[t * CNN_PX1 + k] = cnn_im2col(xs, k, ty, tx);
         }
     } else {
         cnn_load_halo(A.in, (size_t)s * NP, x0, y0, m, n, lds);
@@ -169,8 +179,8 @@ __global__ void __launch_bounds__(256) k_cnn_conv(CnnConvArgs A) {
         const int row = wave * 4 + r;
         if constexpr (IM2COL) {
 #pragma unroll
-            for (int kc = 0; kc < 2; ++kc) {
-                const cnn_v4s b = *(const cnn_v4s*)(lds + (row * CNN_TILE + c16) * CNN_PX + kc * 16 + 4 * g);
+            for (int kc = 0; kc < 3; ++kc) {
+                const cnn_v4s b = *(const cnn_v4s*)(lds + (row * CNN_TILE + c16) * CNN_PX1 + kc * 16 + 4 * g);
 #pragma unroll
                 for (int mt = 0; mt < 2; ++mt)
                     acc[r][mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[kc * 2 + mt], b,
@@ -395,7 +405,7 @@ __global__ void __launch_bounds__(256) k_cnn_wgrad(CnnWgradArgs A) {
     constexpr int SEG = IM2COL ? CNN_SEG1 : CNN_SEG;
     __shared__ __align__(16) uint16_t la[32 * AR * RS];
     __shared__ __align__(16) uint16_t lb[32 * CNN_TILE * RS];
-    __shared__ uint16_t xs[IM2COL ? 2 : 1][IM2COL ? CNN_HALO * CNN_HALO : 1];
+    __shared__ uint16_t xs[IM2COL ? 4 : 1][IM2COL ? CNN_HALO * CNN_HALO : 1];
     const int m = A.m, n = A.n;
     const size_t NP = (size_t)m * n;
     const int tx_n = m / CNN_TILE, ty_n = n / CNN_TILE;
@@ -416,7 +426,9 @@ __global__ void __launch_bounds__(256) k_cnn_wgrad(CnnWgradArgs A) {
             cnn_load_inputs(A.smp[s], A.in_scale, A.sc[4 * s + 0], x0, y0, m, n, xs);
             __syncthreads();
             const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
-            for (int k = 0; k < 32; ++k) la[(k * CNN_TILE + ty) * RS + tx] = cnn_im2col(xs, k, ty, tx);
+            // the weight gradient takes the hi parts of the inputs (rows k < 18)
+            for (int k = 0; k < 32; ++k)
+                la[(k * CNN_TILE + ty) * RS + tx] = k < 18 ? cnn_im2col(xs, k, ty, tx) : (uint16_t)0;
         } else {
             for (int c = threadIdx.x; c < CNN_HALO * CNN_HALO * 4; c += 256) {
                 const int pi = c >> 2, part = c & 3;
@@ -563,7 +575,8 @@ __global__ void __launch_bounds__(256) k_cnn_adam(float* theta, const float* __r
 }
 
 // Per-lane weight fragments (BF16) from the FP32 parameters:
-//   f1: layer 1, [kc][mt][lane][4], A[co][k] = W1[k / 2][k % 2][co] (0 for k >= 18);
+//   f1: layer 1, [kc][mt][lane][4], A[co][k] = W1[tap][c][co] for k = part * 18 + tap * 2 + c
+//       (the same weight for the hi and lo part of an input; 0 for k >= 36);
 //   f2, f3: layers 2, 3 forward, [tap][kc][mt][lane][4], A[co][ci] = W[tap][ci][co];
 //   r2, r3: backward data, A[co'][ci'] = W[8 - tap][co'][ci'] (flipped taps, swapped channels);
 //   w4: output-layer weights rounded to BF16 (as floats).
@@ -583,7 +596,7 @@ __global__ void __launch_bounds__(256) k_cnn_prepare(const float* __restrict__ t
         const int f = e >> 8, lane = (e >> 2) & 63, i = e & 3;
         const int kc = f >> 1, mt = f & 1;
         const int co = mt * 16 + (lane & 15), k = kc * 16 + 4 * (lane >> 4) + i;
-        F.f1[e] = k < 18 ? bf16_bits(th[CNN_W1 + k * CNN_CH + co]) : (uint16_t)0;
+        F.f1[e] = k < 36 ? bf16_bits(th[CNN_W1 + (k % 18) * CNN_CH + co]) : (uint16_t)0;
         return;
     }
     int r = e - N1;
@@ -607,16 +620,20 @@ __global__ void __launch_bounds__(256) k_cnn_prepare(const float* __restrict__ t
 
 // Candidate choice of the step's initial guess: if the learned guess (copy 1)
 // has the smaller FP64 residual, copy it over the extrapolated one (copy 0).
-// counts[0] counts the steps that used it, counts[1] the fallbacks.
+// counts[0] counts the steps that used it, counts[1] the fallbacks; chosen[0]
+// receives the squared residual norm of the guess kept.
 __global__ void __launch_bounds__(256) k_cnn_pick(const double* __restrict__ r2, size_t total,
                                                   double* u0a, double* u0b, double* u0c,
                                                   const double* __restrict__ u1a,
                                                   const double* __restrict__ u1b,
                                                   const double* __restrict__ u1c,
-                                                  unsigned long long* counts) {
+                                                  unsigned long long* counts, double* chosen) {
     const bool use = r2[0] < r2[1];
     const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (q == 0) counts[use ? 0 : 1] += 1ull;
+    if (q == 0) {
+        counts[use ? 0 : 1] += 1ull;
+        chosen[0] = use ? r2[0] : r2[1];
+    }
     if (!use || q >= total) return;
     u0a[q] = u1a[q];
     u0b[q] = u1b[q];

@@ -272,7 +272,8 @@ void cnn_choose(mpfc_ctx* C, hipStream_t s) {
     const size_t total = (size_t)C->m * C->n;
     residual_sq(C, 0, C->cnn_r2 + 1, s);
     hipLaunchKernelGGL(k_cnn_pick, grid1(total), dim3(256), 0, s, C->cnn_r2, total, F0.u[0][0],
-                       F0.u[0][1], F0.u[0][2], F0.u[1][0], F0.u[1][1], F0.u[1][2], C->cnn_counts);
+                       F0.u[0][1], F0.u[0][2], F0.u[1][0], F0.u[1][1], F0.u[1][2], C->cnn_counts,
+                       C->part);
 }
 
 }  // namespace
@@ -391,6 +392,12 @@ int mpfc_cnn_predict(mpfc_cnn_trainer* T, const double* const* d_phi_nm1,
     N.forward(T->stream, false);
     HIP_TRY(hipStreamSynchronize(T->stream));
     HIP_TRY(hipGetLastError());
+    return MPFC_OK;
+}
+
+int mpfc_cnn_trainer_set_lr(mpfc_cnn_trainer* T, float lr) {
+    if (!T || !(lr > 0)) return fail(MPFC_EINVAL, "trainer is NULL or lr <= 0");
+    T->hp.lr = lr;
     return MPFC_OK;
 }
 

@@ -946,7 +946,11 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
                            C->phik, ka, F0.f[1], mu);
     if (learned) cnn_choose(C, s);
     if (C->o.precision != MPFC_MIXED) {
-        resnorm(C, s);
+        if (learned)  // the pick left the kept guess's squared norm in part[0]
+            hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, 1, C->st,
+                               C->hist, F0.h * F0.h, C->o.tol, C->o.max_cycles + 1, C->o.diverge);
+        else
+            resnorm(C, s);
     } else {
         const auto& FF = C->FL[0];
         if (C->p.scheme == 2) {
