@@ -38,9 +38,14 @@ MODEL_BYTES = {"down": 2 * 80.0 + 68.0, "up": 60.0 + 2 * 80.0 + 56.0}
 # u, S, phi^k (56 B) and the coarse u, v (6 quarter fields, 12 B), writes u (24 B).
 COMPULSORY_BYTES = {"down": 56.0 + 24.0 + 18.0, "up": 56.0 + 12.0 + 24.0}
 # HBM bytes per finest-level launch measured with rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (scaled by a 128 MiB copy), valid only for the kernel sources
-# they were measured on (hash of paper_1208_2643_amd/csrc/*).
-MEASURED_TRAFFIC = {"src": "c0d5372ce39ed118", "up": 107387244.0, "down": 112928009.0}
+# WRITE_SIZE (scaled by what the counters read for a 128 MiB copy), per tile
+# shape "TXxTY/HALO", valid only for the kernel sources they were measured on
+# (hash of paper_1208_2643_amd/csrc/*).
+MEASURED_TRAFFIC = {
+    "src": "a6c97f8e59c860af",
+    "down": {"64x32/6": 108142465, "32x32/6": 112935548, "32x16/6": 107991334, "16x16/6": 107892447, "64x16/10": 111877166, "32x16/10": 108048184, "16x16/10": 107947457},
+    "up": {"64x32/6": 109635233, "32x32/6": 107409967, "32x16/6": 103597157, "16x16/6": 103152566, "64x16/10": 103341544, "32x16/10": 103247263, "16x16/10": 103201098},
+}
 
 
 def kernel_source_hash() -> str:
@@ -66,6 +71,8 @@ def parse():
                     help="first run a plain 128 MiB device copy (counter calibration)")
     ap.add_argument("--variants", type=int, default=1,
                     help="also time the mixed-precision variant of the workload")
+    ap.add_argument("--big-steps", type=int, default=40,
+                    help="steps of the 2048^2 FP64-vs-mixed comparison (0 skips it)")
     ap.add_argument("--learned-steps", type=int, default=500,
                     help="steps of the learned-guess comparison (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=50,
@@ -98,6 +105,43 @@ def cpu_baseline(params, phi0, tol, budget_s):
             "sample": f"first {steps} step(s) of the same {phi0.shape[1]}x{phi0.shape[0]} "
                       f"workload from its initial state ({cycles} V-cycles, energies on), "
                       f"{dt:.1f} s wall"}
+
+
+def bench_big(api, inputs, torch, dev, params, tol, steps, warmup, N=2048, inner=4):
+    phi0 = inputs.crystallites(N, N, params["h"], seed=3)
+    res = {"workload": f"{N}x{N}, second-order scheme, crystallites seed 3, {steps} steps, "
+                       "V(2,2) to 1e-10, energies off", "inner_cycles": inner}
+    finals = {}
+    for name, kw in (("fp64", dict(precision=0)), ("mixed", dict(precision=1, inner_cycles=inner))):
+        st = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2, energy=0, **kw)
+        phi = torch.from_numpy(phi0).to(dev)
+        prev = phi.clone()
+        psi = torch.zeros_like(phi)
+        nxt = torch.empty_like(phi)
+        for _ in range(warmup):
+            st.step(phi, prev, psi, nxt)
+        phi = torch.from_numpy(phi0).to(dev)
+        prev = phi.clone()
+        psi.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cycles = outer = 0
+        for _ in range(steps):
+            _, info = st.step(phi, prev, psi, nxt)
+            cycles += info.n_cycles
+            outer += info.outer_iters
+            prev, phi, nxt = phi, nxt, prev
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = {"time_steps_per_s": steps / el, "vcycles_per_step": cycles / steps}
+        if name == "mixed":
+            res[name]["outer_per_step"] = outer / steps
+        finals[name] = phi.cpu()
+        st.close()
+    d = (finals["mixed"] - finals["fp64"]).norm() / finals["fp64"].norm()
+    res["final_state_rel_l2_mixed_vs_fp64"] = float(d)
+    res["speedup"] = res["mixed"]["time_steps_per_s"] / res["fp64"]["time_steps_per_s"]
+    return res
 
 
 def bench_learned(api, inputs, torch, dev, params, tol, steps, warmup, N):
@@ -261,12 +305,14 @@ def main():
         ms, launches, cells = st.profile_read(which, reset=True)
         timing[name] = (ms, launches, cells)
     st.profile(False)
+    shapes = {name: "%dx%d/%d" % st.tile_shape(0, which)
+              for which, name in ((0, "down"), (1, "up"))}
     dom = max(timing, key=lambda k: timing[k][0])
     ms, launches, cells = timing[dom]
     avg_s = ms / 1e3 / max(1, launches)
     achieved = MODEL_BYTES[dom] * cells / avg_s / 1e9 if launches else None
     compulsory = COMPULSORY_BYTES[dom] * cells / avg_s / 1e9 if launches else None
-    kernels = {k: {"avg_launch_us": 1e3 * v[0] / max(1, v[1]), "launches": v[1],
+    kernels = {k: {"avg_launch_us": 1e3 * v[0] / max(1, v[1]), "launches": v[1], "tile": shapes[k],
                    "model_bytes_per_cell": MODEL_BYTES[k],
                    "compulsory_bytes_per_cell": COMPULSORY_BYTES[k]} for k, v in timing.items()}
     out = {
@@ -291,14 +337,15 @@ def main():
             "precision": "fp64", "guess": "extrapolated",
         },
         "roofline": {
-            "kernel": f"k_tile {dom} launch on the finest level (fused red-black passes)",
+            "kernel": f"k_tile {dom} launch on the finest level (fused red-black passes), "
+                      f"tile {shapes[dom]}",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS if achieved else None,
-            "traffic": (MEASURED_TRAFFIC[dom] if kernel_source_hash() == MEASURED_TRAFFIC["src"]
-                        else None),
+            "traffic": (MEASURED_TRAFFIC[dom].get(shapes[dom])
+                        if kernel_source_hash() == MEASURED_TRAFFIC["src"] else None),
             "bytes_per_launch": MODEL_BYTES[dom] * cells,
             "avg_launch_us": avg_s * 1e6,
             "compulsory_GBps": compulsory,
@@ -339,6 +386,11 @@ def main():
         out["variants"]["mixed"] = {"time_steps_per_s": vsteps / el, "steps": vsteps,
                                     "outer_per_step": outer / vsteps,
                                     "fp32_vcycles_per_step": inner / vsteps}
+    # 2048^2 with mixed precision (FP32 correction cycles inside FP64 defect
+    # correction) against FP64 on the same input (seed 3).
+    if args.variants and args.big_steps > 0:
+        out["variants"]["mixed_2048"] = bench_big(api, inputs, torch, dev, params, tol,
+                                                  args.big_steps, args.warmup)
     # Learned initial guess (the committed trained network) against the
     # extrapolated guess on the same evaluation input: 1024^2, the parameters
     # above, crystallites from seed 5, `learned_steps` steps each.

@@ -154,6 +154,14 @@ int mpfc_prof_enable(mpfc_ctx *ctx, int what);
 int mpfc_prof_read(mpfc_ctx *ctx, int which, double *h_total_ms, long long *h_launches,
                    long long *h_cells_per_launch, int reset);
 
+/* Tile of the tiled launch `which` (0 down, 1 up, 2 / 3 the FP32 down / up of
+ * mixed precision, 4 / 5 the Poisson down / up of the energies) on multigrid
+ * level `level` (0 = finest; only levels above 32 x 32 cells are tiled): the
+ * interior tile tx x ty and the halo allowance of the kernel variant.  The
+ * shapes are chosen when the context is created (timed; MPFC_TILE_SHAPE=<k>
+ * forces shape k). */
+int mpfc_tile_shape(mpfc_ctx *ctx, int level, int which, int *tx, int *ty, int *halo);
+
 void mpfc_destroy(mpfc_ctx *ctx);
 const char *mpfc_strerror(int code);
 const char *mpfc_last_error(void);
@@ -231,20 +239,24 @@ void mpfc_batch_destroy(mpfc_batch *b);
 /* ---- learned initial guess -------------------------------------------------------
  * Each step has exactly one solution (Sec. 3, unique solvability), so its
  * initial guess is free; a better one only saves V-cycles.  The learned guess
- * is a periodic convolutional network (four 3x3 layers, 2 -> 32 -> 32 -> 32 -> 1
+ * is a periodic convolutional network (four 3x3 layers, 3 -> 32 -> 32 -> 32 -> 1
  * channels, tanh-form GELU after the first three; BF16 weights and
  * activations on the matrix cores, FP32 accumulation):
- *   inputs  x0 = in_scale phi^n, x1 = (phi^n - phi^{n-1}) / sigma1, sigma1 the
- *           rms of phi^n - phi^{n-1} (x1 = 0 when sigma1 = 0);
+ *   inputs  x0 = in_scale phi^n, x1 = (phi^n - phi^{n-1}) / sigma1 and
+ *           x2 = (dt psi^n - (phi^n - phi^{n-1})) / sigma1, sigma1 the rms of
+ *           phi^n - phi^{n-1} (x1 = x2 = 0 when sigma1 = 0); psi^n enters
+ *           because the step depends on it and, for scheme 2, it carries the
+ *           run's history (eq. discrete_2_b);
  *   output  delta; guess = 2 phi^n - phi^{n-1} + c, c = out_scale sigma1 delta
  *           minus its mean (the guess keeps the mass of the extrapolation).
  * In a step with guess mode MPFC_GUESS_CNN both the learned and the
  * extrapolated guess are completed (mu, kappa as for any guess) and the one
  * with the smaller FP64 residual starts the V-cycles (fallback).
  *
- * Blob (host float32, mpfc_cnn_blob_size() values): header [1, 2, 32, 4,
- * in_scale, out_scale, 0, 0], then per layer W[ky][kx][ci][co] (ky, kx = 0..2
- * for offsets -1..1 in y and x) and b[co]: W1 (3,3,2,32), b1 (32),
+ * Blob (host float32, mpfc_cnn_blob_size() values): header [2, 3, 32, 4,
+ * in_scale, out_scale, dt, 0] (dt: the time step the network was trained
+ * for; mpfc_cnn_load rejects another), then per layer W[ky][kx][ci][co]
+ * (ky, kx = 0..2 for offsets -1..1 in y and x) and b[co]: W1 (3,3,3,32), b1 (32),
  * W2 (3,3,32,32), b2, W3 (3,3,32,32), b3, W4 (3,3,32,1), b4 (1).  Grids must be
  * powers of two of at least 16 x 16. */
 int mpfc_cnn_blob_size(void);
@@ -271,16 +283,19 @@ int mpfc_cnn_trainer_create(mpfc_cnn_trainer **out, int m, int n, int batch,
                             void *stream);
 
 /* Forward and backward pass over one batch (host arrays of `batch` device
- * pointers to m x n FP64 fields); `update` != 0 then takes one Adam step.
+ * pointers to m x n FP64 fields: phi^{n-1}, phi^n, psi^n and the solution
+ * phi^{n+1}); `update` != 0 then takes one Adam step.
  * h_loss: the loss before the update; h_grad: NULL or mpfc_cnn_blob_size() - 8
  * floats receiving the gradient in blob order. */
 int mpfc_cnn_train_step(mpfc_cnn_trainer *t, const double *const *d_phi_nm1,
-                        const double *const *d_phi_n, const double *const *d_phi_np1,
-                        int update, double *h_loss, float *h_grad);
+                        const double *const *d_phi_n, const double *const *d_psi_n,
+                        const double *const *d_phi_np1, int update, double *h_loss,
+                        float *h_grad);
 
 /* Mean-corrected learned guesses of a batch with the current weights. */
 int mpfc_cnn_predict(mpfc_cnn_trainer *t, const double *const *d_phi_nm1,
-                     const double *const *d_phi_n, double *const *d_guess);
+                     const double *const *d_phi_n, const double *const *d_psi_n,
+                     double *const *d_guess);
 
 /* Learning rate of the following Adam steps (a schedule is the caller's). */
 int mpfc_cnn_trainer_set_lr(mpfc_cnn_trainer *t, float lr);

@@ -9,9 +9,14 @@ solution, Sec. 3, unique solvability theorems), so any predictor may supply
 it.  The predictor here is a small convolutional network:
 
   inputs   x0 = in_scale * phi^n,  x1 = (phi^n - phi^{n-1}) / sigma1,
-           sigma1 = rms(phi^n - phi^{n-1}) over the grid (x1 = 0 if sigma1 = 0);
+           x2 = (s psi^n - (phi^n - phi^{n-1})) / sigma1,
+           sigma1 = rms(phi^n - phi^{n-1}) over the grid (x1 = x2 = 0 if
+           sigma1 = 0), s the time step.  psi^n is an input because the step's
+           solution depends on it and, for the second-order scheme, it is not
+           a function of phi^n and phi^{n-1}: it carries the history of the run
+           (eq. discrete_2_b);
   layers   four 3x3 convolutions with periodic (circular) padding,
-           2 -> 32 -> 32 -> 32 -> 1 channels, tanh-form GELU after the first
+           3 -> 32 -> 32 -> 32 -> 1 channels, tanh-form GELU after the first
            three (Hendrycks and Gimpel, 2016);
   output   delta; the guess is 2 phi^n - phi^{n-1} + c, c = out_scale * sigma1
            * delta minus its grid mean (so the guess keeps the mass of phi^n,
@@ -21,9 +26,9 @@ Training minimises the mean over all pixels of (delta - t)^2 with the target
 t = (phi^{n+1} - 2 phi^n + phi^{n-1}) / (out_scale * sigma1), by Adam
 (Kingma and Ba, 2015).
 
-Parameter blob (float32): 8 header values [version, cin, channels, layers,
-in_scale, out_scale, 0, 0], then per layer its weights W[ky][kx][ci][co]
-(ky, kx = 0..2 for offsets -1..1 in y and x) and biases b[co].
+Parameter blob (float32): 8 header values [version 2, cin 3, channels 32,
+layers 4, in_scale, out_scale, s, 0], then per layer its weights
+W[ky][kx][ci][co] (ky, kx = 0..2 for offsets -1..1 in y and x) and biases b[co].
 
 Grids are (n, m) arrays with x fastest, as everywhere in the oracle.
 """
@@ -34,7 +39,7 @@ import math
 import numpy as np
 
 HEADER = 8
-CIN = 2
+CIN = 3
 CH = 32
 LAYERS = ((CIN, CH), (CH, CH), (CH, CH), (CH, 1))
 
@@ -53,12 +58,13 @@ def n_params() -> int:
 
 
 def unpack(blob):
-    """Blob -> (params dict of float64 arrays, in_scale, out_scale)."""
+    """Blob -> (params dict of float64 arrays, in_scale, out_scale); the time
+    step is blob[6] (see dt_of)."""
     blob = np.asarray(blob, dtype=np.float32)
     if blob.size != HEADER + n_params():
         raise ValueError("blob size does not match the network layout")
     hdr = blob[:HEADER].astype(np.float64)
-    if int(hdr[0]) != 1 or int(hdr[1]) != CIN or int(hdr[2]) != CH or int(hdr[3]) != len(LAYERS):
+    if int(hdr[0]) != 2 or int(hdr[1]) != CIN or int(hdr[2]) != CH or int(hdr[3]) != len(LAYERS):
         raise ValueError("blob header does not match the network layout")
     params, off = {}, HEADER
     for name, shape in layout():
@@ -68,14 +74,19 @@ def unpack(blob):
     return params, float(hdr[4]), float(hdr[5])
 
 
-def pack(params, in_scale, out_scale):
-    hdr = np.array([1, CIN, CH, len(LAYERS), in_scale, out_scale, 0, 0], dtype=np.float32)
+def dt_of(blob) -> float:
+    return float(np.asarray(blob, dtype=np.float32)[6])
+
+
+def pack(params, in_scale, out_scale, dt):
+    hdr = np.array([2, CIN, CH, len(LAYERS), in_scale, out_scale, dt, 0], dtype=np.float32)
     parts = [hdr] + [np.asarray(params[name], dtype=np.float32).reshape(-1)
                      for name, _ in layout()]
     return np.concatenate(parts)
 
 
-def init_blob(seed: int, in_scale: float = 2.0, out_scale: float = 1.0, zero_last: bool = True):
+def init_blob(seed: int, in_scale: float = 2.0, out_scale: float = 1.0, dt: float = 0.05,
+              zero_last: bool = True):
     """He-normal weights (std sqrt(2 / fan_in)), zero biases; the last layer
     zero (the untrained network then reproduces the extrapolated guess)."""
     rng = np.random.default_rng(seed)
@@ -87,7 +98,7 @@ def init_blob(seed: int, in_scale: float = 2.0, out_scale: float = 1.0, zero_las
             W[:] = 0.0
         params[f"W{k + 1}"] = W
         params[f"b{k + 1}"] = np.zeros(co)
-    return pack(params, in_scale, out_scale)
+    return pack(params, in_scale, out_scale, dt)
 
 
 # ---- building blocks ---------------------------------------------------------------
@@ -135,12 +146,17 @@ def conv_backward(x, W, gout):
 
 
 # ---- the network -------------------------------------------------------------------
-def inputs(phi_nm1, phi_n, in_scale):
+def inputs(phi_nm1, phi_n, psi_n, dt, in_scale):
     """Input channels and sigma1 = rms(phi^n - phi^{n-1})."""
     d1 = phi_n - phi_nm1
     sigma1 = math.sqrt(float(np.mean(d1 * d1)))
-    x1 = d1 / sigma1 if sigma1 > 0 else np.zeros_like(d1)
-    return np.stack([in_scale * phi_n, x1], axis=-1), sigma1
+    if sigma1 > 0:
+        x1 = d1 / sigma1
+        x2 = (dt * psi_n - d1) / sigma1
+    else:
+        x1 = np.zeros_like(d1)
+        x2 = np.zeros_like(d1)
+    return np.stack([in_scale * phi_n, x1, x2], axis=-1), sigma1
 
 
 def forward(params, x):
@@ -157,19 +173,19 @@ def forward(params, x):
     return delta, cache
 
 
-def guess(blob, phi_nm1, phi_n):
+def guess(blob, phi_nm1, phi_n, psi_n):
     """The learned initial guess phi^(0) (mean-corrected)."""
     params, in_scale, out_scale = unpack(blob)
-    x, sigma1 = inputs(phi_nm1, phi_n, in_scale)
+    x, sigma1 = inputs(phi_nm1, phi_n, psi_n, dt_of(blob), in_scale)
     delta, _ = forward(params, x)
     c = out_scale * sigma1 * delta
     c = c - np.mean(c)
     return 2.0 * phi_n - phi_nm1 + c
 
 
-def delta(blob, phi_nm1, phi_n):
+def delta(blob, phi_nm1, phi_n, psi_n):
     params, in_scale, _ = unpack(blob)
-    x, _ = inputs(phi_nm1, phi_n, in_scale)
+    x, _ = inputs(phi_nm1, phi_n, psi_n, dt_of(blob), in_scale)
     return forward(params, x)[0]
 
 
@@ -183,15 +199,16 @@ def target(phi_nm1, phi_n, phi_np1, out_scale):
 
 def loss_and_grad(blob, samples):
     """Mean squared error over every pixel of every sample (phi^{n-1},
-    phi^n, phi^{n+1}) and its gradient with respect to every parameter, in
-    blob order (without the header)."""
+    phi^n, psi^n, phi^{n+1}) and its gradient with respect to every
+    parameter, in blob order (without the header)."""
     params, in_scale, out_scale = unpack(blob)
+    dt = dt_of(blob)
     npix = sum(s[1].size for s in samples)
     grads = {name: np.zeros(shape) for name, shape in layout()}
     loss = 0.0
     L = len(LAYERS)
-    for phi_nm1, phi_n, phi_np1 in samples:
-        x, _ = inputs(phi_nm1, phi_n, in_scale)
+    for phi_nm1, phi_n, psi_n, phi_np1 in samples:
+        x, _ = inputs(phi_nm1, phi_n, psi_n, dt, in_scale)
         d, cache = forward(params, x)
         t = target(phi_nm1, phi_n, phi_np1, out_scale)
         err = d - t

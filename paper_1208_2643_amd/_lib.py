@@ -85,6 +85,7 @@ SIGNATURES = {
     "mpfc_prof_read": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong),
                             ctypes.POINTER(ctypes.c_longlong), _i]),
     "mpfc_destroy": (None, [_vp]),
+    "mpfc_tile_shape": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "mpfc_strerror": (ctypes.c_char_p, [_i]),
     "mpfc_last_error": (ctypes.c_char_p, []),
     "mpfc_version": (_i, []),
@@ -108,9 +109,10 @@ SIGNATURES = {
     "mpfc_cnn_trainer_create": (_i, [ctypes.POINTER(_vp), _i, _i, _i, ctypes.POINTER(ctypes.c_float),
                                      ctypes.c_size_t, ctypes.POINTER(mpfc_cnn_hparams), _vp]),
     "mpfc_cnn_train_step": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
-                                 _i, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(_vp), _i, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_float)]),
-    "mpfc_cnn_predict": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "mpfc_cnn_predict": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                              ctypes.POINTER(_vp)]),
     "mpfc_cnn_trainer_blob": (_i, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
     "mpfc_cnn_trainer_destroy": (None, [_vp]),
     "mpfc_cnn_trainer_set_lr": (_i, [_vp, ctypes.c_float]),

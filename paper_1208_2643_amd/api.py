@@ -134,6 +134,13 @@ class Stepper:
         L.check(self.lib.mpfc_cnn_counts(self.ctx, ctypes.byref(u), ctypes.byref(f)))
         return u.value, f.value
 
+    def tile_shape(self, level: int = 0, which: int = 0):
+        """(tx, ty, halo) of the tiled launch `which` (0 down, 1 up) on `level`."""
+        tx, ty, h = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        L.check(self.lib.mpfc_tile_shape(self.ctx, level, which, ctypes.byref(tx), ctypes.byref(ty),
+                                         ctypes.byref(h)))
+        return tx.value, ty.value, h.value
+
     def energies(self, phi, phi_prev, psi):
         out = (ctypes.c_double * 4)()
         L.check(self.lib.mpfc_energies(self.ctx, _ptr(phi), _ptr(phi_prev), _ptr(psi), out))
@@ -220,7 +227,7 @@ def _ptrs(ts):
 
 class CnnTrainer:
     """GPU trainer of the learned-guess network (mpfc_cnn_*): batches of
-    `batch` samples (phi^{n-1}, phi^n, phi^{n+1}) of an (n, m) grid."""
+    `batch` samples (phi^{n-1}, phi^n, psi^n, phi^{n+1}) of an (n, m) grid."""
 
     def __init__(self, m: int, n: int, batch: int, blob, lr=1e-3, beta1=0.9, beta2=0.999,
                  eps=1e-8, stream=None):
@@ -249,21 +256,22 @@ class CnnTrainer:
         except Exception:
             pass
 
-    def step(self, pm1, p0, pp1, update=True, grad=False):
+    def step(self, pm1, p0, psi, pp1, update=True, grad=False):
         """Loss before the step (and the gradient, float32, blob order)."""
         loss = ctypes.c_double()
         g = np.zeros(self.nparams, dtype=np.float32) if grad else None
         L.check(self.lib.mpfc_cnn_train_step(
-            self.t, _ptrs(pm1), _ptrs(p0), _ptrs(pp1), 1 if update else 0, ctypes.byref(loss),
+            self.t, _ptrs(pm1), _ptrs(p0), _ptrs(psi), _ptrs(pp1), 1 if update else 0,
+            ctypes.byref(loss),
             g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if grad else None))
         return (loss.value, g) if grad else loss.value
 
     def set_lr(self, lr: float):
         L.check(self.lib.mpfc_cnn_trainer_set_lr(self.t, lr))
 
-    def predict(self, pm1, p0):
+    def predict(self, pm1, p0, psi):
         out = [torch.empty_like(t) for t in p0]
-        L.check(self.lib.mpfc_cnn_predict(self.t, _ptrs(pm1), _ptrs(p0), _ptrs(out)))
+        L.check(self.lib.mpfc_cnn_predict(self.t, _ptrs(pm1), _ptrs(p0), _ptrs(psi), _ptrs(out)))
         return out
 
     def blob(self):

@@ -342,13 +342,15 @@ struct BatchImpl : BatchBase {
                     if (k < 0 || k >= kNumShapes) { rc = fail(MPFC_EINVAL, "MPFC_TILE_SHAPE out of range"); break; }
                     if (H <= kShapes[k].hmax) best = k;
                 } else {
+                    float t[kNumShapes];
                     float best_ms = 1e30f;
                     for (int k = 0; k < kNumShapes && !rc; ++k) {
+                        t[k] = 1e30f;
                         if (H > kShapes[k].hmax) continue;
-                        float ms = 0.f;
-                        rc = run_shape(k, true, ms);
-                        if (!rc && ms < best_ms) { best_ms = ms; best = k; }
+                        rc = run_shape(k, true, t[k]);
+                        best_ms = t[k] < best_ms ? t[k] : best_ms;
                     }
+                    if (!rc) best = pick_tuned(t, best_ms, H);
                 }
                 float dummy = 0.f;
                 if (!rc) rc = run_shape(best, false, dummy);

@@ -4,21 +4,24 @@
 //
 // The step's initial guess is free (each step has exactly one solution, Sec. 3
 // unique-solvability theorems), so a predictor may supply it:
-//   x0 = in_scale * phi^n, x1 = (phi^n - phi^{n-1}) / sigma1 (sigma1 = rms of
-//   the difference; x1 = 0 when it vanishes), four 3x3 periodic convolutions
-//   2 -> 32 -> 32 -> 32 -> 1 with tanh-form GELU after the first three, and the
+//   x0 = in_scale * phi^n, x1 = (phi^n - phi^{n-1}) / sigma1 and
+//   x2 = (s psi^n - (phi^n - phi^{n-1})) / sigma1 (sigma1 = rms of the
+//   difference; x1 = x2 = 0 when it vanishes; psi^n enters because the step
+//   depends on it and, for the second-order scheme, it carries the run's
+//   history, eq. discrete_2_b), four 3x3 periodic convolutions
+//   3 -> 32 -> 32 -> 32 -> 1 with tanh-form GELU after the first three, and the
 //   guess 2 phi^n - phi^{n-1} + c with c = out_scale * sigma1 * delta minus its
 //   mean (the guess keeps the mass of the extrapolation).
 //
 // Layouts.  Activations are BF16 (stored as uint16 bit patterns), NHWC with
 // 32 channels: act[(s * NP + p) * 32 + c], p = y * m + x.  Parameters are an
-// FP32 vector in blob order (W1 [3][3][2][32], b1, W2 [3][3][32][32], b2, W3,
+// FP32 vector in blob order (W1 [3][3][3][32], b1, W2 [3][3][32][32], b2, W3,
 // b3, W4 [3][3][32], b4).  A convolution is a GEMM per tap with the output
 // channels as M (two 16-row tiles), 16 pixels of a tile row as N and the input
 // channels as K; its weight operand is kept in registers as per-lane fragments
 // prepared from the FP32 master weights (k_cnn_prepare).  Layer 1 gathers its
-// 18 taps x channels, each input split into a BF16 hi and lo part, into one
-// K = 48 operand (im2col in LDS).
+// 27 taps x channels, each input split into a BF16 hi and lo part, into one
+// K = 64 operand (im2col in LDS).
 //
 // MFMA v_mfma_f32_16x16x16bf16_1k operand layout (lane l, g = l / 16,
 // c = l % 16): A[m = c][k = 4g + i], B[k = 4g + i][n = c], D[m = 4g + i][n = c].
@@ -37,20 +40,23 @@ constexpr int CNN_CH = 32;
 constexpr int CNN_TILE = 16;
 constexpr int CNN_HALO = 18;
 constexpr int CNN_PX = 36;           // LDS stride of one pixel (32 channels + 4 pad)
-constexpr int CNN_NFRAG1 = 6;        // layer 1: K = 48 (3 chunks) x 2 M tiles
+constexpr int CNN_NFRAG1 = 8;        // layer 1: K = 64 (4 chunks) x 2 M tiles
 constexpr int CNN_NFRAG = 36;        // 9 taps x 2 K chunks x 2 M tiles
 // parameter offsets in the FP32 vector (blob order, no header)
-constexpr int CNN_W1 = 0, CNN_B1 = 576, CNN_W2 = 608, CNN_B2 = 9824, CNN_W3 = 9856,
-              CNN_B3 = 19072, CNN_W4 = 19104, CNN_B4 = 19392, CNN_NPARAM = 19393;
-constexpr int CNN_SEG1 = 18 * 32 + 32;   // layer-1 gradient segment (W1, b1)
+constexpr int CNN_CIN = 3;
+constexpr int CNN_W1 = 0, CNN_B1 = 864, CNN_W2 = 896, CNN_B2 = 10112, CNN_W3 = 10144,
+              CNN_B3 = 19360, CNN_W4 = 19392, CNN_B4 = 19680, CNN_NPARAM = 19681;
+constexpr int CNN_K1H = 9 * CNN_CIN;     // layer-1 K of one (hi or lo) part
+constexpr int CNN_SEG1 = CNN_K1H * 32 + 32;  // layer-1 gradient segment (W1, b1)
 constexpr int CNN_SEG = 9 * 32 * 32 + 32;  // layers 2, 3 (W, b)
 constexpr int CNN_SEG4 = 9 * 32 + 1;     // layer 4 (W4, b4)
 
-// Fields of one sample: the guess reads phi^{n-1}, phi^n; training also phi^{n+1};
-// `out` receives the guess (inference).
+// Fields of one sample: the guess reads phi^{n-1}, phi^n, psi^n; training also
+// phi^{n+1}; `out` receives the guess (inference).
 struct CnnSample {
     const double* pm1;
     const double* p0;
+    const double* psi;
     const double* pp1;
     double* out;
 };
@@ -91,35 +97,38 @@ __device__ __forceinline__ void cnn_load_halo(const uint16_t* __restrict__ act, 
 
 // Layer-1 inputs of an 18 x 18 halo tile as BF16 pairs (hi, lo = the BF16
 // rounding of what hi leaves), so that the first layer sees its inputs to about
-// 16 significant bits: xs[c] and xs[2 + c] for x0 = in_scale * phi^n and
-// x1 = (phi^n - phi^{n-1}) * inv_sigma1.
-__device__ __forceinline__ void cnn_load_inputs(const CnnSample& S, double in_scale,
+// 16 significant bits: xs[c] (hi) and xs[3 + c] (lo) for x0 = in_scale * phi^n,
+// x1 = (phi^n - phi^{n-1}) * inv_sigma1, x2 = (s psi^n - (phi^n - phi^{n-1})) *
+// inv_sigma1.
+__device__ __forceinline__ void cnn_load_inputs(const CnnSample& S, double in_scale, double dt,
                                                 double inv_sigma1, int x0, int y0, int m, int n,
                                                 uint16_t (*xs)[CNN_HALO * CNN_HALO]) {
     for (int t = threadIdx.x; t < CNN_HALO * CNN_HALO; t += blockDim.x) {
         const int ty = t / CNN_HALO, tx = t - ty * CNN_HALO;
         const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (m - 1);
         const size_t q = (size_t)gy * m + gx;
-        const double v0 = S.p0[q], v1 = S.pm1[q];
-        const float a = (float)(in_scale * v0), b = (float)((v0 - v1) * inv_sigma1);
-        const uint16_t ah = bf16_bits(a), bh = bf16_bits(b);
-        xs[0][t] = ah;
-        xs[1][t] = bh;
-        xs[2][t] = bf16_bits(a - bf16_val(ah));
-        xs[3][t] = bf16_bits(b - bf16_val(bh));
+        const double v0 = S.p0[q], d1 = v0 - S.pm1[q];
+        const float x[3] = {(float)(in_scale * v0), (float)(d1 * inv_sigma1),
+                            (float)((dt * S.psi[q] - d1) * inv_sigma1)};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const uint16_t hi = bf16_bits(x[c]);
+            xs[c][t] = hi;
+            xs[3 + c][t] = bf16_bits(x[c] - bf16_val(hi));
+        }
     }
 }
 
-// im2col value k of tile pixel (ty, tx): k = part * 18 + tap * 2 + channel for
-// the hi (part 0) and lo (part 1) inputs, 0 for k >= 36.
-constexpr int CNN_K1 = 48;        // layer-1 K (36 used), 3 chunks of 16
-constexpr int CNN_PX1 = 52;       // LDS stride of one im2col pixel
+// im2col value k of tile pixel (ty, tx): k = part * 27 + tap * 3 + channel for
+// the hi (part 0) and lo (part 1) inputs, 0 for k >= 54.
+constexpr int CNN_K1 = 64;        // layer-1 K (54 used), 4 chunks of 16
+constexpr int CNN_PX1 = 68;       // LDS stride of one im2col pixel
 __device__ __forceinline__ uint16_t cnn_im2col(const uint16_t (*xs)[CNN_HALO * CNN_HALO], int k,
                                                int ty, int tx) {
-    if (k >= 36) return 0;
-    const int part = k >= 18 ? 1 : 0, kk = k - 18 * part;
-    const int tap = kk >> 1, ky = tap / 3, kx = tap - 3 * ky;
-    return xs[2 * part + (kk & 1)][(ty + ky) * CNN_HALO + tx + kx];
+    if (k >= 2 * CNN_K1H) return 0;
+    const int part = k >= CNN_K1H ? 1 : 0, kk = k - CNN_K1H * part;
+    const int tap = kk / 3, c = kk - 3 * tap, ky = tap / 3, kx = tap - 3 * ky;
+    return xs[3 * part + c][(ty + ky) * CNN_HALO + tx + kx];
 }
 
 struct CnnConvArgs {
@@ -127,7 +136,7 @@ struct CnnConvArgs {
     const uint16_t* in;        // NHWC input (layers 2, 3 forward; backward data)
     const CnnSample* smp;      // layer 1: fields of every sample
     const double* sc;          // per sample: inv_sigma1, sigma_out, inv_sigma_out, 0
-    double in_scale;
+    double in_scale, dt;
     const uint16_t* wfrag;     // weight fragments
     const float* bias;         // forward
     uint16_t* out;             // NHWC output
@@ -147,7 +156,7 @@ __global__ void __launch_bounds__(256) k_cnn_conv(CnnConvArgs A) {
     constexpr int NFR = IM2COL ? CNN_NFRAG1 : CNN_NFRAG;
     constexpr int LDS_N = IM2COL ? CNN_TILE * CNN_TILE * CNN_PX1 : CNN_HALO * CNN_HALO * CNN_PX;
     __shared__ __align__(16) uint16_t lds[LDS_N];
-    __shared__ uint16_t xs[IM2COL ? 4 : 1][IM2COL ? CNN_HALO * CNN_HALO : 1];
+    __shared__ uint16_t xs[IM2COL ? 6 : 1][IM2COL ? CNN_HALO * CNN_HALO : 1];
     const int m = A.m, n = A.n;
     const size_t NP = (size_t)m * n;
     const int s = blockIdx.z;
@@ -159,7 +168,7 @@ __global__ void __launch_bounds__(256) k_cnn_conv(CnnConvArgs A) {
     for (int f = 0; f < NFR; ++f) af[f] = *(const cnn_v4s*)(A.wfrag + ((size_t)f * 64 + lane) * 4);
     if constexpr (IM2COL) {
         const CnnSample S = A.smp[s];
-        cnn_load_inputs(S, A.in_scale, A.sc[4 * s + 0], x0, y0, m, n, xs);
+        cnn_load_inputs(S, A.in_scale, A.dt, A.sc[4 * s + 0], x0, y0, m, n, xs);
         __syncthreads();
         {
             const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
@@ -179,7 +188,7 @@ __global__ void __launch_bounds__(256) k_cnn_conv(CnnConvArgs A) {
         const int row = wave * 4 + r;
         if constexpr (IM2COL) {
 #pragma unroll
-            for (int kc = 0; kc < 3; ++kc) {
+            for (int kc = 0; kc < CNN_K1 / 16; ++kc) {
                 const cnn_v4s b = *(const cnn_v4s*)(lds + (row * CNN_TILE + c16) * CNN_PX1 + kc * 16 + 4 * g);
 #pragma unroll
                 for (int mt = 0; mt < 2; ++mt)
@@ -387,7 +396,7 @@ struct CnnWgradArgs {
     const uint16_t* in;        // a_{L-1} (layers 2, 3)
     const CnnSample* smp;      // layer 1
     const double* sc;
-    double in_scale;
+    double in_scale, dt;
     const uint16_t* dz;        // d loss / d z_L
     float* part;               // [block][segment]
 };
@@ -405,7 +414,7 @@ __global__ void __launch_bounds__(256) k_cnn_wgrad(CnnWgradArgs A) {
     constexpr int SEG = IM2COL ? CNN_SEG1 : CNN_SEG;
     __shared__ __align__(16) uint16_t la[32 * AR * RS];
     __shared__ __align__(16) uint16_t lb[32 * CNN_TILE * RS];
-    __shared__ uint16_t xs[IM2COL ? 4 : 1][IM2COL ? CNN_HALO * CNN_HALO : 1];
+    __shared__ uint16_t xs[IM2COL ? 6 : 1][IM2COL ? CNN_HALO * CNN_HALO : 1];
     const int m = A.m, n = A.n;
     const size_t NP = (size_t)m * n;
     const int tx_n = m / CNN_TILE, ty_n = n / CNN_TILE;
@@ -423,12 +432,12 @@ __global__ void __launch_bounds__(256) k_cnn_wgrad(CnnWgradArgs A) {
         const int x0 = bx * CNN_TILE, y0 = by * CNN_TILE;
         __syncthreads();  // previous tile's LDS reads are done
         if constexpr (IM2COL) {
-            cnn_load_inputs(A.smp[s], A.in_scale, A.sc[4 * s + 0], x0, y0, m, n, xs);
+            cnn_load_inputs(A.smp[s], A.in_scale, A.dt, A.sc[4 * s + 0], x0, y0, m, n, xs);
             __syncthreads();
             const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
-            // the weight gradient takes the hi parts of the inputs (rows k < 18)
+            // the weight gradient takes the hi parts of the inputs (rows k < 27)
             for (int k = 0; k < 32; ++k)
-                la[(k * CNN_TILE + ty) * RS + tx] = k < 18 ? cnn_im2col(xs, k, ty, tx) : (uint16_t)0;
+                la[(k * CNN_TILE + ty) * RS + tx] = k < CNN_K1H ? cnn_im2col(xs, k, ty, tx) : (uint16_t)0;
         } else {
             for (int c = threadIdx.x; c < CNN_HALO * CNN_HALO * 4; c += 256) {
                 const int pi = c >> 2, part = c & 3;
@@ -488,7 +497,7 @@ __global__ void __launch_bounds__(256) k_cnn_wgrad(CnnWgradArgs A) {
         for (int i = 0; i < 4; ++i) {
             const int ci = mt * 16 + 4 * g + i;
             if constexpr (IM2COL) {
-                if (ci < 18) out[ci * CNN_CH + co] = acc[j][i];
+                if (ci < CNN_K1H) out[ci * CNN_CH + co] = acc[j][i];
             } else {
                 out[(tap * CNN_CH + ci) * CNN_CH + co] = acc[j][i];
             }
@@ -575,8 +584,8 @@ __global__ void __launch_bounds__(256) k_cnn_adam(float* theta, const float* __r
 }
 
 // Per-lane weight fragments (BF16) from the FP32 parameters:
-//   f1: layer 1, [kc][mt][lane][4], A[co][k] = W1[tap][c][co] for k = part * 18 + tap * 2 + c
-//       (the same weight for the hi and lo part of an input; 0 for k >= 36);
+//   f1: layer 1, [kc][mt][lane][4], A[co][k] = W1[tap][c][co] for k = part * 27 + tap * 3 + c
+//       (the same weight for the hi and lo part of an input; 0 for k >= 54);
 //   f2, f3: layers 2, 3 forward, [tap][kc][mt][lane][4], A[co][ci] = W[tap][ci][co];
 //   r2, r3: backward data, A[co'][ci'] = W[8 - tap][co'][ci'] (flipped taps, swapped channels);
 //   w4: output-layer weights rounded to BF16 (as floats).
@@ -596,7 +605,7 @@ __global__ void __launch_bounds__(256) k_cnn_prepare(const float* __restrict__ t
         const int f = e >> 8, lane = (e >> 2) & 63, i = e & 3;
         const int kc = f >> 1, mt = f & 1;
         const int co = mt * 16 + (lane & 15), k = kc * 16 + 4 * (lane >> 4) + i;
-        F.f1[e] = k < 36 ? bf16_bits(th[CNN_W1 + (k % 18) * CNN_CH + co]) : (uint16_t)0;
+        F.f1[e] = k < 2 * CNN_K1H ? bf16_bits(th[CNN_W1 + (k % CNN_K1H) * CNN_CH + co]) : (uint16_t)0;
         return;
     }
     int r = e - N1;

@@ -14,10 +14,10 @@ constexpr int CNN_BLOB = CNN_BLOB_HEADER + CNN_NPARAM;
 int cnn_check_blob(const float* blob, size_t count) {
     if (!blob) return fail(MPFC_EINVAL, "network blob is NULL");
     if (count != (size_t)CNN_BLOB) return fail(MPFC_EINVAL, "network blob has the wrong size");
-    if ((int)blob[0] != 1 || (int)blob[1] != 2 || (int)blob[2] != CNN_CH || (int)blob[3] != 4)
-        return fail(MPFC_EINVAL, "network blob header does not match (version 1, 2-32-32-32-1)");
-    if (!std::isfinite(blob[4]) || !std::isfinite(blob[5]))
-        return fail(MPFC_EINVAL, "network blob scales are not finite");
+    if ((int)blob[0] != 2 || (int)blob[1] != CNN_CIN || (int)blob[2] != CNN_CH || (int)blob[3] != 4)
+        return fail(MPFC_EINVAL, "network blob header does not match (version 2, 3-32-32-32-1)");
+    if (!std::isfinite(blob[4]) || !std::isfinite(blob[5]) || !(blob[6] > 0))
+        return fail(MPFC_EINVAL, "network blob scales or time step are not valid");
     return MPFC_OK;
 }
 
@@ -33,7 +33,7 @@ struct CnnNet {
     int m = 0, n = 0, B = 0;
     size_t NP = 0;
     bool train = false;
-    double in_scale = 1, out_scale = 1;
+    double in_scale = 1, out_scale = 1, dt = 0;
     std::vector<void*> allocs;
     float* theta = nullptr;
     float *grad = nullptr, *mom = nullptr, *vel = nullptr;
@@ -122,6 +122,7 @@ struct CnnNet {
     int load(const float* blob, hipStream_t s) {
         in_scale = blob[4];
         out_scale = blob[5];
+        dt = blob[6];
         HIP_TRY(hipMemcpyAsync(theta, blob + CNN_BLOB_HEADER, CNN_NPARAM * sizeof(float),
                                hipMemcpyHostToDevice, s));
         prepare(s);
@@ -145,7 +146,7 @@ struct CnnNet {
         hipLaunchKernelGGL(k_cnn_scales, dim3((B + 63) / 64), dim3(64), 0, s, sums, B,
                            (double)NP, out_scale, sc);
         CnnConvArgs c{};
-        c.m = m; c.n = n; c.smp = d_smp; c.sc = sc; c.in_scale = in_scale;
+        c.m = m; c.n = n; c.smp = d_smp; c.sc = sc; c.in_scale = in_scale; c.dt = dt;
         c.wfrag = fr.f1; c.bias = theta + CNN_B1; c.out = a[1]; c.zout = training ? z[1] : nullptr;
         hipLaunchKernelGGL((k_cnn_conv<true, CNN_FWD>), tg, blk, 0, s, c);
         c.in = a[1]; c.wfrag = fr.f2; c.bias = theta + CNN_B2; c.out = a[2];
@@ -184,6 +185,7 @@ struct CnnNet {
         reduce(CNN_SEG4, CNN_W4, s);
         CnnWgradArgs wg{};
         wg.m = m; wg.n = n; wg.samples = B; wg.smp = d_smp; wg.sc = sc; wg.in_scale = in_scale;
+        wg.dt = dt;
         wg.part = wpart;
         wg.in = a[2]; wg.dz = dz[0];
         hipLaunchKernelGGL((k_cnn_wgrad<false>), dim3(nblk_w), blk, 0, s, wg);
@@ -227,12 +229,13 @@ namespace {
 // Learned guess of one step into copy 1 of the finest level, its completion
 // and FP64 residual (r2[0]); then, after the extrapolated guess is in copy 0,
 // cnn_choose compares with its residual (r2[1]) and keeps the smaller.
-int cnn_candidate(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, hipStream_t s) {
+int cnn_candidate(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const double* psi,
+                  hipStream_t s) {
     Level& F0 = C->L[0];
     const Grid g0 = F0.g;
     const double ih2 = 1.0 / (F0.h * F0.h);
     CnnNet& N = *C->cnn;
-    N.h_smp[0] = CnnSample{phi_nm1, phi_n, nullptr, F0.u[1][0]};
+    N.h_smp[0] = CnnSample{phi_nm1, phi_n, psi, nullptr, F0.u[1][0]};
     int rc = N.set_samples(s);
     if (rc) return rc;
     N.forward(s, false);
@@ -287,6 +290,8 @@ int mpfc_cnn_load(mpfc_ctx* C, const float* blob, size_t count) {
     int rc = cnn_check_blob(blob, count);
     if (!rc) rc = cnn_check_grid(C->m, C->n);
     if (rc) return rc;
+    if (std::fabs(blob[6] - C->p.dt) > 1e-6 * C->p.dt)
+        return fail(MPFC_EINVAL, "the network was trained for another time step");
     if (!C->cnn) {
         CnnNet* N = new (std::nothrow) CnnNet();
         if (!N) return fail(MPFC_ENOMEM, "host allocation failed");
@@ -346,23 +351,26 @@ void mpfc_cnn_trainer_destroy(mpfc_cnn_trainer* T) {
 }
 
 static int cnn_fill_samples(CnnNet& N, const double* const* pm1, const double* const* p0,
-                            const double* const* pp1, double* const* out) {
-    if (!pm1 || !p0) return fail(MPFC_EINVAL, "phi^{n-1} and phi^n are required");
+                            const double* const* psi, const double* const* pp1,
+                            double* const* out) {
+    if (!pm1 || !p0 || !psi) return fail(MPFC_EINVAL, "phi^{n-1}, phi^n and psi^n are required");
     for (int s = 0; s < N.B; ++s) {
-        if (!pm1[s] || !p0[s] || (pp1 && !pp1[s]) || (out && !out[s]))
+        if (!pm1[s] || !p0[s] || !psi[s] || (pp1 && !pp1[s]) || (out && !out[s]))
             return fail(MPFC_EINVAL, "NULL sample buffer");
-        N.h_smp[s] = CnnSample{pm1[s], p0[s], pp1 ? pp1[s] : nullptr, out ? out[s] : nullptr};
+        N.h_smp[s] = CnnSample{pm1[s], p0[s], psi[s], pp1 ? pp1[s] : nullptr,
+                               out ? out[s] : nullptr};
     }
     return MPFC_OK;
 }
 
 int mpfc_cnn_train_step(mpfc_cnn_trainer* T, const double* const* d_phi_nm1,
-                        const double* const* d_phi_n, const double* const* d_phi_np1, int update,
-                        double* h_loss, float* h_grad) {
+                        const double* const* d_phi_n, const double* const* d_psi_n,
+                        const double* const* d_phi_np1, int update, double* h_loss,
+                        float* h_grad) {
     if (!T) return fail(MPFC_EINVAL, "trainer is NULL");
     if (!d_phi_np1) return fail(MPFC_EINVAL, "phi^{n+1} is required");
     CnnNet& N = T->net;
-    int rc = cnn_fill_samples(N, d_phi_nm1, d_phi_n, d_phi_np1, nullptr);
+    int rc = cnn_fill_samples(N, d_phi_nm1, d_phi_n, d_psi_n, d_phi_np1, nullptr);
     if (!rc) rc = N.set_samples(T->stream);
     if (rc) return rc;
     N.forward(T->stream, true);
@@ -382,11 +390,12 @@ int mpfc_cnn_train_step(mpfc_cnn_trainer* T, const double* const* d_phi_nm1,
 }
 
 int mpfc_cnn_predict(mpfc_cnn_trainer* T, const double* const* d_phi_nm1,
-                     const double* const* d_phi_n, double* const* d_guess) {
+                     const double* const* d_phi_n, const double* const* d_psi_n,
+                     double* const* d_guess) {
     if (!T) return fail(MPFC_EINVAL, "trainer is NULL");
     if (!d_guess) return fail(MPFC_EINVAL, "outputs are required");
     CnnNet& N = T->net;
-    int rc = cnn_fill_samples(N, d_phi_nm1, d_phi_n, nullptr, d_guess);
+    int rc = cnn_fill_samples(N, d_phi_nm1, d_phi_n, d_psi_n, nullptr, d_guess);
     if (!rc) rc = N.set_samples(T->stream);
     if (rc) return rc;
     N.forward(T->stream, false);
@@ -404,8 +413,9 @@ int mpfc_cnn_trainer_set_lr(mpfc_cnn_trainer* T, float lr) {
 int mpfc_cnn_trainer_blob(mpfc_cnn_trainer* T, float* blob, size_t count) {
     if (!T || !blob) return fail(MPFC_EINVAL, "trainer and blob are required");
     if (count != (size_t)CNN_BLOB) return fail(MPFC_EINVAL, "blob has the wrong size");
-    const float hdr[CNN_BLOB_HEADER] = {1.f, 2.f, (float)CNN_CH, 4.f, (float)T->net.in_scale,
-                                        (float)T->net.out_scale, 0.f, 0.f};
+    const float hdr[CNN_BLOB_HEADER] = {2.f, (float)CNN_CIN, (float)CNN_CH, 4.f,
+                                        (float)T->net.in_scale, (float)T->net.out_scale,
+                                        (float)T->net.dt, 0.f};
     std::memcpy(blob, hdr, sizeof hdr);
     HIP_TRY(hipMemcpyAsync(blob + CNN_BLOB_HEADER, T->net.theta, CNN_NPARAM * sizeof(float),
                            hipMemcpyDeviceToHost, T->stream));

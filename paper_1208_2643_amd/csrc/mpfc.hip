@@ -208,6 +208,14 @@ int pick_shape(int H) {
     return kNumShapes - 1;
 }
 
+// Tuned choice from the measured times: the first shape (in table order)
+// within 5 % of the fastest, so that near-ties do not flip between runs.
+int pick_tuned(const float* t, float best, int H) {
+    for (int k = 0; k < kNumShapes; ++k)
+        if (H <= kShapes[k].hmax && t[k] <= 1.05f * best) return k;
+    return pick_shape(H);
+}
+
 int level_shape(const Level& lv, int kind, int H) {
     const int k = lv.shape[kind];
     return (k >= 0 && H <= kShapes[k].hmax) ? k : pick_shape(H);
@@ -673,10 +681,11 @@ int tune_one(mpfc_ctx* C, Level& lv, int kind, int H, Fn&& launch) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    float t[kNumShapes];
     float best = 1e30f;
-    int best_k = pick_shape(H);
     const int reps = 3;
     for (int k = 0; k < kNumShapes; ++k) {
+        t[k] = 1e30f;
         if (H > kShapes[k].hmax) continue;
         lv.shape[kind] = k;
         launch();
@@ -684,11 +693,10 @@ int tune_one(mpfc_ctx* C, Level& lv, int kind, int H, Fn&& launch) {
         for (int r = 0; r < reps; ++r) launch();
         HIP_TRY(hipEventRecord(e1, s));
         HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) { best = ms; best_k = k; }
+        HIP_TRY(hipEventElapsedTime(&t[k], e0, e1));
+        best = t[k] < best ? t[k] : best;
     }
-    lv.shape[kind] = best_k;
+    lv.shape[kind] = pick_tuned(t, best, H);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return MPFC_OK;
@@ -898,7 +906,8 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
     return MPFC_OK;
 }
 
-int cnn_candidate(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, hipStream_t s);
+int cnn_candidate(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const double* psi,
+                  hipStream_t s);
 void residual_sq(mpfc_ctx* C, int k, double* out, hipStream_t s);
 void cnn_choose(mpfc_ctx* C, hipStream_t s);
 
@@ -929,7 +938,7 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
     hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->st);
     const bool learned = C->o.guess == MPFC_GUESS_CNN;
     if (learned) {
-        int rc = cnn_candidate(C, phi_n, phi_nm1, s);
+        int rc = cnn_candidate(C, phi_n, phi_nm1, psi, s);
         if (rc) return rc;
         residual_sq(C, 1, C->cnn_r2, s);
     }
@@ -1023,6 +1032,24 @@ int mpfc_prof_enable(mpfc_ctx* C, int what) {
     if (what && !C->ev[0])
         for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&C->ev[k]));
     C->prof = what;
+    return MPFC_OK;
+}
+
+int mpfc_tile_shape(mpfc_ctx* C, int level, int which, int* tx, int* ty, int* halo) {
+    if (!C) return fail(MPFC_EINVAL, "ctx is NULL");
+    if (level < 0 || level >= C->Lp || which < 0 || which >= SH_KINDS)
+        return fail(MPFC_EINVAL, "no tiled launch of that level and kind");
+    const Level& lv = C->L[level];
+    const int H = which == SH_DN || which == SH_DN32 ? round_even(2 * C->o.nu1 + 1)
+                  : which == SH_UP ? (level == 0 ? round_even(2 * C->o.nu2 + 1) : 2 * C->o.nu2)
+                  : which == SH_UP32 ? 2 * C->o.nu2
+                  : which == SH_PDN ? 6 : (level == 0 ? 6 : 4);
+    const int k = level_shape(lv, which, H);
+    int x = 0, y = 0;
+    tile_dims(lv, k, x, y);
+    if (tx) *tx = x;
+    if (ty) *ty = y;
+    if (halo) *halo = kShapes[k].hmax;
     return MPFC_OK;
 }
 

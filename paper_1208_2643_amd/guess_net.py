@@ -2,8 +2,8 @@
 weights, files).
 
 The blob is the float32 vector documented with mpfc_cnn_load in
-include/mpfc.h: 8 header values [1, 2, 32, 4, in_scale, out_scale, 0, 0],
-then W1 (3,3,2,32), b1 (32), W2 (3,3,32,32), b2, W3 (3,3,32,32), b3,
+include/mpfc.h: 8 header values [2, 3, 32, 4, in_scale, out_scale, dt, 0],
+then W1 (3,3,3,32), b1 (32), W2 (3,3,32,32), b2, W3 (3,3,32,32), b3,
 W4 (3,3,32,1), b4 (1), weights ordered [ky][kx][ci][co].  The arithmetic of
 the network runs in the library's kernels only.
 """
@@ -15,19 +15,19 @@ import os
 
 import numpy as np
 
-LAYERS = ((2, 32), (32, 32), (32, 32), (32, 1))
+LAYERS = ((3, 32), (32, 32), (32, 32), (32, 1))
 HEADER = 8
 N_PARAMS = sum(9 * ci * co + co for ci, co in LAYERS)
 WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
 DEFAULT_WEIGHTS = os.path.join(WEIGHTS_DIR, "guess_cnn_scheme2.f32")
 
 
-def initial_blob(seed: int, in_scale: float = 2.0, out_scale: float = 1.0) -> np.ndarray:
+def initial_blob(seed: int, dt: float, in_scale: float = 2.0, out_scale: float = 1.0) -> np.ndarray:
     """He-normal hidden weights (std sqrt(2 / fan_in)) from a seeded generator,
     zero biases and a zero output layer: the untrained network's guess is the
     extrapolated one."""
     rng = np.random.default_rng(seed)
-    parts = [np.array([1, 2, 32, 4, in_scale, out_scale, 0, 0], dtype=np.float32)]
+    parts = [np.array([2, 3, 32, 4, in_scale, out_scale, dt, 0], dtype=np.float32)]
     for k, (ci, co) in enumerate(LAYERS):
         if k == len(LAYERS) - 1:
             w = np.zeros(9 * ci * co)

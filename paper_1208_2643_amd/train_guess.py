@@ -8,7 +8,7 @@
    crystallites of radius 20 h (seeds 100, 101, ...; the benchmark's
    evaluation uses seed 5), `--steps` steps each, all advanced together by the
    batched solver in FP64 to residual 1e-10.  Every state stays on the GPU;
-   a training sample is a triple (phi^{n-1}, phi^n, phi^{n+1}) of one run.
+   a training sample is (phi^{n-1}, phi^n, psi^n, phi^{n+1}) of one run.
    The last `--holdout` runs are kept for validation.
 2. Scale: out_scale is set so that the target (phi^{n+1} - 2 phi^n +
    phi^{n-1}) / (out_scale sigma1) has unit mean square over the data (the
@@ -52,41 +52,44 @@ def log(msg):
 
 
 def generate(args, torch, api, inputs, dev):
-    """States of every run: tensor (runs, steps + 1, n, m) on the GPU."""
+    """States phi and psi of every run: tensors (runs, steps + 1, n, m) on the GPU
+    (psi[r, k] = psi^k, the input of step k)."""
     N = args.grid
     h = math.pi / 4
     params = api.Params(eps=0.025, beta=0.9, M=1.0, h=h, dt=0.05, scheme=2)
     R = args.trajectories
     store = torch.empty((R, args.steps + 1, N, N), dtype=torch.float64, device=dev)
+    pstore = torch.zeros((R, args.steps + 1, N, N), dtype=torch.float64, device=dev)
     for r in range(R):
         store[r, 0] = torch.from_numpy(inputs.crystallites(N, N, h, seed=100 + r)).to(dev)
     b = api.Batch([(N, N, params)] * R, tol=1e-10, precision=0)
-    psi = [torch.zeros((N, N), dtype=torch.float64, device=dev) for _ in range(R)]
     cycles = 0
     t0 = time.perf_counter()
     for k in range(args.steps):
         prev = [store[r, max(k - 1, 0)] for r in range(R)]
-        infos = b.step([store[r, k] for r in range(R)], prev, psi,
+        pstore[:, k + 1].copy_(pstore[:, k])
+        infos = b.step([store[r, k] for r in range(R)], prev, [pstore[r, k + 1] for r in range(R)],
                        [store[r, k + 1] for r in range(R)], history=False)
         cycles += sum(i.n_cycles for i in infos)
         if (k + 1) % 250 == 0:
             log(f"data: {k + 1}/{args.steps} steps ({time.perf_counter() - t0:.1f} s)")
     b.close()
     torch.cuda.synchronize()
-    return store, cycles / (R * args.steps)
+    return store, pstore, cycles / (R * args.steps)
 
 
-def batches(store, runs, steps, batch, rng):
-    """Random triples (run, n) with 1 <= n < steps (phi^{n-1} != phi^n)."""
+def batches(data, runs, steps, batch, rng):
+    """Random samples (run, n) with 1 <= n < steps (phi^{n-1} != phi^n)."""
+    store, pstore = data
     rr = rng.choice(runs, size=batch)
     nn = rng.integers(1, steps, size=batch)
     return ([store[r, n - 1] for r, n in zip(rr, nn)], [store[r, n] for r, n in zip(rr, nn)],
-            [store[r, n + 1] for r, n in zip(rr, nn)])
+            [pstore[r, n] for r, n in zip(rr, nn)], [store[r, n + 1] for r, n in zip(rr, nn)])
 
 
-def mean_loss(tr, store, runs, steps, batch, count, seed):
+def mean_loss(tr, data, runs, steps, batch, count, seed):
     rng = np.random.default_rng(seed)
-    return float(np.mean([tr.step(*batches(store, runs, steps, batch, rng), update=False)
+    return float(np.mean([tr.step(*batches(data, runs, steps, batch, rng), update=False)
                           for _ in range(count)]))
 
 
@@ -96,7 +99,8 @@ def main(argv=None):
     from . import api, guess_net, inputs
     dev = torch.device("cuda:0")
     t_start = time.perf_counter()
-    store, cyc = generate(args, torch, api, inputs, dev)
+    store, pstore, cyc = generate(args, torch, api, inputs, dev)
+    data = (store, pstore)
     t_data = time.perf_counter() - t_start
     N = args.grid
     train_runs = np.arange(args.trajectories - args.holdout)
@@ -104,9 +108,9 @@ def main(argv=None):
     log(f"data: {args.trajectories} runs x {args.steps} steps of {N}^2 in {t_data:.1f} s, "
         f"{cyc:.2f} V-cycles per step")
 
-    blob = guess_net.initial_blob(args.seed, out_scale=1.0)
+    blob = guess_net.initial_blob(args.seed, 0.05, out_scale=1.0)
     tr = api.CnnTrainer(N, N, args.batch, blob, lr=args.lr)
-    ms = mean_loss(tr, store, train_runs, args.steps, args.batch, 16, args.seed + 1)
+    ms = mean_loss(tr, data, train_runs, args.steps, args.batch, 16, args.seed + 1)
     tr.close()
     out_scale = math.sqrt(ms)
     blob = guess_net.with_out_scale(blob, out_scale)
@@ -120,7 +124,7 @@ def main(argv=None):
     for it in range(args.iters):
         lr = args.lr * (0.01 + 0.99 * 0.5 * (1 + math.cos(math.pi * it / args.iters)))
         tr.set_lr(lr)
-        loss = tr.step(*batches(store, train_runs, args.steps, args.batch, rng))
+        loss = tr.step(*batches(data, train_runs, args.steps, args.batch, rng))
         if not math.isfinite(loss):
             raise RuntimeError(f"training diverged at iteration {it}")
         run_loss += loss
@@ -130,12 +134,12 @@ def main(argv=None):
                 f"{time.perf_counter() - t0:.1f} s)")
             run_loss = 0.0
     t_train = time.perf_counter() - t0
-    val = mean_loss(tr, store, val_runs, args.steps, args.batch, 32, args.seed + 3)
+    val = mean_loss(tr, data, val_runs, args.steps, args.batch, 32, args.seed + 3)
     trained = tr.blob()
     tr.close()
     log(f"validation loss {val:.4f} (extrapolation = 1)")
     meta = {
-        "network": "4 x conv3x3 (2-32-32-32-1), tanh-GELU, circular padding, BF16/FP32",
+        "network": "4 x conv3x3 (3-32-32-32-1), tanh-GELU, circular padding, BF16/FP32",
         "data": {"grid": N, "runs": args.trajectories, "holdout": args.holdout,
                  "steps": args.steps, "seeds": [100, 100 + args.trajectories - 1],
                  "params": "scheme 2, h=pi/4, eps=0.025, beta=0.9, M=1, dt=0.05, "

@@ -58,14 +58,16 @@ def test_gelu_grad_finite_difference():
     assert np.max(np.abs(N.gelu_grad(x) - fd)) < 1e-8
 
 
-def samples(n, m, count, seed):
+def samples(n, m, count, seed, dt=0.05):
+    """(phi^{n-1}, phi^n, psi^n, phi^{n+1}) with psi^n near the difference quotient."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
         a = 0.1 + 0.1 * rng.standard_normal((n, m))
         b = a + 0.01 * rng.standard_normal((n, m))
+        p = (b - a) / dt + 0.05 * rng.standard_normal((n, m))
         c = b + (b - a) + 0.002 * rng.standard_normal((n, m))
-        out.append((a, b, c))
+        out.append((a, b, p, c))
     return out
 
 
@@ -111,30 +113,42 @@ def test_adam_closed_form():
 
 
 def test_guess_keeps_mass_and_reduces_to_extrapolation():
-    a, b, _ = samples(8, 8, 1, 9)[0]
+    a, b, p, _ = samples(8, 8, 1, 9)[0]
     blob = N.init_blob(10, zero_last=False)
-    g = N.guess(blob, a, b)
+    g = N.guess(blob, a, b, p)
     # the mean of the extrapolation (= mean phi^n for solver data, which conserve it)
     assert abs(np.mean(g) - np.mean(2 * b - a)) < 1e-15
     zero = N.init_blob(10, zero_last=True)
-    assert np.array_equal(N.guess(zero, a, b), 2 * b - a)
+    assert np.array_equal(N.guess(zero, a, b, p), 2 * b - a)
     # no motion at all: the guess is phi^n whatever the weights
-    assert np.allclose(N.guess(blob, b, b), b, atol=1e-15, rtol=0)
+    assert np.allclose(N.guess(blob, b, b, p), b, atol=1e-15, rtol=0)
+
+
+def test_psi_input_is_the_velocity_mismatch():
+    """x2 vanishes when psi^n equals the difference quotient (always so for the
+    first-order scheme, eq. discrete_1_b), so psi then has no influence."""
+    a, b, p, _ = samples(8, 8, 1, 13)[0]
+    x, _ = N.inputs(a, b, (b - a) / 0.05, 0.05, 2.0)
+    assert np.max(np.abs(x[..., 2])) < 1e-12
+    x, _ = N.inputs(a, b, p, 0.05, 2.0)
+    assert np.max(np.abs(x[..., 2])) > 0.01
 
 
 def test_guess_is_translation_equivariant():
-    a, b, _ = samples(8, 16, 1, 11)[0]
+    a, b, p, _ = samples(8, 16, 1, 11)[0]
     blob = N.init_blob(12, zero_last=False)
-    g = N.guess(blob, a, b)
-    gs = N.guess(blob, np.roll(a, (3, 5), (0, 1)), np.roll(b, (3, 5), (0, 1)))
-    assert np.max(np.abs(np.roll(g, (3, 5), (0, 1)) - gs)) < 1e-13
+    g = N.guess(blob, a, b, p)
+    r = lambda f: np.roll(f, (3, 5), (0, 1))  # noqa: E731
+    gs = N.guess(blob, r(a), r(b), r(p))
+    assert np.max(np.abs(r(g) - gs)) < 1e-13
 
 
 def test_blob_layout():
-    assert N.n_params() == 19393
-    blob = N.init_blob(1)
+    assert N.n_params() == 19681
+    blob = N.init_blob(1, dt=0.05)
     p, s_in, s_out = N.unpack(blob)
     assert (s_in, s_out) == (2.0, 1.0)
-    assert np.array_equal(N.pack(p, s_in, s_out), blob)
+    assert abs(N.dt_of(blob) - 0.05) < 1e-8
+    assert np.array_equal(N.pack(p, s_in, s_out, N.dt_of(blob)), blob)
     with pytest.raises(ValueError):
         N.unpack(blob[:-1])
