@@ -195,61 +195,4 @@ __global__ void __launch_bounds__(256) k_b_psi(const BSim* __restrict__ sims,
 
 #undef BATCH_CELLS
 
-// ---------------------------------------------------------------------------
-// Pyramid of 2x2 averages: from a field on level L, the fields on up to
-// PYR_LEVELS coarser levels, each value the average of the four finer ones
-// in the same order of additions as k_restrict (so the results are those of
-// repeated k_restrict launches).  A workgroup reduces a block of at most
-// 32 x 32 cells in LDS; grids with more levels take a second pass from the
-// level this one ends on.
-constexpr int PYR_LEVELS = 5;
-
-template <typename T>
-struct BPyr {
-    const T* src;               // level L field
-    T* dst[PYR_LEVELS];         // levels L + 1 ... L + nlev
-    Grid g;                     // level L grid
-    int nlev;                   // levels produced (1 ... PYR_LEVELS)
-    int bx, by;                 // block of level L cells (min(m, 32) x min(n, 32))
-    int nbx;                    // blocks in x
-    const CycleState* stop;     // skip when set (nullptr: always run)
-};
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_b_pyramid(const BPyr<T>* __restrict__ args,
-                                                   const BatchItem* __restrict__ items) {
-    const BatchItem it = items[blockIdx.x];
-    const BPyr<T>& P = args[it.arg];
-    if (stopped(P.stop)) return;
-    __shared__ T buf[2][32 * 32];
-    const int t = threadIdx.x;
-    const int byi = it.tile / P.nbx, bxi = it.tile - byi * P.nbx;
-    int bx = P.bx, by = P.by;
-    const int x0 = bxi * bx, y0 = byi * by;
-    for (int k = t; k < bx * by; k += 256) {
-        const int x = k % bx, y = k / bx;
-        buf[0][k] = P.src[(size_t)(y0 + y) * P.g.m + (x0 + x)];
-    }
-    __syncthreads();
-    int m = P.g.m;
-    int cur = 0;
-    for (int lev = 0; lev < P.nlev; ++lev) {
-        const int cx = bx >> 1, cy = by >> 1;
-        const int mc = m >> 1;
-        const int ox = x0 >> (lev + 1), oy = y0 >> (lev + 1);
-        for (int k = t; k < cx * cy; k += 256) {
-            const int I = k % cx, J = k / cx;
-            const T* f = buf[cur];
-            const T s = (f[(2 * J) * bx + 2 * I] + f[(2 * J) * bx + 2 * I + 1]) +
-                        (f[(2 * J + 1) * bx + 2 * I] + f[(2 * J + 1) * bx + 2 * I + 1]);
-            const T v = T(0.25) * s;
-            buf[cur ^ 1][k] = v;
-            P.dst[lev][(size_t)(oy + J) * mc + (ox + I)] = v;
-        }
-        __syncthreads();
-        cur ^= 1;
-        bx = cx; by = cy; m = mc;
-    }
-}
-
 }  // namespace mpfc

@@ -10,8 +10,8 @@
 //    from the largest size to the smallest, up phases the other way, so each
 //    simulation sees its own levels in V-cycle order;
 //  - one persistent launch with a workgroup per simulation for the coarse
-//    levels;
-//  - pyramids of 2x2 averages (phi^k, base phi) in one or two launches.
+//    levels (phi^k and the base phi of the coarse levels are averaged by the
+//    down launches, as in the single-grid path).
 // The tile shape of every (size, down/up) phase is chosen by timing each
 // shape on the phase's whole work list.  The step's units (set-up, one
 // V-cycle or one outer iteration, wrap-up) are captured once as hipGraphs and
@@ -38,13 +38,6 @@ struct KindTable {
 struct PhaseKey {
     int m, n;
     std::vector<std::pair<int, int>> members;  // (simulation, level)
-};
-
-template <typename T>
-struct PyrPass {
-    BPyr<T>* d_args = nullptr;
-    BatchItem* d_items = nullptr;
-    int nitems = 0;
 };
 
 struct BatchBase {
@@ -122,8 +115,6 @@ struct BatchImpl : BatchBase {
     BatchCoarse<Op64>* d_c64[2] = {};      // persistent tables (coarsest 4 / 8 cells)
     BatchCoarse<Op32>* d_c32[2] = {};
     int nc[2] = {0, 0};
-    std::vector<PyrPass<double>> pyr_xk64;
-    std::vector<PyrPass<float>> pyr_xk32, pyr_pb32;
 
     explicit BatchImpl(mpfc_batch* b) : B(b) {}
 
@@ -198,56 +189,6 @@ struct BatchImpl : BatchBase {
         if (kt.nitems > 0) launch_tile_batched<Op, UP>(kt.shape, kt.d_args, kt.d_items, kt.nitems, s);
     }
 
-    // Pyramid passes over fields[s][l] (every level of every simulation).
-    template <typename T>
-    int build_pyramid(std::vector<PyrPass<T>>& passes, const std::vector<std::vector<T*>>& fields,
-                      bool with_stop) {
-        for (int pass = 0;; ++pass) {
-            std::vector<BPyr<T>> args;
-            std::vector<BatchItem> items;
-            const int L = PYR_LEVELS * pass;
-            for (int s = 0; s < B->nsim; ++s) {
-                const mpfc_ctx* C = B->C[s];
-                const int nl = (int)C->L.size();
-                if (nl - 1 <= L) continue;
-                const Level& lv = C->L[L];
-                BPyr<T> P{};
-                P.src = fields[s][L];
-                P.nlev = nl - 1 - L < PYR_LEVELS ? nl - 1 - L : PYR_LEVELS;
-                for (int k = 0; k < P.nlev; ++k) P.dst[k] = fields[s][L + 1 + k];
-                P.g = lv.g;
-                P.bx = lv.m < 32 ? lv.m : 32;
-                P.by = lv.n < 32 ? lv.n : 32;
-                if ((P.bx >> P.nlev) < 1 || (P.by >> P.nlev) < 1)
-                    return fail(MPFC_EHIP, "internal: pyramid block too small");
-                P.nbx = lv.m / P.bx;
-                P.stop = with_stop ? C->st : nullptr;
-                const int nb = P.nbx * (lv.n / P.by);
-                for (int t = 0; t < nb; ++t) items.push_back(BatchItem{(int)args.size(), t});
-                args.push_back(P);
-            }
-            if (args.empty()) break;
-            PyrPass<T> pp;
-            int rc = B->dalloc(&pp.d_args, args.size());
-            if (!rc) rc = B->dalloc(&pp.d_items, items.size());
-            if (rc) return rc;
-            HIP_TRY(hipMemcpy(pp.d_args, args.data(), args.size() * sizeof(BPyr<T>),
-                              hipMemcpyHostToDevice));
-            HIP_TRY(hipMemcpy(pp.d_items, items.data(), items.size() * sizeof(BatchItem),
-                              hipMemcpyHostToDevice));
-            pp.nitems = (int)items.size();
-            passes.push_back(pp);
-        }
-        return MPFC_OK;
-    }
-
-    template <typename T>
-    void run_pyramid(const std::vector<PyrPass<T>>& passes, hipStream_t s) {
-        for (auto& pp : passes)
-            hipLaunchKernelGGL((k_b_pyramid<T>), dim3(pp.nitems), dim3(256), 0, s, pp.d_args,
-                               pp.d_items);
-    }
-
     int build() override {
         const int np = (int)B->phases.size();
         for (int up = 0; up < 2; ++up) {
@@ -284,23 +225,7 @@ struct BatchImpl : BatchBase {
             else
                 HIP_TRY(hipMemcpy(d_c32[g], a32.data(), a32.size() * sizeof(a32[0]), hipMemcpyHostToDevice));
         }
-        // pyramids
-        std::vector<std::vector<double*>> xk64(B->nsim);
-        std::vector<std::vector<float*>> xk32(B->nsim), pb32(B->nsim);
-        for (int s = 0; s < B->nsim; ++s) {
-            const mpfc_ctx* C = B->C[s];
-            for (int l = 0; l < (int)C->L.size(); ++l) {
-                xk64[s].push_back(C->L[l].xk);
-                if (B->mixed) {
-                    xk32[s].push_back(C->FL[l].xk);
-                    pb32[s].push_back(C->FL[l].pb);
-                }
-            }
-        }
-        int rc = MPFC_OK;
-        if (S == 2) rc = fp64() ? build_pyramid(pyr_xk64, xk64, false) : build_pyramid(pyr_xk32, xk32, false);
-        if (!rc && B->mixed) rc = build_pyramid(pyr_pb32, pb32, true);
-        return rc;
+        return MPFC_OK;
     }
 
     // Time every admissible shape of every (phase, down/up) on its whole work
@@ -374,11 +299,9 @@ struct BatchImpl : BatchBase {
         hipLaunchKernelGGL(k_b_kappa, gc, blk, 0, s, B->d_sims, B->d_cells);
         if (B->mixed) {
             hipLaunchKernelGGL((k_b_mu<S, true>), gc, blk, 0, s, B->d_sims, B->d_cells);
-            run_pyramid(pyr_xk32, s);
             hipLaunchKernelGGL((k_b_defect<S>), gc, blk, 0, s, B->d_sims, B->d_cells, 0, 0);
         } else {
             hipLaunchKernelGGL((k_b_mu<S, false>), gc, blk, 0, s, B->d_sims, B->d_cells);
-            run_pyramid(pyr_xk64, s);
             hipLaunchKernelGGL((k_b_resnorm<S>), gc, blk, 0, s, B->d_sims, B->d_cells);
         }
         finalize(0, s);
@@ -400,7 +323,6 @@ struct BatchImpl : BatchBase {
     void outer(int from, hipStream_t s) override {
         const int np = (int)B->phases.size();
         hipLaunchKernelGGL(k_b_clear_e, dim3(B->ncells), dim3(256), 0, s, B->d_sims, B->d_cells);
-        run_pyramid(pyr_pb32, s);
         for (int k = 0; k < B->o.inner_cycles; ++k) {
             for (int p = 0; p < np; ++p) launch<Op32, false>(t32[0][p], s);
             if (nc[0]) hipLaunchKernelGGL((k_coarse_persistent_batched<Op32, CP_THREADS, 4>),

@@ -270,6 +270,7 @@ TileArgs<double> dn_args64(const mpfc_ctx* C, int l) {
         T.rH[f] = B.rr[f];
     }
     T.xk = A.xk;
+    T.xkH = B.xk;  // phi^k of the next level (scheme 2), averaged in-kernel
     T.complete_f = l > 0;
     T.nsweep = 2 * C->o.nu1;
     T.H = round_even(T.nsweep + 1);
@@ -344,6 +345,8 @@ TileArgs<float> dn_args32(const mpfc_ctx* C, int l) {
     }
     T.xk = FA.xk;
     T.pb = FA.pb;
+    T.xkH = FB.xk;  // coefficient fields of the next level, averaged in-kernel
+    T.pbH = FB.pb;
     T.complete_f = l > 0;
     T.nsweep = 2 * C->o.nu1;
     T.H = round_even(T.nsweep + 1);
@@ -461,13 +464,15 @@ void resnorm(mpfc_ctx* C, hipStream_t s) {
 // One FP32 FAS V-cycle on the correction equation N(u + e) - N(u) = r (DEFECT
 // operators: the base phi of every level is a coefficient field).
 template <class Op>
-void vcycle_inner_t(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) {
+void vcycle_inner_t(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0,
+                    bool first = false) {
     const int nl = (int)C->L.size(), Lp = C->Lp;
     const CycleState* stop = only >= 0 ? nullptr : C->st;
     for (int l = 0; l < Lp; ++l) {
         if (only >= 0 && (l != only || only_up)) continue;
         const Level& A = C->L[l];
         TileArgs<float> Tg = dn_args32(C, l);
+        Tg.zero_in = first && l == 0;  // the outer iteration's correction starts at zero
         const int shape = level_shape(A, SH_DN32, Tg.H);
         tile_dims(A, shape, Tg.tx, Tg.ty);
         launch_tile<Op, false>(make_op32<Op>(C, A), Tg, shape, stop, s);
@@ -515,25 +520,26 @@ void defect(mpfc_ctx* C, int from, int add, hipStream_t s) {
 }
 
 // One outer iteration of mixed precision starting from FP64 copy `from`:
-// e = 0, base-phi pyramid, `inner_cycles` FP32 V-cycles, then the FP64 defect
-// step into the other copy.
+// `inner_cycles` FP32 V-cycles on the correction (from e = 0), then the FP64
+// defect step into the other copy.
 void outer_mixed(mpfc_ctx* C, int from, hipStream_t s) {
-    const int nl = (int)C->L.size();
     const auto& FF = C->FL[0];
     const size_t total = (size_t)C->m * C->n;
-    for (int f = 0; f < 3; ++f)
-        hipLaunchKernelGGL((k_fill<float>), grid1(total), dim3(256), 0, s, FF.e[0][f], total, 0.f);
-    for (int l = 1; l < nl; ++l)
-        hipLaunchKernelGGL((k_restrict<float, float>), grid2(C->L[l].m, C->L[l].n), B2, 0, s,
-                           C->L[l - 1].g, C->FL[l - 1].pb, C->FL[l].pb);
+    // The first inner cycle's finest down launch starts from e = 0 and its down
+    // launches average the base phi onto the coarser levels; without tiled
+    // levels the persistent kernel reads e from memory, so clear it.
+    if (C->Lp == 0)
+        for (int f = 0; f < 3; ++f)
+            hipLaunchKernelGGL((k_fill<float>), grid1(total), dim3(256), 0, s, FF.e[0][f], total, 0.f);
     const bool nw = C->o.linearization == MPFC_NEWTON;
     for (int k = 0; k < C->inner_cycles; ++k) {
+        const bool first = k == 0;
         if (C->p.scheme == 1) {
-            if (nw) vcycle_inner_t<MpfcOp<float, 1, true, true>>(C, s);
-            else vcycle_inner_t<MpfcOp<float, 1, false, true>>(C, s);
+            if (nw) vcycle_inner_t<MpfcOp<float, 1, true, true>>(C, s, -1, 0, first);
+            else vcycle_inner_t<MpfcOp<float, 1, false, true>>(C, s, -1, 0, first);
         } else {
-            if (nw) vcycle_inner_t<MpfcOp<float, 2, true, true>>(C, s);
-            else vcycle_inner_t<MpfcOp<float, 2, false, true>>(C, s);
+            if (nw) vcycle_inner_t<MpfcOp<float, 2, true, true>>(C, s, -1, 0, first);
+            else vcycle_inner_t<MpfcOp<float, 2, false, true>>(C, s, -1, 0, first);
         }
     }
     defect(C, from, 1, s);
@@ -912,12 +918,12 @@ void residual_sq(mpfc_ctx* C, int k, double* out, hipStream_t s);
 void cnn_choose(mpfc_ctx* C, hipStream_t s);
 
 // ---- one step, split for reuse by the batched path -------------------------------
-// Source (also copies phi^k), phi^k pyramid, guess and its completion, stop
-// state reset and the first residual norm (FP64), or for mixed precision the
-// FP32 coefficient pyramids and the first FP64 defect (copy 0 -> 1).
+// Source (also copies phi^k), guess and its completion, stop state reset and
+// the first residual norm (FP64), or for mixed precision phi^k in FP32 and the
+// first FP64 defect (copy 0 -> 1).  The coarse levels' phi^k (scheme 2) is
+// averaged by each cycle's down launches.
 int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const double* psi,
                   hipStream_t s) {
-    const int nl = (int)C->L.size();
     Level& F0 = C->L[0];
     const Grid g0 = F0.g;
     const size_t total = (size_t)C->m * C->n;
@@ -931,10 +937,6 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
     else
         hipLaunchKernelGGL((k_source<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
                            phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik);
-    if (C->p.scheme == 2)
-        for (int l = 1; l < nl; ++l)
-            hipLaunchKernelGGL((k_restrict<double, double>), grid2(C->L[l].m, C->L[l].n), B2, 0, s,
-                               C->L[l - 1].g, C->L[l - 1].xk, C->L[l].xk);
     hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->st);
     const bool learned = C->o.guess == MPFC_GUESS_CNN;
     if (learned) {
@@ -962,13 +964,10 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
             resnorm(C, s);
     } else {
         const auto& FF = C->FL[0];
-        if (C->p.scheme == 2) {
+        // the coarse levels' phi^k is averaged by the down launches of each cycle
+        if (C->p.scheme == 2)
             hipLaunchKernelGGL((k_convert<double, float>), grid1(total), dim3(256), 0, s, C->phik,
                                FF.xk, total);
-            for (int l = 1; l < nl; ++l)
-                hipLaunchKernelGGL((k_restrict<float, float>), grid2(C->L[l].m, C->L[l].n), B2, 0,
-                                   s, C->L[l - 1].g, C->FL[l - 1].xk, C->FL[l].xk);
-        }
         defect(C, 0, 0, s);
     }
     HIP_TRY(hipGetLastError());

@@ -99,8 +99,10 @@ struct TileArgs {
     const T* xk;            // phi^k on this level (scheme 2)
     const T* pb;            // base phi (correction form)
     T* uH[3]; T* vH[3]; T* rH[3];          // down: restricted u (twice) and residual
+    T* xkH; T* pbH;         // down (nullable): 2x2 averages of phi^k and of the base phi
     const T* cuH[3]; const T* cvH[3];      // up: coarse u after and before its solve
     int complete_f;         // down on a coarse level
+    int zero_in;            // u before the launch is zero (uin is not read)
     int nsweep;             // red-black half-sweeps (2 nu)
     int H;                  // halo (even)
     int tx, ty;             // interior tile (even, divides m, n)
@@ -155,7 +157,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
         const int y = q / LX, x = q - y * LX;
         const size_t gq = at((x0 + x) & (g.m - 1), (y0 + y) & (g.n - 1), g);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) U[f][(x + y) & 1][y][x >> 1] = A.uin[f][gq];
+        for (int f = 0; f < NF; ++f) U[f][(x + y) & 1][y][x >> 1] = A.zero_in ? T(0) : A.uin[f][gq];
     }
     __syncthreads();
 
@@ -345,6 +347,12 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
                 A.vH[f][Q] = avg;
                 A.rH[f][Q] = T(0.25) * sr[f];
             }
+            // coefficient fields of the coarse level, in the order of additions
+            // of a plain 2x2 average: ((f00 + f10) + (f01 + f11)) / 4
+            if constexpr (Op::XK)
+                if (A.xkH) A.xkH[Q] = T(0.25) * ((xkr[s][0] + xkr[s][2]) + (xkr[s][3] + xkr[s][1]));
+            if constexpr (Op::PB)
+                if (A.pbH) A.pbH[Q] = T(0.25) * ((pbr[s][0] + pbr[s][2]) + (pbr[s][3] + pbr[s][1]));
         }
     }
     if constexpr (!UP) {
