@@ -557,6 +557,11 @@ void vcycle_mpfc(mpfc_ctx* C, hipStream_t s) {
     if (C->Lp == 0) resnorm(C, s);
 }
 
+// Stopping test of the Poisson solve of the -1 norm: ||r|| <= 1e-11 ||b||, or
+// stalled at the rounding floor below 1e-8 ||b||; at most 60 cycles per step.
+constexpr double kPoissonRel = 1e-11, kPoissonStall = 1e-8;
+constexpr int kPoissonMax = 60;
+
 // One V-cycle of the Poisson problem -Lap_h w = b (same structure, scalar).
 void vcycle_poisson(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) {
     using Op = PoissonOp<double>;
@@ -610,10 +615,9 @@ void vcycle_poisson(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) 
         tile_dims(A, shape, T.tx, T.ty);
         launch_tile<Op, true>(make_op<Op>(C, A), T, shape, stop, s);
         if (T.norm) {
-            // plain l2 norm; the host compares it with ||b|| (tol 0 never stops)
             const int nb = (A.m / T.tx) * (A.n / T.ty);
-            hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, nb, C->pst,
-                               C->phist, 1.0, 0.0, 60, 1e300);
+            hipLaunchKernelGGL((k_p_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, nb, C->pst,
+                               C->phist, C->acc + 9, kPoissonRel, kPoissonStall, kPoissonMax);
         }
     }
     if (Lp == 0 && only < 0) {
@@ -621,8 +625,8 @@ void vcycle_poisson(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) 
         const unsigned nb = red_blocks((size_t)F0.m * F0.n);
         hipLaunchKernelGGL((k_p_resnorm<NT>), dim3(nb), dim3(NT), 0, s, F0.w[0], F0.pf, F0.g,
                            1.0 / (F0.h * F0.h), C->pst, C->part);
-        hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)nb,
-                           C->pst, C->phist, 1.0, 0.0, 60, 1e300);
+        hipLaunchKernelGGL((k_p_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)nb, C->pst,
+                           C->phist, C->acc + 9, kPoissonRel, kPoissonStall, kPoissonMax);
     }
 }
 
@@ -865,41 +869,41 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
     }
     hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->pst);
     HIP_TRY(hipGetLastError());
-    int ran = 0;
-    for (int k = 0; k < C->poisson_cycles; ++k, ++ran) {
-        int rc = run_cycle(C, CYC_POISSON);
-        if (rc) return rc;
-    }
-    double res = 0.0, bn = 0.0, prev_res = 1e300;
-    bool ok = false;
-    for (;;) {
+    // Poisson cycles stop on the device (k_p_finalize); the energy sums are
+    // enqueued behind them, so one readback usually ends the step.  Only when
+    // the warm count was too small do more cycles (and the sums again) follow.
+    auto terms = [&]() -> int {
+        hipLaunchKernelGGL((k_energy_terms<NT>), dim3(rb), dim3(NT), 0, s, F0.g,
+                           1.0 / (F0.h * F0.h), phi, phiprev, F0.pf, F0.w[0], C->part);
+        hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 8,
+                           C->acc);
+        HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(C->host_buf, C->acc, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(C->host_st, C->pst, sizeof(CycleState), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(C->host_buf + 16, C->phist, 64 * sizeof(double),
-                               hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        const int cnt = C->host_st->count;
-        res = cnt > 0 ? C->host_buf[16 + cnt - 1] : 1e300;
-        prev_res = cnt > 1 ? C->host_buf[16 + cnt - 2] : 1e300;
-        bn = std::sqrt(C->host_buf[9]);
-        // converged, or stalled at the rounding floor of the Poisson operator
-        ok = res <= 1e-11 * bn || bn == 0.0 || (res <= 1e-8 * bn && res > 0.5 * prev_res);
-        if (ok || C->host_st->done || ran >= 50) break;
+        return MPFC_OK;
+    };
+    int launched = 0;
+    for (int k = 0; k < C->poisson_cycles; ++k, ++launched) {
         int rc = run_cycle(C, CYC_POISSON);
         if (rc) return rc;
-        ++ran;
     }
+    int rc = terms();
+    if (rc) return rc;
+    while (!C->host_st->done && launched < kPoissonMax) {
+        for (int k = 0; k < 2; ++k, ++launched) {
+            rc = run_cycle(C, CYC_POISSON);
+            if (rc) return rc;
+        }
+        rc = terms();
+        if (rc) return rc;
+    }
+    const bool ok = C->host_st->status == ST_CONVERGED;
+    const int ran = C->host_st->count;
     // keep the number of warm cycles just large enough
-    if (ran > C->poisson_cycles) C->poisson_cycles = ran < 8 ? ran : 8;
-    else if (ran == C->poisson_cycles && C->poisson_cycles > 1 && res <= 1e-3 * 1e-11 * bn)
-        C->poisson_cycles -= 1;
+    if (ran >= C->poisson_cycles) C->poisson_cycles = ran < 8 ? ran : 8;
+    else if (C->poisson_cycles > 1) C->poisson_cycles -= 1;
     C->have_w = 1;
-    hipLaunchKernelGGL((k_energy_terms<NT>), dim3(rb), dim3(NT), 0, s, F0.g, 1.0 / (F0.h * F0.h),
-                       phi, phiprev, F0.pf, F0.w[0], C->part);
-    hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 8, C->acc);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(C->host_buf, C->acc, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
     const double* a = C->host_buf;
     const double h2 = F0.h * F0.h;
     const double Fe = 0.25 * h2 * a[0] + 0.5 * C->alpha * h2 * a[1] - a[2] + 0.5 * h2 * a[3];
@@ -1229,16 +1233,22 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     const bool mixed = C->o.precision == MPFC_MIXED;
     int rc0 = step_prologue(C, phi_n, phi_nm1, psi, s);
     if (rc0) return rc0;
-    HIP_TRY(hipMemcpyAsync(C->host_st, C->st, sizeof(CycleState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    // Cycles are enqueued speculatively: the first batch is one less than the
-    // previous step needed, then one at a time.  A cycle enqueued after the
-    // stop flag was raised exits at once in every kernel, so speculation only
-    // costs launches, never changes the result.  (Mixed precision: outer
-    // iteration k reads FP64 copy 1 ^ (k & 1).)
+    // Cycles are enqueued speculatively behind the set-up, without waiting for
+    // it: the first batch is one less than the previous step needed, then one
+    // at a time.  A cycle enqueued after the stop flag was raised exits at once
+    // in every kernel, so speculation only costs launches, never changes the
+    // result.  (Mixed precision: outer iteration k reads FP64 copy 1 ^ (k & 1).)
+    // While profiling, cycles go one by one and the set-up is waited for, so
+    // that every timed launch belongs to a cycle that ran.
     int launched = 0;
     int batch = C->prof ? 1 : (C->pred_units > 1 ? C->pred_units - 1 : 1);
-    while (!C->host_st->done) {
+    bool done = false;
+    if (C->prof) {
+        HIP_TRY(hipMemcpyAsync(C->host_st, C->st, sizeof(CycleState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        done = C->host_st->done != 0;
+    }
+    while (!done) {
         if (launched > C->o.max_cycles + 1)
             return fail(MPFC_EHIP, "internal: cycle state did not advance");
         for (int b = 0; b < batch; ++b, ++launched) {
@@ -1249,6 +1259,7 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
         HIP_TRY(hipMemcpyAsync(C->host_st, C->st, sizeof(CycleState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (C->prof && C->Lp > 0 && !mixed) prof_collect(C);
+        done = C->host_st->done != 0;
     }
     const CycleState fin = *C->host_st;
     const int nouter = fin.count - 1;

@@ -77,6 +77,38 @@ __global__ void __launch_bounds__(256) k_w_advance(double* w, const double* __re
     w[q] = a * w[q] - b * (mu[q] - mean);
 }
 
+// Norm bookkeeping of the Poisson cycles with the stop decision on the device:
+// converged when ||r|| <= rel ||b|| (||b||^2 = bsq[0]), or when the residual has
+// reached the operator's rounding floor (||r|| <= stall ||b|| and the last cycle
+// removed less than half of it), or b = 0; the cycle limit gives ST_MAXCYC.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_p_finalize(const double* __restrict__ part, int nparts,
+                                                   CycleState* st, double* hist,
+                                                   const double* __restrict__ bsq, double rel,
+                                                   double stall, int max_norms) {
+    if (stopped(st)) return;
+    __shared__ double red[NT / 64];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += NT) s += part[b];
+    const double tot = block_sum<NT>(s, red);
+    if (threadIdx.x == 0) {
+        const double nr = sqrt(tot);
+        const double bn = sqrt(bsq[0]);
+        const int k = st->count;
+        const double prev = k > 0 ? hist[k - 1] : 1e300;
+        hist[k] = nr;
+        st->acc = nr;
+        st->count = k + 1;
+        int status = ST_RUNNING;
+        if (!(nr == nr)) status = ST_NONFINITE;
+        else if (bn == 0.0 || nr <= rel * bn || (nr <= stall * bn && nr > 0.5 * prev))
+            status = ST_CONVERGED;
+        else if (k + 1 >= max_norms) status = ST_MAXCYC;
+        st->status = status;
+        st->done = status != ST_RUNNING;
+    }
+}
+
 // Finest-grid Poisson residual sum of squares (b + Lap_h w)^2 for grids small
 // enough that every level runs in the persistent kernel.
 template <int NT>
