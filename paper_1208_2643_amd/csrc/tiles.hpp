@@ -453,102 +453,122 @@ struct CoarseArgs {
 // Coarsest grid, MPFC: eliminate kappa and mu (kappa = f3 + e Lap phi,
 // mu = f2 + g(phi) + al phi + Lap kappa) and solve the remaining equation
 //   phi - c Lap(g(phi) + al phi + e Lap^2 phi) = f1 + c Lap(f2 + Lap f3)
-// by Newton with Gaussian elimination (NC <= 16 unknowns), one thread.  Its
-// solution is the unique solution of the three-field system.
+// by Newton with Gaussian elimination (NC <= 8 unknowns), one thread.  Its
+// solution is the unique solution of the three-field system.  Every array is
+// indexed with compile-time indices only (row swaps are selects), so that it
+// lives in registers.
 template <class Op, int NC>
-__device__ void coarse_solve_mpfc(const Op& op, typename Op::real* phi, typename Op::real* mu,
-                                  typename Op::real* ka, const typename Op::real* f,
-                                  const typename Op::real* xk, const typename Op::real* pb,
-                                  int m, int n, int maxit, typename Op::real tol) {
-    constexpr int ncell = NC;
+__device__ __forceinline__ void coarse_solve_mpfc(const Op& op, typename Op::real* phi,
+                                                  typename Op::real* mu, typename Op::real* ka,
+                                                  const typename Op::real (&f)[3 * NC],
+                                                  const typename Op::real* xk,
+                                                  const typename Op::real* pb, int m, int lm,
+                                                  int n, int maxit, typename Op::real tol) {
     using T = typename Op::real;
-    // Laplacian matrix of the periodic m x n grid (entries accumulate, so a
-    // 2-cell direction couples each cell twice to its one neighbour).
+    const T c = op.op.c, e = op.op.e, al = op.op.al;
+    // Laplacian matrix of the periodic m x n grid (a 2-cell direction couples
+    // each cell twice to its one neighbour).
     T L[NC][NC];
-    for (int a = 0; a < NC; ++a)
-        for (int b = 0; b < NC; ++b) L[a][b] = T(0);
-    for (int q = 0; q < ncell; ++q) {
-        const int i = q % m, j = q / m;
-        const int nb[4] = {((i + 1) % m) + j * m, ((i - 1 + m) % m) + j * m,
-                           i + ((j + 1) % n) * m, i + ((j - 1 + n) % n) * m};
-        L[q][q] -= T(4) * op.op.ih2;
-        for (int s = 0; s < 4; ++s) L[q][nb[s]] += op.op.ih2;
-    }
-    const T* f1 = f;
-    const T* f2 = f + ncell;
-    const T* f3 = f + 2 * ncell;
-    T rhs[NC], t1[NC], L2[NC][NC];
-    // rhs = f1 + c Lap(f2 + Lap f3)
+#pragma unroll
     for (int a = 0; a < NC; ++a) {
-        T s = 0;
-        for (int b = 0; b < ncell; ++b) s += L[a][b] * f3[b];
-        t1[a] = f2[a] + s;
-    }
-    for (int a = 0; a < ncell; ++a) {
-        T s = 0;
-        for (int b = 0; b < ncell; ++b) s += L[a][b] * t1[b];
-        rhs[a] = f1[a] + op.op.c * s;
-    }
-    // L2 = Lap^2
-    for (int a = 0; a < ncell; ++a)
-        for (int b = 0; b < ncell; ++b) {
-            T s = 0;
-            for (int k = 0; k < ncell; ++k) s += L[a][k] * L[k][b];
-            L2[a][b] = s;
+        const int i = a & (m - 1), j = a >> lm;
+        const int e0 = ((i + 1) & (m - 1)) + (j << lm), e1 = ((i - 1) & (m - 1)) + (j << lm);
+        const int e2 = i + (((j + 1) & (n - 1)) << lm), e3 = i + (((j - 1) & (n - 1)) << lm);
+#pragma unroll
+        for (int b = 0; b < NC; ++b) {
+            const int k = (b == a ? -4 : 0) + (b == e0) + (b == e1) + (b == e2) + (b == e3);
+            L[a][b] = T(k) * op.op.ih2;
         }
-    T x[NC];
-    for (int a = 0; a < ncell; ++a) x[a] = phi[a];
+    }
+    auto lap = [&](const T (&v)[NC], T (&out)[NC]) {
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            T s = 0;
+#pragma unroll
+            for (int b = 0; b < NC; ++b) s += L[a][b] * v[b];
+            out[a] = s;
+        }
+    };
+    T f1[NC], f2[NC], f3[NC], t1[NC], t2[NC], rhs[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) { f1[a] = f[a]; f2[a] = f[NC + a]; f3[a] = f[2 * NC + a]; }
+    // rhs = f1 + c Lap(f2 + Lap f3)
+    lap(f3, t1);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) t1[a] += f2[a];
+    lap(t1, t2);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) rhs[a] = f1[a] + c * t2[a];
+    // L3 = Lap^3 (constant part of the Jacobian)
+    T L3[NC][NC];
+#pragma unroll
+    for (int b = 0; b < NC; ++b) {
+        T col[NC], l1[NC];
+#pragma unroll
+        for (int a = 0; a < NC; ++a) col[a] = L[a][b];
+        lap(col, l1);
+        lap(l1, col);
+#pragma unroll
+        for (int a = 0; a < NC; ++a) L3[a][b] = col[a];
+    }
+    T x[NC], xkv[NC], pbv[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+        x[a] = phi[a];
+        xkv[a] = Op::XK ? xk[a] : T(0);
+        pbv[a] = Op::PB ? pb[a] : T(0);
+    }
     for (int it = 0; it < maxit; ++it) {
-        // residual R = x - c Lap(g(x) + al x + e Lap^2 x) - rhs, Jacobian J
+        // residual R = x - c Lap(g(x) + al x + e Lap^2 x) - rhs
         T w[NC], d[NC], R[NC], J[NC][NC + 1];
-        for (int a = 0; a < ncell; ++a) {
-            const T xa = x[a];
-            const T xka = Op::XK ? xk[a] : T(0);
-            const T pba = Op::PB ? pb[a] : T(0);
-            T s = 0;
-            for (int b = 0; b < ncell; ++b) s += L2[a][b] * x[b];
-            w[a] = nl_value<T, (Op::XK ? 2 : 1), Op::PB>(xa, pba, xka) + op.op.al * xa + op.op.e * s;
-            d[a] = nl_lin<T, (Op::XK ? 2 : 1), true>(pba + xa, xka) + op.op.al;
+        lap(x, t1);
+        lap(t1, t2);
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            w[a] = nl_value<T, (Op::XK ? 2 : 1), Op::PB>(x[a], pbv[a], xkv[a]) + al * x[a] + e * t2[a];
+            d[a] = nl_lin<T, (Op::XK ? 2 : 1), true>(pbv[a] + x[a], xkv[a]) + al;
         }
-        for (int a = 0; a < ncell; ++a) {
-            T s = 0;
-            for (int b = 0; b < ncell; ++b) s += L[a][b] * w[b];
-            R[a] = x[a] - op.op.c * s - rhs[a];
-        }
-        // J = I - c Lap (diag(d) + e Lap^2)
-        for (int a = 0; a < ncell; ++a) {
-            for (int b = 0; b < ncell; ++b) {
-                const T v = L[a][b] * d[b] + op.op.e * [&] {
-                    T s = 0;
-                    for (int k = 0; k < ncell; ++k) s += L[a][k] * L2[k][b];
-                    return s;
-                }();
-                J[a][b] = (a == b ? T(1) : T(0)) - op.op.c * v;
-            }
-            J[a][ncell] = -R[a];
+        lap(w, t1);
+#pragma unroll
+        for (int a = 0; a < NC; ++a) R[a] = x[a] - c * t1[a] - rhs[a];
+        // Jacobian J = I - c (Lap diag(d) + e Lap^3), augmented with -R
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+#pragma unroll
+            for (int b = 0; b < NC; ++b)
+                J[a][b] = (a == b ? T(1) : T(0)) - c * (L[a][b] * d[b] + e * L3[a][b]);
+            J[a][NC] = -R[a];
         }
         // Gaussian elimination with partial pivoting
-        for (int k = 0; k < ncell; ++k) {
-            int p = k;
-            T best = fabs(J[k][k]);
-            for (int r = k + 1; r < ncell; ++r)
-                if (fabs(J[r][k]) > best) { best = fabs(J[r][k]); p = r; }
-            if (p != k)
-                for (int cc = 0; cc <= ncell; ++cc) {
-                    const T tmp = J[k][cc]; J[k][cc] = J[p][cc]; J[p][cc] = tmp;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+#pragma unroll
+            for (int r = k + 1; r < NC; ++r) {
+                const bool sw = fabs(J[r][k]) > fabs(J[k][k]);
+#pragma unroll
+                for (int cc = k; cc <= NC; ++cc) {
+                    const T hi = J[k][cc], lo = J[r][cc];
+                    J[k][cc] = sw ? lo : hi;
+                    J[r][cc] = sw ? hi : lo;
                 }
-            for (int r = k + 1; r < ncell; ++r) {
+            }
+#pragma unroll
+            for (int r = k + 1; r < NC; ++r) {
                 const T fct = J[r][k] / J[k][k];
-                for (int cc = k; cc <= ncell; ++cc) J[r][cc] -= fct * J[k][cc];
+#pragma unroll
+                for (int cc = k; cc <= NC; ++cc) J[r][cc] -= fct * J[k][cc];
             }
         }
-        T smax = 0, xmax = 0;
-        for (int k = ncell - 1; k >= 0; --k) {
-            T s = J[k][ncell];
-            for (int cc = k + 1; cc < ncell; ++cc) s -= J[k][cc] * t1[cc];
+#pragma unroll
+        for (int k = NC - 1; k >= 0; --k) {
+            T s = J[k][NC];
+#pragma unroll
+            for (int cc = k + 1; cc < NC; ++cc) s -= J[k][cc] * t1[cc];
             t1[k] = s / J[k][k];
         }
-        for (int a = 0; a < ncell; ++a) {
+        T smax = 0, xmax = 0;
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
             x[a] += t1[a];
             smax = fmax(smax, fabs(t1[a]));
             xmax = fmax(xmax, fabs(x[a]));
@@ -556,17 +576,14 @@ __device__ void coarse_solve_mpfc(const Op& op, typename Op::real* phi, typename
         if (smax <= tol * (T(1) + xmax)) break;
     }
     // recover kappa and mu
-    for (int a = 0; a < ncell; ++a) {
-        T s = 0;
-        for (int b = 0; b < ncell; ++b) s += L[a][b] * x[b];
-        ka[a] = f3[a] + op.op.e * s;
-    }
-    for (int a = 0; a < ncell; ++a) {
-        T s = 0;
-        for (int b = 0; b < ncell; ++b) s += L[a][b] * ka[b];
-        const T xka = Op::XK ? xk[a] : T(0);
-        const T pba = Op::PB ? pb[a] : T(0);
-        mu[a] = f2[a] + nl_value<T, (Op::XK ? 2 : 1), Op::PB>(x[a], pba, xka) + op.op.al * x[a] + s;
+    lap(x, t1);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) t1[a] = f3[a] + e * t1[a];
+    lap(t1, t2);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+        ka[a] = t1[a];
+        mu[a] = f2[a] + nl_value<T, (Op::XK ? 2 : 1), Op::PB>(x[a], pbv[a], xkv[a]) + al * x[a] + t2[a];
         phi[a] = x[a];
     }
 }
@@ -630,7 +647,7 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
     if (stopped(stop)) return;
     const int t = threadIdx.x;
     const CoarseGeom& G = A.geo;
-    const int m0 = G.m[0], n0 = G.n[0], N0 = m0 * n0;
+    const int N0 = G.m[0] * G.n[0];
     // load the top level
     for (int q = t; q < N0; q += NTP) {
 #pragma unroll
@@ -643,37 +660,41 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
     }
     __syncthreads();
     // coefficient pyramids (2x2 averages)
-    for (int l = 1; l < G.nlev; ++l) {
-        const int mf = G.m[l - 1], mcv = G.m[l], nc = G.n[l];
-        for (int q = t; q < mcv * nc; q += NTP) {
-            const int I = q % mcv, J = q / mcv;
-            const int a = G.off[l - 1] + 2 * J * mf + 2 * I;
-            if constexpr (Op::XK)
-                Sxk[G.off[l] + q] = T(0.25) * ((Sxk[a] + Sxk[a + 1]) + (Sxk[a + mf] + Sxk[a + mf + 1]));
-            if constexpr (Op::PB)
-                Spb[G.off[l] + q] = T(0.25) * ((Spb[a] + Spb[a + 1]) + (Spb[a + mf] + Spb[a + mf + 1]));
+    if constexpr (Op::XK || Op::PB) {
+        for (int l = 1; l < G.nlev; ++l) {
+            const int mf = G.m[l - 1], lmc = G.lm[l], mcv = G.m[l];
+            for (int q = t; q < mcv * G.n[l]; q += NTP) {
+                const int I = q & (mcv - 1), J = q >> lmc;
+                const int a = G.off[l - 1] + 2 * J * mf + 2 * I;
+                if constexpr (Op::XK)
+                    Sxk[G.off[l] + q] = T(0.25) * ((Sxk[a] + Sxk[a + 1]) + (Sxk[a + mf] + Sxk[a + mf + 1]));
+                if constexpr (Op::PB)
+                    Spb[G.off[l] + q] = T(0.25) * ((Spb[a] + Spb[a + 1]) + (Spb[a + mf] + Spb[a + mf + 1]));
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
+    // level l has spacing 2^l h_top: scale 1/h^2 (and h^2) by exact powers of two
     auto opl = [&](int l) {
         Op o = op_top;
-        const T s = T(1 << l);
-        if constexpr (NF == 3) o.op.ih2 = op_top.op.ih2 / (s * s);
-        else { o.ih2 = op_top.ih2 / (s * s); o.h2 = op_top.h2 * (s * s); }
+        if constexpr (NF == 3) o.op.ih2 = ldexp(op_top.op.ih2, -2 * l);
+        else { o.ih2 = ldexp(op_top.ih2, -2 * l); o.h2 = ldexp(op_top.h2, 2 * l); }
         return o;
     };
-    auto nsum_l = [&](const T* a, int q, int m, int n) {
-        const int i = q % m, j = q / m;
-        return (a[((i + 1) & (m - 1)) + j * m] + a[((i - 1) & (m - 1)) + j * m]) +
-               (a[i + ((j + 1) & (n - 1)) * m] + a[i + ((j - 1) & (n - 1)) * m]);
+    // sum of the four periodic neighbours of cell (i, j) of an m x n level
+    auto nsum_l = [&](const T* a, int i, int j, int m, int lm, int n) {
+        const int r = j << lm;
+        return (a[((i + 1) & (m - 1)) + r] + a[((i - 1) & (m - 1)) + r]) +
+               (a[i + (((j + 1) & (n - 1)) << lm)] + a[i + (((j - 1) & (n - 1)) << lm)]);
     };
     auto complete_rhs = [&](int l) {
         const Op o = opl(l);
-        const int m = G.m[l], n = G.n[l], off = G.off[l];
+        const int m = G.m[l], lm = G.lm[l], n = G.n[l], off = G.off[l];
         for (int q = t; q < m * n; q += NTP) {
+            const int i = q & (m - 1), j = q >> lm;
             T u[NF], ns[NF], N[NF];
 #pragma unroll
-            for (int f = 0; f < NF; ++f) { u[f] = Su[f][off + q]; ns[f] = nsum_l(&Su[f][off], q, m, n); }
+            for (int f = 0; f < NF; ++f) { u[f] = Su[f][off + q]; ns[f] = nsum_l(&Su[f][off], i, j, m, lm, n); }
             o.apply(u, ns, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0), N);
 #pragma unroll
             for (int f = 0; f < NF; ++f) Sf[f][off + q] += N[f];
@@ -682,18 +703,18 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
     };
     auto sweeps = [&](int l, int nsw) {
         const Op o = opl(l);
-        const int m = G.m[l], n = G.n[l], off = G.off[l];
+        const int m = G.m[l], lm = G.lm[l], n = G.n[l], off = G.off[l];
         for (int p = 0; p < nsw; ++p) {
             const int colour = p & 1;
-            for (int q2 = t; q2 < (m * n) / 2; q2 += NTP) {
-                const int j = q2 / (m >> 1), k = q2 - j * (m >> 1);
+            for (int q2 = t; q2 < (m * n) >> 1; q2 += NTP) {
+                const int j = q2 >> (lm - 1), k = q2 & ((m >> 1) - 1);
                 const int i = 2 * k + ((j + colour) & 1);
-                const int q = j * m + i;
+                const int q = (j << lm) + i;
                 T u[NF], ns[NF], fv[NF];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
                     u[f] = Su[f][off + q];
-                    ns[f] = nsum_l(&Su[f][off], q, m, n);
+                    ns[f] = nsum_l(&Su[f][off], i, j, m, lm, n);
                     fv[f] = Sf[f][off + q];
                 }
                 o.relax(u, ns, fv, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0));
@@ -709,19 +730,20 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
     for (int l = 0; l < L - 1; ++l) {
         sweeps(l, A.nsw1);
         const Op o = opl(l);
-        const int m = G.m[l], n = G.n[l], off = G.off[l];
-        const int mc = G.m[l + 1], nc = G.n[l + 1], offc = G.off[l + 1];
+        const int m = G.m[l], lm = G.lm[l], n = G.n[l], off = G.off[l];
+        const int mc = G.m[l + 1], lmc = G.lm[l + 1], nc = G.n[l + 1], offc = G.off[l + 1];
         for (int Q = t; Q < mc * nc; Q += NTP) {
-            const int I = Q % mc, J = Q / mc;
+            const int I = Q & (mc - 1), J = Q >> lmc;
             T su[NF], sr[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) { su[f] = T(0); sr[f] = T(0); }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const int q = (2 * J + (c >> 1)) * m + 2 * I + (c & 1);
+                const int i = 2 * I + (c & 1), j = 2 * J + (c >> 1);
+                const int q = (j << lm) + i;
                 T u[NF], ns[NF], N[NF];
 #pragma unroll
-                for (int f = 0; f < NF; ++f) { u[f] = Su[f][off + q]; ns[f] = nsum_l(&Su[f][off], q, m, n); }
+                for (int f = 0; f < NF; ++f) { u[f] = Su[f][off + q]; ns[f] = nsum_l(&Su[f][off], i, j, m, lm, n); }
                 o.apply(u, ns, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0), N);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) { su[f] += u[f]; sr[f] += Sf[f][off + q] - N[f]; }
@@ -753,7 +775,7 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
                 T* xkp = Op::XK ? &Sxk[off] : nullptr;
                 T* pbp = Op::PB ? &Spb[off] : nullptr;
                 coarse_solve_mpfc<Op, NC>(o, &Su[0][off], &Su[1][off], &Su[2][off], fbuf, xkp, pbp,
-                                          G.m[l], G.n[l], A.newton_maxit, A.newton_tol);
+                                          G.m[l], G.lm[l], G.n[l], A.newton_maxit, A.newton_tol);
             }
         } else {
             coarse_solve_poisson<T>(&Su[0][off], &Sf[0][off], &Sv[0][off], A.G, nc);
@@ -762,10 +784,10 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
     }
     // up
     for (int l = L - 2; l >= 0; --l) {
-        const int m = G.m[l], n = G.n[l], off = G.off[l];
+        const int m = G.m[l], lm = G.lm[l], n = G.n[l], off = G.off[l];
         const int mc = G.m[l + 1], nc = G.n[l + 1], offc = G.off[l + 1];
         for (int q = t; q < m * n; q += NTP) {
-            const int i = q % m, j = q / m, I = i >> 1, J = j >> 1;
+            const int i = q & (m - 1), j = q >> lm, I = i >> 1, J = j >> 1;
             const int Is = ((i & 1) ? I + 1 : I - 1) & (mc - 1);
             const int Js = ((j & 1) ? J + 1 : J - 1) & (nc - 1);
 #pragma unroll
