@@ -229,14 +229,11 @@ struct BatchImpl : BatchBase {
     }
 
     // Time every admissible shape of every (phase, down/up) on its whole work
-    // list; keep the fastest.  MPFC_TILE_SHAPE=<k> forces shape k.
+    // list, from a graph; keep the fastest.  MPFC_TILE_SHAPE=<k> forces shape k.
     int autotune() override {
         const char* forced = std::getenv("MPFC_TILE_SHAPE");
         const int np = (int)B->phases.size();
         hipStream_t s = B->stream;
-        hipEvent_t e0, e1;
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
         int rc = MPFC_OK;
         for (int p = 0; p < np && !rc; ++p)
             for (int up = 0; up < 2 && !rc; ++up) {
@@ -248,18 +245,11 @@ struct BatchImpl : BatchBase {
                     else r = up ? fill<Op32, true, false>(t32[1][p], p, k, !timed)
                                 : fill<Op32, false, false>(t32[0][p], p, k, !timed);
                     if (r || !timed) return r;
-                    auto go = [&] {
-                        if (fp64()) { if (up) launch<Op64, true>(t64[1][p], s); else launch<Op64, false>(t64[0][p], s); }
-                        else { if (up) launch<Op32, true>(t32[1][p], s); else launch<Op32, false>(t32[0][p], s); }
+                    auto go = [&](hipStream_t st) {
+                        if (fp64()) { if (up) launch<Op64, true>(t64[1][p], st); else launch<Op64, false>(t64[0][p], st); }
+                        else { if (up) launch<Op32, true>(t32[1][p], st); else launch<Op32, false>(t32[0][p], st); }
                     };
-                    go();
-                    HIP_TRY(hipEventRecord(e0, s));
-                    for (int r2 = 0; r2 < 3; ++r2) go();
-                    HIP_TRY(hipEventRecord(e1, s));
-                    HIP_TRY(hipEventSynchronize(e1));
-                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                    HIP_TRY(hipGetLastError());
-                    return MPFC_OK;
+                    return time_in_graph(B->cap_stream, s, kTuneReps, go, ms);
                 };
                 int best = pick_shape(H);
                 if (forced && forced[0]) {
@@ -280,8 +270,6 @@ struct BatchImpl : BatchBase {
                 float dummy = 0.f;
                 if (!rc) rc = run_shape(best, false, dummy);
             }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         return rc;
     }
 

@@ -680,35 +680,65 @@ int run_cycle(mpfc_ctx* C, int kind) {
 }
 
 // ---- tile-shape autotuner ----------------------------------------------------------
+// Mean duration of one launch when `reps` launches run back to back from a
+// graph, as inside a captured V-cycle.  Launching them from the host instead
+// would time the host's submission rate for the small levels, whose kernels
+// take a few microseconds.
+template <class Fn>
+int time_in_graph(hipStream_t& cap, hipStream_t s, int reps, Fn&& launch, float& ms) {
+    if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < reps; ++r) launch(cap);
+    const hipError_t le = hipGetLastError();
+    const hipError_t ce = hipStreamEndCapture(cap, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(MPFC_EHIP, std::string("tuning graph capture: ") +
+                                   hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    hipGraphExec_t gx = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(MPFC_EHIP, std::string("tuning graph: ") + hipGetErrorString(ie));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipGraphLaunch(gx, s);  // warm
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < 2 && e == hipSuccess; ++r) e = hipGraphLaunch(gx, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float el = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipGraphExecDestroy(gx);
+    if (e != hipSuccess) return fail(MPFC_EHIP, std::string("tuning: ") + hipGetErrorString(e));
+    ms = el / (2.f * reps);
+    return MPFC_OK;
+}
+
+constexpr int kTuneReps = 8;
+
 // For every level with tile launches and every launch kind, time each tile
-// shape whose halo allowance fits (one warm launch, then `reps` launches
-// between two events) and keep the fastest.  The iterates do not depend on
-// the shape (each cell's update is the same arithmetic in every tiling), so
-// tuning changes speed only.  MPFC_TILE_SHAPE=<k> forces shape k instead.
+// shape whose halo allowance fits and keep the fastest (first within 5 %).
+// The iterates do not depend on the shape (each cell's update is the same
+// arithmetic in every tiling), so tuning changes speed only.
+// MPFC_TILE_SHAPE=<k> forces shape k instead.
 template <class Fn>
 int tune_one(mpfc_ctx* C, Level& lv, int kind, int H, Fn&& launch) {
-    hipStream_t s = C->stream;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
     float t[kNumShapes];
     float best = 1e30f;
-    const int reps = 3;
     for (int k = 0; k < kNumShapes; ++k) {
         t[k] = 1e30f;
         if (H > kShapes[k].hmax) continue;
         lv.shape[kind] = k;
-        launch();
-        HIP_TRY(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) launch();
-        HIP_TRY(hipEventRecord(e1, s));
-        HIP_TRY(hipEventSynchronize(e1));
-        HIP_TRY(hipEventElapsedTime(&t[k], e0, e1));
+        int rc = time_in_graph(C->cap_stream, C->stream, kTuneReps, launch, t[k]);
+        if (rc) return rc;
         best = t[k] < best ? t[k] : best;
     }
     lv.shape[kind] = pick_tuned(t, best, H);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     return MPFC_OK;
 }
 
@@ -721,14 +751,13 @@ int autotune(mpfc_ctx* C) {
             for (int kind = 0; kind < SH_KINDS; ++kind) lv.shape[kind] = k;
         return MPFC_OK;
     }
-    hipStream_t s = C->stream;
     const bool nw = C->o.linearization == MPFC_NEWTON;
     const int Hd = round_even(2 * C->o.nu1 + 1), Hu = round_even(2 * C->o.nu2 + 1);
     for (int l = 0; l < C->Lp; ++l) {
         Level& lv = C->L[l];
         for (int up = 0; up < 2; ++up) {
             const int H = up ? (l == 0 ? Hu : 2 * C->o.nu2) : Hd;
-            int rc = tune_one(C, lv, up ? SH_UP : SH_DN, H, [&] {
+            int rc = tune_one(C, lv, up ? SH_UP : SH_DN, H, [&](hipStream_t s) {
                 if (C->p.scheme == 1) {
                     if (nw) vcycle_mpfc_t<MpfcOp<double, 1, true, false>>(C, s, l, up);
                     else vcycle_mpfc_t<MpfcOp<double, 1, false, false>>(C, s, l, up);
@@ -740,7 +769,7 @@ int autotune(mpfc_ctx* C) {
             if (rc) return rc;
             if (C->o.precision == MPFC_MIXED) {
                 const int H32 = up ? 2 * C->o.nu2 : Hd;
-                rc = tune_one(C, lv, up ? SH_UP32 : SH_DN32, H32, [&] {
+                rc = tune_one(C, lv, up ? SH_UP32 : SH_DN32, H32, [&](hipStream_t s) {
                     if (C->p.scheme == 1) {
                         if (nw) vcycle_inner_t<MpfcOp<float, 1, true, true>>(C, s, l, up);
                         else vcycle_inner_t<MpfcOp<float, 1, false, true>>(C, s, l, up);
@@ -753,7 +782,7 @@ int autotune(mpfc_ctx* C) {
             }
             if (C->o.energy) {
                 rc = tune_one(C, lv, up ? SH_PUP : SH_PDN, up ? (l == 0 ? 6 : 4) : 6,
-                              [&] { vcycle_poisson(C, s, l, up); });
+                              [&](hipStream_t s) { vcycle_poisson(C, s, l, up); });
                 if (rc) return rc;
             }
         }
