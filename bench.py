@@ -29,22 +29,23 @@ METRIC = "time-steps/s at 1024² to 1e-10 residual: FP64 MG vs mixed-prec vs lea
 HBM_PEAK_GBPS = 8000.0
 # Algorithmic bytes per finest cell of the two finest-level launches, FP64,
 # scheme 2, V(2,2), per-operation model: one red-black sweep reads u, S, phi^k
-# and writes u (80 B); residual + 2x2 restriction 68 B; prolongation +
-# correction 60 B; residual norm 56 B.
+# and writes u (80 B); residual + 2x2 restriction of u, R r and phi^k 70 B;
+# prolongation + correction 60 B; residual norm 56 B.
 #   down = 2 sweeps + residual/restriction, up = prolongation + 2 sweeps + norm.
-MODEL_BYTES = {"down": 2 * 80.0 + 68.0, "up": 60.0 + 2 * 80.0 + 56.0}
+MODEL_BYTES = {"down": 2 * 80.0 + 70.0, "up": 60.0 + 2 * 80.0 + 56.0}
 # Compulsory traffic of the fused launches: down reads u, S, phi^k (56 B),
-# writes u (24 B) and the coarse u, v, R r (9 quarter fields, 18 B); up reads
-# u, S, phi^k (56 B) and the coarse u, v (6 quarter fields, 12 B), writes u (24 B).
-COMPULSORY_BYTES = {"down": 56.0 + 24.0 + 18.0, "up": 56.0 + 12.0 + 24.0}
+# writes u (24 B) and the coarse u, v, R r, phi^k (10 quarter fields, 20 B); up
+# reads u, S, phi^k (56 B) and the coarse u, v (6 quarter fields, 12 B), writes
+# u (24 B).
+COMPULSORY_BYTES = {"down": 56.0 + 24.0 + 20.0, "up": 56.0 + 12.0 + 24.0}
 # HBM bytes per finest-level launch measured with rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by what the counters read for a 128 MiB copy), per tile
 # shape "TXxTY/HALO", valid only for the kernel sources they were measured on
 # (hash of paper_1208_2643_amd/csrc/*).
 MEASURED_TRAFFIC = {
-    "src": "a6c97f8e59c860af",
-    "down": {"64x32/6": 108142465, "32x32/6": 112935548, "32x16/6": 107991334, "16x16/6": 107892447, "64x16/10": 111877166, "32x16/10": 108048184, "16x16/10": 107947457},
-    "up": {"64x32/6": 109635233, "32x32/6": 107409967, "32x16/6": 103597157, "16x16/6": 103152566, "64x16/10": 103341544, "32x16/10": 103247263, "16x16/10": 103201098},
+    "src": "a72a9a490c045477",
+    "down": {"64x32/6": 110235261, "32x32/6": 115027428, "32x16/6": 110204754, "16x16/6": 109968370, "64x16/10": 114818174, "32x16/10": 110182436, "16x16/10": 110042797},
+    "up": {"64x32/6": 109655583, "32x32/6": 107611363, "32x16/6": 103329636, "16x16/6": 103159489, "64x16/10": 103345607, "32x16/10": 103248760, "16x16/10": 103208424},
 }
 
 
