@@ -35,13 +35,16 @@ class _Model(ctypes.Structure):
 
 @dataclass
 class Params:
-    """Model and discretisation parameters (Sec. 3; App. B)."""
+    """Model and discretisation parameters (Sec. 3; App. B).  bc = (x, y)
+    boundary conditions of the two axes: 0 periodic, 1 homogeneous Neumann
+    (App. A)."""
     eps: float
     beta: float
     M: float
     h: float
     dt: float
     scheme: int
+    bc: tuple = (0, 0)
 
     @property
     def alpha(self) -> float:
@@ -87,6 +90,7 @@ def load():
         "orc_energies": (v, [i, i, d, d, d, _dp, _dp, _dp, _dp]),
         "orc_step": (i, [P, i, i, i, _dp, _dp, _dp, i, i, i, i, d, i,
                          _dp, _dp, _dp, _dp, _dp, _dp]),
+        "orc_set_bc": (v, [i, i]),
         "orc_version": (i, []),
         "orc_num_threads": (i, []),
     }
@@ -100,6 +104,13 @@ def load():
 
 def num_threads() -> int:
     return load().orc_num_threads()
+
+
+def _lib_bc(bc):
+    """The library with boundary conditions bc = (x, y) selected."""
+    lib = load()
+    lib.orc_set_bc(int(bc[0]), int(bc[1]))
+    return lib
 
 
 def _arr(a) -> np.ndarray:
@@ -126,11 +137,11 @@ def coefficients(p: Params):
     return c.value, d.value
 
 
-def laplacian(f, h):
+def laplacian(f, h, bc=(0, 0)):
     f = _arr(f)
     out = np.empty_like(f)
     m, n = _shape(f)
-    load().orc_laplacian(m, n, h, _p(f), _p(out))
+    _lib_bc(bc).orc_laplacian(m, n, h, _p(f), _p(out))
     return out
 
 
@@ -140,7 +151,7 @@ def source(p: Params, phik, phikm1=None, psik=None):
     psik = _arr(psik) if psik is not None else None
     m, n = _shape(phik)
     S = [np.empty_like(phik) for _ in range(3)]
-    load().orc_source(ctypes.byref(p._c()), m, n, _p(phik), _p(phikm1), _p(psik),
+    _lib_bc(p.bc).orc_source(ctypes.byref(p._c()), m, n, _p(phik), _p(phikm1), _p(psik),
                       *[_p(x) for x in S])
     return S
 
@@ -152,7 +163,7 @@ def operator(p: Params, u, phik=None, h=None):
     c, _ = coefficients(p)
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
     out = [np.empty_like(phi) for _ in range(3)]
-    load().orc_operator(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
+    _lib_bc(p.bc).orc_operator(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
                         _p(phi), _p(mu), _p(ka), *[_p(x) for x in out])
     return out
 
@@ -164,7 +175,7 @@ def residual(p: Params, u, f, phik=None, h=None):
     c, _ = coefficients(p)
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
     out = [np.empty_like(phi) for _ in range(3)]
-    load().orc_residual(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
+    _lib_bc(p.bc).orc_residual(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
                         _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3), *[_p(x) for x in out])
     return out
 
@@ -182,7 +193,8 @@ def smooth(p: Params, u, f, phik=None, sweeps=1, newton=True, h=None, order="rb"
     m, n = _shape(phi)
     c, _ = coefficients(p)
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
-    fn = load().orc_smooth if order == "rb" else load().orc_smooth_lex
+    lib = _lib_bc(p.bc)
+    fn = lib.orc_smooth if order == "rb" else lib.orc_smooth_lex
     fn(p.scheme, int(newton), sweeps, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
        _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3))
     return [phi, mu, ka]
@@ -194,7 +206,7 @@ def smooth_color(p: Params, u, f, color, phik=None, newton=True, h=None):
     m, n = _shape(phi)
     c, _ = coefficients(p)
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
-    load().orc_smooth_color(p.scheme, int(newton), color, m, n, p.h if h is None else h, c,
+    _lib_bc(p.bc).orc_smooth_color(p.scheme, int(newton), color, m, n, p.h if h is None else h, c,
                             p.alpha, _p(pk), _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3))
     return [phi, mu, ka]
 
@@ -207,12 +219,12 @@ def restrict(fine):
     return out
 
 
-def prolong_add(coarse, fine):
+def prolong_add(coarse, fine, bc=(0, 0)):
     """Return fine + bilinear interpolation of coarse."""
     coarse = _arr(coarse)
     fine = _arr(fine).copy()
     m, n = _shape(fine)
-    load().orc_prolong_add(m, n, _p(coarse), _p(fine))
+    _lib_bc(bc).orc_prolong_add(m, n, _p(coarse), _p(fine))
     return fine
 
 
@@ -222,7 +234,7 @@ def dense_newton(p: Params, u, f, phik=None, h=None, maxit=50):
     m, n = _shape(phi)
     c, _ = coefficients(p)
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
-    it = load().orc_dense_newton(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
+    it = _lib_bc(p.bc).orc_dense_newton(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
                                  _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3), maxit)
     return [phi, mu, ka], it
 
@@ -236,7 +248,7 @@ def fas_solve(p: Params, u0, S, phik=None, nu1=2, nu2=2, coarsest=2, tol=1e-10,
     c, _ = coefficients(p)
     pk = _arr(phik) if p.scheme == 2 else None
     hist = np.zeros(max_cycles + 1)
-    cyc = load().orc_fas_solve(p.scheme, int(newton), m, n, p.h, c, p.alpha, _p(pk), _p(phi),
+    cyc = _lib_bc(p.bc).orc_fas_solve(p.scheme, int(newton), m, n, p.h, c, p.alpha, _p(pk), _p(phi),
                                _p(mu), _p(ka), _p(S1), _p(S2), _p(S3), nu1, nu2, coarsest,
                                tol, max_cycles, _p(hist))
     ncyc = cyc if cyc >= 0 else -cyc - 1
@@ -248,7 +260,7 @@ def complete_guess(p: Params, phi, S, phik=None):
     m, n = _shape(phi)
     mu, ka = np.empty_like(phi), np.empty_like(phi)
     pk = _arr(phik) if p.scheme == 2 else None
-    load().orc_complete_guess(p.scheme, m, n, p.h, p.alpha, _p(pk), _p(phi), _p(mu), _p(ka),
+    _lib_bc(p.bc).orc_complete_guess(p.scheme, m, n, p.h, p.alpha, _p(pk), _p(phi), _p(mu), _p(ka),
                               _p(_arr(S[1])), _p(_arr(S[2])))
     return [phi.copy(), mu, ka]
 
@@ -257,34 +269,34 @@ def psi_update(p: Params, phinew, phik, psik):
     phinew, phik = _arr(phinew), _arr(phik)
     psik = _arr(psik) if psik is not None else None
     out = np.empty_like(phinew)
-    load().orc_psi_update(p.scheme, phinew.size, p.dt, _p(phinew), _p(phik), _p(psik), _p(out))
+    _lib_bc(p.bc).orc_psi_update(p.scheme, phinew.size, p.dt, _p(phinew), _p(phik), _p(psik), _p(out))
     return out
 
 
 def energy_F(p: Params, phi):
     phi = _arr(phi)
     m, n = _shape(phi)
-    return load().orc_energy_F(m, n, p.h, p.eps, _p(phi))
+    return _lib_bc(p.bc).orc_energy_F(m, n, p.h, p.eps, _p(phi))
 
 
-def grad_sq(f):
+def grad_sq(f, bc=(0, 0)):
     f = _arr(f)
     m, n = _shape(f)
-    return load().orc_grad_sq(m, n, _p(f))
+    return _lib_bc(bc).orc_grad_sq(m, n, _p(f))
 
 
-def poisson(b, h, rtol=1e-14, maxit=100000):
+def poisson(b, h, rtol=1e-14, maxit=100000, bc=(0, 0)):
     b = _arr(b)
     m, n = _shape(b)
     w = np.empty_like(b)
-    it = load().orc_poisson_cg(m, n, h, _p(b), _p(w), rtol, maxit)
+    it = _lib_bc(bc).orc_poisson_cg(m, n, h, _p(b), _p(w), rtol, maxit)
     return w, it
 
 
-def norm_m1_sq(psi, h):
+def norm_m1_sq(psi, h, bc=(0, 0)):
     psi = _arr(psi)
     m, n = _shape(psi)
-    return load().orc_norm_m1_sq(m, n, h, _p(psi))
+    return _lib_bc(bc).orc_norm_m1_sq(m, n, h, _p(psi))
 
 
 def energies(p: Params, phinew, phik, psinew):
@@ -292,7 +304,7 @@ def energies(p: Params, phinew, phik, psinew):
     phinew, phik, psinew = _arr(phinew), _arr(phik), _arr(psinew)
     m, n = _shape(phinew)
     out = np.zeros(4)
-    load().orc_energies(m, n, p.h, p.eps, p.M, _p(phinew), _p(phik), _p(psinew), _p(out))
+    _lib_bc(p.bc).orc_energies(m, n, p.h, p.eps, p.M, _p(phinew), _p(phik), _p(psinew), _p(out))
     return out
 
 
@@ -317,7 +329,7 @@ def step(p: Params, phik, phikm1=None, psik=None, guess=0, nu1=2, nu2=2, coarses
     outs = [np.empty_like(phik) for _ in range(4)]
     hist = np.zeros(max_cycles + 1)
     en = np.zeros(4)
-    cyc = load().orc_step(ctypes.byref(p._c()), int(newton), m, n, _p(phik), _p(phikm1),
+    cyc = _lib_bc(p.bc).orc_step(ctypes.byref(p._c()), int(newton), m, n, _p(phik), _p(phikm1),
                           _p(psik), guess, nu1, nu2, coarsest, tol, max_cycles,
                           *[_p(x) for x in outs], _p(hist), _p(en) if energy else None)
     ncyc = cyc if cyc >= 0 else -cyc - 1

@@ -15,8 +15,10 @@
  *
  * Notation follows the paper: grid m x n, spacing h, time step s, mobility M,
  * damping beta, alpha = 1 - eps.  Cells (i, j), 0 <= i < m, 0 <= j < n, are
- * stored row-major with i (x) fastest: index j*m + i.  Periodic ghost values
- * (App. A, periodic boundary conditions) are realised by index wrap-around.
+ * stored row-major with i (x) fastest: index j*m + i.  Ghost values (App. A)
+ * are realised by index mapping, per axis: periodic boundary conditions by
+ * wrap-around, homogeneous Neumann conditions by repeating the boundary cell
+ * (orc_set_bc selects the conditions; periodic in both directions unless set).
  *
  * Unknown u = (phi, mu, kappa), three m x n fields (App. B.1 / B.2).
  *
@@ -36,7 +38,13 @@
  *    Newton iteration with Gaussian elimination (partial pivoting);
  *  - the residual norm is sqrt(h^2 * sum over the three components of r^2),
  *    the h-weighted discrete l2 norm of App. A applied to all of r;
- *  - scheme-2 coarse operators use phi^k restricted by the same 2x2 average.
+ *  - scheme-2 coarse operators use phi^k restricted by the same 2x2 average;
+ *  - on a homogeneous Neumann boundary the ghost cell (a copy of the boundary
+ *    cell) enters the smoother's neighbour sums with the value it has before
+ *    the cell is updated (ghosts refreshed before every half-sweep), and the
+ *    smoother's local 3x3 matrix stays the interior one; the residual, the
+ *    transfers (the coarse ghost repeats the boundary coarse cell) and the
+ *    coarsest-grid Newton matrix use the ghost rule exactly.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -47,13 +55,26 @@
 
 #define IX(i, j, m) ((size_t)(j) * (size_t)(m) + (size_t)(i))
 
-/* Periodic index: ghost cell 0 is cell m, ghost m+1 is cell 1 (App. A,
- * periodic boundary conditions), written here for 0-based indices. */
-static int wrap(int i, int m) {
-    if (i < 0) return i + m;
-    if (i >= m) return i - m;
+/* Boundary conditions of the two axes (App. A): 0 = periodic, 1 = homogeneous
+ * Neumann.  Process-wide setting read by every routine below. */
+static int g_neumann_x = 0, g_neumann_y = 0;
+
+void orc_set_bc(int neumann_x, int neumann_y) {
+    g_neumann_x = neumann_x != 0;
+    g_neumann_y = neumann_y != 0;
+}
+
+/* Cell index of the ghost or interior cell i in [-1, m] along one axis, for
+ * 0-based indices.  Periodic (eqs. per-bcs): ghost 0 is cell m and ghost m+1
+ * is cell 1 in the paper's 1-based numbering.  Homogeneous Neumann (eqs.
+ * h-n-bcs): ghost 0 repeats cell 1 and ghost m+1 repeats cell m. */
+static int ghost_index(int i, int m, int neumann) {
+    if (i < 0) return neumann ? 0 : i + m;
+    if (i >= m) return neumann ? m - 1 : i - m;
     return i;
 }
+static int wrapx(int i, int m) { return ghost_index(i, m, g_neumann_x); }
+static int wrapy(int j, int n) { return ghost_index(j, n, g_neumann_y); }
 
 /* ------------------------------------------------------------------------ */
 /* Discrete operators (App. A).                                             */
@@ -61,10 +82,10 @@ static int wrap(int i, int m) {
 
 /* Standard five-point Laplacian, Delta_h f = (f_E + f_W + f_N + f_S - 4 f)/h^2. */
 static double lap_at(const double *f, int i, int j, int m, int n, double h) {
-    double fe = f[IX(wrap(i + 1, m), j, m)];
-    double fw = f[IX(wrap(i - 1, m), j, m)];
-    double fn = f[IX(i, wrap(j + 1, n), m)];
-    double fs = f[IX(i, wrap(j - 1, n), m)];
+    double fe = f[IX(wrapx(i + 1, m), j, m)];
+    double fw = f[IX(wrapx(i - 1, m), j, m)];
+    double fn = f[IX(i, wrapy(j + 1, n), m)];
+    double fs = f[IX(i, wrapy(j - 1, n), m)];
     double fc = f[IX(i, j, m)];
     return (fe + fw + fn + fs - 4.0 * fc) / (h * h);
 }
@@ -282,8 +303,8 @@ void orc_prolong_add(int m, int n, const double *coarse, double *fine) {
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < m; ++i) {
             int I = i / 2, J = j / 2;
-            int Is = wrap((i % 2 == 0) ? I - 1 : I + 1, mc);
-            int Js = wrap((j % 2 == 0) ? J - 1 : J + 1, nc);
+            int Is = wrapx((i % 2 == 0) ? I - 1 : I + 1, mc);
+            int Js = wrapy((j % 2 == 0) ? J - 1 : J + 1, nc);
             double v = 9.0 * coarse[IX(I, J, mc)] + 3.0 * coarse[IX(Is, J, mc)] +
                        3.0 * coarse[IX(I, Js, mc)] + 1.0 * coarse[IX(Is, Js, mc)];
             fine[IX(i, j, m)] += v / 16.0;
@@ -349,8 +370,8 @@ int orc_dense_newton(int scheme, int m, int n, double h, double c, double alpha,
         for (int j = 0; j < n; ++j)
             for (int i = 0; i < m; ++i) {
                 int q = (int)IX(i, j, m);
-                int nb[4] = {(int)IX(wrap(i + 1, m), j, m), (int)IX(wrap(i - 1, m), j, m),
-                             (int)IX(i, wrap(j + 1, n), m), (int)IX(i, wrap(j - 1, n), m)};
+                int nb[4] = {(int)IX(wrapx(i + 1, m), j, m), (int)IX(wrapx(i - 1, m), j, m),
+                             (int)IX(i, wrapy(j + 1, n), m), (int)IX(i, wrapy(j - 1, n), m)};
                 double xk = phik ? phik[q] : 0.0;
                 /* row of N^(1): phi - c Lap(mu) */
                 A[(size_t)q * nn + q] += 1.0;
@@ -564,8 +585,8 @@ double orc_energy_F(int m, int n, double h, double eps, const double *phi) {
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < m; ++i) {
             double x = phi[IX(i, j, m)];
-            double dx = phi[IX(wrap(i + 1, m), j, m)] - x;
-            double dy = phi[IX(i, wrap(j + 1, n), m)] - x;
+            double dx = phi[IX(wrapx(i + 1, m), j, m)] - x;
+            double dy = phi[IX(i, wrapy(j + 1, n), m)] - x;
             double L = lap_at(phi, i, j, m, n, h);
             s4 += x * x * x * x;
             s2 += x * x;
@@ -581,14 +602,14 @@ double orc_grad_sq(int m, int n, const double *f) {
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < m; ++i) {
             double x = f[IX(i, j, m)];
-            double dx = f[IX(wrap(i + 1, m), j, m)] - x;
-            double dy = f[IX(i, wrap(j + 1, n), m)] - x;
+            double dx = f[IX(wrapx(i + 1, m), j, m)] - x;
+            double dy = f[IX(i, wrapy(j + 1, n), m)] - x;
             sg += dx * dx + dy * dy;
         }
     return sg;
 }
 
-/* Solve -Lap_h w = b - mean(b), mean(w) = 0, periodic, by conjugate gradients
+/* Solve -Lap_h w = b - mean(b), mean(w) = 0, by conjugate gradients
  * (the operator is symmetric positive definite on mean-zero functions).
  * Iterates until ||residual||_2 <= rtol * ||b - mean(b)||_2.
  * Returns the iteration count (or -1 if maxit was reached). */
