@@ -51,14 +51,20 @@ enum { MPFC_FP64 = 0, MPFC_MIXED = 1 };                           /* precision *
 enum { MPFC_GUESS_PREV = 0, MPFC_GUESS_EXTRAP = 1,                 /* initial guess */
        MPFC_GUESS_CNN = 2 /* learned, with the extrapolated guess as fallback (mpfc_cnn_load) */ };
 enum { MPFC_NEWTON = 0, MPFC_PICARD = 1 };                        /* linearisation */
+/* Boundary conditions (App. A): every axis is periodic (eqs. per-bcs) unless
+ * its bit is set, then homogeneous Neumann (eqs. h-n-bcs: the ghost cell
+ * repeats the boundary cell).  Sec. 4.3 runs periodic in x, Neumann in y. */
+enum { MPFC_BC_PERIODIC = 0, MPFC_BC_NEUMANN_X = 1, MPFC_BC_NEUMANN_Y = 2 };
 
 /* Model and discretisation (Sec. 2, Sec. 3): alpha = 1 - eps; dt is the time
  * step s.  scheme 1: first-order convex splitting (Sec. 3.1); scheme 2:
- * second-order scheme (Sec. 3.2).  Requires h > 0, dt > 0, M > 0, beta >= 0,
- * eps <= 1. */
+ * second-order scheme (Sec. 3.2).  bc: MPFC_BC_* bits (0 = periodic).
+ * Requires h > 0, dt > 0, M > 0, beta >= 0, eps <= 1.  The learned guess
+ * (MPFC_GUESS_CNN) needs periodic boundaries. */
 typedef struct {
     double eps, beta, M, h, dt;
     int scheme;
+    int bc;
 } mpfc_params;
 
 /* Solver options.  nu1/nu2: pre/post red-black smoothing passes per level
@@ -174,18 +180,20 @@ int mpfc_version(void);
 
 /* `sweeps` red-black nonlinear Gauss-Seidel passes (App. B), red
  * ((i+j) even) first, Newton (linearization 0) or Picard (1) local
- * linearisation, in place on (d_phi, d_mu, d_kappa); m, n >= 4.  Runs the
- * fused tile kernel of the V-cycle and allocates a scratch copy of u. */
+ * linearisation, in place on (d_phi, d_mu, d_kappa); m, n >= 4; bc:
+ * MPFC_BC_* bits.  Runs the fused tile kernel of the V-cycle and allocates a
+ * scratch copy of u. */
 int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double c, double alpha,
                    const double *d_phik, double *d_phi, double *d_mu, double *d_kappa,
                    const double *d_f1, const double *d_f2, const double *d_f3, int sweeps,
-                   void *stream);
+                   int bc, void *stream);
 
-/* r = f - N(u) (App. B), three output arrays. */
+/* r = f - N(u) (App. B), three output arrays; bc: MPFC_BC_* bits. */
 int mpfc_op_residual(int scheme, int m, int n, double h, double c, double alpha,
                      const double *d_phik, const double *d_phi, const double *d_mu,
                      const double *d_kappa, const double *d_f1, const double *d_f2,
-                     const double *d_f3, double *d_r1, double *d_r2, double *d_r3, void *stream);
+                     const double *d_f3, double *d_r1, double *d_r2, double *d_r3, int bc,
+                     void *stream);
 
 /* Source S of the step (App. B.1 / B.2) from phi^k, phi^{k-1}, psi^k. */
 int mpfc_op_source(const mpfc_params *p, int m, int n, const double *d_phik,

@@ -31,7 +31,8 @@ MPFC_NEWTON, MPFC_PICARD = 0, 1
 
 class mpfc_params(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("beta", ctypes.c_double), ("M", ctypes.c_double),
-                ("h", ctypes.c_double), ("dt", ctypes.c_double), ("scheme", ctypes.c_int)]
+                ("h", ctypes.c_double), ("dt", ctypes.c_double), ("scheme", ctypes.c_int),
+                ("bc", ctypes.c_int)]
 
 
 class mpfc_opts(ctypes.Structure):
@@ -55,6 +56,7 @@ class mpfc_sim_desc(ctypes.Structure):
 
 
 MPFC_BATCH_MAX = 4096
+MPFC_BC_PERIODIC, MPFC_BC_NEUMANN_X, MPFC_BC_NEUMANN_Y = 0, 1, 2
 
 
 class mpfc_cnn_hparams(ctypes.Structure):
@@ -90,9 +92,9 @@ SIGNATURES = {
     "mpfc_last_error": (ctypes.c_char_p, []),
     "mpfc_version": (_i, []),
     "mpfc_op_smooth": (_i, [_i, _i, _i, _i, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i,
-                            _vp]),
+                            _i, _vp]),
     "mpfc_op_residual": (_i, [_i, _i, _i, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                              _vp, _vp, _vp]),
+                              _vp, _vp, _i, _vp]),
     "mpfc_op_source": (_i, [ctypes.POINTER(mpfc_params), _i, _i, _vp, _vp, _vp, _vp, _vp, _vp,
                             _vp]),
     "mpfc_op_restrict": (_i, [_i, _i, _vp, _vp, _vp]),

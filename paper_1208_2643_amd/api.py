@@ -19,16 +19,19 @@ from . import _lib as L
 
 @dataclass
 class Params:
-    """Model/discretisation parameters (Sec. 2-3): alpha = 1 - eps."""
+    """Model/discretisation parameters (Sec. 2-3): alpha = 1 - eps.  bc:
+    boundary conditions, MPFC_BC_NEUMANN_X | MPFC_BC_NEUMANN_Y bits (App. A;
+    0 = periodic in both directions)."""
     eps: float
     beta: float
     M: float
     h: float
     dt: float
     scheme: int
+    bc: int = 0
 
     def c(self) -> L.mpfc_params:
-        return L.mpfc_params(self.eps, self.beta, self.M, self.h, self.dt, self.scheme)
+        return L.mpfc_params(self.eps, self.beta, self.M, self.h, self.dt, self.scheme, self.bc)
 
 
 @dataclass
@@ -323,7 +326,7 @@ def op_smooth(p: Params, u, f, phik=None, sweeps=1, newton=True, h=None):
     c, _ = coefficients(p)
     L.check(lib.mpfc_op_smooth(p.scheme, 0 if newton else 1, m, n, p.h if h is None else h, c,
                                1.0 - p.eps, _ptr(phik), _ptr(phi), _ptr(mu), _ptr(ka),
-                               _ptr(f[0]), _ptr(f[1]), _ptr(f[2]), sweeps, _stream()))
+                               _ptr(f[0]), _ptr(f[1]), _ptr(f[2]), sweeps, p.bc, _stream()))
 
 
 def op_residual(p: Params, u, f, phik=None, h=None):
@@ -335,7 +338,7 @@ def op_residual(p: Params, u, f, phik=None, h=None):
     L.check(lib.mpfc_op_residual(p.scheme, m, n, p.h if h is None else h, c, 1.0 - p.eps,
                                  _ptr(phik), _ptr(phi), _ptr(mu), _ptr(ka), _ptr(f[0]),
                                  _ptr(f[1]), _ptr(f[2]), _ptr(r[0]), _ptr(r[1]), _ptr(r[2]),
-                                 _stream()))
+                                 p.bc, _stream()))
     return r
 
 

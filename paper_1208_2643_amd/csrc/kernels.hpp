@@ -2,10 +2,11 @@
 //
 // One implicit step of either convex-splitting scheme (first order: Sec. 3.1,
 // second order: Sec. 3.2) is the solve of N(u) = S for u = (phi, mu, kappa)
-// on a periodic cell-centred grid (App. B.1 / B.2), followed by the psi update
-// (eqs. discrete_1_b / discrete_2_b).  Storage: every field is an m x n array,
-// row-major with x fastest (index j*m + i); periodic ghosts (App. A) are index
-// wrap-arounds, so m and n are powers of two and wrapping is a bit mask.
+// on a cell-centred grid (App. B.1 / B.2), followed by the psi update (eqs.
+// discrete_1_b / discrete_2_b).  Storage: every field is an m x n array,
+// row-major with x fastest (index j*m + i); ghost cells (App. A) are index
+// maps per axis: periodic wrap-around (m and n are powers of two, so a bit
+// mask) or, on a homogeneous Neumann axis, the reflection about the boundary.
 //
 // Kernels are templated on the arithmetic type T (double, or float for the
 // inner cycles of mixed precision) and on the scheme.  DEFECT = true selects
@@ -79,13 +80,31 @@ struct LevelOp {
     T e;     // 1 (scheme 1) or 1/2 (scheme 2): N^(3) = kappa - e Lap phi
 };
 
+// Boundary conditions, per axis (App. A): periodic (eqs. per-bcs) unless the
+// axis' bit is set, then homogeneous Neumann (eqs. h-n-bcs).
+constexpr int BC_NEUMANN_X = 1, BC_NEUMANN_Y = 2;
+
 struct Grid {
     int m, n;       // powers of two
     int lm, ln;     // log2 m, log2 n
+    int bc;         // BC_NEUMANN_X | BC_NEUMANN_Y bits
 };
 
-__device__ __forceinline__ int wrapx(int i, const Grid& g) { return i & (g.m - 1); }
-__device__ __forceinline__ int wrapy(int j, const Grid& g) { return j & (g.n - 1); }
+// Cell holding the value of (ghost or interior) cell i along an axis of m
+// cells.  Periodic: wrap-around.  Neumann: the even reflection about the
+// boundary edges (period 2m), so the first ghost repeats the boundary cell
+// and deeper ghosts (tile halos) mirror the interior.
+__device__ __forceinline__ int axis_index(int i, int m, bool neumann) {
+    if (!neumann) return i & (m - 1);
+    const int r = i & (2 * m - 1);
+    return r < m ? r : 2 * m - 1 - r;
+}
+__device__ __forceinline__ int wrapx(int i, const Grid& g) {
+    return axis_index(i, g.m, g.bc & BC_NEUMANN_X);
+}
+__device__ __forceinline__ int wrapy(int j, const Grid& g) {
+    return axis_index(j, g.n, g.bc & BC_NEUMANN_Y);
+}
 __device__ __forceinline__ size_t at(int i, int j, const Grid& g) {
     return ((size_t)j << g.lm) + (size_t)i;
 }

@@ -54,7 +54,9 @@ int ilog2(int v) {
 }
 int round_even(int v) { return (v + 1) & ~1; }
 
-Grid make_grid(int m, int n) { return Grid{m, n, ilog2(m), ilog2(n)}; }
+static_assert(BC_NEUMANN_X == MPFC_BC_NEUMANN_X && BC_NEUMANN_Y == MPFC_BC_NEUMANN_Y,
+              "boundary-condition bits of the kernels and the C interface agree");
+Grid make_grid(int m, int n, int bc) { return Grid{m, n, ilog2(m), ilog2(n), bc}; }
 
 constexpr int NT = 256;
 const dim3 B2(64, 4);
@@ -228,6 +230,7 @@ void tile_dims(const Level& lv, int shape, int& tx, int& ty) {
 
 CoarseGeom coarse_geom(const mpfc_ctx* C) {
     CoarseGeom G{};
+    G.bc = C->p.bc;
     G.nlev = (int)C->L.size() - C->Lp;
     int off = 0;
     for (int k = 0; k < G.nlev; ++k) {
@@ -791,25 +794,40 @@ int autotune(mpfc_ctx* C) {
     return MPFC_OK;
 }
 
-// Periodic mean-zero Green's matrix of -Lap_h on an m x n grid of spacing h,
-// by the discrete Fourier series: G_pq = (1/(mn)) sum_{k != 0} cos(...)/lambda_k.
-void green_matrix(int m, int n, double h, std::vector<double>& G) {
+// Mean-zero Green's matrix of -Lap_h on an m x n grid of spacing h with the
+// boundary conditions `bc`, from the eigen-decomposition of the separable
+// operator: G_pq = sum over modes k != 0 of v_k(p) v_k(q) / lambda_k.  Per
+// axis of N cells, periodic: v_j(i) v_j(i') summed over the pair j, N - j is
+// cos(2 pi j (i - i') / N) / N with lambda = (4/h^2) sin^2(pi j / N);
+// Neumann: cosine modes w_j^2 cos(pi j (i + 1/2) / N) cos(pi j (i' + 1/2) / N),
+// w_0^2 = 1/N, w_j^2 = 2/N, lambda = (4/h^2) sin^2(pi j / (2N)).
+void green_matrix(int m, int n, double h, int bc, std::vector<double>& G) {
     const int N = m * n;
     G.assign((size_t)N * N, 0.0);
     const double pi = 3.14159265358979323846;
+    auto mode = [&](int len, bool neumann, int j, int i, int i2, double& lam) {
+        if (!neumann) {
+            const double sn = std::sin(pi * j / len);
+            lam = 4.0 / (h * h) * sn * sn;
+            return std::cos(2.0 * pi * j * (double)(i - i2) / len) / len;
+        }
+        const double sn = std::sin(pi * j / (2.0 * len));
+        lam = 4.0 / (h * h) * sn * sn;
+        const double w2 = j == 0 ? 1.0 / len : 2.0 / len;
+        return w2 * std::cos(pi * j * (i + 0.5) / len) * std::cos(pi * j * (i2 + 0.5) / len);
+    };
     for (int a = 0; a < N; ++a)
         for (int b = 0; b < N; ++b) {
-            const int di = (a % m) - (b % m), dj = (a / m) - (b / m);
             double s = 0.0;
             for (int p = 0; p < m; ++p)
                 for (int q = 0; q < n; ++q) {
                     if (p == 0 && q == 0) continue;
-                    const double lam = 4.0 / (h * h) *
-                                       (std::sin(pi * p / m) * std::sin(pi * p / m) +
-                                        std::sin(pi * q / n) * std::sin(pi * q / n));
-                    s += std::cos(2.0 * pi * ((double)p * di / m + (double)q * dj / n)) / lam;
+                    double lx, ly;
+                    const double vx = mode(m, bc & BC_NEUMANN_X, p, a % m, b % m, lx);
+                    const double vy = mode(n, bc & BC_NEUMANN_Y, q, a / m, b / m, ly);
+                    s += vx * vy / (lx + ly);
                 }
-            G[(size_t)a * N + b] = s / N;
+            G[(size_t)a * N + b] = s;
         }
 }
 
@@ -822,6 +840,8 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
     if (!(p->M > 0) || !std::isfinite(p->M)) return fail(MPFC_EINVAL, "M must be > 0");
     if (!(p->beta >= 0) || !std::isfinite(p->beta)) return fail(MPFC_EINVAL, "beta must be >= 0");
     if (!(p->eps <= 1.0) || !std::isfinite(p->eps)) return fail(MPFC_EINVAL, "eps must be <= 1");
+    if (p->bc < 0 || p->bc > (MPFC_BC_NEUMANN_X | MPFC_BC_NEUMANN_Y))
+        return fail(MPFC_EINVAL, "bc must combine MPFC_BC_NEUMANN_X and MPFC_BC_NEUMANN_Y bits");
     if (!is_pow2(m) || !is_pow2(n) || m < 2 || n < 2)
         return fail(MPFC_EINVAL, "m and n must be powers of two >= 2");
     if ((long long)m * n > (1LL << 28)) return fail(MPFC_EINVAL, "grid too large (m*n > 2^28)");
@@ -836,6 +856,8 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
     if (!(o->guess == MPFC_GUESS_PREV || o->guess == MPFC_GUESS_EXTRAP ||
           o->guess == MPFC_GUESS_CNN))
         return fail(MPFC_EINVAL, "unknown guess mode");
+    if (o->guess == MPFC_GUESS_CNN && p->bc != 0)
+        return fail(MPFC_EINVAL, "the learned guess (periodic convolutions) needs periodic boundaries");
     if (!(o->linearization == MPFC_NEWTON || o->linearization == MPFC_PICARD))
         return fail(MPFC_EINVAL, "unknown linearization");
     if (!(o->diverge > 1.0)) return fail(MPFC_EINVAL, "diverge must be > 1");
@@ -1122,7 +1144,7 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
         double h = p->h;
         for (;;) {
             Level lv;
-            lv.m = mm; lv.n = nn; lv.h = h; lv.g = make_grid(mm, nn);
+            lv.m = mm; lv.n = nn; lv.h = h; lv.g = make_grid(mm, nn, p->bc);
             lv.tiled = (long long)mm * nn > CP_CELLS;
             C->L.push_back(lv);
             if ((mm < nn ? mm : nn) <= o->coarsest) break;
@@ -1199,7 +1221,7 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
     }
     layout((double*)C->arena);
     std::vector<double> G;
-    green_matrix(Lc.m, Lc.n, Lc.h, G);
+    green_matrix(Lc.m, Lc.n, Lc.h, p->bc, G);
     e = hipHostMalloc((void**)&C->host_st, sizeof(CycleState) * 2, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&C->host_buf, sizeof(double) * (size_t)(o->max_cycles + 128),
@@ -1346,10 +1368,10 @@ int mpfc_energies(mpfc_ctx* C, const double* phi, const double* phi_prev, const 
 // ping-pong between launches.
 int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double c, double alpha,
                    const double* phik, double* phi, double* mu, double* ka, const double* f1,
-                   const double* f2, const double* f3, int sweeps, void* stream) {
+                   const double* f2, const double* f3, int sweeps, int bc, void* stream) {
     if (!(scheme == 1 || scheme == 2) || !is_pow2(m) || !is_pow2(n) || m < 2 || n < 2 ||
         sweeps < 0 || !(h > 0) || !phi || !mu || !ka || !f1 || !f2 || !f3 ||
-        (scheme == 2 && !phik))
+        (scheme == 2 && !phik) || bc < 0 || bc > 3)
         return fail(MPFC_EINVAL, "mpfc_op_smooth: bad arguments");
     if (m < 4 || n < 4) return fail(MPFC_EINVAL, "mpfc_op_smooth: m, n >= 4");
     hipStream_t s = (hipStream_t)stream;
@@ -1364,7 +1386,7 @@ int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double
     lop.al = scheme == 1 ? alpha : 0.5 * alpha;
     lop.e = scheme == 1 ? 1.0 : 0.5;
     Level lv;
-    lv.m = m; lv.n = n; lv.g = make_grid(m, n);
+    lv.m = m; lv.n = n; lv.g = make_grid(m, n, bc);
     int done = 0;
     while (done < sweeps) {
         const int k = (sweeps - done) >= 2 ? 2 : 1;
@@ -1409,10 +1431,10 @@ int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double
 int mpfc_op_residual(int scheme, int m, int n, double h, double c, double alpha,
                      const double* phik, const double* phi, const double* mu, const double* ka,
                      const double* f1, const double* f2, const double* f3, double* r1, double* r2,
-                     double* r3, void* stream) {
+                     double* r3, int bc, void* stream) {
     if (!(scheme == 1 || scheme == 2) || !is_pow2(m) || !is_pow2(n) || m < 2 || n < 2 ||
         !(h > 0) || !phi || !mu || !ka || !f1 || !f2 || !f3 || !r1 || !r2 || !r3 ||
-        (scheme == 2 && !phik))
+        (scheme == 2 && !phik) || bc < 0 || bc > 3)
         return fail(MPFC_EINVAL, "mpfc_op_residual: bad arguments");
     Fields<double> F;
     F.phi = const_cast<double*>(phi); F.mu = const_cast<double*>(mu); F.ka = const_cast<double*>(ka);
@@ -1421,7 +1443,7 @@ int mpfc_op_residual(int scheme, int m, int n, double h, double c, double alpha,
     op.ih2 = 1.0 / (h * h); op.c = c;
     op.al = scheme == 1 ? alpha : 0.5 * alpha;
     op.e = scheme == 1 ? 1.0 : 0.5;
-    const Grid g = make_grid(m, n);
+    const Grid g = make_grid(m, n, bc);
     hipStream_t s = (hipStream_t)stream;
     if (scheme == 1)
         hipLaunchKernelGGL((k_residual_field<double, 1, false>), grid2(m, n), B2, 0, s, F, op, g,
@@ -1436,12 +1458,13 @@ int mpfc_op_residual(int scheme, int m, int n, double h, double c, double alpha,
 int mpfc_op_source(const mpfc_params* p, int m, int n, const double* phik, const double* phikm1,
                    const double* psik, double* S1, double* S2, double* S3, void* stream) {
     if (!p || !(p->scheme == 1 || p->scheme == 2) || !is_pow2(m) || !is_pow2(n) || m < 2 ||
-        n < 2 || !(p->h > 0) || !(p->dt > 0) || !phik || !psik || !S1 || !S2 || !S3)
+        n < 2 || !(p->h > 0) || !(p->dt > 0) || !phik || !psik || !S1 || !S2 || !S3 ||
+        p->bc < 0 || p->bc > 3)
         return fail(MPFC_EINVAL, "mpfc_op_source: bad arguments");
     if (!phikm1) phikm1 = phik;
     const double q = p->scheme == 1 ? 1.0 : 2.0;
     const double d = q / (p->beta + q / p->dt);
-    const Grid g = make_grid(m, n);
+    const Grid g = make_grid(m, n, p->bc);
     hipStream_t s = (hipStream_t)stream;
     if (p->scheme == 1)
         hipLaunchKernelGGL((k_source<1>), grid2(m, n), B2, 0, s, g, 1.0 / (p->h * p->h), d,
@@ -1457,7 +1480,7 @@ int mpfc_op_restrict(int m, int n, const double* fine, double* coarse, void* str
     if (!is_pow2(m) || !is_pow2(n) || m < 2 || n < 2 || !fine || !coarse)
         return fail(MPFC_EINVAL, "mpfc_op_restrict: bad arguments");
     hipLaunchKernelGGL((k_restrict<double, double>), grid2(m / 2, n / 2), B2, 0,
-                       (hipStream_t)stream, make_grid(m, n), fine, coarse);
+                       (hipStream_t)stream, make_grid(m, n, 0), fine, coarse);
     HIP_TRY(hipGetLastError());
     return MPFC_OK;
 }

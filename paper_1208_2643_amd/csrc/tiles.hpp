@@ -155,7 +155,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
     // 1. u (tile + halo) into LDS, coalesced along rows.
     for (int q = t; q < LX * LY; q += NT) {
         const int y = q / LX, x = q - y * LX;
-        const size_t gq = at((x0 + x) & (g.m - 1), (y0 + y) & (g.n - 1), g);
+        const size_t gq = at(wrapx(x0 + x, g), wrapy(y0 + y, g), g);
 #pragma unroll
         for (int f = 0; f < NF; ++f) U[f][(x + y) & 1][y][x >> 1] = A.zero_in ? T(0) : A.uin[f][gq];
     }
@@ -183,7 +183,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
             const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
             const int x = 2 * bx + dx, y = 2 * by + dy;
             if (x < 1 || y < 1 || x >= LX - 1 || y >= LY - 1) continue;  // never updated
-            const size_t gq = at((x0 + x) & (g.m - 1), (y0 + y) & (g.n - 1), g);
+            const size_t gq = at(wrapx(x0 + x, g), wrapy(y0 + y, g), g);
             if constexpr (Op::XK) xkr[s][c] = A.xk[gq];
             if constexpr (Op::PB) pbr[s][c] = A.pb[gq];
 #pragma unroll
@@ -200,7 +200,8 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
         const int cx0 = (x0 >> 1) - 1, cy0 = (y0 >> 1) - 1;
         for (int q = t; q < CX * CY; q += NT) {
             const int cy = q / CX, cx = q - cy * CX;
-            const size_t gq = (size_t)((cy0 + cy) & (nc - 1)) * mc + ((cx0 + cx) & (mc - 1));
+            const size_t gq = (size_t)axis_index(cy0 + cy, nc, g.bc & BC_NEUMANN_Y) * mc +
+                              axis_index(cx0 + cx, mc, g.bc & BC_NEUMANN_X);
 #pragma unroll
             for (int f = 0; f < NF; ++f) E[f][cy][cx] = A.cuH[f][gq] - A.cvH[f][gq];
         }
@@ -253,6 +254,9 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
                 for (int f = 0; f < NF; ++f) fr[s][c][f] += N[f];
             }
         }
+        // every N(u) above reads u as loaded: no pass may write before all
+        // waves are done (waves with a second owned block finish later)
+        __syncthreads();
     }
 
     // 4. red-black passes; pass p is exact on cells at distance >= p.  The
@@ -286,10 +290,47 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
             }
         }
     };
+    // Neumann boundaries: halo cells outside the grid hold the even reflection
+    // of interior cells (App. A ghost rule, extended through the halo).  A pass
+    // also relaxes them as if they were cells; afterwards they are restored
+    // from their mirror cells, x first, then y (corners get both reflections),
+    // so every relaxed grid cell reads ghosts equal to its mirror's value from
+    // before the pass, as in a global sweep.
+    const bool mir_x = (g.bc & BC_NEUMANN_X) && (x0 < 0 || x0 + LX > g.m);
+    const bool mir_y = (g.bc & BC_NEUMANN_Y) && (y0 < 0 || y0 + LY > g.n);
+    auto restore_ghosts = [&]() {
+        if (mir_x) {
+            for (int q = t; q < 2 * H * LY; q += NT) {
+                const int y = q / (2 * H), k = q - y * (2 * H);
+                const int x = k < H ? k : LX - 2 * H + k;
+                const int gx = x0 + x;
+                if (gx >= 0 && gx < g.m) continue;
+                const int xm = axis_index(gx, g.m, true) - x0;
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+                    U[f][(x + y) & 1][y][x >> 1] = U[f][(xm + y) & 1][y][xm >> 1];
+            }
+            __syncthreads();
+        }
+        if (mir_y) {
+            for (int q = t; q < 2 * H * LX; q += NT) {
+                const int k = q / LX, x = q - k * LX;
+                const int y = k < H ? k : LY - 2 * H + k;
+                const int gy = y0 + y;
+                if (gy >= 0 && gy < g.n) continue;
+                const int ym = axis_index(gy, g.n, true) - y0;
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+                    U[f][(x + y) & 1][y][x >> 1] = U[f][(x + ym) & 1][ym][x >> 1];
+            }
+            __syncthreads();
+        }
+    };
     for (int p = 1; p <= A.nsweep; ++p) {
         if (((p - 1) & 1) == 0) pass(std::integral_constant<int, 0>{}, p);
         else pass(std::integral_constant<int, 1>{}, p);
         __syncthreads();
+        restore_ghosts();
     }
 
     // 5. interior u back to global memory, coalesced along rows.
@@ -430,6 +471,7 @@ constexpr int CP_MAXLEV = 12;
 constexpr int CP_THREADS = 512;  // threads of the persistent workgroup
 
 struct CoarseGeom {
+    int bc;               // boundary conditions (BC_NEUMANN_X | BC_NEUMANN_Y bits)
     int nlev;             // levels in this kernel (top first)
     int m[CP_MAXLEV], n[CP_MAXLEV], lm[CP_MAXLEV];
     int off[CP_MAXLEV];   // cell offset of each level in the LDS arrays
@@ -463,17 +505,21 @@ __device__ __forceinline__ void coarse_solve_mpfc(const Op& op, typename Op::rea
                                                   const typename Op::real (&f)[3 * NC],
                                                   const typename Op::real* xk,
                                                   const typename Op::real* pb, int m, int lm,
-                                                  int n, int maxit, typename Op::real tol) {
+                                                  int n, int bc, int maxit, typename Op::real tol) {
     using T = typename Op::real;
     const T c = op.op.c, e = op.op.e, al = op.op.al;
-    // Laplacian matrix of the periodic m x n grid (a 2-cell direction couples
-    // each cell twice to its one neighbour).
+    // Laplacian matrix of the m x n grid with its ghost rule (periodic: a
+    // 2-cell direction couples each cell twice to its one neighbour; Neumann:
+    // the ghost beside a boundary cell is that cell itself).
+    const bool nx = bc & BC_NEUMANN_X, ny = bc & BC_NEUMANN_Y;
     T L[NC][NC];
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
         const int i = a & (m - 1), j = a >> lm;
-        const int e0 = ((i + 1) & (m - 1)) + (j << lm), e1 = ((i - 1) & (m - 1)) + (j << lm);
-        const int e2 = i + (((j + 1) & (n - 1)) << lm), e3 = i + (((j - 1) & (n - 1)) << lm);
+        const int e0 = axis_index(i + 1, m, nx) + (j << lm);
+        const int e1 = axis_index(i - 1, m, nx) + (j << lm);
+        const int e2 = i + (axis_index(j + 1, n, ny) << lm);
+        const int e3 = i + (axis_index(j - 1, n, ny) << lm);
 #pragma unroll
         for (int b = 0; b < NC; ++b) {
             const int k = (b == a ? -4 : 0) + (b == e0) + (b == e1) + (b == e2) + (b == e3);
@@ -681,11 +727,13 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
         else { o.ih2 = ldexp(op_top.ih2, -2 * l); o.h2 = ldexp(op_top.h2, 2 * l); }
         return o;
     };
-    // sum of the four periodic neighbours of cell (i, j) of an m x n level
+    // sum of the four neighbours (ghost rule of each axis) of cell (i, j) of
+    // an m x n level
+    const bool nbx = G.bc & BC_NEUMANN_X, nby = G.bc & BC_NEUMANN_Y;
     auto nsum_l = [&](const T* a, int i, int j, int m, int lm, int n) {
         const int r = j << lm;
-        return (a[((i + 1) & (m - 1)) + r] + a[((i - 1) & (m - 1)) + r]) +
-               (a[i + (((j + 1) & (n - 1)) << lm)] + a[i + (((j - 1) & (n - 1)) << lm)]);
+        return (a[axis_index(i + 1, m, nbx) + r] + a[axis_index(i - 1, m, nbx) + r]) +
+               (a[i + (axis_index(j + 1, n, nby) << lm)] + a[i + (axis_index(j - 1, n, nby) << lm)]);
     };
     auto complete_rhs = [&](int l) {
         const Op o = opl(l);
@@ -775,7 +823,8 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
                 T* xkp = Op::XK ? &Sxk[off] : nullptr;
                 T* pbp = Op::PB ? &Spb[off] : nullptr;
                 coarse_solve_mpfc<Op, NC>(o, &Su[0][off], &Su[1][off], &Su[2][off], fbuf, xkp, pbp,
-                                          G.m[l], G.lm[l], G.n[l], A.newton_maxit, A.newton_tol);
+                                          G.m[l], G.lm[l], G.n[l], G.bc, A.newton_maxit,
+                                          A.newton_tol);
             }
         } else {
             coarse_solve_poisson<T>(&Su[0][off], &Sf[0][off], &Sv[0][off], A.G, nc);
@@ -788,8 +837,8 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
         const int mc = G.m[l + 1], nc = G.n[l + 1], offc = G.off[l + 1];
         for (int q = t; q < m * n; q += NTP) {
             const int i = q & (m - 1), j = q >> lm, I = i >> 1, J = j >> 1;
-            const int Is = ((i & 1) ? I + 1 : I - 1) & (mc - 1);
-            const int Js = ((j & 1) ? J + 1 : J - 1) & (nc - 1);
+            const int Is = axis_index((i & 1) ? I + 1 : I - 1, mc, nbx);
+            const int Js = axis_index((j & 1) ? J + 1 : J - 1, nc, nby);
 #pragma unroll
             for (int f = 0; f < NF; ++f)
                 Su[f][off + q] += bilinear<T>(&Su[f][offc], &Sv[f][offc], I, J, Is, Js, mc);

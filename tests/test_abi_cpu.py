@@ -123,3 +123,22 @@ def test_batch_null_handles():
     assert lib.mpfc_batch_size(None) == 0
     lib.mpfc_batch_destroy(None)
     assert lib.mpfc_batch_step(None, None, None, None, None, None) == L.MPFC_EINVAL
+
+
+@pytest.mark.parametrize("bc", [-1, 4, 7])
+def test_invalid_boundary_bits_rejected(bc):
+    p, o = good()
+    p.bc = bc
+    assert L.load().mpfc_validate(64, 64, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
+
+
+@pytest.mark.parametrize("bc", [L.MPFC_BC_NEUMANN_X, L.MPFC_BC_NEUMANN_Y,
+                                L.MPFC_BC_NEUMANN_X | L.MPFC_BC_NEUMANN_Y])
+def test_neumann_boundaries_validate(bc):
+    """Neumann and mixed boundary conditions (App. A) are accepted, except with
+    the learned guess, whose convolutions are periodic."""
+    p, o = good()
+    p.bc = bc
+    assert L.load().mpfc_validate(1024, 1024, ctypes.byref(p), ctypes.byref(o)) == 0
+    o.guess = L.MPFC_GUESS_CNN
+    assert L.load().mpfc_validate(1024, 1024, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL

@@ -334,3 +334,26 @@ def test_tile_shape_invariance(shape, monkeypatch):
     diff = float(np.max(np.abs(ref - got)))
     print(f"shape {shape}: max |diff| = {diff:.3e}", flush=True)
     assert diff <= 1e-13 * float(np.max(np.abs(ref))), diff
+
+
+@pytest.mark.parametrize("m,n", [(128, 128), (64, 128)])
+@pytest.mark.parametrize("shape", list(range(7)))
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_every_tile_shape_one_cycle_matches_oracle(scheme, shape, m, n, monkeypatch):
+    """Each tile shape, forced on every level, gives the oracle's one-cycle
+    iterate element by element (coarse down launches complete the right-hand
+    side from u as loaded; regression test for a missing barrier that let a
+    pass overwrite u before every wave had read it, seen only for tiles whose
+    workgroups own an uneven number of blocks per wave)."""
+    po, pg = both(scheme, h=0.5, dt=0.1)
+    phik = I.noise(m, n, mean=0.1, amp=0.1, seed=13)
+    monkeypatch.setenv("MPFC_TILE_SHAPE", str(shape))
+    st = api.Stepper(m, n, pg, tol=1e-30, max_cycles=1, energy=0)
+    psi = torch.zeros(n, m, dtype=torch.float64, device=DEV)
+    phi, info = st.step(dev(phik), dev(phik), psi, allow_fail=True)
+    assert info.n_cycles == 1
+    pk = phik if scheme == 2 else None
+    S = O.source(po, phik, phik, np.zeros_like(phik))
+    u0 = O.complete_guess(po, phik.copy(), S, pk)
+    u, _, _ = O.fas_solve(po, u0, S, phik=pk, tol=1e-30, max_cycles=1)
+    assert relmax(host(phi), u[0]) <= 1e-12
