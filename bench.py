@@ -78,6 +78,8 @@ def parse():
                     help="steps of the learned-guess comparison (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=50,
                     help="steps of the 64-simulation batched variant (0 skips it)")
+    ap.add_argument("--bc-steps", type=int, default=100,
+                    help="steps of the variant with periodic-x / Neumann-y boundaries (0 skips it)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
@@ -247,7 +249,7 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
-    from paper_1208_2643_amd import api, inputs
+    from paper_1208_2643_amd import _lib as L, api, inputs
 
     if args.calib_copy:
         # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
@@ -387,6 +389,31 @@ def main():
         out["variants"]["mixed"] = {"time_steps_per_s": vsteps / el, "steps": vsteps,
                                     "outer_per_step": outer / vsteps,
                                     "fp32_vcycles_per_step": inner / vsteps}
+    # The same workload with Sec. 4.3's boundary conditions: periodic in x,
+    # homogeneous Neumann in y (App. A), FP64, energies as above.
+    if args.variants and args.bc_steps > 0:
+        stb = api.Stepper(N, N, api.Params(**params, bc=L.MPFC_BC_NEUMANN_Y), tol=tol, nu1=2,
+                          nu2=2, energy=0 if args.no_energy else 1)
+        p_, q_, s_ = (torch.from_numpy(phi0).to(dev), torch.from_numpy(phi0).to(dev),
+                      torch.zeros_like(phi))
+        n_ = torch.empty_like(phi)
+        for _ in range(args.warmup):
+            stb.step(p_, q_, s_, n_)
+            q_, p_, n_ = p_, n_, q_
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cyc = 0
+        for _ in range(args.bc_steps):
+            _, inf = stb.step(p_, q_, s_, n_)
+            q_, p_, n_ = p_, n_, q_
+            cyc += inf.n_cycles
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        out["variants"]["neumann_y"] = {
+            "time_steps_per_s": args.bc_steps / el, "steps": args.bc_steps,
+            "vcycles_per_step": cyc / args.bc_steps,
+            "workload": "as above with periodic x, homogeneous Neumann y boundaries"}
+        stb.close()
     # 2048^2 with mixed precision (FP32 correction cycles inside FP64 defect
     # correction) against FP64 on the same input (seed 3).
     if args.variants and args.big_steps > 0:

@@ -57,6 +57,7 @@ struct mpfc_batch {
     mpfc_opts o{};
     int scheme = 2;
     bool mixed = false;
+    bool neu = false;        // some member has a Neumann axis
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     std::vector<mpfc_ctx*> C;
@@ -88,19 +89,35 @@ struct mpfc_batch {
 
 namespace {
 
-template <class Op, bool UP>
-void launch_tile_batched(int shape, const BatchTile<Op>* args, const BatchItem* items, int n,
+template <class Op, bool UP, bool NEU>
+void launch_tile_batched_bc(int shape, const BatchTile<Op>* args, const BatchItem* items, int n,
                          hipStream_t s) {
     const dim3 grid(n), blk(256);
     switch (shape) {
-        case 0: hipLaunchKernelGGL((k_tile_batched<Op, 64, 32, 6, UP>), grid, blk, 0, s, args, items, n); break;
-        case 1: hipLaunchKernelGGL((k_tile_batched<Op, 32, 32, 6, UP>), grid, blk, 0, s, args, items, n); break;
-        case 2: hipLaunchKernelGGL((k_tile_batched<Op, 32, 16, 6, UP>), grid, blk, 0, s, args, items, n); break;
-        case 3: hipLaunchKernelGGL((k_tile_batched<Op, 16, 16, 6, UP>), grid, blk, 0, s, args, items, n); break;
-        case 4: hipLaunchKernelGGL((k_tile_batched<Op, 64, 16, 10, UP>), grid, blk, 0, s, args, items, n); break;
-        case 5: hipLaunchKernelGGL((k_tile_batched<Op, 32, 16, 10, UP>), grid, blk, 0, s, args, items, n); break;
-        default: hipLaunchKernelGGL((k_tile_batched<Op, 16, 16, 10, UP>), grid, blk, 0, s, args, items, n); break;
+        case 0: hipLaunchKernelGGL((k_tile_batched<Op, 64, 32, 6, UP, NEU>), grid, blk, 0, s, args, items, n); break;
+        case 1: hipLaunchKernelGGL((k_tile_batched<Op, 32, 32, 6, UP, NEU>), grid, blk, 0, s, args, items, n); break;
+        case 2: hipLaunchKernelGGL((k_tile_batched<Op, 32, 16, 6, UP, NEU>), grid, blk, 0, s, args, items, n); break;
+        case 3: hipLaunchKernelGGL((k_tile_batched<Op, 16, 16, 6, UP, NEU>), grid, blk, 0, s, args, items, n); break;
+        case 4: hipLaunchKernelGGL((k_tile_batched<Op, 64, 16, 10, UP, NEU>), grid, blk, 0, s, args, items, n); break;
+        case 5: hipLaunchKernelGGL((k_tile_batched<Op, 32, 16, 10, UP, NEU>), grid, blk, 0, s, args, items, n); break;
+        default: hipLaunchKernelGGL((k_tile_batched<Op, 16, 16, 10, UP, NEU>), grid, blk, 0, s, args, items, n); break;
     }
+}
+
+// Batches with a Neumann member run the instantiation with the ghost rule.
+template <class Op, bool UP>
+void launch_tile_batched(bool neu, int shape, const BatchTile<Op>* args, const BatchItem* items,
+                         int n, hipStream_t s) {
+    if (neu) launch_tile_batched_bc<Op, UP, true>(shape, args, items, n, s);
+    else launch_tile_batched_bc<Op, UP, false>(shape, args, items, n, s);
+}
+
+template <class Op, int NC>
+void launch_coarse_batched(bool neu, int nsim, const BatchCoarse<Op>* args, hipStream_t s) {
+    if (neu) hipLaunchKernelGGL((k_coarse_persistent_batched<Op, CP_THREADS, NC, true>), dim3(nsim),
+                                dim3(CP_THREADS), 0, s, args);
+    else hipLaunchKernelGGL((k_coarse_persistent_batched<Op, CP_THREADS, NC, false>), dim3(nsim),
+                            dim3(CP_THREADS), 0, s, args);
 }
 
 template <int S, bool NW>
@@ -186,7 +203,7 @@ struct BatchImpl : BatchBase {
 
     template <class Op, bool UP>
     void launch(const KindTable<Op>& kt, hipStream_t s) {
-        if (kt.nitems > 0) launch_tile_batched<Op, UP>(kt.shape, kt.d_args, kt.d_items, kt.nitems, s);
+        if (kt.nitems > 0) launch_tile_batched<Op, UP>(B->neu, kt.shape, kt.d_args, kt.d_items, kt.nitems, s);
     }
 
     int build() override {
@@ -299,10 +316,8 @@ struct BatchImpl : BatchBase {
     void cycle(hipStream_t s) override {
         const int np = (int)B->phases.size();
         for (int p = 0; p < np; ++p) launch<Op64, false>(t64[0][p], s);
-        if (nc[0]) hipLaunchKernelGGL((k_coarse_persistent_batched<Op64, CP_THREADS, 4>), dim3(nc[0]),
-                                      dim3(CP_THREADS), 0, s, d_c64[0]);
-        if (nc[1]) hipLaunchKernelGGL((k_coarse_persistent_batched<Op64, CP_THREADS, 8>), dim3(nc[1]),
-                                      dim3(CP_THREADS), 0, s, d_c64[1]);
+        if (nc[0]) launch_coarse_batched<Op64, 4>(B->neu, nc[0], d_c64[0], s);
+        if (nc[1]) launch_coarse_batched<Op64, 8>(B->neu, nc[1], d_c64[1], s);
         for (int p = np - 1; p >= 0; --p) launch<Op64, true>(t64[1][p], s);
         finalize(1, s);
     }
@@ -313,10 +328,8 @@ struct BatchImpl : BatchBase {
         hipLaunchKernelGGL(k_b_clear_e, dim3(B->ncells), dim3(256), 0, s, B->d_sims, B->d_cells);
         for (int k = 0; k < B->o.inner_cycles; ++k) {
             for (int p = 0; p < np; ++p) launch<Op32, false>(t32[0][p], s);
-            if (nc[0]) hipLaunchKernelGGL((k_coarse_persistent_batched<Op32, CP_THREADS, 4>),
-                                          dim3(nc[0]), dim3(CP_THREADS), 0, s, d_c32[0]);
-            if (nc[1]) hipLaunchKernelGGL((k_coarse_persistent_batched<Op32, CP_THREADS, 8>),
-                                          dim3(nc[1]), dim3(CP_THREADS), 0, s, d_c32[1]);
+            if (nc[0]) launch_coarse_batched<Op32, 4>(B->neu, nc[0], d_c32[0], s);
+            if (nc[1]) launch_coarse_batched<Op32, 8>(B->neu, nc[1], d_c32[1], s);
             for (int p = np - 1; p >= 0; --p) launch<Op32, true>(t32[1][p], s);
         }
         hipLaunchKernelGGL((k_b_defect<S>), dim3(B->ncells), dim3(256), 0, s, B->d_sims,
@@ -427,6 +440,7 @@ int mpfc_batch_create(mpfc_batch** out, int nsim, const mpfc_sim_desc* sims, con
     B->o.energy = 0;
     B->scheme = sims[0].p.scheme;
     B->mixed = o->precision == MPFC_MIXED;
+    for (int s = 0; s < nsim; ++s) B->neu = B->neu || sims[s].p.bc != 0;
     B->stream = (hipStream_t)stream;
     const char* ng = std::getenv("MPFC_NO_GRAPH");
     B->use_graph = !(ng && ng[0] == '1');

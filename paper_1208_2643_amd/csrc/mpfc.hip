@@ -188,18 +188,41 @@ Fields<double> finest_fields(const mpfc_ctx* C) {
 }
 
 // ---- launches -----------------------------------------------------------------------
+template <class Op, bool UP, bool NEU>
+void launch_tile_bc(const Op& op, const TileArgs<typename Op::real>& A, int shape,
+                    const CycleState* stop, hipStream_t s) {
+    const dim3 grid(A.g.m / A.tx, A.g.n / A.ty), blk(256);
+    switch (shape) {
+        case 0: hipLaunchKernelGGL((k_tile<Op, 64, 32, 6, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
+        case 1: hipLaunchKernelGGL((k_tile<Op, 32, 32, 6, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
+        case 2: hipLaunchKernelGGL((k_tile<Op, 32, 16, 6, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
+        case 3: hipLaunchKernelGGL((k_tile<Op, 16, 16, 6, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
+        case 4: hipLaunchKernelGGL((k_tile<Op, 64, 16, 10, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
+        case 5: hipLaunchKernelGGL((k_tile<Op, 32, 16, 10, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
+        default: hipLaunchKernelGGL((k_tile<Op, 16, 16, 10, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
+    }
+}
+
+// Periodic grids run the instantiation without the Neumann ghost handling.
 template <class Op, bool UP>
 void launch_tile(const Op& op, const TileArgs<typename Op::real>& A, int shape,
                  const CycleState* stop, hipStream_t s) {
-    const dim3 grid(A.g.m / A.tx, A.g.n / A.ty), blk(256);
-    switch (shape) {
-        case 0: hipLaunchKernelGGL((k_tile<Op, 64, 32, 6, UP>), grid, blk, 0, s, op, A, stop); break;
-        case 1: hipLaunchKernelGGL((k_tile<Op, 32, 32, 6, UP>), grid, blk, 0, s, op, A, stop); break;
-        case 2: hipLaunchKernelGGL((k_tile<Op, 32, 16, 6, UP>), grid, blk, 0, s, op, A, stop); break;
-        case 3: hipLaunchKernelGGL((k_tile<Op, 16, 16, 6, UP>), grid, blk, 0, s, op, A, stop); break;
-        case 4: hipLaunchKernelGGL((k_tile<Op, 64, 16, 10, UP>), grid, blk, 0, s, op, A, stop); break;
-        case 5: hipLaunchKernelGGL((k_tile<Op, 32, 16, 10, UP>), grid, blk, 0, s, op, A, stop); break;
-        default: hipLaunchKernelGGL((k_tile<Op, 16, 16, 10, UP>), grid, blk, 0, s, op, A, stop); break;
+    if (A.g.bc) launch_tile_bc<Op, UP, true>(op, A, shape, stop, s);
+    else launch_tile_bc<Op, UP, false>(op, A, shape, stop, s);
+}
+
+// The persistent coarse-level kernel for the coarsest grid's cell count (4:
+// 2x2, else 2x4 or 4x2) and the grid's boundary conditions.
+template <class Op>
+void launch_coarse(const Op& op, const CoarseArgs<typename Op::real>& A, bool four,
+                   const CycleState* stop, hipStream_t s) {
+    const dim3 g1(1), blk(CP_THREADS);
+    if (A.geo.bc) {
+        if (four) hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4, true>), g1, blk, 0, s, op, A, stop);
+        else hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 8, true>), g1, blk, 0, s, op, A, stop);
+    } else {
+        if (four) hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4, false>), g1, blk, 0, s, op, A, stop);
+        else hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 8, false>), g1, blk, 0, s, op, A, stop);
     }
 }
 
@@ -423,12 +446,7 @@ void vcycle_mpfc_t(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) {
     if (Lp < nl && only < 0) {
         const CoarseArgs<double> A = coarse_args64(C);
         const Op op = make_op<Op>(C, C->L[Lp]);
-        if (coarsest_is_4(C))
-            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4>), dim3(1), dim3(CP_THREADS),
-                               0, s, op, A, stop);
-        else
-            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 8>), dim3(1), dim3(CP_THREADS),
-                               0, s, op, A, stop);
+        launch_coarse<Op>(op, A, coarsest_is_4(C), stop, s);
     }
     for (int l = Lp - 1; l >= 0; --l) {
         if (only >= 0 && (l != only || !only_up)) continue;
@@ -483,12 +501,7 @@ void vcycle_inner_t(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0,
     if (Lp < nl && only < 0) {
         const CoarseArgs<float> A = coarse_args32(C);
         const Op op = make_op32<Op>(C, C->L[Lp]);
-        if (coarsest_is_4(C))
-            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4>), dim3(1), dim3(CP_THREADS),
-                               0, s, op, A, stop);
-        else
-            hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 8>), dim3(1), dim3(CP_THREADS),
-                               0, s, op, A, stop);
+        launch_coarse<Op>(op, A, coarsest_is_4(C), stop, s);
     }
     for (int l = Lp - 1; l >= 0; --l) {
         if (only >= 0 && (l != only || !only_up)) continue;
@@ -598,8 +611,7 @@ void vcycle_poisson(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) 
         A.nsw2 = 4;
         A.complete_top = Lp > 0;
         A.G = C->G;
-        hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4>), dim3(1), dim3(CP_THREADS), 0, s,
-                           make_op<Op>(C, top), A, stop);
+        launch_coarse<Op>(make_op<Op>(C, top), A, true, stop, s);
     }
     for (int l = Lp - 1; l >= 0; --l) {
         if (only >= 0 && (l != only || !only_up)) continue;

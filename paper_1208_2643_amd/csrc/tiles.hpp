@@ -121,6 +121,15 @@ __device__ __forceinline__ T bilinear(const T* __restrict__ uH, const T* __restr
            T(1.0 / 16.0) * (uH[d] - vH[d]);
 }
 
+// Cell index along one axis inside the tile and coarse kernels: plain
+// wrap-around in the periodic instantiation (NEU = false), the per-axis ghost
+// rule (axis_index) in the instantiation for grids with a Neumann axis.
+template <bool NEU>
+__device__ __forceinline__ int bidx(int i, int m, int neumann_axis) {
+    if constexpr (NEU) return axis_index(i, m, neumann_axis);
+    else return i & (m - 1);
+}
+
 // XCD-aware order of nt work items: workgroups are dealt round-robin to the 8
 // XCDs, each with its own L2.  Workgroup b (on XCD b % 8) takes item
 // (b % 8) * (nt / 8) + b / 8, so every XCD sweeps one contiguous strip of
@@ -131,7 +140,7 @@ __device__ __forceinline__ int xcd_item(int b, int nt) {
 
 // Body of one tile launch (one workgroup, 256 threads) on tile (tbx, tby).
 // `pslot` is where the workgroup's residual sum goes in A.part.
-template <class Op, int TX, int TY, int HMAX, bool UP>
+template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU>
 __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename Op::real>& A,
                                           const CycleState* stop, int tbx, int tby, int pslot) {
     using T = typename Op::real;
@@ -155,7 +164,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
     // 1. u (tile + halo) into LDS, coalesced along rows.
     for (int q = t; q < LX * LY; q += NT) {
         const int y = q / LX, x = q - y * LX;
-        const size_t gq = at(wrapx(x0 + x, g), wrapy(y0 + y, g), g);
+        const size_t gq = at(bidx<NEU>(x0 + x, g.m, g.bc & BC_NEUMANN_X), bidx<NEU>(y0 + y, g.n, g.bc & BC_NEUMANN_Y), g);
 #pragma unroll
         for (int f = 0; f < NF; ++f) U[f][(x + y) & 1][y][x >> 1] = A.zero_in ? T(0) : A.uin[f][gq];
     }
@@ -183,7 +192,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
             const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
             const int x = 2 * bx + dx, y = 2 * by + dy;
             if (x < 1 || y < 1 || x >= LX - 1 || y >= LY - 1) continue;  // never updated
-            const size_t gq = at(wrapx(x0 + x, g), wrapy(y0 + y, g), g);
+            const size_t gq = at(bidx<NEU>(x0 + x, g.m, g.bc & BC_NEUMANN_X), bidx<NEU>(y0 + y, g.n, g.bc & BC_NEUMANN_Y), g);
             if constexpr (Op::XK) xkr[s][c] = A.xk[gq];
             if constexpr (Op::PB) pbr[s][c] = A.pb[gq];
 #pragma unroll
@@ -200,8 +209,8 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
         const int cx0 = (x0 >> 1) - 1, cy0 = (y0 >> 1) - 1;
         for (int q = t; q < CX * CY; q += NT) {
             const int cy = q / CX, cx = q - cy * CX;
-            const size_t gq = (size_t)axis_index(cy0 + cy, nc, g.bc & BC_NEUMANN_Y) * mc +
-                              axis_index(cx0 + cx, mc, g.bc & BC_NEUMANN_X);
+            const size_t gq = (size_t)bidx<NEU>(cy0 + cy, nc, g.bc & BC_NEUMANN_Y) * mc +
+                              bidx<NEU>(cx0 + cx, mc, g.bc & BC_NEUMANN_X);
 #pragma unroll
             for (int f = 0; f < NF; ++f) E[f][cy][cx] = A.cuH[f][gq] - A.cvH[f][gq];
         }
@@ -296,8 +305,8 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
     // from their mirror cells, x first, then y (corners get both reflections),
     // so every relaxed grid cell reads ghosts equal to its mirror's value from
     // before the pass, as in a global sweep.
-    const bool mir_x = (g.bc & BC_NEUMANN_X) && (x0 < 0 || x0 + LX > g.m);
-    const bool mir_y = (g.bc & BC_NEUMANN_Y) && (y0 < 0 || y0 + LY > g.n);
+    const bool mir_x = NEU && (g.bc & BC_NEUMANN_X) && (x0 < 0 || x0 + LX > g.m);
+    const bool mir_y = NEU && (g.bc & BC_NEUMANN_Y) && (y0 < 0 || y0 + LY > g.n);
     auto restore_ghosts = [&]() {
         if (mir_x) {
             for (int q = t; q < 2 * H * LY; q += NT) {
@@ -330,7 +339,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
         if (((p - 1) & 1) == 0) pass(std::integral_constant<int, 0>{}, p);
         else pass(std::integral_constant<int, 1>{}, p);
         __syncthreads();
-        restore_ghosts();
+        if constexpr (NEU) restore_ghosts();
     }
 
     // 5. interior u back to global memory, coalesced along rows.
@@ -424,13 +433,13 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
 }
 
 // One level of one grid.  Grid: (m / tx, n / ty) workgroups of 256 threads.
-template <class Op, int TX, int TY, int HMAX, bool UP>
+template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU>
 __global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real> A,
                                               const CycleState* stop) {
     const int nt = gridDim.x * gridDim.y;
     const int tl = xcd_item(blockIdx.y * gridDim.x + blockIdx.x, nt);
     const int tby = tl / gridDim.x, tbx = tl - tby * gridDim.x;
-    tile_body<Op, TX, TY, HMAX, UP>(op, A, stop, tbx, tby, tl);
+    tile_body<Op, TX, TY, HMAX, UP, NEU>(op, A, stop, tbx, tby, tl);
 }
 
 // Batched launch: one level of many independent grids.  Each (grid, level)
@@ -450,7 +459,7 @@ struct BatchItem {
     int tile;             // linear tile index within that grid level
 };
 
-template <class Op, int TX, int TY, int HMAX, bool UP>
+template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU>
 __global__ void __launch_bounds__(256) k_tile_batched(const BatchTile<Op>* __restrict__ args,
                                                       const BatchItem* __restrict__ items,
                                                       int nitems) {
@@ -458,7 +467,7 @@ __global__ void __launch_bounds__(256) k_tile_batched(const BatchTile<Op>* __res
     const BatchItem it = items[b];
     const BatchTile<Op>& BA = args[it.arg];
     const int tby = it.tile / BA.ntx, tbx = it.tile - tby * BA.ntx;
-    tile_body<Op, TX, TY, HMAX, UP>(BA.op, BA.A, BA.stop, tbx, tby, BA.part_off + it.tile);
+    tile_body<Op, TX, TY, HMAX, UP, NEU>(BA.op, BA.A, BA.stop, tbx, tby, BA.part_off + it.tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -653,15 +662,15 @@ __device__ void coarse_solve_poisson(T* w, const T* f, const T* v, const double*
     }
 }
 
-template <class Op, int NTP, int NC>
+template <class Op, int NTP, int NC, bool NEU>
 __device__ __forceinline__ void coarse_body(const Op& op_top,
                                             const CoarseArgs<typename Op::real>& A,
                                             const CycleState* stop);
 
-template <class Op, int NTP, int NC>
+template <class Op, int NTP, int NC, bool NEU>
 __global__ void __launch_bounds__(NTP) k_coarse_persistent(Op op_top, CoarseArgs<typename Op::real> A,
                                                            const CycleState* stop) {
-    coarse_body<Op, NTP, NC>(op_top, A, stop);
+    coarse_body<Op, NTP, NC, NEU>(op_top, A, stop);
 }
 
 // Batched: workgroup b runs the coarse levels of grid b.
@@ -672,14 +681,14 @@ struct BatchCoarse {
     const CycleState* stop;
 };
 
-template <class Op, int NTP, int NC>
+template <class Op, int NTP, int NC, bool NEU>
 __global__ void __launch_bounds__(NTP) k_coarse_persistent_batched(
     const BatchCoarse<Op>* __restrict__ args) {
     const BatchCoarse<Op>& B = args[blockIdx.x];
-    coarse_body<Op, NTP, NC>(B.op, B.A, B.stop);
+    coarse_body<Op, NTP, NC, NEU>(B.op, B.A, B.stop);
 }
 
-template <class Op, int NTP, int NC>
+template <class Op, int NTP, int NC, bool NEU>
 __device__ __forceinline__ void coarse_body(const Op& op_top,
                                             const CoarseArgs<typename Op::real>& A,
                                             const CycleState* stop) {
@@ -732,8 +741,8 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
     const bool nbx = G.bc & BC_NEUMANN_X, nby = G.bc & BC_NEUMANN_Y;
     auto nsum_l = [&](const T* a, int i, int j, int m, int lm, int n) {
         const int r = j << lm;
-        return (a[axis_index(i + 1, m, nbx) + r] + a[axis_index(i - 1, m, nbx) + r]) +
-               (a[i + (axis_index(j + 1, n, nby) << lm)] + a[i + (axis_index(j - 1, n, nby) << lm)]);
+        return (a[bidx<NEU>(i + 1, m, nbx) + r] + a[bidx<NEU>(i - 1, m, nbx) + r]) +
+               (a[i + (bidx<NEU>(j + 1, n, nby) << lm)] + a[i + (bidx<NEU>(j - 1, n, nby) << lm)]);
     };
     auto complete_rhs = [&](int l) {
         const Op o = opl(l);
@@ -823,8 +832,8 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
                 T* xkp = Op::XK ? &Sxk[off] : nullptr;
                 T* pbp = Op::PB ? &Spb[off] : nullptr;
                 coarse_solve_mpfc<Op, NC>(o, &Su[0][off], &Su[1][off], &Su[2][off], fbuf, xkp, pbp,
-                                          G.m[l], G.lm[l], G.n[l], G.bc, A.newton_maxit,
-                                          A.newton_tol);
+                                          G.m[l], G.lm[l], G.n[l], NEU ? G.bc : 0,
+                                          A.newton_maxit, A.newton_tol);
             }
         } else {
             coarse_solve_poisson<T>(&Su[0][off], &Sf[0][off], &Sv[0][off], A.G, nc);
@@ -837,8 +846,8 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
         const int mc = G.m[l + 1], nc = G.n[l + 1], offc = G.off[l + 1];
         for (int q = t; q < m * n; q += NTP) {
             const int i = q & (m - 1), j = q >> lm, I = i >> 1, J = j >> 1;
-            const int Is = axis_index((i & 1) ? I + 1 : I - 1, mc, nbx);
-            const int Js = axis_index((j & 1) ? J + 1 : J - 1, nc, nby);
+            const int Is = bidx<NEU>((i & 1) ? I + 1 : I - 1, mc, nbx);
+            const int Js = bidx<NEU>((j & 1) ? J + 1 : J - 1, nc, nby);
 #pragma unroll
             for (int f = 0; f < NF; ++f)
                 Su[f][off + q] += bilinear<T>(&Su[f][offc], &Sv[f][offc], I, J, Is, Js, mc);
