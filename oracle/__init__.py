@@ -69,27 +69,28 @@ def load():
     sigs = {
         "orc_laplacian": (v, [i, i, d, _dp, _dp]),
         "orc_coefficients": (v, [P, _dp, _dp]),
-        "orc_source": (v, [P, i, i, _dp, _dp, _dp, _dp, _dp, _dp]),
-        "orc_operator": (v, [i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
-        "orc_residual": (v, [i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "orc_source": (v, [P, i, i, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "orc_operator": (v, [i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "orc_residual": (v, [i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                             _dp]),
         "orc_norm3": (d, [i, i, d, _dp, _dp, _dp]),
-        "orc_smooth_color": (v, [i, i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
-        "orc_smooth": (v, [i, i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
-        "orc_smooth_lex": (v, [i, i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "orc_smooth_color": (v, [i, i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "orc_smooth": (v, [i, i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "orc_smooth_lex": (v, [i, i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
         "orc_restrict": (v, [i, i, _dp, _dp]),
         "orc_prolong_add": (v, [i, i, _dp, _dp]),
-        "orc_dense_newton": (i, [i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, i]),
+        "orc_dense_newton": (i, [i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, i, _dp]),
         "orc_fas_solve": (i, [i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
-                              i, i, i, d, i, _dp]),
-        "orc_complete_guess": (v, [i, i, i, d, d, _dp, _dp, _dp, _dp, _dp, _dp]),
+                              i, i, i, d, i, _dp, _dp]),
+        "orc_complete_guess": (v, [i, i, i, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
         "orc_psi_update": (v, [i, ctypes.c_size_t, d, _dp, _dp, _dp, _dp]),
         "orc_energy_F": (d, [i, i, d, d, _dp]),
         "orc_grad_sq": (d, [i, i, _dp]),
         "orc_poisson_cg": (i, [i, i, d, _dp, _dp, d, i]),
         "orc_norm_m1_sq": (d, [i, i, d, _dp]),
-        "orc_energies": (v, [i, i, d, d, d, _dp, _dp, _dp, _dp]),
+        "orc_energies": (v, [i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp]),
         "orc_step": (i, [P, i, i, i, _dp, _dp, _dp, i, i, i, i, d, i,
-                         _dp, _dp, _dp, _dp, _dp, _dp]),
+                         _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
         "orc_set_bc": (v, [i, i]),
         "orc_version": (i, []),
         "orc_num_threads": (i, []),
@@ -129,6 +130,18 @@ def _shape(a):
     return m, n
 
 
+def _pin(p, pin, phihat=None, need_hat=False):
+    """Pinning weight (and phi_hat) as arrays, checked (Sec. 4.4: scheme 2)."""
+    if pin is None:
+        return None, None
+    if p.scheme != 2:
+        raise ValueError("pinning is defined for the second-order scheme (Sec. 4.4)")
+    w = _arr(pin)
+    if need_hat and phihat is None:
+        raise ValueError("pinning needs phi_hat")
+    return w, (_arr(phihat) if phihat is not None else None)
+
+
 # ---------------------------------------------------------------- operators
 def coefficients(p: Params):
     """(c, d): c = sM/(beta+1/s), d = 1/(beta+1/s) (scheme 1) or with 2/s (scheme 2)."""
@@ -145,38 +158,42 @@ def laplacian(f, h, bc=(0, 0)):
     return out
 
 
-def source(p: Params, phik, phikm1=None, psik=None):
+def source(p: Params, phik, phikm1=None, psik=None, pin=None, phihat=None):
     phik = _arr(phik)
     phikm1 = _arr(phikm1) if phikm1 is not None else phik
     psik = _arr(psik) if psik is not None else None
+    w, ph = _pin(p, pin, phihat, need_hat=True)
     m, n = _shape(phik)
     S = [np.empty_like(phik) for _ in range(3)]
     _lib_bc(p.bc).orc_source(ctypes.byref(p._c()), m, n, _p(phik), _p(phikm1), _p(psik),
-                      *[_p(x) for x in S])
+                      *[_p(x) for x in S], _p(w), _p(ph))
     return S
 
 
-def operator(p: Params, u, phik=None, h=None):
+def operator(p: Params, u, phik=None, h=None, pin=None):
     """N(u) on the grid of u (spacing h, default p.h)."""
     phi, mu, ka = (_arr(x) for x in u)
     m, n = _shape(phi)
     c, _ = coefficients(p)
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
     out = [np.empty_like(phi) for _ in range(3)]
+    w, _ = _pin(p, pin)
     _lib_bc(p.bc).orc_operator(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
-                        _p(phi), _p(mu), _p(ka), *[_p(x) for x in out])
+                        _p(phi), _p(mu), _p(ka), *[_p(x) for x in out], _p(w))
     return out
 
 
-def residual(p: Params, u, f, phik=None, h=None):
+def residual(p: Params, u, f, phik=None, h=None, pin=None):
     phi, mu, ka = (_arr(x) for x in u)
     f1, f2, f3 = (_arr(x) for x in f)
     m, n = _shape(phi)
     c, _ = coefficients(p)
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
     out = [np.empty_like(phi) for _ in range(3)]
+    w, _ = _pin(p, pin)
     _lib_bc(p.bc).orc_residual(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
-                        _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3), *[_p(x) for x in out])
+                        _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3), *[_p(x) for x in out],
+                        _p(w))
     return out
 
 
@@ -186,7 +203,7 @@ def norm3(r, h):
     return load().orc_norm3(m, n, h, _p(r1), _p(r2), _p(r3))
 
 
-def smooth(p: Params, u, f, phik=None, sweeps=1, newton=True, h=None, order="rb"):
+def smooth(p: Params, u, f, phik=None, sweeps=1, newton=True, h=None, order="rb", pin=None):
     """Nonlinear Gauss-Seidel passes; returns the updated copy of u."""
     phi, mu, ka = (_arr(x).copy() for x in u)
     f1, f2, f3 = (_arr(x) for x in f)
@@ -195,19 +212,21 @@ def smooth(p: Params, u, f, phik=None, sweeps=1, newton=True, h=None, order="rb"
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
     lib = _lib_bc(p.bc)
     fn = lib.orc_smooth if order == "rb" else lib.orc_smooth_lex
+    w, _ = _pin(p, pin)
     fn(p.scheme, int(newton), sweeps, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
-       _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3))
+       _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3), _p(w))
     return [phi, mu, ka]
 
 
-def smooth_color(p: Params, u, f, color, phik=None, newton=True, h=None):
+def smooth_color(p: Params, u, f, color, phik=None, newton=True, h=None, pin=None):
     phi, mu, ka = (_arr(x).copy() for x in u)
     f1, f2, f3 = (_arr(x) for x in f)
     m, n = _shape(phi)
     c, _ = coefficients(p)
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
     _lib_bc(p.bc).orc_smooth_color(p.scheme, int(newton), color, m, n, p.h if h is None else h, c,
-                            p.alpha, _p(pk), _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3))
+                            p.alpha, _p(pk), _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3),
+                            _p(_pin(p, pin)[0]))
     return [phi, mu, ka]
 
 
@@ -228,19 +247,20 @@ def prolong_add(coarse, fine, bc=(0, 0)):
     return fine
 
 
-def dense_newton(p: Params, u, f, phik=None, h=None, maxit=50):
+def dense_newton(p: Params, u, f, phik=None, h=None, maxit=50, pin=None):
     phi, mu, ka = (_arr(x).copy() for x in u)
     f1, f2, f3 = (_arr(x) for x in f)
     m, n = _shape(phi)
     c, _ = coefficients(p)
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
     it = _lib_bc(p.bc).orc_dense_newton(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
-                                 _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3), maxit)
+                                 _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3), maxit,
+                                 _p(_pin(p, pin)[0]))
     return [phi, mu, ka], it
 
 
 def fas_solve(p: Params, u0, S, phik=None, nu1=2, nu2=2, coarsest=2, tol=1e-10,
-              max_cycles=100, newton=True):
+              max_cycles=100, newton=True, pin=None):
     """FAS V-cycles from the guess u0; returns (u, history, cycles)."""
     phi, mu, ka = (_arr(x).copy() for x in u0)
     S1, S2, S3 = (_arr(x) for x in S)
@@ -250,18 +270,18 @@ def fas_solve(p: Params, u0, S, phik=None, nu1=2, nu2=2, coarsest=2, tol=1e-10,
     hist = np.zeros(max_cycles + 1)
     cyc = _lib_bc(p.bc).orc_fas_solve(p.scheme, int(newton), m, n, p.h, c, p.alpha, _p(pk), _p(phi),
                                _p(mu), _p(ka), _p(S1), _p(S2), _p(S3), nu1, nu2, coarsest,
-                               tol, max_cycles, _p(hist))
+                               tol, max_cycles, _p(hist), _p(_pin(p, pin)[0]))
     ncyc = cyc if cyc >= 0 else -cyc - 1
     return [phi, mu, ka], hist[: ncyc + 1], cyc
 
 
-def complete_guess(p: Params, phi, S, phik=None):
+def complete_guess(p: Params, phi, S, phik=None, pin=None):
     phi = _arr(phi)
     m, n = _shape(phi)
     mu, ka = np.empty_like(phi), np.empty_like(phi)
     pk = _arr(phik) if p.scheme == 2 else None
     _lib_bc(p.bc).orc_complete_guess(p.scheme, m, n, p.h, p.alpha, _p(pk), _p(phi), _p(mu), _p(ka),
-                              _p(_arr(S[1])), _p(_arr(S[2])))
+                              _p(_arr(S[1])), _p(_arr(S[2])), _p(_pin(p, pin)[0]))
     return [phi.copy(), mu, ka]
 
 
@@ -299,12 +319,15 @@ def norm_m1_sq(psi, h, bc=(0, 0)):
     return _lib_bc(bc).orc_norm_m1_sq(m, n, h, _p(psi))
 
 
-def energies(p: Params, phinew, phik, psinew):
-    """(F, pseudo energy, modified energy, mass) after a step."""
+def energies(p: Params, phinew, phik, psinew, pin=None, phihat=None):
+    """(F, pseudo energy, modified energy, mass) after a step (with pinning,
+    F includes h^2 sum W (phi - phi_hat)^2)."""
     phinew, phik, psinew = _arr(phinew), _arr(phik), _arr(psinew)
     m, n = _shape(phinew)
     out = np.zeros(4)
-    _lib_bc(p.bc).orc_energies(m, n, p.h, p.eps, p.M, _p(phinew), _p(phik), _p(psinew), _p(out))
+    w, ph = _pin(p, pin, phihat, need_hat=True)
+    _lib_bc(p.bc).orc_energies(m, n, p.h, p.eps, p.M, _p(phinew), _p(phik), _p(psinew), _p(out),
+                               _p(w), _p(ph))
     return out
 
 
@@ -320,8 +343,10 @@ class StepResult:
 
 
 def step(p: Params, phik, phikm1=None, psik=None, guess=0, nu1=2, nu2=2, coarsest=2,
-         tol=1e-10, max_cycles=100, newton=True, energy=True) -> StepResult:
-    """One time step of the chosen scheme from (phi^k, phi^{k-1}, psi^k)."""
+         tol=1e-10, max_cycles=100, newton=True, energy=True, pin=None,
+         phihat=None) -> StepResult:
+    """One time step of the chosen scheme from (phi^k, phi^{k-1}, psi^k);
+    pin / phihat: pinning weight W and prescribed configuration (Sec. 4.4)."""
     phik = _arr(phik)
     phikm1 = _arr(phikm1) if phikm1 is not None else phik
     psik = _arr(psik) if psik is not None else np.zeros_like(phik)
@@ -331,7 +356,8 @@ def step(p: Params, phik, phikm1=None, psik=None, guess=0, nu1=2, nu2=2, coarses
     en = np.zeros(4)
     cyc = _lib_bc(p.bc).orc_step(ctypes.byref(p._c()), int(newton), m, n, _p(phik), _p(phikm1),
                           _p(psik), guess, nu1, nu2, coarsest, tol, max_cycles,
-                          *[_p(x) for x in outs], _p(hist), _p(en) if energy else None)
+                          *[_p(x) for x in outs], _p(hist), _p(en) if energy else None,
+                          *[_p(x) for x in _pin(p, pin, phihat, need_hat=True)])
     ncyc = cyc if cyc >= 0 else -cyc - 1
     return StepResult(outs[0], outs[1], outs[2], outs[3], hist[: ncyc + 1], cyc, en)
 

@@ -13,6 +13,9 @@ Scheme 2 (Sec. 3.2, eqs. mpfc_scheme2_3, mpfc_scheme2_4, discrete_2_a):
     mu = chi(phi, phi^k)(phi + phi^k)/2 + alpha (phi + phi^k)/2 + 2 L phi~ + L kappa,
     R(phi) = phi - phi^k - c2 L mu - d2 psi^k = 0,
 with chi(a, b) = (a^2 + b^2)/2 and phi~ = (3 phi^k - phi^{k-1})/2.
+Pinning (Sec. 4.4, scheme 2): mu is replaced by
+    mu~ = mu + 2 ((phi + phi^k)/2 - phi_hat) W
+in R, with the weight W and the prescribed configuration phi_hat.
 
 This module shares nothing with the FAS code in mpfc_oracle.c: different
 unknowns (phi only), a matrix Laplacian, and a library LU solve.
@@ -35,8 +38,11 @@ def laplacian_matrix(m: int, n: int, h: float) -> np.ndarray:
     return L
 
 
-def solve_step(scheme, eps, beta, M, h, s, phik, phikm1=None, psik=None, tol=1e-15, maxit=60):
-    """Return (phi, mu, kappa, iterations) of one step by dense Newton."""
+def solve_step(scheme, eps, beta, M, h, s, phik, phikm1=None, psik=None, tol=1e-15, maxit=60,
+               pin=None, phihat=None):
+    """Return (phi, mu, kappa, iterations) of one step by dense Newton (with
+    pinning weight `pin` and configuration `phihat`: scheme 2 only; mu is then
+    the pinned mu~)."""
     n, m = phik.shape
     pk = phik.reshape(-1).astype(np.float64)
     pkm1 = (phikm1 if phikm1 is not None else phik).reshape(-1).astype(np.float64)
@@ -59,16 +65,20 @@ def solve_step(scheme, eps, beta, M, h, s, phik, phikm1=None, psik=None, tol=1e-
         d = 2.0 / (beta + 2.0 / s)
         tilde = 0.5 * (3.0 * pk - pkm1)
 
+        W = np.zeros_like(pk) if pin is None else np.asarray(pin, dtype=np.float64).reshape(-1)
+        hat = np.zeros_like(pk) if phihat is None else np.asarray(phihat, dtype=np.float64).reshape(-1)
+
         def mu_of(x):
             g = 0.25 * (x**2 + pk**2) * (x + pk)
-            return g + 0.5 * alpha * (x + pk) + 2.0 * (L @ tilde) + 0.5 * (L @ (L @ (x + pk)))
+            mu = g + 0.5 * alpha * (x + pk) + 2.0 * (L @ tilde) + 0.5 * (L @ (L @ (x + pk)))
+            return mu + 2.0 * (0.5 * (x + pk) - hat) * W
 
         def R(x):
             return x - pk - c * (L @ mu_of(x)) - d * ps
 
         def J(x):
             gp = 0.25 * (3.0 * x**2 + 2.0 * x * pk + pk**2)
-            return I - c * (L @ (np.diag(gp) + 0.5 * alpha * I + 0.5 * (L @ L)))
+            return I - c * (L @ (np.diag(gp + W) + 0.5 * alpha * I + 0.5 * (L @ L)))
     x = pk.copy()
     it = 0
     for it in range(1, maxit + 1):

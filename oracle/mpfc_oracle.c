@@ -39,6 +39,12 @@
  *  - the residual norm is sqrt(h^2 * sum over the three components of r^2),
  *    the h-weighted discrete l2 norm of App. A applied to all of r;
  *  - scheme-2 coarse operators use phi^k restricted by the same 2x2 average;
+ *  - pinning (Sec. 4.4, scheme 2): mu is replaced by
+ *    mu~ = mu + 2 (phi^{k+1/2} - phi_hat) W with phi^{k+1/2} = (phi^{k+1} + phi^k)/2
+ *    and the weight W; taking mu~ as the unknown gives N^(2) an extra -W phi
+ *    and S^(2) an extra W (phi^k - 2 phi_hat); coarse levels use W restricted
+ *    by the 2x2 average, and the reported energy F gains h^2 sum W (phi - phi_hat)^2
+ *    (the discrete form of the added integral);
  *  - on a homogeneous Neumann boundary the ghost cell (a copy of the boundary
  *    cell) enters the smoother's neighbour sums with the value it has before
  *    the cell is updated (ghosts refreshed before every half-sweep), and the
@@ -137,7 +143,8 @@ static double ecoef(int scheme) { return scheme == 1 ? 1.0 : 0.5; }
 
 /* Source S (App. B.1 and B.2). phikm1 and psik may be NULL where unused. */
 void orc_source(const orc_model *p, int m, int n, const double *phik, const double *phikm1,
-                const double *psik, double *S1, double *S2, double *S3) {
+                const double *psik, double *S1, double *S2, double *S3, const double *pin,
+                const double *phihat) {
     double c, d;
     orc_coefficients(p, &c, &d);
     double alpha = 1.0 - p->eps;
@@ -158,6 +165,7 @@ void orc_source(const orc_model *p, int m, int n, const double *phik, const doub
                 S3[q] = 0.0;
             } else {
                 S2[q] = 0.5 * alpha * phik[q] + 2.0 * lap_at(tilde, i, j, m, n, h);
+                if (pin) S2[q] += pin[q] * (phik[q] - 2.0 * phihat[q]);
                 S3[q] = 0.5 * lap_at(phik, i, j, m, n, h);
             }
         }
@@ -165,17 +173,19 @@ void orc_source(const orc_model *p, int m, int n, const double *phik, const doub
 }
 
 /* N(u) on an m x n grid with spacing h (App. B.1 and B.2).  phik is used by
- * scheme 2 only (may be NULL for scheme 1). */
+ * scheme 2 only (may be NULL for scheme 1); pin is the pinning weight on this
+ * grid (NULL: none). */
 void orc_operator(int scheme, int m, int n, double h, double c, double alpha,
                   const double *phik, const double *phi, const double *mu, const double *ka,
-                  double *N1, double *N2, double *N3) {
+                  double *N1, double *N2, double *N3, const double *pin) {
     double al = alin(scheme, alpha), e = ecoef(scheme);
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < m; ++i) {
             size_t q = IX(i, j, m);
             double xk = phik ? phik[q] : 0.0;
             N1[q] = phi[q] - c * lap_at(mu, i, j, m, n, h);
-            N2[q] = mu[q] - gnl(scheme, phi[q], xk) - al * phi[q] - lap_at(ka, i, j, m, n, h);
+            double alq = al + (pin ? pin[q] : 0.0);
+            N2[q] = mu[q] - gnl(scheme, phi[q], xk) - alq * phi[q] - lap_at(ka, i, j, m, n, h);
             N3[q] = ka[q] - e * lap_at(phi, i, j, m, n, h);
         }
 }
@@ -184,8 +194,8 @@ void orc_operator(int scheme, int m, int n, double h, double c, double alpha,
 void orc_residual(int scheme, int m, int n, double h, double c, double alpha,
                   const double *phik, const double *phi, const double *mu, const double *ka,
                   const double *f1, const double *f2, const double *f3,
-                  double *r1, double *r2, double *r3) {
-    orc_operator(scheme, m, n, h, c, alpha, phik, phi, mu, ka, r1, r2, r3);
+                  double *r1, double *r2, double *r3, const double *pin) {
+    orc_operator(scheme, m, n, h, c, alpha, phik, phi, mu, ka, r1, r2, r3, pin);
     size_t N = (size_t)m * n;
     for (size_t q = 0; q < N; ++q) {
         r1[q] = f1[q] - r1[q];
@@ -218,11 +228,11 @@ static double det3(double a0, double a1, double a2, double b0, double b1, double
  * at the cell (correction form). */
 static void relax_cell(int scheme, int newton, int i, int j, int m, int n, double h, double c,
                        double alpha, const double *phik, double *phi, double *mu, double *ka,
-                       const double *f1, const double *f2, const double *f3) {
+                       const double *f1, const double *f2, const double *f3, const double *pin) {
     size_t q = IX(i, j, m);
     double xk = phik ? phik[q] : 0.0;
     double x = phi[q];
-    double al = alin(scheme, alpha), e = ecoef(scheme);
+    double al = alin(scheme, alpha) + (pin ? pin[q] : 0.0), e = ecoef(scheme);
     double r1 = f1[q] - (x - c * lap_at(mu, i, j, m, n, h));
     double r2 = f2[q] - (mu[q] - gnl(scheme, x, xk) - al * x - lap_at(ka, i, j, m, n, h));
     double r3 = f3[q] - (ka[q] - e * lap_at(phi, i, j, m, n, h));
@@ -251,20 +261,20 @@ static void relax_cell(int scheme, int newton, int i, int j, int m, int n, doubl
  * 0 = red).  Cells of one colour only couple to the other colour. */
 void orc_smooth_color(int scheme, int newton, int color, int m, int n, double h, double c,
                       double alpha, const double *phik, double *phi, double *mu, double *ka,
-                      const double *f1, const double *f2, const double *f3) {
+                      const double *f1, const double *f2, const double *f3, const double *pin) {
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < n; ++j)
         for (int i = (j + color) & 1; i < m; i += 2)
-            relax_cell(scheme, newton, i, j, m, n, h, c, alpha, phik, phi, mu, ka, f1, f2, f3);
+            relax_cell(scheme, newton, i, j, m, n, h, c, alpha, phik, phi, mu, ka, f1, f2, f3, pin);
 }
 
 /* nsweeps full red-black passes ("ell_max" smoothing iterations, App. B.1). */
 void orc_smooth(int scheme, int newton, int nsweeps, int m, int n, double h, double c,
                 double alpha, const double *phik, double *phi, double *mu, double *ka,
-                const double *f1, const double *f2, const double *f3) {
+                const double *f1, const double *f2, const double *f3, const double *pin) {
     for (int l = 0; l < nsweeps; ++l) {
-        orc_smooth_color(scheme, newton, 0, m, n, h, c, alpha, phik, phi, mu, ka, f1, f2, f3);
-        orc_smooth_color(scheme, newton, 1, m, n, h, c, alpha, phik, phi, mu, ka, f1, f2, f3);
+        orc_smooth_color(scheme, newton, 0, m, n, h, c, alpha, phik, phi, mu, ka, f1, f2, f3, pin);
+        orc_smooth_color(scheme, newton, 1, m, n, h, c, alpha, phik, phi, mu, ka, f1, f2, f3, pin);
     }
 }
 
@@ -272,11 +282,11 @@ void orc_smooth(int scheme, int newton, int nsweeps, int m, int n, double h, dou
  * (used only to check that the ordering does not change the fixed point). */
 void orc_smooth_lex(int scheme, int newton, int nsweeps, int m, int n, double h, double c,
                     double alpha, const double *phik, double *phi, double *mu, double *ka,
-                    const double *f1, const double *f2, const double *f3) {
+                    const double *f1, const double *f2, const double *f3, const double *pin) {
     for (int l = 0; l < nsweeps; ++l)
         for (int j = 0; j < n; ++j)
             for (int i = 0; i < m; ++i)
-                relax_cell(scheme, newton, i, j, m, n, h, c, alpha, phik, phi, mu, ka, f1, f2, f3);
+                relax_cell(scheme, newton, i, j, m, n, h, c, alpha, phik, phi, mu, ka, f1, f2, f3, pin);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -355,7 +365,8 @@ static int gauss_solve(int nn, double *A, double *b) {
  * times.  Returns the number of iterations, or -1 on a singular Jacobian. */
 int orc_dense_newton(int scheme, int m, int n, double h, double c, double alpha,
                      const double *phik, double *phi, double *mu, double *ka,
-                     const double *f1, const double *f2, const double *f3, int maxit) {
+                     const double *f1, const double *f2, const double *f3, int maxit,
+                     const double *pin) {
     int nc = m * n, nn = 3 * nc;
     double *A = (double *)malloc((size_t)nn * nn * sizeof(double));
     double *b = (double *)malloc((size_t)nn * sizeof(double));
@@ -365,7 +376,7 @@ int orc_dense_newton(int scheme, int m, int n, double h, double c, double alpha,
     double al = alin(scheme, alpha), e = ecoef(scheme), ih2 = 1.0 / (h * h);
     int it, ret = -1;
     for (it = 1; it <= maxit; ++it) {
-        orc_residual(scheme, m, n, h, c, alpha, phik, phi, mu, ka, f1, f2, f3, r1, r2, r3);
+        orc_residual(scheme, m, n, h, c, alpha, phik, phi, mu, ka, f1, f2, f3, r1, r2, r3, pin);
         memset(A, 0, (size_t)nn * nn * sizeof(double));
         for (int j = 0; j < n; ++j)
             for (int i = 0; i < m; ++i) {
@@ -379,7 +390,7 @@ int orc_dense_newton(int scheme, int m, int n, double h, double c, double alpha,
                 for (int t = 0; t < 4; ++t) A[(size_t)q * nn + nc + nb[t]] -= c * ih2;
                 /* row of N^(2): mu - g(phi) - al phi - Lap(kappa) */
                 size_t r = (size_t)(nc + q) * nn;
-                A[r + q] -= al + gnl_prime(scheme, phi[q], xk);
+                A[r + q] -= al + (pin ? pin[q] : 0.0) + gnl_prime(scheme, phi[q], xk);
                 A[r + nc + q] += 1.0;
                 A[r + 2 * nc + q] += 4.0 * ih2;
                 for (int t = 0; t < 4; ++t) A[r + 2 * nc + nb[t]] -= ih2;
@@ -419,7 +430,7 @@ done:
 typedef struct {
     int m, n;
     double h;
-    double *u[3], *f[3], *r[3], *v[3], *phik;
+    double *u[3], *f[3], *r[3], *v[3], *phik, *pin;
 } orc_level;
 
 typedef struct {
@@ -432,14 +443,14 @@ static void vcycle(orc_hier *H, int l) {
     orc_level *A = &H->L[l];
     if (l == H->nlev - 1) {
         orc_dense_newton(H->scheme, A->m, A->n, A->h, H->c, H->alpha, A->phik, A->u[0], A->u[1],
-                         A->u[2], A->f[0], A->f[1], A->f[2], 50);
+                         A->u[2], A->f[0], A->f[1], A->f[2], 50, A->pin);
         return;
     }
     orc_level *B = &H->L[l + 1];
     orc_smooth(H->scheme, H->newton, H->nu1, A->m, A->n, A->h, H->c, H->alpha, A->phik, A->u[0],
-               A->u[1], A->u[2], A->f[0], A->f[1], A->f[2]);
+               A->u[1], A->u[2], A->f[0], A->f[1], A->f[2], A->pin);
     orc_residual(H->scheme, A->m, A->n, A->h, H->c, H->alpha, A->phik, A->u[0], A->u[1], A->u[2],
-                 A->f[0], A->f[1], A->f[2], A->r[0], A->r[1], A->r[2]);
+                 A->f[0], A->f[1], A->f[2], A->r[0], A->r[1], A->r[2], A->pin);
     size_t NB = (size_t)B->m * B->n;
     for (int k = 0; k < 3; ++k) {
         orc_restrict(A->m, A->n, A->u[k], B->u[k]);
@@ -447,7 +458,7 @@ static void vcycle(orc_hier *H, int l) {
     }
     /* f_H = N_H(restricted u) + restricted residual */
     orc_operator(H->scheme, B->m, B->n, B->h, H->c, H->alpha, B->phik, B->u[0], B->u[1], B->u[2],
-                 B->f[0], B->f[1], B->f[2]);
+                 B->f[0], B->f[1], B->f[2], B->pin);
     double *tmp = (double *)malloc(NB * sizeof(double));
     for (int k = 0; k < 3; ++k) {
         orc_restrict(A->m, A->n, A->r[k], tmp);
@@ -460,7 +471,7 @@ static void vcycle(orc_hier *H, int l) {
     }
     free(tmp);
     orc_smooth(H->scheme, H->newton, H->nu2, A->m, A->n, A->h, H->c, H->alpha, A->phik, A->u[0],
-               A->u[1], A->u[2], A->f[0], A->f[1], A->f[2]);
+               A->u[1], A->u[2], A->f[0], A->f[1], A->f[2], A->pin);
 }
 
 /* Solve N(u) = S by FAS V(nu1, nu2) cycles on levels m x n, m/2 x n/2, ...
@@ -472,7 +483,7 @@ static void vcycle(orc_hier *H, int l) {
 int orc_fas_solve(int scheme, int newton, int m, int n, double h, double c, double alpha,
                   const double *phik, double *phi, double *mu, double *ka, const double *S1,
                   const double *S2, const double *S3, int nu1, int nu2, int coarsest, double tol,
-                  int max_cycles, double *history) {
+                  int max_cycles, double *history, const double *pin) {
     int nlev = 1;
     {
         int mm = m, nn = n;
@@ -509,22 +520,30 @@ int orc_fas_solve(int scheme, int newton, int m, int n, double h, double c, doub
         } else {
             A->phik = NULL;
         }
+        if (!pin) {
+            A->pin = NULL;
+        } else if (l == 0) {
+            A->pin = (double *)pin;
+        } else {
+            A->pin = (double *)calloc(N, sizeof(double));
+            orc_restrict(H.L[l - 1].m, H.L[l - 1].n, H.L[l - 1].pin, A->pin);
+        }
     }
     orc_level *F = &H.L[0];
     orc_residual(scheme, m, n, h, c, alpha, F->phik, phi, mu, ka, S1, S2, S3, F->r[0], F->r[1],
-                 F->r[2]);
+                 F->r[2], F->pin);
     double nr = orc_norm3(m, n, h, F->r[0], F->r[1], F->r[2]);
     history[0] = nr;
     int cyc = 0;
     while (!(nr <= tol) && cyc < max_cycles) {
         if (nlev == 1) {
-            orc_dense_newton(scheme, m, n, h, c, alpha, F->phik, phi, mu, ka, S1, S2, S3, 50);
+            orc_dense_newton(scheme, m, n, h, c, alpha, F->phik, phi, mu, ka, S1, S2, S3, 50, F->pin);
         } else {
             vcycle(&H, 0);
         }
         ++cyc;
         orc_residual(scheme, m, n, h, c, alpha, F->phik, phi, mu, ka, S1, S2, S3, F->r[0],
-                     F->r[1], F->r[2]);
+                     F->r[1], F->r[2], F->pin);
         nr = orc_norm3(m, n, h, F->r[0], F->r[1], F->r[2]);
         history[cyc] = nr;
         if (!isfinite(nr)) break;
@@ -536,6 +555,7 @@ int orc_fas_solve(int scheme, int newton, int m, int n, double h, double c, doub
             free(A->r[k]);
         }
         if (l > 0 && A->phik) free(A->phik);
+        if (l > 0 && A->pin) free(A->pin);
     }
     free(H.L);
     return nr <= tol ? cyc : -(cyc + 1);
@@ -549,7 +569,7 @@ int orc_fas_solve(int scheme, int newton, int m, int n, double h, double c, doub
  * exactly: kappa = S3 + e Lap(phi), then mu = S2 + g(phi) + al phi + Lap(kappa). */
 void orc_complete_guess(int scheme, int m, int n, double h, double alpha, const double *phik,
                         const double *phi, double *mu, double *ka, const double *S2,
-                        const double *S3) {
+                        const double *S3, const double *pin) {
     double al = alin(scheme, alpha), e = ecoef(scheme);
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < m; ++i) {
@@ -560,7 +580,8 @@ void orc_complete_guess(int scheme, int m, int n, double h, double alpha, const 
         for (int i = 0; i < m; ++i) {
             size_t q = IX(i, j, m);
             double xk = phik ? phik[q] : 0.0;
-            mu[q] = S2[q] + gnl(scheme, phi[q], xk) + al * phi[q] + lap_at(ka, i, j, m, n, h);
+            double alq = al + (pin ? pin[q] : 0.0);
+            mu[q] = S2[q] + gnl(scheme, phi[q], xk) + alq * phi[q] + lap_at(ka, i, j, m, n, h);
         }
 }
 
@@ -680,9 +701,18 @@ double orc_norm_m1_sq(int m, int n, double h, const double *psi) {
  * out[2] = modified energy pseudo + 1/2 ||grad_h(phi^{k+1} - phi^k)||^2,
  * out[3] = mass h^2 sum phi^{k+1}. */
 void orc_energies(int m, int n, double h, double eps, double M, const double *phinew,
-                  const double *phik, const double *psinew, double *out) {
+                  const double *phik, const double *psinew, double *out, const double *pin,
+                  const double *phihat) {
     size_t N = (size_t)m * n;
     double F = orc_energy_F(m, n, h, eps, phinew);
+    if (pin) {
+        double sp = 0.0;
+        for (size_t q = 0; q < N; ++q) {
+            double dp = phinew[q] - phihat[q];
+            sp += pin[q] * dp * dp;
+        }
+        F += h * h * sp;
+    }
     double nm1 = orc_norm_m1_sq(m, n, h, psinew);
     double *d = (double *)malloc(N * sizeof(double));
     double mass = 0.0;
@@ -709,7 +739,7 @@ void orc_energies(int m, int n, double h, double eps, double M, const double *ph
 int orc_step(const orc_model *p, int newton, int m, int n, const double *phik,
              const double *phikm1, const double *psik, int guess, int nu1, int nu2, int coarsest,
              double tol, int max_cycles, double *phinew, double *mu, double *ka, double *psinew,
-             double *history, double *energies) {
+             double *history, double *energies, const double *pin, const double *phihat) {
     size_t N = (size_t)m * n;
     double c, d;
     orc_coefficients(p, &c, &d);
@@ -717,15 +747,15 @@ int orc_step(const orc_model *p, int newton, int m, int n, const double *phik,
     double *S1 = (double *)malloc(N * sizeof(double));
     double *S2 = (double *)malloc(N * sizeof(double));
     double *S3 = (double *)malloc(N * sizeof(double));
-    orc_source(p, m, n, phik, phikm1, psik, S1, S2, S3);
+    orc_source(p, m, n, phik, phikm1, psik, S1, S2, S3, pin, phihat);
     for (size_t q = 0; q < N; ++q)
         phinew[q] = (guess == 1) ? 2.0 * phik[q] - phikm1[q] : phik[q];
     const double *pk = p->scheme == 2 ? phik : NULL;
-    orc_complete_guess(p->scheme, m, n, p->h, alpha, pk, phinew, mu, ka, S2, S3);
+    orc_complete_guess(p->scheme, m, n, p->h, alpha, pk, phinew, mu, ka, S2, S3, pin);
     int cyc = orc_fas_solve(p->scheme, newton, m, n, p->h, c, alpha, pk, phinew, mu, ka, S1, S2,
-                            S3, nu1, nu2, coarsest, tol, max_cycles, history);
+                            S3, nu1, nu2, coarsest, tol, max_cycles, history, pin);
     orc_psi_update(p->scheme, N, p->s, phinew, phik, psik, psinew);
-    if (energies) orc_energies(m, n, p->h, p->eps, p->M, phinew, phik, psinew, energies);
+    if (energies) orc_energies(m, n, p->h, p->eps, p->M, phinew, phik, psinew, energies, pin, phihat);
     free(S1); free(S2); free(S3);
     return cyc;
 }
