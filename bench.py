@@ -80,6 +80,8 @@ def parse():
                     help="steps of the 64-simulation batched variant (0 skips it)")
     ap.add_argument("--bc-steps", type=int, default=100,
                     help="steps of the variant with periodic-x / Neumann-y boundaries (0 skips it)")
+    ap.add_argument("--pin-steps", type=int, default=100,
+                    help="steps of the variant with the pinning term (0 skips it)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
@@ -414,6 +416,36 @@ def main():
             "vcycles_per_step": cyc / args.bc_steps,
             "workload": "as above with periodic x, homogeneous Neumann y boundaries"}
         stb.close()
+    # The same workload with the pinning term of Sec. 4.4: weight 2 in strips
+    # of 4 rows along the top and bottom, phi_hat the initial field.
+    if args.variants and args.pin_steps > 0:
+        W = torch.zeros_like(phi)
+        W[:4] = 2.0
+        W[-4:] = 2.0
+        stp = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2,
+                          energy=0 if args.no_energy else 1)
+        stp.set_pinning(W, torch.from_numpy(phi0).to(dev))
+        p_, q_, s_ = (torch.from_numpy(phi0).to(dev), torch.from_numpy(phi0).to(dev),
+                      torch.zeros_like(phi))
+        n_ = torch.empty_like(phi)
+        for _ in range(args.warmup):
+            stp.step(p_, q_, s_, n_)
+            q_, p_, n_ = p_, n_, q_
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cyc = 0
+        for _ in range(args.pin_steps):
+            _, inf = stp.step(p_, q_, s_, n_)
+            q_, p_, n_ = p_, n_, q_
+            cyc += inf.n_cycles
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        out["variants"]["pinned"] = {
+            "time_steps_per_s": args.pin_steps / el, "steps": args.pin_steps,
+            "vcycles_per_step": cyc / args.pin_steps,
+            "workload": "as above with the pinning term (weight 2 in 4-row strips top and "
+                        "bottom, phi_hat = initial field)"}
+        stp.close()
     # 2048^2 with mixed precision (FP32 correction cycles inside FP64 defect
     # correction) against FP64 on the same input (seed 3).
     if args.variants and args.big_steps > 0:

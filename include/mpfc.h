@@ -147,6 +147,16 @@ int mpfc_step(mpfc_ctx *ctx, const double *d_phi_n, const double *d_phi_nm1, dou
 int mpfc_energies(mpfc_ctx *ctx, const double *d_phi, const double *d_phi_prev,
                   const double *d_psi, double *h_out);
 
+/* Pinning (Sec. 4.4): from the next step on, mu is replaced by
+ * mu~ = mu + 2 (phi^{k+1/2} - phi_hat) W with phi^{k+1/2} = (phi^{k+1} + phi^k)/2,
+ * i.e. N^(2) gains -W phi and S^(2) gains W (phi^k - 2 phi_hat); the mu that
+ * mpfc_step returns is mu~, and energy_F includes h^2 sum W (phi - phi_hat)^2.
+ * d_weight (W >= 0) and d_phihat are m x n device arrays, copied during the
+ * call (the caller keeps ownership); coarse levels use 2x2 averages of W.
+ * d_weight = NULL switches pinning off.  Needs scheme 2, MPFC_FP64 and
+ * MPFC_NEWTON (else MPFC_EINVAL); allocates the weight pyramid on first use. */
+int mpfc_set_pinning(mpfc_ctx *ctx, const double *d_weight, const double *d_phihat);
+
 /* Live timing of the two finest-level launches of each V-cycle (the dominant
  * kernels of the step) with HIP events on the context's stream:
  * which = 0: the down launch (nu1 red-black passes of the App. B smoother,

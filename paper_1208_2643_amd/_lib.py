@@ -88,6 +88,7 @@ SIGNATURES = {
                             ctypes.POINTER(ctypes.c_longlong), _i]),
     "mpfc_destroy": (None, [_vp]),
     "mpfc_tile_shape": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "mpfc_set_pinning": (_i, [_vp, _vp, _vp]),
     "mpfc_strerror": (ctypes.c_char_p, [_i]),
     "mpfc_last_error": (ctypes.c_char_p, []),
     "mpfc_version": (_i, []),

@@ -137,6 +137,20 @@ class Stepper:
         L.check(self.lib.mpfc_cnn_counts(self.ctx, ctypes.byref(u), ctypes.byref(f)))
         return u.value, f.value
 
+    def set_pinning(self, weight=None, phihat=None):
+        """Pinning term of Sec. 4.4 (scheme 2, FP64, Newton): weight W >= 0 and
+        prescribed configuration phi_hat, (n, m) float64 device tensors copied
+        by the call; weight None switches it off."""
+        if weight is None:
+            L.check(self.lib.mpfc_set_pinning(self.ctx, None, None))
+            return
+        for t in (weight, phihat):
+            if t is None or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("weight and phihat must be contiguous float64 CUDA tensors")
+            if tuple(t.shape) != (self.n, self.m):
+                raise ValueError("weight and phihat must have the grid's shape (n, m)")
+        L.check(self.lib.mpfc_set_pinning(self.ctx, _ptr(weight), _ptr(phihat)))
+
     def tile_shape(self, level: int = 0, which: int = 0):
         """(tx, ty, halo) of the tiled launch `which` (0 down, 1 up) on `level`."""
         tx, ty, h = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -245,10 +245,11 @@ int cnn_candidate(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
                        F0.f[2], F0.u[1][2]);
     if (C->p.scheme == 1)
         hipLaunchKernelGGL((k_complete_mu<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, F0.u[1][0],
-                           C->phik, F0.u[1][2], F0.f[1], F0.u[1][1]);
+                           C->phik, F0.u[1][2], F0.f[1], F0.u[1][1], (const double*)nullptr);
     else
         hipLaunchKernelGGL((k_complete_mu<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, F0.u[1][0],
-                           C->phik, F0.u[1][2], F0.f[1], F0.u[1][1]);
+                           C->phik, F0.u[1][2], F0.f[1], F0.u[1][1],
+                           (const double*)(C->pinned ? F0.pin : nullptr));
     return MPFC_OK;
 }
 
@@ -260,6 +261,7 @@ void residual_sq(mpfc_ctx* C, int k, double* out, hipStream_t s) {
     F.f1 = F0.f[0]; F.f2 = F0.f[1]; F.f3 = F0.f[2];
     F.phik = C->p.scheme == 2 ? C->phik : nullptr;
     F.base = nullptr;
+    F.pin = C->pinned ? F0.pin : nullptr;
     const unsigned nb = red_blocks((size_t)C->m * C->n);
     if (C->p.scheme == 1)
         hipLaunchKernelGGL((k_resnorm<1, NT>), dim3(nb), dim3(NT), 0, s, F, level_op(C, F0), F0.g,

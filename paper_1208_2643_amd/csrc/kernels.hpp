@@ -124,6 +124,7 @@ struct Fields {
     const T* f1; const T* f2; const T* f3;  // right-hand side (S, or FAS coarse RHS)
     const T* phik;                 // phi^k on this level (scheme 2), else null
     const T* base;                 // base phi (DEFECT mode), else null
+    const T* pin = nullptr;        // pinning weight W on this level (Sec. 4.4), else null
 };
 
 // r = f - N(u) at one cell.
@@ -137,8 +138,9 @@ __device__ __forceinline__ void residual_at(const Fields<T>& F, const LevelOp<T>
     const T lphi = (nsum(F.phi, i, j, g) - T(4) * x) * op.ih2;
     const T lmu = (nsum(F.mu, i, j, g) - T(4) * y) * op.ih2;
     const T lka = (nsum(F.ka, i, j, g) - T(4) * z) * op.ih2;
+    const T al = op.al + (F.pin ? F.pin[q] : T(0));  // pinning adds W to the phi coefficient
     r1 = F.f1[q] - (x - op.c * lmu);
-    r2 = F.f2[q] - (y - nl_value<T, SCHEME, DEFECT>(x, pb, xk) - op.al * x - lka);
+    r2 = F.f2[q] - (y - nl_value<T, SCHEME, DEFECT>(x, pb, xk) - al * x - lka);
     r3 = F.f3[q] - (z - op.e * lphi);
 }
 
@@ -156,7 +158,7 @@ __device__ __forceinline__ void relax_at(const Fields<T>& F, const LevelOp<T>& o
     const T x = F.phi[q];
     const T xk = (SCHEME == 2) ? F.phik[q] : T(0);
     const T pb = DEFECT ? F.base[q] : T(0);
-    const T d = op.al + nl_lin<T, SCHEME, NEWTON>(pb + x, xk);
+    const T d = op.al + (F.pin ? F.pin[q] : T(0)) + nl_lin<T, SCHEME, NEWTON>(pb + x, xk);
     const T a = T(4) * op.c * op.ih2, b = T(4) * op.ih2, ec = T(4) * op.e * op.ih2;
     const T det = T(1) + a * d + a * b * ec;
     const T dm = (r2 + (d + b * ec) * r1 - b * r3) / det;
@@ -341,14 +343,17 @@ __global__ void k_state_reset(CycleState* st) {
 // ---------------------------------------------------------------------------
 // Step set-up and wrap-up kernels (one thread per cell).
 
-// Source S (App. B.1 / B.2) at cell (i, j).  d = weight of psi^k.
+// Source S (App. B.1 / B.2) at cell (i, j).  d = weight of psi^k.  With the
+// pinning of Sec. 4.4 (scheme 2; pin != null) S^(2) gains W (phi^k - 2 phi_hat):
+// the unknown mu is then mu~ = mu + 2 ((phi^{k+1} + phi^k)/2 - phi_hat) W.
 template <int SCHEME>
 __device__ __forceinline__ void source_cell(const Grid& g, double ih2, double d, double alpha,
                                             const double* __restrict__ phik,
                                             const double* __restrict__ phikm1,
                                             const double* __restrict__ psik, double* S1,
                                             double* S2, double* S3, double* phik_copy, int i,
-                                            int j) {
+                                            int j, const double* __restrict__ pin = nullptr,
+                                            const double* __restrict__ phihat = nullptr) {
     const size_t q = at(i, j, g);
     const double pk = phik[q];
     if (phik_copy) phik_copy[q] = pk;
@@ -361,6 +366,7 @@ __device__ __forceinline__ void source_cell(const Grid& g, double ih2, double d,
         // 2 Lap((3 phi^k - phi^{k-1})/2) = 3 Lap phi^k - Lap phi^{k-1}
         const double lkm1 = (nsum(phikm1, i, j, g) - 4.0 * phikm1[q]) * ih2;
         S2[q] = 0.5 * alpha * pk + (3.0 * lk - lkm1);
+        if (pin) S2[q] += pin[q] * (pk - 2.0 * phihat[q]);
         S3[q] = 0.5 * lk;
     }
 }
@@ -370,11 +376,14 @@ __global__ void __launch_bounds__(256) k_source(Grid g, double ih2, double d, do
                                                 const double* __restrict__ phik,
                                                 const double* __restrict__ phikm1,
                                                 const double* __restrict__ psik, double* S1,
-                                                double* S2, double* S3, double* phik_copy) {
+                                                double* S2, double* S3, double* phik_copy,
+                                                const double* __restrict__ pin,
+                                                const double* __restrict__ phihat) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.m || j >= g.n) return;
-    source_cell<SCHEME>(g, ih2, d, alpha, phik, phikm1, psik, S1, S2, S3, phik_copy, i, j);
+    source_cell<SCHEME>(g, ih2, d, alpha, phik, phikm1, psik, S1, S2, S3, phik_copy, i, j, pin,
+                        phihat);
 }
 
 // Initial guess phi^(0): phi^k (mode 0) or 2 phi^k - phi^{k-1} (mode 1).
@@ -415,11 +424,12 @@ __device__ __forceinline__ void complete_mu_cell(const Grid& g, double ih2, doub
                                                  const double* __restrict__ phik,
                                                  const double* __restrict__ ka,
                                                  const double* __restrict__ S2, double* mu, int i,
-                                                 int j) {
+                                                 int j, const double* __restrict__ pin = nullptr) {
     const size_t q = at(i, j, g);
     const double x = phi[q];
     const double xk = SCHEME == 2 ? phik[q] : 0.0;
-    mu[q] = S2[q] + nl_value<double, SCHEME, false>(x, 0.0, xk) + al * x +
+    const double alq = al + (pin ? pin[q] : 0.0);
+    mu[q] = S2[q] + nl_value<double, SCHEME, false>(x, 0.0, xk) + alq * x +
             (nsum(ka, i, j, g) - 4.0 * ka[q]) * ih2;
 }
 
@@ -428,11 +438,12 @@ __global__ void __launch_bounds__(256) k_complete_mu(Grid g, double ih2, double 
                                                      const double* __restrict__ phi,
                                                      const double* __restrict__ phik,
                                                      const double* __restrict__ ka,
-                                                     const double* __restrict__ S2, double* mu) {
+                                                     const double* __restrict__ S2, double* mu,
+                                                     const double* __restrict__ pin) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.m || j >= g.n) return;
-    complete_mu_cell<SCHEME>(g, ih2, al, phi, phik, ka, S2, mu, i, j);
+    complete_mu_cell<SCHEME>(g, ih2, al, phi, phik, ka, S2, mu, i, j, pin);
 }
 
 // 2x2 average (restriction of phi^k for the scheme-2 coarse operators).

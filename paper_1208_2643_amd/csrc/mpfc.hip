@@ -88,6 +88,7 @@ struct Level {
     double* f[3] = {};      // complete right-hand side (finest: S)
     double* rr[3] = {};     // restricted residual (coarse levels)
     double* xk = nullptr;   // phi^k on this level (scheme 2)
+    double* pin = nullptr;  // pinning weight on this level (2x2 averages of the finest)
     // Poisson problem of the -1 norm
     double* w[2] = {};
     double* pv = nullptr;
@@ -115,6 +116,9 @@ struct mpfc_ctx {
     double* phist = nullptr;
     double* acc = nullptr;      // reduction results
     double* part = nullptr;     // per-block partial sums of the reductions
+    bool pinned = false;        // pinning term of Sec. 4.4 active
+    double* pin_mem = nullptr;  // weights of every level, then phi_hat (own allocation)
+    double* phihat = nullptr;
     int nparts = 0;
     double* G = nullptr;        // coarsest Poisson Green's matrix
     int have_w = 0;
@@ -184,6 +188,7 @@ Fields<double> finest_fields(const mpfc_ctx* C) {
     F.f1 = lv.f[0]; F.f2 = lv.f[1]; F.f3 = lv.f[2];
     F.phik = C->p.scheme == 2 ? C->phik : nullptr;
     F.base = nullptr;
+    F.pin = C->pinned ? lv.pin : nullptr;
     return F;
 }
 
@@ -297,6 +302,7 @@ TileArgs<double> dn_args64(const mpfc_ctx* C, int l) {
     }
     T.xk = A.xk;
     T.xkH = B.xk;  // phi^k of the next level (scheme 2), averaged in-kernel
+    T.pin = C->pinned ? A.pin : nullptr;
     T.complete_f = l > 0;
     T.nsweep = 2 * C->o.nu1;
     T.H = round_even(T.nsweep + 1);
@@ -317,6 +323,7 @@ TileArgs<double> up_args64(const mpfc_ctx* C, int l, bool norm) {
         T.cvH[f] = B.v[f];
     }
     T.xk = A.xk;
+    T.pin = C->pinned ? A.pin : nullptr;
     T.nsweep = 2 * C->o.nu2;
     T.norm = norm;
     T.H = l == 0 ? round_even(T.nsweep + 1) : T.nsweep;
@@ -334,6 +341,7 @@ CoarseArgs<double> coarse_args64(const mpfc_ctx* C) {
         A.rr[f] = C->Lp > 0 ? top.rr[f] : top.f[f];
     }
     A.xk = top.xk;
+    A.pin = C->pinned ? top.pin : nullptr;
     A.h_top = top.h;
     A.nsw1 = 2 * C->o.nu1;
     A.nsw2 = 2 * C->o.nu2;
@@ -566,6 +574,8 @@ void vcycle_mpfc(mpfc_ctx* C, hipStream_t s) {
     if (C->p.scheme == 1) {
         if (nw) vcycle_mpfc_t<MpfcOp<double, 1, true, false>>(C, s);
         else vcycle_mpfc_t<MpfcOp<double, 1, false, false>>(C, s);
+    } else if (C->pinned) {  // Sec. 4.4 pinning: scheme 2, Newton (checked when set)
+        vcycle_mpfc_t<MpfcOp<double, 2, true, false, true>>(C, s);
     } else {
         if (nw) vcycle_mpfc_t<MpfcOp<double, 2, true, false>>(C, s);
         else vcycle_mpfc_t<MpfcOp<double, 2, false, false>>(C, s);
@@ -937,7 +947,9 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
     // the warm count was too small do more cycles (and the sums again) follow.
     auto terms = [&]() -> int {
         hipLaunchKernelGGL((k_energy_terms<NT>), dim3(rb), dim3(NT), 0, s, F0.g,
-                           1.0 / (F0.h * F0.h), phi, phiprev, F0.pf, F0.w[0], C->part);
+                           1.0 / (F0.h * F0.h), phi, phiprev, F0.pf, F0.w[0], C->part,
+                           (const double*)(C->pinned ? F0.pin : nullptr),
+                           (const double*)(C->pinned ? C->phihat : nullptr));
         hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 8,
                            C->acc);
         HIP_TRY(hipGetLastError());
@@ -969,7 +981,9 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
     C->have_w = 1;
     const double* a = C->host_buf;
     const double h2 = F0.h * F0.h;
-    const double Fe = 0.25 * h2 * a[0] + 0.5 * C->alpha * h2 * a[1] - a[2] + 0.5 * h2 * a[3];
+    // F (eq. discrete_energy_PFC), with pinning plus h^2 sum W (phi - phi_hat)^2
+    const double Fe = 0.25 * h2 * a[0] + 0.5 * C->alpha * h2 * a[1] - a[2] + 0.5 * h2 * a[3] +
+                      h2 * a[7];
     const double nm1 = h2 * a[6];
     out[0] = Fe;
     out[1] = Fe + nm1 / (2.0 * C->p.M);
@@ -1000,10 +1014,13 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
     double* ka = F0.u[0][2];
     if (C->p.scheme == 1)
         hipLaunchKernelGGL((k_source<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
-                           phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik);
+                           phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik,
+                           (const double*)nullptr, (const double*)nullptr);
     else
         hipLaunchKernelGGL((k_source<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
-                           phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik);
+                           phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik,
+                           (const double*)(C->pinned ? F0.pin : nullptr),
+                           (const double*)(C->pinned ? C->phihat : nullptr));
     hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->st);
     const bool learned = C->o.guess == MPFC_GUESS_CNN;
     if (learned) {
@@ -1018,10 +1035,10 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
     hipLaunchKernelGGL(k_complete_kappa, grid2(C->m, C->n), B2, 0, s, g0, ih2, e, phi, F0.f[2], ka);
     if (C->p.scheme == 1)
         hipLaunchKernelGGL((k_complete_mu<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, phi,
-                           C->phik, ka, F0.f[1], mu);
+                           C->phik, ka, F0.f[1], mu, (const double*)nullptr);
     else
         hipLaunchKernelGGL((k_complete_mu<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, phi,
-                           C->phik, ka, F0.f[1], mu);
+                           C->phik, ka, F0.f[1], mu, (const double*)(C->pinned ? F0.pin : nullptr));
     if (learned) cnn_choose(C, s);
     if (C->o.precision != MPFC_MIXED) {
         if (learned)  // the pick left the kept guess's squared norm in part[0]
@@ -1275,6 +1292,7 @@ void mpfc_destroy(mpfc_ctx* C) {
     for (hipEvent_t e : C->ev)
         if (e) (void)hipEventDestroy(e);
     if (C->cnn) cnn_free(C->cnn);
+    if (C->pin_mem) (void)hipFree(C->pin_mem);
     if (C->arena) (void)hipFree(C->arena);
     if (C->host_st) (void)hipHostFree(C->host_st);
     if (C->host_buf) (void)hipHostFree(C->host_buf);
@@ -1365,6 +1383,47 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
                       ncyc);
         return fail(rc, buf);
     }
+    return MPFC_OK;
+}
+
+int mpfc_set_pinning(mpfc_ctx* C, const double* weight, const double* phihat) {
+    if (!C) return fail(MPFC_EINVAL, "ctx is NULL");
+    if (weight && !phihat) return fail(MPFC_EINVAL, "pinning needs phi_hat");
+    if (weight && (C->p.scheme != 2 || C->o.precision != MPFC_FP64 ||
+                   C->o.linearization != MPFC_NEWTON))
+        return fail(MPFC_EINVAL,
+                    "pinning needs the second-order scheme, FP64 and Newton linearisation");
+    hipStream_t s = C->stream;
+    // the captured cycle changes (other operator instantiation): capture again
+    if (C->gx_mpfc) {
+        HIP_TRY(hipStreamSynchronize(s));
+        (void)hipGraphExecDestroy(C->gx_mpfc);
+        C->gx_mpfc = nullptr;
+    }
+    if (!weight) {
+        C->pinned = false;
+        return MPFC_OK;
+    }
+    const int nl = (int)C->L.size();
+    if (!C->pin_mem) {
+        size_t cells = 0;
+        for (const Level& lv : C->L) cells += (size_t)lv.m * lv.n;
+        cells += (size_t)C->m * C->n;  // phi_hat
+        HIP_TRY(hipMalloc(&C->pin_mem, cells * sizeof(double)));
+        double* p = C->pin_mem;
+        for (Level& lv : C->L) { lv.pin = p; p += (size_t)lv.m * lv.n; }
+        C->phihat = p;
+    }
+    const size_t N = (size_t)C->m * C->n;
+    HIP_TRY(hipMemcpyAsync(C->L[0].pin, weight, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(C->phihat, phihat, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // coarse weights: 2x2 averages, level by level
+    for (int l = 1; l < nl; ++l)
+        hipLaunchKernelGGL((k_restrict<double, double>), grid2(C->L[l].m, C->L[l].n), B2, 0, s,
+                           C->L[l - 1].g, C->L[l - 1].pin, C->L[l].pin);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    C->pinned = true;
     return MPFC_OK;
 }
 
@@ -1480,10 +1539,12 @@ int mpfc_op_source(const mpfc_params* p, int m, int n, const double* phik, const
     hipStream_t s = (hipStream_t)stream;
     if (p->scheme == 1)
         hipLaunchKernelGGL((k_source<1>), grid2(m, n), B2, 0, s, g, 1.0 / (p->h * p->h), d,
-                           1.0 - p->eps, phik, phikm1, psik, S1, S2, S3, nullptr);
+                           1.0 - p->eps, phik, phikm1, psik, S1, S2, S3, nullptr,
+                           (const double*)nullptr, (const double*)nullptr);
     else
         hipLaunchKernelGGL((k_source<2>), grid2(m, n), B2, 0, s, g, 1.0 / (p->h * p->h), d,
-                           1.0 - p->eps, phik, phikm1, psik, S1, S2, S3, nullptr);
+                           1.0 - p->eps, phik, phikm1, psik, S1, S2, S3, nullptr,
+                           (const double*)nullptr, (const double*)nullptr);
     HIP_TRY(hipGetLastError());
     return MPFC_OK;
 }

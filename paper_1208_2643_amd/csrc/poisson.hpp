@@ -135,15 +135,18 @@ __global__ void __launch_bounds__(NT) k_p_resnorm(const double* __restrict__ w,
 //   2: sum over east/north edges of (phi difference)^2,
 //   3: sum (Lap_h phi)^2, 4: sum phi,
 //   5: sum over edges of (difference of phi - phi_prev)^2,
-//   6: sum (psi - mean psi) w.
+//   6: sum (psi - mean psi) w,
+//   7: sum W (phi - phi_hat)^2 (pinning, Sec. 4.4; 0 without pinning).
 template <int NT>
 __global__ void __launch_bounds__(NT) k_energy_terms(Grid g, double ih2,
                                                      const double* __restrict__ phi,
                                                      const double* __restrict__ phiprev,
                                                      const double* __restrict__ b,
-                                                     const double* __restrict__ w, double* part) {
+                                                     const double* __restrict__ w, double* part,
+                                                     const double* __restrict__ pin,
+                                                     const double* __restrict__ phihat) {
     __shared__ double red[NT / 64];
-    double a[7] = {0, 0, 0, 0, 0, 0, 0};
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const size_t total = (size_t)g.m * g.n;
     for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
         const int i = (int)(q & (size_t)(g.m - 1));
@@ -163,14 +166,17 @@ __global__ void __launch_bounds__(NT) k_energy_terms(Grid g, double ih2,
             a[5] += de * de + dn * dn;
         }
         a[6] += b[q] * w[q];
+        if (pin) {  // pinning energy sum W (phi - phi_hat)^2 (Sec. 4.4)
+            const double dp = x - phihat[q];
+            a[7] += pin[q] * dp * dp;
+        }
     }
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < 8; ++k) {
         const double tot = block_sum<NT>(a[k], red);
         if (threadIdx.x == 0) part[(size_t)blockIdx.x * 8 + k] = tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[(size_t)blockIdx.x * 8 + 7] = 0.0;
 }
 
 }  // namespace mpfc

@@ -38,28 +38,32 @@ namespace mpfc {
 // Cell operators.  ns[f] is the sum of the four neighbours of field f.
 
 // MPFC system N(u) = f (App. B.1 / B.2), optionally in correction (DEFECT) form.
-template <typename T, int SCHEME, bool NEWTON, bool DEFECT>
+// PIN: the pinning of Sec. 4.4 adds the per-cell weight w to the coefficient
+// of phi in N^(2) (the unknown mu is mu~); w = 0 otherwise.
+template <typename T, int SCHEME, bool NEWTON, bool DEFECT, bool PIN = false>
 struct MpfcOp {
     using real = T;
     static constexpr int NF = 3;
     static constexpr bool XK = SCHEME == 2;
     static constexpr bool PB = DEFECT;
+    static constexpr bool PW = PIN;
     LevelOp<T> op;
 
-    __device__ __forceinline__ void apply(const T* u, const T* ns, T xk, T pb, T* N) const {
+    __device__ __forceinline__ void apply(const T* u, const T* ns, T xk, T pb, T w, T* N) const {
         const T lphi = (ns[0] - T(4) * u[0]) * op.ih2;
         const T lmu = (ns[1] - T(4) * u[1]) * op.ih2;
         const T lka = (ns[2] - T(4) * u[2]) * op.ih2;
+        const T al = PIN ? op.al + w : op.al;
         N[0] = u[0] - op.c * lmu;
-        N[1] = u[1] - nl_value<T, SCHEME, DEFECT>(u[0], pb, xk) - op.al * u[0] - lka;
+        N[1] = u[1] - nl_value<T, SCHEME, DEFECT>(u[0], pb, xk) - al * u[0] - lka;
         N[2] = u[2] - op.e * lphi;
     }
     // Collective update of one cell: J_loc delta = f - N(u) (see relax_at).
-    __device__ __forceinline__ void relax(T* u, const T* ns, const T* f, T xk, T pb) const {
+    __device__ __forceinline__ void relax(T* u, const T* ns, const T* f, T xk, T pb, T w) const {
         T N[3];
-        apply(u, ns, xk, pb, N);
+        apply(u, ns, xk, pb, w, N);
         const T r1 = f[0] - N[0], r2 = f[1] - N[1], r3 = f[2] - N[2];
-        const T d = op.al + nl_lin<T, SCHEME, NEWTON>(pb + u[0], xk);
+        const T d = (PIN ? op.al + w : op.al) + nl_lin<T, SCHEME, NEWTON>(pb + u[0], xk);
         const T a = T(4) * op.c * op.ih2, b = T(4) * op.ih2, ec = T(4) * op.e * op.ih2;
         const T det = T(1) + a * d + a * b * ec;
         const T dm = (r2 + (d + b * ec) * r1 - b * r3) / det;
@@ -78,11 +82,12 @@ struct PoissonOp {
     static constexpr int NF = 1;
     static constexpr bool XK = false;
     static constexpr bool PB = false;
+    static constexpr bool PW = false;
     T ih2, h2;
-    __device__ __forceinline__ void apply(const T* u, const T* ns, T, T, T* N) const {
+    __device__ __forceinline__ void apply(const T* u, const T* ns, T, T, T, T* N) const {
         N[0] = (T(4) * u[0] - ns[0]) * ih2;
     }
-    __device__ __forceinline__ void relax(T* u, const T* ns, const T* f, T, T) const {
+    __device__ __forceinline__ void relax(T* u, const T* ns, const T* f, T, T, T) const {
         u[0] = T(0.25) * (h2 * f[0] + ns[0]);
     }
 };
@@ -100,6 +105,7 @@ struct TileArgs {
     const T* pb;            // base phi (correction form)
     T* uH[3]; T* vH[3]; T* rH[3];          // down: restricted u (twice) and residual
     T* xkH; T* pbH;         // down (nullable): 2x2 averages of phi^k and of the base phi
+    const T* pin;           // pinning weight on this level (Op::PW)
     const T* cuH[3]; const T* cvH[3];      // up: coarse u after and before its solve
     int complete_f;         // down on a coarse level
     int zero_in;            // u before the launch is zero (uin is not read)
@@ -175,6 +181,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
     T fr[SL][4][NF];
     T xkr[SL][4];
     T pbr[SL][4];
+    T wr[SL][4];
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
         const int b = t + s * NT;
@@ -184,6 +191,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
             for (int f = 0; f < NF; ++f) fr[s][c][f] = T(0);
             xkr[s][c] = T(0);
             pbr[s][c] = T(0);
+            wr[s][c] = T(0);
         }
         if (b >= nblk) continue;
         const int by = b / LX2, bx = b - by * LX2;
@@ -195,6 +203,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
             const size_t gq = at(bidx<NEU>(x0 + x, g.m, g.bc & BC_NEUMANN_X), bidx<NEU>(y0 + y, g.n, g.bc & BC_NEUMANN_Y), g);
             if constexpr (Op::XK) xkr[s][c] = A.xk[gq];
             if constexpr (Op::PB) pbr[s][c] = A.pb[gq];
+            if constexpr (Op::PW) wr[s][c] = A.pin[gq];
 #pragma unroll
             for (int f = 0; f < NF; ++f) fr[s][c][f] = A.f[f][gq];
         }
@@ -258,7 +267,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
                     ns[f] = (U[f][oc][y][ke] + U[f][oc][y][kw]) +
                             (U[f][oc][y + 1][k] + U[f][oc][y - 1][k]);
                 }
-                op.apply(u, ns, xkr[s][c], pbr[s][c], N);
+                op.apply(u, ns, xkr[s][c], pbr[s][c], wr[s][c], N);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) fr[s][c][f] += N[f];
             }
@@ -293,7 +302,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
                     ns[f] = (U[f][oc][y][ke] + U[f][oc][y][kw]) +
                             (U[f][oc][y + 1][k] + U[f][oc][y - 1][k]);
                 }
-                op.relax(u, ns, fr[s][c], xkr[s][c], pbr[s][c]);
+                op.relax(u, ns, fr[s][c], xkr[s][c], pbr[s][c], wr[s][c]);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) U[f][colour][y][k] = u[f];
             }
@@ -378,7 +387,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
                 ns[f] = (U[f][oc][y][ke] + U[f][oc][y][kw]) +
                         (U[f][oc][y + 1][k] + U[f][oc][y - 1][k]);
             }
-            op.apply(u, ns, xkr[s][c], pbr[s][c], N);
+            op.apply(u, ns, xkr[s][c], pbr[s][c], wr[s][c], N);
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 const T r = fr[s][c][f] - N[f];
@@ -493,6 +502,7 @@ struct CoarseArgs {
     const T* rr[3];       // top level restricted residual R r (global)
     const T* xk;          // phi^k on the top level (global)
     const T* pb;          // base phi on the top level (global)
+    const T* pin;         // pinning weight on the top level (global; Op::PW)
     T h_top;              // spacing of the top level
     int nsw1, nsw2;       // half-sweeps down / up
     int complete_top;     // 1: rr holds R r (add N(u)); 0: rr is already the full f
@@ -513,7 +523,8 @@ __device__ __forceinline__ void coarse_solve_mpfc(const Op& op, typename Op::rea
                                                   typename Op::real* mu, typename Op::real* ka,
                                                   const typename Op::real (&f)[3 * NC],
                                                   const typename Op::real* xk,
-                                                  const typename Op::real* pb, int m, int lm,
+                                                  const typename Op::real* pb,
+                                                  const typename Op::real* pw, int m, int lm,
                                                   int n, int bc, int maxit, typename Op::real tol) {
     using T = typename Op::real;
     const T c = op.op.c, e = op.op.e, al = op.op.al;
@@ -566,12 +577,13 @@ __device__ __forceinline__ void coarse_solve_mpfc(const Op& op, typename Op::rea
 #pragma unroll
         for (int a = 0; a < NC; ++a) L3[a][b] = col[a];
     }
-    T x[NC], xkv[NC], pbv[NC];
+    T x[NC], xkv[NC], pbv[NC], alv[NC];
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
         x[a] = phi[a];
         xkv[a] = Op::XK ? xk[a] : T(0);
         pbv[a] = Op::PB ? pb[a] : T(0);
+        alv[a] = Op::PW ? al + pw[a] : al;  // pinning: W added to the phi coefficient
     }
     for (int it = 0; it < maxit; ++it) {
         // residual R = x - c Lap(g(x) + al x + e Lap^2 x) - rhs
@@ -580,8 +592,8 @@ __device__ __forceinline__ void coarse_solve_mpfc(const Op& op, typename Op::rea
         lap(t1, t2);
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
-            w[a] = nl_value<T, (Op::XK ? 2 : 1), Op::PB>(x[a], pbv[a], xkv[a]) + al * x[a] + e * t2[a];
-            d[a] = nl_lin<T, (Op::XK ? 2 : 1), true>(pbv[a] + x[a], xkv[a]) + al;
+            w[a] = nl_value<T, (Op::XK ? 2 : 1), Op::PB>(x[a], pbv[a], xkv[a]) + alv[a] * x[a] + e * t2[a];
+            d[a] = nl_lin<T, (Op::XK ? 2 : 1), true>(pbv[a] + x[a], xkv[a]) + alv[a];
         }
         lap(w, t1);
 #pragma unroll
@@ -638,7 +650,7 @@ __device__ __forceinline__ void coarse_solve_mpfc(const Op& op, typename Op::rea
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
         ka[a] = t1[a];
-        mu[a] = f2[a] + nl_value<T, (Op::XK ? 2 : 1), Op::PB>(x[a], pbv[a], xkv[a]) + al * x[a] + t2[a];
+        mu[a] = f2[a] + nl_value<T, (Op::XK ? 2 : 1), Op::PB>(x[a], pbv[a], xkv[a]) + alv[a] * x[a] + t2[a];
         phi[a] = x[a];
     }
 }
@@ -699,6 +711,7 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
     __shared__ T Sv[NF][CP_TOTAL];
     __shared__ T Sxk[Op::XK ? CP_TOTAL : 1];
     __shared__ T Spb[Op::PB ? CP_TOTAL : 1];
+    __shared__ T Spw[Op::PW ? CP_TOTAL : 1];
     if (stopped(stop)) return;
     const int t = threadIdx.x;
     const CoarseGeom& G = A.geo;
@@ -712,10 +725,11 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
         }
         if constexpr (Op::XK) Sxk[q] = A.xk[q];
         if constexpr (Op::PB) Spb[q] = A.pb[q];
+        if constexpr (Op::PW) Spw[q] = A.pin[q];
     }
     __syncthreads();
     // coefficient pyramids (2x2 averages)
-    if constexpr (Op::XK || Op::PB) {
+    if constexpr (Op::XK || Op::PB || Op::PW) {
         for (int l = 1; l < G.nlev; ++l) {
             const int mf = G.m[l - 1], lmc = G.lm[l], mcv = G.m[l];
             for (int q = t; q < mcv * G.n[l]; q += NTP) {
@@ -725,6 +739,8 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
                     Sxk[G.off[l] + q] = T(0.25) * ((Sxk[a] + Sxk[a + 1]) + (Sxk[a + mf] + Sxk[a + mf + 1]));
                 if constexpr (Op::PB)
                     Spb[G.off[l] + q] = T(0.25) * ((Spb[a] + Spb[a + 1]) + (Spb[a + mf] + Spb[a + mf + 1]));
+                if constexpr (Op::PW)
+                    Spw[G.off[l] + q] = T(0.25) * ((Spw[a] + Spw[a + 1]) + (Spw[a + mf] + Spw[a + mf + 1]));
             }
             __syncthreads();
         }
@@ -752,7 +768,8 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
             T u[NF], ns[NF], N[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) { u[f] = Su[f][off + q]; ns[f] = nsum_l(&Su[f][off], i, j, m, lm, n); }
-            o.apply(u, ns, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0), N);
+            o.apply(u, ns, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0),
+                    Op::PW ? Spw[off + q] : T(0), N);
 #pragma unroll
             for (int f = 0; f < NF; ++f) Sf[f][off + q] += N[f];
         }
@@ -774,7 +791,8 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
                     ns[f] = nsum_l(&Su[f][off], i, j, m, lm, n);
                     fv[f] = Sf[f][off + q];
                 }
-                o.relax(u, ns, fv, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0));
+                o.relax(u, ns, fv, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0),
+                        Op::PW ? Spw[off + q] : T(0));
 #pragma unroll
                 for (int f = 0; f < NF; ++f) Su[f][off + q] = u[f];
             }
@@ -801,7 +819,8 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
                 T u[NF], ns[NF], N[NF];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) { u[f] = Su[f][off + q]; ns[f] = nsum_l(&Su[f][off], i, j, m, lm, n); }
-                o.apply(u, ns, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0), N);
+                o.apply(u, ns, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0),
+                    Op::PW ? Spw[off + q] : T(0), N);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) { su[f] += u[f]; sr[f] += Sf[f][off + q] - N[f]; }
             }
@@ -831,7 +850,8 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
                 }
                 T* xkp = Op::XK ? &Sxk[off] : nullptr;
                 T* pbp = Op::PB ? &Spb[off] : nullptr;
-                coarse_solve_mpfc<Op, NC>(o, &Su[0][off], &Su[1][off], &Su[2][off], fbuf, xkp, pbp,
+                T* pwp = Op::PW ? &Spw[off] : nullptr;
+                coarse_solve_mpfc<Op, NC>(o, &Su[0][off], &Su[1][off], &Su[2][off], fbuf, xkp, pbp, pwp,
                                           G.m[l], G.lm[l], G.n[l], NEU ? G.bc : 0,
                                           A.newton_maxit, A.newton_tol);
             }
