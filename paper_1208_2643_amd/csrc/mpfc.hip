@@ -916,8 +916,11 @@ int status_code(int st) {
 // step's chemical potential) the previous Poisson solution is first advanced
 // by the scheme's own relation between psi^{k+1}, psi^k and Lap mu, which
 // leaves only the solver residual for the Poisson cycles to remove.
+// hist_count > 0: the step's residual history (that many entries) rides on
+// the same readback, into host_buf + kHistSlot.
+constexpr int kHistSlot = 16;
 int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, const double* psi,
-                     const double* mu, double* out) {
+                     const double* mu, double* out, int hist_count = 0) {
     hipStream_t s = C->stream;
     Level& F0 = C->L[0];
     const size_t total = (size_t)C->m * C->n;
@@ -954,6 +957,9 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
                            C->acc);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(C->host_buf, C->acc, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (hist_count > 0)
+            HIP_TRY(hipMemcpyAsync(C->host_buf + kHistSlot, C->hist, sizeof(double) * hist_count,
+                                   hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(C->host_st, C->pst, sizeof(CycleState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         return MPFC_OK;
@@ -1357,7 +1363,8 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     const int rc = status_code(fin.status);
     double en[4] = {0, 0, 0, 0};
     if (C->o.energy) {
-        const int erc = compute_energies(C, phi, phi_n, psi, mu, en);
+        // the history rides on the energies' readback (one wait for both)
+        const int erc = compute_energies(C, phi, phi_n, psi, mu, en, info ? fin.count : 0);
         if (erc && erc != MPFC_ENOTCONVERGED) return erc;
     }
     if (info) {
@@ -1368,12 +1375,15 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
         info->energy_pseudo = en[1];
         info->energy_mod = en[2];
         info->mass = en[3];
-        HIP_TRY(hipMemcpyAsync(C->host_buf, C->hist, sizeof(double) * fin.count,
-                               hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        info->residual = C->host_buf[fin.count - 1];
+        if (!C->o.energy) {
+            HIP_TRY(hipMemcpyAsync(C->host_buf + kHistSlot, C->hist, sizeof(double) * fin.count,
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        const double* hb = C->host_buf + kHistSlot;
+        info->residual = hb[fin.count - 1];
         if (info->residual_history)
-            std::memcpy(info->residual_history, C->host_buf, sizeof(double) * fin.count);
+            std::memcpy(info->residual_history, hb, sizeof(double) * fin.count);
     } else {
         HIP_TRY(hipStreamSynchronize(s));
     }
