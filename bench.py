@@ -43,9 +43,9 @@ COMPULSORY_BYTES = {"down": 56.0 + 24.0 + 20.0, "up": 56.0 + 12.0 + 24.0}
 # shape "TXxTY/HALO", valid only for the kernel sources they were measured on
 # (hash of paper_1208_2643_amd/csrc/*).
 MEASURED_TRAFFIC = {
-    "src": "a72a9a490c045477",
-    "down": {"64x32/6": 110235261, "32x32/6": 115027428, "32x16/6": 110204754, "16x16/6": 109968370, "64x16/10": 114818174, "32x16/10": 110182436, "16x16/10": 110042797},
-    "up": {"64x32/6": 109655583, "32x32/6": 107611363, "32x16/6": 103329636, "16x16/6": 103159489, "64x16/10": 103345607, "32x16/10": 103248760, "16x16/10": 103208424},
+    "src": "67e24d572c0daacd",
+    "down": {"64x32/6": 110247360, "32x32/6": 115010423, "32x16/6": 110159727, "16x16/6": 109968185, "64x16/10": 114774962, "32x16/10": 110196992, "16x16/10": 110044045},
+    "up": {"64x32/6": 109615756, "32x32/6": 107605741, "32x16/6": 103353320, "16x16/6": 103160242, "64x16/10": 103347996, "32x16/10": 103231494, "16x16/10": 103215114},
 }
 
 
