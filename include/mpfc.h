@@ -9,9 +9,10 @@
  * phase field crystal equation".
  *
  * The problem (Sec. 3.1, Sec. 3.2, App. B): given phi^k, psi^k (and phi^{k-1}
- * for the second-order scheme) on a periodic m x n cell-centred grid with
- * spacing h, find phi^{k+1}, mu, kappa solving N(u) = S (App. B.1, B.2) and
- * then psi^{k+1} (eq. discrete_1_b or discrete_2_b).
+ * for the second-order scheme) on an m x n cell-centred grid with spacing h
+ * (each axis periodic or homogeneous Neumann, App. A), find phi^{k+1}, mu,
+ * kappa solving N(u) = S (App. B.1, B.2) and then psi^{k+1} (eq. discrete_1_b
+ * or discrete_2_b).
  *
  * Conventions for every entry point:
  *  - Grid functions are contiguous arrays of m*n values, row-major with x
@@ -140,8 +141,8 @@ int mpfc_create(mpfc_ctx **out, int m, int n, const mpfc_params *p, const mpfc_o
 int mpfc_step(mpfc_ctx *ctx, const double *d_phi_n, const double *d_phi_nm1, double *d_psi,
               double *d_phi_np1, double *d_mu, double *d_kappa, mpfc_info *h_info);
 
-/* Energies of a state (Sec. 3; App. A "-1" norm with a mean-zero periodic
- * Poisson solve): out[0..3] = F(phi), F + ||psi||_{-1}^2/(2M),
+/* Energies of a state (Sec. 3; App. A "-1" norm with a mean-zero Poisson
+ * solve under the context's boundary conditions): out[0..3] = F(phi), F + ||psi||_{-1}^2/(2M),
  * that + ||grad_h(phi - phi_prev)||^2/2, h^2 sum phi.  d_phi_prev may be NULL
  * (then the last term is 0). */
 int mpfc_energies(mpfc_ctx *ctx, const double *d_phi, const double *d_phi_prev,

@@ -2,10 +2,11 @@
 // (Sec. 3; App. A).
 //
 // The "-1" norm of a mean-zero grid function psi is ||psi||_{-1}^2 = h^2 (psi, w)
-// with -Lap_h w = psi, w periodic and mean-zero (App. A, mean-zero space H).
+// with -Lap_h w = psi, w mean-zero with the grid's boundary conditions (App. A,
+// mean-zero space H).
 // w is found with the same V-cycle kernels as the MPFC system (tiles.hpp,
 // PoissonOp): red-black Gauss-Seidel, 2x2-average restriction, bilinear
-// prolongation, and on the coarsest grid a precomputed periodic Green's matrix.
+// prolongation, and on the coarsest grid a precomputed Green's matrix.
 //
 // Every reduction writes one partial sum per block (no atomics, no
 // device-wide fences); k_partials_sum adds them in a fixed order, so all sums

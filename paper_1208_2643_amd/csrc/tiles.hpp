@@ -12,7 +12,7 @@
 // kernel that keeps them in LDS and solves the coarsest grid directly.
 //
 // Tiles.  A workgroup owns a tx x ty interior tile and loads it with a halo
-// of H cells (periodic wrap) into LDS.  After p half-sweeps the cells at
+// of H cells (periodic wrap, or reflection on a Neumann axis) into LDS.  After p half-sweeps the cells at
 // distance >= p from the loaded border hold exactly the values of a global
 // red-black sweep (a red cell only reads black neighbours and vice versa), so
 // H >= number of half-sweeps (+1 when a residual follows) makes the interior
@@ -75,7 +75,7 @@ struct MpfcOp {
     }
 };
 
-// Periodic Poisson problem -Lap_h w = b (App. A "-1" norm), same interface.
+// Poisson problem -Lap_h w = b (App. A "-1" norm), same interface.
 template <typename T>
 struct PoissonOp {
     using real = T;
