@@ -944,6 +944,15 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
                            C->acc + 10);
     }
     hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->pst);
+    // The warm start may already meet the stopping test: its residual is the
+    // first norm of the solve, so cycles enqueued behind it exit at once.
+    const bool warm = C->have_w != 0;
+    if (warm) {
+        hipLaunchKernelGGL((k_p_resid<NT>), dim3(rb), dim3(NT), 0, s, F0.g, 1.0 / (F0.h * F0.h),
+                           F0.w[0], F0.pf, C->part);
+        hipLaunchKernelGGL((k_p_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, C->pst,
+                           C->phist, C->acc + 9, kPoissonRel, kPoissonStall, kPoissonMax);
+    }
     HIP_TRY(hipGetLastError());
     // Poisson cycles stop on the device (k_p_finalize); the energy sums are
     // enqueued behind them, so one readback usually ends the step.  Only when
@@ -980,10 +989,11 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
         if (rc) return rc;
     }
     const bool ok = C->host_st->status == ST_CONVERGED;
-    const int ran = C->host_st->count;
-    // keep the number of warm cycles just large enough
+    const int ran = C->host_st->count - (warm ? 1 : 0);  // V-cycles that ran
+    // keep the number of cycles enqueued up front just large enough (0 when
+    // the warm start alone passes)
     if (ran >= C->poisson_cycles) C->poisson_cycles = ran < 8 ? ran : 8;
-    else if (C->poisson_cycles > 1) C->poisson_cycles -= 1;
+    else if (C->poisson_cycles > 0) C->poisson_cycles -= 1;
     C->have_w = 1;
     const double* a = C->host_buf;
     const double h2 = F0.h * F0.h;

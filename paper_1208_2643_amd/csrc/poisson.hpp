@@ -130,6 +130,24 @@ __global__ void __launch_bounds__(NT) k_p_resnorm(const double* __restrict__ w,
     if (threadIdx.x == 0) part[blockIdx.x] = bs;
 }
 
+// part[blk] = block share of sum r^2, r = b - (-Lap_h w): the residual of a
+// Poisson iterate, here of the warm start before any cycle.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_p_resid(Grid g, double ih2, const double* __restrict__ w,
+                                                const double* __restrict__ b, double* part) {
+    __shared__ double red[NT / 64];
+    double acc = 0.0;
+    const size_t total = (size_t)g.m * g.n;
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
+        const int i = (int)(q & (size_t)(g.m - 1));
+        const int j = (int)(q >> g.lm);
+        const double r = b[q] - (4.0 * w[q] - nsum(w, i, j, g)) * ih2;
+        acc += r * r;
+    }
+    const double bs = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
 // Energy sums after a step (Sec. 3, eqs. discrete_energy_PFC, energy_numer;
 // App. A norms), per block into part[blk * 8 + k]:
 //   k = 0: sum phi^4, 1: sum phi^2,
