@@ -642,7 +642,7 @@ void vcycle_poisson(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) 
         if (T.norm) {
             const int nb = (A.m / T.tx) * (A.n / T.ty);
             hipLaunchKernelGGL((k_p_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, nb, C->pst,
-                               C->phist, C->acc + 9, kPoissonRel, kPoissonStall, kPoissonMax);
+                               C->phist, C->acc + 10, kPoissonRel, kPoissonStall, kPoissonMax);
         }
     }
     if (Lp == 0 && only < 0) {
@@ -651,7 +651,7 @@ void vcycle_poisson(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) 
         hipLaunchKernelGGL((k_p_resnorm<NT>), dim3(nb), dim3(NT), 0, s, F0.w[0], F0.pf, F0.g,
                            1.0 / (F0.h * F0.h), C->pst, C->part);
         hipLaunchKernelGGL((k_p_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)nb, C->pst,
-                           C->phist, C->acc + 9, kPoissonRel, kPoissonStall, kPoissonMax);
+                           C->phist, C->acc + 10, kPoissonRel, kPoissonStall, kPoissonMax);
     }
 }
 
@@ -925,34 +925,33 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
     Level& F0 = C->L[0];
     const size_t total = (size_t)C->m * C->n;
     const unsigned rb = red_blocks(total);
-    hipLaunchKernelGGL((k_sum<NT>), dim3(rb), dim3(NT), 0, s, psi, total, C->part);
-    hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 1, C->acc + 8);
-    hipLaunchKernelGGL((k_p_rhs<NT>), dim3(rb), dim3(NT), 0, s, psi, total, C->acc + 8, F0.pf,
-                       C->part);
-    hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 1, C->acc + 9);
-    if (!C->have_w) {
+    // sums of psi and mu (acc[8], acc[9]), Poisson state reset; then the
+    // recursion for w, b = psi - mean and the sums of b^2 and of the warm
+    // start's squared residual (acc[10], acc[11])
+    const bool warm = C->have_w != 0;
+    const bool advance = warm && mu;
+    hipLaunchKernelGGL((k_sum2<NT>), dim3(rb), dim3(NT), 0, s, psi, advance ? mu : nullptr, total,
+                       C->part, C->pst);
+    hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 2, C->acc + 8);
+    if (!warm) {
         hipLaunchKernelGGL((k_fill<double>), grid1(total), dim3(256), 0, s, F0.w[0], total, 0.0);
-    } else if (mu) {
+    } else if (advance) {
         const double sb = C->p.dt * C->p.beta, sM = C->p.dt * C->p.M;
         double a, b;
         if (C->p.scheme == 1) { a = 1.0 / (1.0 + sb); b = sM / (1.0 + sb); }
         else { a = (1.0 - 0.5 * sb) / (1.0 + 0.5 * sb); b = sM / (1.0 + 0.5 * sb); }
-        hipLaunchKernelGGL((k_sum<NT>), dim3(rb), dim3(NT), 0, s, mu, total, C->part);
-        hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 1,
-                           C->acc + 10);
         hipLaunchKernelGGL((k_w_advance), grid1(total), dim3(256), 0, s, F0.w[0], mu, total, a, b,
-                           C->acc + 10);
+                           C->acc + 9);
     }
-    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->pst);
+    hipLaunchKernelGGL((k_p_rhs_resid<NT>), dim3(rb), dim3(NT), 0, s, F0.g, 1.0 / (F0.h * F0.h),
+                       psi, C->acc + 8, F0.pf, warm ? F0.w[0] : nullptr, C->part);
+    hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 2,
+                       C->acc + 10);
     // The warm start may already meet the stopping test: its residual is the
     // first norm of the solve, so cycles enqueued behind it exit at once.
-    const bool warm = C->have_w != 0;
-    if (warm) {
-        hipLaunchKernelGGL((k_p_resid<NT>), dim3(rb), dim3(NT), 0, s, F0.g, 1.0 / (F0.h * F0.h),
-                           F0.w[0], F0.pf, C->part);
-        hipLaunchKernelGGL((k_p_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, C->pst,
-                           C->phist, C->acc + 9, kPoissonRel, kPoissonStall, kPoissonMax);
-    }
+    if (warm)
+        hipLaunchKernelGGL((k_p_finalize<NT>), dim3(1), dim3(NT), 0, s, C->acc + 11, 1, C->pst,
+                           C->phist, C->acc + 10, kPoissonRel, kPoissonStall, kPoissonMax);
     HIP_TRY(hipGetLastError());
     // Poisson cycles stop on the device (k_p_finalize); the energy sums are
     // enqueued behind them, so one readback usually ends the step.  Only when

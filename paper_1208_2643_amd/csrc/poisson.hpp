@@ -36,33 +36,7 @@ __global__ void __launch_bounds__(NT) k_partials_sum(const double* __restrict__ 
     }
 }
 
-// part[b] = block b's share of sum f
-template <int NT>
-__global__ void __launch_bounds__(NT) k_sum(const double* __restrict__ f, size_t total, double* part) {
-    __shared__ double red[NT / 64];
-    double s = 0.0;
-    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT)
-        s += f[q];
-    const double tot = block_sum<NT>(s, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
 
-// b = psi - mean(psi) (mean = sum[0]/total); part[blk] = block share of sum b^2.
-template <int NT>
-__global__ void __launch_bounds__(NT) k_p_rhs(const double* __restrict__ psi, size_t total,
-                                              const double* __restrict__ sum, double* b,
-                                              double* part) {
-    __shared__ double red[NT / 64];
-    const double mean = sum[0] / (double)total;
-    double s = 0.0;
-    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
-        const double v = psi[q] - mean;
-        b[q] = v;
-        s += v * v;
-    }
-    const double tot = block_sum<NT>(s, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
 
 // Advance the Poisson solution across a time step.  With -Lap_h w^k = psi^k,
 // the scheme's psi equation (eq. scheme1_1 or mpfc_scheme2_1 with the psi
@@ -130,22 +104,61 @@ __global__ void __launch_bounds__(NT) k_p_resnorm(const double* __restrict__ w,
     if (threadIdx.x == 0) part[blockIdx.x] = bs;
 }
 
-// part[blk] = block share of sum r^2, r = b - (-Lap_h w): the residual of a
-// Poisson iterate, here of the warm start before any cycle.
+// Step 1 of the energies: per-block sums of x and y (y may be null: 0) into
+// part[blk * 2 + 0/1]; block 0 also resets the Poisson cycle state `st`.
 template <int NT>
-__global__ void __launch_bounds__(NT) k_p_resid(Grid g, double ih2, const double* __restrict__ w,
-                                                const double* __restrict__ b, double* part) {
+__global__ void __launch_bounds__(NT) k_sum2(const double* __restrict__ x,
+                                             const double* __restrict__ y, size_t total,
+                                             double* part, CycleState* st) {
     __shared__ double red[NT / 64];
-    double acc = 0.0;
-    const size_t total = (size_t)g.m * g.n;
-    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
-        const int i = (int)(q & (size_t)(g.m - 1));
-        const int j = (int)(q >> g.lm);
-        const double r = b[q] - (4.0 * w[q] - nsum(w, i, j, g)) * ih2;
-        acc += r * r;
+    if (st && blockIdx.x == 0 && threadIdx.x == 0) {
+        st->acc = 0.0; st->blocks = 0u; st->count = 0;
+        st->status = ST_RUNNING; st->done = 0; st->pad0 = st->pad1 = 0;
     }
-    const double bs = block_sum<NT>(acc, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+    double sx = 0.0, sy = 0.0;
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
+        sx += x[q];
+        if (y) sy += y[q];
+    }
+    const double tx = block_sum<NT>(sx, red);
+    __syncthreads();
+    const double ty = block_sum<NT>(sy, red);
+    if (threadIdx.x == 0) {
+        part[(size_t)blockIdx.x * 2] = tx;
+        part[(size_t)blockIdx.x * 2 + 1] = ty;
+    }
+}
+
+// b = psi - mean(psi) (mean = sum[0] / total) and per-block sums of b^2 and,
+// when w is given, of r^2 with r = b - (-Lap_h w), the residual of the warm
+// start before any cycle, into part[blk * 2 + 0/1].
+template <int NT>
+__global__ void __launch_bounds__(NT) k_p_rhs_resid(Grid g, double ih2,
+                                                    const double* __restrict__ psi,
+                                                    const double* __restrict__ sum, double* b,
+                                                    const double* __restrict__ w, double* part) {
+    __shared__ double red[NT / 64];
+    const size_t total = (size_t)g.m * g.n;
+    const double mean = sum[0] / (double)total;
+    double sb = 0.0, sr = 0.0;
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
+        const double v = psi[q] - mean;
+        b[q] = v;
+        sb += v * v;
+        if (w) {
+            const int i = (int)(q & (size_t)(g.m - 1));
+            const int j = (int)(q >> g.lm);
+            const double r = v - (4.0 * w[q] - nsum(w, i, j, g)) * ih2;
+            sr += r * r;
+        }
+    }
+    const double tb = block_sum<NT>(sb, red);
+    __syncthreads();
+    const double tr = block_sum<NT>(sr, red);
+    if (threadIdx.x == 0) {
+        part[(size_t)blockIdx.x * 2] = tb;
+        part[(size_t)blockIdx.x * 2 + 1] = tr;
+    }
 }
 
 // Energy sums after a step (Sec. 3, eqs. discrete_energy_PFC, energy_numer;
