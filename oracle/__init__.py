@@ -81,7 +81,7 @@ def load():
         "orc_prolong_add": (v, [i, i, _dp, _dp]),
         "orc_dense_newton": (i, [i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, i, _dp]),
         "orc_fas_solve": (i, [i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
-                              i, i, i, d, i, _dp, _dp]),
+                              i, i, i, i, d, i, _dp, _dp]),
         "orc_complete_guess": (v, [i, i, i, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
         "orc_psi_update": (v, [i, ctypes.c_size_t, d, _dp, _dp, _dp, _dp]),
         "orc_energy_F": (d, [i, i, d, d, _dp]),
@@ -89,7 +89,7 @@ def load():
         "orc_poisson_cg": (i, [i, i, d, _dp, _dp, d, i]),
         "orc_norm_m1_sq": (d, [i, i, d, _dp]),
         "orc_energies": (v, [i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp]),
-        "orc_step": (i, [P, i, i, i, _dp, _dp, _dp, i, i, i, i, d, i,
+        "orc_step": (i, [P, i, i, i, _dp, _dp, _dp, i, i, i, i, i, d, i,
                          _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
         "orc_set_bc": (v, [i, i]),
         "orc_version": (i, []),
@@ -260,8 +260,10 @@ def dense_newton(p: Params, u, f, phik=None, h=None, maxit=50, pin=None):
 
 
 def fas_solve(p: Params, u0, S, phik=None, nu1=2, nu2=2, coarsest=2, tol=1e-10,
-              max_cycles=100, newton=True, pin=None):
-    """FAS V-cycles from the guess u0; returns (u, history, cycles)."""
+              max_cycles=100, newton=True, pin=None, coarse_sweeps=0):
+    """FAS V-cycles from the guess u0; returns (u, history, cycles).
+    coarse_sweeps = K > 0 relaxes the coarsest grid by K red-black sweeps
+    instead of solving it by dense Newton."""
     phi, mu, ka = (_arr(x).copy() for x in u0)
     S1, S2, S3 = (_arr(x) for x in S)
     m, n = _shape(phi)
@@ -270,7 +272,7 @@ def fas_solve(p: Params, u0, S, phik=None, nu1=2, nu2=2, coarsest=2, tol=1e-10,
     hist = np.zeros(max_cycles + 1)
     cyc = _lib_bc(p.bc).orc_fas_solve(p.scheme, int(newton), m, n, p.h, c, p.alpha, _p(pk), _p(phi),
                                _p(mu), _p(ka), _p(S1), _p(S2), _p(S3), nu1, nu2, coarsest,
-                               tol, max_cycles, _p(hist), _p(_pin(p, pin)[0]))
+                               coarse_sweeps, tol, max_cycles, _p(hist), _p(_pin(p, pin)[0]))
     ncyc = cyc if cyc >= 0 else -cyc - 1
     return [phi, mu, ka], hist[: ncyc + 1], cyc
 
@@ -344,7 +346,7 @@ class StepResult:
 
 def step(p: Params, phik, phikm1=None, psik=None, guess=0, nu1=2, nu2=2, coarsest=2,
          tol=1e-10, max_cycles=100, newton=True, energy=True, pin=None,
-         phihat=None) -> StepResult:
+         phihat=None, coarse_sweeps=0) -> StepResult:
     """One time step of the chosen scheme from (phi^k, phi^{k-1}, psi^k);
     pin / phihat: pinning weight W and prescribed configuration (Sec. 4.4)."""
     phik = _arr(phik)
@@ -355,7 +357,7 @@ def step(p: Params, phik, phikm1=None, psik=None, guess=0, nu1=2, nu2=2, coarses
     hist = np.zeros(max_cycles + 1)
     en = np.zeros(4)
     cyc = _lib_bc(p.bc).orc_step(ctypes.byref(p._c()), int(newton), m, n, _p(phik), _p(phikm1),
-                          _p(psik), guess, nu1, nu2, coarsest, tol, max_cycles,
+                          _p(psik), guess, nu1, nu2, coarsest, coarse_sweeps, tol, max_cycles,
                           *[_p(x) for x in outs], _p(hist), _p(en) if energy else None,
                           *[_p(x) for x in _pin(p, pin, phihat, need_hat=True)])
     ncyc = cyc if cyc >= 0 else -cyc - 1

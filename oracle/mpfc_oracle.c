@@ -45,6 +45,10 @@
  *    and S^(2) an extra W (phi^k - 2 phi_hat); coarse levels use W restricted
  *    by the 2x2 average, and the reported energy F gains h^2 sum W (phi - phi_hat)^2
  *    (the discrete form of the added integral);
+ *  - grids whose sides are not powers of two (Sec. 4.4 uses 512 x 400) coarsen
+ *    while both sides of the next level stay even; the coarsest level may
+ *    then be too large for the dense Newton solve and is instead relaxed by
+ *    a fixed number of the same red-black sweeps;
  *  - on a homogeneous Neumann boundary the ghost cell (a copy of the boundary
  *    cell) enters the smoother's neighbour sums with the value it has before
  *    the cell is updated (ghosts refreshed before every half-sweep), and the
@@ -435,6 +439,7 @@ typedef struct {
 
 typedef struct {
     int scheme, newton, nu1, nu2, nlev;
+    int coarse_sweeps;  /* 0: dense Newton on the coarsest grid; K > 0: K red-black sweeps */
     double c, alpha;
     orc_level *L;
 } orc_hier;
@@ -442,8 +447,12 @@ typedef struct {
 static void vcycle(orc_hier *H, int l) {
     orc_level *A = &H->L[l];
     if (l == H->nlev - 1) {
-        orc_dense_newton(H->scheme, A->m, A->n, A->h, H->c, H->alpha, A->phik, A->u[0], A->u[1],
-                         A->u[2], A->f[0], A->f[1], A->f[2], 50, A->pin);
+        if (H->coarse_sweeps > 0)
+            orc_smooth(H->scheme, H->newton, H->coarse_sweeps, A->m, A->n, A->h, H->c, H->alpha,
+                       A->phik, A->u[0], A->u[1], A->u[2], A->f[0], A->f[1], A->f[2], A->pin);
+        else
+            orc_dense_newton(H->scheme, A->m, A->n, A->h, H->c, H->alpha, A->phik, A->u[0],
+                             A->u[1], A->u[2], A->f[0], A->f[1], A->f[2], 50, A->pin);
         return;
     }
     orc_level *B = &H->L[l + 1];
@@ -475,24 +484,31 @@ static void vcycle(orc_hier *H, int l) {
 }
 
 /* Solve N(u) = S by FAS V(nu1, nu2) cycles on levels m x n, m/2 x n/2, ...
- * down to the first level whose smaller side equals `coarsest` (or is odd).
+ * A level is coarsened while its smaller side exceeds `coarsest` and both
+ * sides of the next level are even (the red-black colouring of a periodic
+ * axis needs an even number of cells), so 512 x 400 stops at 64 x 50.
+ * The coarsest grid is solved by dense Newton (coarse_sweeps = 0) or
+ * approximately by coarse_sweeps red-black sweeps, for grids whose coarsest
+ * level is too large for a dense solve.
  * u holds the initial guess on entry and the last iterate on exit.
  * history[0] = ||r|| of the guess, history[k] = ||r|| after cycle k
  * (history has room for max_cycles + 1 entries).  Returns the number of
  * cycles run, or -(cycles + 1) if the tolerance was not reached. */
 int orc_fas_solve(int scheme, int newton, int m, int n, double h, double c, double alpha,
                   const double *phik, double *phi, double *mu, double *ka, const double *S1,
-                  const double *S2, const double *S3, int nu1, int nu2, int coarsest, double tol,
-                  int max_cycles, double *history, const double *pin) {
+                  const double *S2, const double *S3, int nu1, int nu2, int coarsest,
+                  int coarse_sweeps, double tol, int max_cycles, double *history,
+                  const double *pin) {
     int nlev = 1;
     {
         int mm = m, nn = n;
-        while ((mm < nn ? mm : nn) > coarsest && mm % 2 == 0 && nn % 2 == 0) {
+        while ((mm < nn ? mm : nn) > coarsest && mm % 4 == 0 && nn % 4 == 0) {
             mm /= 2; nn /= 2; ++nlev;
         }
     }
     orc_hier H;
     H.scheme = scheme; H.newton = newton; H.nu1 = nu1; H.nu2 = nu2; H.nlev = nlev;
+    H.coarse_sweeps = coarse_sweeps;
     H.c = c; H.alpha = alpha;
     H.L = (orc_level *)calloc((size_t)nlev, sizeof(orc_level));
     for (int l = 0; l < nlev; ++l) {
@@ -536,7 +552,10 @@ int orc_fas_solve(int scheme, int newton, int m, int n, double h, double c, doub
     history[0] = nr;
     int cyc = 0;
     while (!(nr <= tol) && cyc < max_cycles) {
-        if (nlev == 1) {
+        if (nlev == 1 && coarse_sweeps > 0) {
+            orc_smooth(scheme, newton, coarse_sweeps, m, n, h, c, alpha, F->phik, phi, mu, ka, S1,
+                       S2, S3, F->pin);
+        } else if (nlev == 1) {
             orc_dense_newton(scheme, m, n, h, c, alpha, F->phik, phi, mu, ka, S1, S2, S3, 50, F->pin);
         } else {
             vcycle(&H, 0);
@@ -738,7 +757,7 @@ void orc_energies(int m, int n, double h, double eps, double M, const double *ph
  * Returns the number of V-cycles, or a negative count if tol was not met. */
 int orc_step(const orc_model *p, int newton, int m, int n, const double *phik,
              const double *phikm1, const double *psik, int guess, int nu1, int nu2, int coarsest,
-             double tol, int max_cycles, double *phinew, double *mu, double *ka, double *psinew,
+             int coarse_sweeps, double tol, int max_cycles, double *phinew, double *mu, double *ka, double *psinew,
              double *history, double *energies, const double *pin, const double *phihat) {
     size_t N = (size_t)m * n;
     double c, d;
@@ -753,7 +772,7 @@ int orc_step(const orc_model *p, int newton, int m, int n, const double *phik,
     const double *pk = p->scheme == 2 ? phik : NULL;
     orc_complete_guess(p->scheme, m, n, p->h, alpha, pk, phinew, mu, ka, S2, S3, pin);
     int cyc = orc_fas_solve(p->scheme, newton, m, n, p->h, c, alpha, pk, phinew, mu, ka, S1, S2,
-                            S3, nu1, nu2, coarsest, tol, max_cycles, history, pin);
+                            S3, nu1, nu2, coarsest, coarse_sweeps, tol, max_cycles, history, pin);
     orc_psi_update(p->scheme, N, p->s, phinew, phik, psik, psinew);
     if (energies) orc_energies(m, n, p->h, p->eps, p->M, phinew, phik, psinew, energies, pin, phihat);
     free(S1); free(S2); free(S3);

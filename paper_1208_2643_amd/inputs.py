@@ -21,6 +21,12 @@ Workloads (each named by what it is):
   (Sec. 4.1, eq. initial-data) on Omega = (0, 32)^2.
 * ``batch``: 64 independent simulations with sizes, eps, mean density and
   beta drawn per simulation.
+* ``strained_crystal``: the sheared-crystal set-up of Sec. 4.4 on its 512 x 400
+  grid: a band of 20 atomic layers of the one-mode profile (solid density
+  phi_s, amplitude A(phi_s, eps)) in a liquid of density phi_l, a pinning
+  weight of 2 in strips of height pi around the bottom and top rows of atoms,
+  and a prescribed configuration equal to the crystal with its bottom row
+  shifted left by 4 % of 2 pi.
 """
 from __future__ import annotations
 
@@ -95,6 +101,43 @@ def paper_initial_data(m: int, n: int, L: float = 32.0) -> np.ndarray:
     return (0.07 - 0.02 * np.cos(2 * p * (X - 12) / 32) * np.sin(2 * p * (Y - 1) / 32)
             + 0.02 * np.cos(p * (X + 10) / 32) ** 2 * np.cos(p * (Y + 3) / 32) ** 2
             - 0.01 * np.sin(4 * p * X / 32) ** 2 * np.sin(4 * p * (Y - 6) / 32) ** 2)
+
+
+def strained_crystal(m: int = 512, n: int = 400, h: float = 4 * math.pi / (16 * math.sqrt(3)),
+                     eps: float = 0.6, phi_s: float = 0.395, phi_l: float = 0.57,
+                     layers: int = 20, weight: float = 2.0, shear: float = 0.04,
+                     seed: int = 6, amp: float = 1e-3):
+    """(phi0, W, phi_hat) of the sheared-crystal test (Sec. 4.4).
+
+    The crystal is phi_s + A (cos(q x) cos(q y / sqrt3) - cos(2 q y / sqrt3) / 2)
+    with q = sqrt(3)/2 and A = 4 phi_s / 5 + (4/15) sqrt(15 eps - 36 phi_s^2)
+    (eq. single_mode_density); its rows of atoms are 2 pi apart in y, and a
+    band of `layers` rows centred in the domain holds it, the rest is liquid
+    phi_l.  A seeded perturbation of size `amp` breaks the symmetry.  W =
+    `weight` within pi / 2 of the bottom and top rows, else 0; phi_hat is the
+    crystal there, its bottom strip shifted left by `shear` * 2 pi.
+    """
+    q = math.sqrt(3.0) / 2.0
+    A = 0.8 * phi_s + (4.0 / 15.0) * math.sqrt(15.0 * eps - 36.0 * phi_s ** 2)
+    X, Y = cell_centres(m, n, h)
+    Ly = n * h
+    y0 = Ly / 2 - (layers - 1) * math.pi       # bottom row of atoms
+    y1 = y0 + 2 * math.pi * (layers - 1)       # top row
+
+    def crystal(x, y):
+        return phi_s + A * (np.cos(q * x) * np.cos(q * y / math.sqrt(3.0))
+                            - 0.5 * np.cos(2 * q * y / math.sqrt(3.0)))
+
+    band = np.abs(Y - 0.5 * (y0 + y1)) <= 0.5 * (y1 - y0) + math.pi
+    phi = np.where(band, crystal(X, Y - y0), phi_l)
+    rng = np.random.default_rng(seed)
+    phi = phi + amp * rng.uniform(-1.0, 1.0, size=phi.shape)
+    bottom = np.abs(Y - y0) < 0.5 * math.pi
+    top = np.abs(Y - y1) < 0.5 * math.pi
+    W = np.where(bottom | top, weight, 0.0)
+    hat = np.where(bottom, crystal(X + shear * 2 * math.pi, Y - y0), crystal(X, Y - y0))
+    hat = np.where(bottom | top, hat, phi)
+    return phi, W, hat
 
 
 @dataclass
