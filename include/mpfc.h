@@ -16,7 +16,8 @@
  *
  * Conventions for every entry point:
  *  - Grid functions are contiguous arrays of m*n values, row-major with x
- *    fastest: cell (i, j) at index j*m + i.  m and n are powers of two.
+ *    fastest: cell (i, j) at index j*m + i.  m and n are powers of two, or
+ *    (mpfc_create, FP64 only) multiples of 4 such as Sec. 4.4's 512 x 400.
  *  - Pointers named d_* are device pointers (hipMalloc'd or from a PyTorch
  *    tensor), owned by the caller, and must stay valid until the call
  *    returns.  Pointers named h_* are host pointers owned by the caller.
@@ -71,9 +72,14 @@ typedef struct {
 /* Solver options.  nu1/nu2: pre/post red-black smoothing passes per level
  * (App. B "l_max"), each in [0, 4]; tol: stop when the finest residual norm
  * sqrt(h^2 sum_c sum_ij r_c^2) <= tol; max_cycles: V-cycle limit;
- * coarsest: smaller side of the coarsest grid, must be 2 (the coarsest grid,
- * 2x2 or 2x4 cells, so m/n or n/m is at most 2, is solved directly by
- * Newton's method); energy: 1 to compute the energies of Sec. 3 after each
+ * coarsest: smaller side of the coarsest grid, must be 2.  Levels are
+ * coarsened while the smaller side exceeds it and both sides of the next
+ * level stay even.  Power-of-two grids end at 2x2 or 2x4 cells (so m/n or n/m
+ * is at most 2), solved directly by Newton's method.  Other grids (sides
+ * multiples of 4; FP64, nu1, nu2 <= 2, no learned guess) end at a larger
+ * level (512 x 400: 64 x 50, at most 4096 cells), relaxed by coarse_sweeps
+ * red-black sweeps per V-cycle (in [1, 64], default 4); its Poisson problem
+ * is solved exactly in the separable eigenbasis.  energy: 1 to compute the energies of Sec. 3 after each
  * step; diverge: factor of residual growth over the initial residual
  * reported as MPFC_EDIVERGED.
  * precision = MPFC_MIXED: FP64 outer defect correction (FP64 finest residual,
@@ -89,6 +95,7 @@ typedef struct {
     int energy;
     double diverge;
     int inner_cycles;
+    int coarse_sweeps;
 } mpfc_opts;
 
 /* Per-step report.  residual_history is a caller-owned host array of

@@ -422,6 +422,8 @@ int mpfc_batch_create(mpfc_batch** out, int nsim, const mpfc_sim_desc* sims, con
     if (o->guess == MPFC_GUESS_CNN)
         return fail(MPFC_EINVAL, "the learned guess is not available in a batch");
     for (int s = 0; s < nsim; ++s) {
+        if (!is_pow2(sims[s].m) || !is_pow2(sims[s].n))
+            return fail(MPFC_EINVAL, "every simulation of a batch needs power-of-two sides");
         int rc = validate(sims[s].m, sims[s].n, &sims[s].p, o);
         if (rc) {
             char buf[64];

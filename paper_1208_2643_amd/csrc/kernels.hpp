@@ -85,28 +85,50 @@ struct LevelOp {
 constexpr int BC_NEUMANN_X = 1, BC_NEUMANN_Y = 2;
 
 struct Grid {
-    int m, n;       // powers of two
-    int lm, ln;     // log2 m, log2 n
+    int m, n;       // cells along x and y
+    int lm, ln;     // log2 m, log2 n; -1 for a side that is not a power of two
     int bc;         // BC_NEUMANN_X | BC_NEUMANN_Y bits
 };
 
 // Cell holding the value of (ghost or interior) cell i along an axis of m
 // cells.  Periodic: wrap-around.  Neumann: the even reflection about the
 // boundary edges (period 2m), so the first ghost repeats the boundary cell
-// and deeper ghosts (tile halos) mirror the interior.
+// and deeper ghosts (tile halos) mirror the interior.  axis_index needs m a
+// power of two; axis_index_any takes any m.
 __device__ __forceinline__ int axis_index(int i, int m, bool neumann) {
     if (!neumann) return i & (m - 1);
     const int r = i & (2 * m - 1);
     return r < m ? r : 2 * m - 1 - r;
 }
+__device__ __forceinline__ int axis_index_any(int i, int m, bool neumann) {
+    if (!neumann) {
+        const int r = i % m;
+        return r < 0 ? r + m : r;
+    }
+    int r = i % (2 * m);
+    if (r < 0) r += 2 * m;
+    return r < m ? r : 2 * m - 1 - r;
+}
 __device__ __forceinline__ int wrapx(int i, const Grid& g) {
-    return axis_index(i, g.m, g.bc & BC_NEUMANN_X);
+    return g.lm >= 0 ? axis_index(i, g.m, g.bc & BC_NEUMANN_X)
+                     : axis_index_any(i, g.m, g.bc & BC_NEUMANN_X);
 }
 __device__ __forceinline__ int wrapy(int j, const Grid& g) {
-    return axis_index(j, g.n, g.bc & BC_NEUMANN_Y);
+    return g.ln >= 0 ? axis_index(j, g.n, g.bc & BC_NEUMANN_Y)
+                     : axis_index_any(j, g.n, g.bc & BC_NEUMANN_Y);
 }
 __device__ __forceinline__ size_t at(int i, int j, const Grid& g) {
-    return ((size_t)j << g.lm) + (size_t)i;
+    return g.lm >= 0 ? ((size_t)j << g.lm) + (size_t)i : (size_t)j * (size_t)g.m + (size_t)i;
+}
+// (i, j) of the cell at linear index q.
+__device__ __forceinline__ void cell_of(size_t q, const Grid& g, int& i, int& j) {
+    if (g.lm >= 0) {
+        i = (int)(q & (size_t)(g.m - 1));
+        j = (int)(q >> g.lm);
+    } else {
+        j = (int)(q / (size_t)g.m);
+        i = (int)(q - (size_t)j * (size_t)g.m);
+    }
 }
 
 // Sum of the four neighbours of (i, j).
@@ -254,8 +276,8 @@ __global__ void __launch_bounds__(NT) k_resnorm(Fields<double> F, LevelOp<double
     double acc = 0.0;
     const size_t total = (size_t)g.m * g.n;
     for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
-        const int i = (int)(q & (size_t)(g.m - 1));
-        const int j = (int)(q >> g.lm);
+        int i, j;
+        cell_of(q, g, i, j);
         double a, b, c;
         residual_at<double, SCHEME, false>(F, op, g, i, j, a, b, c);
         acc += a * a + b * b + c * c;
@@ -320,9 +342,11 @@ __global__ void __launch_bounds__(NT) k_defect(Fields<double> F, LevelOp<double>
     __shared__ double red[NT / 64];
     double acc = 0.0;
     const size_t total = (size_t)g.m * g.n;
-    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT)
-        acc += defect_cell<SCHEME>(F, op, g, e0, e1, e2, add, un0, un1, un2, r0, r1, r2, pbase,
-                                   (int)(q & (size_t)(g.m - 1)), (int)(q >> g.lm));
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
+        int i, j;
+        cell_of(q, g, i, j);
+        acc += defect_cell<SCHEME>(F, op, g, e0, e1, e2, add, un0, un1, un2, r0, r1, r2, pbase, i, j);
+    }
     const double bs = block_sum<NT>(acc, red);
     if (threadIdx.x == 0) part[blockIdx.x] = bs;
 }

@@ -56,7 +56,18 @@ int round_even(int v) { return (v + 1) & ~1; }
 
 static_assert(BC_NEUMANN_X == MPFC_BC_NEUMANN_X && BC_NEUMANN_Y == MPFC_BC_NEUMANN_Y,
               "boundary-condition bits of the kernels and the C interface agree");
-Grid make_grid(int m, int n, int bc) { return Grid{m, n, ilog2(m), ilog2(n), bc}; }
+Grid make_grid(int m, int n, int bc) {
+    return Grid{m, n, is_pow2(m) ? ilog2(m) : -1, is_pow2(n) ? ilog2(n) : -1, bc};
+}
+bool general_grid(const Grid& g) { return g.lm < 0 || g.ln < 0; }
+
+// Levels of the hierarchy: coarsen while the smaller side exceeds `coarsest`
+// and both sides of the next level stay even (a periodic red-black colouring
+// needs an even number of cells per axis).  Powers of two end at the 2 x 2
+// (or 2 x 4) grid; 512 x 400 ends at 64 x 50.
+bool coarsen_more(int mm, int nn, int coarsest) {
+    return (mm < nn ? mm : nn) > coarsest && mm % 4 == 0 && nn % 4 == 0;
+}
 
 constexpr int NT = 256;
 const dim3 B2(64, 4);
@@ -103,6 +114,7 @@ void cnn_free(CnnNet* net);
 
 struct mpfc_ctx {
     int m = 0, n = 0;
+    bool gen = false;           // a side is not a power of two (general-index kernels)
     mpfc_params p{};
     mpfc_opts o{};
     hipStream_t stream = nullptr;
@@ -208,12 +220,41 @@ void launch_tile_bc(const Op& op, const TileArgs<typename Op::real>& A, int shap
     }
 }
 
+// Grids with a side that is not a power of two: the general-index
+// instantiation, shapes 0 and 2 only (FP64; halos up to 6).
+constexpr bool gen_shape(int k) { return k == 0 || k == 2; }
+template <class Op, bool UP, bool NEU>
+void launch_tile_gen(const Op& op, const TileArgs<typename Op::real>& A, int shape,
+                     const CycleState* stop, hipStream_t s) {
+    const dim3 grid(A.g.m / A.tx, A.g.n / A.ty), blk(256);
+    if (shape == 2)
+        hipLaunchKernelGGL((k_tile<Op, 32, 16, 6, UP, NEU, true>), grid, blk, 0, s, op, A, stop);
+    else
+        hipLaunchKernelGGL((k_tile<Op, 64, 32, 6, UP, NEU, true>), grid, blk, 0, s, op, A, stop);
+}
+
 // Periodic grids run the instantiation without the Neumann ghost handling.
 template <class Op, bool UP>
 void launch_tile(const Op& op, const TileArgs<typename Op::real>& A, int shape,
                  const CycleState* stop, hipStream_t s) {
+    if constexpr (std::is_same<typename Op::real, double>::value) {
+        if (general_grid(A.g)) {
+            if (A.g.bc) launch_tile_gen<Op, UP, true>(op, A, shape, stop, s);
+            else launch_tile_gen<Op, UP, false>(op, A, shape, stop, s);
+            return;
+        }
+    }
     if (A.g.bc) launch_tile_bc<Op, UP, true>(op, A, shape, stop, s);
     else launch_tile_bc<Op, UP, false>(op, A, shape, stop, s);
+}
+
+// Coarsest level of a general grid (MPFC system: red-black sweeps).
+template <class Op>
+void launch_coarsest_gen(const Op& op, const CoarseArgs<typename Op::real>& A,
+                         const CycleState* stop, hipStream_t s) {
+    const dim3 g1(1), blk(CG_THREADS);
+    if (A.geo.bc) hipLaunchKernelGGL((k_coarsest_sweeps<Op, true>), g1, blk, 0, s, op, A, stop);
+    else hipLaunchKernelGGL((k_coarsest_sweeps<Op, false>), g1, blk, 0, s, op, A, stop);
 }
 
 // The persistent coarse-level kernel for the coarsest grid's cell count (4:
@@ -251,7 +292,21 @@ int level_shape(const Level& lv, int kind, int H) {
     return (k >= 0 && H <= kShapes[k].hmax) ? k : pick_shape(H);
 }
 
+// Largest even divisor of `side` that is at most `cap` (side even).
+int even_divisor(int side, int cap) {
+    for (int d = cap < side ? cap : side; d >= 2; --d)
+        if (d % 2 == 0 && side % d == 0) return d;
+    return 2;
+}
+
+// Tile interior of a launch: the shape's sides, clamped to the level; on a
+// general grid the largest even divisors of the level's sides within them.
 void tile_dims(const Level& lv, int shape, int& tx, int& ty) {
+    if (general_grid(lv.g)) {
+        tx = even_divisor(lv.m, kShapes[shape].tx);
+        ty = even_divisor(lv.n, kShapes[shape].ty);
+        return;
+    }
     tx = lv.m < kShapes[shape].tx ? lv.m : kShapes[shape].tx;
     ty = lv.n < kShapes[shape].ty ? lv.n : kShapes[shape].ty;
 }
@@ -452,9 +507,14 @@ void vcycle_mpfc_t(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) {
         if (l == 0 && C->prof) prof_mark(C, 1, s);
     }
     if (Lp < nl && only < 0) {
-        const CoarseArgs<double> A = coarse_args64(C);
+        CoarseArgs<double> A = coarse_args64(C);
         const Op op = make_op<Op>(C, C->L[Lp]);
-        launch_coarse<Op>(op, A, coarsest_is_4(C), stop, s);
+        if (C->gen) {
+            A.nsw2 = 2 * C->o.coarse_sweeps;
+            launch_coarsest_gen<Op>(op, A, stop, s);
+        } else {
+            launch_coarse<Op>(op, A, coarsest_is_4(C), stop, s);
+        }
     }
     for (int l = Lp - 1; l >= 0; --l) {
         if (only >= 0 && (l != only || !only_up)) continue;
@@ -621,7 +681,11 @@ void vcycle_poisson(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) 
         A.nsw2 = 4;
         A.complete_top = Lp > 0;
         A.G = C->G;
-        launch_coarse<Op>(make_op<Op>(C, top), A, true, stop, s);
+        if (C->gen)
+            hipLaunchKernelGGL((k_coarsest_poisson<double>), dim3(1), dim3(CG_THREADS), 0, s,
+                               make_op<Op>(C, top), A, stop);
+        else
+            launch_coarse<Op>(make_op<Op>(C, top), A, true, stop, s);
     }
     for (int l = Lp - 1; l >= 0; --l) {
         if (only >= 0 && (l != only || !only_up)) continue;
@@ -757,7 +821,7 @@ int tune_one(mpfc_ctx* C, Level& lv, int kind, int H, Fn&& launch) {
     float best = 1e30f;
     for (int k = 0; k < kNumShapes; ++k) {
         t[k] = 1e30f;
-        if (H > kShapes[k].hmax) continue;
+        if (H > kShapes[k].hmax || (C->gen && !gen_shape(k))) continue;
         lv.shape[kind] = k;
         int rc = time_in_graph(C->cap_stream, C->stream, kTuneReps, launch, t[k]);
         if (rc) return rc;
@@ -772,6 +836,9 @@ int autotune(mpfc_ctx* C) {
     if (forced && forced[0]) {
         const int k = std::atoi(forced);
         if (k < 0 || k >= kNumShapes) return fail(MPFC_EINVAL, "MPFC_TILE_SHAPE out of range");
+        if (C->gen && !gen_shape(k))
+            return fail(MPFC_EINVAL, "MPFC_TILE_SHAPE: grids with a side that is not a power of two "
+                                     "take shape 0 or 2");
         for (auto& lv : C->L)
             for (int kind = 0; kind < SH_KINDS; ++kind) lv.shape[kind] = k;
         return MPFC_OK;
@@ -853,6 +920,50 @@ void green_matrix(int m, int n, double h, int bc, std::vector<double>& G) {
         }
 }
 
+// Separable eigenbasis of -Lap_h on an m x n grid (general grids' coarsest
+// Poisson solve): G = [V_x (m x m) | V_y (n x n) | 1/lam (n x m)], V[i][k] =
+// value of orthonormal mode k at cell i.  Periodic axis of N cells: mode 0 =
+// 1/sqrt(N), modes 2j-1, 2j = sqrt(2/N) cos, sin(2 pi j i / N) (j < N/2),
+// mode N-1 = (-1)^i / sqrt(N) (N even), each with lambda = (4/h^2)
+// sin^2(pi j / N); Neumann: sqrt(w_k) cos(pi k (i + 1/2) / N), lambda =
+// (4/h^2) sin^2(pi k / (2N)).  1/lam of the (0, 0) mode is 0.
+void spectral_factors(int m, int n, double h, int bc, std::vector<double>& G) {
+    const double pi = 3.14159265358979323846;
+    G.assign((size_t)m * m + (size_t)n * n + (size_t)m * n, 0.0);
+    auto basis = [&](int N, bool neumann, double* V, std::vector<double>& lam) {
+        lam.assign(N, 0.0);
+        for (int k = 0; k < N; ++k) {
+            int j;             // frequency of mode k
+            if (neumann) j = k;
+            else j = k == 0 ? 0 : (k == N - 1 ? N / 2 : (k + 1) / 2);
+            const double sn = neumann ? std::sin(pi * j / (2.0 * N)) : std::sin(pi * j / N);
+            lam[k] = 4.0 / (h * h) * sn * sn;
+            for (int i = 0; i < N; ++i) {
+                double v;
+                if (neumann) {
+                    v = (k == 0 ? std::sqrt(1.0 / N) : std::sqrt(2.0 / N)) *
+                        std::cos(pi * k * (i + 0.5) / N);
+                } else if (k == 0) {
+                    v = std::sqrt(1.0 / N);
+                } else if (k == N - 1) {
+                    v = ((i & 1) ? -1.0 : 1.0) / std::sqrt((double)N);
+                } else {
+                    const double a = 2.0 * pi * j * i / N;
+                    v = std::sqrt(2.0 / N) * ((k & 1) ? std::cos(a) : std::sin(a));
+                }
+                V[(size_t)i * N + k] = v;
+            }
+        }
+    };
+    std::vector<double> lx, ly;
+    basis(m, bc & BC_NEUMANN_X, G.data(), lx);
+    basis(n, bc & BC_NEUMANN_Y, G.data() + (size_t)m * m, ly);
+    double* il = G.data() + (size_t)m * m + (size_t)n * n;
+    for (int l = 0; l < n; ++l)
+        for (int k = 0; k < m; ++k)
+            il[(size_t)l * m + k] = (l == 0 && k == 0) ? 0.0 : 1.0 / (lx[k] + ly[l]);
+}
+
 int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
     if (!p) return fail(MPFC_EINVAL, "params is NULL");
     if (!o) return fail(MPFC_EINVAL, "opts is NULL");
@@ -864,8 +975,10 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
     if (!(p->eps <= 1.0) || !std::isfinite(p->eps)) return fail(MPFC_EINVAL, "eps must be <= 1");
     if (p->bc < 0 || p->bc > (MPFC_BC_NEUMANN_X | MPFC_BC_NEUMANN_Y))
         return fail(MPFC_EINVAL, "bc must combine MPFC_BC_NEUMANN_X and MPFC_BC_NEUMANN_Y bits");
-    if (!is_pow2(m) || !is_pow2(n) || m < 2 || n < 2)
-        return fail(MPFC_EINVAL, "m and n must be powers of two >= 2");
+    const bool gen = !(is_pow2(m) && is_pow2(n));
+    if (m < 2 || n < 2) return fail(MPFC_EINVAL, "m and n must be >= 2");
+    if (gen && (m % 4 != 0 || n % 4 != 0))
+        return fail(MPFC_EINVAL, "m and n must be powers of two or multiples of 4");
     if ((long long)m * n > (1LL << 28)) return fail(MPFC_EINVAL, "grid too large (m*n > 2^28)");
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 || o->nu1 > 4 || o->nu2 > 4)
         return fail(MPFC_EINVAL, "nu1, nu2 must be in [0, 4] with nu1 + nu2 >= 1");
@@ -885,6 +998,23 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
     if (!(o->diverge > 1.0)) return fail(MPFC_EINVAL, "diverge must be > 1");
     if (o->inner_cycles < 1 || o->inner_cycles > 16)
         return fail(MPFC_EINVAL, "inner_cycles must be in [1, 16]");
+    if (o->coarse_sweeps < 1 || o->coarse_sweeps > 64)
+        return fail(MPFC_EINVAL, "coarse_sweeps must be in [1, 64]");
+    if (gen) {
+        // general-index kernels: FP64, halos up to 6, coarsest level in one workgroup
+        if (o->precision != MPFC_FP64)
+            return fail(MPFC_EINVAL, "grids with a side that is not a power of two run in MPFC_FP64");
+        if (o->guess == MPFC_GUESS_CNN)
+            return fail(MPFC_EINVAL, "the learned guess needs power-of-two grids");
+        if (o->nu1 > 2 || o->nu2 > 2)
+            return fail(MPFC_EINVAL, "nu1, nu2 must be at most 2 when a side is not a power of two");
+        int gm = m, gn = n;
+        while (coarsen_more(gm, gn, o->coarsest)) { gm /= 2; gn /= 2; }
+        if (gm * gn > CG_CELLS)
+            return fail(MPFC_EINVAL, "the coarsest level (coarsened while both sides stay even) "
+                                     "exceeds 4096 cells");
+        return MPFC_OK;
+    }
     // coarsest grid: coarsen while the smaller side exceeds `coarsest`
     int mm = m, nn = n;
     while ((mm < nn ? mm : nn) > o->coarsest) { mm /= 2; nn /= 2; }
@@ -1102,6 +1232,7 @@ void mpfc_default_opts(mpfc_opts* o) {
     o->energy = 1;
     o->diverge = 1e8;
     o->inner_cycles = 3;
+    o->coarse_sweeps = 4;
 }
 
 int mpfc_validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
@@ -1181,17 +1312,19 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
     const char* ng = std::getenv("MPFC_NO_GRAPH");
     C->use_graph = !(ng && ng[0] == '1');
     C->inner_cycles = o->inner_cycles;
+    C->gen = !(is_pow2(m) && is_pow2(n));
     const bool mixed = o->precision == MPFC_MIXED;
-    // level hierarchy
+    // level hierarchy; a general grid tiles every level but its coarsest
     {
         int mm = m, nn = n;
         double h = p->h;
         for (;;) {
             Level lv;
             lv.m = mm; lv.n = nn; lv.h = h; lv.g = make_grid(mm, nn, p->bc);
-            lv.tiled = (long long)mm * nn > CP_CELLS;
+            const bool last = !coarsen_more(mm, nn, o->coarsest);
+            lv.tiled = C->gen ? !last : (long long)mm * nn > CP_CELLS;
             C->L.push_back(lv);
-            if ((mm < nn ? mm : nn) <= o->coarsest) break;
+            if (last) break;
             mm /= 2; nn /= 2; h *= 2.0;
         }
     }
@@ -1202,7 +1335,10 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
     // Arena layout in doubles, every piece 256-byte aligned: the same function
     // sizes the arena (base == nullptr) and then assigns the pointers.
     const Level& Lc = C->L[nl - 1];
-    const size_t nG = (size_t)(Lc.m * Lc.n) * (Lc.m * Lc.n);
+    // coarsest Poisson solve: dense Green's matrix, or (general grid) the
+    // separable eigenbasis V_x, V_y and the inverse eigenvalues
+    const size_t nG = C->gen ? (size_t)Lc.m * Lc.m + (size_t)Lc.n * Lc.n + (size_t)Lc.m * Lc.n
+                             : (size_t)(Lc.m * Lc.n) * (Lc.m * Lc.n);
     auto layout = [&](double* base) {
         size_t off = 0;
         auto take = [&](size_t cnt) {
@@ -1249,7 +1385,9 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
         C->hist = take(o->max_cycles + 1 + 8);
         C->phist = take(64);
         C->acc = take(64);
-        C->nparts = (int)((size_t)m * n / 256 > 4096 ? (size_t)m * n / 256 : 4096);
+        // one partial sum per finest tile (general grids: tiles down to 2 x 2)
+        const size_t cells_per_part = C->gen ? 4 : 256;
+        C->nparts = (int)((size_t)m * n / cells_per_part > 4096 ? (size_t)m * n / cells_per_part : 4096);
         C->part = take((size_t)C->nparts);
         C->st = (CycleState*)take(16);
         C->pst = (CycleState*)take(16);
@@ -1265,7 +1403,8 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
     }
     layout((double*)C->arena);
     std::vector<double> G;
-    green_matrix(Lc.m, Lc.n, Lc.h, p->bc, G);
+    if (C->gen) spectral_factors(Lc.m, Lc.n, Lc.h, p->bc, G);
+    else green_matrix(Lc.m, Lc.n, Lc.h, p->bc, G);
     e = hipHostMalloc((void**)&C->host_st, sizeof(CycleState) * 2, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&C->host_buf, sizeof(double) * (size_t)(o->max_cycles + 128),
@@ -1459,7 +1598,7 @@ int mpfc_energies(mpfc_ctx* C, const double* phi, const double* phi_prev, const 
 int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double c, double alpha,
                    const double* phik, double* phi, double* mu, double* ka, const double* f1,
                    const double* f2, const double* f3, int sweeps, int bc, void* stream) {
-    if (!(scheme == 1 || scheme == 2) || !is_pow2(m) || !is_pow2(n) || m < 2 || n < 2 ||
+    if (!(scheme == 1 || scheme == 2) || m < 2 || n < 2 || (m & 1) || (n & 1) ||
         sweeps < 0 || !(h > 0) || !phi || !mu || !ka || !f1 || !f2 || !f3 ||
         (scheme == 2 && !phik) || bc < 0 || bc > 3)
         return fail(MPFC_EINVAL, "mpfc_op_smooth: bad arguments");
@@ -1522,7 +1661,7 @@ int mpfc_op_residual(int scheme, int m, int n, double h, double c, double alpha,
                      const double* phik, const double* phi, const double* mu, const double* ka,
                      const double* f1, const double* f2, const double* f3, double* r1, double* r2,
                      double* r3, int bc, void* stream) {
-    if (!(scheme == 1 || scheme == 2) || !is_pow2(m) || !is_pow2(n) || m < 2 || n < 2 ||
+    if (!(scheme == 1 || scheme == 2) || m < 2 || n < 2 || (m & 1) || (n & 1) ||
         !(h > 0) || !phi || !mu || !ka || !f1 || !f2 || !f3 || !r1 || !r2 || !r3 ||
         (scheme == 2 && !phik) || bc < 0 || bc > 3)
         return fail(MPFC_EINVAL, "mpfc_op_residual: bad arguments");
@@ -1547,8 +1686,8 @@ int mpfc_op_residual(int scheme, int m, int n, double h, double c, double alpha,
 
 int mpfc_op_source(const mpfc_params* p, int m, int n, const double* phik, const double* phikm1,
                    const double* psik, double* S1, double* S2, double* S3, void* stream) {
-    if (!p || !(p->scheme == 1 || p->scheme == 2) || !is_pow2(m) || !is_pow2(n) || m < 2 ||
-        n < 2 || !(p->h > 0) || !(p->dt > 0) || !phik || !psik || !S1 || !S2 || !S3 ||
+    if (!p || !(p->scheme == 1 || p->scheme == 2) || m < 2 || n < 2 || (m & 1) || (n & 1) ||
+        !(p->h > 0) || !(p->dt > 0) || !phik || !psik || !S1 || !S2 || !S3 ||
         p->bc < 0 || p->bc > 3)
         return fail(MPFC_EINVAL, "mpfc_op_source: bad arguments");
     if (!phikm1) phikm1 = phik;
@@ -1569,7 +1708,7 @@ int mpfc_op_source(const mpfc_params* p, int m, int n, const double* phik, const
 }
 
 int mpfc_op_restrict(int m, int n, const double* fine, double* coarse, void* stream) {
-    if (!is_pow2(m) || !is_pow2(n) || m < 2 || n < 2 || !fine || !coarse)
+    if (m < 2 || n < 2 || (m & 1) || (n & 1) || !fine || !coarse)
         return fail(MPFC_EINVAL, "mpfc_op_restrict: bad arguments");
     hipLaunchKernelGGL((k_restrict<double, double>), grid2(m / 2, n / 2), B2, 0,
                        (hipStream_t)stream, make_grid(m, n, 0), fine, coarse);

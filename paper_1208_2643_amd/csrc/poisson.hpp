@@ -95,8 +95,8 @@ __global__ void __launch_bounds__(NT) k_p_resnorm(const double* __restrict__ w,
     double acc = 0.0;
     const size_t total = (size_t)g.m * g.n;
     for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
-        const int i = (int)(q & (size_t)(g.m - 1));
-        const int j = (int)(q >> g.lm);
+        int i, j;
+        cell_of(q, g, i, j);
         const double r = b[q] + (nsum(w, i, j, g) - 4.0 * w[q]) * ih2;
         acc += r * r;
     }
@@ -146,8 +146,8 @@ __global__ void __launch_bounds__(NT) k_p_rhs_resid(Grid g, double ih2,
         b[q] = v;
         sb += v * v;
         if (w) {
-            const int i = (int)(q & (size_t)(g.m - 1));
-            const int j = (int)(q >> g.lm);
+            int i, j;
+            cell_of(q, g, i, j);
             const double r = v - (4.0 * w[q] - nsum(w, i, j, g)) * ih2;
             sr += r * r;
         }
@@ -181,8 +181,8 @@ __global__ void __launch_bounds__(NT) k_energy_terms(Grid g, double ih2,
     double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const size_t total = (size_t)g.m * g.n;
     for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
-        const int i = (int)(q & (size_t)(g.m - 1));
-        const int j = (int)(q >> g.lm);
+        int i, j;
+        cell_of(q, g, i, j);
         const double x = phi[q];
         const double xe = phi[at(wrapx(i + 1, g), j, g)], xn = phi[at(i, wrapy(j + 1, g), g)];
         const double L = (nsum(phi, i, j, g) - 4.0 * x) * ih2;

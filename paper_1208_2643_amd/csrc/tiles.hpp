@@ -130,10 +130,17 @@ __device__ __forceinline__ T bilinear(const T* __restrict__ uH, const T* __restr
 // Cell index along one axis inside the tile and coarse kernels: plain
 // wrap-around in the periodic instantiation (NEU = false), the per-axis ghost
 // rule (axis_index) in the instantiation for grids with a Neumann axis.
-template <bool NEU>
+// GEN: instantiation for grids whose sides need not be powers of two.
+template <bool NEU, bool GEN = false>
 __device__ __forceinline__ int bidx(int i, int m, int neumann_axis) {
-    if constexpr (NEU) return axis_index(i, m, neumann_axis);
+    if constexpr (GEN) return axis_index_any(i, m, NEU && neumann_axis);
+    else if constexpr (NEU) return axis_index(i, m, neumann_axis);
     else return i & (m - 1);
+}
+template <bool GEN>
+__device__ __forceinline__ size_t tat(int i, int j, const Grid& g) {
+    if constexpr (GEN) return (size_t)j * (size_t)g.m + (size_t)i;
+    else return ((size_t)j << g.lm) + (size_t)i;
 }
 
 // XCD-aware order of nt work items: workgroups are dealt round-robin to the 8
@@ -146,7 +153,7 @@ __device__ __forceinline__ int xcd_item(int b, int nt) {
 
 // Body of one tile launch (one workgroup, 256 threads) on tile (tbx, tby).
 // `pslot` is where the workgroup's residual sum goes in A.part.
-template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU>
+template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU, bool GEN = false>
 __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename Op::real>& A,
                                           const CycleState* stop, int tbx, int tby, int pslot) {
     using T = typename Op::real;
@@ -170,7 +177,8 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
     // 1. u (tile + halo) into LDS, coalesced along rows.
     for (int q = t; q < LX * LY; q += NT) {
         const int y = q / LX, x = q - y * LX;
-        const size_t gq = at(bidx<NEU>(x0 + x, g.m, g.bc & BC_NEUMANN_X), bidx<NEU>(y0 + y, g.n, g.bc & BC_NEUMANN_Y), g);
+        const size_t gq = tat<GEN>(bidx<NEU, GEN>(x0 + x, g.m, g.bc & BC_NEUMANN_X),
+                                   bidx<NEU, GEN>(y0 + y, g.n, g.bc & BC_NEUMANN_Y), g);
 #pragma unroll
         for (int f = 0; f < NF; ++f) U[f][(x + y) & 1][y][x >> 1] = A.zero_in ? T(0) : A.uin[f][gq];
     }
@@ -200,7 +208,8 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
             const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
             const int x = 2 * bx + dx, y = 2 * by + dy;
             if (x < 1 || y < 1 || x >= LX - 1 || y >= LY - 1) continue;  // never updated
-            const size_t gq = at(bidx<NEU>(x0 + x, g.m, g.bc & BC_NEUMANN_X), bidx<NEU>(y0 + y, g.n, g.bc & BC_NEUMANN_Y), g);
+            const size_t gq = tat<GEN>(bidx<NEU, GEN>(x0 + x, g.m, g.bc & BC_NEUMANN_X),
+                                       bidx<NEU, GEN>(y0 + y, g.n, g.bc & BC_NEUMANN_Y), g);
             if constexpr (Op::XK) xkr[s][c] = A.xk[gq];
             if constexpr (Op::PB) pbr[s][c] = A.pb[gq];
             if constexpr (Op::PW) wr[s][c] = A.pin[gq];
@@ -218,8 +227,8 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
         const int cx0 = (x0 >> 1) - 1, cy0 = (y0 >> 1) - 1;
         for (int q = t; q < CX * CY; q += NT) {
             const int cy = q / CX, cx = q - cy * CX;
-            const size_t gq = (size_t)bidx<NEU>(cy0 + cy, nc, g.bc & BC_NEUMANN_Y) * mc +
-                              bidx<NEU>(cx0 + cx, mc, g.bc & BC_NEUMANN_X);
+            const size_t gq = (size_t)bidx<NEU, GEN>(cy0 + cy, nc, g.bc & BC_NEUMANN_Y) * mc +
+                              bidx<NEU, GEN>(cx0 + cx, mc, g.bc & BC_NEUMANN_X);
 #pragma unroll
             for (int f = 0; f < NF; ++f) E[f][cy][cx] = A.cuH[f][gq] - A.cvH[f][gq];
         }
@@ -323,7 +332,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
                 const int x = k < H ? k : LX - 2 * H + k;
                 const int gx = x0 + x;
                 if (gx >= 0 && gx < g.m) continue;
-                const int xm = axis_index(gx, g.m, true) - x0;
+                const int xm = (GEN ? axis_index_any(gx, g.m, true) : axis_index(gx, g.m, true)) - x0;
 #pragma unroll
                 for (int f = 0; f < NF; ++f)
                     U[f][(x + y) & 1][y][x >> 1] = U[f][(xm + y) & 1][y][xm >> 1];
@@ -336,7 +345,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
                 const int y = k < H ? k : LY - 2 * H + k;
                 const int gy = y0 + y;
                 if (gy >= 0 && gy < g.n) continue;
-                const int ym = axis_index(gy, g.n, true) - y0;
+                const int ym = (GEN ? axis_index_any(gy, g.n, true) : axis_index(gy, g.n, true)) - y0;
 #pragma unroll
                 for (int f = 0; f < NF; ++f)
                     U[f][(x + y) & 1][y][x >> 1] = U[f][(x + ym) & 1][ym][x >> 1];
@@ -356,7 +365,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
     for (int q = t; q < tx * ty; q += NT) {
         const int yi = q / tx, xi = q - yi * tx;
         const int x = xi + H, y = yi + H;
-        const size_t gq = at(gx0 + xi, gy0 + yi, g);
+        const size_t gq = tat<GEN>(gx0 + xi, gy0 + yi, g);
 #pragma unroll
         for (int f = 0; f < NF; ++f) A.uout[f][gq] = U[f][(x + y) & 1][y][x >> 1];
     }
@@ -426,7 +435,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
-                    const size_t gq = at(gx0 + 2 * bx - H + dx, gy0 + 2 * by - H + dy, g);
+                    const size_t gq = tat<GEN>(gx0 + 2 * bx - H + dx, gy0 + 2 * by - H + dy, g);
 #pragma unroll
                     for (int f = 0; f < NF; ++f) A.fout[f][gq] = fr[s][c][f];
                 }
@@ -441,14 +450,15 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
     }
 }
 
-// One level of one grid.  Grid: (m / tx, n / ty) workgroups of 256 threads.
-template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU>
+// One level of one grid.  Grid: (m / tx, n / ty) workgroups of 256 threads
+// (tx, ty divide m, n).
+template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU, bool GEN = false>
 __global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real> A,
                                               const CycleState* stop) {
     const int nt = gridDim.x * gridDim.y;
     const int tl = xcd_item(blockIdx.y * gridDim.x + blockIdx.x, nt);
     const int tby = tl / gridDim.x, tbx = tl - tby * gridDim.x;
-    tile_body<Op, TX, TY, HMAX, UP, NEU>(op, A, stop, tbx, tby, tl);
+    tile_body<Op, TX, TY, HMAX, UP, NEU, GEN>(op, A, stop, tbx, tby, tl);
 }
 
 // Batched launch: one level of many independent grids.  Each (grid, level)
@@ -879,6 +889,194 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
     for (int q = t; q < N0; q += NTP) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) A.u[f][q] = Su[f][q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest level of a grid whose sides are not all powers of two.  Such a grid
+// is coarsened while both sides of the next level stay even, so its coarsest
+// level (m x n, both even, at most CG_CELLS cells; 64 x 50 for 512 x 400) can
+// be far larger than the 2 x 2 grid the dense Newton solve is made for.  One
+// workgroup of CG_THREADS threads; every index is general (no power-of-two
+// masks), and each axis follows its ghost rule.
+constexpr int CG_THREADS = 1024;
+constexpr int CG_CELLS = 4096;
+constexpr int CG_SLOTS = CG_CELLS / 2 / CG_THREADS;  // cells of one colour per thread
+
+// MPFC system: complete the FAS right-hand side f = R r + N(u), then relax the
+// level by A.nsw2 half-sweeps of the red-black collective smoother (the
+// coarsest "solve" is approximate; the finer levels correct what it leaves).
+// u lives in LDS; f and the coefficients of each thread's cells in registers.
+template <class Op, bool NEU>
+__global__ void __launch_bounds__(CG_THREADS) k_coarsest_sweeps(Op op,
+                                                                CoarseArgs<typename Op::real> A,
+                                                                const CycleState* stop) {
+    using T = typename Op::real;
+    constexpr int NF = Op::NF;
+    __shared__ T Su[NF][CG_CELLS];
+    if (stopped(stop)) return;
+    const int t = threadIdx.x;
+    const int m = A.geo.m[0], n = A.geo.n[0], N = m * n, mh = m >> 1;
+    const bool nbx = NEU && (A.geo.bc & BC_NEUMANN_X), nby = NEU && (A.geo.bc & BC_NEUMANN_Y);
+    for (int q = t; q < N; q += CG_THREADS) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) Su[f][q] = A.u[f][q];
+    }
+    __syncthreads();
+    auto nsum = [&](const T* a, int i, int j) {
+        const int ie = i + 1 < m ? i + 1 : (nbx ? m - 1 : 0);
+        const int iw = i > 0 ? i - 1 : (nbx ? 0 : m - 1);
+        const int jn = j + 1 < n ? j + 1 : (nby ? n - 1 : 0);
+        const int js = j > 0 ? j - 1 : (nby ? 0 : n - 1);
+        const int r = j * m;
+        return (a[ie + r] + a[iw + r]) + (a[i + jn * m] + a[i + js * m]);
+    };
+    // slot s of colour c of this thread: cell (i, j), or q = -1 for none
+    auto cell = [&](int c, int s, int& i, int& j) {
+        const int q2 = t + s * CG_THREADS;
+        if (q2 >= (N >> 1)) return -1;
+        j = q2 / mh;
+        i = 2 * (q2 - j * mh) + ((j + c) & 1);
+        return j * m + i;
+    };
+    T fr[2][CG_SLOTS][NF], xkr[2][CG_SLOTS], pbr[2][CG_SLOTS], wr[2][CG_SLOTS];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+#pragma unroll
+        for (int s = 0; s < CG_SLOTS; ++s) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) fr[c][s][f] = T(0);
+            xkr[c][s] = T(0);
+            pbr[c][s] = T(0);
+            wr[c][s] = T(0);
+            int i = 0, j = 0;
+            const int q = cell(c, s, i, j);
+            if (q < 0) continue;
+            if constexpr (Op::XK) xkr[c][s] = A.xk[q];
+            if constexpr (Op::PB) pbr[c][s] = A.pb[q];
+            if constexpr (Op::PW) wr[c][s] = A.pin[q];
+            T u[NF], ns[NF], Nu[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                u[f] = Su[f][q];
+                ns[f] = nsum(Su[f], i, j);
+                fr[c][s][f] = A.rr[f][q];
+            }
+            if (A.complete_top) {
+                op.apply(u, ns, xkr[c][s], pbr[c][s], wr[c][s], Nu);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) fr[c][s][f] += Nu[f];
+            }
+        }
+    }
+    __syncthreads();  // every N(u) above read u as loaded
+    auto pass = [&](auto colc) {
+        constexpr int c = decltype(colc)::value;
+#pragma unroll
+        for (int s = 0; s < CG_SLOTS; ++s) {
+            int i = 0, j = 0;
+            const int q = cell(c, s, i, j);
+            if (q < 0) continue;
+            T u[NF], ns[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                u[f] = Su[f][q];
+                ns[f] = nsum(Su[f], i, j);
+            }
+            op.relax(u, ns, fr[c][s], xkr[c][s], pbr[c][s], wr[c][s]);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) Su[f][q] = u[f];
+        }
+    };
+    for (int p = 0; p < A.nsw2; ++p) {
+        if ((p & 1) == 0) pass(std::integral_constant<int, 0>{});
+        else pass(std::integral_constant<int, 1>{});
+        __syncthreads();
+    }
+    for (int q = t; q < N; q += CG_THREADS) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) A.u[f][q] = Su[f][q];
+    }
+}
+
+// Poisson problem -Lap_h w = f on the same coarsest level, solved exactly in
+// the separable eigenbasis of the operator: with V_x (m x m) and V_y (n x n)
+// the orthonormal eigenvectors of the one-dimensional second difference under
+// each axis' boundary rule (columns: modes) and lam the eigenvalue sums,
+//   w = V_y [ (V_y^T F V_x) / lam ] V_x^T + mean(v),
+// the (0, 0) mode dropped (1/lam stored as 0), F the m x n grid function f.
+// A.G holds V_x (row i: cell, column k: mode), then V_y, then 1/lam (row l:
+// y mode, column k: x mode).  v is u as loaded (the restricted iterate): the
+// correction keeps mean zero, as the dense Green's-matrix solve does.
+template <typename T>
+__global__ void __launch_bounds__(CG_THREADS) k_coarsest_poisson(PoissonOp<T> op, CoarseArgs<T> A,
+                                                                 const CycleState* stop) {
+    __shared__ T S0[CG_CELLS];
+    __shared__ T S1[CG_CELLS];
+    __shared__ double red[CG_THREADS / 64];
+    __shared__ double mean_v;
+    if (stopped(stop)) return;
+    const int t = threadIdx.x;
+    const int m = A.geo.m[0], n = A.geo.n[0], N = m * n;
+    const bool nbx = A.geo.bc & BC_NEUMANN_X, nby = A.geo.bc & BC_NEUMANN_Y;
+    const double* Vx = A.G;
+    const double* Vy = Vx + (size_t)m * m;
+    const double* il = Vy + (size_t)n * n;
+    double sv = 0.0;
+    for (int q = t; q < N; q += CG_THREADS) {
+        S0[q] = A.u[0][q];
+        sv += (double)S0[q];
+    }
+    const double tot = block_sum<CG_THREADS>(sv, red);  // contains a barrier
+    if (t == 0) mean_v = tot / (double)N;
+    for (int q = t; q < N; q += CG_THREADS) {
+        const int j = q / m, i = q - j * m;
+        const int ie = i + 1 < m ? i + 1 : (nbx ? m - 1 : 0);
+        const int iw = i > 0 ? i - 1 : (nbx ? 0 : m - 1);
+        const int jn = j + 1 < n ? j + 1 : (nby ? n - 1 : 0);
+        const int js = j > 0 ? j - 1 : (nby ? 0 : n - 1);
+        T f = A.rr[0][q];
+        if (A.complete_top) {
+            const T u[1] = {S0[q]};
+            const T ns[1] = {(S0[ie + j * m] + S0[iw + j * m]) + (S0[i + jn * m] + S0[i + js * m])};
+            T Nu[1];
+            op.apply(u, ns, T(0), T(0), T(0), Nu);
+            f += Nu[0];
+        }
+        S1[q] = f;
+    }
+    __syncthreads();
+    // S0 = F V_x   (row j, column k)
+    for (int q = t; q < N; q += CG_THREADS) {
+        const int j = q / m, k = q - j * m;
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += (double)S1[j * m + i] * Vx[(size_t)i * m + k];
+        S0[q] = (T)s;
+    }
+    __syncthreads();
+    // S1 = (V_y^T S0) / lam   (row l, column k)
+    for (int q = t; q < N; q += CG_THREADS) {
+        const int l = q / m, k = q - l * m;
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += Vy[(size_t)j * n + l] * (double)S0[j * m + k];
+        S1[q] = (T)(s * il[q]);
+    }
+    __syncthreads();
+    // S0 = V_y S1   (row j, column k)
+    for (int q = t; q < N; q += CG_THREADS) {
+        const int j = q / m, k = q - j * m;
+        double s = 0.0;
+        for (int l = 0; l < n; ++l) s += Vy[(size_t)j * n + l] * (double)S1[l * m + k];
+        S0[q] = (T)s;
+    }
+    __syncthreads();
+    // w = S0 V_x^T + mean(v)
+    const double mv = mean_v;
+    for (int q = t; q < N; q += CG_THREADS) {
+        const int j = q / m, i = q - j * m;
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += (double)S0[j * m + k] * Vx[(size_t)i * m + k];
+        A.u[0][q] = (T)(s + mv);
     }
 }
 

@@ -44,7 +44,8 @@ def good():
 
 def test_defaults():
     o = L.default_opts()
-    assert (o.nu1, o.nu2, o.max_cycles, o.tol, o.coarsest) == (2, 2, 100, 1e-10, 2)
+    assert (o.nu1, o.nu2, o.max_cycles, o.tol, o.coarsest, o.coarse_sweeps) == \
+        (2, 2, 100, 1e-10, 2, 4)
     p, o = good()
     assert L.load().mpfc_validate(1024, 1024, ctypes.byref(p), ctypes.byref(o)) == 0
 
@@ -58,10 +59,37 @@ def test_invalid_params_rejected(field, value):
     assert L.load().mpfc_validate(64, 64, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
 
 
-@pytest.mark.parametrize("m,n", [(0, 64), (48, 64), (64, 100), (1, 1), (2, 128), (64, 256)])
+@pytest.mark.parametrize("m,n", [(0, 64), (48, 66), (64, 102), (1, 1), (2, 128), (64, 256),
+                                 (6, 8), (404, 404)])
 def test_invalid_sizes_rejected(m, n):
+    """Sides must be powers of two (aspect ratio at most 2) or multiples of 4
+    whose coarsest level (coarsened while both sides stay even) has at most
+    4096 cells (404 x 404 stops at 202 x 202)."""
     p, o = good()
     assert L.load().mpfc_validate(m, n, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
+
+
+@pytest.mark.parametrize("m,n", [(512, 400), (48, 64), (64, 100), (96, 96), (12, 4), (4000, 8)])
+def test_general_sizes_accepted(m, n):
+    p, o = good()
+    assert L.load().mpfc_validate(m, n, ctypes.byref(p), ctypes.byref(o)) == 0
+
+
+@pytest.mark.parametrize("field,value", [("precision", 1), ("guess", 2), ("nu1", 3), ("nu2", 3)])
+def test_general_sizes_reject_unsupported_options(field, value):
+    """Grids with a side that is not a power of two run the FP64 general-index
+    kernels only: no mixed precision, no learned guess, halos up to nu = 2."""
+    p, o = good()
+    setattr(o, field, value)
+    assert L.load().mpfc_validate(512, 400, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
+    assert L.load().mpfc_validate(512, 512, ctypes.byref(p), ctypes.byref(o)) == 0
+
+
+@pytest.mark.parametrize("value", [0, 65])
+def test_coarse_sweeps_range(value):
+    p, o = good()
+    o.coarse_sweeps = value
+    assert L.load().mpfc_validate(512, 400, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
 
 
 @pytest.mark.parametrize("field,value", [("tol", 0.0), ("max_cycles", 0), ("nu1", -1),
