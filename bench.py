@@ -38,6 +38,9 @@ MODEL_BYTES = {"down": 2 * 80.0 + 70.0, "up": 60.0 + 2 * 80.0 + 56.0}
 # reads u, S, phi^k (56 B) and the coarse u, v (6 quarter fields, 12 B), writes
 # u (24 B).
 COMPULSORY_BYTES = {"down": 56.0 + 24.0 + 20.0, "up": 56.0 + 12.0 + 24.0}
+# The pinning weight W (8 B per cell) adds one read per sweep and per residual
+# pass: down 2 sweeps + residual, up 2 sweeps + norm.
+PIN_BYTES = {"down": 3 * 8.0, "up": 3 * 8.0}
 # HBM bytes per finest-level launch measured with rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by what the counters read for a 128 MiB copy), per tile
 # shape "TXxTY/HALO", valid only for the kernel sources they were measured on
@@ -89,6 +92,8 @@ def parse():
                     help="steps of the variant with periodic-x / Neumann-y boundaries (0 skips it)")
     ap.add_argument("--pin-steps", type=int, default=100,
                     help="steps of the variant with the pinning term (0 skips it)")
+    ap.add_argument("--shear-steps", type=int, default=100,
+                    help="steps of the 512 x 400 sheared-crystal variant of Sec. 4.4 (0 skips it)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
@@ -207,6 +212,74 @@ def bench_learned(api, inputs, torch, dev, params, tol, steps, warmup, N):
     res["final_state_rel_l2_difference"] = float(d)
     res["speedup"] = res["learned"]["time_steps_per_s"] / res["extrapolated"]["time_steps_per_s"]
     return res
+
+
+def bench_sheared(api, inputs, torch, dev, steps, warmup, energy, nu1, nu2):
+    """Sec. 4.4's sheared crystal on its 512 x 400 grid (sides not both powers
+    of two: general-index tile kernels, coarsest level 64 x 50 relaxed by one
+    red-black sweep per cycle, which converges as fast here as 2 or 4): eps 0.6, M = 15^2, h = 4 pi / (16 sqrt 3), s = 0.025 h^2,
+    beta 0.2, scheme 2, FP64, pinning weight 2 in strips of height pi at the
+    bottom and top rows of a 20-row crystal band, phi_hat sheared by 4 % of
+    2 pi at the bottom; FAS V(nu1, nu2) to 1e-10.  Also the live timing of the
+    two finest-level launches."""
+    m, n = 512, 400
+    h = 4 * math.pi / (16 * math.sqrt(3))
+    prm = dict(eps=0.6, beta=0.2, M=225.0, h=h, dt=0.025 * h * h, scheme=2)
+    phi0, W, hat = inputs.strained_crystal(m, n, h)
+    st = api.Stepper(m, n, api.Params(**prm), tol=1e-10, nu1=nu1, nu2=nu2, energy=energy,
+                     coarse_sweeps=1)
+    st.set_pinning(torch.from_numpy(W).to(dev), torch.from_numpy(hat).to(dev))
+    p_ = torch.from_numpy(phi0).to(dev)
+    q_ = p_.clone()
+    s_ = torch.zeros_like(p_)
+    n_ = torch.empty_like(p_)
+    for _ in range(warmup):
+        st.step(p_, q_, s_, n_)
+        q_, p_, n_ = p_, n_, q_
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cyc = 0
+    for _ in range(steps):
+        _, inf = st.step(p_, q_, s_, n_)
+        q_, p_, n_ = p_, n_, q_
+        cyc += inf.n_cycles
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    st.profile(True)
+    for which in (0, 1):
+        st.profile_read(which, reset=True)
+    for _ in range(max(1, min(10, steps))):
+        st.step(p_, q_, s_, n_)
+        q_, p_, n_ = p_, n_, q_
+    torch.cuda.synchronize()
+    kern = {}
+    for which, name in ((0, "down"), (1, "up")):
+        ms, launches, cells = st.profile_read(which, reset=True)
+        avg = ms / 1e3 / max(1, launches)
+        # per-operation model (FP64, scheme 2, pinned) for nu sweeps per launch
+        sweeps = nu1 if name == "down" else nu2
+        model = (sweeps * (80.0 + 8.0) + (70.0 + 8.0 if name == "down" else 60.0 + 56.0 + 8.0))
+        kern[name] = {"avg_launch_us": avg * 1e6, "launches": launches,
+                      "tile": "%dx%d/%d" % st.tile_shape(0, which),
+                      "model_bytes_per_cell": model,
+                      "achieved_GBps": model * cells / avg / 1e9 if launches else None}
+    st.profile(False)
+    st.close()
+    dom = max(kern, key=lambda k: kern[k]["avg_launch_us"])
+    return {"time_steps_per_s": steps / el, "steps": steps, "vcycles_per_step": cyc / steps,
+            "ms_per_vcycle": 1e3 * el / max(1, cyc),
+            "unknowns_x_vcycles_per_s": 3.0 * m * n * cyc / el,
+            "roofline": {"kernel": f"k_tile {dom} launch (general-index) on the 512x400 level",
+                         "bound": "hbm", "achieved": kern[dom]["achieved_GBps"],
+                         "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": (kern[dom]["achieved_GBps"] / HBM_PEAK_GBPS
+                                  if kern[dom]["achieved_GBps"] else None)},
+            "kernels": kern,
+            "workload": "Sec. 4.4 sheared crystal, 512x400 periodic, eps=0.6, M=225, "
+                        "h=4pi/(16sqrt3), s=0.025h^2, beta=0.2, scheme 2, FP64, pinning strips "
+                        "(weight 2, height pi) with phi_hat sheared 4% of 2pi at the bottom, "
+                        f"V({nu1},{nu2}) to 1e-10, coarsest 64x50 by 1 red-black sweep"
+                        + ("" if energy else ", energies off")}
 
 
 def bench_batch(api, inputs, torch, dev, steps, warmup):
@@ -453,6 +526,16 @@ def main():
             "workload": "as above with the pinning term (weight 2 in 4-row strips top and "
                         "bottom, phi_hat = initial field)"}
         stp.close()
+    # Sec. 4.4's sheared crystal on its 512 x 400 grid (general grid sides).
+    if args.variants and args.shear_steps > 0:
+        # V(1,0) is the fastest cycle here (the collective smoother is close to
+        # its stability limit at these parameters); V(2,2) as the headline's
+        out["variants"]["sheared_crystal_512x400"] = bench_sheared(
+            api, inputs, torch, dev, args.shear_steps, args.warmup, 0 if args.no_energy else 1,
+            1, 0)
+        out["variants"]["sheared_crystal_512x400_v22"] = bench_sheared(
+            api, inputs, torch, dev, max(1, args.shear_steps // 2), args.warmup,
+            0 if args.no_energy else 1, 2, 2)
     # 2048^2 with mixed precision (FP32 correction cycles inside FP64 defect
     # correction) against FP64 on the same input (seed 3).
     if args.variants and args.big_steps > 0:

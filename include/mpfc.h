@@ -78,7 +78,7 @@ typedef struct {
  * is at most 2), solved directly by Newton's method.  Other grids (sides
  * multiples of 4; FP64, nu1, nu2 <= 2, no learned guess) end at a larger
  * level (512 x 400: 64 x 50, at most 4096 cells), relaxed by coarse_sweeps
- * red-black sweeps per V-cycle (in [1, 64], default 4); its Poisson problem
+ * red-black sweeps per V-cycle (in [1, 64], default 2); its Poisson problem
  * is solved exactly in the separable eigenbasis.  energy: 1 to compute the energies of Sec. 3 after each
  * step; diverge: factor of residual growth over the initial residual
  * reported as MPFC_EDIVERGED.

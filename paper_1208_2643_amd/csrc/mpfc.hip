@@ -1232,7 +1232,7 @@ void mpfc_default_opts(mpfc_opts* o) {
     o->energy = 1;
     o->diverge = 1e8;
     o->inner_cycles = 3;
-    o->coarse_sweeps = 4;
+    o->coarse_sweeps = 2;
 }
 
 int mpfc_validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {

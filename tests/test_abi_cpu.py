@@ -45,7 +45,7 @@ def good():
 def test_defaults():
     o = L.default_opts()
     assert (o.nu1, o.nu2, o.max_cycles, o.tol, o.coarsest, o.coarse_sweeps) == \
-        (2, 2, 100, 1e-10, 2, 4)
+        (2, 2, 100, 1e-10, 2, 2)
     p, o = good()
     assert L.load().mpfc_validate(1024, 1024, ctypes.byref(p), ctypes.byref(o)) == 0
 

@@ -54,7 +54,7 @@ def both(bc=0, **kw):
     return O.Params(**d, bc=(bc & 1, (bc >> 1) & 1)), api.Params(**d, bc=bc)
 
 
-def one_cycle(m, n, bc=0, scheme=2, newton=True, pin=False, seed=70, **kw):
+def one_cycle(m, n, bc=0, scheme=2, newton=True, pin=False, seed=70, nu=(2, 2), **kw):
     po, pg = both(bc, scheme=scheme, **kw)
     phik = I.crystallites(m, n, pg.h, count=2, radius_cells=min(m, n) / 8, seed=seed)
     prev = phik + 0.002 * I.noise(m, n, mean=0.0, amp=1.0, seed=seed + 1)
@@ -62,7 +62,7 @@ def one_cycle(m, n, bc=0, scheme=2, newton=True, pin=False, seed=70, **kw):
     W = hat = None
     lin = L.MPFC_NEWTON if newton else L.MPFC_PICARD
     st = api.Stepper(m, n, pg, tol=1e-30, max_cycles=1, energy=0, coarse_sweeps=K,
-                     linearization=lin)
+                     linearization=lin, nu1=nu[0], nu2=nu[1])
     if pin:
         W = np.zeros((n, m))
         W[:4] = 2.0
@@ -77,7 +77,7 @@ def one_cycle(m, n, bc=0, scheme=2, newton=True, pin=False, seed=70, **kw):
     S = O.source(po, phik, prev, psi0, pin=W, phihat=hat)
     u0 = O.complete_guess(po, 2 * phik - prev, S, phik=phik, pin=W)
     u, hist, _ = O.fas_solve(po, u0, S, phik=phik, tol=1e-30, max_cycles=1, newton=newton,
-                             pin=W, coarse_sweeps=K)
+                             pin=W, coarse_sweeps=K, nu1=nu[0], nu2=nu[1])
     out = (host(phi_g), host(mu), host(ka))
     st.close()
     return out, u, info, hist
@@ -111,6 +111,16 @@ def test_one_cycle_picard_and_pinning_match_oracle():
         for a, b in zip(got, ref):
             assert relmax(a, b) <= 1e-12, kw
         np.testing.assert_allclose(info.history, hist, rtol=1e-9)
+
+
+@pytest.mark.parametrize("nu", [(1, 0), (0, 1), (1, 1), (2, 1)])
+def test_other_cycles_match_oracle(nu):
+    """V(nu1, nu2) with fewer smoothing passes (the fastest cycles for the
+    Sec. 4.4 parameters), pinned as in that workload."""
+    got, ref, info, hist = one_cycle(200, 120, nu=nu, pin=True)
+    for a, b in zip(got, ref):
+        assert relmax(a, b) <= 1e-12
+    np.testing.assert_allclose(info.history, hist, rtol=1e-9)
 
 
 @pytest.mark.parametrize("shape", ["0", "2"])
