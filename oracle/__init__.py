@@ -59,8 +59,9 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    src = os.path.join(_HERE, "mpfc_oracle.c")
-    if not os.path.exists(_LIBPATH) or os.path.getmtime(_LIBPATH) < os.path.getmtime(src):
+    srcs = [os.path.join(_HERE, f) for f in ("mpfc_oracle.c", "mpfc3d_oracle.c")]
+    if not os.path.exists(_LIBPATH) or any(os.path.getmtime(_LIBPATH) < os.path.getmtime(f)
+                                           for f in srcs):
         from . import build as _b
         _b.build()
     lib = ctypes.CDLL(_LIBPATH)
@@ -92,6 +93,26 @@ def load():
         "orc_step": (i, [P, i, i, i, _dp, _dp, _dp, i, i, i, i, i, d, i,
                          _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
         "orc_set_bc": (v, [i, i]),
+        # three dimensions (mpfc3d_oracle.c)
+        "o3_laplacian": (v, [i, i, i, d, _dp, _dp]),
+        "o3_source": (v, [i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "o3_operator": (v, [i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "o3_residual": (v, [i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                            _dp]),
+        "o3_norm3": (d, [i, i, i, d, _dp, _dp, _dp]),
+        "o3_smooth": (v, [i, i, i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "o3_restrict": (v, [i, i, i, _dp, _dp]),
+        "o3_prolong_add": (v, [i, i, i, _dp, _dp]),
+        "o3_dense_newton": (i, [i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, i]),
+        "o3_fas_solve": (i, [i, i, i, i, i, d, d, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, i, i, i,
+                             i, d, i, _dp]),
+        "o3_complete_guess": (v, [i, i, i, i, d, d, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "o3_grad_sq": (d, [i, i, i, d, _dp]),
+        "o3_energy_F": (d, [i, i, i, d, d, _dp]),
+        "o3_poisson_cg": (i, [i, i, i, d, _dp, _dp, d, i]),
+        "o3_energies": (v, [i, i, i, d, d, d, _dp, _dp, _dp, _dp]),
+        "o3_step": (i, [i, i, i, i, i, d, d, d, d, d, _dp, _dp, _dp, i, i, i, i, i, d, i,
+                        _dp, _dp, _dp, _dp, _dp, _dp]),
         "orc_version": (i, []),
         "orc_num_threads": (i, []),
     }
@@ -376,3 +397,116 @@ def run(p: Params, phi0, steps, **kw):
         results.append(r)
         prev, phi, psi = phi, r.phi, r.psi
     return phi, prev, psi, results
+
+
+# ---------------------------------------------------------------------------
+# Three dimensions (mpfc3d_oracle.c): periodic m x n x l grids, arrays of shape
+# (l, n, m) with x fastest.  Same parameters (bc must be periodic).
+
+def _shape3(a):
+    l, n, m = a.shape
+    return m, n, l
+
+
+def laplacian3(f, h):
+    f = _arr(f)
+    out = np.empty_like(f)
+    load().o3_laplacian(*_shape3(f), h, _p(f), _p(out))
+    return out
+
+
+def source3(p: Params, phik, phikm1=None, psik=None):
+    phik = _arr(phik)
+    phikm1 = _arr(phikm1) if phikm1 is not None else phik
+    psik = _arr(psik) if psik is not None else None
+    _, d = coefficients(p)
+    S = [np.empty_like(phik) for _ in range(3)]
+    load().o3_source(p.scheme, *_shape3(phik), p.h, d, p.alpha, _p(phik), _p(phikm1), _p(psik),
+                     *[_p(x) for x in S])
+    return S
+
+
+def operator3(p: Params, u, phik=None, h=None):
+    phi, mu, ka = (_arr(x) for x in u)
+    c, _ = coefficients(p)
+    pk = _arr(phik) if p.scheme == 2 else None
+    N = [np.empty_like(phi) for _ in range(3)]
+    load().o3_operator(p.scheme, *_shape3(phi), p.h if h is None else h, c, p.alpha, _p(pk),
+                       _p(phi), _p(mu), _p(ka), *[_p(x) for x in N])
+    return N
+
+
+def complete_guess3(p: Params, phi, S, phik=None):
+    phi = _arr(phi)
+    mu, ka = np.empty_like(phi), np.empty_like(phi)
+    pk = _arr(phik) if p.scheme == 2 else None
+    load().o3_complete_guess(p.scheme, *_shape3(phi), p.h, p.alpha, _p(pk), _p(phi), _p(mu),
+                             _p(ka), _p(_arr(S[1])), _p(_arr(S[2])))
+    return [phi.copy(), mu, ka]
+
+
+def smooth3(p: Params, u, f, phik=None, sweeps=1, newton=True):
+    phi, mu, ka = (_arr(x).copy() for x in u)
+    c, _ = coefficients(p)
+    pk = _arr(phik) if p.scheme == 2 else None
+    load().o3_smooth(p.scheme, int(newton), sweeps, *_shape3(phi), p.h, c, p.alpha, _p(pk),
+                     _p(phi), _p(mu), _p(ka), *[_p(_arr(x)) for x in f])
+    return [phi, mu, ka]
+
+
+def fas_solve3(p: Params, u0, S, phik=None, nu1=2, nu2=2, coarsest=2, tol=1e-10,
+               max_cycles=100, newton=True, coarse_sweeps=0):
+    phi, mu, ka = (_arr(x).copy() for x in u0)
+    S1, S2, S3 = (_arr(x) for x in S)
+    c, _ = coefficients(p)
+    pk = _arr(phik) if p.scheme == 2 else None
+    hist = np.zeros(max_cycles + 1)
+    cyc = load().o3_fas_solve(p.scheme, int(newton), *_shape3(phi), p.h, c, p.alpha, _p(pk),
+                              _p(phi), _p(mu), _p(ka), _p(S1), _p(S2), _p(S3), nu1, nu2,
+                              coarsest, coarse_sweeps, tol, max_cycles, _p(hist))
+    ncyc = cyc if cyc >= 0 else -cyc - 1
+    return [phi, mu, ka], hist[: ncyc + 1], cyc
+
+
+def energies3(p: Params, phinew, phik, psinew):
+    phinew, phik, psinew = _arr(phinew), _arr(phik), _arr(psinew)
+    out = np.zeros(4)
+    load().o3_energies(*_shape3(phinew), p.h, p.eps, p.M, _p(phinew), _p(phik), _p(psinew),
+                       _p(out))
+    return out
+
+
+def grad_sq3(f, h):
+    f = _arr(f)
+    return load().o3_grad_sq(*_shape3(f), h, _p(f))
+
+
+def step3(p: Params, phik, phikm1=None, psik=None, guess=0, nu1=2, nu2=2, coarsest=2,
+          coarse_sweeps=0, tol=1e-10, max_cycles=100, newton=True, energy=True) -> StepResult:
+    """One time step in three dimensions (periodic)."""
+    assert tuple(p.bc) == (0, 0), "the three-dimensional oracle is periodic"
+    phik = _arr(phik)
+    phikm1 = _arr(phikm1) if phikm1 is not None else phik
+    psik = _arr(psik) if psik is not None else np.zeros_like(phik)
+    outs = [np.empty_like(phik) for _ in range(4)]
+    hist = np.zeros(max_cycles + 1)
+    en = np.zeros(4)
+    cyc = load().o3_step(p.scheme, int(newton), *_shape3(phik), p.h, p.dt, p.M, p.beta, p.eps,
+                         _p(phik), _p(phikm1), _p(psik), guess, nu1, nu2, coarsest,
+                         coarse_sweeps, tol, max_cycles, *[_p(x) for x in outs], _p(hist),
+                         _p(en) if energy else None)
+    ncyc = cyc if cyc >= 0 else -cyc - 1
+    return StepResult(outs[0], outs[1], outs[2], outs[3], hist[: ncyc + 1], cyc, en)
+
+
+def run3(p: Params, phi0, steps, **kw):
+    phi = _arr(phi0).copy()
+    prev = phi.copy()
+    psi = np.zeros_like(phi)
+    results = []
+    for _ in range(steps):
+        r = step3(p, phi, prev, psi, **kw)
+        results.append(r)
+        prev, phi, psi = phi, r.phi, r.psi
+    return phi, prev, psi, results
+

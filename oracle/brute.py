@@ -38,18 +38,37 @@ def laplacian_matrix(m: int, n: int, h: float) -> np.ndarray:
     return L
 
 
+def laplacian_matrix3(m: int, n: int, l: int, h: float) -> np.ndarray:
+    """Dense periodic seven-point Laplacian on an m x n x l cell grid, x fastest."""
+    N = m * n * l
+    L = np.zeros((N, N))
+    for k in range(l):
+        for j in range(n):
+            for i in range(m):
+                q = (k * n + j) * m + i
+                L[q, q] -= 6.0 / h**2
+                for (ii, jj, kk) in (((i + 1) % m, j, k), ((i - 1) % m, j, k),
+                                     (i, (j + 1) % n, k), (i, (j - 1) % n, k),
+                                     (i, j, (k + 1) % l), (i, j, (k - 1) % l)):
+                    L[q, (kk * n + jj) * m + ii] += 1.0 / h**2
+    return L
+
+
 def solve_step(scheme, eps, beta, M, h, s, phik, phikm1=None, psik=None, tol=1e-15, maxit=60,
                pin=None, phihat=None):
     """Return (phi, mu, kappa, iterations) of one step by dense Newton (with
     pinning weight `pin` and configuration `phihat`: scheme 2 only; mu is then
-    the pinned mu~)."""
-    n, m = phik.shape
+    the pinned mu~).  A 3-D array (l, n, m) is a three-dimensional grid (the
+    seven-point Laplacian); the reduced equation is the same."""
+    if phik.ndim == 3:
+        L = laplacian_matrix3(phik.shape[2], phik.shape[1], phik.shape[0], h)
+    else:
+        L = laplacian_matrix(phik.shape[1], phik.shape[0], h)
     pk = phik.reshape(-1).astype(np.float64)
     pkm1 = (phikm1 if phikm1 is not None else phik).reshape(-1).astype(np.float64)
     ps = (psik if psik is not None else np.zeros_like(phik)).reshape(-1).astype(np.float64)
-    L = laplacian_matrix(m, n, h)
     alpha = 1.0 - eps
-    I = np.eye(m * n)
+    I = np.eye(pk.size)
     if scheme == 1:
         c = s * M / (beta + 1.0 / s)
         d = 1.0 / (beta + 1.0 / s)

@@ -7,7 +7,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "mpfc_oracle.c")
+SRC = [os.path.join(HERE, "mpfc_oracle.c"), os.path.join(HERE, "mpfc3d_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 # -ffp-contract=off: no fused multiply-add, every expression rounds as written.
@@ -17,7 +17,7 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fopenmp", "-std=c99", "-fPIC", "-shared"
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = ["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"]
+    cmd = ["gcc", *CFLAGS, *SRC, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
