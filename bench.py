@@ -94,6 +94,8 @@ def parse():
                     help="steps of the variant with the pinning term (0 skips it)")
     ap.add_argument("--shear-steps", type=int, default=100,
                     help="steps of the 512 x 400 sheared-crystal variant of Sec. 4.4 (0 skips it)")
+    ap.add_argument("--steps-3d", type=int, default=20,
+                    help="steps of the 128^3 three-dimensional variant (0 skips it)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
     return ap.parse_args()
@@ -279,6 +281,62 @@ def bench_sheared(api, inputs, torch, dev, steps, warmup, energy, nu1, nu2):
                         "h=4pi/(16sqrt3), s=0.025h^2, beta=0.2, scheme 2, FP64, pinning strips "
                         "(weight 2, height pi) with phi_hat sheared 4% of 2pi at the bottom, "
                         f"V({nu1},{nu2}) to 1e-10, coarsest 64x50 by 1 red-black sweep"
+                        + ("" if energy else ", energies off")}
+
+
+# Algorithmic bytes of one red-black half-sweep launch in three dimensions, per
+# cell of the level (FP64, scheme 2): read u of every cell (24 B; the colour's
+# own cells and all their neighbours), S and phi^k of the colour's cells
+# (32 B x 1/2), write u of the colour's cells (24 B x 1/2).
+HALF_SWEEP_3D_BYTES = 24.0 + 16.0 + 12.0
+
+
+def bench_3d(api, inputs, torch, dev, steps, warmup, energy, N=128):
+    """Three dimensions: scheme 2, FP64, N^3 periodic, h = pi/4, eps = 0.025,
+    beta = 0.9, M = 1, dt = 0.05, phi0 = 0.07 + U[-0.05, 0.05] (seed 7),
+    V(2,2) to 1e-10, energies every step.  Also the live timing of the finest
+    level's half-sweep launches (the dominant kernel)."""
+    prm = dict(eps=0.025, beta=0.9, M=1.0, h=math.pi / 4, dt=0.05, scheme=2)
+    phi0 = inputs.noise3(N, N, N, seed=7)
+    st = api.Stepper3(N, N, N, api.Params(**prm), tol=1e-10, nu1=2, nu2=2, energy=energy)
+    p_ = torch.from_numpy(phi0).to(dev)
+    q_ = p_.clone()
+    s_ = torch.zeros_like(p_)
+    n_ = torch.empty_like(p_)
+    for _ in range(warmup):
+        st.step(p_, q_, s_, n_)
+        q_, p_, n_ = p_, n_, q_
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cyc = 0
+    for _ in range(steps):
+        _, inf = st.step(p_, q_, s_, n_)
+        q_, p_, n_ = p_, n_, q_
+        cyc += inf.n_cycles
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    st.profile(True)
+    st.profile_read(reset=True)
+    for _ in range(2):
+        st.step(p_, q_, s_, n_)
+        q_, p_, n_ = p_, n_, q_
+    torch.cuda.synchronize()
+    ms, launches, cells = st.profile_read(reset=True)
+    st.profile(False)
+    st.close()
+    avg = ms / 1e3 / max(1, launches)
+    ach = HALF_SWEEP_3D_BYTES * cells / avg / 1e9 if launches else None
+    return {"time_steps_per_s": steps / el, "steps": steps, "vcycles_per_step": cyc / steps,
+            "ms_per_vcycle": 1e3 * el / max(1, cyc),
+            "unknowns_x_vcycles_per_s": 3.0 * N ** 3 * cyc / el,
+            "roofline": {"kernel": "k3_relax half-sweep launch on the finest level",
+                         "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBPS if ach else None,
+                         "bytes_per_launch": HALF_SWEEP_3D_BYTES * cells,
+                         "avg_launch_us": avg * 1e6, "launches": launches},
+            "workload": f"three dimensions, scheme 2, FP64, {N}^3 periodic, h=pi/4, eps=0.025, "
+                        "beta=0.9, M=1, dt=0.05, 0.07 + U[-0.05,0.05] (seed 7), V(2,2) to 1e-10, "
+                        "coarsest 2^3 by 2 red-black sweeps"
                         + ("" if energy else ", energies off")}
 
 
@@ -536,6 +594,10 @@ def main():
         out["variants"]["sheared_crystal_512x400_v22"] = bench_sheared(
             api, inputs, torch, dev, max(1, args.shear_steps // 2), args.warmup,
             0 if args.no_energy else 1, 2, 2)
+    # The three-dimensional extension of the step at 128^3.
+    if args.variants and args.steps_3d > 0:
+        out["variants"]["three_d_128"] = bench_3d(api, inputs, torch, dev, args.steps_3d,
+                                                  args.warmup, 0 if args.no_energy else 1)
     # 2048^2 with mixed precision (FP32 correction cycles inside FP64 defect
     # correction) against FP64 on the same input (seed 3).
     if args.variants and args.big_steps > 0:

@@ -165,6 +165,31 @@ int mpfc_energies(mpfc_ctx *ctx, const double *d_phi, const double *d_phi_prev,
  * MPFC_NEWTON (else MPFC_EINVAL); allocates the weight pyramid on first use. */
 int mpfc_set_pinning(mpfc_ctx *ctx, const double *d_weight, const double *d_phihat);
 
+/* Three space dimensions.  The paper notes that the schemes extend to three
+ * dimensions in a straightforward way; this is that extension: the same
+ * equations (Sec. 3.1 / 3.2, App. B.1 / B.2) with the seven-point Laplacian
+ * (sum of the six face neighbours - 6 f) / h^2 on an m x n x l cell-centred
+ * grid, periodic in every axis, cell (i, j, k) at index (k*n + j)*m + i; the
+ * FAS V-cycle uses 2x2x2-average restriction and trilinear prolongation, the
+ * coarsest level (smallest side 2) is relaxed by coarse_sweeps red-black sweeps
+ * (red = (i+j+k) even); grid sums carry h^3 and the gradient norm is h times
+ * the sum of squared face differences.  m, n, l powers of two >= 2, bc = 0,
+ * MPFC_FP64, guess MPFC_GUESS_PREV or MPFC_GUESS_EXTRAP; other options as for
+ * mpfc_create.  Arguments, ownership, outputs and return codes of
+ * mpfc3d_step are those of mpfc_step (arrays of m*n*l doubles). */
+typedef struct mpfc3d_ctx mpfc3d_ctx;
+int mpfc3d_validate(int m, int n, int l, const mpfc_params *p, const mpfc_opts *o);
+int mpfc3d_create(mpfc3d_ctx **out, int m, int n, int l, const mpfc_params *p,
+                  const mpfc_opts *o, void *stream);
+int mpfc3d_step(mpfc3d_ctx *ctx, const double *d_phi_n, const double *d_phi_nm1, double *d_psi,
+                double *d_phi_np1, double *d_mu, double *d_kappa, mpfc_info *h_info);
+/* Live timing (HIP events, direct launches while on) of the finest level's
+ * red-black half-sweep launches: total ms, launch count, finest cells. */
+int mpfc3d_prof_enable(mpfc3d_ctx *ctx, int on);
+int mpfc3d_prof_read(mpfc3d_ctx *ctx, double *total_ms, long long *launches, long long *cells,
+                     int reset);
+void mpfc3d_destroy(mpfc3d_ctx *ctx);
+
 /* Live timing of the two finest-level launches of each V-cycle (the dominant
  * kernels of the step) with HIP events on the context's stream:
  * which = 0: the down launch (nu1 red-black passes of the App. B smoother,

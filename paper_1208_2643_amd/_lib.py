@@ -119,6 +119,14 @@ SIGNATURES = {
     "mpfc_cnn_trainer_blob": (_i, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
     "mpfc_cnn_trainer_destroy": (None, [_vp]),
     "mpfc_cnn_trainer_set_lr": (_i, [_vp, ctypes.c_float]),
+    "mpfc3d_validate": (_i, [_i, _i, _i, ctypes.POINTER(mpfc_params), ctypes.POINTER(mpfc_opts)]),
+    "mpfc3d_create": (_i, [ctypes.POINTER(_vp), _i, _i, _i, ctypes.POINTER(mpfc_params),
+                           ctypes.POINTER(mpfc_opts), _vp]),
+    "mpfc3d_step": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(mpfc_info)]),
+    "mpfc3d_prof_enable": (_i, [_vp, _i]),
+    "mpfc3d_prof_read": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong),
+                              ctypes.POINTER(ctypes.c_longlong), _i]),
+    "mpfc3d_destroy": (None, [_vp]),
 }
 
 

@@ -164,6 +164,60 @@ class Stepper:
         return np.array(out[:])
 
 
+class Stepper3:
+    """Solver context for a periodic m x n x l grid in three dimensions
+    (tensors of shape (l, n, m), x fastest); same options and step
+    semantics as Stepper."""
+
+    def __init__(self, m: int, n: int, l: int, params: Params, stream=None, **opts):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libmpfc needs a HIP GPU; none is visible")
+        self.lib = L.load()
+        self.m, self.n, self.l = m, n, l
+        self.params = params
+        self.opts = make_opts(**opts)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        ctx = ctypes.c_void_p()
+        L.check(self.lib.mpfc3d_create(ctypes.byref(ctx), m, n, l, ctypes.byref(params.c()),
+                                       ctypes.byref(self.opts), _stream(self.stream)))
+        self.ctx = ctx
+        self._hist = np.zeros(self.opts.max_cycles + 1)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.mpfc3d_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, phi_n, phi_nm1, psi, phi_np1=None, mu=None, kappa=None, allow_fail=False):
+        if phi_np1 is None:
+            phi_np1 = torch.empty_like(phi_n)
+        info = L.mpfc_info()
+        info.residual_history = self._hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        rc = self.lib.mpfc3d_step(self.ctx, _ptr(phi_n), _ptr(phi_nm1), _ptr(psi), _ptr(phi_np1),
+                                  _ptr(mu), _ptr(kappa), ctypes.byref(info))
+        allow = (L.MPFC_ENOTCONVERGED, L.MPFC_ENONFINITE, L.MPFC_EDIVERGED) if allow_fail else ()
+        L.check(rc, allow)
+        si = StepInfo(rc, info.n_cycles, info.residual, self._hist[:info.n_cycles + 1].copy(),
+                      info.energy_F, info.energy_pseudo, info.energy_mod, info.mass, 0)
+        return phi_np1, si
+
+    def profile(self, on: bool = True):
+        """Time the finest level's red-black half-sweep launches with HIP events."""
+        L.check(self.lib.mpfc3d_prof_enable(self.ctx, 1 if on else 0))
+
+    def profile_read(self, reset: bool = True):
+        ms, n, cells = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_longlong()
+        L.check(self.lib.mpfc3d_prof_read(self.ctx, ctypes.byref(ms), ctypes.byref(n),
+                                          ctypes.byref(cells), 1 if reset else 0))
+        return ms.value, n.value, cells.value
+
+
 class Batch:
     """Many independent simulations advanced together (mpfc_batch_*).
 

@@ -1720,3 +1720,4 @@ int mpfc_op_restrict(int m, int n, const double* fine, double* coarse, void* str
 
 #include "batch_host.hpp"
 #include "cnn_host.hpp"
+#include "mpfc3d_host.hpp"

@@ -21,6 +21,8 @@ Workloads (each named by what it is):
   (Sec. 4.1, eq. initial-data) on Omega = (0, 32)^2.
 * ``batch``: 64 independent simulations with sizes, eps, mean density and
   beta drawn per simulation.
+* ``noise3``: the three-dimensional workload, 0.07 + U[-0.05, 0.05] on an
+  m x n x l grid.
 * ``strained_crystal``: the sheared-crystal set-up of Sec. 4.4 on its 512 x 400
   grid: a band of 20 atomic layers of the one-mode profile (solid density
   phi_s, amplitude A(phi_s, eps)) in a liquid of density phi_l, a pinning
@@ -46,6 +48,13 @@ def noise(m: int, n: int, mean: float = 0.07, amp: float = 0.05, seed: int = 1) 
     """mean + uniform noise in [-amp, amp] on every cell."""
     rng = np.random.default_rng(seed)
     return mean + rng.uniform(-amp, amp, size=(n, m))
+
+
+def noise3(m: int, n: int, l: int, mean: float = 0.07, amp: float = 0.05,
+           seed: int = 7) -> np.ndarray:
+    """Three-dimensional grid (shape (l, n, m), x fastest): mean + U[-amp, amp]."""
+    rng = np.random.default_rng(seed)
+    return mean + rng.uniform(-amp, amp, size=(l, n, m))
 
 
 def crystallites(m: int, n: int, h: float, count: int = 3, radius_cells: float = 20.0,

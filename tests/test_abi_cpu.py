@@ -170,3 +170,31 @@ def test_neumann_boundaries_validate(bc):
     assert L.load().mpfc_validate(1024, 1024, ctypes.byref(p), ctypes.byref(o)) == 0
     o.guess = L.MPFC_GUESS_CNN
     assert L.load().mpfc_validate(1024, 1024, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
+
+
+@pytest.mark.parametrize("m,n,l", [(128, 128, 128), (2, 2, 2), (64, 32, 16), (8, 8, 64)])
+def test_3d_sizes_accepted(m, n, l):
+    p, o = good()
+    assert L.load().mpfc3d_validate(m, n, l, ctypes.byref(p), ctypes.byref(o)) == 0
+
+
+@pytest.mark.parametrize("m,n,l", [(96, 64, 64), (64, 64, 1), (0, 8, 8), (1024, 1024, 512)])
+def test_3d_bad_sizes_rejected(m, n, l):
+    p, o = good()
+    assert L.load().mpfc3d_validate(m, n, l, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(bc=1), dict(precision=1), dict(guess=2), dict(dt=-1.0),
+                                dict(coarse_sweeps=0)])
+def test_3d_unsupported_configurations_rejected(kw):
+    """The three-dimensional step is periodic, FP64, without the learned guess;
+    parameters and options are checked as for the two-dimensional step."""
+    p, o = good()
+    for k, v in kw.items():
+        setattr(p if k in ("bc", "dt") else o, k, v)
+    assert L.load().mpfc3d_validate(16, 16, 16, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
+    ctx = ctypes.c_void_p()
+    assert L.load().mpfc3d_create(ctypes.byref(ctx), 16, 16, 16, ctypes.byref(p), ctypes.byref(o),
+                                  None) == L.MPFC_EINVAL
+    assert ctx.value is None
+
