@@ -51,6 +51,7 @@ struct mpfc3d_ctx {
     hipStream_t stream = nullptr;
     double c = 0, d = 0, alpha = 0;
     std::vector<Level3> L;
+    int Lp = 0;                         // first level of at most CP3_CELLS cells (persistent kernel)
     CycleState* st = nullptr;
     double* hist = nullptr;
     CycleState* pst = nullptr;
@@ -129,7 +130,10 @@ int vcycle3(mpfc3d_ctx* C, hipStream_t s) {
         return A;
     };
     const int nu1 = POISSON ? 2 : C->o.nu1, nu2 = POISSON ? 2 : C->o.nu2;
-    for (int lv = 0; lv < nl - 1; ++lv) {
+    const int csweeps = POISSON ? kPoissonCoarseSweeps3 : C->o.coarse_sweeps;
+    const bool pers = C->Lp < nl;               // small levels in one persistent launch
+    const int top = pers ? C->Lp : nl - 1;      // levels below `top` use per-level launches
+    for (int lv = 0; lv < top; ++lv) {
         const Level3& A = C->L[lv];
         const Level3& B = C->L[lv + 1];
         const auto op = op_of(A);
@@ -148,8 +152,9 @@ int vcycle3(mpfc3d_ctx* C, hipStream_t s) {
             L3 FR{};
             FR.u[0] = B.w;
             FR.f[0] = B.prr;
-            hipLaunchKernelGGL((k3_complete<PoissonOp3>), dim3(blocks256(ncB)), dim3(256), 0, s,
-                               op_of(B), B.g, FR, B.pf, nullptr, nullptr, stop);
+            if (!(pers && lv + 1 == top))
+                hipLaunchKernelGGL((k3_complete<PoissonOp3>), dim3(blocks256(ncB)), dim3(256), 0, s,
+                                   op_of(B), B.g, FR, B.pf, nullptr, nullptr, stop);
         } else {
             hipLaunchKernelGGL((k3_restrict<Op>), dim3(blocks256(ncB)), dim3(256), 0, s, op, A.g, FA,
                                FB, B.v[0], B.v[1], B.v[2], B.rr[0], B.rr[1], B.rr[2],
@@ -157,37 +162,77 @@ int vcycle3(mpfc3d_ctx* C, hipStream_t s) {
             L3 FR{};
             for (int f = 0; f < 3; ++f) { FR.u[f] = B.u[f]; FR.f[f] = B.rr[f]; }
             FR.xk = B.xk;
-            hipLaunchKernelGGL((k3_complete<Op>), dim3(blocks256(ncB)), dim3(256), 0, s, op_of(B),
-                               B.g, FR, B.f[0], B.f[1], B.f[2], stop);
+            if (!(pers && lv + 1 == top))
+                hipLaunchKernelGGL((k3_complete<Op>), dim3(blocks256(ncB)), dim3(256), 0, s, op_of(B),
+                                   B.g, FR, B.f[0], B.f[1], B.f[2], stop);
         }
     }
-    {
+    if (pers) {
+        // levels top .. nl-1 in one workgroup
+        const Level3& T = C->L[top];
+        CoarseArgs3 CA{};
+        CA.geo.nlev = nl - top;
+        int off = 0;
+        for (int k = 0; k < CA.geo.nlev; ++k) {
+            const Level3& lv = C->L[top + k];
+            CA.geo.m[k] = lv.m; CA.geo.n[k] = lv.n; CA.geo.l[k] = lv.l;
+            CA.geo.lm[k] = lv.g.lm; CA.geo.ln[k] = lv.g.ln;
+            CA.geo.off[k] = off;
+            off += lv.m * lv.n * lv.l;
+        }
+        CA.gtop = T.g;
+        CA.complete_top = top > 0;
+        CA.nsw1 = nu1;
+        CA.nsw2 = nu2;
+        CA.nswc = csweeps;
+        if constexpr (POISSON) {
+            CA.u[0] = T.w;
+            CA.f[0] = top > 0 ? T.prr : T.pf;
+            CA.xk = nullptr;
+        } else {
+            for (int f = 0; f < 3; ++f) {
+                CA.u[f] = T.u[f];
+                CA.f[f] = top > 0 ? T.rr[f] : T.f[f];
+            }
+            CA.xk = T.xk;
+        }
+        if constexpr (POISSON)
+            hipLaunchKernelGGL((k3_coarse<PoissonOp3>), dim3(1), dim3(CP3_THREADS), 0, s, op_of(T), CA,
+                               stop);
+        else
+            hipLaunchKernelGGL((k3_coarse<Op>), dim3(1), dim3(CP3_THREADS), 0, s, op_of(T), CA, stop);
+    } else {
         // coarsest level: red-black sweeps
         const Level3& A = C->L[nl - 1];
         const auto op = op_of(A);
         const L3 FA = fields(A, nl - 1);
-        const int sweeps = POISSON ? kPoissonCoarseSweeps3 : C->o.coarse_sweeps;
-        for (int k = 0; k < sweeps; ++k)
+        for (int k = 0; k < csweeps; ++k)
             for (int col = 0; col < 2; ++col) {
                 int rc = relax3(C, op, A, FA, col, stop, s, nl == 1);
                 if (rc) return rc;
             }
     }
-    for (int lv = nl - 2; lv >= 0; --lv) {
+    for (int lv = top - 1; lv >= 0; --lv) {
         const Level3& A = C->L[lv];
         const Level3& B = C->L[lv + 1];
         const auto op = op_of(A);
         const L3 FA = fields(A, lv);
         const L3 FB = fields(B, lv + 1);
-        const size_t nc = (size_t)A.m * A.n * A.l;
-        if constexpr (POISSON)
-            hipLaunchKernelGGL((k3_prolong<1>), dim3(blocks256(nc)), dim3(256), 0, s, A.g, FA, FB,
+        const size_t nc = (size_t)A.m * A.n * A.l / 2;   // pairs of fine cells
+        const size_t ncB = (size_t)B.m * B.n * B.l;
+        if constexpr (POISSON) {
+            hipLaunchKernelGGL((k3_correction<1>), dim3(blocks256(ncB)), dim3(256), 0, s, B.g, FB,
+                               B.pv, (double*)nullptr, (double*)nullptr, stop);
+            hipLaunchKernelGGL((k3_prolong<1>), dim3(blocks256(nc)), dim3(256), 0, s, A.g, FA,
                                (const double*)B.pv, (const double*)nullptr,
                                (const double*)nullptr, stop);
-        else
-            hipLaunchKernelGGL((k3_prolong<3>), dim3(blocks256(nc)), dim3(256), 0, s, A.g, FA, FB,
+        } else {
+            hipLaunchKernelGGL((k3_correction<3>), dim3(blocks256(ncB)), dim3(256), 0, s, B.g, FB,
+                               B.v[0], B.v[1], B.v[2], stop);
+            hipLaunchKernelGGL((k3_prolong<3>), dim3(blocks256(nc)), dim3(256), 0, s, A.g, FA,
                                (const double*)B.v[0], (const double*)B.v[1],
                                (const double*)B.v[2], stop);
+        }
         for (int k = 0; k < nu2; ++k)
             for (int col = 0; col < 2; ++col) {
                 int rc = relax3(C, op, A, FA, col, stop, s, lv == 0);
@@ -361,6 +406,9 @@ int mpfc3d_create(mpfc3d_ctx** out, int m, int n, int l, const mpfc_params* p,
         }
     }
     const int nl = (int)C->L.size();
+    C->Lp = nl;
+    for (int k = 0; k < nl; ++k)
+        if ((long long)C->L[k].m * C->L[k].n * C->L[k].l <= CP3_CELLS) { C->Lp = k; break; }
     auto layout = [&](double* base) {
         size_t off = 0;
         auto take = [&](size_t cnt) {
@@ -434,9 +482,8 @@ int mpfc3d_step(mpfc3d_ctx* C, const double* phi_n, const double* phi_nm1, doubl
     else
         hipLaunchKernelGGL((k3_source<2>), dim3(nb), dim3(256), 0, s, F0.g, ih2, C->d, C->alpha,
                            phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2]);
-    if (F0.xk) HIP_TRY(hipMemcpyAsync(F0.xk, phi_n, total * sizeof(double), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k3_guess, dim3(nb), dim3(256), 0, s, total,
-                       C->o.guess == MPFC_GUESS_EXTRAP ? 1 : 0, phi_n, phi_nm1, F0.u[0]);
+    hipLaunchKernelGGL(k3_guess, dim3(nb), dim3(256), 0, s, F0.g,
+                       C->o.guess == MPFC_GUESS_EXTRAP ? 1 : 0, phi_n, phi_nm1, F0.u[0], F0.xk);
     const LevelOp<double> lo = level_op3(C, F0);
     hipLaunchKernelGGL(k3_complete_kappa, dim3(nb), dim3(256), 0, s, F0.g, ih2, lo.e, F0.u[0],
                        F0.f[2], F0.u[2]);
@@ -484,13 +531,13 @@ int mpfc3d_step(mpfc3d_ctx* C, const double* phi_n, const double* phi_nm1, doubl
     C->pred = cycles > 0 ? cycles : 1;
     // psi^{k+1} (in place) and phi^{k+1} out; mu and kappa if asked
     if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_psi_update<1>), dim3(nb), dim3(256), 0, s, total, C->p.dt, F0.u[0],
+        hipLaunchKernelGGL((k3_psi_update<1>), dim3(nb), dim3(256), 0, s, F0.g, C->p.dt, F0.u[0],
                            phi_n, psi, phi_np1);
     else
-        hipLaunchKernelGGL((k_psi_update<2>), dim3(nb), dim3(256), 0, s, total, C->p.dt, F0.u[0],
+        hipLaunchKernelGGL((k3_psi_update<2>), dim3(nb), dim3(256), 0, s, F0.g, C->p.dt, F0.u[0],
                            phi_n, psi, phi_np1);
-    if (mu_out) HIP_TRY(hipMemcpyAsync(mu_out, F0.u[1], total * sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (ka_out) HIP_TRY(hipMemcpyAsync(ka_out, F0.u[2], total * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (mu_out) hipLaunchKernelGGL(k3_from_split, dim3(nb), dim3(256), 0, s, F0.g, F0.u[1], mu_out);
+    if (ka_out) hipLaunchKernelGGL(k3_from_split, dim3(nb), dim3(256), 0, s, F0.g, F0.u[2], ka_out);
     HIP_TRY(hipGetLastError());
     double en[4] = {0, 0, 0, 0};
     int erc = MPFC_OK;
