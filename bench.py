@@ -46,9 +46,9 @@ PIN_BYTES = {"down": 3 * 8.0, "up": 3 * 8.0}
 # shape "TXxTY/HALO", valid only for the kernel sources they were measured on
 # (kernel_source_hash).
 MEASURED_TRAFFIC = {
-    "src": "474e243098f76f38",
-    "down": {"64x32/6": 110247360, "32x32/6": 115010423, "32x16/6": 110159727, "16x16/6": 109968185, "64x16/10": 114774962, "32x16/10": 110196992, "16x16/10": 110044045},
-    "up": {"64x32/6": 109615756, "32x32/6": 107605741, "32x16/6": 103353320, "16x16/6": 103160242, "64x16/10": 103347996, "32x16/10": 103231494, "16x16/10": 103215114},
+    "src": "20376d4096086463",
+    "down": {"64x32/6": 110239064, "32x32/6": 115034554, "32x16/6": 110176866, "16x16/6": 109971995, "64x16/10": 114825554, "32x16/10": 110187253, "16x16/10": 110048253},
+    "up": {"64x32/6": 109655854, "32x32/6": 107619018, "32x16/6": 103322696, "16x16/6": 103157196, "64x16/10": 103318937, "32x16/10": 103235758, "16x16/10": 103221052},
 }
 
 

@@ -109,25 +109,32 @@ __device__ __forceinline__ int axis_index_any(int i, int m, bool neumann) {
     if (r < 0) r += 2 * m;
     return r < m ? r : 2 * m - 1 - r;
 }
+// One step outside the axis (i in [-m, 2m)), any m: compares and selects, no
+// branch and no division; the per-cell kernels only look one cell across.
+__device__ __forceinline__ int wrap1(int i, int m, bool neumann) {
+    const int lo = neumann ? -1 - i : i + m;
+    const int hi = neumann ? 2 * m - 1 - i : i - m;
+    return i < 0 ? lo : (i >= m ? hi : i);
+}
 __device__ __forceinline__ int wrapx(int i, const Grid& g) {
-    return g.lm >= 0 ? axis_index(i, g.m, g.bc & BC_NEUMANN_X)
-                     : axis_index_any(i, g.m, g.bc & BC_NEUMANN_X);
+    return wrap1(i, g.m, g.bc & BC_NEUMANN_X);
 }
 __device__ __forceinline__ int wrapy(int j, const Grid& g) {
-    return g.ln >= 0 ? axis_index(j, g.n, g.bc & BC_NEUMANN_Y)
-                     : axis_index_any(j, g.n, g.bc & BC_NEUMANN_Y);
+    return wrap1(j, g.n, g.bc & BC_NEUMANN_Y);
 }
 __device__ __forceinline__ size_t at(int i, int j, const Grid& g) {
-    return g.lm >= 0 ? ((size_t)j << g.lm) + (size_t)i : (size_t)j * (size_t)g.m + (size_t)i;
+    const unsigned r = g.lm >= 0 ? (unsigned)j << g.lm : (unsigned)j * (unsigned)g.m;
+    return (size_t)r + (size_t)i;   // m * n <= 2^28
 }
-// (i, j) of the cell at linear index q.
+// (i, j) of the cell at linear index q (< 2^28).
 __device__ __forceinline__ void cell_of(size_t q, const Grid& g, int& i, int& j) {
+    const unsigned u = (unsigned)q;
     if (g.lm >= 0) {
-        i = (int)(q & (size_t)(g.m - 1));
-        j = (int)(q >> g.lm);
+        i = (int)(u & (unsigned)(g.m - 1));
+        j = (int)(u >> g.lm);
     } else {
-        j = (int)(q / (size_t)g.m);
-        i = (int)(q - (size_t)j * (size_t)g.m);
+        j = (int)(u / (unsigned)g.m);
+        i = (int)(u - (unsigned)j * (unsigned)g.m);
     }
 }
 
