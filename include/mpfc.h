@@ -219,7 +219,9 @@ int mpfc_version(void);
 /* ---- Operator-level entry points (one operation of the V-cycle each) ----
  * Same operators as mpfc_step uses, on caller-provided FP64 device arrays;
  * c is s M/(beta + 1/s) (scheme 1) or s M/(beta + 2/s) (scheme 2), alpha =
- * 1 - eps.  d_phik is phi^k on this grid (scheme 2; ignored for scheme 1). */
+ * 1 - eps.  d_phik is phi^k on this grid (scheme 2; ignored for scheme 1).
+ * m and n are even (any even value: powers of two use the bit-mask kernels,
+ * other sides the general-index ones); otherwise MPFC_EINVAL. */
 
 /* `sweeps` red-black nonlinear Gauss-Seidel passes (App. B), red
  * ((i+j) even) first, Newton (linearization 0) or Picard (1) local
