@@ -438,6 +438,62 @@ __device__ __forceinline__ void complete_kappa_cell(const Grid& g, double ih2, d
     ka[q] = S3[q] + e * (nsum(phi, i, j, g) - 4.0 * phi[q]) * ih2;
 }
 
+// Step set-up in one pass (extrapolated or previous-step guess): the source S
+// (source_cell), the guess phi0 = guess_value(mode, phi^k, phi^{k-1}) and
+// kappa = S3 + e Lap phi0, the first half of the guess's completion.  Each
+// thread forms the guess at its four neighbours itself, so no other thread's
+// output is read; the arithmetic is that of k_guess and complete_kappa_cell.
+// Workgroup (0, 0) also resets the cycle state.
+template <int SCHEME>
+__global__ void __launch_bounds__(256) k_setup(Grid g, double ih2, double d, double alpha,
+                                               double e, int mode,
+                                               const double* __restrict__ phik,
+                                               const double* __restrict__ phikm1,
+                                               const double* __restrict__ psik, double* S1,
+                                               double* S2, double* S3, double* phik_copy,
+                                               const double* __restrict__ pin,
+                                               const double* __restrict__ phihat, double* phi0,
+                                               double* ka, CycleState* st) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+        st->acc = 0.0; st->blocks = 0u; st->count = 0;
+        st->status = ST_RUNNING; st->done = 0; st->pad0 = st->pad1 = 0;
+    }
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.m || j >= g.n) return;
+    source_cell<SCHEME>(g, ih2, d, alpha, phik, phikm1, psik, S1, S2, S3, phik_copy, i, j, pin,
+                        phihat);
+    const size_t q = at(i, j, g);
+    auto gv = [&](size_t k) { return guess_value(mode, phik[k], phikm1[k]); };
+    const double x = gv(q);
+    phi0[q] = x;
+    const int ip = wrapx(i + 1, g), im = wrapx(i - 1, g);
+    const int jp = wrapy(j + 1, g), jm = wrapy(j - 1, g);
+    const double ns = (gv(at(ip, j, g)) + gv(at(im, j, g))) + (gv(at(i, jp, g)) + gv(at(i, jm, g)));
+    ka[q] = S3[q] + e * (ns - 4.0 * x) * ih2;
+}
+
+// Residual norm of a guess completed by k_setup and k_complete_mu: N^(2) = S^(2)
+// and N^(3) = S^(3) hold by construction (up to rounding), so only
+// r1 = S1 - (phi - c Lap mu) is summed (per-block sums of r1^2 into part[];
+// k_norm_finalize turns them into the norm).  Reads phi, mu and S1.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_resnorm_guess(Fields<double> F, LevelOp<double> op, Grid g,
+                                                      double* part) {
+    __shared__ double red[NT / 64];
+    double acc = 0.0;
+    const size_t total = (size_t)g.m * g.n;
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
+        int i, j;
+        cell_of(q, g, i, j);
+        const double lmu = (nsum(F.mu, i, j, g) - 4.0 * F.mu[q]) * op.ih2;
+        const double r1 = F.f1[q] - (F.phi[q] - op.c * lmu);
+        acc += r1 * r1;
+    }
+    const double bs = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
 __global__ void __launch_bounds__(256) k_complete_kappa(Grid g, double ih2, double e,
                                                         const double* __restrict__ phi,
                                                         const double* __restrict__ S3,

@@ -1157,27 +1157,39 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
     double* phi = F0.u[0][0];
     double* mu = F0.u[0][1];
     double* ka = F0.u[0][2];
-    if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_source<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
-                           phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik,
-                           (const double*)nullptr, (const double*)nullptr);
-    else
-        hipLaunchKernelGGL((k_source<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
-                           phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik,
-                           (const double*)(C->pinned ? F0.pin : nullptr),
-                           (const double*)(C->pinned ? C->phihat : nullptr));
-    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->st);
+    const double e = C->p.scheme == 1 ? 1.0 : 0.5;
+    const double al = C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha;
     const bool learned = C->o.guess == MPFC_GUESS_CNN;
-    if (learned) {
+    const int gmode = C->o.guess == MPFC_GUESS_PREV ? 0 : 1;
+    const double* pin = C->pinned ? F0.pin : nullptr;
+    const double* phihat = C->pinned ? C->phihat : nullptr;
+    if (!learned) {
+        // source, guess and kappa in one pass
+        if (C->p.scheme == 1)
+            hipLaunchKernelGGL((k_setup<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
+                               e, gmode, phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik,
+                               (const double*)nullptr, (const double*)nullptr, phi, ka, C->st);
+        else
+            hipLaunchKernelGGL((k_setup<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
+                               e, gmode, phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik,
+                               pin, phihat, phi, ka, C->st);
+    } else {
+        if (C->p.scheme == 1)
+            hipLaunchKernelGGL((k_source<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
+                               phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik,
+                               (const double*)nullptr, (const double*)nullptr);
+        else
+            hipLaunchKernelGGL((k_source<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
+                               phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik, pin,
+                               phihat);
+        hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->st);
         int rc = cnn_candidate(C, phi_n, phi_nm1, psi, s);
         if (rc) return rc;
         residual_sq(C, 1, C->cnn_r2, s);
+        hipLaunchKernelGGL(k_guess, grid1(total), dim3(256), 0, s, g0, gmode, phi_n, phi_nm1, phi);
+        hipLaunchKernelGGL(k_complete_kappa, grid2(C->m, C->n), B2, 0, s, g0, ih2, e, phi, F0.f[2],
+                           ka);
     }
-    hipLaunchKernelGGL(k_guess, grid1(total), dim3(256), 0, s, g0,
-                       C->o.guess == MPFC_GUESS_PREV ? 0 : 1, phi_n, phi_nm1, phi);
-    const double e = C->p.scheme == 1 ? 1.0 : 0.5;
-    const double al = C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha;
-    hipLaunchKernelGGL(k_complete_kappa, grid2(C->m, C->n), B2, 0, s, g0, ih2, e, phi, F0.f[2], ka);
     if (C->p.scheme == 1)
         hipLaunchKernelGGL((k_complete_mu<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, phi,
                            C->phik, ka, F0.f[1], mu, (const double*)nullptr);
@@ -1186,11 +1198,18 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
                            C->phik, ka, F0.f[1], mu, (const double*)(C->pinned ? F0.pin : nullptr));
     if (learned) cnn_choose(C, s);
     if (C->o.precision != MPFC_MIXED) {
-        if (learned)  // the pick left the kept guess's squared norm in part[0]
+        if (learned) {  // the pick left the kept guess's squared norm in part[0]
             hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, 1, C->st,
                                C->hist, F0.h * F0.h, C->o.tol, C->o.max_cycles + 1, C->o.diverge);
-        else
-            resnorm(C, s);
+        } else {
+            // the completed guess satisfies N^(2) = S^(2), N^(3) = S^(3): only r1 is left
+            const unsigned nb = red_blocks(total);
+            hipLaunchKernelGGL((k_resnorm_guess<NT>), dim3(nb), dim3(NT), 0, s, finest_fields(C),
+                               level_op(C, F0), g0, C->part);
+            hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)nb,
+                               C->st, C->hist, F0.h * F0.h, C->o.tol, C->o.max_cycles + 1,
+                               C->o.diverge);
+        }
     } else {
         const auto& FF = C->FL[0];
         // the coarse levels' phi^k is averaged by the down launches of each cycle
