@@ -145,3 +145,26 @@ def test_128_cubed_mass_and_energy():
         prev, phi, nxt = phi, nxt, prev
     assert all(b <= a + 1e-9 * abs(a) for a, b in zip(mods, mods[1:]))
     st.close()
+
+
+def test_128_cubed_step_matches_oracle():
+    """The benchmark's configuration at its full size (128^3, h = pi/4, dt =
+    0.05, scheme 2, the bench's seeded initial data): one step, element by
+    element against the oracle (about 40 s on one CPU thread; the energies are
+    checked against the oracle on 32^3 and 64^3)."""
+    m = n = l = 128
+    po, pg = both(h=math.pi / 4)
+    phi0 = field3(m, n, l, 7)
+    st = api.Stepper3(m, n, l, pg, tol=1e-10)
+    psi = torch.zeros(l, n, m, dtype=torch.float64, device=DEV)
+    mu = torch.empty_like(psi)
+    phi_g, info = st.step(dev(phi0), dev(phi0), psi, mu=mu)
+    r = O.step3(po, phi0, phi0, np.zeros_like(phi0), tol=1e-11, max_cycles=200, coarse_sweeps=2,
+                energy=False)
+    assert r.cycles > 0 and info.status == 0
+    assert rel_l2(host(phi_g), r.phi) <= 1e-9
+    assert rel_l2(host(mu), r.mu) <= 1e-8
+    assert rel_l2(host(psi), r.psi) <= 1e-6
+    h3 = (math.pi / 4) ** 3
+    assert info.mass == pytest.approx(h3 * float(r.phi.sum()), rel=1e-12)
+    st.close()
