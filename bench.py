@@ -46,9 +46,9 @@ PIN_BYTES = {"down": 3 * 8.0, "up": 3 * 8.0}
 # shape "TXxTY/HALO", valid only for the kernel sources they were measured on
 # (kernel_source_hash).
 MEASURED_TRAFFIC = {
-    "src": "20376d4096086463",
-    "down": {"64x32/6": 110239064, "32x32/6": 115034554, "32x16/6": 110176866, "16x16/6": 109971995, "64x16/10": 114825554, "32x16/10": 110187253, "16x16/10": 110048253},
-    "up": {"64x32/6": 109655854, "32x32/6": 107619018, "32x16/6": 103322696, "16x16/6": 103157196, "64x16/10": 103318937, "32x16/10": 103235758, "16x16/10": 103221052},
+    "src": "381aab36beb77074",
+    "down": {"64x32/6": 110239096, "32x32/6": 115031665, "32x16/6": 110181958, "16x16/6": 109972091, "64x16/10": 114797977, "32x16/10": 110187562, "16x16/10": 110048818},
+    "up": {"64x32/6": 109659394, "32x32/6": 107628113, "32x16/6": 103324823, "16x16/6": 103158118, "64x16/10": 103342344, "32x16/10": 103233929, "16x16/10": 103223297},
 }
 
 
