@@ -282,6 +282,26 @@ def test_mixed_precision_full_size_1024():
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_2048(precision):
+    """One step of the 2048^2 workload (scheme 2, h = pi/4, dt = 0.05,
+    crystallites seed 3) in FP64 and in mixed precision (four FP32 V-cycles per
+    FP64 outer iteration, the benchmark's setting), against the oracle's step
+    solved to 1e-12 (eight cycles, a few seconds on the host)."""
+    N = 2048
+    po, pg = both(2, h=math.pi / 4, dt=0.05)
+    phi0 = I.crystallites(N, N, math.pi / 4, seed=3)
+    kw = dict(precision=L.MPFC_MIXED, inner_cycles=4) if precision else {}
+    st = api.Stepper(N, N, pg, tol=1e-10, energy=0, **kw)
+    psi = torch.zeros(N, N, dtype=torch.float64, device=DEV)
+    phi_g, info = st.step(dev(phi0), dev(phi0), psi)
+    r = O.step(po, phi0, phi0, np.zeros_like(phi0), tol=1e-12, max_cycles=100, energy=False)
+    assert r.cycles > 0 and info.status == 0 and info.residual <= 1e-10
+    assert rel_l2(host(phi_g), r.phi) <= (1e-9 if precision else 1e-10)
+    assert rel_l2(host(psi), r.psi) <= 1e-6
+    st.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_one_cycle_iterate_matches_oracle(precision):
     """After exactly one V-cycle (FP64) the fused kernels' iterate equals the
     oracle's one-cycle iterate element by element (same components, same
