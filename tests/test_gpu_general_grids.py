@@ -225,3 +225,26 @@ def test_tile_sides_divide_the_levels():
             assert m % tx == 0 and n % ty == 0 and tx % 2 == 0 and ty % 2 == 0
             assert tx <= 64 and ty <= 32
     st.close()
+
+
+def test_diverged_status():
+    """A solve whose residual grows stops with MPFC_EDIVERGED.  On a 12 x 12
+    grid the coarsest level (6 x 6) is relaxed by two red-black sweeps, not
+    solved, and at h = 0.5, dt = 0.3 the collective smoother is unstable there:
+    the oracle's residual rises above its initial value by a clear margin (the
+    first cycle above 1.01 x the initial norm is at least 5 % above it).  With a
+    divergence factor of 1.01 the GPU stops at that cycle with the same history."""
+    po, pg = both(scheme=2, h=0.5, dt=0.3)
+    phi = I.noise(12, 12, mean=0.1, amp=0.05, seed=91)
+    r = O.step(po, phi, phi, np.zeros_like(phi), tol=1e-12, max_cycles=10, energy=False,
+               coarse_sweeps=2)
+    hs = np.asarray(r.history)
+    k = int(np.argmax(hs > 1.01 * hs[0]))
+    assert k > 0 and hs[k] > 1.05 * hs[0] and np.all(hs[1:k] < 0.95 * hs[0])
+    st = api.Stepper(12, 12, pg, tol=1e-12, max_cycles=50, energy=0, coarse_sweeps=2,
+                     diverge=1.01)
+    psi = torch.zeros(12, 12, dtype=torch.float64, device=DEV)
+    _, info = st.step(dev(phi), dev(phi), psi, allow_fail=True)
+    assert info.status == L.MPFC_EDIVERGED and info.n_cycles == k
+    np.testing.assert_allclose(info.history, hs[:k + 1], rtol=1e-6)
+    st.close()
