@@ -299,6 +299,67 @@ __global__ void __launch_bounds__(256) k3_prolong(Grid3 g, L3 A, const double* E
     }
 }
 
+// The same prolongation with the coarse correction staged in LDS, for fine
+// grids with m >= 32 (n, l >= 4 hold on every fine level): a workgroup takes
+// P3X x-pairs x P3Y rows x P3Z planes, whose coarse footprint (one coarse cell
+// of margin on each side) is read from global memory once instead of twelve
+// times per pair.  Same values, same order of operations as k3_prolong.
+constexpr int P3X = 16, P3Y = 4, P3Z = 4;
+template <int NF>
+__global__ void __launch_bounds__(256) k3_prolong_blk(Grid3 g, L3 A, const double* E0,
+                                                      const double* E1, const double* E2,
+                                                      const CycleState* st) {
+    static_assert(P3X * P3Y * P3Z == 256, "one x-pair per thread");
+    constexpr int CXN = P3X + 2, CYN = P3Y / 2 + 2, CZN = P3Z / 2 + 2;
+    __shared__ double Es[NF][CZN][CYN][CXN];
+    if (stopped(st)) return;
+    const int nbx = (g.m >> 1) / P3X, nby = g.n / P3Y;
+    const int b = xcd_item(blockIdx.x, gridDim.x);
+    const int bx = b % nbx, r = b / nbx, by = r % nby, bz = r / nby;
+    const int I0 = bx * P3X, j0 = by * P3Y, k0 = bz * P3Z;
+    const Grid3 c{g.m >> 1, g.n >> 1, g.l >> 1, g.lm - 1, g.ln - 1, g.ll - 1};
+    const int cx0 = I0 - 1, cy0 = (j0 >> 1) - 1, cz0 = (k0 >> 1) - 1;
+    const double* E[3] = {E0, E1, E2};
+    for (int q = threadIdx.x; q < CXN * CYN * CZN; q += 256) {
+        const int x = q % CXN, yz = q / CXN, y = yz % CYN, z = yz / CYN;
+        const size_t Q = sidx((cx0 + x) & (c.m - 1), (cy0 + y) & (c.n - 1), (cz0 + z) & (c.l - 1), c);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) Es[f][z][y][x] = E[f][Q];
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & (P3X - 1), ty = (threadIdx.x / P3X) & (P3Y - 1),
+              tz = threadIdx.x / (P3X * P3Y);
+    const int I = I0 + tx, j = j0 + ty, k = k0 + tz;
+    // local coarse indices: parent x tx + 1 with sides tx, tx + 2; parent y
+    // (ty >> 1) + 1 with its side on the fine cell's side; z alike
+    const int LY[2] = {(ty >> 1) + 1, (ty >> 1) + 1 + ((j & 1) ? 1 : -1)};
+    const int LZ[2] = {(tz >> 1) + 1, (tz >> 1) + 1 + ((k & 1) ? 1 : -1)};
+    const double w[2] = {0.75, 0.25};
+    const size_t q0 = sidx(2 * I, j, k, g), q1 = sidx(2 * I + 1, j, k, g);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        double e[2][2][3];
+#pragma unroll
+        for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int x = 0; x < 3; ++x) e[z][y][x] = Es[f][LZ[z]][LY[y]][tx + x];
+        double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+        for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int x = 0; x < 2; ++x) {
+                    v0 += w[x] * w[y] * w[z] * e[z][y][x == 0 ? 1 : 0];
+                    v1 += w[x] * w[y] * w[z] * e[z][y][x == 0 ? 1 : 2];
+                }
+        A.u[f][q0] += v0;
+        A.u[f][q1] += v1;
+    }
+}
+
 // Per-block sums of r^2 = (f - N(u))^2 over all fields (the stopping test;
 // k_norm_finalize / k_p_finalize turn them into the norm).
 template <class Op, int NT>

@@ -219,19 +219,32 @@ int vcycle3(mpfc3d_ctx* C, hipStream_t s) {
         const L3 FA = fields(A, lv);
         const L3 FB = fields(B, lv + 1);
         const size_t nc = (size_t)A.m * A.n * A.l / 2;   // pairs of fine cells
+        // blocked prolongation: whole blocks of P3X x P3Y x P3Z pairs (sides
+        // are powers of two, so m >= 2 P3X with n, l >= 4 tiles the level)
+        const bool blk = A.m >= 2 * P3X && A.n >= P3Y && A.l >= P3Z;
         const size_t ncB = (size_t)B.m * B.n * B.l;
         if constexpr (POISSON) {
             hipLaunchKernelGGL((k3_correction<1>), dim3(blocks256(ncB)), dim3(256), 0, s, B.g, FB,
                                B.pv, (double*)nullptr, (double*)nullptr, stop);
-            hipLaunchKernelGGL((k3_prolong<1>), dim3(blocks256(nc)), dim3(256), 0, s, A.g, FA,
-                               (const double*)B.pv, (const double*)nullptr,
-                               (const double*)nullptr, stop);
+            if (blk)
+                hipLaunchKernelGGL((k3_prolong_blk<1>), dim3(blocks256(nc)), dim3(256), 0, s, A.g,
+                                   FA, (const double*)B.pv, (const double*)nullptr,
+                                   (const double*)nullptr, stop);
+            else
+                hipLaunchKernelGGL((k3_prolong<1>), dim3(blocks256(nc)), dim3(256), 0, s, A.g, FA,
+                                   (const double*)B.pv, (const double*)nullptr,
+                                   (const double*)nullptr, stop);
         } else {
             hipLaunchKernelGGL((k3_correction<3>), dim3(blocks256(ncB)), dim3(256), 0, s, B.g, FB,
                                B.v[0], B.v[1], B.v[2], stop);
-            hipLaunchKernelGGL((k3_prolong<3>), dim3(blocks256(nc)), dim3(256), 0, s, A.g, FA,
-                               (const double*)B.v[0], (const double*)B.v[1],
-                               (const double*)B.v[2], stop);
+            if (blk)
+                hipLaunchKernelGGL((k3_prolong_blk<3>), dim3(blocks256(nc)), dim3(256), 0, s, A.g,
+                                   FA, (const double*)B.v[0], (const double*)B.v[1],
+                                   (const double*)B.v[2], stop);
+            else
+                hipLaunchKernelGGL((k3_prolong<3>), dim3(blocks256(nc)), dim3(256), 0, s, A.g, FA,
+                                   (const double*)B.v[0], (const double*)B.v[1],
+                                   (const double*)B.v[2], stop);
         }
         for (int k = 0; k < nu2; ++k)
             for (int col = 0; col < 2; ++col) {
