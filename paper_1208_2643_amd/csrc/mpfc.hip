@@ -73,9 +73,13 @@ constexpr int NT = 256;
 const dim3 B2(64, 4);
 dim3 grid2(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); }
 dim3 grid1(size_t total) { return dim3((unsigned)((total + 255) / 256)); }
+// Workgroups of the grid-stride reductions (norms, energies): each writes its
+// partial sums (up to 8 values) to `part`; one workgroup per CU left these
+// passes latency bound.
+constexpr unsigned kRedBlocks = 1024;
 unsigned red_blocks(size_t total) {
     size_t b = (total + NT - 1) / NT;
-    return (unsigned)(b < 256 ? b : 256);  // one workgroup per CU: few atomics per reduction
+    return (unsigned)(b < kRedBlocks ? b : kRedBlocks);
 }
 
 // Tile shapes (interior TX x TY, largest halo HMAX) instantiated for the
@@ -1404,9 +1408,12 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
         C->hist = take(o->max_cycles + 1 + 8);
         C->phist = take(64);
         C->acc = take(64);
-        // one partial sum per finest tile (general grids: tiles down to 2 x 2)
+        // one partial sum per finest tile (general grids: tiles down to 2 x 2),
+        // and at least 8 per reduction workgroup
         const size_t cells_per_part = C->gen ? 4 : 256;
-        C->nparts = (int)((size_t)m * n / cells_per_part > 4096 ? (size_t)m * n / cells_per_part : 4096);
+        const size_t min_parts = (size_t)kRedBlocks * 8;
+        C->nparts = (int)((size_t)m * n / cells_per_part > min_parts ? (size_t)m * n / cells_per_part
+                                                                      : min_parts);
         C->part = take((size_t)C->nparts);
         C->st = (CycleState*)take(16);
         C->pst = (CycleState*)take(16);

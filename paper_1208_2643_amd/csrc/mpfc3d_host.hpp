@@ -447,7 +447,8 @@ int mpfc3d_create(mpfc3d_ctx** out, int m, int n, int l, const mpfc_params* p,
         C->hist = take(o->max_cycles + 1 + 8);
         C->phist = take(kPoissonMax + 8);
         C->acc = take(64);
-        C->nparts = 4096;
+        C->nparts = 4096;  // per-block partials (up to 8 values) of at most kRedBlocks blocks
+        static_assert(kRedBlocks <= 4096, "reduction partials exceed the buffer");
         C->part = take((size_t)C->nparts * 8);
         C->st = (CycleState*)take(16);
         C->pst = (CycleState*)take(16);
