@@ -1495,14 +1495,15 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     int rc0 = step_prologue(C, phi_n, phi_nm1, psi, s);
     if (rc0) return rc0;
     // Cycles are enqueued speculatively behind the set-up, without waiting for
-    // it: the first batch is one less than the previous step needed, then one
-    // at a time.  A cycle enqueued after the stop flag was raised exits at once
+    // it: the first batch is what the previous step needed (a steady step then
+    // costs one host round trip), then one at a time.  A cycle enqueued after
+    // the stop flag was raised exits at once
     // in every kernel, so speculation only costs launches, never changes the
     // result.  (Mixed precision: outer iteration k reads FP64 copy 1 ^ (k & 1).)
     // While profiling, cycles go one by one and the set-up is waited for, so
     // that every timed launch belongs to a cycle that ran.
     int launched = 0;
-    int batch = C->prof ? 1 : (C->pred_units > 1 ? C->pred_units - 1 : 1);
+    int batch = C->prof ? 1 : (C->pred_units > 1 ? C->pred_units : 1);
     bool done = false;
     if (C->prof) {
         HIP_TRY(hipMemcpyAsync(C->host_st, C->st, sizeof(CycleState), hipMemcpyDeviceToHost, s));
