@@ -250,6 +250,37 @@ def test_translation_equivariance():
     assert np.max(np.abs(np.roll(host(a), (13, 37), axis=(0, 1)) - host(b))) <= 1e-10
 
 
+@pytest.mark.parametrize("scheme,precision,N", [
+    (1, L.MPFC_FP64, 256), (2, L.MPFC_FP64, 256), (2, L.MPFC_MIXED, 256), (2, L.MPFC_FP64, 1024)])
+def test_transposition_equivariance(scheme, precision, N):
+    """On a square periodic grid the scheme treats x and y alike, so
+    exchanging the axes of the input exchanges them in phi^{k+1}, psi^{k+1}
+    and mu and leaves the energies and the mass unchanged.  The tiles are not
+    square (64 x 32, 32 x 16 ...), so an index or halo mistake along one axis
+    breaks the symmetry."""
+    _, pg = both(scheme, h=math.pi / 4, dt=0.05)
+    phik = I.noise(N, N, mean=0.1, amp=0.1, seed=95)
+    phikm1 = I.noise(N, N, mean=0.1, amp=0.1, seed=96)
+    psik = I.noise(N, N, mean=0.0, amp=0.05, seed=97)
+    tol = 1e-12 if N <= 256 else 1e-11
+    out = []
+    for t in (lambda a: a, lambda a: np.ascontiguousarray(a.T)):
+        st = api.Stepper(N, N, pg, tol=tol, precision=precision, max_cycles=100)
+        psi = dev(t(psik))
+        mu = torch.empty_like(psi)
+        phi, info = st.step(dev(t(phik)), dev(t(phikm1)), psi, mu=mu)
+        assert info.status == 0 and info.n_cycles > 0
+        out.append((t(host(phi)), t(host(psi)), t(host(mu)), info))
+        st.close()
+    (pa, sa, ma, ia), (pb, sb, mb, ib) = out
+    assert np.max(np.abs(pa - pb)) <= 1e-10
+    assert np.max(np.abs(sa - sb)) <= 1e-8   # psi scales the phi difference by 1/s or 2/s
+    assert np.max(np.abs(ma - mb)) <= 1e-8
+    for key in ("energy_F", "energy_pseudo", "energy_mod", "mass"):
+        a, b = getattr(ia, key), getattr(ib, key)
+        assert abs(a - b) <= 1e-10 * max(1.0, abs(a)), key
+
+
 # ------------------------------------------------------------ mixed precision
 @pytest.mark.parametrize("scheme", [1, 2])
 def test_mixed_precision_matches_fp64_oracle(scheme):
