@@ -248,3 +248,32 @@ def test_diverged_status():
     assert info.status == L.MPFC_EDIVERGED and info.n_cycles == k
     np.testing.assert_allclose(info.history, hs[:k + 1], rtol=1e-6)
     st.close()
+
+
+@pytest.mark.parametrize("m,n,bc", [(192, 160, 0), (192, 160, L.MPFC_BC_NEUMANN_Y), (512, 400, 0)])
+def test_axis_exchange_general(m, n, bc):
+    """Sides that are not powers of two: the transposed input, on the n x m
+    grid with the two axes' boundary conditions exchanged, gives the
+    transposed step, its psi and mu, and the same energies."""
+    swapped = ((bc & 1) << 1) | ((bc >> 1) & 1)
+    phik = I.crystallites(m, n, math.pi / 4, radius_cells=14, seed=151)
+    phikm1 = phik + 0.002 * I.noise(m, n, mean=0.0, amp=1.0, seed=152)
+    out = []
+    for b, t, (mm, nn) in ((bc, lambda a: a, (m, n)),
+                           (swapped, lambda a: np.ascontiguousarray(a.T), (n, m))):
+        _, pg = both(b)
+        st = api.Stepper(mm, nn, pg, tol=1e-11, max_cycles=200, coarse_sweeps=K)
+        psi = torch.zeros(nn, mm, dtype=torch.float64, device=DEV)
+        mu = torch.empty_like(psi)
+        phi, info = st.step(dev(t(phik)), dev(t(phikm1)), psi, mu=mu)
+        assert info.status == 0 and info.n_cycles > 0
+        out.append((t(host(phi)), t(host(psi)), t(host(mu)), info))
+        st.close()
+    (pa, sa, ma, ia), (pb, sb, mb, ib) = out
+    assert pa.shape == pb.shape == (n, m)
+    assert np.max(np.abs(pa - pb)) <= 1e-10
+    assert np.max(np.abs(sa - sb)) <= 1e-8
+    assert np.max(np.abs(ma - mb)) <= 1e-8
+    for key in ("energy_F", "energy_mod", "mass"):
+        a, b = getattr(ia, key), getattr(ib, key)
+        assert abs(a - b) <= 1e-10 * max(1.0, abs(a)), key
