@@ -163,3 +163,32 @@ def test_unsupported_configurations_rejected(kw):
     with pytest.raises(L.MpfcError):
         st.set_pinning(w, w.clone())
     st.close()
+
+
+@pytest.mark.parametrize("bc", [0, L.MPFC_BC_NEUMANN_Y])
+def test_pinned_axis_exchange(bc):
+    """With the weight, phi_hat, the input and the two axes' boundary
+    conditions all transposed (horizontal strips become vertical ones), the
+    pinned step is the transposed step, with the same energies."""
+    m, n = 128, 64
+    swapped = ((bc & 1) << 1) | ((bc >> 1) & 1)
+    phi0 = I.crystallites(m, n, math.pi / 4, radius_cells=10, seed=171)
+    W, hat = pinning(m, n, 172, phi0)
+    out = []
+    for b, t, (mm, nn) in ((bc, lambda a: a, (m, n)),
+                           (swapped, lambda a: np.ascontiguousarray(a.T), (n, m))):
+        _, pg = both(b)
+        st = api.Stepper(mm, nn, pg, tol=1e-12, max_cycles=200)
+        st.set_pinning(dev(t(W)), dev(t(hat)))
+        phi, prev, psi, infos = api.run(st, dev(t(phi0)), 3)
+        assert all(i.status == 0 for i in infos)
+        out.append((t(host(phi)), t(host(psi)), infos))
+        st.close()
+    (pa, sa, ia), (pb, sb, ib) = out
+    assert pa.shape == pb.shape == (n, m)
+    assert np.max(np.abs(pa - pb)) <= 1e-10
+    assert np.max(np.abs(sa - sb)) <= 1e-8
+    for a, b in zip(ia, ib):
+        for key in ("energy_F", "energy_mod", "mass"):
+            x, y = getattr(a, key), getattr(b, key)
+            assert abs(x - y) <= 1e-10 * max(1.0, abs(x)), key
