@@ -93,7 +93,7 @@ def parse():
     ap.add_argument("--pin-steps", type=int, default=100,
                     help="steps of the variant with the pinning term (0 skips it)")
     ap.add_argument("--shear-steps", type=int, default=100,
-                    help="steps of the 512 x 400 sheared-crystal variant of Sec. 4.4 (0 skips it)")
+                    help="steps of the 512 x 400 sheared-crystal variant of Sec. 4.6 (0 skips it)")
     ap.add_argument("--steps-3d", type=int, default=20,
                     help="steps of the 128^3 three-dimensional variant (0 skips it)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -217,7 +217,7 @@ def bench_learned(api, inputs, torch, dev, params, tol, steps, warmup, N):
 
 
 def bench_sheared(api, inputs, torch, dev, steps, warmup, energy, nu1, nu2):
-    """Sec. 4.4's sheared crystal on its 512 x 400 grid (sides not both powers
+    """Sec. 4.6's sheared crystal on its 512 x 400 grid (sides not both powers
     of two: general-index tile kernels, coarsest level 64 x 50 relaxed by one
     red-black sweep per cycle, which converges as fast here as 2 or 4): eps 0.6, M = 15^2, h = 4 pi / (16 sqrt 3), s = 0.025 h^2,
     beta 0.2, scheme 2, FP64, pinning weight 2 in strips of height pi at the
@@ -277,7 +277,7 @@ def bench_sheared(api, inputs, torch, dev, steps, warmup, energy, nu1, nu2):
                          "frac": (kern[dom]["achieved_GBps"] / HBM_PEAK_GBPS
                                   if kern[dom]["achieved_GBps"] else None)},
             "kernels": kern,
-            "workload": "Sec. 4.4 sheared crystal, 512x400 periodic, eps=0.6, M=225, "
+            "workload": "Sec. 4.6 sheared crystal, 512x400 periodic, eps=0.6, M=225, "
                         "h=4pi/(16sqrt3), s=0.025h^2, beta=0.2, scheme 2, FP64, pinning strips "
                         "(weight 2, height pi) with phi_hat sheared 4% of 2pi at the bottom, "
                         f"V({nu1},{nu2}) to 1e-10, coarsest 64x50 by 1 red-black sweep"
@@ -532,7 +532,7 @@ def main():
                                     "outer_per_step": outer / vsteps,
                                     "fp32_vcycles_per_step": inner / vsteps,
                                     "speedup_vs_fp64": vsteps / el / steps_per_s}
-    # The same workload with Sec. 4.3's boundary conditions: periodic in x,
+    # The same workload with Sec. 4.5's boundary conditions: periodic in x,
     # homogeneous Neumann in y (App. A), FP64, energies as above.
     if args.variants and args.bc_steps > 0:
         stb = api.Stepper(N, N, api.Params(**params, bc=L.MPFC_BC_NEUMANN_Y), tol=tol, nu1=2,
@@ -557,7 +557,7 @@ def main():
             "vcycles_per_step": cyc / args.bc_steps,
             "workload": "as above with periodic x, homogeneous Neumann y boundaries"}
         stb.close()
-    # The same workload with the pinning term of Sec. 4.4: weight 2 in strips
+    # The same workload with the pinning term of Sec. 4.6: weight 2 in strips
     # of 4 rows along the top and bottom, phi_hat the initial field.
     if args.variants and args.pin_steps > 0:
         W = torch.zeros_like(phi)
@@ -587,7 +587,7 @@ def main():
             "workload": "as above with the pinning term (weight 2 in 4-row strips top and "
                         "bottom, phi_hat = initial field)"}
         stp.close()
-    # Sec. 4.4's sheared crystal on its 512 x 400 grid (general grid sides).
+    # Sec. 4.6's sheared crystal on its 512 x 400 grid (general grid sides).
     if args.variants and args.shear_steps > 0:
         # V(1,0) is the fastest cycle here (the collective smoother is close to
         # its stability limit at these parameters); V(2,2) as the headline's

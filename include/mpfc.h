@@ -17,7 +17,7 @@
  * Conventions for every entry point:
  *  - Grid functions are contiguous arrays of m*n values, row-major with x
  *    fastest: cell (i, j) at index j*m + i.  m and n are powers of two, or
- *    (mpfc_create, FP64 only) multiples of 4 such as Sec. 4.4's 512 x 400.
+ *    (mpfc_create, FP64 only) multiples of 4 such as Sec. 4.6's 512 x 400.
  *  - Pointers named d_* are device pointers (hipMalloc'd or from a PyTorch
  *    tensor), owned by the caller, and must stay valid until the call
  *    returns.  Pointers named h_* are host pointers owned by the caller.
@@ -55,7 +55,7 @@ enum { MPFC_GUESS_PREV = 0, MPFC_GUESS_EXTRAP = 1,                 /* initial gu
 enum { MPFC_NEWTON = 0, MPFC_PICARD = 1 };                        /* linearisation */
 /* Boundary conditions (App. A): every axis is periodic (eqs. per-bcs) unless
  * its bit is set, then homogeneous Neumann (eqs. h-n-bcs: the ghost cell
- * repeats the boundary cell).  Sec. 4.3 runs periodic in x, Neumann in y. */
+ * repeats the boundary cell).  Sec. 4.5 runs periodic in x, Neumann in y. */
 enum { MPFC_BC_PERIODIC = 0, MPFC_BC_NEUMANN_X = 1, MPFC_BC_NEUMANN_Y = 2 };
 
 /* Model and discretisation (Sec. 2, Sec. 3): alpha = 1 - eps; dt is the time
@@ -111,7 +111,9 @@ typedef struct {
     int n_cycles;        /* V-cycles run */
     int status;          /* return code of the step */
     int outer_iters;     /* mixed precision: FP64 defect-correction iterations */
-    int pad;
+    int energy_status;   /* 0, or MPFC_ENOTCONVERGED when the Poisson solve of the
+                            -1 norm stopped at its cycle limit (energy_pseudo and
+                            energy_mod are then approximate) */
     double *residual_history;
 } mpfc_info;
 
@@ -155,7 +157,7 @@ int mpfc_step(mpfc_ctx *ctx, const double *d_phi_n, const double *d_phi_nm1, dou
 int mpfc_energies(mpfc_ctx *ctx, const double *d_phi, const double *d_phi_prev,
                   const double *d_psi, double *h_out);
 
-/* Pinning (Sec. 4.4): from the next step on, mu is replaced by
+/* Pinning (Sec. 4.6): from the next step on, mu is replaced by
  * mu~ = mu + 2 (phi^{k+1/2} - phi_hat) W with phi^{k+1/2} = (phi^{k+1} + phi^k)/2,
  * i.e. N^(2) gains -W phi and S^(2) gains W (phi^k - 2 phi_hat); the mu that
  * mpfc_step returns is mu~, and energy_F includes h^2 sum W (phi - phi_hat)^2.
@@ -217,28 +219,29 @@ const char *mpfc_last_error(void);
 int mpfc_version(void);
 
 /* ---- Operator-level entry points (one operation of the V-cycle each) ----
- * Same operators as mpfc_step uses, on caller-provided FP64 device arrays;
- * c is s M/(beta + 1/s) (scheme 1) or s M/(beta + 2/s) (scheme 2), alpha =
- * 1 - eps.  d_phik is phi^k on this grid (scheme 2; ignored for scheme 1).
- * m and n are even (any even value: powers of two use the bit-mask kernels,
- * other sides the general-index ones); otherwise MPFC_EINVAL. */
+ * Same operators as mpfc_step uses, on caller-provided FP64 device arrays of
+ * an m x n grid with spacing p->h and boundary conditions p->bc; the library
+ * forms the coefficients of eqs. discrete_1_a / discrete_2_a from *p
+ * (c = s M/(beta + 1/s) or s M/(beta + 2/s), alpha = 1 - eps); *p is checked
+ * as by mpfc_validate.  A coarse level of the multigrid hierarchy is a grid
+ * of spacing 2^l h: pass a copy of the parameters with that h.  d_phik is
+ * phi^k on this grid (scheme 2; ignored for scheme 1).  m and n are even
+ * (any even value: powers of two use the bit-mask kernels, other sides the
+ * general-index ones); otherwise MPFC_EINVAL. */
 
 /* `sweeps` red-black nonlinear Gauss-Seidel passes (App. B), red
- * ((i+j) even) first, Newton (linearization 0) or Picard (1) local
- * linearisation, in place on (d_phi, d_mu, d_kappa); m, n >= 4; bc:
- * MPFC_BC_* bits.  Runs the fused tile kernel of the V-cycle and allocates a
- * scratch copy of u. */
-int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double c, double alpha,
-                   const double *d_phik, double *d_phi, double *d_mu, double *d_kappa,
-                   const double *d_f1, const double *d_f2, const double *d_f3, int sweeps,
-                   int bc, void *stream);
+ * ((i+j) even) first, Newton (MPFC_NEWTON) or Picard (MPFC_PICARD) local
+ * linearisation, in place on (d_phi, d_mu, d_kappa); m, n >= 4.  Runs the
+ * fused tile kernel of the V-cycle and allocates a scratch copy of u. */
+int mpfc_op_smooth(const mpfc_params *p, int linearization, int m, int n, const double *d_phik,
+                   double *d_phi, double *d_mu, double *d_kappa, const double *d_f1,
+                   const double *d_f2, const double *d_f3, int sweeps, void *stream);
 
-/* r = f - N(u) (App. B), three output arrays; bc: MPFC_BC_* bits. */
-int mpfc_op_residual(int scheme, int m, int n, double h, double c, double alpha,
-                     const double *d_phik, const double *d_phi, const double *d_mu,
-                     const double *d_kappa, const double *d_f1, const double *d_f2,
-                     const double *d_f3, double *d_r1, double *d_r2, double *d_r3, int bc,
-                     void *stream);
+/* r = f - N(u) (App. B), three output arrays. */
+int mpfc_op_residual(const mpfc_params *p, int m, int n, const double *d_phik,
+                     const double *d_phi, const double *d_mu, const double *d_kappa,
+                     const double *d_f1, const double *d_f2, const double *d_f3, double *d_r1,
+                     double *d_r2, double *d_r3, void *stream);
 
 /* Source S of the step (App. B.1 / B.2) from phi^k, phi^{k-1}, psi^k. */
 int mpfc_op_source(const mpfc_params *p, int m, int n, const double *d_phik,

@@ -152,11 +152,11 @@ def _shape(a):
 
 
 def _pin(p, pin, phihat=None, need_hat=False):
-    """Pinning weight (and phi_hat) as arrays, checked (Sec. 4.4: scheme 2)."""
+    """Pinning weight (and phi_hat) as arrays, checked (Sec. 4.6: scheme 2)."""
     if pin is None:
         return None, None
     if p.scheme != 2:
-        raise ValueError("pinning is defined for the second-order scheme (Sec. 4.4)")
+        raise ValueError("pinning is defined for the second-order scheme (Sec. 4.6)")
     w = _arr(pin)
     if need_hat and phihat is None:
         raise ValueError("pinning needs phi_hat")
@@ -369,7 +369,7 @@ def step(p: Params, phik, phikm1=None, psik=None, guess=0, nu1=2, nu2=2, coarses
          tol=1e-10, max_cycles=100, newton=True, energy=True, pin=None,
          phihat=None, coarse_sweeps=0) -> StepResult:
     """One time step of the chosen scheme from (phi^k, phi^{k-1}, psi^k);
-    pin / phihat: pinning weight W and prescribed configuration (Sec. 4.4)."""
+    pin / phihat: pinning weight W and prescribed configuration (Sec. 4.6)."""
     phik = _arr(phik)
     phikm1 = _arr(phikm1) if phikm1 is not None else phik
     psik = _arr(psik) if psik is not None else np.zeros_like(phik)

@@ -13,7 +13,7 @@ Scheme 2 (Sec. 3.2, eqs. mpfc_scheme2_3, mpfc_scheme2_4, discrete_2_a):
     mu = chi(phi, phi^k)(phi + phi^k)/2 + alpha (phi + phi^k)/2 + 2 L phi~ + L kappa,
     R(phi) = phi - phi^k - c2 L mu - d2 psi^k = 0,
 with chi(a, b) = (a^2 + b^2)/2 and phi~ = (3 phi^k - phi^{k-1})/2.
-Pinning (Sec. 4.4, scheme 2): mu is replaced by
+Pinning (Sec. 4.6, scheme 2): mu is replaced by
     mu~ = mu + 2 ((phi + phi^k)/2 - phi_hat) W
 in R, with the weight W and the prescribed configuration phi_hat.
 

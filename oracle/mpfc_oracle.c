@@ -39,13 +39,13 @@
  *  - the residual norm is sqrt(h^2 * sum over the three components of r^2),
  *    the h-weighted discrete l2 norm of App. A applied to all of r;
  *  - scheme-2 coarse operators use phi^k restricted by the same 2x2 average;
- *  - pinning (Sec. 4.4, scheme 2): mu is replaced by
+ *  - pinning (Sec. 4.6, scheme 2): mu is replaced by
  *    mu~ = mu + 2 (phi^{k+1/2} - phi_hat) W with phi^{k+1/2} = (phi^{k+1} + phi^k)/2
  *    and the weight W; taking mu~ as the unknown gives N^(2) an extra -W phi
  *    and S^(2) an extra W (phi^k - 2 phi_hat); coarse levels use W restricted
  *    by the 2x2 average, and the reported energy F gains h^2 sum W (phi - phi_hat)^2
  *    (the discrete form of the added integral);
- *  - grids whose sides are not powers of two (Sec. 4.4 uses 512 x 400) coarsen
+ *  - grids whose sides are not powers of two (Sec. 4.6 uses 512 x 400) coarsen
  *    while both sides of the next level stay even; the coarsest level may
  *    then be too large for the dense Newton solve and is instead relaxed by
  *    a fixed number of the same red-black sweeps;

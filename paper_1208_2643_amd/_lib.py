@@ -47,7 +47,7 @@ class mpfc_info(ctypes.Structure):
     _fields_ = [("energy_F", ctypes.c_double), ("energy_pseudo", ctypes.c_double),
                 ("energy_mod", ctypes.c_double), ("mass", ctypes.c_double),
                 ("residual", ctypes.c_double), ("n_cycles", ctypes.c_int),
-                ("status", ctypes.c_int), ("outer_iters", ctypes.c_int), ("pad", ctypes.c_int),
+                ("status", ctypes.c_int), ("outer_iters", ctypes.c_int), ("energy_status", ctypes.c_int),
                 ("residual_history", ctypes.POINTER(ctypes.c_double))]
 
 
@@ -92,10 +92,10 @@ SIGNATURES = {
     "mpfc_strerror": (ctypes.c_char_p, [_i]),
     "mpfc_last_error": (ctypes.c_char_p, []),
     "mpfc_version": (_i, []),
-    "mpfc_op_smooth": (_i, [_i, _i, _i, _i, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i,
-                            _i, _vp]),
-    "mpfc_op_residual": (_i, [_i, _i, _i, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                              _vp, _vp, _i, _vp]),
+    "mpfc_op_smooth": (_i, [ctypes.POINTER(mpfc_params), _i, _i, _i, _vp, _vp, _vp, _vp, _vp,
+                            _vp, _vp, _i, _vp]),
+    "mpfc_op_residual": (_i, [ctypes.POINTER(mpfc_params), _i, _i, _vp, _vp, _vp, _vp, _vp, _vp,
+                              _vp, _vp, _vp, _vp, _vp]),
     "mpfc_op_source": (_i, [ctypes.POINTER(mpfc_params), _i, _i, _vp, _vp, _vp, _vp, _vp, _vp,
                             _vp]),
     "mpfc_op_restrict": (_i, [_i, _i, _vp, _vp, _vp]),

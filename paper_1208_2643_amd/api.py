@@ -45,6 +45,7 @@ class StepInfo:
     energy_mod: float
     mass: float
     outer_iters: int
+    energy_status: int = 0   # MPFC_ENOTCONVERGED if the -1 norm's Poisson solve did not converge
 
 
 def make_opts(**kw) -> L.mpfc_opts:
@@ -111,7 +112,7 @@ class Stepper:
         nh = (info.outer_iters if self.opts.precision == L.MPFC_MIXED else info.n_cycles) + 1
         si = StepInfo(rc, info.n_cycles, info.residual, self._hist[:nh].copy(),
                       info.energy_F, info.energy_pseudo, info.energy_mod, info.mass,
-                      info.outer_iters)
+                      info.outer_iters, info.energy_status)
         return phi_np1, si
 
     def profile(self, on: bool = True):
@@ -138,7 +139,7 @@ class Stepper:
         return u.value, f.value
 
     def set_pinning(self, weight=None, phihat=None):
-        """Pinning term of Sec. 4.4 (scheme 2, FP64, Newton): weight W >= 0 and
+        """Pinning term of Sec. 4.6 (scheme 2, FP64, Newton): weight W >= 0 and
         prescribed configuration phi_hat, (n, m) float64 device tensors copied
         by the call; weight None switches it off."""
         if weight is None:
@@ -204,7 +205,8 @@ class Stepper3:
         allow = (L.MPFC_ENOTCONVERGED, L.MPFC_ENONFINITE, L.MPFC_EDIVERGED) if allow_fail else ()
         L.check(rc, allow)
         si = StepInfo(rc, info.n_cycles, info.residual, self._hist[:info.n_cycles + 1].copy(),
-                      info.energy_F, info.energy_pseudo, info.energy_mod, info.mass, 0)
+                      info.energy_F, info.energy_pseudo, info.energy_mod, info.mass, 0,
+                      info.energy_status)
         return phi_np1, si
 
     def profile(self, on: bool = True):
@@ -382,31 +384,29 @@ def run(stepper: Stepper, phi0: torch.Tensor, steps: int, record=None):
 
 
 # ---- operator-level wrappers (one V-cycle operation each) -------------------
-def coefficients(p: Params):
-    q = 1.0 if p.scheme == 1 else 2.0
-    return p.dt * p.M / (p.beta + q / p.dt), q / (p.beta + q / p.dt)
+def _at_spacing(p: Params, h):
+    """The parameters with the grid spacing of the level the operator acts on."""
+    return p if h is None else Params(p.eps, p.beta, p.M, h, p.dt, p.scheme, p.bc)
 
 
 def op_smooth(p: Params, u, f, phik=None, sweeps=1, newton=True, h=None):
     lib = L.load()
     phi, mu, ka = u
     n, m = phi.shape
-    c, _ = coefficients(p)
-    L.check(lib.mpfc_op_smooth(p.scheme, 0 if newton else 1, m, n, p.h if h is None else h, c,
-                               1.0 - p.eps, _ptr(phik), _ptr(phi), _ptr(mu), _ptr(ka),
-                               _ptr(f[0]), _ptr(f[1]), _ptr(f[2]), sweeps, p.bc, _stream()))
+    L.check(lib.mpfc_op_smooth(ctypes.byref(_at_spacing(p, h).c()),
+                               L.MPFC_NEWTON if newton else L.MPFC_PICARD, m, n, _ptr(phik),
+                               _ptr(phi), _ptr(mu), _ptr(ka), _ptr(f[0]), _ptr(f[1]), _ptr(f[2]),
+                               sweeps, _stream()))
 
 
 def op_residual(p: Params, u, f, phik=None, h=None):
     lib = L.load()
     phi, mu, ka = u
     n, m = phi.shape
-    c, _ = coefficients(p)
     r = [torch.empty_like(phi) for _ in range(3)]
-    L.check(lib.mpfc_op_residual(p.scheme, m, n, p.h if h is None else h, c, 1.0 - p.eps,
-                                 _ptr(phik), _ptr(phi), _ptr(mu), _ptr(ka), _ptr(f[0]),
-                                 _ptr(f[1]), _ptr(f[2]), _ptr(r[0]), _ptr(r[1]), _ptr(r[2]),
-                                 p.bc, _stream()))
+    L.check(lib.mpfc_op_residual(ctypes.byref(_at_spacing(p, h).c()), m, n, _ptr(phik),
+                                 _ptr(phi), _ptr(mu), _ptr(ka), _ptr(f[0]), _ptr(f[1]),
+                                 _ptr(f[2]), _ptr(r[0]), _ptr(r[1]), _ptr(r[2]), _stream()))
     return r
 
 

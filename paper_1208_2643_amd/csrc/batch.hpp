@@ -13,7 +13,7 @@
 // per-cell device functions of kernels.hpp), so a simulation's iterates do not
 // depend on what it is batched with.
 #pragma once
-#include "kernels.hpp"
+#include "step.hpp"
 #include "tiles.hpp"
 
 namespace mpfc {

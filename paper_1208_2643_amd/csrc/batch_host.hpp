@@ -89,37 +89,6 @@ struct mpfc_batch {
 
 namespace {
 
-template <class Op, bool UP, bool NEU>
-void launch_tile_batched_bc(int shape, const BatchTile<Op>* args, const BatchItem* items, int n,
-                         hipStream_t s) {
-    const dim3 grid(n), blk(256);
-    switch (shape) {
-        case 0: hipLaunchKernelGGL((k_tile_batched<Op, 64, 32, 6, UP, NEU>), grid, blk, 0, s, args, items, n); break;
-        case 1: hipLaunchKernelGGL((k_tile_batched<Op, 32, 32, 6, UP, NEU>), grid, blk, 0, s, args, items, n); break;
-        case 2: hipLaunchKernelGGL((k_tile_batched<Op, 32, 16, 6, UP, NEU>), grid, blk, 0, s, args, items, n); break;
-        case 3: hipLaunchKernelGGL((k_tile_batched<Op, 16, 16, 6, UP, NEU>), grid, blk, 0, s, args, items, n); break;
-        case 4: hipLaunchKernelGGL((k_tile_batched<Op, 64, 16, 10, UP, NEU>), grid, blk, 0, s, args, items, n); break;
-        case 5: hipLaunchKernelGGL((k_tile_batched<Op, 32, 16, 10, UP, NEU>), grid, blk, 0, s, args, items, n); break;
-        default: hipLaunchKernelGGL((k_tile_batched<Op, 16, 16, 10, UP, NEU>), grid, blk, 0, s, args, items, n); break;
-    }
-}
-
-// Batches with a Neumann member run the instantiation with the ghost rule.
-template <class Op, bool UP>
-void launch_tile_batched(bool neu, int shape, const BatchTile<Op>* args, const BatchItem* items,
-                         int n, hipStream_t s) {
-    if (neu) launch_tile_batched_bc<Op, UP, true>(shape, args, items, n, s);
-    else launch_tile_batched_bc<Op, UP, false>(shape, args, items, n, s);
-}
-
-template <class Op, int NC>
-void launch_coarse_batched(bool neu, int nsim, const BatchCoarse<Op>* args, hipStream_t s) {
-    if (neu) hipLaunchKernelGGL((k_coarse_persistent_batched<Op, CP_THREADS, NC, true>), dim3(nsim),
-                                dim3(CP_THREADS), 0, s, args);
-    else hipLaunchKernelGGL((k_coarse_persistent_batched<Op, CP_THREADS, NC, false>), dim3(nsim),
-                            dim3(CP_THREADS), 0, s, args);
-}
-
 template <int S, bool NW>
 struct BatchImpl : BatchBase {
     using Op64 = MpfcOp<double, S, NW, false>;
@@ -584,6 +553,7 @@ int mpfc_batch_step(mpfc_batch* B, const double* const* phi_n, const double* con
             I.n_cycles = B->mixed ? nouter * B->o.inner_cycles : nouter;
             I.status = code;
             I.outer_iters = B->mixed ? nouter : 0;
+            I.energy_status = MPFC_OK;  // a batch computes no energies
             I.energy_F = I.energy_pseudo = I.energy_mod = I.mass = 0.0;
             I.residual = st.acc;
             if (I.residual_history)

@@ -29,7 +29,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "kernels.hpp"
+#include "step.hpp"
 
 namespace mpfc {
 

@@ -24,8 +24,9 @@
 #include <vector>
 
 #include "../../include/mpfc.h"
-#include "kernels.hpp"
+#include "step.hpp"
 #include "poisson.hpp"
+#include "launch.hpp"
 #include "tiles.hpp"
 
 using namespace mpfc;
@@ -82,12 +83,6 @@ unsigned red_blocks(size_t total) {
     return (unsigned)(b < kRedBlocks ? b : kRedBlocks);
 }
 
-// Tile shapes (interior TX x TY, largest halo HMAX) instantiated for the
-// tiled levels.  Variant 0 serves halos up to 6 (nu <= 2), variant 1 up to 10.
-struct TileShape { int tx, ty, hmax; };
-constexpr TileShape kShapes[] = {{64, 32, 6},  {32, 32, 6},  {32, 16, 6}, {16, 16, 6},
-                                 {64, 16, 10}, {32, 16, 10}, {16, 16, 10}};
-constexpr int kNumShapes = 7;
 // Launch kinds that carry a tuned shape per level.
 enum { SH_DN = 0, SH_UP = 1, SH_DN32 = 2, SH_UP32 = 3, SH_PDN = 4, SH_PUP = 5, SH_KINDS = 6 };
 
@@ -132,7 +127,7 @@ struct mpfc_ctx {
     double* phist = nullptr;
     double* acc = nullptr;      // reduction results
     double* part = nullptr;     // per-block partial sums of the reductions
-    bool pinned = false;        // pinning term of Sec. 4.4 active
+    bool pinned = false;        // pinning term of Sec. 4.6 active
     double* pin_mem = nullptr;  // weights of every level, then phi_hat (own allocation)
     double* phihat = nullptr;
     int nparts = 0;
@@ -206,74 +201,6 @@ Fields<double> finest_fields(const mpfc_ctx* C) {
     F.base = nullptr;
     F.pin = C->pinned ? lv.pin : nullptr;
     return F;
-}
-
-// ---- launches -----------------------------------------------------------------------
-template <class Op, bool UP, bool NEU>
-void launch_tile_bc(const Op& op, const TileArgs<typename Op::real>& A, int shape,
-                    const CycleState* stop, hipStream_t s) {
-    const dim3 grid(A.g.m / A.tx, A.g.n / A.ty), blk(256);
-    switch (shape) {
-        case 0: hipLaunchKernelGGL((k_tile<Op, 64, 32, 6, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
-        case 1: hipLaunchKernelGGL((k_tile<Op, 32, 32, 6, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
-        case 2: hipLaunchKernelGGL((k_tile<Op, 32, 16, 6, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
-        case 3: hipLaunchKernelGGL((k_tile<Op, 16, 16, 6, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
-        case 4: hipLaunchKernelGGL((k_tile<Op, 64, 16, 10, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
-        case 5: hipLaunchKernelGGL((k_tile<Op, 32, 16, 10, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
-        default: hipLaunchKernelGGL((k_tile<Op, 16, 16, 10, UP, NEU>), grid, blk, 0, s, op, A, stop); break;
-    }
-}
-
-// Grids with a side that is not a power of two: the general-index
-// instantiation, shapes 0 and 2 only (FP64; halos up to 6).
-constexpr bool gen_shape(int k) { return k == 0 || k == 2; }
-template <class Op, bool UP, bool NEU>
-void launch_tile_gen(const Op& op, const TileArgs<typename Op::real>& A, int shape,
-                     const CycleState* stop, hipStream_t s) {
-    const dim3 grid(A.g.m / A.tx, A.g.n / A.ty), blk(256);
-    if (shape == 2)
-        hipLaunchKernelGGL((k_tile<Op, 32, 16, 6, UP, NEU, true>), grid, blk, 0, s, op, A, stop);
-    else
-        hipLaunchKernelGGL((k_tile<Op, 64, 32, 6, UP, NEU, true>), grid, blk, 0, s, op, A, stop);
-}
-
-// Periodic grids run the instantiation without the Neumann ghost handling.
-template <class Op, bool UP>
-void launch_tile(const Op& op, const TileArgs<typename Op::real>& A, int shape,
-                 const CycleState* stop, hipStream_t s) {
-    if constexpr (std::is_same<typename Op::real, double>::value) {
-        if (general_grid(A.g)) {
-            if (A.g.bc) launch_tile_gen<Op, UP, true>(op, A, shape, stop, s);
-            else launch_tile_gen<Op, UP, false>(op, A, shape, stop, s);
-            return;
-        }
-    }
-    if (A.g.bc) launch_tile_bc<Op, UP, true>(op, A, shape, stop, s);
-    else launch_tile_bc<Op, UP, false>(op, A, shape, stop, s);
-}
-
-// Coarsest level of a general grid (MPFC system: red-black sweeps).
-template <class Op>
-void launch_coarsest_gen(const Op& op, const CoarseArgs<typename Op::real>& A,
-                         const CycleState* stop, hipStream_t s) {
-    const dim3 g1(1), blk(CG_THREADS);
-    if (A.geo.bc) hipLaunchKernelGGL((k_coarsest_sweeps<Op, true>), g1, blk, 0, s, op, A, stop);
-    else hipLaunchKernelGGL((k_coarsest_sweeps<Op, false>), g1, blk, 0, s, op, A, stop);
-}
-
-// The persistent coarse-level kernel for the coarsest grid's cell count (4:
-// 2x2, else 2x4 or 4x2) and the grid's boundary conditions.
-template <class Op>
-void launch_coarse(const Op& op, const CoarseArgs<typename Op::real>& A, bool four,
-                   const CycleState* stop, hipStream_t s) {
-    const dim3 g1(1), blk(CP_THREADS);
-    if (A.geo.bc) {
-        if (four) hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4, true>), g1, blk, 0, s, op, A, stop);
-        else hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 8, true>), g1, blk, 0, s, op, A, stop);
-    } else {
-        if (four) hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 4, false>), g1, blk, 0, s, op, A, stop);
-        else hipLaunchKernelGGL((k_coarse_persistent<Op, CP_THREADS, 8, false>), g1, blk, 0, s, op, A, stop);
-    }
 }
 
 // First shape whose halo allowance covers H (used until the autotuner has run).
@@ -638,7 +565,7 @@ void vcycle_mpfc(mpfc_ctx* C, hipStream_t s) {
     if (C->p.scheme == 1) {
         if (nw) vcycle_mpfc_t<MpfcOp<double, 1, true, false>>(C, s);
         else vcycle_mpfc_t<MpfcOp<double, 1, false, false>>(C, s);
-    } else if (C->pinned) {  // Sec. 4.4 pinning: scheme 2, Newton (checked when set)
+    } else if (C->pinned) {  // Sec. 4.6 pinning: scheme 2, Newton (checked when set)
         vcycle_mpfc_t<MpfcOp<double, 2, true, false, true>>(C, s);
     } else {
         if (nw) vcycle_mpfc_t<MpfcOp<double, 2, true, false>>(C, s);
@@ -686,8 +613,7 @@ void vcycle_poisson(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) 
         A.complete_top = Lp > 0;
         A.G = C->G;
         if (C->gen)
-            hipLaunchKernelGGL((k_coarsest_poisson<double>), dim3(1), dim3(CG_THREADS), 0, s,
-                               make_op<Op>(C, top), A, stop);
+            launch_coarsest_poisson(make_op<Op>(C, top), A, stop, s);
         else
             launch_coarse<Op>(make_op<Op>(C, top), A, true, stop, s);
     }
@@ -968,9 +894,19 @@ void spectral_factors(int m, int n, double h, int bc, std::vector<double>& G) {
             il[(size_t)l * m + k] = (l == 0 && k == 0) ? 0.0 : 1.0 / (lx[k] + ly[l]);
 }
 
-int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
+// Coefficients of the decoupled schemes (eqs. discrete_1_a, discrete_2_a):
+// with q = 1 (first-order scheme) or 2 (second-order scheme),
+// c = s M / (beta + q/s) on Lap mu, and d = q / (beta + q/s) on psi^k in S^(1).
+void scheme_coefficients(const mpfc_params* p, double& c, double& d) {
+    const double q = p->scheme == 1 ? 1.0 : 2.0;
+    c = p->dt * p->M / (p->beta + q / p->dt);
+    d = q / (p->beta + q / p->dt);
+}
+
+// Physical parameters alone (shared by the context and the operator-level
+// entry points).
+int validate_params(const mpfc_params* p) {
     if (!p) return fail(MPFC_EINVAL, "params is NULL");
-    if (!o) return fail(MPFC_EINVAL, "opts is NULL");
     if (!(p->scheme == 1 || p->scheme == 2)) return fail(MPFC_EINVAL, "scheme must be 1 or 2");
     if (!(p->h > 0) || !std::isfinite(p->h)) return fail(MPFC_EINVAL, "h must be > 0");
     if (!(p->dt > 0) || !std::isfinite(p->dt)) return fail(MPFC_EINVAL, "dt must be > 0");
@@ -979,6 +915,26 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
     if (!(p->eps <= 1.0) || !std::isfinite(p->eps)) return fail(MPFC_EINVAL, "eps must be <= 1");
     if (p->bc < 0 || p->bc > (MPFC_BC_NEUMANN_X | MPFC_BC_NEUMANN_Y))
         return fail(MPFC_EINVAL, "bc must combine MPFC_BC_NEUMANN_X and MPFC_BC_NEUMANN_Y bits");
+    return MPFC_OK;
+}
+
+// Operator constants of a grid of spacing p->h (LevelOp of the tile kernels).
+LevelOp<double> params_op(const mpfc_params* p) {
+    double c, d;
+    scheme_coefficients(p, c, d);
+    const double alpha = 1.0 - p->eps;
+    LevelOp<double> op;
+    op.ih2 = 1.0 / (p->h * p->h);
+    op.c = c;
+    op.al = p->scheme == 1 ? alpha : 0.5 * alpha;
+    op.e = p->scheme == 1 ? 1.0 : 0.5;
+    return op;
+}
+
+int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
+    int prc = validate_params(p);
+    if (prc) return prc;
+    if (!o) return fail(MPFC_EINVAL, "opts is NULL");
     const bool gen = !(is_pow2(m) && is_pow2(n));
     if (m < 2 || n < 2) return fail(MPFC_EINVAL, "m and n must be >= 2");
     if (gen && (m % 4 != 0 || n % 4 != 0))
@@ -1329,9 +1285,7 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
     C->m = m; C->n = n; C->p = *p; C->o = *o;
     C->stream = (hipStream_t)stream;
     C->alpha = 1.0 - p->eps;
-    const double q = p->scheme == 1 ? 1.0 : 2.0;
-    C->c = p->dt * p->M / (p->beta + q / p->dt);
-    C->d = q / (p->beta + q / p->dt);
+    scheme_coefficients(p, C->c, C->d);
     const char* ng = std::getenv("MPFC_NO_GRAPH");
     C->use_graph = !(ng && ng[0] == '1');
     C->inner_cycles = o->inner_cycles;
@@ -1374,7 +1328,9 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
             const size_t Nl = (size_t)lv.m * lv.n;
             for (int f = 0; f < 3; ++f) {
                 lv.u[0][f] = take(Nl);
-                lv.u[1][f] = (l < C->Lp || (l == 0 && mixed)) ? take(Nl) : nullptr;
+                // level 0 always has copy 1: mixed precision and the learned
+                // guess's candidate use it even when the finest level is untiled
+                lv.u[1][f] = (l < C->Lp || l == 0) ? take(Nl) : nullptr;
                 lv.f[f] = take(Nl);
                 lv.v[f] = l > 0 ? take(Nl) : nullptr;
                 lv.rr[f] = l > 0 ? take(Nl) : nullptr;
@@ -1537,15 +1493,18 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     HIP_TRY(hipGetLastError());
     const int rc = status_code(fin.status);
     double en[4] = {0, 0, 0, 0};
+    int energy_status = MPFC_OK;
     if (C->o.energy) {
         // the history rides on the energies' readback (one wait for both)
         const int erc = compute_energies(C, phi, phi_n, psi, mu, en, info ? fin.count : 0);
         if (erc && erc != MPFC_ENOTCONVERGED) return erc;
+        energy_status = erc;
     }
     if (info) {
         info->n_cycles = ncyc;
         info->status = rc;
         info->outer_iters = mixed ? nouter : 0;
+        info->energy_status = energy_status;
         info->energy_F = en[0];
         info->energy_pseudo = en[1];
         info->energy_mod = en[2];
@@ -1622,27 +1581,41 @@ int mpfc_energies(mpfc_ctx* C, const double* phi, const double* phi_prev, const 
 // Red-black sweeps through the same fused tile kernel the V-cycle uses (down
 // direction without the restriction outputs); a scratch copy keeps the
 // ping-pong between launches.
-int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double c, double alpha,
-                   const double* phik, double* phi, double* mu, double* ka, const double* f1,
-                   const double* f2, const double* f3, int sweeps, int bc, void* stream) {
-    if (!(scheme == 1 || scheme == 2) || m < 2 || n < 2 || (m & 1) || (n & 1) ||
-        sweeps < 0 || !(h > 0) || !phi || !mu || !ka || !f1 || !f2 || !f3 ||
-        (scheme == 2 && !phik) || bc < 0 || bc > 3)
-        return fail(MPFC_EINVAL, "mpfc_op_smooth: bad arguments");
-    if (m < 4 || n < 4) return fail(MPFC_EINVAL, "mpfc_op_smooth: m, n >= 4");
-    hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+int op_smooth_check(const mpfc_params* p, int linearization, int m, int n, const double* phik,
+                    const double* phi, const double* mu, const double* ka, const double* f1,
+                    const double* f2, const double* f3, int sweeps, const char* name) {
+    int rc = validate_params(p);
+    if (rc) return rc;
+    if (m < 4 || n < 4 || (m & 1) || (n & 1) || sweeps < 0 || !phi || !mu || !ka || !f1 ||
+        !f2 || !f3 || (p->scheme == 2 && !phik) ||
+        !(linearization == MPFC_NEWTON || linearization == MPFC_PICARD))
+        return fail(MPFC_EINVAL, std::string(name) + ": bad arguments");
+    return MPFC_OK;
+}
+
+// Doubles of scratch the sweeps need: a copy of u (3 m n) and one (m/2)(n/2)
+// array that takes the down launch's restriction outputs, which are discarded.
+size_t op_smooth_scratch(int m, int n) {
     const size_t N = (size_t)m * n;
-    double* tmp = nullptr;
-    HIP_TRY(hipMalloc(&tmp, 3 * N * sizeof(double) + 3 * (N / 4 + 1) * sizeof(double)));
+    return 3 * N + N / 4 + 1;
+}
+
+// The passes, with `tmp` (op_smooth_scratch(m, n) doubles of device memory)
+// as scratch; ends with a wait on the stream.
+int op_smooth_run(const mpfc_params* p, int linearization, int m, int n, const double* phik,
+                  double* phi, double* mu, double* ka, const double* f1, const double* f2,
+                  const double* f3, int sweeps, hipStream_t s, double* tmp) {
+    const size_t N = (size_t)m * n;
     double* cz = tmp + 3 * N;  // coarse outputs land here and are discarded
     double* a[3] = {phi, mu, ka};
     double* b[3] = {tmp, tmp + N, tmp + 2 * N};
-    LevelOp<double> lop;
-    lop.ih2 = 1.0 / (h * h); lop.c = c;
-    lop.al = scheme == 1 ? alpha : 0.5 * alpha;
-    lop.e = scheme == 1 ? 1.0 : 0.5;
+    const LevelOp<double> lop = params_op(p);
     Level lv;
-    lv.m = m; lv.n = n; lv.g = make_grid(m, n, bc);
+    lv.m = m; lv.n = n; lv.g = make_grid(m, n, p->bc);
     int done = 0;
     while (done < sweeps) {
         const int k = (sweeps - done) >= 2 ? 2 : 1;
@@ -1659,7 +1632,7 @@ int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double
         T.complete_f = 0;
         T.norm = 0;
         tile_dims(lv, 0, T.tx, T.ty);
-        if (scheme == 1) {
+        if (p->scheme == 1) {
             MpfcOp<double, 1, true, false> on{lop};
             MpfcOp<double, 1, false, false> op{lop};
             if (linearization == MPFC_NEWTON) launch_tile<decltype(on), false>(on, T, 0, nullptr, s);
@@ -1680,28 +1653,44 @@ int mpfc_op_smooth(int scheme, int linearization, int m, int n, double h, double
         }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(hipFree(tmp));
     return MPFC_OK;
 }
 
-int mpfc_op_residual(int scheme, int m, int n, double h, double c, double alpha,
-                     const double* phik, const double* phi, const double* mu, const double* ka,
-                     const double* f1, const double* f2, const double* f3, double* r1, double* r2,
-                     double* r3, int bc, void* stream) {
-    if (!(scheme == 1 || scheme == 2) || m < 2 || n < 2 || (m & 1) || (n & 1) ||
-        !(h > 0) || !phi || !mu || !ka || !f1 || !f2 || !f3 || !r1 || !r2 || !r3 ||
-        (scheme == 2 && !phik) || bc < 0 || bc > 3)
+}  // namespace
+
+extern "C" {
+
+int mpfc_op_smooth(const mpfc_params* p, int linearization, int m, int n, const double* phik,
+                   double* phi, double* mu, double* ka, const double* f1, const double* f2,
+                   const double* f3, int sweeps, void* stream) {
+    int rc = op_smooth_check(p, linearization, m, n, phik, phi, mu, ka, f1, f2, f3, sweeps,
+                             "mpfc_op_smooth");
+    if (rc) return rc;
+    double* tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, op_smooth_scratch(m, n) * sizeof(double)));
+    rc = op_smooth_run(p, linearization, m, n, phik, phi, mu, ka, f1, f2, f3, sweeps,
+                       (hipStream_t)stream, tmp);
+    const hipError_t fe = hipFree(tmp);
+    if (rc) return rc;
+    if (fe != hipSuccess) return fail(MPFC_EHIP, std::string("hipFree: ") + hipGetErrorString(fe));
+    return MPFC_OK;
+}
+
+int mpfc_op_residual(const mpfc_params* p, int m, int n, const double* phik, const double* phi,
+                     const double* mu, const double* ka, const double* f1, const double* f2,
+                     const double* f3, double* r1, double* r2, double* r3, void* stream) {
+    int rc = validate_params(p);
+    if (rc) return rc;
+    if (m < 2 || n < 2 || (m & 1) || (n & 1) || !phi || !mu || !ka || !f1 || !f2 || !f3 ||
+        !r1 || !r2 || !r3 || (p->scheme == 2 && !phik))
         return fail(MPFC_EINVAL, "mpfc_op_residual: bad arguments");
     Fields<double> F;
     F.phi = const_cast<double*>(phi); F.mu = const_cast<double*>(mu); F.ka = const_cast<double*>(ka);
     F.f1 = f1; F.f2 = f2; F.f3 = f3; F.phik = phik; F.base = nullptr;
-    LevelOp<double> op;
-    op.ih2 = 1.0 / (h * h); op.c = c;
-    op.al = scheme == 1 ? alpha : 0.5 * alpha;
-    op.e = scheme == 1 ? 1.0 : 0.5;
-    const Grid g = make_grid(m, n, bc);
+    const LevelOp<double> op = params_op(p);
+    const Grid g = make_grid(m, n, p->bc);
     hipStream_t s = (hipStream_t)stream;
-    if (scheme == 1)
+    if (p->scheme == 1)
         hipLaunchKernelGGL((k_residual_field<double, 1, false>), grid2(m, n), B2, 0, s, F, op, g,
                            r1, r2, r3);
     else
@@ -1713,13 +1702,13 @@ int mpfc_op_residual(int scheme, int m, int n, double h, double c, double alpha,
 
 int mpfc_op_source(const mpfc_params* p, int m, int n, const double* phik, const double* phikm1,
                    const double* psik, double* S1, double* S2, double* S3, void* stream) {
-    if (!p || !(p->scheme == 1 || p->scheme == 2) || m < 2 || n < 2 || (m & 1) || (n & 1) ||
-        !(p->h > 0) || !(p->dt > 0) || !phik || !psik || !S1 || !S2 || !S3 ||
-        p->bc < 0 || p->bc > 3)
+    int rc = validate_params(p);
+    if (rc) return rc;
+    if (m < 2 || n < 2 || (m & 1) || (n & 1) || !phik || !psik || !S1 || !S2 || !S3)
         return fail(MPFC_EINVAL, "mpfc_op_source: bad arguments");
     if (!phikm1) phikm1 = phik;
-    const double q = p->scheme == 1 ? 1.0 : 2.0;
-    const double d = q / (p->beta + q / p->dt);
+    double c, d;
+    scheme_coefficients(p, c, d);
     const Grid g = make_grid(m, n, p->bc);
     hipStream_t s = (hipStream_t)stream;
     if (p->scheme == 1)

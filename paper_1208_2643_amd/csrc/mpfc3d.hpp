@@ -19,7 +19,7 @@
 // XCD-contiguous order (xcd_item), so the neighbouring rows and planes a
 // workgroup reads are mostly in its own XCD's L2.
 #pragma once
-#include "kernels.hpp"
+#include "step.hpp"
 #include "tiles.hpp"
 
 namespace mpfc {

@@ -572,6 +572,7 @@ int mpfc3d_step(mpfc3d_ctx* C, const double* phi_n, const double* phi_nm1, doubl
         info->residual = stc.acc;
         info->n_cycles = cycles;
         info->outer_iters = 0;
+        info->energy_status = erc;
         if (info->residual_history && stc.count > 0)
             HIP_TRY(hipMemcpy(info->residual_history, C->hist, sizeof(double) * stc.count,
                               hipMemcpyDeviceToHost));

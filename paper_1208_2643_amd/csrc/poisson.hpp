@@ -12,7 +12,7 @@
 // device-wide fences); k_partials_sum adds them in a fixed order, so all sums
 // are deterministic.
 #pragma once
-#include "kernels.hpp"
+#include "step.hpp"
 
 namespace mpfc {
 
@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(NT) k_p_rhs_resid(Grid g, double ih2,
 //   3: sum (Lap_h phi)^2, 4: sum phi,
 //   5: sum over edges of (difference of phi - phi_prev)^2,
 //   6: sum (psi - mean psi) w,
-//   7: sum W (phi - phi_hat)^2 (pinning, Sec. 4.4; 0 without pinning).
+//   7: sum W (phi - phi_hat)^2 (pinning, Sec. 4.6; 0 without pinning).
 template <int NT>
 __global__ void __launch_bounds__(NT) k_energy_terms(Grid g, double ih2,
                                                      const double* __restrict__ phi,
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(NT) k_energy_terms(Grid g, double ih2,
             a[5] += de * de + dn * dn;
         }
         a[6] += b[q] * w[q];
-        if (pin) {  // pinning energy sum W (phi - phi_hat)^2 (Sec. 4.4)
+        if (pin) {  // pinning energy sum W (phi - phi_hat)^2 (Sec. 4.6)
             const double dp = x - phihat[q];
             a[7] += pin[q] * dp * dp;
         }

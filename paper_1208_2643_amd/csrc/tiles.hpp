@@ -38,7 +38,7 @@ namespace mpfc {
 // Cell operators.  ns[f] is the sum of the four neighbours of field f.
 
 // MPFC system N(u) = f (App. B.1 / B.2), optionally in correction (DEFECT) form.
-// PIN: the pinning of Sec. 4.4 adds the per-cell weight w to the coefficient
+// PIN: the pinning of Sec. 4.6 adds the per-cell weight w to the coefficient
 // of phi in N^(2) (the unknown mu is mu~); w = 0 otherwise.
 template <typename T, int SCHEME, bool NEWTON, bool DEFECT, bool PIN = false>
 struct MpfcOp {

@@ -23,7 +23,7 @@ Workloads (each named by what it is):
   beta drawn per simulation.
 * ``noise3``: the three-dimensional workload, 0.07 + U[-0.05, 0.05] on an
   m x n x l grid.
-* ``strained_crystal``: the sheared-crystal set-up of Sec. 4.4 on its 512 x 400
+* ``strained_crystal``: the sheared-crystal set-up of Sec. 4.6 on its 512 x 400
   grid: a band of 20 atomic layers of the one-mode profile (solid density
   phi_s, amplitude A(phi_s, eps)) in a liquid of density phi_l, a pinning
   weight of 2 in strips of height pi around the bottom and top rows of atoms,
@@ -116,7 +116,7 @@ def strained_crystal(m: int = 512, n: int = 400, h: float = 4 * math.pi / (16 * 
                      eps: float = 0.6, phi_s: float = 0.395, phi_l: float = 0.57,
                      layers: int = 20, weight: float = 2.0, shear: float = 0.04,
                      seed: int = 6, amp: float = 1e-3):
-    """(phi0, W, phi_hat) of the sheared-crystal test (Sec. 4.4).
+    """(phi0, W, phi_hat) of the sheared-crystal test (Sec. 4.6).
 
     The crystal is phi_s + A (cos(q x) cos(q y / sqrt3) - cos(2 q y / sqrt3) / 2)
     with q = sqrt(3)/2 and A = 4 phi_s / 5 + (4/15) sqrt(15 eps - 36 phi_s^2)

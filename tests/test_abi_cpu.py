@@ -198,3 +198,26 @@ def test_3d_unsupported_configurations_rejected(kw):
                                   None) == L.MPFC_EINVAL
     assert ctx.value is None
 
+
+
+def test_operator_entry_points_validate_params_on_the_host():
+    """The operator-level calls form the scheme's coefficients from mpfc_params
+    in the library and reject invalid parameters before any HIP call."""
+    lib = L.load()
+    p, _ = good()
+    z = ctypes.c_void_p(0)
+    for field, value in (("dt", -1.0), ("h", 0.0), ("scheme", 5), ("bc", 9)):
+        q = L.mpfc_params(p.eps, p.beta, p.M, p.h, p.dt, p.scheme, p.bc)
+        setattr(q, field, value)
+        assert lib.mpfc_op_smooth(ctypes.byref(q), 0, 64, 64, z, z, z, z, z, z, z, 1, None) \
+            == L.MPFC_EINVAL, field
+        assert lib.mpfc_op_residual(ctypes.byref(q), 64, 64, z, z, z, z, z, z, z, z, z, z,
+                                    None) == L.MPFC_EINVAL, field
+        assert lib.mpfc_op_source(ctypes.byref(q), 64, 64, z, z, z, z, z, z, None) \
+            == L.MPFC_EINVAL, field
+    assert lib.mpfc_op_smooth(None, 0, 64, 64, z, z, z, z, z, z, z, 1, None) == L.MPFC_EINVAL
+    # valid parameters, missing arrays: still rejected on the host
+    assert lib.mpfc_op_smooth(ctypes.byref(p), 0, 64, 64, z, z, z, z, z, z, z, 1, None) \
+        == L.MPFC_EINVAL
+    assert lib.mpfc_op_smooth(ctypes.byref(p), 7, 64, 64, z, z, z, z, z, z, z, 1, None) \
+        == L.MPFC_EINVAL

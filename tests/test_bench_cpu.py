@@ -58,7 +58,7 @@ def test_source_hash_ignores_comments_not_code(tmp_path):
 
 
 def test_measured_traffic_covers_every_tile_shape():
-    with open(os.path.join(CSRC, "mpfc.hip"), encoding="utf-8") as fh:
+    with open(os.path.join(CSRC, "launch.hpp"), encoding="utf-8") as fh:
         text = fh.read()
     body = re.search(r"kShapes\[\]\s*=\s*\{(.*?)\};", text, re.S).group(1)
     labels = {f"{a}x{b}/{c}" for a, b, c in re.findall(r"\{(\d+),\s*(\d+),\s*(\d+)\}", body)}

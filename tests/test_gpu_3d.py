@@ -147,11 +147,15 @@ def test_128_cubed_mass_and_energy():
     st.close()
 
 
+@pytest.mark.timeout(300)
 def test_128_cubed_step_matches_oracle():
     """The benchmark's configuration at its full size (128^3, h = pi/4, dt =
     0.05, scheme 2, the bench's seeded initial data): one step, element by
-    element against the oracle (about 40 s on one CPU thread; the energies are
-    checked against the oracle on 32^3 and 64^3)."""
+    element against the oracle solved to 1e-12 (about a minute on one CPU
+    thread; the energies are checked against the oracle on 32^3 and 64^3).
+    Bars as in two dimensions: phi 1e-10; mu 1e-9; psi = (2/s)(phi^{k+1} -
+    phi^k) - psi^k scales the error of phi by 2/s = 40 against a much smaller
+    field, 1e-8."""
     m = n = l = 128
     po, pg = both(h=math.pi / 4)
     phi0 = field3(m, n, l, 7)
@@ -159,12 +163,15 @@ def test_128_cubed_step_matches_oracle():
     psi = torch.zeros(l, n, m, dtype=torch.float64, device=DEV)
     mu = torch.empty_like(psi)
     phi_g, info = st.step(dev(phi0), dev(phi0), psi, mu=mu)
-    r = O.step3(po, phi0, phi0, np.zeros_like(phi0), tol=1e-11, max_cycles=200, coarse_sweeps=2,
+    r = O.step3(po, phi0, phi0, np.zeros_like(phi0), tol=1e-12, max_cycles=200, coarse_sweeps=2,
                 energy=False)
     assert r.cycles > 0 and info.status == 0
-    assert rel_l2(host(phi_g), r.phi) <= 1e-9
-    assert rel_l2(host(mu), r.mu) <= 1e-8
-    assert rel_l2(host(psi), r.psi) <= 1e-6
+    e_phi, e_mu, e_psi = (rel_l2(host(phi_g), r.phi), rel_l2(host(mu), r.mu),
+                          rel_l2(host(psi), r.psi))
+    print(f"\n128^3 step: rel L2 phi {e_phi:.2e}, mu {e_mu:.2e}, psi {e_psi:.2e}")
+    assert e_phi <= 1e-10
+    assert e_mu <= 1e-9
+    assert e_psi <= 1e-8
     h3 = (math.pi / 4) ** 3
     assert info.mass == pytest.approx(h3 * float(r.phi.sum()), rel=1e-12)
     st.close()

@@ -197,3 +197,27 @@ def test_trained_network_gain():
     assert sum(i.n_cycles for i in ic) <= sum(i.n_cycles for i in ie)
     assert used >= 35 and used + fb == 40
     assert rel(pc, pe) < 1e-9
+
+
+@pytest.mark.parametrize("m,n", [(16, 16), (32, 32), (16, 32)])
+def test_learned_guess_on_untiled_grids(m, n):
+    """Grids of at most 32 x 32 cells have no tiled level; the learned
+    candidate still has its own copy of the finest level.  The steps agree
+    with the extrapolated steps to the solver tolerance (the solution does not
+    depend on the guess) and each starts from the learned or the extrapolated
+    guess."""
+    from paper_1208_2643_amd import guess_net
+    p = api.Params(**PARAMS)
+    phi0 = I.noise(m, n, mean=0.07, amp=0.05, seed=11)
+    out = {}
+    for guess in (L.MPFC_GUESS_EXTRAP, L.MPFC_GUESS_CNN):
+        st = api.Stepper(m, n, p, energy=0, guess=guess, tol=1e-11)
+        if guess == L.MPFC_GUESS_CNN:
+            st.load_cnn(guess_net.load())
+        phi, _, _, infos = api.run(st, dev(phi0), 4)
+        assert all(i.status == 0 for i in infos)
+        out[guess] = host(phi)
+        if guess == L.MPFC_GUESS_CNN:
+            used, fb = st.cnn_counts()
+            assert used + fb == 4
+    assert rel(out[L.MPFC_GUESS_CNN], out[L.MPFC_GUESS_EXTRAP]) < 1e-10

@@ -1,5 +1,5 @@
 """Parity of the HIP library with the CPU oracle on grids whose sides are not
-powers of two (Sec. 4.4 runs on 512 x 400).
+powers of two (Sec. 4.6 runs on 512 x 400).
 
 Both sides coarsen while both sides of the next level stay even and relax
 the coarsest level by the same number of red-black sweeps, so single
@@ -116,7 +116,7 @@ def test_one_cycle_picard_and_pinning_match_oracle():
 @pytest.mark.parametrize("nu", [(1, 0), (0, 1), (1, 1), (2, 1)])
 def test_other_cycles_match_oracle(nu):
     """V(nu1, nu2) with fewer smoothing passes (the fastest cycles for the
-    Sec. 4.4 parameters), pinned as in that workload."""
+    Sec. 4.6 parameters), pinned as in that workload."""
     got, ref, info, hist = one_cycle(200, 120, nu=nu, pin=True)
     for a, b in zip(got, ref):
         assert relmax(a, b) <= 1e-12
@@ -178,7 +178,7 @@ def test_energies_of_a_state_match_oracle():
 
 
 def test_full_size_512x400_step():
-    """Sec. 4.4's grid at the cycle test's parameters: one step from the
+    """Sec. 4.6's grid at the cycle test's parameters: one step from the
     crystallites workload, to 1e-10, against the oracle at 1e-12."""
     m, n = 512, 400
     po, pg = both()
@@ -194,7 +194,7 @@ def test_full_size_512x400_step():
 
 
 def test_sheared_crystal_sec44_one_cycle_full_size():
-    """The Sec. 4.4 workload itself (eps 0.6, M = 15^2, h = 4 pi / (16 sqrt 3),
+    """The Sec. 4.6 workload itself (eps 0.6, M = 15^2, h = 4 pi / (16 sqrt 3),
     s = 0.025 h^2, beta 0.2, pinning strips, 512 x 400): one V-cycle element
     by element."""
     m, n = 512, 400

@@ -1,5 +1,5 @@
 """Parity of the HIP library with the CPU oracle under homogeneous Neumann and
-mixed periodic-Neumann boundary conditions (App. A, eqs. h-n-bcs; Sec. 4.3
+mixed periodic-Neumann boundary conditions (App. A, eqs. h-n-bcs; Sec. 4.5
 runs periodic in x and Neumann in y).
 
 Operator level on the same seeded inputs, element by element; one whole
@@ -228,7 +228,7 @@ def test_mixed_precision_matches_fp64_oracle(bc):
 
 
 def test_full_size_1024_periodic_x_neumann_y():
-    """One step of the 1024^2 workload with Sec. 4.3's boundary conditions
+    """One step of the 1024^2 workload with Sec. 4.5's boundary conditions
     (periodic in x, Neumann in y), in the benchmark's launch configuration,
     against the oracle."""
     N = 1024

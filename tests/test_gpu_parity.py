@@ -131,6 +131,7 @@ def test_scheme1_64_ten_steps():
     assert rel_l2(pg_, po_) <= 1e-10
     assert rel_l2(sg, so) <= 1e-8   # psi = (phi^{k+1} - phi^k)/s amplifies by 1/s
     for i, r in zip(infos, res):
+        assert i.energy_status == 0  # the -1 norm's Poisson solve converged
         assert abs(i.energy_pseudo - r.energies[1]) <= 1e-9 * abs(r.energies[1])
         assert abs(i.mass - r.energies[3]) <= 1e-12 * abs(r.energies[3])
 
@@ -145,6 +146,7 @@ def test_scheme2_crystallites(N):
     assert rel_l2(pg_, po_) <= 1e-10
     assert rel_l2(sg, so) <= 1e-8
     for i, r in zip(infos, res):
+        assert i.energy_status == 0
         assert abs(i.energy_mod - r.energies[2]) <= 1e-9 * abs(r.energies[2])
 
 
@@ -174,7 +176,7 @@ def test_full_size_single_step_1024():
     psi = torch.zeros(N, N, dtype=torch.float64, device=DEV)
     phi_g, info = st.step(dev(phi0), dev(phi0), psi)
     r = O.step(po, phi0, phi0, np.zeros_like(phi0), tol=1e-12, max_cycles=100)
-    assert r.cycles > 0 and info.status == 0
+    assert r.cycles > 0 and info.status == 0 and info.energy_status == 0
     assert rel_l2(host(phi_g), r.phi) <= 1e-10
     assert abs(info.energy_mod - r.energies[2]) <= 1e-9 * abs(r.energies[2])
 
@@ -208,6 +210,7 @@ def test_mass_and_energy_invariants_gpu(scheme):
     key = "energy_pseudo" if scheme == 1 else "energy_mod"
     e = [getattr(i, key) for i in infos]
     for i in infos:
+        assert i.energy_status == 0
         assert abs(i.mass - mass0) <= 1e-10 * abs(mass0)
     assert all(b <= a + 1e-12 * abs(a) for a, b in zip(e, e[1:]))
     assert abs(host(psi).mean()) <= 1e-10

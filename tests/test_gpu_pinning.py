@@ -1,5 +1,5 @@
 """Parity of the HIP library with the CPU oracle for the pinning term of
-Sec. 4.4 (second-order scheme): mu~ = mu + 2 (phi^{k+1/2} - phi_hat) W.
+Sec. 4.6 (second-order scheme): mu~ = mu + 2 (phi^{k+1/2} - phi_hat) W.
 
 Whole steps (phi, mu~, psi and the energies, whose F includes the pinning
 energy) and one V-cycle element by element, on periodic and mixed
@@ -51,7 +51,7 @@ def both(bc=0, **kw):
 
 
 def pinning(m, n, seed, phi0):
-    """Weight 2 in strips of 4 rows at the top and bottom (as Sec. 4.4's
+    """Weight 2 in strips of 4 rows at the top and bottom (as Sec. 4.6's
     horizontal strips) plus a random interior patch; phi_hat a shifted copy of
     the initial field."""
     W = np.zeros((n, m))

@@ -1,4 +1,4 @@
-"""Pins of the oracle on grids whose sides are not powers of two (Sec. 4.4
+"""Pins of the oracle on grids whose sides are not powers of two (Sec. 4.6
 runs on 512 x 400).  Such a grid is coarsened while both sides of the next
 level stay even, and its coarsest level is either solved by dense Newton or
 relaxed by a fixed number of red-black sweeps (coarse_sweeps).
@@ -142,7 +142,7 @@ def test_general_grid_steps_conserve_mass_and_dissipate_energy(bc):
 
 
 def test_sheared_crystal_input_recipe():
-    """The Sec. 4.4 set-up: band of 20 rows of atoms, pinning strips of
+    """The Sec. 4.6 set-up: band of 20 rows of atoms, pinning strips of
     weight 2 and height pi at its bottom and top rows, phi_hat shifted by 4 %
     of 2 pi at the bottom only."""
     phi, W, hat = I.strained_crystal()

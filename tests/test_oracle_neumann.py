@@ -1,5 +1,5 @@
 """Pins of the oracle's homogeneous Neumann and mixed periodic-Neumann
-boundary conditions (App. A, eqs. h-n-bcs; Sec. 4.3 uses periodic in x and
+boundary conditions (App. A, eqs. h-n-bcs; Sec. 4.5 uses periodic in x and
 Neumann in y).
 
 Two references that do not go through the Neumann code path:

@@ -1,4 +1,4 @@
-"""Pins of the oracle's pinning term (Sec. 4.4): in the second-order scheme
+"""Pins of the oracle's pinning term (Sec. 4.6): in the second-order scheme
 mu is replaced by mu~ = mu + 2 (phi^{k+1/2} - phi_hat) W, phi^{k+1/2} =
 (phi^{k+1} + phi^k)/2, with a weight W >= 0 and a prescribed configuration
 phi_hat.  The oracle carries mu~ as its unknown (an extra -W phi in N^(2) and
