@@ -26,6 +26,7 @@
 #include "../../include/mpfc.h"
 #include "step.hpp"
 #include "poisson.hpp"
+#include "wrapup.hpp"
 #include "launch.hpp"
 #include "tiles.hpp"
 
@@ -136,11 +137,16 @@ struct mpfc_ctx {
     int poisson_cycles = 3;
     void* arena = nullptr;
     size_t arena_bytes = 0;
-    CycleState* host_st = nullptr;  // pinned readback
-    double* host_buf = nullptr;     // pinned readback (history / sums)
-    // hipGraphs of one V-cycle (MPFC, Poisson); rebuilt when profiling toggles
+    double* host_buf = nullptr;     // pinned mirror of the readback block
+    // Readback block: the cycle state (rb[0..7]), the Poisson state
+    // (rb[8..15]), the reduction results `acc` (rb[16..31]) and the residual
+    // history (rb[32..]), so that one copy returns all of them.
+    double* rb = nullptr;
+    size_t rb_count = 0;            // doubles of one full readback
+    StepIO* io = nullptr;           // the caller's arrays of the current step
+    // captured graphs (set-up, runs of cycles, Poisson cycle, wrap-up)
     bool use_graph = true;
-    hipGraphExec_t gx_mpfc = nullptr, gx_poisson = nullptr;
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;
     hipStream_t cap_stream = nullptr;  // capture only (the caller's stream may be the null stream)
     // live timing of the finest-level launches (HIP events on `stream`)
     int prof = 0;
@@ -159,7 +165,6 @@ struct mpfc_ctx {
     std::vector<FLevel> FL;
     int inner_cycles = 3;
     int pred_units = 4;                    // cycles (outer iterations) the last step needed
-    hipGraphExec_t gx_mixed[2] = {};       // one outer iteration, from copy 0 / copy 1
     // learned initial guess (guess mode MPFC_GUESS_CNN)
     CnnNet* cnn = nullptr;
     double* cnn_r2 = nullptr;              // squared residual norms: [0] learned, [1] extrapolated
@@ -661,25 +666,40 @@ void enqueue(mpfc_ctx* C, int kind, hipStream_t s) {
     }
 }
 
-// Replay one unit (a V-cycle, or one mixed-precision outer iteration) from a
-// graph captured on first use; launched directly while profiling.
-int run_cycle(mpfc_ctx* C, int kind) {
+// Captured graphs of a context, keyed by what they hold (graph_key): the
+// step's set-up, runs of 1..kMaxRun V-cycles (or mixed-precision outer
+// iterations, by the parity of the first one), one Poisson V-cycle, and the
+// wrap-up variants.
+enum GraphKind { GK_PROLOGUE = 1, GK_CYCLES = 2, GK_MIXED = 3, GK_POISSON = 4, GK_WRAPUP = 5 };
+constexpr int kMaxRun = 8;
+int graph_key(int kind, int a = 0, int b = 0) { return (kind * 16 + a) * 64 + b; }
+
+void destroy_graphs(mpfc_ctx* C) {
+    for (auto& g : C->graphs)
+        if (g.second) (void)hipGraphExecDestroy(g.second);
+    C->graphs.clear();
+}
+
+// Run the work `fn` enqueues: replayed from the graph captured under `key` on
+// first use, or launched directly while profiling (or with graphs off).
+template <class Fn>
+int run_unit(mpfc_ctx* C, int key, Fn&& fn) {
     hipStream_t s = C->stream;
     if (!C->use_graph || C->prof) {
-        enqueue(C, kind, s);
+        fn(s);
         HIP_TRY(hipGetLastError());
         return MPFC_OK;
     }
-    hipGraphExec_t& gx = kind == CYC_MPFC ? C->gx_mpfc
-                         : kind == CYC_POISSON ? C->gx_poisson
-                                               : C->gx_mixed[kind - CYC_MIXED0];
+    hipGraphExec_t gx = nullptr;
+    for (auto& g : C->graphs)
+        if (g.first == key) { gx = g.second; break; }
     if (!gx) {
         // Record the launches on a context-owned stream (nothing executes while
         // capturing), then replay the graph on the caller's stream.
         if (!C->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&C->cap_stream, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(C->cap_stream, hipStreamCaptureModeThreadLocal));
-        enqueue(C, kind, C->cap_stream);
+        fn(C->cap_stream);
         hipError_t le = hipGetLastError();
         hipError_t ce = hipStreamEndCapture(C->cap_stream, &g);
         if (le != hipSuccess || ce != hipSuccess) {
@@ -689,12 +709,36 @@ int run_cycle(mpfc_ctx* C, int kind) {
         }
         hipError_t ie = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
-        if (ie != hipSuccess) {
-            gx = nullptr;
+        if (ie != hipSuccess)
             return fail(MPFC_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
-        }
+        C->graphs.emplace_back(key, gx);
     }
     HIP_TRY(hipGraphLaunch(gx, s));
+    return MPFC_OK;
+}
+
+// One V-cycle of the Poisson problem of the -1 norm.
+int run_poisson_cycle(mpfc_ctx* C) {
+    return run_unit(C, graph_key(GK_POISSON), [&](hipStream_t s) { enqueue(C, CYC_POISSON, s); });
+}
+
+// `count` units of the step's solve (V-cycles, or mixed-precision outer
+// iterations, the first being the step's unit number `first`), in runs of at
+// most kMaxRun replayed from one graph each.
+int run_cycles(mpfc_ctx* C, int first, int count) {
+    const bool mixed = C->o.precision == MPFC_MIXED;
+    while (count > 0) {
+        const int k = count < kMaxRun ? count : kMaxRun;
+        const int par = first & 1;
+        const int key = mixed ? graph_key(GK_MIXED, par, k) : graph_key(GK_CYCLES, 0, k);
+        int rc = run_unit(C, key, [&](hipStream_t s) {
+            for (int j = 0; j < k; ++j)
+                enqueue(C, mixed ? CYC_MIXED0 + (1 ^ ((par + j) & 1)) : CYC_MPFC, s);
+        });
+        if (rc) return rc;
+        first += k;
+        count -= k;
+    }
     return MPFC_OK;
 }
 
@@ -1002,50 +1046,56 @@ int status_code(int st) {
     }
 }
 
-// Energies of (phi, phi_prev, psi) into out[0..3].  When `mu` is given (the
-// step's chemical potential) the previous Poisson solution is first advanced
-// by the scheme's own relation between psi^{k+1}, psi^k and Lap mu, which
-// leaves only the solver residual for the Poisson cycles to remove.
-// hist_count > 0: the step's residual history (that many entries) rides on
-// the same readback, into host_buf + kHistSlot.
-constexpr int kHistSlot = 16;
+// Energies from the reduction results a[0..7] (k_energy_terms) into out[0..3]:
+// F (eq. discrete_energy_PFC, with pinning plus h^2 sum W (phi - phi_hat)^2),
+// the pseudo energy F + ||psi||_{-1}^2 / (2M) (eq. discrete_energy_MPFC), the
+// modified energy (eq. energy_numer) and the mass h^2 sum phi.
+void energies_from_sums(const mpfc_ctx* C, const double* a, double* out) {
+    const double h2 = C->L[0].h * C->L[0].h;
+    const double Fe = 0.25 * h2 * a[0] + 0.5 * C->alpha * h2 * a[1] - a[2] + 0.5 * h2 * a[3] +
+                      h2 * a[7];
+    const double nm1 = h2 * a[6];
+    out[0] = Fe;
+    out[1] = Fe + nm1 / (2.0 * C->p.M);
+    out[2] = out[1] + 0.5 * a[5];
+    out[3] = h2 * a[4];
+}
+
+// Keep the number of Poisson cycles enqueued up front just large enough (0
+// when the warm start alone passes), from the count of the last solve.
+void adapt_poisson_cycles(mpfc_ctx* C, const CycleState& pst, bool warm) {
+    const int ran = pst.count - (warm ? 1 : 0);  // V-cycles that ran
+    if (ran >= C->poisson_cycles) C->poisson_cycles = ran < kMaxRun ? ran : kMaxRun;
+    else if (C->poisson_cycles > 0) C->poisson_cycles -= 1;
+}
+
+// Energies of (phi, phi_prev, psi) into out[0..3] (mpfc_energies): the
+// Poisson problem of the -1 norm is solved from the context's last solution
+// (or from zero before the first).
 int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, const double* psi,
-                     const double* mu, double* out, int hist_count = 0) {
+                     double* out) {
     hipStream_t s = C->stream;
     Level& F0 = C->L[0];
     const size_t total = (size_t)C->m * C->n;
     const unsigned rb = red_blocks(total);
-    // sums of psi and mu (acc[8], acc[9]), Poisson state reset; then the
-    // recursion for w, b = psi - mean and the sums of b^2 and of the warm
-    // start's squared residual (acc[10], acc[11])
     const bool warm = C->have_w != 0;
-    const bool advance = warm && mu;
-    hipLaunchKernelGGL((k_sum2<NT>), dim3(rb), dim3(NT), 0, s, psi, advance ? mu : nullptr, total,
+    // sum of psi (acc[8]), Poisson state reset; b = psi - mean and the sums of
+    // b^2 and of the warm start's squared residual (acc[10], acc[11])
+    hipLaunchKernelGGL((k_sum2<NT>), dim3(rb), dim3(NT), 0, s, psi, (const double*)nullptr, total,
                        C->part, C->pst);
     hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 2, C->acc + 8);
-    if (!warm) {
+    if (!warm)
         hipLaunchKernelGGL((k_fill<double>), grid1(total), dim3(256), 0, s, F0.w[0], total, 0.0);
-    } else if (advance) {
-        const double sb = C->p.dt * C->p.beta, sM = C->p.dt * C->p.M;
-        double a, b;
-        if (C->p.scheme == 1) { a = 1.0 / (1.0 + sb); b = sM / (1.0 + sb); }
-        else { a = (1.0 - 0.5 * sb) / (1.0 + 0.5 * sb); b = sM / (1.0 + 0.5 * sb); }
-        hipLaunchKernelGGL((k_w_advance), grid1(total), dim3(256), 0, s, F0.w[0], mu, total, a, b,
-                           C->acc + 9);
-    }
     hipLaunchKernelGGL((k_p_rhs_resid<NT>), dim3(rb), dim3(NT), 0, s, F0.g, 1.0 / (F0.h * F0.h),
                        psi, C->acc + 8, F0.pf, warm ? F0.w[0] : nullptr, C->part);
     hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 2,
                        C->acc + 10);
-    // The warm start may already meet the stopping test: its residual is the
-    // first norm of the solve, so cycles enqueued behind it exit at once.
+    // the warm start may already meet the stopping test (its residual is the
+    // first norm of the solve)
     if (warm)
         hipLaunchKernelGGL((k_p_finalize<NT>), dim3(1), dim3(NT), 0, s, C->acc + 11, 1, C->pst,
                            C->phist, C->acc + 10, kPoissonRel, kPoissonStall, kPoissonMax);
     HIP_TRY(hipGetLastError());
-    // Poisson cycles stop on the device (k_p_finalize); the energy sums are
-    // enqueued behind them, so one readback usually ends the step.  Only when
-    // the warm count was too small do more cycles (and the sums again) follow.
     auto terms = [&]() -> int {
         hipLaunchKernelGGL((k_energy_terms<NT>), dim3(rb), dim3(NT), 0, s, F0.g,
                            1.0 / (F0.h * F0.h), phi, phiprev, F0.pf, F0.w[0], C->part,
@@ -1054,46 +1104,30 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
         hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)rb, 8,
                            C->acc);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(C->host_buf, C->acc, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
-        if (hist_count > 0)
-            HIP_TRY(hipMemcpyAsync(C->host_buf + kHistSlot, C->hist, sizeof(double) * hist_count,
-                                   hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(C->host_st, C->pst, sizeof(CycleState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(C->host_buf, C->rb, 32 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         return MPFC_OK;
     };
     int launched = 0;
     for (int k = 0; k < C->poisson_cycles; ++k, ++launched) {
-        int rc = run_cycle(C, CYC_POISSON);
+        int rc = run_poisson_cycle(C);
         if (rc) return rc;
     }
     int rc = terms();
     if (rc) return rc;
-    while (!C->host_st->done && launched < kPoissonMax) {
+    const CycleState* hp = (const CycleState*)(C->host_buf + 8);
+    while (!hp->done && launched < kPoissonMax) {
         for (int k = 0; k < 2; ++k, ++launched) {
-            rc = run_cycle(C, CYC_POISSON);
+            rc = run_poisson_cycle(C);
             if (rc) return rc;
         }
         rc = terms();
         if (rc) return rc;
     }
-    const bool ok = C->host_st->status == ST_CONVERGED;
-    const int ran = C->host_st->count - (warm ? 1 : 0);  // V-cycles that ran
-    // keep the number of cycles enqueued up front just large enough (0 when
-    // the warm start alone passes)
-    if (ran >= C->poisson_cycles) C->poisson_cycles = ran < 8 ? ran : 8;
-    else if (C->poisson_cycles > 0) C->poisson_cycles -= 1;
+    const bool ok = hp->status == ST_CONVERGED;
+    adapt_poisson_cycles(C, *hp, warm);
     C->have_w = 1;
-    const double* a = C->host_buf;
-    const double h2 = F0.h * F0.h;
-    // F (eq. discrete_energy_PFC), with pinning plus h^2 sum W (phi - phi_hat)^2
-    const double Fe = 0.25 * h2 * a[0] + 0.5 * C->alpha * h2 * a[1] - a[2] + 0.5 * h2 * a[3] +
-                      h2 * a[7];
-    const double nm1 = h2 * a[6];
-    out[0] = Fe;
-    out[1] = Fe + nm1 / (2.0 * C->p.M);
-    out[2] = out[1] + 0.5 * a[5];
-    out[3] = h2 * a[4];
+    energies_from_sums(C, C->host_buf + 16, out);
     if (!ok) return fail(MPFC_ENOTCONVERGED, "Poisson solve of the -1 norm did not converge");
     return MPFC_OK;
 }
@@ -1107,7 +1141,8 @@ void cnn_choose(mpfc_ctx* C, hipStream_t s);
 // Source (also copies phi^k), guess and its completion, stop state reset and
 // the first residual norm (FP64), or for mixed precision phi^k in FP32 and the
 // first FP64 defect (copy 0 -> 1).  The coarse levels' phi^k (scheme 2) is
-// averaged by each cycle's down launches.
+// averaged by each cycle's down launches.  Without the learned guess the
+// caller's arrays are read from C->io (k_set_io) and the arguments are unused.
 int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const double* psi,
                   hipStream_t s) {
     Level& F0 = C->L[0];
@@ -1125,13 +1160,14 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
     const double* phihat = C->pinned ? C->phihat : nullptr;
     if (!learned) {
         // source, guess and kappa in one pass
+        // (the caller's arrays from C->io: this part is captured once and replayed)
         if (C->p.scheme == 1)
             hipLaunchKernelGGL((k_setup<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
-                               e, gmode, phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik,
+                               e, gmode, (const StepIO*)C->io, F0.f[0], F0.f[1], F0.f[2], C->phik,
                                (const double*)nullptr, (const double*)nullptr, phi, ka, C->st);
         else
             hipLaunchKernelGGL((k_setup<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
-                               e, gmode, phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik,
+                               e, gmode, (const StepIO*)C->io, F0.f[0], F0.f[1], F0.f[2], C->phik,
                                pin, phihat, phi, ka, C->st);
     } else {
         if (C->p.scheme == 1)
@@ -1182,17 +1218,64 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
     return MPFC_OK;
 }
 
-// psi update from FP64 copy `cur` and copy-out of phi^{k+1}.
-void step_epilogue(mpfc_ctx* C, int cur, const double* phi_n, double* psi, double* phi_np1,
-                   hipStream_t s) {
+void enqueue_energy_terms(mpfc_ctx* C, hipStream_t s);
+
+// Wrap-up of a step, enqueued behind its cycles (every kernel gated on the
+// step's cycle state, wrapup.hpp): psi^{k+1} and phi^{k+1} into the caller's
+// arrays, then (energies on) the -1 norm's Poisson problem, warm-started from
+// the last step's solution by the scheme's relation between psi and mu
+// (k_wrap_w_advance) or from zero (`warm` false), with `npoisson` V-cycles up
+// front, and the energy sums.  The readback block then holds all results.
+void enqueue_wrapup(mpfc_ctx* C, hipStream_t s, bool warm, int npoisson) {
+    Level& F0 = C->L[0];
     const size_t total = (size_t)C->m * C->n;
-    const double* phi = C->L[0].u[cur][0];
+    const int mixed = C->o.precision == MPFC_MIXED;
+    const StepIO* io = C->io;
     if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_psi_update<1>), grid1(total), dim3(256), 0, s, total, C->p.dt, phi,
-                           phi_n, psi, phi_np1);
+        hipLaunchKernelGGL((k_wrap_psi<1>), grid1(total), dim3(256), 0, s, io, C->st, mixed,
+                           F0.u[0][0], F0.u[1][0], total, C->p.dt);
     else
-        hipLaunchKernelGGL((k_psi_update<2>), grid1(total), dim3(256), 0, s, total, C->p.dt, phi,
-                           phi_n, psi, phi_np1);
+        hipLaunchKernelGGL((k_wrap_psi<2>), grid1(total), dim3(256), 0, s, io, C->st, mixed,
+                           F0.u[0][0], F0.u[1][0], total, C->p.dt);
+    if (!C->o.energy) return;
+    const unsigned rb = red_blocks(total);
+    hipLaunchKernelGGL((k_wrap_sums<NT>), dim3(rb), dim3(NT), 0, s, io, C->st, mixed, F0.u[0][1],
+                       F0.u[1][1], warm ? 1 : 0, total, C->part, C->pst);
+    hipLaunchKernelGGL((k_wrap_partials<NT>), dim3(1), dim3(NT), 0, s, C->st, C->part, (int)rb, 2,
+                       C->acc + 8);
+    if (!warm) {
+        hipLaunchKernelGGL(k_wrap_w_zero, grid1(total), dim3(256), 0, s, C->st, F0.w[0], total);
+    } else {
+        const double sb = C->p.dt * C->p.beta, sM = C->p.dt * C->p.M;
+        double a, b;
+        if (C->p.scheme == 1) { a = 1.0 / (1.0 + sb); b = sM / (1.0 + sb); }
+        else { a = (1.0 - 0.5 * sb) / (1.0 + 0.5 * sb); b = sM / (1.0 + 0.5 * sb); }
+        hipLaunchKernelGGL(k_wrap_w_advance, grid1(total), dim3(256), 0, s, C->st, mixed,
+                           F0.u[0][1], F0.u[1][1], F0.w[0], total, a, b, C->acc + 9);
+    }
+    hipLaunchKernelGGL((k_wrap_rhs_resid<NT>), dim3(rb), dim3(NT), 0, s, C->st, io, F0.g,
+                       1.0 / (F0.h * F0.h), C->acc + 8, F0.pf, warm ? F0.w[0] : nullptr, C->part);
+    hipLaunchKernelGGL((k_wrap_partials<NT>), dim3(1), dim3(NT), 0, s, C->st, C->part, (int)rb, 2,
+                       C->acc + 10);
+    // the warm start's residual is the first norm of the Poisson solve: it
+    // may already meet the test, and the cycles behind it then exit at once
+    if (warm)
+        hipLaunchKernelGGL((k_p_finalize<NT>), dim3(1), dim3(NT), 0, s, C->acc + 11, 1, C->pst,
+                           C->phist, C->acc + 10, kPoissonRel, kPoissonStall, kPoissonMax);
+    for (int k = 0; k < npoisson; ++k) vcycle_poisson(C, s);
+    enqueue_energy_terms(C, s);
+}
+
+// Energy sums of phi^{k+1} (gated on the step's state) into acc[0..7].
+void enqueue_energy_terms(mpfc_ctx* C, hipStream_t s) {
+    Level& F0 = C->L[0];
+    const unsigned rb = red_blocks((size_t)C->m * C->n);
+    hipLaunchKernelGGL((k_wrap_terms<NT>), dim3(rb), dim3(NT), 0, s, C->st, (const StepIO*)C->io,
+                       F0.g, 1.0 / (F0.h * F0.h), F0.pf, F0.w[0], C->part,
+                       (const double*)(C->pinned ? F0.pin : nullptr),
+                       (const double*)(C->pinned ? C->phihat : nullptr));
+    hipLaunchKernelGGL((k_wrap_partials<NT>), dim3(1), dim3(NT), 0, s, C->st, C->part, (int)rb, 8,
+                       C->acc);
 }
 
 }  // namespace
@@ -1361,9 +1444,14 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
             }
         }
         C->G = take(nG);
-        C->hist = take(o->max_cycles + 1 + 8);
+        C->rb_count = 32 + (size_t)o->max_cycles + 1;
+        C->rb = take(C->rb_count + 8);
+        C->st = (CycleState*)C->rb;
+        C->pst = (CycleState*)(C->rb + 8);
+        C->acc = C->rb + 16;
+        C->hist = C->rb + 32;
+        C->io = (StepIO*)take(8);
         C->phist = take(64);
-        C->acc = take(64);
         // one partial sum per finest tile (general grids: tiles down to 2 x 2),
         // and at least 8 per reduction workgroup
         const size_t cells_per_part = C->gen ? 4 : 256;
@@ -1371,8 +1459,6 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
         C->nparts = (int)((size_t)m * n / cells_per_part > min_parts ? (size_t)m * n / cells_per_part
                                                                       : min_parts);
         C->part = take((size_t)C->nparts);
-        C->st = (CycleState*)take(16);
-        C->pst = (CycleState*)take(16);
         C->cnn_r2 = take(8);
         C->cnn_counts = (unsigned long long*)take(8);
         return off;
@@ -1387,9 +1473,7 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
     std::vector<double> G;
     if (C->gen) spectral_factors(Lc.m, Lc.n, Lc.h, p->bc, G);
     else green_matrix(Lc.m, Lc.n, Lc.h, p->bc, G);
-    e = hipHostMalloc((void**)&C->host_st, sizeof(CycleState) * 2, hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void**)&C->host_buf, sizeof(double) * (size_t)(o->max_cycles + 128),
+    e = hipHostMalloc((void**)&C->host_buf, sizeof(double) * (C->rb_count + 64),
                           hipHostMallocDefault);
     // zero the whole arena once (the autotuner runs the tile kernels on it)
     if (e == hipSuccess) e = hipMemsetAsync(C->arena, 0, C->arena_bytes, C->stream);
@@ -1420,17 +1504,13 @@ int mpfc_create(mpfc_ctx** out, int m, int n, const mpfc_params* p, const mpfc_o
 
 void mpfc_destroy(mpfc_ctx* C) {
     if (!C) return;
-    if (C->gx_mpfc) (void)hipGraphExecDestroy(C->gx_mpfc);
-    if (C->gx_poisson) (void)hipGraphExecDestroy(C->gx_poisson);
-    for (hipGraphExec_t g : C->gx_mixed)
-        if (g) (void)hipGraphExecDestroy(g);
+    destroy_graphs(C);
     if (C->cap_stream) (void)hipStreamDestroy(C->cap_stream);
     for (hipEvent_t e : C->ev)
         if (e) (void)hipEventDestroy(e);
     if (C->cnn) cnn_free(C->cnn);
     if (C->pin_mem) (void)hipFree(C->pin_mem);
     if (C->arena) (void)hipFree(C->arena);
-    if (C->host_st) (void)hipHostFree(C->host_st);
     if (C->host_buf) (void)hipHostFree(C->host_buf);
     delete C;
 }
@@ -1448,84 +1528,117 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     Level& F0 = C->L[0];
     const size_t total = (size_t)C->m * C->n;
     const bool mixed = C->o.precision == MPFC_MIXED;
-    int rc0 = step_prologue(C, phi_n, phi_nm1, psi, s);
-    if (rc0) return rc0;
-    // Cycles are enqueued speculatively behind the set-up, without waiting for
-    // it: the first batch is what the previous step needed (a steady step then
-    // costs one host round trip), then one at a time.  A cycle enqueued after
-    // the stop flag was raised exits at once
-    // in every kernel, so speculation only costs launches, never changes the
-    // result.  (Mixed precision: outer iteration k reads FP64 copy 1 ^ (k & 1).)
-    // While profiling, cycles go one by one and the set-up is waited for, so
-    // that every timed launch belongs to a cycle that ran.
-    int launched = 0;
-    int batch = C->prof ? 1 : (C->pred_units > 1 ? C->pred_units : 1);
-    bool done = false;
-    if (C->prof) {
-        HIP_TRY(hipMemcpyAsync(C->host_st, C->st, sizeof(CycleState), hipMemcpyDeviceToHost, s));
+    const bool learned = C->o.guess == MPFC_GUESS_CNN;
+    // The caller's arrays, for the captured set-up and wrap-up.
+    hipLaunchKernelGGL(k_set_io, dim3(1), dim3(64), 0, s, C->io, phi_n, phi_nm1, psi, phi_np1);
+    int rc = learned ? step_prologue(C, phi_n, phi_nm1, psi, s)
+                     : run_unit(C, graph_key(GK_PROLOGUE), [&](hipStream_t cs) {
+                           (void)step_prologue(C, phi_n, phi_nm1, psi, cs);
+                       });
+    if (rc) return rc;
+    const CycleState* hst = (const CycleState*)C->host_buf;
+    const CycleState* hpst = (const CycleState*)(C->host_buf + 8);
+    auto readback = [&](size_t count) -> int {
+        HIP_TRY(hipMemcpyAsync(C->host_buf, C->rb, count * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        done = C->host_st->done != 0;
-    }
-    while (!done) {
+        return MPFC_OK;
+    };
+    const bool warm = C->have_w != 0;
+    const int npoisson = C->poisson_cycles;
+    auto wrapup = [&]() {
+        return run_unit(C, graph_key(GK_WRAPUP, warm ? 1 : 0, npoisson),
+                        [&](hipStream_t cs) { enqueue_wrapup(C, cs, warm, npoisson); });
+    };
+    // Cycles (or mixed-precision outer iterations) are enqueued without
+    // waiting for the set-up: as many as the previous step needed, then the
+    // wrap-up, which runs only if they were enough (a steady step costs one
+    // host round trip).  A cycle enqueued after the stop flag was raised exits
+    // at once in every kernel, so speculation only costs launches, never
+    // changes the result.  Otherwise the missing cycles run one by one, each
+    // followed by a look at the state, and then the wrap-up again.  While
+    // profiling, every cycle is waited for, so that each timed launch belongs
+    // to a cycle that ran.
+    int launched = 0;
+    auto one_more = [&]() -> int {
         if (launched > C->o.max_cycles + 1)
             return fail(MPFC_EHIP, "internal: cycle state did not advance");
-        for (int b = 0; b < batch; ++b, ++launched) {
-            int rc = run_cycle(C, mixed ? CYC_MIXED0 + (1 ^ (launched & 1)) : CYC_MPFC);
+        int r = run_cycles(C, launched, 1);
+        ++launched;
+        if (!r) r = readback(8);
+        if (!r && C->prof && C->Lp > 0 && !mixed) prof_collect(C);
+        return r;
+    };
+    if (C->prof) {
+        rc = readback(8);
+        while (!rc && !hst->done) rc = one_more();
+        if (!rc) rc = wrapup();
+        if (!rc) rc = readback(C->rb_count);
+    } else {
+        const int batch = C->pred_units < 1 ? 1
+                          : (C->pred_units > C->o.max_cycles ? C->o.max_cycles : C->pred_units);
+        rc = run_cycles(C, 0, batch);
+        launched = batch;
+        if (!rc) rc = wrapup();
+        if (!rc) rc = readback(C->rb_count);
+        if (!rc && !hst->done) {
+            while (!rc && !hst->done) rc = one_more();
+            if (!rc) rc = wrapup();
+            if (!rc) rc = readback(C->rb_count);
+        }
+    }
+    if (rc) return rc;
+    // Energies: more Poisson cycles when the ones enqueued up front were not
+    // enough, then the sums once more.
+    int energy_status = MPFC_OK;
+    double en[4] = {0, 0, 0, 0};
+    if (C->o.energy) {
+        int np = npoisson;
+        while (!hpst->done && np < kPoissonMax) {
+            for (int k = 0; k < 2; ++k, ++np) {
+                rc = run_poisson_cycle(C);
+                if (rc) return rc;
+            }
+            enqueue_energy_terms(C, s);
+            HIP_TRY(hipGetLastError());
+            rc = readback(32);
             if (rc) return rc;
         }
-        batch = 1;
-        HIP_TRY(hipMemcpyAsync(C->host_st, C->st, sizeof(CycleState), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (C->prof && C->Lp > 0 && !mixed) prof_collect(C);
-        done = C->host_st->done != 0;
+        if (hpst->status != ST_CONVERGED) energy_status = MPFC_ENOTCONVERGED;
+        adapt_poisson_cycles(C, *hpst, warm);
+        C->have_w = 1;
+        energies_from_sums(C, C->host_buf + 16, en);
     }
-    const CycleState fin = *C->host_st;
+    const CycleState fin = *hst;
     const int nouter = fin.count - 1;
     const int ncyc = mixed ? nouter * C->inner_cycles : nouter;
     C->pred_units = nouter > 0 ? nouter : 1;
     const int cur = mixed ? 1 ^ (nouter & 1) : 0;
-    double* phi = F0.u[cur][0];
-    double* mu = F0.u[cur][1];
-    double* ka = F0.u[cur][2];
-    step_epilogue(C, cur, phi_n, psi, phi_np1, s);
-    if (mu_out) HIP_TRY(hipMemcpyAsync(mu_out, mu, total * sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (ka_out) HIP_TRY(hipMemcpyAsync(ka_out, ka, total * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipGetLastError());
-    const int rc = status_code(fin.status);
-    double en[4] = {0, 0, 0, 0};
-    int energy_status = MPFC_OK;
-    if (C->o.energy) {
-        // the history rides on the energies' readback (one wait for both)
-        const int erc = compute_energies(C, phi, phi_n, psi, mu, en, info ? fin.count : 0);
-        if (erc && erc != MPFC_ENOTCONVERGED) return erc;
-        energy_status = erc;
-    }
+    if (mu_out)
+        HIP_TRY(hipMemcpyAsync(mu_out, F0.u[cur][1], total * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+    if (ka_out)
+        HIP_TRY(hipMemcpyAsync(ka_out, F0.u[cur][2], total * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+    const int st_rc = status_code(fin.status);
     if (info) {
         info->n_cycles = ncyc;
-        info->status = rc;
+        info->status = st_rc;
         info->outer_iters = mixed ? nouter : 0;
         info->energy_status = energy_status;
         info->energy_F = en[0];
         info->energy_pseudo = en[1];
         info->energy_mod = en[2];
         info->mass = en[3];
-        if (!C->o.energy) {
-            HIP_TRY(hipMemcpyAsync(C->host_buf + kHistSlot, C->hist, sizeof(double) * fin.count,
-                                   hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-        }
-        const double* hb = C->host_buf + kHistSlot;
+        const double* hb = C->host_buf + 32;
         info->residual = hb[fin.count - 1];
         if (info->residual_history)
             std::memcpy(info->residual_history, hb, sizeof(double) * fin.count);
-    } else {
-        HIP_TRY(hipStreamSynchronize(s));
     }
-    if (rc) {
+    if (st_rc) {
         char buf[160];
         std::snprintf(buf, sizeof buf, "step stopped with status %d after %d cycles", fin.status,
                       ncyc);
-        return fail(rc, buf);
+        return fail(st_rc, buf);
     }
     return MPFC_OK;
 }
@@ -1538,12 +1651,10 @@ int mpfc_set_pinning(mpfc_ctx* C, const double* weight, const double* phihat) {
         return fail(MPFC_EINVAL,
                     "pinning needs the second-order scheme, FP64 and Newton linearisation");
     hipStream_t s = C->stream;
-    // the captured cycle changes (other operator instantiation): capture again
-    if (C->gx_mpfc) {
-        HIP_TRY(hipStreamSynchronize(s));
-        (void)hipGraphExecDestroy(C->gx_mpfc);
-        C->gx_mpfc = nullptr;
-    }
+    // the captured set-up, cycles and wrap-up change (other operator
+    // instantiation, pinning terms): capture again
+    HIP_TRY(hipStreamSynchronize(s));
+    destroy_graphs(C);
     if (!weight) {
         C->pinned = false;
         return MPFC_OK;
@@ -1574,7 +1685,7 @@ int mpfc_set_pinning(mpfc_ctx* C, const double* weight, const double* phihat) {
 int mpfc_energies(mpfc_ctx* C, const double* phi, const double* phi_prev, const double* psi,
                   double* out) {
     if (!C || !phi || !psi || !out) return fail(MPFC_EINVAL, "ctx, phi, psi and out are required");
-    return compute_energies(C, phi, phi_prev, psi, nullptr, out);
+    return compute_energies(C, phi, phi_prev, psi, out);
 }
 
 // ---- operator-level entry points --------------------------------------------

@@ -24,8 +24,8 @@ __global__ void __launch_bounds__(256) k_fill(T* a, size_t n, T v) {
 
 // out[k] = sum over b < nparts of part[b * nvals + k], for k < nvals (one block).
 template <int NT>
-__global__ void __launch_bounds__(NT) k_partials_sum(const double* __restrict__ part, int nparts,
-                                                     int nvals, double* out) {
+__device__ __forceinline__ void partials_sum_body(const double* __restrict__ part, int nparts,
+                                                  int nvals, double* out) {
     __shared__ double red[NT / 64];
     for (int k = 0; k < nvals; ++k) {
         double s = 0.0;
@@ -34,6 +34,12 @@ __global__ void __launch_bounds__(NT) k_partials_sum(const double* __restrict__ 
         if (threadIdx.x == 0) out[k] = tot;
         __syncthreads();
     }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_partials_sum(const double* __restrict__ part, int nparts,
+                                                     int nvals, double* out) {
+    partials_sum_body<NT>(part, nparts, nvals, out);
 }
 
 
@@ -133,10 +139,10 @@ __global__ void __launch_bounds__(NT) k_sum2(const double* __restrict__ x,
 // when w is given, of r^2 with r = b - (-Lap_h w), the residual of the warm
 // start before any cycle, into part[blk * 2 + 0/1].
 template <int NT>
-__global__ void __launch_bounds__(NT) k_p_rhs_resid(Grid g, double ih2,
-                                                    const double* __restrict__ psi,
-                                                    const double* __restrict__ sum, double* b,
-                                                    const double* __restrict__ w, double* part) {
+__device__ __forceinline__ void p_rhs_resid_body(Grid g, double ih2,
+                                                 const double* __restrict__ psi,
+                                                 const double* __restrict__ sum, double* b,
+                                                 const double* __restrict__ w, double* part) {
     __shared__ double red[NT / 64];
     const size_t total = (size_t)g.m * g.n;
     const double mean = sum[0] / (double)total;
@@ -161,6 +167,14 @@ __global__ void __launch_bounds__(NT) k_p_rhs_resid(Grid g, double ih2,
     }
 }
 
+template <int NT>
+__global__ void __launch_bounds__(NT) k_p_rhs_resid(Grid g, double ih2,
+                                                    const double* __restrict__ psi,
+                                                    const double* __restrict__ sum, double* b,
+                                                    const double* __restrict__ w, double* part) {
+    p_rhs_resid_body<NT>(g, ih2, psi, sum, b, w, part);
+}
+
 // Energy sums after a step (Sec. 3, eqs. discrete_energy_PFC, energy_numer;
 // App. A norms), per block into part[blk * 8 + k]:
 //   k = 0: sum phi^4, 1: sum phi^2,
@@ -170,13 +184,13 @@ __global__ void __launch_bounds__(NT) k_p_rhs_resid(Grid g, double ih2,
 //   6: sum (psi - mean psi) w,
 //   7: sum W (phi - phi_hat)^2 (pinning, Sec. 4.6; 0 without pinning).
 template <int NT>
-__global__ void __launch_bounds__(NT) k_energy_terms(Grid g, double ih2,
-                                                     const double* __restrict__ phi,
-                                                     const double* __restrict__ phiprev,
-                                                     const double* __restrict__ b,
-                                                     const double* __restrict__ w, double* part,
-                                                     const double* __restrict__ pin,
-                                                     const double* __restrict__ phihat) {
+__device__ __forceinline__ void energy_terms_body(Grid g, double ih2,
+                                                  const double* __restrict__ phi,
+                                                  const double* __restrict__ phiprev,
+                                                  const double* __restrict__ b,
+                                                  const double* __restrict__ w, double* part,
+                                                  const double* __restrict__ pin,
+                                                  const double* __restrict__ phihat) {
     __shared__ double red[NT / 64];
     double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const size_t total = (size_t)g.m * g.n;
@@ -209,6 +223,17 @@ __global__ void __launch_bounds__(NT) k_energy_terms(Grid g, double ih2,
         if (threadIdx.x == 0) part[(size_t)blockIdx.x * 8 + k] = tot;
         __syncthreads();
     }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_energy_terms(Grid g, double ih2,
+                                                     const double* __restrict__ phi,
+                                                     const double* __restrict__ phiprev,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ w, double* part,
+                                                     const double* __restrict__ pin,
+                                                     const double* __restrict__ phihat) {
+    energy_terms_body<NT>(g, ih2, phi, phiprev, b, w, part, pin, phihat);
 }
 
 }  // namespace mpfc

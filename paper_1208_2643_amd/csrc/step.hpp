@@ -175,8 +175,28 @@ __device__ __forceinline__ void complete_kappa_cell(const Grid& g, double ih2, d
     ka[q] = S3[q] + e * (nsum(phi, i, j, g) - 4.0 * phi[q]) * ih2;
 }
 
-// Step set-up in one pass (extrapolated or previous-step guess): the source S
-// (source_cell), the guess phi0 = guess_value(mode, phi^k, phi^{k-1}) and
+// Caller arrays of one step.  The step's set-up and wrap-up run as captured
+// graphs, so these pointers, which change from step to step, are read from a
+// small device table that k_set_io fills before each step.
+struct StepIO {
+    const double* phi_n;    // phi^k
+    const double* phi_nm1;  // phi^{k-1}
+    double* psi;            // psi^k on entry, psi^{k+1} after the wrap-up
+    double* phi_np1;        // phi^{k+1}
+};
+
+__global__ void k_set_io(StepIO* io, const double* phi_n, const double* phi_nm1, double* psi,
+                         double* phi_np1) {
+    if (threadIdx.x == 0) {
+        io->phi_n = phi_n;
+        io->phi_nm1 = phi_nm1;
+        io->psi = psi;
+        io->phi_np1 = phi_np1;
+    }
+}
+
+// Step set-up in one pass (extrapolated or previous-step guess; the caller's
+// phi^k, phi^{k-1} and psi^k from `io`): the source S (source_cell), the guess phi0 = guess_value(mode, phi^k, phi^{k-1}) and
 // kappa = S3 + e Lap phi0, the first half of the guess's completion.  Each
 // thread forms the guess at its four neighbours itself, so no other thread's
 // output is read; the arithmetic is that of k_guess and complete_kappa_cell.
@@ -184,9 +204,7 @@ __device__ __forceinline__ void complete_kappa_cell(const Grid& g, double ih2, d
 template <int SCHEME>
 __global__ void __launch_bounds__(256) k_setup(Grid g, double ih2, double d, double alpha,
                                                double e, int mode,
-                                               const double* __restrict__ phik,
-                                               const double* __restrict__ phikm1,
-                                               const double* __restrict__ psik, double* S1,
+                                               const StepIO* __restrict__ io, double* S1,
                                                double* S2, double* S3, double* phik_copy,
                                                const double* __restrict__ pin,
                                                const double* __restrict__ phihat, double* phi0,
@@ -198,7 +216,9 @@ __global__ void __launch_bounds__(256) k_setup(Grid g, double ih2, double d, dou
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.m || j >= g.n) return;
-    source_cell<SCHEME>(g, ih2, d, alpha, phik, phikm1, psik, S1, S2, S3, phik_copy, i, j, pin,
+    const double* phik = io->phi_n;
+    const double* phikm1 = io->phi_nm1;
+    source_cell<SCHEME>(g, ih2, d, alpha, phik, phikm1, io->psi, S1, S2, S3, phik_copy, i, j, pin,
                         phihat);
     const size_t q = at(i, j, g);
     auto gv = [&](size_t k) { return guess_value(mode, phik[k], phikm1[k]); };
