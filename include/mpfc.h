@@ -237,6 +237,20 @@ int mpfc_op_smooth(const mpfc_params *p, int linearization, int m, int n, const 
                    double *d_phi, double *d_mu, double *d_kappa, const double *d_f1,
                    const double *d_f2, const double *d_f3, int sweeps, void *stream);
 
+/* mpfc_op_smooth without any allocation, for callers that cannot allocate
+ * device memory during a call (code under HIP graph capture, serving loops):
+ * same arguments, same result.  Its scratch (a copy of u and the discarded
+ * restriction outputs) is a static device array of about 6.8 MB that each
+ * GPU the library runs on holds until the process ends, so m n must be at
+ * most 512 x 512 = 262144 cells (else MPFC_EINVAL).  Calls that overlap on
+ * one GPU (other threads or streams) race on that array; each call waits for
+ * its stream before returning, so calls in sequence do not.  The scratch is
+ * fully written before it is read; nothing is kept between calls. */
+int mpfc_op_smooth_noalloc(const mpfc_params *p, int linearization, int m, int n,
+                           const double *d_phik, double *d_phi, double *d_mu, double *d_kappa,
+                           const double *d_f1, const double *d_f2, const double *d_f3,
+                           int sweeps, void *stream);
+
 /* r = f - N(u) (App. B), three output arrays. */
 int mpfc_op_residual(const mpfc_params *p, int m, int n, const double *d_phik,
                      const double *d_phi, const double *d_mu, const double *d_kappa,

@@ -94,6 +94,8 @@ SIGNATURES = {
     "mpfc_version": (_i, []),
     "mpfc_op_smooth": (_i, [ctypes.POINTER(mpfc_params), _i, _i, _i, _vp, _vp, _vp, _vp, _vp,
                             _vp, _vp, _i, _vp]),
+    "mpfc_op_smooth_noalloc": (_i, [ctypes.POINTER(mpfc_params), _i, _i, _i, _vp, _vp, _vp, _vp,
+                                    _vp, _vp, _vp, _i, _vp]),
     "mpfc_op_residual": (_i, [ctypes.POINTER(mpfc_params), _i, _i, _vp, _vp, _vp, _vp, _vp, _vp,
                               _vp, _vp, _vp, _vp, _vp]),
     "mpfc_op_source": (_i, [ctypes.POINTER(mpfc_params), _i, _i, _vp, _vp, _vp, _vp, _vp, _vp,

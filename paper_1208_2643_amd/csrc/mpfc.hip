@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1785,6 +1786,64 @@ int mpfc_op_smooth(const mpfc_params* p, int linearization, int m, int n, const 
     if (rc) return rc;
     if (fe != hipSuccess) return fail(MPFC_EHIP, std::string("hipFree: ") + hipGetErrorString(fe));
     return MPFC_OK;
+}
+
+}  // extern "C"
+
+// ---- the same sweeps without allocation ---------------------------------------
+// For callers that cannot allocate device memory during a call (code under
+// HIP graph capture, tight serving loops): the scratch of mpfc_op_smooth lives
+// in a file-scope device array sized for grids of up to kNoAllocMaxCells
+// cells.  Each GPU holds its own copy for the life of the process; host code
+// uses its device address, looked up once per device, never the name.
+namespace {
+constexpr int kNoAllocMaxCells = 1 << 18;  // 512 x 512
+constexpr size_t kNoAllocScratch = 3 * (size_t)kNoAllocMaxCells + kNoAllocMaxCells / 4 + 1;
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNoAllocScratch];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on first use
+// with that device current).
+int scratch_on_device(double** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MPFC_EHIP, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MPFC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mpfc_op_smooth_noalloc(const mpfc_params* p, int linearization, int m, int n,
+                           const double* phik, double* phi, double* mu, double* ka,
+                           const double* f1, const double* f2, const double* f3, int sweeps,
+                           void* stream) {
+    int rc = op_smooth_check(p, linearization, m, n, phik, phi, mu, ka, f1, f2, f3, sweeps,
+                             "mpfc_op_smooth_noalloc");
+    if (rc) return rc;
+    if ((long long)m * n > kNoAllocMaxCells)
+        return fail(MPFC_EINVAL, "mpfc_op_smooth_noalloc: more than 512 x 512 cells (the size of "
+                                 "its static scratch)");
+    static_assert(kNoAllocScratch >= 3 * (size_t)kNoAllocMaxCells + kNoAllocMaxCells / 4 + 1,
+                  "the static scratch holds op_smooth_scratch() of the largest grid");
+    double* tmp = nullptr;
+    rc = scratch_on_device(&tmp);
+    if (rc) return rc;
+    return op_smooth_run(p, linearization, m, n, phik, phi, mu, ka, f1, f2, f3, sweeps,
+                         (hipStream_t)stream, tmp);
 }
 
 int mpfc_op_residual(const mpfc_params* p, int m, int n, const double* phik, const double* phi,
