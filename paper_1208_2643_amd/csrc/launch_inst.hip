@@ -10,17 +10,27 @@ namespace {
 
 bool general_index(const Grid& g) { return g.lm < 0 || g.ln < 0; }
 
+#ifndef MPFC_TILE_EXACT
+#define MPFC_TILE_EXACT 1
+#endif
+
 template <class Op, bool UP, bool NEU, int K>
 void tile_k(const Op& op, const TileArgs<typename Op::real>& A, const CycleState* stop,
             hipStream_t s, bool gen) {
     constexpr TileShape S = kShapes[K];
-    const dim3 grid(A.g.m / A.tx, A.g.n / A.ty), blk(256);
+    const dim3 grid(A.g.m / A.tx, A.g.n / A.ty), blk(kTileThreads);
     if constexpr (std::is_same<typename Op::real, double>::value && gen_shape(K)) {
         if (gen) {
             hipLaunchKernelGGL((k_tile<Op, S.tx, S.ty, S.hmax, UP, NEU, true>), grid, blk, 0, s, op,
                                A, stop);
             return;
         }
+    }
+    // the shape's own tile and halo (the larger levels): compile-time extents
+    if (MPFC_TILE_EXACT && A.tx == S.tx && A.ty == S.ty && A.H == S.hmax) {
+        hipLaunchKernelGGL((k_tile<Op, S.tx, S.ty, S.hmax, UP, NEU, false, true>), grid, blk, 0, s,
+                           op, A, stop);
+        return;
     }
     hipLaunchKernelGGL((k_tile<Op, S.tx, S.ty, S.hmax, UP, NEU>), grid, blk, 0, s, op, A, stop);
 }
@@ -44,7 +54,7 @@ void tile_bc(const Op& op, const TileArgs<typename Op::real>& A, int shape,
 template <class Op, bool UP, bool NEU, int K>
 void tile_batched_k(const BatchTile<Op>* args, const BatchItem* items, int n, hipStream_t s) {
     constexpr TileShape S = kShapes[K];
-    hipLaunchKernelGGL((k_tile_batched<Op, S.tx, S.ty, S.hmax, UP, NEU>), dim3(n), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_tile_batched<Op, S.tx, S.ty, S.hmax, UP, NEU>), dim3(n), dim3(kTileThreads), 0, s,
                        args, items, n);
 }
 

@@ -151,14 +151,24 @@ __device__ __forceinline__ int xcd_item(int b, int nt) {
     return (nt & 7) == 0 ? (b & 7) * (nt >> 3) + (b >> 3) : b;
 }
 
-// Body of one tile launch (one workgroup, 256 threads) on tile (tbx, tby).
-// `pslot` is where the workgroup's residual sum goes in A.part.
-template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU, bool GEN = false>
+#ifndef MPFC_TILE_THREADS
+#define MPFC_TILE_THREADS 512
+#endif
+// Threads of a tile workgroup.
+constexpr int kTileThreads = MPFC_TILE_THREADS;
+
+// Body of one tile launch (one workgroup of kTileThreads threads) on tile
+// (tbx, tby).  `pslot` is where the workgroup's residual sum goes in A.part.
+// EXACT: the launch's tile is the shape's (A.tx = TX, A.ty = TY) and its halo
+// the shape's allowance (A.H = HMAX), so every extent is a compile-time
+// constant.
+template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU, bool GEN = false,
+          bool EXACT = false>
 __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename Op::real>& A,
                                           const CycleState* stop, int tbx, int tby, int pslot) {
     using T = typename Op::real;
     constexpr int NF = Op::NF;
-    constexpr int NT = 256;
+    constexpr int NT = kTileThreads;
     constexpr int LX2M = (TX + 2 * HMAX) / 2;
     constexpr int LYM = TY + 2 * HMAX;
     constexpr int SL = (LX2M * (LYM / 2) + NT - 1) / NT;  // owned blocks per thread
@@ -168,7 +178,7 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
     if (stopped(stop)) return;
 
     const Grid g = A.g;
-    const int H = A.H, tx = A.tx, ty = A.ty;
+    const int H = EXACT ? HMAX : A.H, tx = EXACT ? TX : A.tx, ty = EXACT ? TY : A.ty;
     const int LX = tx + 2 * H, LY = ty + 2 * H, LX2 = LX >> 1;
     const int nblk = LX2 * (LY >> 1);
     const int x0 = tbx * tx - H, y0 = tby * ty - H;
@@ -450,15 +460,16 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
     }
 }
 
-// One level of one grid.  Grid: (m / tx, n / ty) workgroups of 256 threads
-// (tx, ty divide m, n).
-template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU, bool GEN = false>
-__global__ void __launch_bounds__(256) k_tile(Op op, TileArgs<typename Op::real> A,
-                                              const CycleState* stop) {
+// One level of one grid.  Grid: (m / tx, n / ty) workgroups of kTileThreads
+// threads (tx, ty divide m, n).
+template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU, bool GEN = false,
+          bool EXACT = false>
+__global__ void __launch_bounds__(kTileThreads) k_tile(Op op, TileArgs<typename Op::real> A,
+                                                       const CycleState* stop) {
     const int nt = gridDim.x * gridDim.y;
     const int tl = xcd_item(blockIdx.y * gridDim.x + blockIdx.x, nt);
     const int tby = tl / gridDim.x, tbx = tl - tby * gridDim.x;
-    tile_body<Op, TX, TY, HMAX, UP, NEU, GEN>(op, A, stop, tbx, tby, tl);
+    tile_body<Op, TX, TY, HMAX, UP, NEU, GEN, EXACT>(op, A, stop, tbx, tby, tl);
 }
 
 // Batched launch: one level of many independent grids.  Each (grid, level)
@@ -479,7 +490,7 @@ struct BatchItem {
 };
 
 template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU>
-__global__ void __launch_bounds__(256) k_tile_batched(const BatchTile<Op>* __restrict__ args,
+__global__ void __launch_bounds__(kTileThreads) k_tile_batched(const BatchTile<Op>* __restrict__ args,
                                                       const BatchItem* __restrict__ items,
                                                       int nitems) {
     const int b = xcd_item(blockIdx.x, nitems);

@@ -1,0 +1,114 @@
+"""Consecutive steps of the full-size second-order workloads against the
+oracle's trajectory (tests/golden/make_fullsize.py: the CPU oracle solved to
+1e-12 per step from the same seeded initial field).
+
+Every step k of the run is compared, not only the last:
+  * phi^k and psi^k at the stored cells (a whole row, a whole column and 2048
+    seeded random cells), relative L2 over those cells;
+  * the full-grid L2 norms of phi^k and psi^k;
+  * the energies F, pseudo and modified energy and the mass (full-grid
+    functionals, eqs. discrete_energy_PFC, discrete_energy_MPFC, energy_numer).
+Bars: phi 1e-10 in FP64 and 1e-9 with mixed precision (FP32 correction
+cycles inside FP64 defect correction); psi^k = (2/s)(phi^k - phi^{k-1}) -
+psi^{k-1} (eq. discrete_2_b) scales the error of phi by 2/s = 40 against a
+field about 20x smaller than phi here, so psi is held to 1e-8 (FP64) and
+1e-7 (mixed); energies 1e-9.  The mass is compared with the correctly rounded
+h^2 sum of the oracle's field: summing the first equation over the periodic
+grid gives sum phi^{k+1} = sum S^(1) + sum r^(1), so two solves that stop at
+residual norms t1 and t2 differ in mass by at most h sqrt(m n) (t1 + t2); the
+bar is that bound plus 1e-13 relative for the GPU's own summation.  The
+per-step error curve is printed (pytest -s shows it).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1208_2643_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1208_2643_amd import api  # noqa: E402
+from paper_1208_2643_amd import _lib as L  # noqa: E402
+
+DEV = torch.device("cuda:0")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(N, seed):
+    g = np.load(os.path.join(GOLDEN, f"fullsize_{N}_seed{seed}.npz"))
+    return g, json.loads(str(g["meta"]))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run_and_compare(N, seed, steps, bars, **opts):
+    g, meta = golden(N, seed)
+    assert meta["N"] == N and meta["steps"] >= steps and meta["oracle_tol"] <= 1e-12
+    P = meta["params"]
+    st = api.Stepper(N, N, api.Params(**P), tol=1e-10, **opts)
+    phi0 = I.crystallites(N, N, P["h"], seed=seed)
+    phi = torch.from_numpy(phi0).to(DEV)
+    prev = phi.clone()
+    psi = torch.zeros_like(phi)
+    nxt = torch.empty_like(phi)
+    idx = torch.from_numpy(g["idx"]).to(DEV)
+    curve = []
+    for k in range(steps):
+        _, info = st.step(phi, prev, psi, nxt)
+        assert info.status == 0 and info.energy_status == 0, (k, info.status)
+        prev, phi, nxt = phi, nxt, prev
+        torch.cuda.synchronize()
+        sp = phi.view(-1)[idx].cpu().numpy()
+        ss = psi.view(-1)[idx].cpu().numpy()
+        e_phi, e_psi = rel(sp, g["phi"][k]), rel(ss, g["psi"][k])
+        n_phi = abs(float(torch.linalg.norm(phi)) - g["norm_phi"][k]) / g["norm_phi"][k]
+        n_psi = abs(float(torch.linalg.norm(psi)) - g["norm_psi"][k]) / g["norm_psi"][k]
+        en = g["energies"][k]
+        got = (info.energy_F, info.energy_pseudo, info.energy_mod, info.mass)
+        e_en = max(abs(a - b) / abs(b) for a, b in zip(got[:3], en[:3]))
+        mass = g["mass_fsum"][k]
+        e_mass = abs(got[3] - mass) / abs(mass)
+        mass_bar = P["h"] * N * (1e-10 + meta["oracle_tol"]) / abs(mass) + 1e-13
+        curve.append((k + 1, info.n_cycles, e_phi, e_psi, n_phi, e_en, e_mass))
+        assert e_phi <= bars["phi"] and n_phi <= bars["phi"], (k + 1, e_phi, n_phi)
+        assert e_psi <= bars["psi"] and n_psi <= bars["psi"], (k + 1, e_psi, n_psi)
+        assert e_en <= 1e-9 and e_mass <= mass_bar, (k + 1, e_en, e_mass, mass_bar)
+    print(f"\n{N}^2 {opts}: step, cycles, rel err phi (cells), psi (cells), |phi| (grid), "
+          "energies, mass")
+    for row in curve:
+        print("  %3d %3d  %.2e  %.2e  %.2e  %.2e  %.2e" % row)
+    return curve
+
+
+@pytest.mark.timeout(300)
+def test_1024_twenty_steps_fp64():
+    """The benchmark's workload and configuration (FP64, V(2,2), energies every
+    step) over 20 consecutive steps."""
+    run_and_compare(1024, 2, 20, dict(phi=1e-10, psi=1e-8), precision=L.MPFC_FP64)
+
+
+@pytest.mark.timeout(300)
+def test_1024_twenty_steps_mixed():
+    """Mixed precision on the same 20 steps: FP32 smoothing, restriction and
+    prolongation inside FP64 defect correction, same 1e-10 FP64 residual."""
+    run_and_compare(1024, 2, 20, dict(phi=1e-9, psi=1e-7), precision=L.MPFC_MIXED,
+                    inner_cycles=3)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("precision,inner", [(L.MPFC_FP64, 3), (L.MPFC_MIXED, 4)])
+def test_2048_five_steps(precision, inner):
+    """The 2048^2 workload (crystallites, seed 3) over 5 consecutive steps, in
+    FP64 and with mixed precision (4 inner FP32 cycles per outer iteration)."""
+    mixed = precision == L.MPFC_MIXED
+    run_and_compare(2048, 3, 5, dict(phi=1e-9 if mixed else 1e-10, psi=1e-7 if mixed else 1e-8),
+                    precision=precision, inner_cycles=inner)
