@@ -157,92 +157,154 @@ __device__ __forceinline__ int xcd_item(int b, int nt) {
 // Threads of a tile workgroup.
 constexpr int kTileThreads = MPFC_TILE_THREADS;
 
-// Body of one tile launch (one workgroup of kTileThreads threads) on tile
-// (tbx, tby).  `pslot` is where the workgroup's residual sum goes in A.part.
+// One tile of a tiled level, in phases:
+//   load_direct  u (tile + halo) and, for up launches, u_H - v_H over the
+//                tile's coarse footprint, from global memory into LDS;
+//   fetch_rhs    the right-hand side and coefficients of the owned blocks
+//                into registers;
+//   compute      prolongation (up), completion of the coarse right-hand side
+//                (coarse down), the red-black passes, the store of u, and the
+//                residual with its restriction (down) or norm (finest up).
 // EXACT: the launch's tile is the shape's (A.tx = TX, A.ty = TY) and its halo
 // the shape's allowance (A.H = HMAX), so every extent is a compile-time
 // constant.
-template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU, bool GEN = false,
-          bool EXACT = false>
-__device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename Op::real>& A,
-                                          const CycleState* stop, int tbx, int tby, int pslot) {
+template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU, bool GEN, bool EXACT>
+struct TileWork {
     using T = typename Op::real;
-    constexpr int NF = Op::NF;
-    constexpr int NT = kTileThreads;
-    constexpr int LX2M = (TX + 2 * HMAX) / 2;
-    constexpr int LYM = TY + 2 * HMAX;
-    constexpr int SL = (LX2M * (LYM / 2) + NT - 1) / NT;  // owned blocks per thread
-    __shared__ T U[NF][2][LYM][LX2M];
-    __shared__ T E[UP ? NF : 1][UP ? LYM / 2 + 2 : 1][UP ? LX2M + 2 : 1];  // up: uH - vH
-    __shared__ double red[NT / 64];
-    if (stopped(stop)) return;
-
-    const Grid g = A.g;
-    const int H = EXACT ? HMAX : A.H, tx = EXACT ? TX : A.tx, ty = EXACT ? TY : A.ty;
-    const int LX = tx + 2 * H, LY = ty + 2 * H, LX2 = LX >> 1;
-    const int nblk = LX2 * (LY >> 1);
-    const int x0 = tbx * tx - H, y0 = tby * ty - H;
-    const int t = threadIdx.x;
-
-    // 1. u (tile + halo) into LDS, coalesced along rows.
-    for (int q = t; q < LX * LY; q += NT) {
-        const int y = q / LX, x = q - y * LX;
-        const size_t gq = tat<GEN>(bidx<NEU, GEN>(x0 + x, g.m, g.bc & BC_NEUMANN_X),
-                                   bidx<NEU, GEN>(y0 + y, g.n, g.bc & BC_NEUMANN_Y), g);
-#pragma unroll
-        for (int f = 0; f < NF; ++f) U[f][(x + y) & 1][y][x >> 1] = A.zero_in ? T(0) : A.uin[f][gq];
+    static constexpr int NF = Op::NF;
+    static constexpr int NT = kTileThreads;
+    static constexpr int LX2M = (TX + 2 * HMAX) / 2;
+    static constexpr int LYM = TY + 2 * HMAX;
+    static constexpr int SL = (LX2M * (LYM / 2) + NT - 1) / NT;  // owned blocks per thread
+    // LDS row length (doubles per colour and row), padded so that a wave's
+    // consecutive blocks continue across a block-row break on the next banks:
+    // the block-row stride 2 P equals LX2 modulo the 32 doubles of a bank cycle.
+    static constexpr int pad_row(int l) {
+        int p = l;
+        while (((2 * p - l) % 32 + 32) % 32 != 0) ++p;
+        return p;
     }
-    __syncthreads();
+    static constexpr int LXP = pad_row(LX2M);
+    static constexpr int CXM = LX2M + 2, CYM = LYM / 2 + 2;       // coarse footprint
 
-    // 2. per owned block: right-hand side and coefficients of its four cells
-    //    (cell order: (0,0) (1,1) red, (1,0) (0,1) black).
-    T fr[SL][4][NF];
-    T xkr[SL][4];
-    T pbr[SL][4];
-    T wr[SL][4];
-#pragma unroll
-    for (int s = 0; s < SL; ++s) {
-        const int b = t + s * NT;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) fr[s][c][f] = T(0);
-            xkr[s][c] = T(0);
-            pbr[s][c] = T(0);
-            wr[s][c] = T(0);
-        }
-        if (b >= nblk) continue;
-        const int by = b / LX2, bx = b - by * LX2;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
-            const int x = 2 * bx + dx, y = 2 * by + dy;
-            if (x < 1 || y < 1 || x >= LX - 1 || y >= LY - 1) continue;  // never updated
-            const size_t gq = tat<GEN>(bidx<NEU, GEN>(x0 + x, g.m, g.bc & BC_NEUMANN_X),
-                                       bidx<NEU, GEN>(y0 + y, g.n, g.bc & BC_NEUMANN_Y), g);
-            if constexpr (Op::XK) xkr[s][c] = A.xk[gq];
-            if constexpr (Op::PB) pbr[s][c] = A.pb[gq];
-            if constexpr (Op::PW) wr[s][c] = A.pin[gq];
-#pragma unroll
-            for (int f = 0; f < NF; ++f) fr[s][c][f] = A.f[f][gq];
-        }
+    struct Lds {
+        T U[NF][2][LYM][LXP];
+        T E[UP ? NF : 1][UP ? CYM : 1][UP ? CXM : 1];  // up: uH - vH
+        double red[NT / 64];
+    };
+    // Extents of the tile (tbx, tby) of a launch.
+    struct Geo {
+        int H, tx, ty, LX, LY, LX2, nblk, x0, y0, tbx, tby;
+    };
+    // Right-hand side and coefficients of the owned blocks' four cells (cell
+    // order: (0,0) (1,1) red, (1,0) (0,1) black).
+    struct Rhs {
+        T f[SL][4][NF];
+        T xk[SL][4];
+        T pb[SL][4];
+        T w[SL][4];
+    };
+
+    static __device__ __forceinline__ Geo geo(const TileArgs<T>& A, int tbx, int tby) {
+        Geo G;
+        G.H = EXACT ? HMAX : A.H;
+        G.tx = EXACT ? TX : A.tx;
+        G.ty = EXACT ? TY : A.ty;
+        G.LX = G.tx + 2 * G.H;
+        G.LY = G.ty + 2 * G.H;
+        G.LX2 = G.LX >> 1;
+        G.nblk = G.LX2 * (G.LY >> 1);
+        G.x0 = tbx * G.tx - G.H;
+        G.y0 = tby * G.ty - G.H;
+        G.tbx = tbx;
+        G.tby = tby;
+        return G;
     }
 
-    // 3. up: add the coarse-grid correction P(uH - vH) to every loaded cell.
-    //    uH - vH over the tile's coarse footprint (one coarse cell of margin)
-    //    is staged in LDS first, read coalesced.
-    if constexpr (UP) {
+    static __device__ __forceinline__ size_t cell(const Grid& g, int x, int y) {
+        return tat<GEN>(bidx<NEU, GEN>(x, g.m, g.bc & BC_NEUMANN_X),
+                        bidx<NEU, GEN>(y, g.n, g.bc & BC_NEUMANN_Y), g);
+    }
+    static __device__ __forceinline__ size_t coarse_cell(const Grid& g, int cx, int cy) {
         const int mc = g.m >> 1, nc = g.n >> 1;
-        const int CX = LX2 + 2, CY = (LY >> 1) + 2;
-        const int cx0 = (x0 >> 1) - 1, cy0 = (y0 >> 1) - 1;
-        for (int q = t; q < CX * CY; q += NT) {
-            const int cy = q / CX, cx = q - cy * CX;
-            const size_t gq = (size_t)bidx<NEU, GEN>(cy0 + cy, nc, g.bc & BC_NEUMANN_Y) * mc +
-                              bidx<NEU, GEN>(cx0 + cx, mc, g.bc & BC_NEUMANN_X);
+        return (size_t)bidx<NEU, GEN>(cy, nc, g.bc & BC_NEUMANN_Y) * mc +
+               bidx<NEU, GEN>(cx, mc, g.bc & BC_NEUMANN_X);
+    }
+
+    static __device__ __forceinline__ void fetch_rhs(const TileArgs<T>& A, const Geo& G, Rhs& R) {
+        const Grid g = A.g;
+        const int t = threadIdx.x;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) E[f][cy][cx] = A.cuH[f][gq] - A.cvH[f][gq];
+        for (int s = 0; s < SL; ++s) {
+            const int b = t + s * NT;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) R.f[s][c][f] = T(0);
+                R.xk[s][c] = T(0);
+                R.pb[s][c] = T(0);
+                R.w[s][c] = T(0);
+            }
+            if (b >= G.nblk) continue;
+            const int by = b / G.LX2, bx = b - by * G.LX2;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
+                const int x = 2 * bx + dx, y = 2 * by + dy;
+                if (x < 1 || y < 1 || x >= G.LX - 1 || y >= G.LY - 1) continue;  // never updated
+                const size_t gq = cell(g, G.x0 + x, G.y0 + y);
+                if constexpr (Op::XK) R.xk[s][c] = A.xk[gq];
+                if constexpr (Op::PB) R.pb[s][c] = A.pb[gq];
+                if constexpr (Op::PW) R.w[s][c] = A.pin[gq];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) R.f[s][c][f] = A.f[f][gq];
+            }
         }
-        __syncthreads();
+    }
+
+    // u (tile + halo) and, up, uH - vH into LDS, coalesced along rows; a
+    // barrier must follow.
+    static __device__ __forceinline__ void load_direct(const TileArgs<T>& A, const Geo& G, Lds& S) {
+        const Grid g = A.g;
+        const int t = threadIdx.x;
+        for (int q = t; q < G.LX * G.LY; q += NT) {
+            const int y = q / G.LX, x = q - y * G.LX;
+            const size_t gq = cell(g, G.x0 + x, G.y0 + y);
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                S.U[f][(x + y) & 1][y][x >> 1] = A.zero_in ? T(0) : A.uin[f][gq];
+        }
+        if constexpr (UP) {
+            const int CX = G.LX2 + 2, CY = (G.LY >> 1) + 2;
+            const int cx0 = (G.x0 >> 1) - 1, cy0 = (G.y0 >> 1) - 1;
+            for (int q = t; q < CX * CY; q += NT) {
+                const int cy = q / CX, cx = q - cy * CX;
+                const size_t gq = coarse_cell(g, cx0 + cx, cy0 + cy);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) S.E[f][cy][cx] = A.cuH[f][gq] - A.cvH[f][gq];
+            }
+        }
+    }
+
+    // Everything after the tile is in LDS (entered after a barrier).  `pslot`
+    // is where the workgroup's residual sum goes in A.part.
+    static __device__ __forceinline__ void compute(const Op& op, const TileArgs<T>& A,
+                                                   const Geo& G, Lds& S, Rhs& R, int pslot) {
+        const Grid g = A.g;
+        const int H = G.H, tx = G.tx, ty = G.ty, LX = G.LX, LY = G.LY, LX2 = G.LX2;
+        const int nblk = G.nblk, x0 = G.x0, y0 = G.y0, tbx = G.tbx, tby = G.tby;
+        const int t = threadIdx.x;
+        auto& U = S.U;
+        auto& E = S.E;
+        auto& red = S.red;
+        auto& fr = R.f;
+        const auto& xkr = R.xk;
+        const auto& pbr = R.pb;
+        const auto& wr = R.w;
+    // 3. up: add the coarse-grid correction P(uH - vH) to every loaded cell
+    //    (uH - vH over the tile's coarse footprint, one coarse cell of margin,
+    //    staged in LDS).
+    if constexpr (UP) {
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             const int b = t + s * NT;
@@ -458,6 +520,24 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
             if (t == 0) A.part[pslot] = bs;
         }
     }
+    }
+};
+
+// Body of one tile launch: the tile into LDS, its right-hand side into
+// registers, then the computation.
+template <class Op, int TX, int TY, int HMAX, bool UP, bool NEU, bool GEN = false,
+          bool EXACT = false>
+__device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename Op::real>& A,
+                                          const CycleState* stop, int tbx, int tby, int pslot) {
+    using W = TileWork<Op, TX, TY, HMAX, UP, NEU, GEN, EXACT>;
+    __shared__ typename W::Lds S;
+    if (stopped(stop)) return;
+    const typename W::Geo G = W::geo(A, tbx, tby);
+    W::load_direct(A, G, S);
+    __syncthreads();
+    typename W::Rhs R;
+    W::fetch_rhs(A, G, R);
+    W::compute(op, A, G, S, R, pslot);
 }
 
 // One level of one grid.  Grid: (m / tx, n / ty) workgroups of kTileThreads
