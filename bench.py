@@ -41,6 +41,13 @@ COMPULSORY_BYTES = {"down": 56.0 + 24.0 + 20.0, "up": 56.0 + 12.0 + 24.0}
 # The pinning weight W (8 B per cell) adds one read per sweep and per residual
 # pass: down 2 sweeps + residual, up 2 sweeps + norm.
 PIN_BYTES = {"down": 3 * 8.0, "up": 3 * 8.0}
+# One whole V(2,2) cycle, FP64, scheme 2, per finest cell: 468 B on the
+# finest level (2 x 2 sweeps of 80 B, residual and restriction 68 B, coarse
+# FAS right-hand side 20 B, prolongation 60 B), 4/3 of it over all levels, and
+# the stopping test's residual read (56 B).
+VCYCLE_MODEL_BYTES = 680.0
+# One FP32 correction V(2,2) cycle of the batch, per finest cell (all levels).
+BATCH_FP32_VCYCLE_BYTES = 340.0
 # HBM bytes per finest-level launch measured with rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by what the counters read for a 128 MiB copy), per tile
 # shape "TXxTY/HALO", valid only for the kernel sources they were measured on
@@ -101,12 +108,31 @@ def parse():
     return ap.parse_args()
 
 
+def host_cores():
+    """(logical CPUs this process may use, physical cores among them)."""
+    cpus = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else []
+    phys = set()
+    try:
+        for c in cpus:
+            base = f"/sys/devices/system/cpu/cpu{c}/topology/"
+            with open(base + "physical_package_id") as f1, open(base + "core_id") as f2:
+                phys.add((f1.read().strip(), f2.read().strip()))
+    except OSError:
+        phys = set()
+    return len(cpus) or (os.cpu_count() or 1), len(phys) or None
+
+
 def cpu_baseline(params, phi0, tol, budget_s):
     """The oracle, as it stands, on the same workload from the same initial
-    state: whole steps until about `budget_s` seconds have passed."""
+    state: whole steps on all usable host threads until about `budget_s`
+    seconds have passed; then one V-cycle of the first step on all threads
+    and on one thread (a whole step on one core takes minutes), as
+    unknowns x V-cycles/s."""
     import numpy as np
     import oracle as O
     p = O.Params(**params)
+    logical, physical = host_cores()
+    threads = O.num_threads()
     phi, prev, psi = phi0.copy(), phi0.copy(), np.zeros_like(phi0)
     t0 = time.perf_counter()
     steps = 0
@@ -119,11 +145,34 @@ def cpu_baseline(params, phi0, tol, budget_s):
         if time.perf_counter() - t0 >= budget_s or steps >= 20:
             break
     dt = time.perf_counter() - t0
-    return {"value": steps / dt, "unit": "time-steps/s", "cores": O.num_threads(),
+    unknowns = 3.0 * phi0.size
+    # one thread: one V-cycle from the completed extrapolated guess of step 1
+    S = O.source(p, phi0, phi0, np.zeros_like(phi0))
+    u0 = O.complete_guess(p, phi0.copy(), S, phi0 if p.scheme == 2 else None)
+    pk = phi0 if p.scheme == 2 else None
+    t1 = time.perf_counter()
+    O.fas_solve(p, u0, S, phik=pk, tol=1e-30, max_cycles=1)
+    t_cycle_all = time.perf_counter() - t1
+    O.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        O.fas_solve(p, u0, S, phik=pk, tol=1e-30, max_cycles=1)
+        t_cycle = time.perf_counter() - t1
+    finally:
+        O.set_threads(threads)
+    return {"value": steps / dt, "unit": "time-steps/s", "cores": threads,
+            "logical_cpus": logical, "physical_cores": physical,
             "kind": "oracle",
             "sample": f"first {steps} step(s) of the same {phi0.shape[1]}x{phi0.shape[0]} "
                       f"workload from its initial state ({cycles} V-cycles, energies on), "
-                      f"{dt:.1f} s wall"}
+                      f"{dt:.1f} s wall, {threads} OpenMP threads",
+            "vcycle": {"unknowns_x_vcycles_per_s": unknowns / t_cycle_all,
+                       "single_thread_unknowns_x_vcycles_per_s": unknowns / t_cycle,
+                       "sample": f"one V(2,2) cycle of the first step: {t_cycle_all:.2f} s on "
+                                 f"{threads} threads, {t_cycle:.2f} s on one thread (a whole "
+                                 "step also solves the -1 norm's Poisson problem to 1e-14 by "
+                                 "conjugate gradients, which the whole-step rate above "
+                                 "includes)"}}
 
 
 def bench_big(api, inputs, torch, dev, params, tol, steps, warmup, N=2048, inner=4):
@@ -372,9 +421,15 @@ def bench_batch(api, inputs, torch, dev, steps, warmup):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     b.close()
+    # FP32 V-cycles of all simulations against the per-operation byte model
+    model_GBps = BATCH_FP32_VCYCLE_BYTES * work / 3.0 / el / 1e9
     return {"simulations": len(sims), "steps": steps, "sim_steps_per_s": len(sims) * steps / el,
             "batch_steps_per_s": steps / el, "cells": int(sum(cells)),
             "unknowns_x_fp32_vcycles_per_s": work / el,
+            "roofline": {"basis": "340 B per cell per FP32 V(2,2) cycle (per-operation model), "
+                                  "defect passes and set-up charged to the cycles",
+                         "bound": "hbm", "achieved": model_GBps, "peak": HBM_PEAK_GBPS,
+                         "unit": "GB/s", "frac": model_GBps / HBM_PEAK_GBPS},
             "max_outer_per_step": outer / steps, "create_s": t_create,
             "precision": "mixed (FP32 correction cycles, FP64 defect correction)",
             "sizes": {str(n): sum(1 for sp in specs if sp.N == n) for n in (128, 256, 512, 1024)}}
@@ -452,6 +507,8 @@ def main():
               for which, name in ((0, "down"), (1, "up"))}
     dom = max(timing, key=lambda k: timing[k][0])
     ms, launches, cells = timing[dom]
+    traffic = (MEASURED_TRAFFIC[dom].get(shapes[dom])
+               if kernel_source_hash() == MEASURED_TRAFFIC["src"] else None)
     avg_s = ms / 1e3 / max(1, launches)
     achieved = MODEL_BYTES[dom] * cells / avg_s / 1e9 if launches else None
     compulsory = COMPULSORY_BYTES[dom] * cells / avg_s / 1e9 if launches else None
@@ -487,8 +544,15 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS if achieved else None,
-            "traffic": (MEASURED_TRAFFIC[dom].get(shapes[dom])
-                        if kernel_source_hash() == MEASURED_TRAFFIC["src"] else None),
+            "traffic": traffic,
+            "traffic_source": ("rocprofv3 FETCH_SIZE and WRITE_SIZE per launch of this tile "
+                               "shape, scaled by a 128 MiB copy's readings, from a separate "
+                               "run on these kernel sources (profiles/), not this run"
+                               if traffic else "no counter reading for these kernel sources"),
+            "measured_GBps": traffic / avg_s / 1e9 if traffic and launches else None,
+            "frac_measured": traffic / avg_s / 1e9 / HBM_PEAK_GBPS if traffic and launches
+                             else None,
+            "achieved_basis": "algorithmic bytes: per-operation model of the launch's passes",
             "bytes_per_launch": MODEL_BYTES[dom] * cells,
             "avg_launch_us": avg_s * 1e6,
             "compulsory_GBps": compulsory,
@@ -500,6 +564,12 @@ def main():
             "vcycles_per_step": total_cycles / args.steps,
             "unknowns_x_vcycles_per_s": 3.0 * N * N * total_cycles / elapsed,
             "ms_per_vcycle": 1e3 * elapsed / max(1, total_cycles),
+            # whole V-cycle against the per-operation byte model (680 B per
+            # finest cell, all levels and the stopping test), with the step's
+            # set-up, psi update and energies charged to its cycles
+            "vcycle_model_bytes": VCYCLE_MODEL_BYTES * N * N,
+            "vcycle_frac_of_hbm_peak": VCYCLE_MODEL_BYTES * N * N * total_cycles / elapsed
+                                       / 1e9 / HBM_PEAK_GBPS,
         },
     }
     # The same workload with mixed precision (FP32 correction cycles inside

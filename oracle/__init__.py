@@ -115,6 +115,7 @@ def load():
                         _dp, _dp, _dp, _dp, _dp, _dp]),
         "orc_version": (i, []),
         "orc_num_threads": (i, []),
+        "orc_set_threads": (None, [i]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -126,6 +127,11 @@ def load():
 
 def num_threads() -> int:
     return load().orc_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (timing only)."""
+    load().orc_set_threads(int(n))
 
 
 def _lib_bc(bc):

@@ -789,3 +789,13 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Threads of the OpenMP loops (the CPU timing of the oracle); no effect on
+ * the arithmetic. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

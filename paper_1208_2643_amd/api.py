@@ -383,6 +383,30 @@ def run(stepper: Stepper, phi0: torch.Tensor, steps: int, record=None):
     return phi, prev, psi, infos
 
 
+# ---- checkpoint / resume ------------------------------------------------------
+# The whole state of a run is (phi^k, phi^{k-1}, psi^k) and the step count: for
+# the second-order scheme psi^k carries the run's history (eq. discrete_2_b),
+# so it is saved with the two phi's.  A context holds nothing a resumed run
+# needs (its Poisson warm start and cycle prediction only save work).
+def save_state(path, phi, phi_prev, psi, step: int, params: Params) -> None:
+    """Write a run's state to `path` (numpy .npz, FP64, no pickled objects)."""
+    np.savez(path, phi=phi.detach().cpu().numpy(), phi_prev=phi_prev.detach().cpu().numpy(),
+             psi=psi.detach().cpu().numpy(), step=np.int64(step),
+             params=np.array([params.eps, params.beta, params.M, params.h, params.dt,
+                              params.scheme, params.bc], dtype=np.float64))
+
+
+def load_state(path, device="cuda:0"):
+    """(phi, phi_prev, psi, step, params) from a file written by save_state."""
+    with np.load(path, allow_pickle=False) as z:
+        pr = z["params"]
+        params = Params(float(pr[0]), float(pr[1]), float(pr[2]), float(pr[3]), float(pr[4]),
+                        int(pr[5]), int(pr[6]))
+        dev = torch.device(device)
+        return (torch.from_numpy(z["phi"]).to(dev), torch.from_numpy(z["phi_prev"]).to(dev),
+                torch.from_numpy(z["psi"]).to(dev), int(z["step"]), params)
+
+
 # ---- operator-level wrappers (one V-cycle operation each) -------------------
 def _at_spacing(p: Params, h):
     """The parameters with the grid spacing of the level the operator acts on."""
