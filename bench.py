@@ -180,6 +180,15 @@ def bench_big(api, inputs, torch, dev, params, tol, steps, warmup, N=2048, inner
     res = {"workload": f"{N}x{N}, second-order scheme, crystallites seed 3, {steps} steps, "
                        "V(2,2) to 1e-10, energies off", "inner_cycles": inner}
     finals = {}
+    # the oracle's trajectory of this workload (FP64, solved to 1e-12 per step),
+    # sampled at fixed cells, for the first steps (tests/golden/make_fullsize.py)
+    gpath = os.path.join(ROOT, "tests", "golden", f"fullsize_{N}_seed3.npz")
+    golden = None
+    if os.path.exists(gpath):
+        import numpy as np
+        with np.load(gpath, allow_pickle=False) as z:
+            golden = {"idx": z["idx"], "phi": z["phi"], "steps": int(z["phi"].shape[0])}
+        gidx = torch.from_numpy(golden["idx"]).to(dev)
     for name, kw in (("fp64", dict(precision=0)), ("mixed", dict(precision=1, inner_cycles=inner))):
         st = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2, energy=0, **kw)
         phi = torch.from_numpy(phi0).to(dev)
@@ -194,16 +203,26 @@ def bench_big(api, inputs, torch, dev, params, tol, steps, warmup, N=2048, inner
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         cycles = outer = 0
-        for _ in range(steps):
+        sample = None
+        for k in range(steps):
             _, info = st.step(phi, prev, psi, nxt)
             cycles += info.n_cycles
             outer += info.outer_iters
             prev, phi, nxt = phi, nxt, prev
+            if golden is not None and k + 1 == min(steps, golden["steps"]):
+                sample = phi.view(-1)[gidx].clone()  # gathered on the stream, read after timing
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         res[name] = {"time_steps_per_s": steps / el, "vcycles_per_step": cycles / steps}
         if name == "mixed":
             res[name]["outer_per_step"] = outer / steps
+        if sample is not None:
+            k = min(steps, golden["steps"])
+            ref = golden["phi"][k - 1]
+            got = sample.cpu().numpy()
+            res[name]["rel_l2_vs_oracle"] = {
+                "step": k, "value": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                "cells": int(ref.size)}
         finals[name] = phi.cpu()
         st.close()
     d = (finals["mixed"] - finals["fp64"]).norm() / finals["fp64"].norm()

@@ -45,6 +45,7 @@ class Params:
     dt: float
     scheme: int
     bc: tuple = (0, 0)
+    omega: float = 1.0  # relaxation factor of the smoother's cell update (1: App. B)
 
     @property
     def alpha(self) -> float:
@@ -116,6 +117,7 @@ def load():
         "orc_version": (i, []),
         "orc_num_threads": (i, []),
         "orc_set_threads": (None, [i]),
+        "orc_set_omega": (None, [d]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -134,10 +136,12 @@ def set_threads(n: int) -> None:
     load().orc_set_threads(int(n))
 
 
-def _lib_bc(bc):
-    """The library with boundary conditions bc = (x, y) selected."""
+def _lib_bc(bc, omega=1.0):
+    """The library with boundary conditions bc = (x, y) and the smoother's
+    relaxation factor selected."""
     lib = load()
     lib.orc_set_bc(int(bc[0]), int(bc[1]))
+    lib.orc_set_omega(float(omega))
     return lib
 
 
@@ -192,7 +196,7 @@ def source(p: Params, phik, phikm1=None, psik=None, pin=None, phihat=None):
     w, ph = _pin(p, pin, phihat, need_hat=True)
     m, n = _shape(phik)
     S = [np.empty_like(phik) for _ in range(3)]
-    _lib_bc(p.bc).orc_source(ctypes.byref(p._c()), m, n, _p(phik), _p(phikm1), _p(psik),
+    _lib_bc(p.bc, p.omega).orc_source(ctypes.byref(p._c()), m, n, _p(phik), _p(phikm1), _p(psik),
                       *[_p(x) for x in S], _p(w), _p(ph))
     return S
 
@@ -205,7 +209,7 @@ def operator(p: Params, u, phik=None, h=None, pin=None):
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
     out = [np.empty_like(phi) for _ in range(3)]
     w, _ = _pin(p, pin)
-    _lib_bc(p.bc).orc_operator(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
+    _lib_bc(p.bc, p.omega).orc_operator(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
                         _p(phi), _p(mu), _p(ka), *[_p(x) for x in out], _p(w))
     return out
 
@@ -218,7 +222,7 @@ def residual(p: Params, u, f, phik=None, h=None, pin=None):
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
     out = [np.empty_like(phi) for _ in range(3)]
     w, _ = _pin(p, pin)
-    _lib_bc(p.bc).orc_residual(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
+    _lib_bc(p.bc, p.omega).orc_residual(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
                         _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3), *[_p(x) for x in out],
                         _p(w))
     return out
@@ -237,7 +241,7 @@ def smooth(p: Params, u, f, phik=None, sweeps=1, newton=True, h=None, order="rb"
     m, n = _shape(phi)
     c, _ = coefficients(p)
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
-    lib = _lib_bc(p.bc)
+    lib = _lib_bc(p.bc, p.omega)
     fn = lib.orc_smooth if order == "rb" else lib.orc_smooth_lex
     w, _ = _pin(p, pin)
     fn(p.scheme, int(newton), sweeps, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
@@ -251,7 +255,7 @@ def smooth_color(p: Params, u, f, color, phik=None, newton=True, h=None, pin=Non
     m, n = _shape(phi)
     c, _ = coefficients(p)
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
-    _lib_bc(p.bc).orc_smooth_color(p.scheme, int(newton), color, m, n, p.h if h is None else h, c,
+    _lib_bc(p.bc, p.omega).orc_smooth_color(p.scheme, int(newton), color, m, n, p.h if h is None else h, c,
                             p.alpha, _p(pk), _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3),
                             _p(_pin(p, pin)[0]))
     return [phi, mu, ka]
@@ -280,7 +284,7 @@ def dense_newton(p: Params, u, f, phik=None, h=None, maxit=50, pin=None):
     m, n = _shape(phi)
     c, _ = coefficients(p)
     pk = _arr(phik) if (p.scheme == 2 and phik is not None) else None
-    it = _lib_bc(p.bc).orc_dense_newton(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
+    it = _lib_bc(p.bc, p.omega).orc_dense_newton(p.scheme, m, n, p.h if h is None else h, c, p.alpha, _p(pk),
                                  _p(phi), _p(mu), _p(ka), _p(f1), _p(f2), _p(f3), maxit,
                                  _p(_pin(p, pin)[0]))
     return [phi, mu, ka], it
@@ -297,7 +301,7 @@ def fas_solve(p: Params, u0, S, phik=None, nu1=2, nu2=2, coarsest=2, tol=1e-10,
     c, _ = coefficients(p)
     pk = _arr(phik) if p.scheme == 2 else None
     hist = np.zeros(max_cycles + 1)
-    cyc = _lib_bc(p.bc).orc_fas_solve(p.scheme, int(newton), m, n, p.h, c, p.alpha, _p(pk), _p(phi),
+    cyc = _lib_bc(p.bc, p.omega).orc_fas_solve(p.scheme, int(newton), m, n, p.h, c, p.alpha, _p(pk), _p(phi),
                                _p(mu), _p(ka), _p(S1), _p(S2), _p(S3), nu1, nu2, coarsest,
                                coarse_sweeps, tol, max_cycles, _p(hist), _p(_pin(p, pin)[0]))
     ncyc = cyc if cyc >= 0 else -cyc - 1
@@ -309,7 +313,7 @@ def complete_guess(p: Params, phi, S, phik=None, pin=None):
     m, n = _shape(phi)
     mu, ka = np.empty_like(phi), np.empty_like(phi)
     pk = _arr(phik) if p.scheme == 2 else None
-    _lib_bc(p.bc).orc_complete_guess(p.scheme, m, n, p.h, p.alpha, _p(pk), _p(phi), _p(mu), _p(ka),
+    _lib_bc(p.bc, p.omega).orc_complete_guess(p.scheme, m, n, p.h, p.alpha, _p(pk), _p(phi), _p(mu), _p(ka),
                               _p(_arr(S[1])), _p(_arr(S[2])), _p(_pin(p, pin)[0]))
     return [phi.copy(), mu, ka]
 
@@ -318,14 +322,14 @@ def psi_update(p: Params, phinew, phik, psik):
     phinew, phik = _arr(phinew), _arr(phik)
     psik = _arr(psik) if psik is not None else None
     out = np.empty_like(phinew)
-    _lib_bc(p.bc).orc_psi_update(p.scheme, phinew.size, p.dt, _p(phinew), _p(phik), _p(psik), _p(out))
+    _lib_bc(p.bc, p.omega).orc_psi_update(p.scheme, phinew.size, p.dt, _p(phinew), _p(phik), _p(psik), _p(out))
     return out
 
 
 def energy_F(p: Params, phi):
     phi = _arr(phi)
     m, n = _shape(phi)
-    return _lib_bc(p.bc).orc_energy_F(m, n, p.h, p.eps, _p(phi))
+    return _lib_bc(p.bc, p.omega).orc_energy_F(m, n, p.h, p.eps, _p(phi))
 
 
 def grad_sq(f, bc=(0, 0)):
@@ -355,7 +359,7 @@ def energies(p: Params, phinew, phik, psinew, pin=None, phihat=None):
     m, n = _shape(phinew)
     out = np.zeros(4)
     w, ph = _pin(p, pin, phihat, need_hat=True)
-    _lib_bc(p.bc).orc_energies(m, n, p.h, p.eps, p.M, _p(phinew), _p(phik), _p(psinew), _p(out),
+    _lib_bc(p.bc, p.omega).orc_energies(m, n, p.h, p.eps, p.M, _p(phinew), _p(phik), _p(psinew), _p(out),
                                _p(w), _p(ph))
     return out
 
@@ -383,7 +387,7 @@ def step(p: Params, phik, phikm1=None, psik=None, guess=0, nu1=2, nu2=2, coarses
     outs = [np.empty_like(phik) for _ in range(4)]
     hist = np.zeros(max_cycles + 1)
     en = np.zeros(4)
-    cyc = _lib_bc(p.bc).orc_step(ctypes.byref(p._c()), int(newton), m, n, _p(phik), _p(phikm1),
+    cyc = _lib_bc(p.bc, p.omega).orc_step(ctypes.byref(p._c()), int(newton), m, n, _p(phik), _p(phikm1),
                           _p(psik), guess, nu1, nu2, coarsest, coarse_sweeps, tol, max_cycles,
                           *[_p(x) for x in outs], _p(hist), _p(en) if energy else None,
                           *[_p(x) for x in _pin(p, pin, phihat, need_hat=True)])

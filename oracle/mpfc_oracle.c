@@ -54,7 +54,16 @@
  *    the cell is updated (ghosts refreshed before every half-sweep), and the
  *    smoother's local 3x3 matrix stays the interior one; the residual, the
  *    transfers (the coarse ghost repeats the boundary coarse cell) and the
- *    coarsest-grid Newton matrix use the ghost rule exactly.
+ *    coarsest-grid Newton matrix use the ghost rule exactly;
+ *  - optional under-relaxation of the smoother (orc_set_omega; default 1, the
+ *    update of App. B unchanged): each cell moves by omega times its local
+ *    correction.  A local Fourier analysis of the linearised App. B smoother
+ *    shows it amplifies a band of error modes (spectral radius of one
+ *    red-black pass up to about 1.3) whenever c/h^4 lies in an intermediate
+ *    range; V-cycles then diverge for some time steps (first-order scheme,
+ *    h = 0.5: s from about 0.15 to 0.3), and omega near 0.8 restores a
+ *    contraction of about 0.2 per V(2,2) cycle there.  The fixed point (the
+ *    discrete solution) does not depend on omega.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -230,6 +239,16 @@ static double det3(double a0, double a1, double a2, double b0, double b1, double
  * App. B.1), then the 3x3 system in the cell's own unknowns solved by
  * Cramer's rule (App. B.1, B.2).  The right-hand side is the current residual
  * at the cell (correction form). */
+/* Relaxation factor of the cell update (orc_set_omega): the smoother moves
+ * each cell by omega times the solution of its local 3x3 system.  omega = 1
+ * is the collective Gauss-Seidel update of App. B; 0 < omega < 1
+ * under-relaxes it (not in the paper: a reading adopted because App. B's
+ * update amplifies a band of error modes whenever c/h^4 lies in an
+ * intermediate range, where V-cycles then diverge; see the file header). */
+static double g_omega = 1.0;
+
+void orc_set_omega(double omega) { g_omega = omega; }
+
 static void relax_cell(int scheme, int newton, int i, int j, int m, int n, double h, double c,
                        double alpha, const double *phik, double *phi, double *mu, double *ka,
                        const double *f1, const double *f2, const double *f3, const double *pin) {
@@ -256,9 +275,9 @@ static void relax_cell(int scheme, int newton, int i, int j, int m, int n, doubl
     double dx = det3(r1, a12, a13, r2, a22, a23, r3, a32, a33) / D;
     double dm = det3(a11, r1, a13, a21, r2, a23, a31, r3, a33) / D;
     double dk = det3(a11, a12, r1, a21, a22, r2, a31, a32, r3) / D;
-    phi[q] = x + dx;
-    mu[q] += dm;
-    ka[q] += dk;
+    phi[q] = x + g_omega * dx;
+    mu[q] += g_omega * dm;
+    ka[q] += g_omega * dk;
 }
 
 /* One half-sweep over the cells of one colour (colour = (i + j) mod 2,
