@@ -86,7 +86,15 @@ typedef struct {
  * norm and stopping test; u updated in FP64) around inner_cycles FP32 FAS
  * V-cycles per outer iteration on the correction equation N(u+e) - N(u) = r,
  * whose nonlinear difference is evaluated in factored form; max_cycles then
- * limits the outer iterations. */
+ * limits the outer iterations.
+ * omega: relaxation factor of the smoother, in (0, 2): each cell moves by
+ * omega times the solution of its local 3x3 system.  1 (the default) is the
+ * collective Gauss-Seidel update of App. B.  App. B's update amplifies a band
+ * of error modes when s M h^-4 / (beta + q/s) is in an intermediate range
+ * (q = 1 or 2 by scheme), where V-cycles can diverge (first-order scheme at
+ * h = 0.5: s from about 0.15 to 0.3); under-relaxation near 0.8 converges
+ * there.  The solution of the step does not depend on omega.  The 3-D
+ * contexts take omega = 1 only. */
 typedef struct {
     int nu1, nu2, max_cycles;
     double tol;
@@ -96,6 +104,7 @@ typedef struct {
     double diverge;
     int inner_cycles;
     int coarse_sweeps;
+    double omega;
 } mpfc_opts;
 
 /* Per-step report.  residual_history is a caller-owned host array of

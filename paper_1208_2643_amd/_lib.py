@@ -40,7 +40,8 @@ class mpfc_opts(ctypes.Structure):
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("guess", ctypes.c_int),
                 ("linearization", ctypes.c_int), ("coarsest", ctypes.c_int),
                 ("energy", ctypes.c_int), ("diverge", ctypes.c_double),
-                ("inner_cycles", ctypes.c_int), ("coarse_sweeps", ctypes.c_int)]
+                ("inner_cycles", ctypes.c_int), ("coarse_sweeps", ctypes.c_int),
+                ("omega", ctypes.c_double)]
 
 
 class mpfc_info(ctypes.Structure):

@@ -18,7 +18,9 @@ paths the red-black collective Gauss-Seidel smoother of App. B is unstable on
 its own (the residual grows by orders of magnitude per sweep, the CPU oracle
 alike) and V(2,2) cycles diverge; V(0,1) cycles (one red-black pass after the
 coarse-grid correction) converge in 8-14 cycles per step there.  So grids up
-to 128^2 run V(2,2) and finer ones V(0,1); the residual tolerance is 1e-11,
+to 128^2 run V(2,2) and finer ones V(0,1), unless the smoother is
+under-relaxed (omega < 1, e.g. 0.8), which makes V(2,2) converge on every
+grid of both paths (9-12 cycles per step); the residual tolerance is 1e-11,
 and 3e-11 on 512^2, where the FP64 residual of the first-order scheme
 (s = 0.025 h^2) levels off near 2e-11.  There the extrapolated guess often
 meets that tolerance without a cycle (its residual is at the floor too), and
@@ -38,18 +40,19 @@ import time
 import numpy as np
 
 
-def cycle_for(N: int, scheme: int):
+def cycle_for(N: int, scheme: int, omega: float = 1.0):
     """(nu1, nu2, tol, guess) of the solves on an N x N grid of these
-    refinement paths (guess 1: extrapolated, 0: the previous step's phi)."""
-    if N <= 128:
-        return 2, 2, 1e-11, 1
-    if N <= 256:
-        return 0, 1, 1e-11, 1
-    return 0, 1, 3e-11, (0 if scheme == 1 else 1)
+    refinement paths (guess 1: extrapolated, 0: the previous step's phi).
+    With an under-relaxed smoother (omega < 1) every grid runs V(2,2)."""
+    tol, guess = (1e-11, 1) if N <= 256 else (3e-11, 0 if scheme == 1 else 1)
+    if N <= 128 or omega != 1.0:
+        return 2, 2, tol, guess
+    return 0, 1, tol, guess
 
 
-def final_state(N: int, scheme: int, tol: float = None):
-    """phi at t_f = 10 on an N x N grid (a GPU tensor) and the run's statistics."""
+def final_state(N: int, scheme: int, tol: float = None, omega: float = 1.0):
+    """phi at t_f = 10 on an N x N grid (a GPU tensor) and the run's statistics
+    (omega: the smoother's relaxation factor)."""
     import torch
     from . import api, inputs
     h = 32.0 / N
@@ -60,10 +63,11 @@ def final_state(N: int, scheme: int, tol: float = None):
         s = 0.025 * h * h
         beta, M = 1.0 / 0.9, 1.0 / 0.9
     steps = int(round(10.0 / s))
-    nu1, nu2, tol_n, guess = cycle_for(N, scheme)
+    nu1, nu2, tol_n, guess = cycle_for(N, scheme, omega)
     tol = tol_n if tol is None else tol
     p = api.Params(eps=0.025, beta=beta, M=M, h=h, dt=s, scheme=scheme)
-    st = api.Stepper(N, N, p, tol=tol, energy=0, max_cycles=300, nu1=nu1, nu2=nu2, guess=guess)
+    st = api.Stepper(N, N, p, tol=tol, energy=0, max_cycles=300, nu1=nu1, nu2=nu2, guess=guess,
+                     omega=omega)
     phi = torch.from_numpy(inputs.paper_initial_data(N, N)).cuda()
     prev = phi.clone()
     psi = torch.zeros_like(phi)
@@ -79,18 +83,18 @@ def final_state(N: int, scheme: int, tol: float = None):
     torch.cuda.synchronize()
     st.close()
     return phi, {"N": N, "h": h, "s": s, "steps": steps, "cycle": f"V({nu1},{nu2})", "tol": tol,
-                 "guess": "extrapolated" if guess == 1 else "previous",
+                 "guess": "extrapolated" if guess == 1 else "previous", "omega": omega,
                  "vcycles_per_step": cycles / steps, "seconds": time.perf_counter() - t0}
 
 
-def table(scheme: int, sizes=(32, 64, 128, 256, 512)):
+def table(scheme: int, sizes=(32, 64, 128, 256, 512), omega: float = 1.0):
     """Rows (h_coarse, difference, rate) of the table of `scheme`."""
     from . import api
     from ._lib import MpfcError
     finals, stats = {}, []
     for N in sizes:
         try:
-            finals[N], st = final_state(N, scheme)
+            finals[N], st = final_state(N, scheme, omega=omega)
         except MpfcError as e:
             stats.append({"N": N, "error": str(e)})
             print(f"[convergence] scheme {scheme}, N = {N}: {e}", file=sys.stderr, flush=True)
@@ -112,9 +116,11 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--scheme", type=int, default=2, choices=(1, 2))
     ap.add_argument("--max-n", type=int, default=512)
+    ap.add_argument("--omega", type=float, default=1.0,
+                    help="relaxation factor of the smoother (below 1: V(2,2) on every grid)")
     a = ap.parse_args(argv)
     sizes = tuple(n for n in (32, 64, 128, 256, 512) if n <= a.max_n)
-    rows, stats = table(a.scheme, sizes)
+    rows, stats = table(a.scheme, sizes, omega=a.omega)
     print(json.dumps({"scheme": a.scheme, "rows": rows, "runs": stats}), flush=True)
 
 

@@ -78,6 +78,7 @@ struct LevelOp {
     T c;     // s M/(beta + 1/s) or s M/(beta + 2/s)
     T al;    // alpha (scheme 1) or alpha/2 (scheme 2)
     T e;     // 1 (scheme 1) or 1/2 (scheme 2): N^(3) = kappa - e Lap phi
+    T w = T(1);  // relaxation factor of the smoother's cell update (1: App. B)
 };
 
 // Boundary conditions, per axis (App. A): periodic (eqs. per-bcs) unless the
@@ -193,9 +194,9 @@ __device__ __forceinline__ void relax_at(const Fields<T>& F, const LevelOp<T>& o
     const T dm = (r2 + (d + b * ec) * r1 - b * r3) / det;
     const T dx = r1 - a * dm;
     const T dk = r3 - ec * dx;
-    F.phi[q] = x + dx;
-    F.mu[q] += dm;
-    F.ka[q] += dk;
+    F.phi[q] = x + op.w * dx;
+    F.mu[q] += op.w * dm;
+    F.ka[q] += op.w * dk;
 }
 
 // r = f - N(u) on every cell (operator-level entry point).

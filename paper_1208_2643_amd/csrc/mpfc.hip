@@ -181,6 +181,7 @@ LevelOp<double> level_op(const mpfc_ctx* C, const Level& lv) {
     op.c = C->c;
     op.al = C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha;
     op.e = C->p.scheme == 1 ? 1.0 : 0.5;
+    op.w = C->o.omega;
     return op;
 }
 
@@ -351,6 +352,7 @@ Op make_op32(const mpfc_ctx* C, const Level& lv) {
     o.op.c = (float)C->c;
     o.op.al = (float)(C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha);
     o.op.e = (float)(C->p.scheme == 1 ? 1.0 : 0.5);
+    o.op.w = (float)C->o.omega;
     return o;
 }
 
@@ -1010,6 +1012,8 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
         return fail(MPFC_EINVAL, "inner_cycles must be in [1, 16]");
     if (o->coarse_sweeps < 1 || o->coarse_sweeps > 64)
         return fail(MPFC_EINVAL, "coarse_sweeps must be in [1, 64]");
+    if (!(o->omega > 0.0 && o->omega < 2.0))
+        return fail(MPFC_EINVAL, "omega must be in (0, 2)");
     if (gen) {
         // general-index kernels: FP64, halos up to 6, coarsest level in one workgroup
         if (o->precision != MPFC_FP64)
@@ -1301,6 +1305,7 @@ void mpfc_default_opts(mpfc_opts* o) {
     o->diverge = 1e8;
     o->inner_cycles = 3;
     o->coarse_sweeps = 2;
+    o->omega = 1.0;
 }
 
 int mpfc_validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {

@@ -69,9 +69,9 @@ struct MpfcOp {
         const T dm = (r2 + (d + b * ec) * r1 - b * r3) / det;
         const T dx = r1 - a * dm;
         const T dk = r3 - ec * dx;
-        u[0] += dx;
-        u[1] += dm;
-        u[2] += dk;
+        u[0] += op.w * dx;
+        u[1] += op.w * dm;
+        u[2] += op.w * dk;
     }
 };
 

@@ -74,6 +74,11 @@ int main(void) {
     { mpfc_opts q = o; q.coarse_sweeps = 65; EXPECT(mpfc_validate(512, 400, &p, &q) == MPFC_EINVAL); }
     { mpfc_opts q = o; q.precision = MPFC_MIXED; EXPECT(mpfc_validate(512, 400, &p, &q) == MPFC_EINVAL); }
     { mpfc_opts q = o; q.precision = MPFC_MIXED; EXPECT(mpfc_validate(512, 512, &p, &q) == MPFC_OK); }
+    { mpfc_opts q = o; q.omega = 0.0; EXPECT(mpfc_validate(64, 64, &p, &q) == MPFC_EINVAL); }
+    { mpfc_opts q = o; q.omega = 2.0; EXPECT(mpfc_validate(64, 64, &p, &q) == MPFC_EINVAL); }
+    { mpfc_opts q = o; q.omega = NAN; EXPECT(mpfc_validate(64, 64, &p, &q) == MPFC_EINVAL); }
+    { mpfc_opts q = o; q.omega = 0.8; EXPECT(mpfc_validate(64, 64, &p, &q) == MPFC_OK); }
+    { mpfc_opts q = o; q.omega = 0.8; EXPECT(mpfc3d_validate(64, 64, 64, &p, &q) == MPFC_EINVAL); }
 
     /* three dimensions */
     EXPECT(mpfc3d_validate(64, 64, 64, &p, &o) == MPFC_OK);

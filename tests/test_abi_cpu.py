@@ -94,7 +94,8 @@ def test_coarse_sweeps_range(value):
 
 @pytest.mark.parametrize("field,value", [("tol", 0.0), ("max_cycles", 0), ("nu1", -1),
                                          ("coarsest", 3), ("precision", 7), ("guess", 9),
-                                         ("linearization", 5), ("diverge", 0.5)])
+                                         ("linearization", 5), ("diverge", 0.5),
+                                         ("omega", 0.0), ("omega", 2.0), ("omega", float("nan"))])
 def test_invalid_opts_rejected(field, value):
     p, o = good()
     setattr(o, field, value)
@@ -221,3 +222,14 @@ def test_operator_entry_points_validate_params_on_the_host():
         == L.MPFC_EINVAL
     assert lib.mpfc_op_smooth(ctypes.byref(p), 7, 64, 64, z, z, z, z, z, z, z, 1, None) \
         == L.MPFC_EINVAL
+
+
+def test_relaxation_factor_default_and_range():
+    """omega defaults to App. B's update (1); under-relaxation validates in 2-D,
+    the 3-D step takes omega = 1 only."""
+    p, o = good()
+    assert o.omega == 1.0
+    o.omega = 0.8
+    assert L.load().mpfc_validate(64, 64, ctypes.byref(p), ctypes.byref(o)) == 0
+    assert L.load().mpfc_validate(512, 400, ctypes.byref(p), ctypes.byref(o)) == 0
+    assert L.load().mpfc3d_validate(64, 64, 64, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
