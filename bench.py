@@ -41,6 +41,8 @@ COMPULSORY_BYTES = {"down": 56.0 + 24.0 + 20.0, "up": 56.0 + 12.0 + 24.0}
 # The pinning weight W (8 B per cell) adds one read per sweep and per residual
 # pass: down 2 sweeps + residual, up 2 sweeps + norm.
 PIN_BYTES = {"down": 3 * 8.0, "up": 3 * 8.0}
+# Relaxation factor of the smoother in the relaxed variants (App. B: 1).
+RELAXED_OMEGA = 0.9
 # One whole V(2,2) cycle, FP64, scheme 2, per finest cell: 468 B on the
 # finest level (2 x 2 sweeps of 80 B, residual and restriction 68 B, coarse
 # FAS right-hand side 20 B, prolongation 60 B), 4/3 of it over all levels, and
@@ -507,6 +509,7 @@ def main():
     elapsed = time.perf_counter() - t0
     steps_per_s = args.steps / elapsed
     total_cycles = int(sum(cycles))
+    final_state = phi.clone()  # after warmup + steps, for the variants' comparison
 
     # Live per-kernel timing of the two finest-level launches (HIP events on
     # the library's stream), over a second timed region of the same workload.
@@ -598,29 +601,49 @@ def main():
     if args.variants:
         out["variants"] = {"fp64": {"time_steps_per_s": steps_per_s,
                                     "vcycles_per_step": total_cycles / args.steps}}
-        stm = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2,
-                          energy=0 if args.no_energy else 1, precision=1)
-        p_, q_, s_ = (torch.from_numpy(phi0).to(dev), torch.from_numpy(phi0).to(dev),
-                      torch.zeros_like(phi))
-        n_ = torch.empty_like(phi)
-        for _ in range(args.warmup):
-            stm.step(p_, q_, s_, n_)
-            q_, p_, n_ = p_, n_, q_
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        outer = inner = 0
-        vsteps = args.steps
-        for _ in range(vsteps):
-            _, inf = stm.step(p_, q_, s_, n_)
-            q_, p_, n_ = p_, n_, q_
-            outer += inf.outer_iters
-            inner += inf.n_cycles
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t1
-        out["variants"]["mixed"] = {"time_steps_per_s": vsteps / el, "steps": vsteps,
-                                    "outer_per_step": outer / vsteps,
-                                    "fp32_vcycles_per_step": inner / vsteps,
-                                    "speedup_vs_fp64": vsteps / el / steps_per_s}
+
+        def same_workload(**opts):
+            """The headline's protocol (warmup steps, then args.steps timed) in
+            a fresh context with other solver options."""
+            sv = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2,
+                             energy=0 if args.no_energy else 1, **opts)
+            p_, q_, s_ = (torch.from_numpy(phi0).to(dev), torch.from_numpy(phi0).to(dev),
+                          torch.zeros_like(phi))
+            n_ = torch.empty_like(phi)
+            for _ in range(args.warmup):
+                sv.step(p_, q_, s_, n_)
+                q_, p_, n_ = p_, n_, q_
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            outer = cyc = 0
+            for _ in range(args.steps):
+                _, inf = sv.step(p_, q_, s_, n_)
+                q_, p_, n_ = p_, n_, q_
+                outer += inf.outer_iters
+                cyc += inf.n_cycles
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t1
+            sv.close()
+            d = float(torch.linalg.norm(p_ - final_state) / torch.linalg.norm(final_state))
+            r = {"time_steps_per_s": args.steps / el, "steps": args.steps,
+                 "speedup_vs_fp64": args.steps / el / steps_per_s,
+                 "final_state_rel_l2_vs_fp64": d}
+            if opts.get("precision") == 1:
+                r.update(outer_per_step=outer / args.steps, fp32_vcycles_per_step=cyc / args.steps)
+            else:
+                r.update(vcycles_per_step=cyc / args.steps,
+                         ms_per_vcycle=1e3 * el / max(1, cyc))
+            return r
+
+        # mixed precision: FP32 correction cycles inside FP64 defect correction
+        out["variants"]["mixed"] = same_workload(precision=1, inner_cycles=3)
+        # App. B's smoother under-relaxed (omega = 0.9): same discrete solution,
+        # fewer V-cycles per step; alone and with mixed precision
+        out["variants"]["relaxed_smoother"] = dict(
+            omega=RELAXED_OMEGA, **same_workload(omega=RELAXED_OMEGA))
+        out["variants"]["relaxed_mixed"] = dict(
+            omega=RELAXED_OMEGA, inner_cycles=2,
+            **same_workload(omega=RELAXED_OMEGA, precision=1, inner_cycles=2))
     # The same workload with Sec. 4.5's boundary conditions: periodic in x,
     # homogeneous Neumann in y (App. A), FP64, energies as above.
     if args.variants and args.bc_steps > 0:
