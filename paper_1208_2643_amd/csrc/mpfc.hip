@@ -80,6 +80,8 @@ dim3 grid1(size_t total) { return dim3((unsigned)((total + 255) / 256)); }
 // partial sums (up to 8 values) to `part`; one workgroup per CU left these
 // passes latency bound.
 constexpr unsigned kRedBlocks = 1024;
+// Values per reduction workgroup in the step's wrap-up (k_wrap_rhs_terms).
+constexpr unsigned kWrapSums = 12;
 unsigned red_blocks(size_t total) {
     size_t b = (total + NT - 1) / NT;
     return (unsigned)(b < kRedBlocks ? b : kRedBlocks);
@@ -1228,7 +1230,7 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
     return MPFC_OK;
 }
 
-void enqueue_energy_terms(mpfc_ctx* C, hipStream_t s);
+void enqueue_energy_terms(mpfc_ctx* C, hipStream_t s, bool warm);
 
 // Wrap-up of a step, enqueued behind its cycles (every kernel gated on the
 // step's cycle state, wrapup.hpp): psi^{k+1} and phi^{k+1} into the caller's
@@ -1241,16 +1243,20 @@ void enqueue_wrapup(mpfc_ctx* C, hipStream_t s, bool warm, int npoisson) {
     const size_t total = (size_t)C->m * C->n;
     const int mixed = C->o.precision == MPFC_MIXED;
     const StepIO* io = C->io;
-    if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_wrap_psi<1>), grid1(total), dim3(256), 0, s, io, C->st, mixed,
-                           F0.u[0][0], F0.u[1][0], total, C->p.dt);
-    else
-        hipLaunchKernelGGL((k_wrap_psi<2>), grid1(total), dim3(256), 0, s, io, C->st, mixed,
-                           F0.u[0][0], F0.u[1][0], total, C->p.dt);
-    if (!C->o.energy) return;
+    if (!C->o.energy) {
+        if (C->p.scheme == 1)
+            hipLaunchKernelGGL((k_wrap_psi<1>), grid1(total), dim3(256), 0, s, io, C->st, mixed,
+                               F0.u[0][0], F0.u[1][0], total, C->p.dt);
+        else
+            hipLaunchKernelGGL((k_wrap_psi<2>), grid1(total), dim3(256), 0, s, io, C->st, mixed,
+                               F0.u[0][0], F0.u[1][0], total, C->p.dt);
+        return;
+    }
     const unsigned rb = red_blocks(total);
-    hipLaunchKernelGGL((k_wrap_sums<NT>), dim3(rb), dim3(NT), 0, s, io, C->st, mixed, F0.u[0][1],
-                       F0.u[1][1], warm ? 1 : 0, total, C->part, C->pst);
+    // psi^{k+1}, phi^{k+1} and the sums of psi^{k+1} and mu (acc[8], acc[9])
+    auto k1 = C->p.scheme == 1 ? k_wrap_psi_sums<1, NT> : k_wrap_psi_sums<2, NT>;
+    hipLaunchKernelGGL(k1, dim3(rb), dim3(NT), 0, s, io, C->st, mixed, F0.u[0][0], F0.u[1][0],
+                       F0.u[0][1], F0.u[1][1], warm ? 1 : 0, total, C->p.dt, C->part, C->pst);
     hipLaunchKernelGGL((k_wrap_partials<NT>), dim3(1), dim3(NT), 0, s, C->st, C->part, (int)rb, 2,
                        C->acc + 8);
     if (!warm) {
@@ -1263,29 +1269,34 @@ void enqueue_wrapup(mpfc_ctx* C, hipStream_t s, bool warm, int npoisson) {
         hipLaunchKernelGGL(k_wrap_w_advance, grid1(total), dim3(256), 0, s, C->st, mixed,
                            F0.u[0][1], F0.u[1][1], F0.w[0], total, a, b, C->acc + 9);
     }
-    hipLaunchKernelGGL((k_wrap_rhs_resid<NT>), dim3(rb), dim3(NT), 0, s, C->st, io, F0.g,
-                       1.0 / (F0.h * F0.h), C->acc + 8, F0.pf, warm ? F0.w[0] : nullptr, C->part);
-    hipLaunchKernelGGL((k_wrap_partials<NT>), dim3(1), dim3(NT), 0, s, C->st, C->part, (int)rb, 2,
-                       C->acc + 10);
+    // b = psi - mean, its square sum (acc[10]), the warm start's squared
+    // residual (acc[11]) and the energy sums with the warm start (acc[0..7])
+    hipLaunchKernelGGL((k_wrap_rhs_terms<NT>), dim3(rb), dim3(NT), 0, s, C->st, io, F0.g,
+                       1.0 / (F0.h * F0.h), C->acc + 8, F0.pf, warm ? F0.w[0] : nullptr, C->part,
+                       (const double*)(C->pinned ? F0.pin : nullptr),
+                       (const double*)(C->pinned ? C->phihat : nullptr));
+    hipLaunchKernelGGL((k_wrap_partials<NT>), dim3(1), dim3(NT), 0, s, C->st, C->part, (int)rb, 12,
+                       C->acc);
     // the warm start's residual is the first norm of the Poisson solve: it
     // may already meet the test, and the cycles behind it then exit at once
     if (warm)
         hipLaunchKernelGGL((k_p_finalize<NT>), dim3(1), dim3(NT), 0, s, C->acc + 11, 1, C->pst,
                            C->phist, C->acc + 10, kPoissonRel, kPoissonStall, kPoissonMax);
     for (int k = 0; k < npoisson; ++k) vcycle_poisson(C, s);
-    enqueue_energy_terms(C, s);
+    enqueue_energy_terms(C, s, warm);
 }
 
-// Energy sums of phi^{k+1} (gated on the step's state) into acc[0..7].
-void enqueue_energy_terms(mpfc_ctx* C, hipStream_t s) {
+// Energy sums of phi^{k+1} with the Poisson cycles' w into acc[0..7], when
+// any cycle ran (gated on the step's and the Poisson solve's states).
+void enqueue_energy_terms(mpfc_ctx* C, hipStream_t s, bool warm) {
     Level& F0 = C->L[0];
     const unsigned rb = red_blocks((size_t)C->m * C->n);
-    hipLaunchKernelGGL((k_wrap_terms<NT>), dim3(rb), dim3(NT), 0, s, C->st, (const StepIO*)C->io,
-                       F0.g, 1.0 / (F0.h * F0.h), F0.pf, F0.w[0], C->part,
+    hipLaunchKernelGGL((k_wrap_terms<NT>), dim3(rb), dim3(NT), 0, s, C->st, C->pst, warm ? 1 : 0,
+                       (const StepIO*)C->io, F0.g, 1.0 / (F0.h * F0.h), F0.pf, F0.w[0], C->part,
                        (const double*)(C->pinned ? F0.pin : nullptr),
                        (const double*)(C->pinned ? C->phihat : nullptr));
-    hipLaunchKernelGGL((k_wrap_partials<NT>), dim3(1), dim3(NT), 0, s, C->st, C->part, (int)rb, 8,
-                       C->acc);
+    hipLaunchKernelGGL((k_wrap_terms_sum<NT>), dim3(1), dim3(NT), 0, s, C->st, C->pst,
+                       warm ? 1 : 0, C->part, (int)rb, C->acc);
 }
 
 }  // namespace
@@ -1464,9 +1475,9 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
         C->io = (StepIO*)take(8);
         C->phist = take(64);
         // one partial sum per finest tile (general grids: tiles down to 2 x 2),
-        // and at least 8 per reduction workgroup
+        // and at least kWrapSums per reduction workgroup
         const size_t cells_per_part = C->gen ? 4 : 256;
-        const size_t min_parts = (size_t)kRedBlocks * 8;
+        const size_t min_parts = (size_t)kRedBlocks * kWrapSums;
         C->nparts = (int)((size_t)m * n / cells_per_part > min_parts ? (size_t)m * n / cells_per_part
                                                                       : min_parts);
         C->part = take((size_t)C->nparts);
@@ -1609,7 +1620,7 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
                 rc = run_poisson_cycle(C);
                 if (rc) return rc;
             }
-            enqueue_energy_terms(C, s);
+            enqueue_energy_terms(C, s, warm);
             HIP_TRY(hipGetLastError());
             rc = readback(32);
             if (rc) return rc;

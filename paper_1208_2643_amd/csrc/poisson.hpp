@@ -22,17 +22,26 @@ __global__ void __launch_bounds__(256) k_fill(T* a, size_t n, T v) {
     if (t < n) a[t] = v;
 }
 
-// out[k] = sum over b < nparts of part[b * nvals + k], for k < nvals (one block).
+// out[k] = sum over b < nparts of part[b * nvals + k], for k < nvals <= NT (one
+// block).  Thread t < (NT / nvals) * nvals adds the values of one k in a
+// fixed stride, reading consecutive addresses with its neighbours; then
+// thread k adds the NT / nvals thread sums of value k in order.
 template <int NT>
 __device__ __forceinline__ void partials_sum_body(const double* __restrict__ part, int nparts,
                                                   int nvals, double* out) {
-    __shared__ double red[NT / 64];
-    for (int k = 0; k < nvals; ++k) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nparts; b += NT) s += part[(size_t)b * nvals + k];
-        const double tot = block_sum<NT>(s, red);
-        if (threadIdx.x == 0) out[k] = tot;
-        __syncthreads();
+    __shared__ double red[NT];
+    const int t = threadIdx.x, per = NT / nvals;
+    double s = 0.0;
+    if (t < per * nvals) {
+        const int k = t % nvals;
+        for (int b = t / nvals; b < nparts; b += per) s += part[(size_t)b * nvals + k];
+    }
+    red[t] = s;
+    __syncthreads();
+    if (t < nvals) {
+        double tot = 0.0;
+        for (int r = 0; r < per; ++r) tot += red[r * nvals + t];
+        out[t] = tot;
     }
 }
 

@@ -27,7 +27,8 @@ __device__ __forceinline__ int final_copy(const CycleState* st, int mixed) {
     return mixed ? 1 ^ ((st->count - 1) & 1) : 0;
 }
 
-// psi^{k+1} in place on the caller's psi and phi^{k+1} into the caller's array.
+// psi^{k+1} in place on the caller's psi and phi^{k+1} into the caller's array
+// (steps without energies).
 template <int SCHEME>
 __global__ void __launch_bounds__(256) k_wrap_psi(const StepIO* __restrict__ io,
                                                   const CycleState* st, int mixed,
@@ -41,15 +42,19 @@ __global__ void __launch_bounds__(256) k_wrap_psi(const StepIO* __restrict__ io,
     psi_cell<SCHEME>(s, phi, io->phi_n, io->psi, io->phi_np1, q);
 }
 
-// Per-block sums of psi^{k+1} and (advance) of the step's mu into
-// part[blk * 2 + 0/1]; block 0 resets the Poisson cycle state, or, while the
+// psi^{k+1} in place on the caller's psi, phi^{k+1} into the caller's array,
+// and per-block sums of psi^{k+1} and (advance) of the step's mu into
+// part[blk * 2 + 0/1].  Block 0 resets the Poisson cycle state, or, while the
 // wrap-up is off, marks it stopped so that the Poisson cycles skip too.
-template <int NT>
-__global__ void __launch_bounds__(NT) k_wrap_sums(const StepIO* __restrict__ io,
-                                                  const CycleState* st, int mixed,
-                                                  const double* __restrict__ mu0,
-                                                  const double* __restrict__ mu1, int advance,
-                                                  size_t total, double* part, CycleState* pst) {
+template <int SCHEME, int NT>
+__global__ void __launch_bounds__(NT) k_wrap_psi_sums(const StepIO* __restrict__ io,
+                                                      const CycleState* st, int mixed,
+                                                      const double* __restrict__ phi0,
+                                                      const double* __restrict__ phi1,
+                                                      const double* __restrict__ mu0,
+                                                      const double* __restrict__ mu1, int advance,
+                                                      size_t total, double s, double* part,
+                                                      CycleState* pst) {
     __shared__ double red[NT / 64];
     const bool off = wrapup_off(st);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -61,12 +66,15 @@ __global__ void __launch_bounds__(NT) k_wrap_sums(const StepIO* __restrict__ io,
         }
     }
     if (off) return;
-    const double* x = io->psi;
-    const double* y = advance ? (final_copy(st, mixed) ? mu1 : mu0) : nullptr;
+    const int fc = final_copy(st, mixed);
+    const double* phi = fc ? phi1 : phi0;
+    const double* mu = advance ? (fc ? mu1 : mu0) : nullptr;
+    double* psi = io->psi;
     double sx = 0.0, sy = 0.0;
     for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
-        sx += x[q];
-        if (y) sy += y[q];
+        psi_cell<SCHEME>(s, phi, io->phi_n, psi, io->phi_np1, q);
+        sx += psi[q];
+        if (mu) sy += mu[q];
     }
     const double tx = block_sum<NT>(sx, red);
     __syncthreads();
@@ -107,28 +115,105 @@ __global__ void __launch_bounds__(256) k_wrap_w_advance(const CycleState* st, in
     w[q] = a * w[q] - b * (mu[q] - mean);
 }
 
-// b = psi^{k+1} - mean and the sums of b^2 and of the warm start's residual.
+// One pass over the grid after the psi update: b = psi^{k+1} - mean (the
+// Poisson right-hand side), the sums of b^2 and of the warm start's squared
+// residual (b + Lap_h w)^2 (w null: cold start, no residual), and the energy
+// sums of phi^{k+1} with phi^k as the previous state (energy_terms_body's
+// eight), per block into part[blk * 12 + k]: k < 8 the energy sums, 8 and 9
+// zero, 10 the sum of b^2, 11 the residual sum (the slots of the step's
+// accumulator array that the Poisson cycles read).  The term sum (b, w) uses
+// the warm start; k_wrap_terms recomputes the energy sums when Poisson cycles
+// ran.
 template <int NT>
-__global__ void __launch_bounds__(NT) k_wrap_rhs_resid(const CycleState* st,
+__global__ void __launch_bounds__(NT) k_wrap_rhs_terms(const CycleState* st,
                                                        const StepIO* __restrict__ io, Grid g,
-                                                       double ih2, const double* __restrict__ sum,
-                                                       double* b, const double* __restrict__ w,
-                                                       double* part) {
+                                                       double ih2,
+                                                       const double* __restrict__ sum, double* b,
+                                                       const double* __restrict__ w, double* part,
+                                                       const double* __restrict__ pin,
+                                                       const double* __restrict__ phihat) {
     if (wrapup_off(st)) return;
-    p_rhs_resid_body<NT>(g, ih2, io->psi, sum, b, w, part);
+    __shared__ double red[NT / 64][10];
+    const size_t total = (size_t)g.m * g.n;
+    const double mean = sum[0] / (double)total;
+    const double* phi = io->phi_np1;
+    const double* phiprev = io->phi_n;
+    const double* psi = io->psi;
+    double a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
+        int i, j;
+        cell_of(q, g, i, j);
+        const double v = psi[q] - mean;
+        b[q] = v;
+        a[8] += v * v;
+        if (w) {
+            const double r = v - (4.0 * w[q] - nsum(w, i, j, g)) * ih2;
+            a[9] += r * r;
+            a[6] += v * w[q];
+        }
+        const double x = phi[q];
+        const size_t qe = at(wrapx(i + 1, g), j, g), qn = at(i, wrapy(j + 1, g), g);
+        const double xe = phi[qe], xn = phi[qn];
+        const double L = (nsum(phi, i, j, g) - 4.0 * x) * ih2;
+        a[0] += (x * x) * (x * x);
+        a[1] += x * x;
+        a[2] += (xe - x) * (xe - x) + (xn - x) * (xn - x);
+        a[3] += L * L;
+        a[4] += x;
+        const double d = x - phiprev[q];
+        const double de = xe - phiprev[qe] - d;
+        const double dn = xn - phiprev[qn] - d;
+        a[5] += de * de + dn * dn;
+        if (pin) {  // pinning energy sum W (phi - phi_hat)^2 (Sec. 4.6)
+            const double dp = x - phihat[q];
+            a[7] += pin[q] * dp * dp;
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        const double v = wave_sum(a[k]);
+        if (lane == 0) red[wid][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        const int k = threadIdx.x < 8 ? threadIdx.x : threadIdx.x - 2;
+        double s = 0.0;
+        if (threadIdx.x < 8 || threadIdx.x >= 10) {
+#pragma unroll
+            for (int wv = 0; wv < NT / 64; ++wv) s += red[wv][k];
+        }
+        part[(size_t)blockIdx.x * 12 + threadIdx.x] = s;
+    }
 }
 
-// Energy sums of phi^{k+1} (the caller's array, written by k_wrap_psi) with
-// phi^k as the previous state.
+// The energy sums once more, with the solution w of the Poisson cycles, when
+// any ran (cold start, or a warm start that did not pass the test); else the
+// sums of k_wrap_rhs_terms stand.
+__device__ __forceinline__ bool terms_again(const CycleState* st, const CycleState* pst,
+                                            int warm) {
+    return !wrapup_off(st) && (!warm || pst->count > 1);
+}
+
 template <int NT>
-__global__ void __launch_bounds__(NT) k_wrap_terms(const CycleState* st,
-                                                   const StepIO* __restrict__ io, Grid g,
-                                                   double ih2, const double* __restrict__ b,
+__global__ void __launch_bounds__(NT) k_wrap_terms(const CycleState* st, const CycleState* pst,
+                                                   int warm, const StepIO* __restrict__ io,
+                                                   Grid g, double ih2,
+                                                   const double* __restrict__ b,
                                                    const double* __restrict__ w, double* part,
                                                    const double* __restrict__ pin,
                                                    const double* __restrict__ phihat) {
-    if (wrapup_off(st)) return;
+    if (!terms_again(st, pst, warm)) return;
     energy_terms_body<NT>(g, ih2, io->phi_np1, io->phi_n, b, w, part, pin, phihat);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_wrap_terms_sum(const CycleState* st,
+                                                       const CycleState* pst, int warm,
+                                                       const double* __restrict__ part,
+                                                       int nparts, double* out) {
+    if (!terms_again(st, pst, warm)) return;
+    partials_sum_body<NT>(part, nparts, 8, out);
 }
 
 }  // namespace mpfc
