@@ -148,7 +148,8 @@ int mpfc_create(mpfc_ctx **out, int m, int n, const mpfc_params *p, const mpfc_o
  *              the start-up rule of Sec. 3.2)
  *   d_psi      psi^k on entry, psi^{k+1} on return (required: for scheme 2
  *              psi carries the history of the run, eq. discrete_2_b; the
- *              first step uses psi^0 = 0)
+ *              first step uses psi^0 = 0; must not alias d_phi_n or
+ *              d_phi_nm1)
  *   d_phi_np1  phi^{k+1} (written; must not alias the inputs)
  *   d_mu, d_kappa  optional outputs (NULL to skip): mu^{k+1} (mu^{k+1/2} for
  *              scheme 2) and kappa

@@ -38,6 +38,23 @@ __device__ __forceinline__ bool stopped(const CycleState* st) {
 }
 
 // ---------------------------------------------------------------------------
+// 1/x for x >= 1 (the determinant of the smoother's local system, 1 + a d +
+// a b e_c with a, b, e_c, d >= 0): the hardware reciprocal estimate refined by
+// Newton steps e = 1 - x r, r += r e (two in FP64, one in FP32), within an
+// ulp of the correctly rounded quotient and shorter than a division.
+__device__ __forceinline__ double recip_ge1(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip_ge1(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// ---------------------------------------------------------------------------
 // Nonlinear term of N^(2) (App. B.1: phi^3; App. B.2: chi(phi, phi^k)(phi + phi^k)/2
 // with chi(a, b) = (a^2 + b^2)/2) and its derivative.  In DEFECT mode v is a
 // correction to the base value pb and the value is g(pb + v) - g(pb).
@@ -191,7 +208,7 @@ __device__ __forceinline__ void relax_at(const Fields<T>& F, const LevelOp<T>& o
     const T d = op.al + (F.pin ? F.pin[q] : T(0)) + nl_lin<T, SCHEME, NEWTON>(pb + x, xk);
     const T a = T(4) * op.c * op.ih2, b = T(4) * op.ih2, ec = T(4) * op.e * op.ih2;
     const T det = T(1) + a * d + a * b * ec;
-    const T dm = (r2 + (d + b * ec) * r1 - b * r3) / det;
+    const T dm = (r2 + (d + b * ec) * r1 - b * r3) * recip_ge1(det);
     const T dx = r1 - a * dm;
     const T dk = r3 - ec * dx;
     F.phi[q] = x + op.w * dx;

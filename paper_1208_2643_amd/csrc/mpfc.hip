@@ -1543,6 +1543,8 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     if (!phi_n || !psi || !phi_np1) return fail(MPFC_EINVAL, "phi_n, psi and phi_np1 are required");
     if (phi_np1 == phi_n || phi_np1 == phi_nm1 || phi_np1 == psi)
         return fail(MPFC_EINVAL, "phi_np1 must not alias an input");
+    if (psi == phi_n || psi == phi_nm1)
+        return fail(MPFC_EINVAL, "psi (updated in place) must not alias phi_n or phi_nm1");
     if (!phi_nm1) phi_nm1 = phi_n;
     if (C->o.guess == MPFC_GUESS_CNN && !C->cnn)
         return fail(MPFC_EINVAL, "guess mode MPFC_GUESS_CNN needs a network (mpfc_cnn_load)");

@@ -33,8 +33,18 @@ __device__ __forceinline__ void partials_sum_body(const double* __restrict__ par
     const int t = threadIdx.x, per = NT / nvals;
     double s = 0.0;
     if (t < per * nvals) {
+        // four loads in flight per thread: blocks b, b + per, b + 2 per, b + 3 per
         const int k = t % nvals;
-        for (int b = t / nvals; b < nparts; b += per) s += part[(size_t)b * nvals + k];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int b = t / nvals;
+        for (; b + 3 * per < nparts; b += 4 * per) {
+            s0 += part[(size_t)b * nvals + k];
+            s1 += part[(size_t)(b + per) * nvals + k];
+            s2 += part[(size_t)(b + 2 * per) * nvals + k];
+            s3 += part[(size_t)(b + 3 * per) * nvals + k];
+        }
+        for (; b < nparts; b += per) s0 += part[(size_t)b * nvals + k];
+        s = (s0 + s1) + (s2 + s3);
     }
     red[t] = s;
     __syncthreads();

@@ -66,7 +66,7 @@ struct MpfcOp {
         const T d = (PIN ? op.al + w : op.al) + nl_lin<T, SCHEME, NEWTON>(pb + u[0], xk);
         const T a = T(4) * op.c * op.ih2, b = T(4) * op.ih2, ec = T(4) * op.e * op.ih2;
         const T det = T(1) + a * d + a * b * ec;
-        const T dm = (r2 + (d + b * ec) * r1 - b * r3) / det;
+        const T dm = (r2 + (d + b * ec) * r1 - b * r3) * recip_ge1(det);
         const T dx = r1 - a * dm;
         const T dk = r3 - ec * dx;
         u[0] += op.w * dx;
@@ -707,7 +707,8 @@ __device__ __forceinline__ void coarse_solve_mpfc(const Op& op, typename Op::rea
                 J[a][b] = (a == b ? T(1) : T(0)) - c * (L[a][b] * d[b] + e * L3[a][b]);
             J[a][NC] = -R[a];
         }
-        // Gaussian elimination with partial pivoting
+        // Gaussian elimination with partial pivoting (one division per pivot)
+        T ip[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
 #pragma unroll
@@ -720,9 +721,10 @@ __device__ __forceinline__ void coarse_solve_mpfc(const Op& op, typename Op::rea
                     J[r][cc] = sw ? hi : lo;
                 }
             }
+            ip[k] = T(1) / J[k][k];
 #pragma unroll
             for (int r = k + 1; r < NC; ++r) {
-                const T fct = J[r][k] / J[k][k];
+                const T fct = J[r][k] * ip[k];
 #pragma unroll
                 for (int cc = k; cc <= NC; ++cc) J[r][cc] -= fct * J[k][cc];
             }
@@ -732,7 +734,7 @@ __device__ __forceinline__ void coarse_solve_mpfc(const Op& op, typename Op::rea
             T s = J[k][NC];
 #pragma unroll
             for (int cc = k + 1; cc < NC; ++cc) s -= J[k][cc] * t1[cc];
-            t1[k] = s / J[k][k];
+            t1[k] = s * ip[k];
         }
         T smax = 0, xmax = 0;
 #pragma unroll
@@ -908,28 +910,43 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
         const Op o = opl(l);
         const int m = G.m[l], lm = G.lm[l], n = G.n[l], off = G.off[l];
         const int mc = G.m[l + 1], lmc = G.lm[l + 1], nc = G.n[l + 1], offc = G.off[l + 1];
-        for (int Q = t; Q < mc * nc; Q += NTP) {
-            const int I = Q & (mc - 1), J = Q >> lmc;
+        // four consecutive lanes take the four fine cells under one coarse
+        // cell (c = (0,0), (1,0), (0,1), (1,1)) and add u and r across the
+        // group with lane exchanges: ((c0 + c1) + (c2 + c3)); every lane runs
+        // the exchanges (idle groups add zeros)
+        const int nfine = 4 * mc * nc;
+        for (int e0 = 0; e0 < nfine; e0 += NTP) {
+            const int e = e0 + t, Q = e >> 2, c = e & 3;
+            const bool act = e < nfine;
             T su[NF], sr[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) { su[f] = T(0); sr[f] = T(0); }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
+            if (act) {
+                const int I = Q & (mc - 1), J = Q >> lmc;
                 const int i = 2 * I + (c & 1), j = 2 * J + (c >> 1);
                 const int q = (j << lm) + i;
                 T u[NF], ns[NF], N[NF];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) { u[f] = Su[f][off + q]; ns[f] = nsum_l(&Su[f][off], i, j, m, lm, n); }
                 o.apply(u, ns, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0),
-                    Op::PW ? Spw[off + q] : T(0), N);
+                        Op::PW ? Spw[off + q] : T(0), N);
 #pragma unroll
-                for (int f = 0; f < NF; ++f) { su[f] += u[f]; sr[f] += Sf[f][off + q] - N[f]; }
+                for (int f = 0; f < NF; ++f) { su[f] = u[f]; sr[f] = Sf[f][off + q] - N[f]; }
             }
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                Su[f][offc + Q] = T(0.25) * su[f];
-                Sv[f][offc + Q] = T(0.25) * su[f];
-                Sf[f][offc + Q] = T(0.25) * sr[f];
+                su[f] += __shfl_xor(su[f], 1, 64);
+                sr[f] += __shfl_xor(sr[f], 1, 64);
+                su[f] += __shfl_xor(su[f], 2, 64);
+                sr[f] += __shfl_xor(sr[f], 2, 64);
+            }
+            if (act && c == 0) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    Su[f][offc + Q] = T(0.25) * su[f];
+                    Sv[f][offc + Q] = T(0.25) * su[f];
+                    Sf[f][offc + Q] = T(0.25) * sr[f];
+                }
             }
         }
         __syncthreads();

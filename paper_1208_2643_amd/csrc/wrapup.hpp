@@ -67,13 +67,18 @@ __global__ void __launch_bounds__(NT) k_wrap_psi_sums(const StepIO* __restrict__
     }
     if (off) return;
     const int fc = final_copy(st, mixed);
-    const double* phi = fc ? phi1 : phi0;
-    const double* mu = advance ? (fc ? mu1 : mu0) : nullptr;
-    double* psi = io->psi;
+    const double* __restrict__ phi = fc ? phi1 : phi0;
+    const double* __restrict__ mu = advance ? (fc ? mu1 : mu0) : nullptr;
+    const double* __restrict__ phik = io->phi_n;
+    double* __restrict__ psi = io->psi;
+    double* __restrict__ out = io->phi_np1;
     double sx = 0.0, sy = 0.0;
     for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
-        psi_cell<SCHEME>(s, phi, io->phi_n, psi, io->phi_np1, q);
-        sx += psi[q];
+        const double x = phi[q];
+        const double v = SCHEME == 1 ? (x - phik[q]) / s : (2.0 / s) * (x - phik[q]) - psi[q];
+        psi[q] = v;
+        out[q] = x;
+        sx += v;
         if (mu) sy += mu[q];
     }
     const double tx = block_sum<NT>(sx, red);
@@ -136,15 +141,16 @@ __global__ void __launch_bounds__(NT) k_wrap_rhs_terms(const CycleState* st,
     __shared__ double red[NT / 64][10];
     const size_t total = (size_t)g.m * g.n;
     const double mean = sum[0] / (double)total;
-    const double* phi = io->phi_np1;
-    const double* phiprev = io->phi_n;
-    const double* psi = io->psi;
+    const double* __restrict__ phi = io->phi_np1;
+    const double* __restrict__ phiprev = io->phi_n;
+    const double* __restrict__ psi = io->psi;
+    double* __restrict__ bo = b;
     double a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
         int i, j;
         cell_of(q, g, i, j);
         const double v = psi[q] - mean;
-        b[q] = v;
+        bo[q] = v;
         a[8] += v * v;
         if (w) {
             const double r = v - (4.0 * w[q] - nsum(w, i, j, g)) * ih2;
