@@ -55,9 +55,9 @@ BATCH_FP32_VCYCLE_BYTES = 340.0
 # shape "TXxTY/HALO", valid only for the kernel sources they were measured on
 # (kernel_source_hash).
 MEASURED_TRAFFIC = {
-    "src": "381aab36beb77074",
-    "down": {"64x32/6": 110239096, "32x32/6": 115031665, "32x16/6": 110181958, "16x16/6": 109972091, "64x16/10": 114797977, "32x16/10": 110187562, "16x16/10": 110048818},
-    "up": {"64x32/6": 109659394, "32x32/6": 107628113, "32x16/6": 103324823, "16x16/6": 103158118, "64x16/10": 103342344, "32x16/10": 103233929, "16x16/10": 103223297},
+    "src": "dac28424d7a5c2c4",
+    "down": {"64x32/6": 115034206, "32x32/6": 113578913, "32x16/6": 109964482, "16x16/6": 109950149, "64x16/10": 110048815, "32x16/10": 109976767, "16x16/10": 109964482},
+    "up": {"64x32/6": 109756105, "32x32/6": 107017640, "32x16/6": 103144706, "16x16/6": 103142531, "64x16/10": 103303135, "32x16/10": 103161982, "16x16/10": 103161982},
 }
 
 

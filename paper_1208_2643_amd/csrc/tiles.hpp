@@ -910,43 +910,28 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
         const Op o = opl(l);
         const int m = G.m[l], lm = G.lm[l], n = G.n[l], off = G.off[l];
         const int mc = G.m[l + 1], lmc = G.lm[l + 1], nc = G.n[l + 1], offc = G.off[l + 1];
-        // four consecutive lanes take the four fine cells under one coarse
-        // cell (c = (0,0), (1,0), (0,1), (1,1)) and add u and r across the
-        // group with lane exchanges: ((c0 + c1) + (c2 + c3)); every lane runs
-        // the exchanges (idle groups add zeros)
-        const int nfine = 4 * mc * nc;
-        for (int e0 = 0; e0 < nfine; e0 += NTP) {
-            const int e = e0 + t, Q = e >> 2, c = e & 3;
-            const bool act = e < nfine;
+        for (int Q = t; Q < mc * nc; Q += NTP) {
+            const int I = Q & (mc - 1), J = Q >> lmc;
             T su[NF], sr[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) { su[f] = T(0); sr[f] = T(0); }
-            if (act) {
-                const int I = Q & (mc - 1), J = Q >> lmc;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
                 const int i = 2 * I + (c & 1), j = 2 * J + (c >> 1);
                 const int q = (j << lm) + i;
                 T u[NF], ns[NF], N[NF];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) { u[f] = Su[f][off + q]; ns[f] = nsum_l(&Su[f][off], i, j, m, lm, n); }
                 o.apply(u, ns, Op::XK ? Sxk[off + q] : T(0), Op::PB ? Spb[off + q] : T(0),
-                        Op::PW ? Spw[off + q] : T(0), N);
+                    Op::PW ? Spw[off + q] : T(0), N);
 #pragma unroll
-                for (int f = 0; f < NF; ++f) { su[f] = u[f]; sr[f] = Sf[f][off + q] - N[f]; }
+                for (int f = 0; f < NF; ++f) { su[f] += u[f]; sr[f] += Sf[f][off + q] - N[f]; }
             }
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                su[f] += __shfl_xor(su[f], 1, 64);
-                sr[f] += __shfl_xor(sr[f], 1, 64);
-                su[f] += __shfl_xor(su[f], 2, 64);
-                sr[f] += __shfl_xor(sr[f], 2, 64);
-            }
-            if (act && c == 0) {
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    Su[f][offc + Q] = T(0.25) * su[f];
-                    Sv[f][offc + Q] = T(0.25) * su[f];
-                    Sf[f][offc + Q] = T(0.25) * sr[f];
-                }
+                Su[f][offc + Q] = T(0.25) * su[f];
+                Sv[f][offc + Q] = T(0.25) * su[f];
+                Sf[f][offc + Q] = T(0.25) * sr[f];
             }
         }
         __syncthreads();
