@@ -94,7 +94,12 @@ typedef struct {
  * (q = 1 or 2 by scheme), where V-cycles can diverge (first-order scheme at
  * h = 0.5: s from about 0.15 to 0.3); under-relaxation near 0.8 converges
  * there.  The solution of the step does not depend on omega.  The 3-D
- * contexts take omega = 1 only. */
+ * contexts take omega = 1 only.
+ * coarse_threshold: cells of the largest level the persistent coarse kernel
+ * takes (every smaller level runs there too, in one workgroup; larger ones
+ * run as fused tile launches): 0 for the default 1024 (32 x 32), else a power
+ * of two in [256, 1024].  Power-of-two grids only (others: 0); a batch takes
+ * 0 only.  The iterates do not depend on it. */
 typedef struct {
     int nu1, nu2, max_cycles;
     double tol;
@@ -105,6 +110,7 @@ typedef struct {
     int inner_cycles;
     int coarse_sweeps;
     double omega;
+    int coarse_threshold;
 } mpfc_opts;
 
 /* Per-step report.  residual_history is a caller-owned host array of

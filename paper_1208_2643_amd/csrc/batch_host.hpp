@@ -404,6 +404,8 @@ int mpfc_batch_create(mpfc_batch** out, int nsim, const mpfc_sim_desc* sims, con
         if ((long long)sims[s].m * sims[s].n <= CP_CELLS)
             return fail(MPFC_EINVAL, "batched grids need more than 1024 cells");
     }
+    if (o->coarse_threshold != 0)
+        return fail(MPFC_EINVAL, "a batch runs with the default coarse_threshold (0)");
     mpfc_batch* B = new (std::nothrow) mpfc_batch();
     if (!B) return fail(MPFC_ENOMEM, "host allocation failed");
     B->nsim = nsim;

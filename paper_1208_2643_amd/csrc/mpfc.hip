@@ -57,6 +57,11 @@ int ilog2(int v) {
 }
 int round_even(int v) { return (v + 1) & ~1; }
 
+// Cells of the largest level the persistent coarse kernel takes.
+int persistent_cells(const mpfc_opts* o) {
+    return o->coarse_threshold ? o->coarse_threshold : CP_CELLS;
+}
+
 static_assert(BC_NEUMANN_X == MPFC_BC_NEUMANN_X && BC_NEUMANN_Y == MPFC_BC_NEUMANN_Y,
               "boundary-condition bits of the kernels and the C interface agree");
 Grid make_grid(int m, int n, int bc) {
@@ -1016,6 +1021,10 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
         return fail(MPFC_EINVAL, "coarse_sweeps must be in [1, 64]");
     if (!(o->omega > 0.0 && o->omega < 2.0))
         return fail(MPFC_EINVAL, "omega must be in (0, 2)");
+    const int thr = o->coarse_threshold;
+    if (thr != 0 && (gen || !is_pow2(thr) || thr < 256 || thr > CP_CELLS))
+        return fail(MPFC_EINVAL, "coarse_threshold must be 0 or a power of two in [256, 1024] "
+                                 "(power-of-two grids)");
     if (gen) {
         // general-index kernels: FP64, halos up to 6, coarsest level in one workgroup
         if (o->precision != MPFC_FP64)
@@ -1036,11 +1045,12 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
     while ((mm < nn ? mm : nn) > o->coarsest) { mm /= 2; nn /= 2; }
     if (mm * nn > 8)
         return fail(MPFC_EINVAL, "aspect ratio above 2: the coarsest grid must be 2x2 or 2x4");
-    // the levels of at most 32x32 cells must fit the persistent kernel
+    // the levels of at most coarse_threshold cells must fit the persistent kernel
+    const int cp = persistent_cells(o);
     int cells = 0;
     mm = m; nn = n;
     for (;;) {
-        if (mm * nn <= CP_CELLS) cells += mm * nn;
+        if (mm * nn <= cp) cells += mm * nn;
         if ((mm < nn ? mm : nn) <= o->coarsest) break;
         mm /= 2; nn /= 2;
     }
@@ -1317,6 +1327,7 @@ void mpfc_default_opts(mpfc_opts* o) {
     o->inner_cycles = 3;
     o->coarse_sweeps = 2;
     o->omega = 1.0;
+    o->coarse_threshold = 0;
 }
 
 int mpfc_validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
@@ -1404,7 +1415,7 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
             Level lv;
             lv.m = mm; lv.n = nn; lv.h = h; lv.g = make_grid(mm, nn, p->bc);
             const bool last = !coarsen_more(mm, nn, o->coarsest);
-            lv.tiled = C->gen ? !last : (long long)mm * nn > CP_CELLS;
+            lv.tiled = C->gen ? !last : (long long)mm * nn > persistent_cells(o);
             C->L.push_back(lv);
             if (last) break;
             mm /= 2; nn /= 2; h *= 2.0;

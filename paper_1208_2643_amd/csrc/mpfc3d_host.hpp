@@ -49,6 +49,8 @@ int validate3(int m, int n, int l, const mpfc_params* p, const mpfc_opts* o) {
         return fail(MPFC_EINVAL, "the learned guess is two-dimensional");
     if (o->omega != 1.0)
         return fail(MPFC_EINVAL, "the three-dimensional step runs App. B's smoother (omega = 1)");
+    if (o->coarse_threshold != 0)
+        return fail(MPFC_EINVAL, "the three-dimensional step takes coarse_threshold = 0");
     return MPFC_OK;
 }
 

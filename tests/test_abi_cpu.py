@@ -233,3 +233,26 @@ def test_relaxation_factor_default_and_range():
     assert L.load().mpfc_validate(64, 64, ctypes.byref(p), ctypes.byref(o)) == 0
     assert L.load().mpfc_validate(512, 400, ctypes.byref(p), ctypes.byref(o)) == 0
     assert L.load().mpfc3d_validate(64, 64, 64, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
+
+
+@pytest.mark.parametrize("thr,ok", [(0, True), (256, True), (512, True), (1024, True),
+                                    (128, False), (300, False), (2048, False), (-256, False)])
+def test_coarse_threshold_values(thr, ok):
+    p, o = good()
+    assert o.coarse_threshold == 0
+    o.coarse_threshold = thr
+    rc = L.load().mpfc_validate(256, 256, ctypes.byref(p), ctypes.byref(o))
+    assert rc == (0 if ok else L.MPFC_EINVAL)
+
+
+def test_coarse_threshold_only_for_power_of_two_2d_single_grids():
+    lib = L.load()
+    p, o = good()
+    o.coarse_threshold = 256
+    assert lib.mpfc_validate(512, 400, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
+    assert lib.mpfc3d_validate(64, 64, 64, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL
+    d = (L.mpfc_sim_desc * 1)()
+    d[0].m, d[0].n, d[0].p = 64, 64, p
+    b = ctypes.c_void_p()
+    assert lib.mpfc_batch_create(ctypes.byref(b), 1, d, ctypes.byref(o), None) == L.MPFC_EINVAL
+    assert not b.value
