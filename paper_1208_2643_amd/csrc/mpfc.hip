@@ -1434,9 +1434,17 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
                              : (size_t)(Lc.m * Lc.n) * (Lc.m * Lc.n);
     auto layout = [&](double* base) {
         size_t off = 0;
+        // Pieces start 256-byte aligned; after each one a gap of 0-15 x 256
+        // bytes (varying from piece to piece) keeps fields of equal
+        // power-of-two size from starting at the same offset modulo the HBM
+        // channel interleave, where same-index accesses to several fields
+        // would fall on one channel.
+        int piece = 0;
         auto take = [&](size_t cnt) {
             double* r = base ? base + off : nullptr;
             off += (cnt + 31) & ~(size_t)31;
+            off += (size_t)32 * ((piece * 7) & 15);
+            ++piece;
             return r;
         };
         for (int l = 0; l < nl; ++l) {
