@@ -240,12 +240,16 @@ def bench_learned(api, inputs, torch, dev, params, tol, steps, warmup, N):
     blob = guess_net.load()
     phi0 = inputs.crystallites(N, N, params["h"], seed=5)
     res = {"workload": f"{N}x{N}, second-order scheme, crystallites seed 5, {steps} steps, "
-                       "FP64 V(2,2) to 1e-10, energies off",
+                       "V(2,2) to 1e-10 (FP64, and mixed precision with 3 FP32 cycles per outer "
+                       "iteration), energies off",
            "network": guess_net.meta().get("validation_loss") if os.path.exists(
                guess_net.DEFAULT_WEIGHTS + ".json") else None}
     finals = {}
-    for name, guess in (("extrapolated", 1), ("learned", 2)):
-        st = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2, energy=0, guess=guess)
+    # FP64, then mixed precision (3 inner cycles) with each guess
+    for name, guess, prec in (("extrapolated", 1, 0), ("learned", 2, 0),
+                              ("mixed_extrapolated", 1, 1), ("mixed_learned", 2, 1)):
+        st = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2, energy=0, guess=guess,
+                         precision=prec, inner_cycles=3)
         if guess == 2:
             st.load_cnn(blob)
         phi = torch.from_numpy(phi0).to(dev)
@@ -271,7 +275,8 @@ def bench_learned(api, inputs, torch, dev, params, tol, steps, warmup, N):
             prev, phi, nxt = phi, nxt, prev
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        entry = {"time_steps_per_s": steps / el, "vcycles_per_step": cycles / steps,
+        entry = {"time_steps_per_s": steps / el,
+                 ("fp32_vcycles_per_step" if prec else "vcycles_per_step"): cycles / steps,
                  "median_initial_residual": float(sorted(r0)[len(r0) // 2])}
         if guess == 2:
             used, fb = st.cnn_counts()
@@ -280,9 +285,14 @@ def bench_learned(api, inputs, torch, dev, params, tol, steps, warmup, N):
         finals[name] = phi.double().cpu()
         res[name] = entry
         st.close()
-    d = (finals["learned"] - finals["extrapolated"]).norm() / finals["extrapolated"].norm()
+    ref = finals["extrapolated"]
+    d = (finals["learned"] - ref).norm() / ref.norm()
     res["final_state_rel_l2_difference"] = float(d)
-    res["speedup"] = res["learned"]["time_steps_per_s"] / res["extrapolated"]["time_steps_per_s"]
+    res["mixed_learned_final_state_rel_l2_vs_fp64"] = float(
+        (finals["mixed_learned"] - ref).norm() / ref.norm())
+    fp64 = res["extrapolated"]["time_steps_per_s"]
+    res["speedup"] = res["learned"]["time_steps_per_s"] / fp64
+    res["speedup_mixed_learned"] = res["mixed_learned"]["time_steps_per_s"] / fp64
     return res
 
 

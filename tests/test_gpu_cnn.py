@@ -221,3 +221,24 @@ def test_learned_guess_on_untiled_grids(m, n):
             used, fb = st.cnn_counts()
             assert used + fb == 4
     assert rel(out[L.MPFC_GUESS_CNN], out[L.MPFC_GUESS_EXTRAP]) < 1e-10
+
+
+def test_learned_guess_with_mixed_precision():
+    """The learned guess starting mixed-precision steps (FP32 correction
+    cycles inside FP64 defect correction): the network's candidate is used,
+    every step reaches the FP64 tolerance, and the states agree with FP64
+    steps from the extrapolated guess to the mixed-precision bar (1e-9)."""
+    from paper_1208_2643_amd import guess_net
+    p = api.Params(**PARAMS)
+    phi0 = I.crystallites(256, 256, math.pi / 4, seed=5)
+    st = api.Stepper(256, 256, p, energy=0, guess=L.MPFC_GUESS_CNN, precision=L.MPFC_MIXED)
+    st.load_cnn(guess_net.load())
+    pm, _, _, im = api.run(st, dev(phi0), 12)
+    used, fb = st.cnn_counts()
+    st.close()
+    st = api.Stepper(256, 256, p, energy=0, guess=L.MPFC_GUESS_EXTRAP)
+    pe, _, _, ie = api.run(st, dev(phi0), 12)
+    st.close()
+    assert all(i.status == 0 and i.residual <= 1e-10 and i.outer_iters > 0 for i in im)
+    assert used >= 10 and used + fb == 12
+    assert rel(host(pm), host(pe)) < 1e-9
