@@ -8,8 +8,8 @@ each cell by omega times its local correction).
 * the first-order scheme at h = 0.5, s = 0.2 (inside the window where App. B's
   smoother makes V(2,2) diverge): the step converges with omega = 0.8 and
   matches the oracle to 1e-10, while omega = 1 does not converge;
-* mixed precision, grids whose sides are not powers of two and the batched
-  path take the same factor;
+* mixed precision, Neumann axes, the pinning term, grids whose sides are not
+  powers of two and the batched path take the same factor;
 * Table 2 of Sec. 4.1 with V(2,2) cycles on every grid (omega = 0.8), where
   App. B's smoother needs V(0,1) from 256^2 on.
 """
@@ -177,3 +177,38 @@ def test_table2_with_vcycles_on_every_grid():
         assert abs(row["difference"] - d) <= 2 * 10.0 ** (math.floor(math.log10(abs(d))) - 4), k
         if ref["rate"][k] is not None:
             assert abs(row["rate"] - ref["rate"][k]) <= 1e-4, k
+
+
+@pytest.mark.parametrize("bc,pin", [(L.MPFC_BC_NEUMANN_Y, False),
+                                    (L.MPFC_BC_NEUMANN_X | L.MPFC_BC_NEUMANN_Y, False),
+                                    (0, True), (L.MPFC_BC_NEUMANN_Y, True)])
+def test_one_cycle_neumann_and_pinning_match_oracle(bc, pin):
+    """Under-relaxation with Neumann axes (the halo restore after every pass)
+    and with the pinning term, 128 x 64, one V(2,2) cycle."""
+    m, n = 128, 64
+    d = dict(eps=0.025, beta=0.9, M=1.0, h=math.pi / 4, dt=0.05, scheme=2)
+    po = O.Params(omega=W, bc=(1 if bc & L.MPFC_BC_NEUMANN_X else 0,
+                               1 if bc & L.MPFC_BC_NEUMANN_Y else 0), **d)
+    pg = api.Params(bc=bc, **d)
+    phik = I.crystallites(m, n, pg.h, count=2, radius_cells=8, seed=90)
+    prev = phik + 0.002 * I.noise(m, n, mean=0.0, amp=1.0, seed=91)
+    psi0 = 0.002 * I.noise(m, n, mean=0.0, amp=1.0, seed=92)
+    st = api.Stepper(m, n, pg, tol=1e-30, max_cycles=1, energy=0, omega=W)
+    Wt = hat = None
+    if pin:
+        Wt = np.zeros((n, m))
+        Wt[:4] = 2.0
+        Wt[n // 2:n // 2 + 6] = 1.5
+        hat = np.roll(phik, 2, axis=1)
+        st.set_pinning(dev(Wt), dev(hat))
+    psi = dev(psi0)
+    mu, ka = torch.empty_like(psi), torch.empty_like(psi)
+    phi_g, info = st.step(dev(phik), dev(prev), psi, mu=mu, kappa=ka, allow_fail=True)
+    assert info.status == L.MPFC_ENOTCONVERGED and info.n_cycles == 1
+    S = O.source(po, phik, prev, psi0, pin=Wt, phihat=hat)
+    u0 = O.complete_guess(po, 2 * phik - prev, S, phik=phik, pin=Wt)
+    u, hist, _ = O.fas_solve(po, u0, S, phik=phik, tol=1e-30, max_cycles=1, pin=Wt)
+    for a, b in zip((host(phi_g), host(mu), host(ka)), u):
+        assert relmax(a, b) <= 1e-12
+    np.testing.assert_allclose(info.history, hist, rtol=1e-9)
+    st.close()
