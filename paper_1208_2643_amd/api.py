@@ -49,6 +49,10 @@ class StepInfo:
 
 
 def make_opts(**kw) -> L.mpfc_opts:
+    """Solver options (mpfc_opts, include/mpfc.h) from the library's defaults
+    with the given fields replaced: nu1, nu2, max_cycles, tol, precision,
+    guess, linearization, coarsest, energy, diverge, inner_cycles,
+    coarse_sweeps, omega (smoother relaxation, 1 = App. B), coarse_threshold."""
     o = L.default_opts()
     for k, v in kw.items():
         if not hasattr(o, k):
