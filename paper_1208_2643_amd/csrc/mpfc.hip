@@ -1083,12 +1083,12 @@ void energies_from_sums(const mpfc_ctx* C, const double* a, double* out) {
     out[3] = h2 * a[4];
 }
 
-// Keep the number of Poisson cycles enqueued up front just large enough (0
-// when the warm start alone passes), from the count of the last solve.
+// Enqueue up front as many Poisson cycles as the last solve ran (0 when the
+// warm start alone passed): skipped cycles still cost their launches, and
+// each count is a graph of its own.
 void adapt_poisson_cycles(mpfc_ctx* C, const CycleState& pst, bool warm) {
     const int ran = pst.count - (warm ? 1 : 0);  // V-cycles that ran
-    if (ran >= C->poisson_cycles) C->poisson_cycles = ran < kMaxRun ? ran : kMaxRun;
-    else if (C->poisson_cycles > 0) C->poisson_cycles -= 1;
+    C->poisson_cycles = ran < kMaxRun ? ran : kMaxRun;
 }
 
 // Energies of (phi, phi_prev, psi) into out[0..3] (mpfc_energies): the
