@@ -204,6 +204,50 @@ struct TileWork {
         T pb[SL][4];
         T w[SL][4];
     };
+    // OWN (a thread owns at most one block): the block's four cells are also
+    // kept in registers, updated together with LDS.  Two of each cell's four
+    // neighbours lie in its own block, so half of the neighbour reads come
+    // from registers and LDS traffic per relaxation halves.  Only the owner
+    // writes a cell (except the Neumann ghost restore, after which the copy
+    // is reloaded).
+    static constexpr bool OWN = SL == 1;
+    struct Own {
+        T u[4][NF];
+    };
+    // cell offsets within a block: 0 = (0,0), 1 = (1,1) red; 2 = (1,0), 3 = (0,1) black
+    static constexpr int cdx(int c) { return (c == 1 || c == 2) ? 1 : 0; }
+    static constexpr int cdy(int c) { return (c == 1 || c == 3) ? 1 : 0; }
+    static constexpr int cid(int dx, int dy) { return dx == dy ? dx : (dx ? 2 : 3); }
+
+    // Neighbour sums of cell C of the owned block (bx, by), every field, in
+    // the order (east + west) + (north + south): own-block neighbours from
+    // registers, the others from LDS.
+    template <int C>
+    static __device__ __forceinline__ void nsum_own(const Lds& S, const Own& O, int bx, int by,
+                                                    T (&ns)[NF]) {
+        constexpr int dx = cdx(C), dy = cdy(C), oc = ((dx + dy) & 1) ^ 1;
+        const int y = 2 * by + dy;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const T e = dx == 0 ? O.u[cid(1, dy)][f] : S.U[f][oc][y][bx + 1];
+            const T w = dx == 1 ? O.u[cid(0, dy)][f] : S.U[f][oc][y][bx - 1];
+            const T n = dy == 0 ? O.u[cid(dx, 1)][f] : S.U[f][oc][y + 1][bx];
+            const T s = dy == 1 ? O.u[cid(dx, 0)][f] : S.U[f][oc][y - 1][bx];
+            ns[f] = (e + w) + (n + s);
+        }
+    }
+    // The owned block's cells from LDS into registers (after a barrier).
+    static __device__ __forceinline__ void load_own(const Lds& S, const Geo& G, Own& O) {
+        const int b = threadIdx.x;
+        if (b >= G.nblk) return;
+        const int by = b / G.LX2, bx = b - by * G.LX2;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int y = 2 * by + cdy(c);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) O.u[c][f] = S.U[f][(cdx(c) + cdy(c)) & 1][y][bx];
+        }
+    }
 
     static __device__ __forceinline__ Geo geo(const TileArgs<T>& A, int tbx, int tby) {
         Geo G;
@@ -301,10 +345,38 @@ struct TileWork {
         const auto& xkr = R.xk;
         const auto& pbr = R.pb;
         const auto& wr = R.w;
+        Own O;
+        if constexpr (OWN && !UP) load_own(S, G, O);
     // 3. up: add the coarse-grid correction P(uH - vH) to every loaded cell
     //    (uH - vH over the tile's coarse footprint, one coarse cell of margin,
     //    staged in LDS).
-    if constexpr (UP) {
+    if constexpr (UP && OWN) {
+        // the block's 3x3 coarse neighbourhood once per field, then its four cells
+        if (t < nblk) {
+            const int by = t / LX2, bx = t - by * LX2;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                T e9[3][3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) e9[j][i] = E[f][by + j][bx + i];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int dx = cdx(c), dy = cdy(c);
+                    const int x = 2 * bx + dx, y = 2 * by + dy;
+                    const int si = dx ? 2 : 0, sj = dy ? 2 : 0;
+                    const T v = U[f][(x + y) & 1][y][x >> 1] +
+                                (T(9.0 / 16.0) * e9[1][1] +
+                                 T(3.0 / 16.0) * (e9[1][si] + e9[sj][1]) +
+                                 T(1.0 / 16.0) * e9[sj][si]);
+                    U[f][(x + y) & 1][y][x >> 1] = v;
+                    O.u[c][f] = v;
+                }
+            }
+        }
+        __syncthreads();
+    } else if constexpr (UP) {
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             const int b = t + s * NT;
@@ -328,7 +400,26 @@ struct TileWork {
     }
 
     // 3'. coarse down: f = R r + N(u) at every cell that can be updated.
-    if (!UP && A.complete_f) {
+    if (!UP && OWN && A.complete_f) {
+        if (t < nblk) {
+            const int by = t / LX2, bx = t - by * LX2;
+            auto cell_f = [&](auto cc_) {
+                constexpr int c = decltype(cc_)::value;
+                const int x = 2 * bx + cdx(c), y = 2 * by + cdy(c);
+                if (x < 1 || y < 1 || x >= LX - 1 || y >= LY - 1) return;
+                T ns[NF], N[NF];
+                nsum_own<c>(S, O, bx, by, ns);
+                op.apply(O.u[c], ns, xkr[0][c], pbr[0][c], wr[0][c], N);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) fr[0][c][f] += N[f];
+            };
+            cell_f(std::integral_constant<int, 0>{});
+            cell_f(std::integral_constant<int, 1>{});
+            cell_f(std::integral_constant<int, 2>{});
+            cell_f(std::integral_constant<int, 3>{});
+        }
+        __syncthreads();
+    } else if (!UP && A.complete_f) {
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             const int b = t + s * NT;
@@ -364,6 +455,28 @@ struct TileWork {
     auto pass = [&](auto colc, int p) {
         constexpr int colour = decltype(colc)::value;
         constexpr int oc = colour ^ 1;
+        if constexpr (OWN) {
+            if (t >= nblk) return;
+            const int by = t / LX2, bx = t - by * LX2;
+            auto cell = [&](auto cc_) {
+                constexpr int c = decltype(cc_)::value;
+                const int x = 2 * bx + cdx(c), y = 2 * by + cdy(c);
+                if (x < p || y < p || x >= LX - p || y >= LY - p) return;
+                T u[NF], ns[NF];
+                nsum_own<c>(S, O, bx, by, ns);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) u[f] = O.u[c][f];
+                op.relax(u, ns, fr[0][c], xkr[0][c], pbr[0][c], wr[0][c]);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    U[f][colour][y][bx] = u[f];
+                    O.u[c][f] = u[f];
+                }
+            };
+            cell(std::integral_constant<int, colour == 0 ? 0 : 2>{});
+            cell(std::integral_constant<int, colour == 0 ? 1 : 3>{});
+            return;
+        }
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             const int b = t + s * NT;
@@ -429,7 +542,11 @@ struct TileWork {
         if (((p - 1) & 1) == 0) pass(std::integral_constant<int, 0>{}, p);
         else pass(std::integral_constant<int, 1>{}, p);
         __syncthreads();
-        if constexpr (NEU) restore_ghosts();
+        if constexpr (NEU) {
+            restore_ghosts();
+            if constexpr (OWN)
+                if (mir_x || mir_y) load_own(S, G, O);
+        }
     }
 
     // 5. interior u back to global memory, coalesced along rows.
@@ -455,26 +572,46 @@ struct TileWork {
         T su[NF], sr[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) { su[f] = T(0); sr[f] = T(0); }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
-            const int x = 2 * bx + dx, y = 2 * by + dy;
-            const int col = (x + y) & 1, oc = col ^ 1, k = x >> 1;
-            const int ke = (x + 1) >> 1, kw = (x - 1) >> 1;
-            T u[NF], ns[NF], N[NF];
+        auto res_own = [&](auto cc_) {
+            constexpr int c = decltype(cc_)::value;
+            T ns[NF], N[NF];
+            nsum_own<c>(S, O, bx, by, ns);
+            op.apply(O.u[c], ns, xkr[0][c], pbr[0][c], wr[0][c], N);
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                u[f] = U[f][col][y][k];
-                ns[f] = (U[f][oc][y][ke] + U[f][oc][y][kw]) +
-                        (U[f][oc][y + 1][k] + U[f][oc][y - 1][k]);
-            }
-            op.apply(u, ns, xkr[s][c], pbr[s][c], wr[s][c], N);
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const T r = fr[s][c][f] - N[f];
-                su[f] += u[f];
+                const T r = fr[0][c][f] - N[f];
+                su[f] += O.u[c][f];
                 sr[f] += r;
                 acc += (double)r * (double)r;
+            }
+        };
+        if constexpr (OWN) {
+            res_own(std::integral_constant<int, 0>{});
+            res_own(std::integral_constant<int, 1>{});
+            res_own(std::integral_constant<int, 2>{});
+            res_own(std::integral_constant<int, 3>{});
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int dx = (c == 1 || c == 2) ? 1 : 0, dy = (c == 1 || c == 3) ? 1 : 0;
+                const int x = 2 * bx + dx, y = 2 * by + dy;
+                const int col = (x + y) & 1, oc = col ^ 1, k = x >> 1;
+                const int ke = (x + 1) >> 1, kw = (x - 1) >> 1;
+                T u[NF], ns[NF], N[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    u[f] = U[f][col][y][k];
+                    ns[f] = (U[f][oc][y][ke] + U[f][oc][y][kw]) +
+                            (U[f][oc][y + 1][k] + U[f][oc][y - 1][k]);
+                }
+                op.apply(u, ns, xkr[s][c], pbr[s][c], wr[s][c], N);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const T r = fr[s][c][f] - N[f];
+                    su[f] += u[f];
+                    sr[f] += r;
+                    acc += (double)r * (double)r;
+                }
             }
         }
         if constexpr (!UP) {
