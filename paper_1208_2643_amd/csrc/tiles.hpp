@@ -308,25 +308,65 @@ struct TileWork {
 
     // u (tile + halo) and, up, uH - vH into LDS, coalesced along rows; a
     // barrier must follow.
+    // Loads of LCH consecutive strides are issued together, so a thread waits
+    // once per LCH strides rather than once per stride.  Indices past the end
+    // are clamped to the last cell, for the load and the store alike (the
+    // same value stored twice), so no load sits behind a branch.
+    static constexpr int LCH = 4;
     static __device__ __forceinline__ void load_direct(const TileArgs<T>& A, const Geo& G, Lds& S) {
         const Grid g = A.g;
         const int t = threadIdx.x;
-        for (int q = t; q < G.LX * G.LY; q += NT) {
-            const int y = q / G.LX, x = q - y * G.LX;
-            const size_t gq = cell(g, G.x0 + x, G.y0 + y);
+        const int total = G.LX * G.LY;
+        constexpr int NLD = (2 * LX2M * LYM + NT - 1) / NT;  // strides of the largest tile
+        if (A.zero_in) {
+            for (int q = t; q < total; q += NT) {
+                const int y = q / G.LX, x = q - y * G.LX;
 #pragma unroll
-            for (int f = 0; f < NF; ++f)
-                S.U[f][(x + y) & 1][y][x >> 1] = A.zero_in ? T(0) : A.uin[f][gq];
+                for (int f = 0; f < NF; ++f) S.U[f][(x + y) & 1][y][x >> 1] = T(0);
+            }
+        } else {
+#pragma unroll
+            for (int k0 = 0; k0 < NLD; k0 += LCH) {
+                T v[LCH][NF];
+                int xs[LCH], ys[LCH];
+#pragma unroll
+                for (int j = 0; j < LCH; ++j) {
+                    if (k0 + j >= NLD) break;
+                    const int q = min(t + (k0 + j) * NT, total - 1);
+                    ys[j] = q / G.LX;
+                    xs[j] = q - ys[j] * G.LX;
+                    const size_t gq = cell(g, G.x0 + xs[j], G.y0 + ys[j]);
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) v[j][f] = A.uin[f][gq];
+                }
+#pragma unroll
+                for (int j = 0; j < LCH; ++j) {
+                    if (k0 + j >= NLD) break;
+                    const int x = xs[j], y = ys[j];
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) S.U[f][(x + y) & 1][y][x >> 1] = v[j][f];
+                }
+            }
         }
         if constexpr (UP) {
-            const int CX = G.LX2 + 2, CY = (G.LY >> 1) + 2;
+            const int CX = G.LX2 + 2, CY = (G.LY >> 1) + 2, ctot = CX * CY;
             const int cx0 = (G.x0 >> 1) - 1, cy0 = (G.y0 >> 1) - 1;
-            for (int q = t; q < CX * CY; q += NT) {
-                const int cy = q / CX, cx = q - cy * CX;
-                const size_t gq = coarse_cell(g, cx0 + cx, cy0 + cy);
+            constexpr int NE = (CXM * CYM + NT - 1) / NT;
+            T v[NE][NF];
+            int xs[NE], ys[NE];
 #pragma unroll
-                for (int f = 0; f < NF; ++f) S.E[f][cy][cx] = A.cuH[f][gq] - A.cvH[f][gq];
+            for (int j = 0; j < NE; ++j) {
+                const int q = min(t + j * NT, ctot - 1);
+                ys[j] = q / CX;
+                xs[j] = q - ys[j] * CX;
+                const size_t gq = coarse_cell(g, cx0 + xs[j], cy0 + ys[j]);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) v[j][f] = A.cuH[f][gq] - A.cvH[f][gq];
             }
+#pragma unroll
+            for (int j = 0; j < NE; ++j)
+#pragma unroll
+                for (int f = 0; f < NF; ++f) S.E[f][ys[j]][xs[j]] = v[j][f];
         }
     }
 
