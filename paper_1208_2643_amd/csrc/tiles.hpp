@@ -222,17 +222,21 @@ struct TileWork {
     // Neighbour sums of cell C of the owned block (bx, by), every field, in
     // the order (east + west) + (north + south): own-block neighbours from
     // registers, the others from LDS.
+    // Indices are clamped to the loaded region: a cell on its border gets a
+    // meaningless sum, and its result is discarded by the caller.
     template <int C>
-    static __device__ __forceinline__ void nsum_own(const Lds& S, const Own& O, int bx, int by,
-                                                    T (&ns)[NF]) {
+    static __device__ __forceinline__ void nsum_own(const Lds& S, const Own& O, const Geo& G,
+                                                    int bx, int by, T (&ns)[NF]) {
         constexpr int dx = cdx(C), dy = cdy(C), oc = ((dx + dy) & 1) ^ 1;
         const int y = 2 * by + dy;
+        const int ke = min(bx + 1, G.LX2 - 1), kw = max(bx - 1, 0);
+        const int yn = min(y + 1, G.LY - 1), ys = max(y - 1, 0);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            const T e = dx == 0 ? O.u[cid(1, dy)][f] : S.U[f][oc][y][bx + 1];
-            const T w = dx == 1 ? O.u[cid(0, dy)][f] : S.U[f][oc][y][bx - 1];
-            const T n = dy == 0 ? O.u[cid(dx, 1)][f] : S.U[f][oc][y + 1][bx];
-            const T s = dy == 1 ? O.u[cid(dx, 0)][f] : S.U[f][oc][y - 1][bx];
+            const T e = dx == 0 ? O.u[cid(1, dy)][f] : S.U[f][oc][y][ke];
+            const T w = dx == 1 ? O.u[cid(0, dy)][f] : S.U[f][oc][y][kw];
+            const T n = dy == 0 ? O.u[cid(dx, 1)][f] : S.U[f][oc][yn][bx];
+            const T s = dy == 1 ? O.u[cid(dx, 0)][f] : S.U[f][oc][ys][bx];
             ns[f] = (e + w) + (n + s);
         }
     }
@@ -443,15 +447,17 @@ struct TileWork {
     if (!UP && OWN && A.complete_f) {
         if (t < nblk) {
             const int by = t / LX2, bx = t - by * LX2;
+            // all four cells computed without branches (the chains
+            // interleave), kept only where the cell can be updated
             auto cell_f = [&](auto cc_) {
                 constexpr int c = decltype(cc_)::value;
                 const int x = 2 * bx + cdx(c), y = 2 * by + cdy(c);
-                if (x < 1 || y < 1 || x >= LX - 1 || y >= LY - 1) return;
+                const bool in = x >= 1 && y >= 1 && x < LX - 1 && y < LY - 1;
                 T ns[NF], N[NF];
-                nsum_own<c>(S, O, bx, by, ns);
+                nsum_own<c>(S, O, G, bx, by, ns);
                 op.apply(O.u[c], ns, xkr[0][c], pbr[0][c], wr[0][c], N);
 #pragma unroll
-                for (int f = 0; f < NF; ++f) fr[0][c][f] += N[f];
+                for (int f = 0; f < NF; ++f) fr[0][c][f] = in ? fr[0][c][f] + N[f] : fr[0][c][f];
             };
             cell_f(std::integral_constant<int, 0>{});
             cell_f(std::integral_constant<int, 1>{});
@@ -498,23 +504,36 @@ struct TileWork {
         if constexpr (OWN) {
             if (t >= nblk) return;
             const int by = t / LX2, bx = t - by * LX2;
-            auto cell = [&](auto cc_) {
+            // both cells of the colour are relaxed without branches (their
+            // chains interleave; they do not neighbour each other), then
+            // stored where the pass updates them
+            auto cell = [&](auto cc_, T (&u)[NF]) {
                 constexpr int c = decltype(cc_)::value;
-                const int x = 2 * bx + cdx(c), y = 2 * by + cdy(c);
-                if (x < p || y < p || x >= LX - p || y >= LY - p) return;
-                T u[NF], ns[NF];
-                nsum_own<c>(S, O, bx, by, ns);
+                T ns[NF];
+                nsum_own<c>(S, O, G, bx, by, ns);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) u[f] = O.u[c][f];
                 op.relax(u, ns, fr[0][c], xkr[0][c], pbr[0][c], wr[0][c]);
+            };
+            // (a cell the pass does not update gets its own value back: only
+            // its owner writes it, so the store is branch-free)
+            auto put = [&](auto cc_, const T (&u)[NF]) {
+                constexpr int c = decltype(cc_)::value;
+                const int x = 2 * bx + cdx(c), y = 2 * by + cdy(c);
+                const bool in = x >= p && y >= p && x < LX - p && y < LY - p;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    U[f][colour][y][bx] = u[f];
-                    O.u[c][f] = u[f];
+                    const T v = in ? u[f] : O.u[c][f];
+                    U[f][colour][y][bx] = v;
+                    O.u[c][f] = v;
                 }
             };
-            cell(std::integral_constant<int, colour == 0 ? 0 : 2>{});
-            cell(std::integral_constant<int, colour == 0 ? 1 : 3>{});
+            constexpr int c0 = colour == 0 ? 0 : 2, c1 = colour == 0 ? 1 : 3;
+            T u0[NF], u1[NF];
+            cell(std::integral_constant<int, c0>{}, u0);
+            cell(std::integral_constant<int, c1>{}, u1);
+            put(std::integral_constant<int, c0>{}, u0);
+            put(std::integral_constant<int, c1>{}, u1);
             return;
         }
 #pragma unroll
@@ -615,7 +634,7 @@ struct TileWork {
         auto res_own = [&](auto cc_) {
             constexpr int c = decltype(cc_)::value;
             T ns[NF], N[NF];
-            nsum_own<c>(S, O, bx, by, ns);
+            nsum_own<c>(S, O, G, bx, by, ns);
             op.apply(O.u[c], ns, xkr[0][c], pbr[0][c], wr[0][c], N);
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
@@ -996,16 +1015,41 @@ __device__ __forceinline__ void coarse_body(const Op& op_top,
     const int t = threadIdx.x;
     const CoarseGeom& G = A.geo;
     const int N0 = G.m[0] * G.n[0];
-    // load the top level
-    for (int q = t; q < N0; q += NTP) {
+    // load the top level: every stride's loads are issued before the LDS
+    // stores (indices clamped to the last cell, which is then stored twice
+    // with the same value)
+    {
+        constexpr int NQ = (CP_CELLS + NTP - 1) / NTP;
+        constexpr int NV = 2 * NF + (Op::XK ? 1 : 0) + (Op::PB ? 1 : 0) + (Op::PW ? 1 : 0);
+        T v[NQ][NV];
+        int qs[NQ];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            Su[f][q] = A.u[f][q];
-            Sf[f][q] = A.rr[f][q];
+        for (int j = 0; j < NQ; ++j) {
+            const int q = min(t + j * NTP, N0 - 1);
+            qs[j] = q;
+            int k = 0;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                v[j][k++] = A.u[f][q];
+                v[j][k++] = A.rr[f][q];
+            }
+            if constexpr (Op::XK) v[j][k++] = A.xk[q];
+            if constexpr (Op::PB) v[j][k++] = A.pb[q];
+            if constexpr (Op::PW) v[j][k++] = A.pin[q];
         }
-        if constexpr (Op::XK) Sxk[q] = A.xk[q];
-        if constexpr (Op::PB) Spb[q] = A.pb[q];
-        if constexpr (Op::PW) Spw[q] = A.pin[q];
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+            const int q = qs[j];
+            int k = 0;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                Su[f][q] = v[j][k++];
+                Sf[f][q] = v[j][k++];
+            }
+            if constexpr (Op::XK) Sxk[q] = v[j][k++];
+            if constexpr (Op::PB) Spb[q] = v[j][k++];
+            if constexpr (Op::PW) Spw[q] = v[j][k++];
+        }
     }
     __syncthreads();
     // coefficient pyramids (2x2 averages)
