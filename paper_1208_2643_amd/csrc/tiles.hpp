@@ -63,7 +63,9 @@ struct MpfcOp {
         T N[3];
         apply(u, ns, xk, pb, w, N);
         const T r1 = f[0] - N[0], r2 = f[1] - N[1], r3 = f[2] - N[2];
-        const T d = (PIN ? op.al + w : op.al) + nl_lin<T, SCHEME, NEWTON>(pb + u[0], xk);
+        // (the base phi pb exists only in correction form)
+        const T d = (PIN ? op.al + w : op.al) +
+                    nl_lin<T, SCHEME, NEWTON>(DEFECT ? pb + u[0] : u[0], xk);
         const T a = T(4) * op.c * op.ih2, b = T(4) * op.ih2, ec = T(4) * op.e * op.ih2;
         const T det = T(1) + a * d + a * b * ec;
         const T dm = (r2 + (d + b * ec) * r1 - b * r3) * recip_ge1(det);
@@ -322,6 +324,25 @@ struct TileWork {
         const int t = threadIdx.x;
         const int total = G.LX * G.LY;
         constexpr int NLD = (2 * LX2M * LYM + NT - 1) / NT;  // strides of the largest tile
+        // up: u_H - v_H over the tile's coarse footprint, requested first so
+        // that its loads are in flight together with the tile's
+        constexpr int NE = UP ? (CXM * CYM + NT - 1) / NT : 1;
+        T ev[NE][NF];
+        int exs[NE], eys[NE];
+        if constexpr (UP) {
+            const int CX = G.LX2 + 2, CY = (G.LY >> 1) + 2, ctot = CX * CY;
+            const int cx0 = (G.x0 >> 1) - 1, cy0 = (G.y0 >> 1) - 1;
+            (void)CY;
+#pragma unroll
+            for (int j = 0; j < NE; ++j) {
+                const int q = min(t + j * NT, ctot - 1);
+                eys[j] = q / CX;
+                exs[j] = q - eys[j] * CX;
+                const size_t gq = coarse_cell(g, cx0 + exs[j], cy0 + eys[j]);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) ev[j][f] = A.cuH[f][gq] - A.cvH[f][gq];
+            }
+        }
         if (A.zero_in) {
             for (int q = t; q < total; q += NT) {
                 const int y = q / G.LX, x = q - y * G.LX;
@@ -353,24 +374,10 @@ struct TileWork {
             }
         }
         if constexpr (UP) {
-            const int CX = G.LX2 + 2, CY = (G.LY >> 1) + 2, ctot = CX * CY;
-            const int cx0 = (G.x0 >> 1) - 1, cy0 = (G.y0 >> 1) - 1;
-            constexpr int NE = (CXM * CYM + NT - 1) / NT;
-            T v[NE][NF];
-            int xs[NE], ys[NE];
-#pragma unroll
-            for (int j = 0; j < NE; ++j) {
-                const int q = min(t + j * NT, ctot - 1);
-                ys[j] = q / CX;
-                xs[j] = q - ys[j] * CX;
-                const size_t gq = coarse_cell(g, cx0 + xs[j], cy0 + ys[j]);
-#pragma unroll
-                for (int f = 0; f < NF; ++f) v[j][f] = A.cuH[f][gq] - A.cvH[f][gq];
-            }
 #pragma unroll
             for (int j = 0; j < NE; ++j)
 #pragma unroll
-                for (int f = 0; f < NF; ++f) S.E[f][ys[j]][xs[j]] = v[j][f];
+                for (int f = 0; f < NF; ++f) S.E[f][eys[j]][exs[j]] = ev[j][f];
         }
     }
 
