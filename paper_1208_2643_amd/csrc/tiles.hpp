@@ -319,7 +319,11 @@ struct TileWork {
     // are clamped to the last cell, for the load and the store alike (the
     // same value stored twice), so no load sits behind a branch.
     static constexpr int LCH = 4;
-    static __device__ __forceinline__ void load_direct(const TileArgs<T>& A, const Geo& G, Lds& S) {
+    // `mid` runs once the first stride group's loads are issued (before any of
+    // them is waited for): the caller requests the right-hand side there.
+    template <class Mid>
+    static __device__ __forceinline__ void load_direct(const TileArgs<T>& A, const Geo& G, Lds& S,
+                                                       Mid&& mid) {
         const Grid g = A.g;
         const int t = threadIdx.x;
         const int total = G.LX * G.LY;
@@ -344,6 +348,7 @@ struct TileWork {
             }
         }
         if (A.zero_in) {
+            mid();
             for (int q = t; q < total; q += NT) {
                 const int y = q / G.LX, x = q - y * G.LX;
 #pragma unroll
@@ -364,6 +369,7 @@ struct TileWork {
 #pragma unroll
                     for (int f = 0; f < NF; ++f) v[j][f] = A.uin[f][gq];
                 }
+                if (k0 == 0) mid();
 #pragma unroll
                 for (int j = 0; j < LCH; ++j) {
                     if (k0 + j >= NLD) break;
@@ -736,10 +742,9 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
     __shared__ typename W::Lds S;
     if (stopped(stop)) return;
     const typename W::Geo G = W::geo(A, tbx, tby);
-    W::load_direct(A, G, S);
-    __syncthreads();
     typename W::Rhs R;
-    W::fetch_rhs(A, G, R);
+    W::load_direct(A, G, S, [&] { W::fetch_rhs(A, G, R); });
+    __syncthreads();
     W::compute(op, A, G, S, R, pslot);
 }
 
