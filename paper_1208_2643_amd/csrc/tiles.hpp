@@ -743,8 +743,16 @@ __device__ __forceinline__ void tile_body(const Op& op, const TileArgs<typename 
     if (stopped(stop)) return;
     const typename W::Geo G = W::geo(A, tbx, tby);
     typename W::Rhs R;
-    W::load_direct(A, G, S, [&] { W::fetch_rhs(A, G, R); });
-    __syncthreads();
+    if constexpr (UP) {
+        // the right-hand side is first used after the prolongation, which
+        // covers its latency
+        W::load_direct(A, G, S, [] {});
+        __syncthreads();
+        W::fetch_rhs(A, G, R);
+    } else {
+        W::load_direct(A, G, S, [&] { W::fetch_rhs(A, G, R); });
+        __syncthreads();
+    }
     W::compute(op, A, G, S, R, pslot);
 }
 
