@@ -798,12 +798,23 @@ constexpr int kTuneReps = 8;
 // shape whose halo allowance fits and keep the fastest (first within 5 %).
 // The iterates do not depend on the shape (each cell's update is the same
 // arithmetic in every tiling), so tuning changes speed only.
+// `pre` launches the kernel that writes the candidate's inputs in a V-cycle
+// (or nothing): each candidate launch is timed right after it, as in the
+// cycle, where the inputs were just written (by other compute units) rather
+// than left in cache by the candidate's own previous launch; the time of
+// `pre` alone is subtracted.  Back-to-back launches of one small level favour
+// large tiles that are slower inside the cycle.
 // MPFC_TILE_SHAPE=<k> forces shape k instead.
-template <class Fn>
-int tune_one(mpfc_ctx* C, Level& lv, int kind, int H, Fn&& launch) {
+template <class Fn, class Pre>
+int tune_one(mpfc_ctx* C, Level& lv, int kind, int H, Fn&& launch, Pre&& pre, bool has_pre) {
     float t[kNumShapes];
     float best = 1e30f;
     for (int k = 0; k < kNumShapes; ++k) t[k] = 1e30f;
+    float t_pre = 0.f;
+    if (has_pre) {
+        int rc = time_in_graph(C->cap_stream, C->stream, kTuneReps, pre, t_pre);
+        if (rc) return rc;
+    }
     // two interleaved rounds, each shape's faster one counts (the launches of
     // the small levels take a few microseconds and vary from run to run)
     for (int round = 0; round < 2; ++round)
@@ -811,8 +822,11 @@ int tune_one(mpfc_ctx* C, Level& lv, int kind, int H, Fn&& launch) {
             if (H > kShapes[k].hmax || (C->gen && !gen_shape(k))) continue;
             lv.shape[kind] = k;
             float ms = 0.f;
-            int rc = time_in_graph(C->cap_stream, C->stream, kTuneReps, launch, ms);
+            int rc = has_pre ? time_in_graph(C->cap_stream, C->stream, kTuneReps,
+                                             [&](hipStream_t s) { pre(s); launch(s); }, ms)
+                             : time_in_graph(C->cap_stream, C->stream, kTuneReps, launch, ms);
             if (rc) return rc;
+            ms -= t_pre;
             t[k] = ms < t[k] ? ms : t[k];
             best = t[k] < best ? t[k] : best;
         }
@@ -834,36 +848,52 @@ int autotune(mpfc_ctx* C) {
     }
     const bool nw = C->o.linearization == MPFC_NEWTON;
     const int Hd = round_even(2 * C->o.nu1 + 1), Hu = round_even(2 * C->o.nu2 + 1);
+    // one launch of level `lev` (down or up) of the FP64 cycle, of the FP32
+    // correction cycle and of the Poisson cycle
+    auto f64 = [&](hipStream_t s, int lev, int up) {
+        if (C->p.scheme == 1) {
+            if (nw) vcycle_mpfc_t<MpfcOp<double, 1, true, false>>(C, s, lev, up);
+            else vcycle_mpfc_t<MpfcOp<double, 1, false, false>>(C, s, lev, up);
+        } else {
+            if (nw) vcycle_mpfc_t<MpfcOp<double, 2, true, false>>(C, s, lev, up);
+            else vcycle_mpfc_t<MpfcOp<double, 2, false, false>>(C, s, lev, up);
+        }
+    };
+    auto f32 = [&](hipStream_t s, int lev, int up) {
+        if (C->p.scheme == 1) {
+            if (nw) vcycle_inner_t<MpfcOp<float, 1, true, true>>(C, s, lev, up);
+            else vcycle_inner_t<MpfcOp<float, 1, false, true>>(C, s, lev, up);
+        } else {
+            if (nw) vcycle_inner_t<MpfcOp<float, 2, true, true>>(C, s, lev, up);
+            else vcycle_inner_t<MpfcOp<float, 2, false, true>>(C, s, lev, up);
+        }
+    };
+    // Levels in order, down before up: the kernel that writes a candidate's
+    // inputs (the down launch of the level above for a down launch, the same
+    // level's down launch for an up launch) is tuned before it.  The finest
+    // down launch is timed alone.
     for (int l = 0; l < C->Lp; ++l) {
         Level& lv = C->L[l];
         for (int up = 0; up < 2; ++up) {
             const int H = up ? (l == 0 ? Hu : 2 * C->o.nu2) : Hd;
-            int rc = tune_one(C, lv, up ? SH_UP : SH_DN, H, [&](hipStream_t s) {
-                if (C->p.scheme == 1) {
-                    if (nw) vcycle_mpfc_t<MpfcOp<double, 1, true, false>>(C, s, l, up);
-                    else vcycle_mpfc_t<MpfcOp<double, 1, false, false>>(C, s, l, up);
-                } else {
-                    if (nw) vcycle_mpfc_t<MpfcOp<double, 2, true, false>>(C, s, l, up);
-                    else vcycle_mpfc_t<MpfcOp<double, 2, false, false>>(C, s, l, up);
-                }
-            });
+            const int pl = up ? l : l - 1;  // level of the preceding down launch
+            const bool has_pre = pl >= 0;
+            int rc = tune_one(
+                C, lv, up ? SH_UP : SH_DN, H, [&](hipStream_t s) { f64(s, l, up); },
+                [&](hipStream_t s) { f64(s, pl, 0); }, has_pre);
             if (rc) return rc;
             if (C->o.precision == MPFC_MIXED) {
                 const int H32 = up ? 2 * C->o.nu2 : Hd;
-                rc = tune_one(C, lv, up ? SH_UP32 : SH_DN32, H32, [&](hipStream_t s) {
-                    if (C->p.scheme == 1) {
-                        if (nw) vcycle_inner_t<MpfcOp<float, 1, true, true>>(C, s, l, up);
-                        else vcycle_inner_t<MpfcOp<float, 1, false, true>>(C, s, l, up);
-                    } else {
-                        if (nw) vcycle_inner_t<MpfcOp<float, 2, true, true>>(C, s, l, up);
-                        else vcycle_inner_t<MpfcOp<float, 2, false, true>>(C, s, l, up);
-                    }
-                });
+                rc = tune_one(
+                    C, lv, up ? SH_UP32 : SH_DN32, H32, [&](hipStream_t s) { f32(s, l, up); },
+                    [&](hipStream_t s) { f32(s, pl, 0); }, has_pre);
                 if (rc) return rc;
             }
             if (C->o.energy) {
-                rc = tune_one(C, lv, up ? SH_PUP : SH_PDN, up ? (l == 0 ? 6 : 4) : 6,
-                              [&](hipStream_t s) { vcycle_poisson(C, s, l, up); });
+                rc = tune_one(
+                    C, lv, up ? SH_PUP : SH_PDN, up ? (l == 0 ? 6 : 4) : 6,
+                    [&](hipStream_t s) { vcycle_poisson(C, s, l, up); },
+                    [&](hipStream_t s) { vcycle_poisson(C, s, pl, 0); }, has_pre);
                 if (rc) return rc;
             }
         }
