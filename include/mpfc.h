@@ -86,7 +86,10 @@ typedef struct {
  * norm and stopping test; u updated in FP64) around inner_cycles FP32 FAS
  * V-cycles per outer iteration on the correction equation N(u+e) - N(u) = r,
  * whose nonlinear difference is evaluated in factored form; max_cycles then
- * limits the outer iterations.
+ * limits the outer iterations.  inner_cycles_next: FP32 V-cycles in each
+ * outer iteration after the step's first, in [0, 16] (0: inner_cycles).  The
+ * first outer iteration takes the defect of the initial guess down to FP32's
+ * floor; the later ones start from that floor and need fewer cycles.
  * omega: relaxation factor of the smoother, in (0, 2): each cell moves by
  * omega times the solution of its local 3x3 system.  1 (the default) is the
  * collective Gauss-Seidel update of App. B.  App. B's update amplifies a band
@@ -111,6 +114,7 @@ typedef struct {
     int coarse_sweeps;
     double omega;
     int coarse_threshold;
+    int inner_cycles_next;
 } mpfc_opts;
 
 /* Per-step report.  residual_history is a caller-owned host array of

@@ -52,7 +52,9 @@ def make_opts(**kw) -> L.mpfc_opts:
     """Solver options (mpfc_opts, include/mpfc.h) from the library's defaults
     with the given fields replaced: nu1, nu2, max_cycles, tol, precision,
     guess, linearization, coarsest, energy, diverge, inner_cycles,
-    coarse_sweeps, omega (smoother relaxation, 1 = App. B), coarse_threshold."""
+    coarse_sweeps, omega (smoother relaxation, 1 = App. B), coarse_threshold,
+    inner_cycles_next (FP32 cycles of each outer iteration after the first;
+    0 = inner_cycles)."""
     o = L.default_opts()
     for k, v in kw.items():
         if not hasattr(o, k):

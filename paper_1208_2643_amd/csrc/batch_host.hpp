@@ -46,7 +46,7 @@ struct BatchBase {
     virtual int autotune() = 0;
     virtual void prologue(hipStream_t s) = 0;
     virtual void cycle(hipStream_t s) = 0;
-    virtual void outer(int from, hipStream_t s) = 0;
+    virtual void outer(int from, int ncyc, hipStream_t s) = 0;
     virtual void epilogue(hipStream_t s) = 0;
 };
 
@@ -72,7 +72,7 @@ struct mpfc_batch {
     int ncells = 0;
     std::vector<PhaseKey> phases;        // tile phases, largest size first
     BatchBase* impl = nullptr;
-    hipGraphExec_t gx_pro = nullptr, gx_cyc = nullptr, gx_epi = nullptr, gx_out[2] = {};
+    hipGraphExec_t gx_pro = nullptr, gx_cyc = nullptr, gx_epi = nullptr, gx_out[3] = {};  // outer iterations from copy 0, 1; the step's first
     bool use_graph = true;
     int pred_units = 4;
 
@@ -291,11 +291,12 @@ struct BatchImpl : BatchBase {
         finalize(1, s);
     }
 
-    // One outer iteration of mixed precision from FP64 copy `from`.
-    void outer(int from, hipStream_t s) override {
+    // One outer iteration of mixed precision from FP64 copy `from` with
+    // `ncyc` FP32 cycles.
+    void outer(int from, int ncyc, hipStream_t s) override {
         const int np = (int)B->phases.size();
         hipLaunchKernelGGL(k_b_clear_e, dim3(B->ncells), dim3(256), 0, s, B->d_sims, B->d_cells);
-        for (int k = 0; k < B->o.inner_cycles; ++k) {
+        for (int k = 0; k < ncyc; ++k) {
             for (int p = 0; p < np; ++p) launch<Op32, false>(t32[0][p], s);
             if (nc[0]) launch_coarse_batched<Op32, 4>(B->neu, nc[0], d_c32[0], s);
             if (nc[1]) launch_coarse_batched<Op32, 8>(B->neu, nc[1], d_c32[1], s);
@@ -316,14 +317,20 @@ struct BatchImpl : BatchBase {
     }
 };
 
-enum BatchUnit { BU_PRO = 0, BU_CYC = 1, BU_OUT0 = 2, BU_OUT1 = 3, BU_EPI = 4 };
+enum BatchUnit { BU_PRO = 0, BU_CYC = 1, BU_OUT0 = 2, BU_OUT1 = 3, BU_OUTF = 4, BU_EPI = 5 };
+
+// FP32 cycles of the later outer iterations of a step (inner_cycles_next, 0: inner_cycles).
+int batch_inner_next(const mpfc_batch* B) {
+    return B->o.inner_cycles_next ? B->o.inner_cycles_next : B->o.inner_cycles;
+}
 
 void batch_enqueue(mpfc_batch* B, int unit, hipStream_t s) {
     switch (unit) {
         case BU_PRO: B->impl->prologue(s); break;
         case BU_CYC: B->impl->cycle(s); break;
-        case BU_OUT0: B->impl->outer(0, s); break;
-        case BU_OUT1: B->impl->outer(1, s); break;
+        case BU_OUT0: B->impl->outer(0, batch_inner_next(B), s); break;
+        case BU_OUT1: B->impl->outer(1, batch_inner_next(B), s); break;
+        case BU_OUTF: B->impl->outer(1, B->o.inner_cycles, s); break;
         default: B->impl->epilogue(s); break;
     }
 }
@@ -371,7 +378,7 @@ extern "C" {
 void mpfc_batch_destroy(mpfc_batch* B) {
     if (!B) return;
     if (B->stream) (void)hipStreamSynchronize(B->stream);
-    for (hipGraphExec_t g : {B->gx_pro, B->gx_cyc, B->gx_epi, B->gx_out[0], B->gx_out[1]})
+    for (hipGraphExec_t g : {B->gx_pro, B->gx_cyc, B->gx_epi, B->gx_out[0], B->gx_out[1], B->gx_out[2]})
         if (g) (void)hipGraphExecDestroy(g);
     if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
     delete B->impl;
@@ -530,7 +537,8 @@ int mpfc_batch_step(mpfc_batch* B, const double* const* phi_n, const double* con
         if (launched > B->o.max_cycles + 1)
             return fail(MPFC_EHIP, "internal: batch cycle state did not advance");
         for (int k = 0; k < batch; ++k, ++launched) {
-            rc = batch_run(B, B->mixed ? BU_OUT0 + (1 ^ (launched & 1)) : BU_CYC);
+            const int unit = !B->mixed ? BU_CYC : launched == 0 ? BU_OUTF : BU_OUT0 + (1 ^ (launched & 1));
+            rc = batch_run(B, unit);
             if (rc) return rc;
         }
         batch = 1;
@@ -552,7 +560,8 @@ int mpfc_batch_step(mpfc_batch* B, const double* const* phi_n, const double* con
         if (code && worst == MPFC_OK) { worst = code; worst_sim = k; }
         if (infos) {
             mpfc_info& I = infos[k];
-            I.n_cycles = B->mixed ? nouter * B->o.inner_cycles : nouter;
+            I.n_cycles = !B->mixed ? nouter
+                         : nouter > 0 ? B->o.inner_cycles + (nouter - 1) * batch_inner_next(B) : 0;
             I.status = code;
             I.outer_iters = B->mixed ? nouter : 0;
             I.energy_status = MPFC_OK;  // a batch computes no energies

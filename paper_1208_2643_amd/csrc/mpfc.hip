@@ -171,7 +171,8 @@ struct mpfc_ctx {
         float* pb = nullptr;  // base phi (FP32) on this level
     };
     std::vector<FLevel> FL;
-    int inner_cycles = 3;
+    int inner_cycles = 3;                  // FP32 cycles of the step's first outer iteration
+    int inner_next = 3;                    // ... and of each later one
     int pred_units = 4;                    // cycles (outer iterations) the last step needed
     // learned initial guess (guess mode MPFC_GUESS_CNN)
     CnnNet* cnn = nullptr;
@@ -550,9 +551,9 @@ void defect(mpfc_ctx* C, int from, int add, hipStream_t s) {
 }
 
 // One outer iteration of mixed precision starting from FP64 copy `from`:
-// `inner_cycles` FP32 V-cycles on the correction (from e = 0), then the FP64
-// defect step into the other copy.
-void outer_mixed(mpfc_ctx* C, int from, hipStream_t s) {
+// `ncyc` FP32 V-cycles on the correction (from e = 0), then the FP64 defect
+// step into the other copy.
+void outer_mixed(mpfc_ctx* C, int from, int ncyc, hipStream_t s) {
     const auto& FF = C->FL[0];
     const size_t total = (size_t)C->m * C->n;
     // The first inner cycle's finest down launch starts from e = 0 and its down
@@ -562,7 +563,7 @@ void outer_mixed(mpfc_ctx* C, int from, hipStream_t s) {
         for (int f = 0; f < 3; ++f)
             hipLaunchKernelGGL((k_fill<float>), grid1(total), dim3(256), 0, s, FF.e[0][f], total, 0.f);
     const bool nw = C->o.linearization == MPFC_NEWTON;
-    for (int k = 0; k < C->inner_cycles; ++k) {
+    for (int k = 0; k < ncyc; ++k) {
         const bool first = k == 0;
         if (C->p.scheme == 1) {
             if (nw) vcycle_inner_t<MpfcOp<float, 1, true, true>>(C, s, -1, 0, first);
@@ -665,15 +666,23 @@ void vcycle_poisson(mpfc_ctx* C, hipStream_t s, int only = -1, int only_up = 0) 
 }
 
 // What one replayable unit of work is.
-enum CycleKind { CYC_MPFC = 0, CYC_POISSON = 1, CYC_MIXED0 = 2, CYC_MIXED1 = 3 };
+enum CycleKind { CYC_MPFC = 0, CYC_POISSON = 1 };
 
 void enqueue(mpfc_ctx* C, int kind, hipStream_t s) {
-    switch (kind) {
-        case CYC_MPFC: vcycle_mpfc(C, s); break;
-        case CYC_POISSON: vcycle_poisson(C, s); break;
-        case CYC_MIXED0: outer_mixed(C, 0, s); break;
-        default: outer_mixed(C, 1, s); break;
-    }
+    if (kind == CYC_MPFC) vcycle_mpfc(C, s);
+    else vcycle_poisson(C, s);
+}
+
+// Unit `unit` (0, 1, ...) of a mixed-precision step: an outer iteration from
+// FP64 copy 1 (even units; the set-up writes copy 1) or 0, with the first
+// unit's FP32 cycle count or the later ones'.
+void enqueue_outer(mpfc_ctx* C, int unit, hipStream_t s) {
+    outer_mixed(C, 1 ^ (unit & 1), unit == 0 ? C->inner_cycles : C->inner_next, s);
+}
+
+// FP32 cycles that `nouter` outer iterations ran.
+int inner_cycles_run(const mpfc_ctx* C, int nouter) {
+    return nouter > 0 ? C->inner_cycles + (nouter - 1) * C->inner_next : 0;
 }
 
 // Captured graphs of a context, keyed by what they hold (graph_key): the
@@ -734,16 +743,20 @@ int run_poisson_cycle(mpfc_ctx* C) {
 
 // `count` units of the step's solve (V-cycles, or mixed-precision outer
 // iterations, the first being the step's unit number `first`), in runs of at
-// most kMaxRun replayed from one graph each.
+// most kMaxRun replayed from one graph each.  A mixed run's graph depends on
+// the parity of its first unit and on whether it holds unit 0.
 int run_cycles(mpfc_ctx* C, int first, int count) {
     const bool mixed = C->o.precision == MPFC_MIXED;
     while (count > 0) {
         const int k = count < kMaxRun ? count : kMaxRun;
-        const int par = first & 1;
-        const int key = mixed ? graph_key(GK_MIXED, par, k) : graph_key(GK_CYCLES, 0, k);
+        const int f0 = first;
+        const int key = mixed ? graph_key(GK_MIXED, (f0 & 1) + (f0 == 0 ? 2 : 0), k)
+                              : graph_key(GK_CYCLES, 0, k);
         int rc = run_unit(C, key, [&](hipStream_t s) {
-            for (int j = 0; j < k; ++j)
-                enqueue(C, mixed ? CYC_MIXED0 + (1 ^ ((par + j) & 1)) : CYC_MPFC, s);
+            for (int j = 0; j < k; ++j) {
+                if (mixed) enqueue_outer(C, f0 + j, s);
+                else enqueue(C, CYC_MPFC, s);
+            }
         });
         if (rc) return rc;
         first += k;
@@ -1047,6 +1060,8 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
     if (!(o->diverge > 1.0)) return fail(MPFC_EINVAL, "diverge must be > 1");
     if (o->inner_cycles < 1 || o->inner_cycles > 16)
         return fail(MPFC_EINVAL, "inner_cycles must be in [1, 16]");
+    if (o->inner_cycles_next < 0 || o->inner_cycles_next > 16)
+        return fail(MPFC_EINVAL, "inner_cycles_next must be in [0, 16]");
     if (o->coarse_sweeps < 1 || o->coarse_sweeps > 64)
         return fail(MPFC_EINVAL, "coarse_sweeps must be in [1, 64]");
     if (!(o->omega > 0.0 && o->omega < 2.0))
@@ -1358,6 +1373,7 @@ void mpfc_default_opts(mpfc_opts* o) {
     o->coarse_sweeps = 2;
     o->omega = 1.0;
     o->coarse_threshold = 0;
+    o->inner_cycles_next = 0;
 }
 
 int mpfc_validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
@@ -1435,6 +1451,7 @@ static int create_ctx(mpfc_ctx** out, int m, int n, const mpfc_params* p, const 
     const char* ng = std::getenv("MPFC_NO_GRAPH");
     C->use_graph = !(ng && ng[0] == '1');
     C->inner_cycles = o->inner_cycles;
+    C->inner_next = o->inner_cycles_next ? o->inner_cycles_next : o->inner_cycles;
     C->gen = !(is_pow2(m) && is_pow2(n));
     const bool mixed = o->precision == MPFC_MIXED;
     // level hierarchy; a general grid tiles every level but its coarsest
@@ -1683,7 +1700,7 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     }
     const CycleState fin = *hst;
     const int nouter = fin.count - 1;
-    const int ncyc = mixed ? nouter * C->inner_cycles : nouter;
+    const int ncyc = mixed ? inner_cycles_run(C, nouter) : nouter;
     C->pred_units = nouter > 0 ? nouter : 1;
     const int cur = mixed ? 1 ^ (nouter & 1) : 0;
     if (mu_out)

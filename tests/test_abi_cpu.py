@@ -44,6 +44,7 @@ def good():
 
 def test_defaults():
     o = L.default_opts()
+    assert (o.inner_cycles, o.inner_cycles_next) == (3, 0)
     assert (o.nu1, o.nu2, o.max_cycles, o.tol, o.coarsest, o.coarse_sweeps) == \
         (2, 2, 100, 1e-10, 2, 2)
     p, o = good()
@@ -95,7 +96,9 @@ def test_coarse_sweeps_range(value):
 @pytest.mark.parametrize("field,value", [("tol", 0.0), ("max_cycles", 0), ("nu1", -1),
                                          ("coarsest", 3), ("precision", 7), ("guess", 9),
                                          ("linearization", 5), ("diverge", 0.5),
-                                         ("omega", 0.0), ("omega", 2.0), ("omega", float("nan"))])
+                                         ("omega", 0.0), ("omega", 2.0), ("omega", float("nan")),
+                                         ("inner_cycles", 0), ("inner_cycles", 17),
+                                         ("inner_cycles_next", -1), ("inner_cycles_next", 17)])
 def test_invalid_opts_rejected(field, value):
     p, o = good()
     setattr(o, field, value)

@@ -68,19 +68,24 @@ def run_single(m, n, p, phi0, steps, **opts):
     return host(phi), host(psi), [i.n_cycles for i in infos]
 
 
-@pytest.mark.parametrize("scheme,precision,lin", [(2, L.MPFC_FP64, L.MPFC_NEWTON),
-                                                  (1, L.MPFC_FP64, L.MPFC_NEWTON),
-                                                  (2, L.MPFC_MIXED, L.MPFC_NEWTON),
-                                                  (1, L.MPFC_MIXED, L.MPFC_PICARD)])
-def test_batch_matches_single_contexts(scheme, precision, lin):
+@pytest.mark.parametrize("scheme,precision,lin,nxt", [(2, L.MPFC_FP64, L.MPFC_NEWTON, 0),
+                                                      (1, L.MPFC_FP64, L.MPFC_NEWTON, 0),
+                                                      (2, L.MPFC_MIXED, L.MPFC_NEWTON, 0),
+                                                      (1, L.MPFC_MIXED, L.MPFC_PICARD, 0),
+                                                      (2, L.MPFC_MIXED, L.MPFC_NEWTON, 1)])
+def test_batch_matches_single_contexts(scheme, precision, lin, nxt):
+    """Each member of a batch steps as its own context does: same iterates,
+    same cycle counts (nxt: FP32 cycles of the outer iterations after the
+    first, 0 = as many as the first)."""
     sims = members(scheme)
     steps = 3
-    b = api.Batch([(m, n, p) for m, n, p, _ in sims], precision=precision, linearization=lin)
+    b = api.Batch([(m, n, p) for m, n, p, _ in sims], precision=precision, linearization=lin,
+                  inner_cycles_next=nxt)
     phi_b, _, psi_b, infos = api.run_batch(b, [dev(x) for *_, x in sims], steps)
     b.close()
     for k, (m, n, p, phi0) in enumerate(sims):
         phi_s, psi_s, cyc_s = run_single(m, n, p, phi0, steps, precision=precision,
-                                         linearization=lin)
+                                         linearization=lin, inner_cycles_next=nxt)
         assert rel_l2(host(phi_b[k]), phi_s) <= 1e-12, k
         assert rel_l2(host(psi_b[k]), psi_s) <= 1e-10, k
         assert [infos[t][k].n_cycles for t in range(steps)] == cyc_s, k

@@ -338,6 +338,25 @@ def test_mixed_precision_matches_fp64_oracle(scheme):
         assert abs(i.energy_mod - r.energies[2]) <= 1e-9 * abs(r.energies[2])
 
 
+@pytest.mark.parametrize("inner,nxt", [(3, 1), (2, 4)])
+def test_mixed_precision_later_outer_cycle_count(inner, nxt):
+    """inner_cycles FP32 cycles in a step's first outer iteration and
+    inner_cycles_next in each later one: same FP64 fixed point (oracle, 1e-9),
+    and the reported FP32 cycle count is inner + (outer - 1) nxt."""
+    N = 128
+    po, pg = both(2, h=math.pi / 4, dt=0.05)
+    phi0 = I.crystallites(N, N, math.pi / 4, radius_cells=N / 8, seed=3)
+    st = api.Stepper(N, N, pg, tol=1e-10, precision=L.MPFC_MIXED, max_cycles=60,
+                     inner_cycles=inner, inner_cycles_next=nxt)
+    phi_g, _, _, infos = api.run(st, dev(phi0), 5)
+    st.close()
+    phi_o, _, _, _ = O.run(po, phi0, 5, tol=1e-12, max_cycles=300)
+    for i in infos:
+        assert i.status == 0 and i.residual <= 1e-10 and i.outer_iters >= 1
+        assert i.n_cycles == inner + (i.outer_iters - 1) * nxt
+    assert rel_l2(host(phi_g), phi_o) <= 1e-9
+
+
 def test_mixed_precision_full_size_1024():
     """One mixed-precision step of the 1024^2 workload against the oracle."""
     N = 1024
