@@ -305,6 +305,12 @@ __global__ void __launch_bounds__(256) k_cnn_out(CnnOutArgs A) {
         A.part[(size_t)(blockIdx.y * gridDim.x + blockIdx.x) * gridDim.z + s] = bs;
 }
 
+// The one sample of a step's learned guess: the caller's arrays from `io`,
+// the guess into `out`.
+__global__ void k_cnn_sample_io(CnnSample* smp, const StepIO* __restrict__ io, double* out) {
+    if (threadIdx.x == 0) smp[0] = CnnSample{io->phi_nm1, io->phi_n, io->psi, nullptr, out};
+}
+
 // Per-sample scale factors from the sums of (phi^n - phi^{n-1})^2.
 __global__ void k_cnn_scales(const double* __restrict__ sums, int samples, double npix,
                              double out_scale, double* sc) {

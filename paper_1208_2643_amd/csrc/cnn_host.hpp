@@ -229,15 +229,13 @@ namespace {
 // Learned guess of one step into copy 1 of the finest level, its completion
 // and FP64 residual (r2[0]); then, after the extrapolated guess is in copy 0,
 // cnn_choose compares with its residual (r2[1]) and keeps the smaller.
-int cnn_candidate(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const double* psi,
-                  hipStream_t s) {
+// The step's phi^n, phi^{n-1} and psi^n are the caller's arrays in `io`.
+int cnn_candidate(mpfc_ctx* C, const StepIO* io, hipStream_t s) {
     Level& F0 = C->L[0];
     const Grid g0 = F0.g;
     const double ih2 = 1.0 / (F0.h * F0.h);
     CnnNet& N = *C->cnn;
-    N.h_smp[0] = CnnSample{phi_nm1, phi_n, psi, nullptr, F0.u[1][0]};
-    int rc = N.set_samples(s);
-    if (rc) return rc;
+    hipLaunchKernelGGL(k_cnn_sample_io, dim3(1), dim3(64), 0, s, N.d_smp, io, F0.u[1][0]);
     N.forward(s, false);
     const double e = C->p.scheme == 1 ? 1.0 : 0.5;
     const double al = C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha;

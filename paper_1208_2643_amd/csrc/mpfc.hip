@@ -1199,8 +1199,7 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
     return MPFC_OK;
 }
 
-int cnn_candidate(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const double* psi,
-                  hipStream_t s);
+int cnn_candidate(mpfc_ctx* C, const StepIO* io, hipStream_t s);
 void residual_sq(mpfc_ctx* C, int k, double* out, hipStream_t s);
 void cnn_choose(mpfc_ctx* C, hipStream_t s);
 
@@ -1208,10 +1207,9 @@ void cnn_choose(mpfc_ctx* C, hipStream_t s);
 // Source (also copies phi^k), guess and its completion, stop state reset and
 // the first residual norm (FP64), or for mixed precision phi^k in FP32 and the
 // first FP64 defect (copy 0 -> 1).  The coarse levels' phi^k (scheme 2) is
-// averaged by each cycle's down launches.  Without the learned guess the
-// caller's arrays are read from C->io (k_set_io) and the arguments are unused.
-int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const double* psi,
-                  hipStream_t s) {
+// averaged by each cycle's down launches.  The caller's arrays are read from
+// C->io (k_set_io), so the set-up is captured once and replayed.
+int step_prologue(mpfc_ctx* C, hipStream_t s) {
     Level& F0 = C->L[0];
     const Grid g0 = F0.g;
     const size_t total = (size_t)C->m * C->n;
@@ -1237,19 +1235,19 @@ int step_prologue(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, const
                                e, gmode, (const StepIO*)C->io, F0.f[0], F0.f[1], F0.f[2], C->phik,
                                pin, phihat, phi, ka, C->st);
     } else {
+        const StepIO* io = (const StepIO*)C->io;
         if (C->p.scheme == 1)
-            hipLaunchKernelGGL((k_source<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
-                               phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik,
-                               (const double*)nullptr, (const double*)nullptr);
+            hipLaunchKernelGGL((k_source_io<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d,
+                               C->alpha, io, F0.f[0], F0.f[1], F0.f[2], C->phik, (const double*)nullptr,
+                               (const double*)nullptr);
         else
-            hipLaunchKernelGGL((k_source<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
-                               phi_n, phi_nm1, psi, F0.f[0], F0.f[1], F0.f[2], C->phik, pin,
-                               phihat);
+            hipLaunchKernelGGL((k_source_io<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d,
+                               C->alpha, io, F0.f[0], F0.f[1], F0.f[2], C->phik, pin, phihat);
         hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->st);
-        int rc = cnn_candidate(C, phi_n, phi_nm1, psi, s);
+        int rc = cnn_candidate(C, io, s);
         if (rc) return rc;
         residual_sq(C, 1, C->cnn_r2, s);
-        hipLaunchKernelGGL(k_guess, grid1(total), dim3(256), 0, s, g0, gmode, phi_n, phi_nm1, phi);
+        hipLaunchKernelGGL(k_guess, grid1(total), dim3(256), 0, s, g0, gmode, io, phi);
         hipLaunchKernelGGL(k_complete_kappa, grid2(C->m, C->n), B2, 0, s, g0, ih2, e, phi, F0.f[2],
                            ka);
     }
@@ -1621,10 +1619,9 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     const bool learned = C->o.guess == MPFC_GUESS_CNN;
     // The caller's arrays, for the captured set-up and wrap-up.
     hipLaunchKernelGGL(k_set_io, dim3(1), dim3(64), 0, s, C->io, phi_n, phi_nm1, psi, phi_np1);
-    int rc = learned ? step_prologue(C, phi_n, phi_nm1, psi, s)
-                     : run_unit(C, graph_key(GK_PROLOGUE), [&](hipStream_t cs) {
-                           (void)step_prologue(C, phi_n, phi_nm1, psi, cs);
-                       });
+    int rc = run_unit(C, graph_key(GK_PROLOGUE), [&](hipStream_t cs) {
+        (void)step_prologue(C, cs);
+    });
     if (rc) return rc;
     const CycleState* hst = (const CycleState*)C->host_buf;
     const CycleState* hpst = (const CycleState*)(C->host_buf + 8);

@@ -139,6 +139,16 @@ __device__ __forceinline__ void source_cell(const Grid& g, double ih2, double d,
     }
 }
 
+// Caller arrays of one step.  The step's set-up and wrap-up run as captured
+// graphs, so these pointers, which change from step to step, are read from a
+// small device table that k_set_io fills before each step.
+struct StepIO {
+    const double* phi_n;    // phi^k
+    const double* phi_nm1;  // phi^{k-1}
+    double* psi;            // psi^k on entry, psi^{k+1} after the wrap-up
+    double* phi_np1;        // phi^{k+1}
+};
+
 template <int SCHEME>
 __global__ void __launch_bounds__(256) k_source(Grid g, double ih2, double d, double alpha,
                                                 const double* __restrict__ phik,
@@ -154,16 +164,32 @@ __global__ void __launch_bounds__(256) k_source(Grid g, double ih2, double d, do
                         phihat);
 }
 
+// The same, for a step whose phi^k, phi^{k-1}, psi^k are the caller's arrays
+// in `io`.
+template <int SCHEME>
+__global__ void __launch_bounds__(256) k_source_io(Grid g, double ih2, double d, double alpha,
+                                                   const StepIO* __restrict__ io, double* S1,
+                                                   double* S2, double* S3, double* phik_copy,
+                                                   const double* __restrict__ pin,
+                                                   const double* __restrict__ phihat) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.m || j >= g.n) return;
+    source_cell<SCHEME>(g, ih2, d, alpha, io->phi_n, io->phi_nm1, io->psi, S1, S2, S3, phik_copy,
+                        i, j, pin, phihat);
+}
+
 // Initial guess phi^(0): phi^k (mode 0) or 2 phi^k - phi^{k-1} (mode 1).
 __device__ __forceinline__ double guess_value(int mode, double pk, double pkm1) {
     return mode == 1 ? 2.0 * pk - pkm1 : pk;
 }
 
-__global__ void __launch_bounds__(256) k_guess(Grid g, int mode, const double* __restrict__ phik,
-                                               const double* __restrict__ phikm1, double* phi) {
+// The guess from the caller's arrays in `io`.
+__global__ void __launch_bounds__(256) k_guess(Grid g, int mode, const StepIO* __restrict__ io,
+                                               double* phi) {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= (size_t)g.m * g.n) return;
-    phi[q] = guess_value(mode, phik[q], phikm1[q]);
+    phi[q] = guess_value(mode, io->phi_n[q], io->phi_nm1[q]);
 }
 
 // Consistent completion of the guess: kappa = S3 + e Lap phi (so N^(3) = S^(3)).
@@ -174,16 +200,6 @@ __device__ __forceinline__ void complete_kappa_cell(const Grid& g, double ih2, d
     const size_t q = at(i, j, g);
     ka[q] = S3[q] + e * (nsum(phi, i, j, g) - 4.0 * phi[q]) * ih2;
 }
-
-// Caller arrays of one step.  The step's set-up and wrap-up run as captured
-// graphs, so these pointers, which change from step to step, are read from a
-// small device table that k_set_io fills before each step.
-struct StepIO {
-    const double* phi_n;    // phi^k
-    const double* phi_nm1;  // phi^{k-1}
-    double* psi;            // psi^k on entry, psi^{k+1} after the wrap-up
-    double* phi_np1;        // phi^{k+1}
-};
 
 __global__ void k_set_io(StepIO* io, const double* phi_n, const double* phi_nm1, double* psi,
                          double* phi_np1) {
