@@ -42,6 +42,7 @@ constexpr int CNN_HALO = 18;
 constexpr int CNN_PX = 36;           // LDS stride of one pixel (32 channels + 4 pad)
 constexpr int CNN_NFRAG1 = 8;        // layer 1: K = 64 (4 chunks) x 2 M tiles
 constexpr int CNN_NFRAG = 36;        // 9 taps x 2 K chunks x 2 M tiles
+constexpr int CNN_NFRAG32 = 18;      // K = 32 instruction: 9 taps x 2 M tiles
 // parameter offsets in the FP32 vector (blob order, no header)
 constexpr int CNN_CIN = 3;
 constexpr int CNN_W1 = 0, CNN_B1 = 864, CNN_W2 = 896, CNN_B2 = 10112, CNN_W3 = 10144,
@@ -81,17 +82,33 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
 }
 
 // Halo tile (18 x 18 pixels, 32 channels) of an NHWC activation into LDS
-// (pixel stride CNN_PX), periodic wrap.  Uses every thread of the block.
+// (pixel stride CNN_PX), periodic wrap.  Workgroups of 256 threads; each
+// thread moves CNN_HREG pieces of 16 bytes (8 channels of a pixel), all loads
+// issued before the first is waited for: the piece index is clamped (surplus
+// loads of the last threads repeat a valid piece and are not stored), so no
+// load sits behind a branch.
+constexpr int CNN_HCH = CNN_HALO * CNN_HALO * 4;  // 16-byte pieces of a halo tile
+constexpr int CNN_HREG = (CNN_HCH + 255) / 256;   // ... per thread
 __device__ __forceinline__ void cnn_load_halo(const uint16_t* __restrict__ act, size_t base,
                                               int x0, int y0, int m, int n, uint16_t* lds) {
-    for (int c = threadIdx.x; c < CNN_HALO * CNN_HALO * 4; c += blockDim.x) {
+    const int t = threadIdx.x;
+    uint4 v[CNN_HREG];
+#pragma unroll
+    for (int j = 0; j < CNN_HREG; ++j) {
+        const int c = min(t + 256 * j, CNN_HCH - 1);
         const int pi = c >> 2, part = c & 3;
         const int ty = pi / CNN_HALO, tx = pi - ty * CNN_HALO;
         const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (m - 1);
-        const uint4 v = *(const uint4*)(act + (base + (size_t)gy * m + gx) * CNN_CH + part * 8);
-        uint2* d = (uint2*)(lds + pi * CNN_PX + part * 8);
-        d[0] = make_uint2(v.x, v.y);
-        d[1] = make_uint2(v.z, v.w);
+        v[j] = *(const uint4*)(act + (base + (size_t)gy * m + gx) * CNN_CH + part * 8);
+    }
+#pragma unroll
+    for (int j = 0; j < CNN_HREG; ++j) {
+        const int c = t + 256 * j;
+        if (c < CNN_HCH) {
+            uint2* d = (uint2*)(lds + (c >> 2) * CNN_PX + (c & 3) * 8);
+            d[0] = make_uint2(v[j].x, v[j].y);
+            d[1] = make_uint2(v[j].z, v[j].w);
+        }
     }
 }
 
@@ -103,13 +120,27 @@ __device__ __forceinline__ void cnn_load_halo(const uint16_t* __restrict__ act, 
 __device__ __forceinline__ void cnn_load_inputs(const CnnSample& S, double in_scale, double dt,
                                                 double inv_sigma1, int x0, int y0, int m, int n,
                                                 uint16_t (*xs)[CNN_HALO * CNN_HALO]) {
-    for (int t = threadIdx.x; t < CNN_HALO * CNN_HALO; t += blockDim.x) {
+    // 256 threads, two pixels each (the second clamped and not stored), all
+    // six loads issued before any is used
+    constexpr int NPIX = CNN_HALO * CNN_HALO;
+    double p0[2], pm[2], ps[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int t = min((int)threadIdx.x + 256 * j, NPIX - 1);
         const int ty = t / CNN_HALO, tx = t - ty * CNN_HALO;
         const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (m - 1);
         const size_t q = (size_t)gy * m + gx;
-        const double v0 = S.p0[q], d1 = v0 - S.pm1[q];
+        p0[j] = S.p0[q];
+        pm[j] = S.pm1[q];
+        ps[j] = S.psi[q];
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int t = threadIdx.x + 256 * j;
+        if (t >= NPIX) continue;
+        const double v0 = p0[j], d1 = v0 - pm[j];
         const float x[3] = {(float)(in_scale * v0), (float)(d1 * inv_sigma1),
-                            (float)((dt * S.psi[q] - d1) * inv_sigma1)};
+                            (float)((dt * ps[j] - d1) * inv_sigma1)};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const uint16_t hi = bf16_bits(x[c]);
@@ -172,6 +203,7 @@ __global__ void __launch_bounds__(256) k_cnn_conv(CnnConvArgs A) {
         __syncthreads();
         {
             const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
+#pragma unroll
             for (int k = 0; k < CNN_K1; ++k) lds[t * CNN_PX1 + k] = cnn_im2col(xs, k, ty, tx);
         }
     } else {
@@ -241,6 +273,96 @@ __global__ void __launch_bounds__(256) k_cnn_conv(CnnConvArgs A) {
             }
             *(uint2*)(A.out + q * CNN_CH + co) = make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16),
                                                            (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+        }
+    }
+}
+
+// Forward 32 -> 32 convolution on the K = 32 instruction
+// (v_mfma_f32_16x16x32_bf16: A[m = l % 16][k = 8 (l / 16) + i],
+// B[k = 8 (l / 16) + i][n = l % 16], D as for the K = 16 one), same result as
+// k_cnn_conv<false, CNN_FWD> up to the order of the FP32 additions.  The halo
+// tile's LDS pixel stride is CNN_PX32, so every lane reads the 8 channels of
+// its B operand as one 16-byte access.  Grid (m / 16, n / 16, samples), 256
+// threads; wave w computes rows 4w ... 4w + 3, the nine taps outside and the
+// four rows inside (eight independent accumulation chains).
+constexpr int CNN_PX32 = 40;
+typedef __bf16 cnn_v8b __attribute__((ext_vector_type(8)));
+
+__global__ void __launch_bounds__(256, 3) k_cnn_conv32(CnnConvArgs A) {
+    __shared__ __align__(16) uint16_t lds[CNN_HALO * CNN_HALO * CNN_PX32];
+    const int m = A.m, n = A.n;
+    const size_t NP = (size_t)m * n;
+    const int s = blockIdx.z;
+    const size_t base = (size_t)s * NP;
+    const int x0 = blockIdx.x * CNN_TILE, y0 = blockIdx.y * CNN_TILE;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int g = lane >> 4, c16 = lane & 15;
+    cnn_v8b wf[CNN_NFRAG32];
+#pragma unroll
+    for (int f = 0; f < CNN_NFRAG32; ++f)
+        wf[f] = __builtin_bit_cast(cnn_v8b, *(const uint4*)(A.wfrag + ((size_t)f * 64 + lane) * 8));
+    {
+        // halo pieces as in cnn_load_halo, stored with the 16-byte stride
+        uint4 v[CNN_HREG];
+#pragma unroll
+        for (int j = 0; j < CNN_HREG; ++j) {
+            const int c = min(t + 256 * j, CNN_HCH - 1);
+            const int pi = c >> 2, part = c & 3;
+            const int ty = pi / CNN_HALO, tx = pi - ty * CNN_HALO;
+            const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (m - 1);
+            v[j] = *(const uint4*)(A.in + (base + (size_t)gy * m + gx) * CNN_CH + part * 8);
+        }
+#pragma unroll
+        for (int j = 0; j < CNN_HREG; ++j) {
+            const int c = t + 256 * j;
+            if (c < CNN_HCH) *(uint4*)(lds + (c >> 2) * CNN_PX32 + (c & 3) * 8) = v[j];
+        }
+    }
+    __syncthreads();
+    cnn_v4f acc[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        acc[r][0] = cnn_v4f{0.f, 0.f, 0.f, 0.f};
+        acc[r][1] = cnn_v4f{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+        cnn_v8b b[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            b[r] = __builtin_bit_cast(
+                cnn_v8b,
+                *(const uint4*)(lds + ((wave * 4 + r + ky) * CNN_HALO + c16 + kx) * CNN_PX32 + 8 * g));
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+                acc[r][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[tap * 2 + mt], b[r],
+                                                                     acc[r][mt], 0, 0, 0);
+    }
+    // epilogue: lane holds channels 16 mt + 4g .. + 3 of pixel (row, c16)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = wave * 4 + r;
+        const size_t q = base + (size_t)(y0 + row) * m + x0 + c16;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const int co = mt * 16 + 4 * g;
+            uint16_t o[4], zb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float z = acc[r][mt][i] + A.bias[co + i];
+                zb[i] = bf16_bits(z);
+                o[i] = bf16_bits(gelu_f(z));
+            }
+            if (A.zout)
+                *(uint2*)(A.zout + q * CNN_CH + co) =
+                    make_uint2((uint32_t)zb[0] | ((uint32_t)zb[1] << 16),
+                               (uint32_t)zb[2] | ((uint32_t)zb[3] << 16));
+            *(uint2*)(A.out + q * CNN_CH + co) =
+                make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16),
+                           (uint32_t)o[2] | ((uint32_t)o[3] << 16));
         }
     }
 }
@@ -602,7 +724,24 @@ struct CnnFrags {
     uint16_t* r2;
     uint16_t* r3;
     float* w4;
+    uint16_t* x2;   // layers 2, 3 forward for the K = 32 instruction (k_cnn_conv32)
+    uint16_t* x3;
 };
+
+// Weight fragments of layers 2 and 3 for v_mfma_f32_16x16x32_bf16: fragment
+// f = tap * 2 + mt, lane l, element i holds W[tap][ci = 8 (l / 16) + i][co =
+// 16 mt + l % 16] at ((f * 64 + l) * 8 + i).
+__global__ void __launch_bounds__(256) k_cnn_prepare32(const float* __restrict__ th, CnnFrags F) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    constexpr int NX = CNN_NFRAG32 * 64 * 8;
+    if (e >= 2 * NX) return;
+    const int which = e / NX, r = e - which * NX;
+    const int f = r >> 9, lane = (r >> 3) & 63, i = r & 7;
+    const int tap = f >> 1, mt = f & 1;
+    const int co = mt * 16 + (lane & 15), ci = 8 * (lane >> 4) + i;
+    const int base = which ? CNN_W3 : CNN_W2;
+    (which ? F.x3 : F.x2)[r] = bf16_bits(th[base + (tap * CNN_CH + ci) * CNN_CH + co]);
+}
 
 __global__ void __launch_bounds__(256) k_cnn_prepare(const float* __restrict__ th, CnnFrags F) {
     const int e = blockIdx.x * 256 + threadIdx.x;

@@ -82,6 +82,8 @@ struct CnnNet {
         A(&fr.r2, CNN_NFRAG * 256);
         A(&fr.r3, CNN_NFRAG * 256);
         A(&fr.w4, 9 * CNN_CH);
+        A(&fr.x2, CNN_NFRAG32 * 64 * 8);
+        A(&fr.x3, CNN_NFRAG32 * 64 * 8);
         if (train) {
             for (int l = 1; l <= 3; ++l) { A(&a[l], act); A(&z[l], act); }
             A(&dz[0], act);
@@ -117,6 +119,8 @@ struct CnnNet {
     void prepare(hipStream_t s) {
         const int total = CNN_NFRAG1 * 256 + 4 * CNN_NFRAG * 256 + 9 * CNN_CH;
         hipLaunchKernelGGL(k_cnn_prepare, dim3((total + 255) / 256), dim3(256), 0, s, theta, fr);
+        hipLaunchKernelGGL(k_cnn_prepare32, dim3(2 * CNN_NFRAG32 * 64 * 8 / 256), dim3(256), 0, s,
+                           theta, fr);
     }
 
     int load(const float* blob, hipStream_t s) {
@@ -136,6 +140,11 @@ struct CnnNet {
         return MPFC_OK;
     }
 
+    // A forward 32 -> 32 layer on the K = 32 instruction.
+    void conv32(const CnnConvArgs& c, hipStream_t s) {
+        hipLaunchKernelGGL(k_cnn_conv32, dim3(m / CNN_TILE, n / CNN_TILE, B), dim3(256), 0, s, c);
+    }
+
     // Scales, three hidden layers and the output layer.  Inference writes the
     // mean-corrected guess into every sample's `out`; training writes d loss /
     // d delta and leaves the per-sample sums of err^2 in `sums`.
@@ -149,12 +158,12 @@ struct CnnNet {
         c.m = m; c.n = n; c.smp = d_smp; c.sc = sc; c.in_scale = in_scale; c.dt = dt;
         c.wfrag = fr.f1; c.bias = theta + CNN_B1; c.out = a[1]; c.zout = training ? z[1] : nullptr;
         hipLaunchKernelGGL((k_cnn_conv<true, CNN_FWD>), tg, blk, 0, s, c);
-        c.in = a[1]; c.wfrag = fr.f2; c.bias = theta + CNN_B2; c.out = a[2];
+        c.in = a[1]; c.wfrag = fr.x2; c.bias = theta + CNN_B2; c.out = a[2];
         c.zout = training ? z[2] : nullptr;
-        hipLaunchKernelGGL((k_cnn_conv<false, CNN_FWD>), tg, blk, 0, s, c);
-        c.in = a[2]; c.wfrag = fr.f3; c.bias = theta + CNN_B3; c.out = a[3];
+        conv32(c, s);
+        c.in = a[2]; c.wfrag = fr.x3; c.bias = theta + CNN_B3; c.out = a[3];
         c.zout = training ? z[3] : nullptr;
-        hipLaunchKernelGGL((k_cnn_conv<false, CNN_FWD>), tg, blk, 0, s, c);
+        conv32(c, s);
         CnnOutArgs o{};
         o.m = m; o.n = n; o.in = a[3]; o.smp = d_smp; o.sc = sc; o.w4 = fr.w4;
         o.b4 = theta + CNN_B4; o.gd = gd; o.part = part;
