@@ -772,8 +772,9 @@ __global__ void __launch_bounds__(256) k_cnn_prepare(const float* __restrict__ t
     if (r < 9 * CNN_CH) F.w4[r] = bf16_val(bf16_bits(th[CNN_W4 + r]));
 }
 
-// Candidate choice of the step's initial guess: if the learned guess (copy 1)
-// has the smaller FP64 residual, copy it over the extrapolated one (copy 0).
+// Candidate choice of the step's initial guess: the learned guess (copy 0) is
+// kept when its FP64 residual is the smaller one; otherwise the extrapolated
+// guess (copy 1) is copied over it.
 // counts[0] counts the steps that used it, counts[1] the fallbacks; chosen[0]
 // receives the squared residual norm of the guess kept.
 __global__ void __launch_bounds__(256) k_cnn_pick(const double* __restrict__ r2, size_t total,
@@ -788,7 +789,7 @@ __global__ void __launch_bounds__(256) k_cnn_pick(const double* __restrict__ r2,
         counts[use ? 0 : 1] += 1ull;
         chosen[0] = use ? r2[0] : r2[1];
     }
-    if (!use || q >= total) return;
+    if (use || q >= total) return;
     u0a[q] = u1a[q];
     u0b[q] = u1b[q];
     u0c[q] = u1c[q];

@@ -1214,50 +1214,38 @@ int step_prologue(mpfc_ctx* C, hipStream_t s) {
     const Grid g0 = F0.g;
     const size_t total = (size_t)C->m * C->n;
     const double ih2 = 1.0 / (F0.h * F0.h);
-    double* phi = F0.u[0][0];
-    double* mu = F0.u[0][1];
-    double* ka = F0.u[0][2];
     const double e = C->p.scheme == 1 ? 1.0 : 0.5;
     const double al = C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha;
     const bool learned = C->o.guess == MPFC_GUESS_CNN;
     const int gmode = C->o.guess == MPFC_GUESS_PREV ? 0 : 1;
     const double* pin = C->pinned ? F0.pin : nullptr;
     const double* phihat = C->pinned ? C->phihat : nullptr;
-    if (!learned) {
-        // source, guess and kappa in one pass
-        // (the caller's arrays from C->io: this part is captured once and replayed)
-        if (C->p.scheme == 1)
-            hipLaunchKernelGGL((k_setup<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
-                               e, gmode, (const StepIO*)C->io, F0.f[0], F0.f[1], F0.f[2], C->phik,
-                               (const double*)nullptr, (const double*)nullptr, phi, ka, C->st);
-        else
-            hipLaunchKernelGGL((k_setup<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha,
-                               e, gmode, (const StepIO*)C->io, F0.f[0], F0.f[1], F0.f[2], C->phik,
-                               pin, phihat, phi, ka, C->st);
-    } else {
-        const StepIO* io = (const StepIO*)C->io;
-        if (C->p.scheme == 1)
-            hipLaunchKernelGGL((k_source_io<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d,
-                               C->alpha, io, F0.f[0], F0.f[1], F0.f[2], C->phik, (const double*)nullptr,
-                               (const double*)nullptr);
-        else
-            hipLaunchKernelGGL((k_source_io<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d,
-                               C->alpha, io, F0.f[0], F0.f[1], F0.f[2], C->phik, pin, phihat);
-        hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, C->st);
-        int rc = cnn_candidate(C, io, s);
-        if (rc) return rc;
-        residual_sq(C, 1, C->cnn_r2, s);
-        hipLaunchKernelGGL(k_guess, grid1(total), dim3(256), 0, s, g0, gmode, io, phi);
-        hipLaunchKernelGGL(k_complete_kappa, grid2(C->m, C->n), B2, 0, s, g0, ih2, e, phi, F0.f[2],
-                           ka);
-    }
+    // Source, guess and kappa in one pass (the caller's arrays from C->io: this
+    // part is captured once and replayed); with the learned guess the
+    // extrapolated candidate goes to copy 1 and the network's to copy 0.
+    const int ce = learned ? 1 : 0;
     if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_complete_mu<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, phi,
-                           C->phik, ka, F0.f[1], mu, (const double*)nullptr);
+        hipLaunchKernelGGL((k_setup<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha, e,
+                           gmode, (const StepIO*)C->io, F0.f[0], F0.f[1], F0.f[2], C->phik,
+                           (const double*)nullptr, (const double*)nullptr, F0.u[ce][0],
+                           F0.u[ce][2], C->st);
     else
-        hipLaunchKernelGGL((k_complete_mu<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, phi,
-                           C->phik, ka, F0.f[1], mu, (const double*)(C->pinned ? F0.pin : nullptr));
-    if (learned) cnn_choose(C, s);
+        hipLaunchKernelGGL((k_setup<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, C->d, C->alpha, e,
+                           gmode, (const StepIO*)C->io, F0.f[0], F0.f[1], F0.f[2], C->phik, pin,
+                           phihat, F0.u[ce][0], F0.u[ce][2], C->st);
+    if (C->p.scheme == 1)
+        hipLaunchKernelGGL((k_complete_mu<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al,
+                           F0.u[ce][0], C->phik, F0.u[ce][2], F0.f[1], F0.u[ce][1],
+                           (const double*)nullptr);
+    else
+        hipLaunchKernelGGL((k_complete_mu<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al,
+                           F0.u[ce][0], C->phik, F0.u[ce][2], F0.f[1], F0.u[ce][1],
+                           (const double*)(C->pinned ? F0.pin : nullptr));
+    if (learned) {
+        int rc = cnn_candidate(C, (const StepIO*)C->io, s);  // into copy 0, completed
+        if (rc) return rc;
+        cnn_choose(C, s);
+    }
     if (C->o.precision != MPFC_MIXED) {
         if (learned) {  // the pick left the kept guess's squared norm in part[0]
             hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, 1, C->st,
