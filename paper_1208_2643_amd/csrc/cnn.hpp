@@ -289,12 +289,17 @@ constexpr int CNN_PX32 = 40;
 typedef __bf16 cnn_v8b __attribute__((ext_vector_type(8)));
 
 __global__ void __launch_bounds__(256, 3) k_cnn_conv32(CnnConvArgs A) {
-    __shared__ __align__(16) uint16_t lds[CNN_HALO * CNN_HALO * CNN_PX32];
+    constexpr int RW = 4;                      // rows per wave (8 measured slower)
+    constexpr int TH = 4 * RW;                 // tile rows (four waves of RW rows)
+    constexpr int HR = TH + 2;                 // halo rows
+    constexpr int NPC = HR * CNN_HALO * 4;     // 16-byte pieces of the halo tile
+    constexpr int NREG = (NPC + 255) / 256;
+    __shared__ __align__(16) uint16_t lds[HR * CNN_HALO * CNN_PX32];
     const int m = A.m, n = A.n;
     const size_t NP = (size_t)m * n;
     const int s = blockIdx.z;
     const size_t base = (size_t)s * NP;
-    const int x0 = blockIdx.x * CNN_TILE, y0 = blockIdx.y * CNN_TILE;
+    const int x0 = blockIdx.x * CNN_TILE, y0 = blockIdx.y * TH;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int g = lane >> 4, c16 = lane & 15;
     cnn_v8b wf[CNN_NFRAG32];
@@ -303,39 +308,39 @@ __global__ void __launch_bounds__(256, 3) k_cnn_conv32(CnnConvArgs A) {
         wf[f] = __builtin_bit_cast(cnn_v8b, *(const uint4*)(A.wfrag + ((size_t)f * 64 + lane) * 8));
     {
         // halo pieces as in cnn_load_halo, stored with the 16-byte stride
-        uint4 v[CNN_HREG];
+        uint4 v[NREG];
 #pragma unroll
-        for (int j = 0; j < CNN_HREG; ++j) {
-            const int c = min(t + 256 * j, CNN_HCH - 1);
+        for (int j = 0; j < NREG; ++j) {
+            const int c = min(t + 256 * j, NPC - 1);
             const int pi = c >> 2, part = c & 3;
             const int ty = pi / CNN_HALO, tx = pi - ty * CNN_HALO;
             const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (m - 1);
             v[j] = *(const uint4*)(A.in + (base + (size_t)gy * m + gx) * CNN_CH + part * 8);
         }
 #pragma unroll
-        for (int j = 0; j < CNN_HREG; ++j) {
+        for (int j = 0; j < NREG; ++j) {
             const int c = t + 256 * j;
-            if (c < CNN_HCH) *(uint4*)(lds + (c >> 2) * CNN_PX32 + (c & 3) * 8) = v[j];
+            if (c < NPC) *(uint4*)(lds + (c >> 2) * CNN_PX32 + (c & 3) * 8) = v[j];
         }
     }
     __syncthreads();
-    cnn_v4f acc[4][2];
+    cnn_v4f acc[RW][2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < RW; ++r) {
         acc[r][0] = cnn_v4f{0.f, 0.f, 0.f, 0.f};
         acc[r][1] = cnn_v4f{0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int ky = tap / 3, kx = tap - 3 * (tap / 3);
-        cnn_v8b b[4];
+        cnn_v8b b[RW];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < RW; ++r)
             b[r] = __builtin_bit_cast(
                 cnn_v8b,
-                *(const uint4*)(lds + ((wave * 4 + r + ky) * CNN_HALO + c16 + kx) * CNN_PX32 + 8 * g));
+                *(const uint4*)(lds + ((wave * RW + r + ky) * CNN_HALO + c16 + kx) * CNN_PX32 + 8 * g));
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < RW; ++r)
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt)
                 acc[r][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[tap * 2 + mt], b[r],
@@ -343,8 +348,8 @@ __global__ void __launch_bounds__(256, 3) k_cnn_conv32(CnnConvArgs A) {
     }
     // epilogue: lane holds channels 16 mt + 4g .. + 3 of pixel (row, c16)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = wave * 4 + r;
+    for (int r = 0; r < RW; ++r) {
+        const int row = wave * RW + r;
         const size_t q = base + (size_t)(y0 + row) * m + x0 + c16;
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
