@@ -242,3 +242,37 @@ def test_learned_guess_with_mixed_precision():
     assert all(i.status == 0 and i.residual <= 1e-10 and i.outer_iters > 0 for i in im)
     assert used >= 10 and used + fb == 12
     assert rel(host(pm), host(pe)) < 1e-9
+
+
+@pytest.mark.parametrize("precision", [L.MPFC_FP64, L.MPFC_MIXED])
+def test_learned_guess_graph_replay_equals_direct_launches(precision):
+    """The learned-guess set-up (the network, both candidates, their residuals
+    and the choice) replays a captured graph whose kernels read the caller's
+    arrays from the step's device table; with launch timing on, the same
+    kernels are launched one by one.  Six steps of each, with the program's
+    own eager work between them and the arrays rotating, give the same states
+    (each context tunes its own tile shapes, which may regroup the norm's
+    partial sums, hence a bar rather than bitwise equality) and the same
+    choice of candidate in every step."""
+    from paper_1208_2643_amd import guess_net
+    p = api.Params(**PARAMS)
+    phi0 = I.crystallites(128, 128, math.pi / 4, radius_cells=16, seed=5)
+
+    def touch(phi, nxt, psi, info):
+        assert info.status == 0
+        float((nxt - phi).abs().sum())   # eager torch kernels, then a sync
+
+    runs = []
+    for direct in (False, True):
+        st = api.Stepper(128, 128, p, energy=0, guess=L.MPFC_GUESS_CNN, precision=precision)
+        st.load_cnn(guess_net.load())
+        if direct:
+            st.profile(True)
+        phi, _, psi, infos = api.run(st, dev(phi0), 6, record=touch)
+        runs.append((host(phi), host(psi), [i.history[0] for i in infos], st.cnn_counts()))
+        st.close()
+    (pa, sa, ha, ca), (pb, sb, hb, cb) = runs
+    assert np.max(np.abs(pa - pb)) <= 1e-12
+    assert np.max(np.abs(sa - sb)) <= 1e-10
+    assert np.allclose(ha, hb, rtol=1e-9, atol=0)   # residual of the kept guess
+    assert ca == cb and ca[0] >= 4
