@@ -178,11 +178,11 @@ def cpu_baseline(params, phi0, tol, budget_s):
                                  "includes)"}}
 
 
-def bench_big(api, inputs, torch, dev, params, tol, steps, warmup, N=2048, inner=4, nxt=3):
+def bench_big(api, inputs, torch, dev, params, tol, steps, warmup, N=2048, inner=4, nxt=3, nuc=1):
     phi0 = inputs.crystallites(N, N, params["h"], seed=3)
     res = {"workload": f"{N}x{N}, second-order scheme, crystallites seed 3, {steps} steps, "
                        "V(2,2) to 1e-10, energies off", "inner_cycles": inner,
-           "inner_cycles_next": nxt}
+           "inner_cycles_next": nxt, "inner_nu_coarse": nuc}
     finals = {}
     # the oracle's trajectory of this workload (FP64, solved to 1e-12 per step),
     # sampled at fixed cells, for the first steps (tests/golden/make_fullsize.py)
@@ -194,7 +194,8 @@ def bench_big(api, inputs, torch, dev, params, tol, steps, warmup, N=2048, inner
             golden = {"idx": z["idx"], "phi": z["phi"], "steps": int(z["phi"].shape[0])}
         gidx = torch.from_numpy(golden["idx"]).to(dev)
     for name, kw in (("fp64", dict(precision=0)),
-                     ("mixed", dict(precision=1, inner_cycles=inner, inner_cycles_next=nxt))):
+                     ("mixed", dict(precision=1, inner_cycles=inner, inner_cycles_next=nxt,
+                                    inner_nu_coarse=nuc))):
         st = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2, energy=0, **kw)
         phi = torch.from_numpy(phi0).to(dev)
         prev = phi.clone()
@@ -245,7 +246,8 @@ def bench_learned(api, inputs, torch, dev, params, tol, steps, warmup, N):
     phi0 = inputs.crystallites(N, N, params["h"], seed=5)
     res = {"workload": f"{N}x{N}, second-order scheme, crystallites seed 5, {steps} steps, "
                        "V(2,2) to 1e-10 (FP64, and mixed precision with 3 FP32 cycles in the "
-                       "first outer iteration and 2 in each later one), energies off",
+                       "first outer iteration and 2 in each later one, V(1,1) below the finest "
+                       "level), energies off",
            "network": guess_net.meta().get("validation_loss") if os.path.exists(
                guess_net.DEFAULT_WEIGHTS + ".json") else None}
     finals = {}
@@ -253,7 +255,8 @@ def bench_learned(api, inputs, torch, dev, params, tol, steps, warmup, N):
     for name, guess, prec in (("extrapolated", 1, 0), ("learned", 2, 0),
                               ("mixed_extrapolated", 1, 1), ("mixed_learned", 2, 1)):
         st = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2, energy=0, guess=guess,
-                         precision=prec, inner_cycles=3, inner_cycles_next=2)
+                         precision=prec, inner_cycles=3, inner_cycles_next=2,
+                         inner_nu_coarse=1 if prec else 0)
         if guess == 2:
             st.load_cnn(blob)
         phi = torch.from_numpy(phi0).to(dev)
@@ -666,17 +669,17 @@ def main():
 
         # mixed precision: FP32 correction cycles inside FP64 defect correction
         # (three in the first outer iteration, which takes the defect of the
-        # guess down to FP32's floor, two in each later one)
-        out["variants"]["mixed"] = dict(
-            inner_cycles=3, inner_cycles_next=2,
-            **same_workload(precision=1, inner_cycles=3, inner_cycles_next=2))
+        # guess down to FP32's floor, two in each later one; V(1,1) on the
+        # levels below the finest)
+        mixed_opts = dict(inner_cycles=3, inner_cycles_next=2, inner_nu_coarse=1)
+        out["variants"]["mixed"] = dict(**mixed_opts, **same_workload(precision=1, **mixed_opts))
         # App. B's smoother under-relaxed (omega = 0.9): same discrete solution,
         # fewer V-cycles per step; alone and with mixed precision
         out["variants"]["relaxed_smoother"] = dict(
             omega=RELAXED_OMEGA, **same_workload(omega=RELAXED_OMEGA))
+        relaxed_mixed_opts = dict(omega=RELAXED_OMEGA, inner_cycles=2, inner_nu_coarse=1)
         out["variants"]["relaxed_mixed"] = dict(
-            omega=RELAXED_OMEGA, inner_cycles=2,
-            **same_workload(omega=RELAXED_OMEGA, precision=1, inner_cycles=2))
+            **relaxed_mixed_opts, **same_workload(precision=1, **relaxed_mixed_opts))
     # The same workload with Sec. 4.5's boundary conditions: periodic in x,
     # homogeneous Neumann in y (App. A), FP64, energies as above.
     if args.variants and args.bc_steps > 0:

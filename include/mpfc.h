@@ -90,6 +90,14 @@ typedef struct {
  * outer iteration after the step's first, in [0, 16] (0: inner_cycles).  The
  * first outer iteration takes the defect of the initial guess down to FP32's
  * floor; the later ones start from that floor and need fewer cycles.
+ * inner_nu_coarse: smoothing passes before and after the coarse-grid
+ * correction on the levels below the finest in those FP32 cycles, in
+ * [0, min(nu1, nu2)]; 0 keeps nu1 and nu2.  Each FP32 cycle only has to
+ * reduce the correction equation's residual, which the next FP64 defect
+ * measures, so it need not be the finest level's V(nu1, nu2): the levels
+ * below the finest are latency bound, and V(1, 1) there costs less per cycle
+ * for the same contraction.  Grids with tiled levels only (larger than
+ * 32 x 32 cells); others ignore it.
  * omega: relaxation factor of the smoother, in (0, 2): each cell moves by
  * omega times the solution of its local 3x3 system.  1 (the default) is the
  * collective Gauss-Seidel update of App. B.  App. B's update amplifies a band
@@ -115,6 +123,7 @@ typedef struct {
     double omega;
     int coarse_threshold;
     int inner_cycles_next;
+    int inner_nu_coarse;
 } mpfc_opts;
 
 /* Per-step report.  residual_history is a caller-owned host array of

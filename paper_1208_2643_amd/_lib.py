@@ -42,7 +42,7 @@ class mpfc_opts(ctypes.Structure):
                 ("energy", ctypes.c_int), ("diverge", ctypes.c_double),
                 ("inner_cycles", ctypes.c_int), ("coarse_sweeps", ctypes.c_int),
                 ("omega", ctypes.c_double), ("coarse_threshold", ctypes.c_int),
-                ("inner_cycles_next", ctypes.c_int)]
+                ("inner_cycles_next", ctypes.c_int), ("inner_nu_coarse", ctypes.c_int)]
 
 
 class mpfc_info(ctypes.Structure):

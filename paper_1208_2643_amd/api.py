@@ -54,7 +54,8 @@ def make_opts(**kw) -> L.mpfc_opts:
     guess, linearization, coarsest, energy, diverge, inner_cycles,
     coarse_sweeps, omega (smoother relaxation, 1 = App. B), coarse_threshold,
     inner_cycles_next (FP32 cycles of each outer iteration after the first;
-    0 = inner_cycles)."""
+    0 = inner_cycles), inner_nu_coarse (smoothing passes of those FP32
+    cycles on the levels below the finest; 0 = nu1, nu2)."""
     o = L.default_opts()
     for k, v in kw.items():
         if not hasattr(o, k):

@@ -386,6 +386,9 @@ TileArgs<float> dn_args32(const mpfc_ctx* C, int l) {
     T.complete_f = l > 0;
     T.nsweep = 2 * C->o.nu1;
     T.H = round_even(T.nsweep + 1);
+    // fewer passes below the finest level (the halo stays that of nu1, which
+    // covers them: inner_nu_coarse <= nu1)
+    if (l > 0 && C->o.inner_nu_coarse) T.nsweep = 2 * C->o.inner_nu_coarse;
     return T;
 }
 
@@ -407,6 +410,7 @@ TileArgs<float> up_args32(const mpfc_ctx* C, int l) {
     T.nsweep = 2 * C->o.nu2;
     T.norm = 0;
     T.H = T.nsweep;
+    if (l > 0 && C->o.inner_nu_coarse) T.nsweep = 2 * C->o.inner_nu_coarse;  // H covers it
     return T;
 }
 
@@ -424,6 +428,8 @@ CoarseArgs<float> coarse_args32(const mpfc_ctx* C) {
     A.h_top = (float)top.h;
     A.nsw1 = 2 * C->o.nu1;
     A.nsw2 = 2 * C->o.nu2;
+    if (C->Lp > 0 && C->o.inner_nu_coarse)  // every level here is below the finest
+        A.nsw1 = A.nsw2 = 2 * C->o.inner_nu_coarse;
     A.complete_top = C->Lp > 0;
     A.newton_maxit = 20;
     A.newton_tol = 1e-6f;
@@ -1062,6 +1068,8 @@ int validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {
         return fail(MPFC_EINVAL, "inner_cycles must be in [1, 16]");
     if (o->inner_cycles_next < 0 || o->inner_cycles_next > 16)
         return fail(MPFC_EINVAL, "inner_cycles_next must be in [0, 16]");
+    if (o->inner_nu_coarse < 0 || o->inner_nu_coarse > o->nu1 || o->inner_nu_coarse > o->nu2)
+        return fail(MPFC_EINVAL, "inner_nu_coarse must be in [0, min(nu1, nu2)]");
     if (o->coarse_sweeps < 1 || o->coarse_sweeps > 64)
         return fail(MPFC_EINVAL, "coarse_sweeps must be in [1, 64]");
     if (!(o->omega > 0.0 && o->omega < 2.0))
@@ -1360,6 +1368,7 @@ void mpfc_default_opts(mpfc_opts* o) {
     o->omega = 1.0;
     o->coarse_threshold = 0;
     o->inner_cycles_next = 0;
+    o->inner_nu_coarse = 0;
 }
 
 int mpfc_validate(int m, int n, const mpfc_params* p, const mpfc_opts* o) {

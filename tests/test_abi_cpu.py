@@ -44,7 +44,7 @@ def good():
 
 def test_defaults():
     o = L.default_opts()
-    assert (o.inner_cycles, o.inner_cycles_next) == (3, 0)
+    assert (o.inner_cycles, o.inner_cycles_next, o.inner_nu_coarse) == (3, 0, 0)
     assert (o.nu1, o.nu2, o.max_cycles, o.tol, o.coarsest, o.coarse_sweeps) == \
         (2, 2, 100, 1e-10, 2, 2)
     p, o = good()
@@ -98,7 +98,8 @@ def test_coarse_sweeps_range(value):
                                          ("linearization", 5), ("diverge", 0.5),
                                          ("omega", 0.0), ("omega", 2.0), ("omega", float("nan")),
                                          ("inner_cycles", 0), ("inner_cycles", 17),
-                                         ("inner_cycles_next", -1), ("inner_cycles_next", 17)])
+                                         ("inner_cycles_next", -1), ("inner_cycles_next", 17),
+                                         ("inner_nu_coarse", -1), ("inner_nu_coarse", 3)])
 def test_invalid_opts_rejected(field, value):
     p, o = good()
     setattr(o, field, value)
@@ -259,3 +260,14 @@ def test_coarse_threshold_only_for_power_of_two_2d_single_grids():
     b = ctypes.c_void_p()
     assert lib.mpfc_batch_create(ctypes.byref(b), 1, d, ctypes.byref(o), None) == L.MPFC_EINVAL
     assert not b.value
+
+
+def test_inner_nu_coarse_bounded_by_the_finest_passes():
+    """The FP32 inner cycles may smooth less below the finest level, never
+    more (the tiles' halo is sized for nu1, nu2)."""
+    p, o = good()
+    lib = L.load()
+    o.inner_nu_coarse = 1
+    assert lib.mpfc_validate(64, 64, ctypes.byref(p), ctypes.byref(o)) == 0
+    o.nu2 = 0
+    assert lib.mpfc_validate(64, 64, ctypes.byref(p), ctypes.byref(o)) == L.MPFC_EINVAL

@@ -72,20 +72,22 @@ def run_single(m, n, p, phi0, steps, **opts):
                                                       (1, L.MPFC_FP64, L.MPFC_NEWTON, 0),
                                                       (2, L.MPFC_MIXED, L.MPFC_NEWTON, 0),
                                                       (1, L.MPFC_MIXED, L.MPFC_PICARD, 0),
-                                                      (2, L.MPFC_MIXED, L.MPFC_NEWTON, 1)])
+                                                      (2, L.MPFC_MIXED, L.MPFC_NEWTON, 1),
+                                                      (2, L.MPFC_MIXED, L.MPFC_NEWTON, -1)])
 def test_batch_matches_single_contexts(scheme, precision, lin, nxt):
     """Each member of a batch steps as its own context does: same iterates,
     same cycle counts (nxt: FP32 cycles of the outer iterations after the
-    first, 0 = as many as the first)."""
+    first, 0 = as many as the first; -1: two, with V(1,1) below the finest
+    level in the FP32 cycles)."""
     sims = members(scheme)
     steps = 3
-    b = api.Batch([(m, n, p) for m, n, p, _ in sims], precision=precision, linearization=lin,
-                  inner_cycles_next=nxt)
+    kw = dict(inner_cycles_next=2, inner_nu_coarse=1) if nxt < 0 else dict(inner_cycles_next=nxt)
+    b = api.Batch([(m, n, p) for m, n, p, _ in sims], precision=precision, linearization=lin, **kw)
     phi_b, _, psi_b, infos = api.run_batch(b, [dev(x) for *_, x in sims], steps)
     b.close()
     for k, (m, n, p, phi0) in enumerate(sims):
         phi_s, psi_s, cyc_s = run_single(m, n, p, phi0, steps, precision=precision,
-                                         linearization=lin, inner_cycles_next=nxt)
+                                         linearization=lin, **kw)
         assert rel_l2(host(phi_b[k]), phi_s) <= 1e-12, k
         assert rel_l2(host(psi_b[k]), psi_s) <= 1e-10, k
         assert [infos[t][k].n_cycles for t in range(steps)] == cyc_s, k

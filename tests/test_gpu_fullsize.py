@@ -97,24 +97,28 @@ def test_1024_twenty_steps_fp64():
 
 
 @pytest.mark.timeout(300)
-@pytest.mark.parametrize("nxt", [0, 2])
-def test_1024_twenty_steps_mixed(nxt):
+@pytest.mark.parametrize("nxt,nuc", [(0, 0), (2, 1)])
+def test_1024_twenty_steps_mixed(nxt, nuc):
     """Mixed precision on the same 20 steps: FP32 smoothing, restriction and
     prolongation inside FP64 defect correction, same 1e-10 FP64 residual;
     three FP32 cycles per outer iteration, or (the benchmark's setting) three
-    in the first and two in each later one."""
+    in the first and two in each later one with V(1,1) below the finest
+    level."""
     curve = run_and_compare(1024, 2, 20, dict(phi=1e-9, psi=1e-7), precision=L.MPFC_MIXED,
-                            inner_cycles=3, inner_cycles_next=nxt)
+                            inner_cycles=3, inner_cycles_next=nxt, inner_nu_coarse=nuc)
     assert all(c[1] >= 3 for c in curve)
 
 
 @pytest.mark.timeout(300)
-@pytest.mark.parametrize("precision,inner,nxt", [(L.MPFC_FP64, 3, 0), (L.MPFC_MIXED, 4, 0),
-                                               (L.MPFC_MIXED, 4, 3)])
-def test_2048_five_steps(precision, inner, nxt):
+@pytest.mark.parametrize("precision,inner,nxt,nuc", [(L.MPFC_FP64, 3, 0, 0),
+                                                   (L.MPFC_MIXED, 4, 0, 0),
+                                                   (L.MPFC_MIXED, 4, 3, 1)])
+def test_2048_five_steps(precision, inner, nxt, nuc):
     """The 2048^2 workload (crystallites, seed 3) over 5 consecutive steps, in
     FP64 and with mixed precision (4 inner FP32 cycles per outer iteration, or
-    the benchmark's 4 in the first and 3 in each later one)."""
+    the benchmark's 4 in the first and 3 in each later one with V(1,1) below
+    the finest level)."""
     mixed = precision == L.MPFC_MIXED
     run_and_compare(2048, 3, 5, dict(phi=1e-9 if mixed else 1e-10, psi=1e-7 if mixed else 1e-8),
-                    precision=precision, inner_cycles=inner, inner_cycles_next=nxt)
+                    precision=precision, inner_cycles=inner, inner_cycles_next=nxt,
+                    inner_nu_coarse=nuc)

@@ -338,16 +338,18 @@ def test_mixed_precision_matches_fp64_oracle(scheme):
         assert abs(i.energy_mod - r.energies[2]) <= 1e-9 * abs(r.energies[2])
 
 
-@pytest.mark.parametrize("inner,nxt", [(3, 1), (2, 4)])
-def test_mixed_precision_later_outer_cycle_count(inner, nxt):
+@pytest.mark.parametrize("inner,nxt,nuc", [(3, 1, 0), (2, 4, 0), (3, 2, 1)])
+def test_mixed_precision_later_outer_cycle_count(inner, nxt, nuc):
     """inner_cycles FP32 cycles in a step's first outer iteration and
-    inner_cycles_next in each later one: same FP64 fixed point (oracle, 1e-9),
-    and the reported FP32 cycle count is inner + (outer - 1) nxt."""
+    inner_cycles_next in each later one (nuc: smoothing passes of those
+    cycles below the finest level, 0 = nu1, nu2): same FP64 fixed point
+    (oracle, 1e-9), and the reported FP32 cycle count is inner + (outer - 1)
+    nxt."""
     N = 128
     po, pg = both(2, h=math.pi / 4, dt=0.05)
     phi0 = I.crystallites(N, N, math.pi / 4, radius_cells=N / 8, seed=3)
     st = api.Stepper(N, N, pg, tol=1e-10, precision=L.MPFC_MIXED, max_cycles=60,
-                     inner_cycles=inner, inner_cycles_next=nxt)
+                     inner_cycles=inner, inner_cycles_next=nxt, inner_nu_coarse=nuc)
     phi_g, _, _, infos = api.run(st, dev(phi0), 5)
     st.close()
     phi_o, _, _, _ = O.run(po, phi0, 5, tol=1e-12, max_cycles=300)
