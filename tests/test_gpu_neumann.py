@@ -216,11 +216,14 @@ def test_neumann_equals_mirrored_periodic_gpu(bc):
     assert k * ia.mass == pytest.approx(ib.mass, rel=1e-12)
 
 
-@pytest.mark.parametrize("bc", [2, 3])
-def test_mixed_precision_matches_fp64_oracle(bc):
+@pytest.mark.parametrize("bc,nuc", [(2, 0), (3, 0), (2, 1), (3, 1)])
+def test_mixed_precision_matches_fp64_oracle(bc, nuc):
+    """Mixed precision with Neumann axes (nuc: smoothing passes of the FP32
+    cycles below the finest level, 0 = nu1, nu2) reaches the FP64 fixed point."""
     po, pg = both(2, bc, h=math.pi / 4, dt=0.05)
     phi0 = I.crystallites(128, 128, math.pi / 4, radius_cells=14, seed=19)
-    st = api.Stepper(128, 128, pg, tol=1e-10, precision=L.MPFC_MIXED, energy=0)
+    st = api.Stepper(128, 128, pg, tol=1e-10, precision=L.MPFC_MIXED, energy=0,
+                     inner_cycles_next=2 if nuc else 0, inner_nu_coarse=nuc)
     phi_g, _, _, infos = api.run(st, dev(phi0), 4)
     phi_o, _, _, res = O.run(po, phi0, 4, tol=1e-12, max_cycles=300, energy=False)
     assert all(i.status == 0 for i in infos)

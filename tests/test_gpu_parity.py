@@ -359,6 +359,22 @@ def test_mixed_precision_later_outer_cycle_count(inner, nxt, nuc):
     assert rel_l2(host(phi_g), phi_o) <= 1e-9
 
 
+def test_inner_nu_coarse_ignored_without_tiled_levels():
+    """A 32 x 32 grid has no tiled level (the persistent kernel takes the
+    finest level too), so the FP32 cycles keep nu1, nu2 there: the steps equal
+    those without the option bit for bit."""
+    _, pg = both(2, h=math.pi / 4, dt=0.05)
+    phi0 = I.noise(32, 32, mean=0.07, amp=0.05, seed=23)
+    out = []
+    for nuc in (0, 1):
+        st = api.Stepper(32, 32, pg, tol=1e-10, precision=L.MPFC_MIXED, energy=0,
+                         inner_nu_coarse=nuc)
+        phi, _, _, infos = api.run(st, dev(phi0), 3)
+        st.close()
+        out.append((host(phi), [i.n_cycles for i in infos]))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
 def test_mixed_precision_full_size_1024():
     """One mixed-precision step of the 1024^2 workload against the oracle."""
     N = 1024
