@@ -548,7 +548,10 @@ void defect(mpfc_ctx* C, int from, int add, hipStream_t s) {
     const int to = from ^ 1;
     const int max_norms = C->o.max_cycles + 1;
     auto kern = C->p.scheme == 1 ? k_defect<1, NT> : k_defect<2, NT>;
-    const unsigned nb = red_blocks(total);
+    // one thread per cell (the partial sums hold one value per 256 cells):
+    // a grid-stride loop of a few cells per thread waits on each cell's loads
+    // in turn
+    const unsigned nb = (unsigned)((total + NT - 1) / NT);
     hipLaunchKernelGGL(kern, dim3(nb), dim3(NT), 0, s, F, level_op(C, F0), F0.g, C->st, C->part,
                        FF.e[0][0], FF.e[0][1], FF.e[0][2], add, F0.u[to][0], F0.u[to][1],
                        F0.u[to][2], FF.f[0], FF.f[1], FF.f[2], FF.pb);
