@@ -181,7 +181,8 @@ def cpu_baseline(params, phi0, tol, budget_s):
 def bench_big(api, inputs, torch, dev, params, tol, steps, warmup, N=2048, inner=4, nxt=3, nuc=1):
     phi0 = inputs.crystallites(N, N, params["h"], seed=3)
     res = {"workload": f"{N}x{N}, second-order scheme, crystallites seed 3, {steps} steps, "
-                       "V(2,2) to 1e-10, energies off", "inner_cycles": inner,
+                       "V(2,2) to 1e-10, energies off; each leg run twice in fresh contexts, "
+                       "the faster run reported", "inner_cycles": inner,
            "inner_cycles_next": nxt, "inner_nu_coarse": nuc}
     finals = {}
     # the oracle's trajectory of this workload (FP64, solved to 1e-12 per step),
@@ -193,9 +194,13 @@ def bench_big(api, inputs, torch, dev, params, tol, steps, warmup, N=2048, inner
         with np.load(gpath, allow_pickle=False) as z:
             golden = {"idx": z["idx"], "phi": z["phi"], "steps": int(z["phi"].shape[0])}
         gidx = torch.from_numpy(golden["idx"]).to(dev)
-    for name, kw in (("fp64", dict(precision=0)),
-                     ("mixed", dict(precision=1, inner_cycles=inner, inner_cycles_next=nxt,
-                                    inner_nu_coarse=nuc))):
+    # each leg twice, interleaved, in fresh contexts; the faster run of each
+    # is reported (a context now and then runs slower with identical cycle
+    # counts, which would otherwise decide the ratio)
+    legs = (("fp64", dict(precision=0)),
+            ("mixed", dict(precision=1, inner_cycles=inner, inner_cycles_next=nxt,
+                           inner_nu_coarse=nuc)))
+    for rep, (name, kw) in [(r, leg) for r in range(2) for leg in legs]:
         st = api.Stepper(N, N, api.Params(**params), tol=tol, nu1=2, nu2=2, energy=0, **kw)
         phi = torch.from_numpy(phi0).to(dev)
         prev = phi.clone()
@@ -220,7 +225,9 @@ def bench_big(api, inputs, torch, dev, params, tol, steps, warmup, N=2048, inner
                 sample = phi.view(-1)[gidx].clone()  # gathered on the stream, read after timing
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        res[name] = {"time_steps_per_s": steps / el, "vcycles_per_step": cycles / steps}
+        runs = res.get(name, {}).get("runs_time_steps_per_s", []) + [steps / el]
+        res[name] = {"time_steps_per_s": max(runs), "runs_time_steps_per_s": runs,
+                     "vcycles_per_step": cycles / steps}
         if name == "mixed":
             res[name]["outer_per_step"] = outer / steps
         if sample is not None:
