@@ -438,17 +438,25 @@ __global__ void k_cnn_sample_io(CnnSample* smp, const StepIO* __restrict__ io, d
     if (threadIdx.x == 0) smp[0] = CnnSample{io->phi_nm1, io->phi_n, io->psi, nullptr, out};
 }
 
-// Per-sample scale factors from the sums of (phi^n - phi^{n-1})^2.
-__global__ void k_cnn_scales(const double* __restrict__ sums, int samples, double npix,
-                             double out_scale, double* sc) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= samples) return;
-    const double sig = sqrt(sums[s] / npix);
-    const double so = out_scale * sig;
-    sc[4 * s + 0] = sig > 0.0 ? 1.0 / sig : 0.0;
-    sc[4 * s + 1] = so;
-    sc[4 * s + 2] = so > 0.0 ? 1.0 / so : 0.0;
-    sc[4 * s + 3] = 0.0;
+// Per-sample scale factors from the sums of (phi^n - phi^{n-1})^2: one
+// workgroup per sample s adds the per-block shares part[b * samples + s] over
+// the nblk blocks in a fixed order, then sigma1 = rms of the difference.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_cnn_scales_sum(const double* __restrict__ part, int nblk,
+                                                       double npix, double out_scale, double* sc) {
+    __shared__ double red[NT / 64];
+    const int s = blockIdx.x, samples = gridDim.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += NT) acc += part[(size_t)b * samples + s];
+    const double tot = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) {
+        const double sig = sqrt(tot / npix);
+        const double so = out_scale * sig;
+        sc[4 * s + 0] = sig > 0.0 ? 1.0 / sig : 0.0;
+        sc[4 * s + 1] = so;
+        sc[4 * s + 2] = so > 0.0 ? 1.0 / so : 0.0;
+        sc[4 * s + 3] = 0.0;
+    }
 }
 
 // part[blk * samples + s] = block's share of sum (phi^n - phi^{n-1})^2 of sample s.
@@ -777,27 +785,90 @@ __global__ void __launch_bounds__(256) k_cnn_prepare(const float* __restrict__ t
     if (r < 9 * CNN_CH) F.w4[r] = bf16_val(bf16_bits(th[CNN_W4 + r]));
 }
 
-// Candidate choice of the step's initial guess: the learned guess (copy 0) is
-// kept when its FP64 residual is the smaller one; otherwise the extrapolated
-// guess (copy 1) is copied over it.
-// counts[0] counts the steps that used it, counts[1] the fallbacks; chosen[0]
-// receives the squared residual norm of the guess kept.
+// Candidates of the step's initial guess, the learned one in copy 0 and the
+// extrapolated one in copy 1: per-block sums of the first residual component
+// squared of both in one pass (part[b] for copy 0, part[gridDim.x + b] for
+// copy 1; the completion makes the other components vanish).
+template <int NT>
+__global__ void __launch_bounds__(NT) k_cnn_resnorm2(Fields<double> A, Fields<double> B,
+                                                     LevelOp<double> op, Grid g, double* part) {
+    __shared__ double red[2][NT / 64];  // one per sum: thread 0 reads them after the barrier
+    double a2 = 0.0, b2 = 0.0;
+    const size_t total = (size_t)g.m * g.n;
+    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
+        int i, j;
+        cell_of(q, g, i, j);
+        const double ra = A.f1[q] - (A.phi[q] - op.c * (nsum(A.mu, i, j, g) - 4.0 * A.mu[q]) * op.ih2);
+        const double rb = B.f1[q] - (B.phi[q] - op.c * (nsum(B.mu, i, j, g) - 4.0 * B.mu[q]) * op.ih2);
+        a2 += ra * ra;
+        b2 += rb * rb;
+    }
+    const double sa = block_sum<NT>(a2, red[0]);
+    const double sb = block_sum<NT>(b2, red[1]);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = sa;
+        part[gridDim.x + blockIdx.x] = sb;
+    }
+}
+
+// The choice, one workgroup: r2[0], r2[1] = the two candidates' sums (fixed
+// order); the learned guess is used when its sum is the smaller one (a NaN
+// network falls back); counts[0] counts the steps that used it, counts[1]
+// the fallbacks; part[0] receives the kept guess's sum (the step's first norm).
+template <int NT>
+__global__ void __launch_bounds__(NT) k_cnn_decide(double* part, int nblk, double* r2,
+                                                   unsigned long long* counts) {
+    __shared__ double red[2][NT / 64];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += NT) {
+        a += part[k];
+        b += part[nblk + k];
+    }
+    const double sa = block_sum<NT>(a, red[0]);
+    const double sb = block_sum<NT>(b, red[1]);
+    if (threadIdx.x == 0) {
+        const bool use = sa < sb;
+        r2[0] = sa;
+        r2[1] = sb;
+        counts[use ? 0 : 1] += 1ull;
+        part[0] = use ? sa : sb;
+    }
+}
+
+// Fallback: the extrapolated guess (copy 1) over the learned one (copy 0)
+// when k_cnn_decide did not keep the learned one.
 __global__ void __launch_bounds__(256) k_cnn_pick(const double* __restrict__ r2, size_t total,
                                                   double* u0a, double* u0b, double* u0c,
                                                   const double* __restrict__ u1a,
                                                   const double* __restrict__ u1b,
-                                                  const double* __restrict__ u1c,
-                                                  unsigned long long* counts, double* chosen) {
-    const bool use = r2[0] < r2[1];
+                                                  const double* __restrict__ u1c) {
     const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (q == 0) {
-        counts[use ? 0 : 1] += 1ull;
-        chosen[0] = use ? r2[0] : r2[1];
-    }
-    if (use || q >= total) return;
+    if (r2[0] < r2[1] || q >= total) return;
     u0a[q] = u1a[q];
     u0b[q] = u1b[q];
     u0c[q] = u1c[q];
+}
+
+// Completion of the learned candidate's mu, with the correction's mean (sum
+// csum[0] over the grid, times inv_npix) taken off its phi first, so the guess
+// keeps the extrapolation's mass.  Each thread shifts its own cell only (kappa
+// was formed before from the unshifted phi, whose Laplacian is the same).
+template <int SCHEME>
+__global__ void __launch_bounds__(256) k_cnn_complete_mu(Grid g, double ih2, double al,
+                                                         double* phi,
+                                                         const double* __restrict__ phik,
+                                                         const double* __restrict__ ka,
+                                                         const double* __restrict__ S2, double* mu,
+                                                         const double* __restrict__ pin,
+                                                         const double* __restrict__ csum,
+                                                         double inv_npix) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.m || j >= g.n) return;
+    const size_t q = at(i, j, g);
+    const double x = phi[q] - csum[0] * inv_npix;
+    phi[q] = x;
+    complete_mu_at<SCHEME>(g, ih2, al, x, phik, ka, S2, mu, i, j, pin);
 }
 
 }  // namespace mpfc

@@ -146,14 +146,15 @@ struct CnnNet {
     }
 
     // Scales, three hidden layers and the output layer.  Inference writes the
-    // mean-corrected guess into every sample's `out`; training writes d loss /
-    // d delta and leaves the per-sample sums of err^2 in `sums`.
-    void forward(hipStream_t s, bool training) {
+    // guess into every sample's `out` and the sum of its correction into
+    // `sums`; with `shift` the correction's mean is taken off there (the step
+    // does that in the candidate's completion instead).  Training writes
+    // d loss / d delta and leaves the per-sample sums of err^2 in `sums`.
+    void forward(hipStream_t s, bool training, bool shift = true) {
         const dim3 tg(m / CNN_TILE, n / CNN_TILE, B), blk(256);
         hipLaunchKernelGGL((k_cnn_sigma<256>), dim3(nblk_sig, B), blk, 0, s, d_smp, NP, part);
-        hipLaunchKernelGGL((k_partials_sum<256>), dim3(1), blk, 0, s, part, nblk_sig, B, sums);
-        hipLaunchKernelGGL(k_cnn_scales, dim3((B + 63) / 64), dim3(64), 0, s, sums, B,
-                           (double)NP, out_scale, sc);
+        hipLaunchKernelGGL((k_cnn_scales_sum<256>), dim3(B), blk, 0, s, part, nblk_sig, (double)NP,
+                           out_scale, sc);
         CnnConvArgs c{};
         c.m = m; c.n = n; c.smp = d_smp; c.sc = sc; c.in_scale = in_scale; c.dt = dt;
         c.wfrag = fr.f1; c.bias = theta + CNN_B1; c.out = a[1]; c.zout = training ? z[1] : nullptr;
@@ -174,8 +175,9 @@ struct CnnNet {
         } else {
             hipLaunchKernelGGL((k_cnn_out<false>), tg, blk, 0, s, o);
             hipLaunchKernelGGL((k_partials_sum<256>), dim3(1), blk, 0, s, part, nblk_out, B, sums);
-            hipLaunchKernelGGL(k_cnn_shift, dim3((unsigned)((NP + 255) / 256), B), blk, 0, s, d_smp,
-                               NP, sums);
+            if (shift)
+                hipLaunchKernelGGL(k_cnn_shift, dim3((unsigned)((NP + 255) / 256), B), blk, 0, s,
+                                   d_smp, NP, sums);
         }
     }
 
@@ -244,49 +246,46 @@ int cnn_candidate(mpfc_ctx* C, const StepIO* io, hipStream_t s) {
     const double ih2 = 1.0 / (F0.h * F0.h);
     CnnNet& N = *C->cnn;
     hipLaunchKernelGGL(k_cnn_sample_io, dim3(1), dim3(64), 0, s, N.d_smp, io, F0.u[0][0]);
-    N.forward(s, false);
+    N.forward(s, false, false);  // the correction's mean is taken off in the mu pass
     const double e = C->p.scheme == 1 ? 1.0 : 0.5;
     const double al = C->p.scheme == 1 ? C->alpha : 0.5 * C->alpha;
+    const double inv_npix = 1.0 / (double)((size_t)C->m * C->n);
     hipLaunchKernelGGL(k_complete_kappa, grid2(C->m, C->n), B2, 0, s, g0, ih2, e, F0.u[0][0],
                        F0.f[2], F0.u[0][2]);
     if (C->p.scheme == 1)
-        hipLaunchKernelGGL((k_complete_mu<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, F0.u[0][0],
-                           C->phik, F0.u[0][2], F0.f[1], F0.u[0][1], (const double*)nullptr);
+        hipLaunchKernelGGL((k_cnn_complete_mu<1>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al,
+                           F0.u[0][0], C->phik, F0.u[0][2], F0.f[1], F0.u[0][1],
+                           (const double*)nullptr, (const double*)N.sums, inv_npix);
     else
-        hipLaunchKernelGGL((k_complete_mu<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al, F0.u[0][0],
-                           C->phik, F0.u[0][2], F0.f[1], F0.u[0][1],
-                           (const double*)(C->pinned ? F0.pin : nullptr));
+        hipLaunchKernelGGL((k_cnn_complete_mu<2>), grid2(C->m, C->n), B2, 0, s, g0, ih2, al,
+                           F0.u[0][0], C->phik, F0.u[0][2], F0.f[1], F0.u[0][1],
+                           (const double*)(C->pinned ? F0.pin : nullptr), (const double*)N.sums,
+                           inv_npix);
     return MPFC_OK;
 }
 
-// Sum of squared residuals of the completed guess in finest copy `k` into
-// out (no stop test): N^(2) = S^(2) and N^(3) = S^(3) hold by construction, so
-// only the first component is summed, as for the step's first norm without
-// the learned guess.
-void residual_sq(mpfc_ctx* C, int k, double* out, hipStream_t s) {
-    Level& F0 = C->L[0];
-    Fields<double> F;
-    F.phi = F0.u[k][0]; F.mu = F0.u[k][1]; F.ka = F0.u[k][2];
-    F.f1 = F0.f[0]; F.f2 = F0.f[1]; F.f3 = F0.f[2];
-    F.phik = C->p.scheme == 2 ? C->phik : nullptr;
-    F.base = nullptr;
-    F.pin = C->pinned ? F0.pin : nullptr;
-    const unsigned nb = red_blocks((size_t)C->m * C->n);
-    hipLaunchKernelGGL((k_resnorm_guess<NT>), dim3(nb), dim3(NT), 0, s, F, level_op(C, F0), F0.g,
-                       C->part);
-    hipLaunchKernelGGL((k_partials_sum<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)nb, 1, out);
-}
-
-// Candidate choice: the learned guess (copy 0) is kept when its residual is
-// the smaller one, else the extrapolated guess (copy 1) is copied over it.
+// Candidate choice: the first residual component of both completed
+// candidates (the other two vanish by construction) in one pass, the choice
+// in one workgroup, and the extrapolated guess (copy 1) copied over the
+// learned one (copy 0) only when it has the smaller residual.
 void cnn_choose(mpfc_ctx* C, hipStream_t s) {
     Level& F0 = C->L[0];
     const size_t total = (size_t)C->m * C->n;
-    residual_sq(C, 0, C->cnn_r2, s);
-    residual_sq(C, 1, C->cnn_r2 + 1, s);
+    Fields<double> F[2];
+    for (int k = 0; k < 2; ++k) {
+        F[k].phi = F0.u[k][0]; F[k].mu = F0.u[k][1]; F[k].ka = F0.u[k][2];
+        F[k].f1 = F0.f[0]; F[k].f2 = F0.f[1]; F[k].f3 = F0.f[2];
+        F[k].phik = C->p.scheme == 2 ? C->phik : nullptr;
+        F[k].base = nullptr;
+        F[k].pin = C->pinned ? F0.pin : nullptr;
+    }
+    const unsigned nb = red_blocks(total);
+    hipLaunchKernelGGL((k_cnn_resnorm2<NT>), dim3(nb), dim3(NT), 0, s, F[0], F[1],
+                       level_op(C, F0), F0.g, C->part);
+    hipLaunchKernelGGL((k_cnn_decide<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)nb, C->cnn_r2,
+                       C->cnn_counts);
     hipLaunchKernelGGL(k_cnn_pick, grid1(total), dim3(256), 0, s, C->cnn_r2, total, F0.u[0][0],
-                       F0.u[0][1], F0.u[0][2], F0.u[1][0], F0.u[1][1], F0.u[1][2], C->cnn_counts,
-                       C->part);
+                       F0.u[0][1], F0.u[0][2], F0.u[1][0], F0.u[1][1], F0.u[1][2]);
 }
 
 }  // namespace

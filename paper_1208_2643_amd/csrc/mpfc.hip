@@ -1211,7 +1211,6 @@ int compute_energies(mpfc_ctx* C, const double* phi, const double* phiprev, cons
 }
 
 int cnn_candidate(mpfc_ctx* C, const StepIO* io, hipStream_t s);
-void residual_sq(mpfc_ctx* C, int k, double* out, hipStream_t s);
 void cnn_choose(mpfc_ctx* C, hipStream_t s);
 
 // ---- one step, split for reuse by the batched path -------------------------------

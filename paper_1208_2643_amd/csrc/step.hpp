@@ -277,7 +277,21 @@ __global__ void __launch_bounds__(256) k_complete_kappa(Grid g, double ih2, doub
     complete_kappa_cell(g, ih2, e, phi, S3, ka, i, j);
 }
 
-// ... and mu = S2 + g(phi) + al phi + Lap kappa (so N^(2) = S^(2)).
+// ... and mu = S2 + g(phi) + al phi + Lap kappa (so N^(2) = S^(2)); the
+// cell's phi is x.
+template <int SCHEME>
+__device__ __forceinline__ void complete_mu_at(const Grid& g, double ih2, double al, double x,
+                                               const double* __restrict__ phik,
+                                               const double* __restrict__ ka,
+                                               const double* __restrict__ S2, double* mu, int i,
+                                               int j, const double* __restrict__ pin) {
+    const size_t q = at(i, j, g);
+    const double xk = SCHEME == 2 ? phik[q] : 0.0;
+    const double alq = al + (pin ? pin[q] : 0.0);
+    mu[q] = S2[q] + nl_value<double, SCHEME, false>(x, 0.0, xk) + alq * x +
+            (nsum(ka, i, j, g) - 4.0 * ka[q]) * ih2;
+}
+
 template <int SCHEME>
 __device__ __forceinline__ void complete_mu_cell(const Grid& g, double ih2, double al,
                                                  const double* __restrict__ phi,
@@ -285,12 +299,7 @@ __device__ __forceinline__ void complete_mu_cell(const Grid& g, double ih2, doub
                                                  const double* __restrict__ ka,
                                                  const double* __restrict__ S2, double* mu, int i,
                                                  int j, const double* __restrict__ pin = nullptr) {
-    const size_t q = at(i, j, g);
-    const double x = phi[q];
-    const double xk = SCHEME == 2 ? phik[q] : 0.0;
-    const double alq = al + (pin ? pin[q] : 0.0);
-    mu[q] = S2[q] + nl_value<double, SCHEME, false>(x, 0.0, xk) + alq * x +
-            (nsum(ka, i, j, g) - 4.0 * ka[q]) * ih2;
+    complete_mu_at<SCHEME>(g, ih2, al, phi[at(i, j, g)], phik, ka, S2, mu, i, j, pin);
 }
 
 template <int SCHEME>
