@@ -284,13 +284,17 @@ def test_transposition_equivariance(scheme, precision, N):
         assert abs(a - b) <= 1e-10 * max(1.0, abs(a)), key
 
 
-@pytest.mark.parametrize("dims,scheme,precision", [
-    (2, 1, L.MPFC_FP64), (2, 2, L.MPFC_FP64), (2, 2, L.MPFC_MIXED), (3, 2, L.MPFC_FP64)])
-def test_graph_replay_equals_eager_launches(dims, scheme, precision):
+@pytest.mark.parametrize("dims,scheme,precision,sched", [
+    (2, 1, L.MPFC_FP64, None), (2, 2, L.MPFC_FP64, None), (2, 2, L.MPFC_MIXED, None),
+    (2, 2, L.MPFC_MIXED, (3, 1, 1)), (3, 2, L.MPFC_FP64, None)])
+def test_graph_replay_equals_eager_launches(dims, scheme, precision, sched):
     """Steps replay captured HIP graphs; with launch timing switched on the
     same kernels are launched one by one.  Six steps of each, with the
     program's own eager work and a synchronisation between the steps, give
-    the same states and energies (every replay after the first is checked)."""
+    the same states and energies (every replay after the first is checked).
+    sched: FP32 cycles of a step's first and later outer iterations and the
+    passes below the finest level (runs holding a step's first outer
+    iteration are graphs of their own)."""
     _, pg = both(scheme, h=math.pi / 4, dt=0.05)
     if dims == 2:
         phi0 = I.crystallites(256, 256, math.pi / 4, radius_cells=20, seed=2)
@@ -304,7 +308,9 @@ def test_graph_replay_equals_eager_launches(dims, scheme, precision):
     runs = []
     for eager in (False, True):
         if dims == 2:
-            st = api.Stepper(256, 256, pg, tol=1e-10, precision=precision)
+            kw = {} if sched is None else dict(inner_cycles=sched[0], inner_cycles_next=sched[1],
+                                               inner_nu_coarse=sched[2])
+            st = api.Stepper(256, 256, pg, tol=1e-10, precision=precision, **kw)
         else:
             st = api.Stepper3(32, 32, 32, pg, tol=1e-10, coarse_sweeps=2)
         if eager:
