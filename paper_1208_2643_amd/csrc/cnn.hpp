@@ -377,59 +377,90 @@ struct CnnOutArgs {
     const uint16_t* in;        // a3 (NHWC)
     const CnnSample* smp;
     const double* sc;
-    const float* w4;           // [tap][ci], BF16-rounded values
+    const uint16_t* w4frag;    // output-layer weights as K = 32 fragments (k_cnn_prepare_out32)
     const float* b4;
     float* gd;                 // training: d loss / d delta
     double* part;              // per block and sample: sum of the correction / of err^2
     double gscale;             // training: 2 / (pixels of the batch)
 };
 
-// Output layer (32 -> 1) on a 16 x 16 tile, one thread per pixel.
+// Output layer (32 -> 1) on a 16 x 16 tile.
 // Inference: guess = 2 phi^n - phi^{n-1} + sigma_out * delta into smp.out and
 // the block's sum of the correction.  Training: err = delta - target,
 // gd = gscale * err and the block's sum of err^2.  part[blk * samples + s].
+// It runs on the K = 32 instruction: M = 16 rows of which only row 0 (the one
+// output channel) has weights, N = 16 pixels of a tile row, K = the 32
+// channels of a tap; the products of BF16 values are exact in FP32, so only
+// the order of the FP32 additions differs from a sum over taps and channels.
+// The halo tile is read as in k_cnn_conv32; lanes 0-15 of each wave hold the
+// row's 16 outputs (D[0][n]).
 template <bool TRAIN>
-__global__ void __launch_bounds__(256) k_cnn_out(CnnOutArgs A) {
-    __shared__ __align__(16) uint16_t lds[CNN_HALO * CNN_HALO * CNN_PX];
-    __shared__ float w4s[9 * CNN_CH];
+__global__ void __launch_bounds__(256) k_cnn_out32(CnnOutArgs A) {
+    __shared__ __align__(16) uint16_t lds[CNN_HALO * CNN_HALO * CNN_PX32];
     __shared__ double red[4];
     const int m = A.m, n = A.n;
     const size_t NP = (size_t)m * n;
     const int s = blockIdx.z;
+    const size_t base = (size_t)s * NP;
     const int x0 = blockIdx.x * CNN_TILE, y0 = blockIdx.y * CNN_TILE;
-    for (int k = threadIdx.x; k < 9 * CNN_CH; k += 256) w4s[k] = A.w4[k];
-    cnn_load_halo(A.in, (size_t)s * NP, x0, y0, m, n, lds);
-    __syncthreads();
-    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-    float d = A.b4[0];
-    for (int tap = 0; tap < 9; ++tap) {
-        const int ky = tap / 3, kx = tap - 3 * ky;
-        const uint16_t* a = lds + ((ty + ky) * CNN_HALO + tx + kx) * CNN_PX;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int g = lane >> 4, c16 = lane & 15;
+    cnn_v8b wf[9];
 #pragma unroll
-        for (int c = 0; c < CNN_CH; c += 4) {
-            const uint2 v = *(const uint2*)(a + c);
-            d += w4s[tap * CNN_CH + c] * bf16_val((uint16_t)(v.x & 0xffff)) +
-                 w4s[tap * CNN_CH + c + 1] * bf16_val((uint16_t)(v.x >> 16)) +
-                 w4s[tap * CNN_CH + c + 2] * bf16_val((uint16_t)(v.y & 0xffff)) +
-                 w4s[tap * CNN_CH + c + 3] * bf16_val((uint16_t)(v.y >> 16));
+    for (int f = 0; f < 9; ++f)
+        wf[f] = __builtin_bit_cast(cnn_v8b, *(const uint4*)(A.w4frag + ((size_t)f * 64 + lane) * 8));
+    {
+        uint4 v[CNN_HREG];
+#pragma unroll
+        for (int j = 0; j < CNN_HREG; ++j) {
+            const int c = min(t + 256 * j, CNN_HCH - 1);
+            const int pi = c >> 2, part = c & 3;
+            const int ty = pi / CNN_HALO, tx = pi - ty * CNN_HALO;
+            const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (m - 1);
+            v[j] = *(const uint4*)(A.in + (base + (size_t)gy * m + gx) * CNN_CH + part * 8);
+        }
+#pragma unroll
+        for (int j = 0; j < CNN_HREG; ++j) {
+            const int c = t + 256 * j;
+            if (c < CNN_HCH) *(uint4*)(lds + (c >> 2) * CNN_PX32 + (c & 3) * 8) = v[j];
+        }
+    }
+    __syncthreads();
+    cnn_v4f acc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = cnn_v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const cnn_v8b b = __builtin_bit_cast(
+                cnn_v8b,
+                *(const uint4*)(lds + ((wave * 4 + r + ky) * CNN_HALO + c16 + kx) * CNN_PX32 + 8 * g));
+            acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[tap], b, acc[r], 0, 0, 0);
         }
     }
     const CnnSample S = A.smp[s];
-    const size_t q = (size_t)(y0 + ty) * m + x0 + tx;
-    double acc;
-    if constexpr (!TRAIN) {
-        const double corr = A.sc[4 * s + 1] * (double)d;
-        S.out[q] = 2.0 * S.p0[q] - S.pm1[q] + corr;
-        acc = corr;
-    } else {
-        const double t = (S.pp1[q] - 2.0 * S.p0[q] + S.pm1[q]) * A.sc[4 * s + 2];
-        const double err = (double)d - t;
-        A.gd[(size_t)s * NP + q] = (float)(A.gscale * err);
-        acc = err * err;
+    double sum = 0.0;
+    if (g == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float d = acc[r][0] + A.b4[0];
+            const size_t q = (size_t)(y0 + wave * 4 + r) * m + x0 + c16;
+            if constexpr (!TRAIN) {
+                const double corr = A.sc[4 * s + 1] * (double)d;
+                S.out[q] = 2.0 * S.p0[q] - S.pm1[q] + corr;
+                sum += corr;
+            } else {
+                const double tv = (S.pp1[q] - 2.0 * S.p0[q] + S.pm1[q]) * A.sc[4 * s + 2];
+                const double err = (double)d - tv;
+                A.gd[base + q] = (float)(A.gscale * err);
+                sum += err * err;
+            }
+        }
     }
-    const double bs = block_sum<256>(acc, red);
-    if (threadIdx.x == 0)
-        A.part[(size_t)(blockIdx.y * gridDim.x + blockIdx.x) * gridDim.z + s] = bs;
+    const double bs = block_sum<256>(sum, red);
+    if (t == 0) A.part[(size_t)(blockIdx.y * gridDim.x + blockIdx.x) * gridDim.z + s] = bs;
 }
 
 // The one sample of a step's learned guess: the caller's arrays from `io`,
@@ -739,6 +770,7 @@ struct CnnFrags {
     float* w4;
     uint16_t* x2;   // layers 2, 3 forward for the K = 32 instruction (k_cnn_conv32)
     uint16_t* x3;
+    uint16_t* x4;   // output layer, K = 32 (k_cnn_out32): 9 fragments, row 0 only
 };
 
 // Weight fragments of layers 2 and 3 for v_mfma_f32_16x16x32_bf16: fragment
@@ -754,6 +786,16 @@ __global__ void __launch_bounds__(256) k_cnn_prepare32(const float* __restrict__
     const int co = mt * 16 + (lane & 15), ci = 8 * (lane >> 4) + i;
     const int base = which ? CNN_W3 : CNN_W2;
     (which ? F.x3 : F.x2)[r] = bf16_bits(th[base + (tap * CNN_CH + ci) * CNN_CH + co]);
+}
+
+// Output-layer fragments for k_cnn_out32: fragment tap, lane l, element i holds
+// W4[tap][ci = 8 (l / 16) + i] in row m = l % 16 = 0, zero in the other rows.
+__global__ void __launch_bounds__(256) k_cnn_prepare_out32(const float* __restrict__ th, CnnFrags F) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= 9 * 64 * 8) return;
+    const int tap = e >> 9, lane = (e >> 3) & 63, i = e & 7;
+    const int ci = 8 * (lane >> 4) + i;
+    F.x4[e] = (lane & 15) == 0 ? bf16_bits(th[CNN_W4 + tap * CNN_CH + ci]) : (uint16_t)0;
 }
 
 __global__ void __launch_bounds__(256) k_cnn_prepare(const float* __restrict__ th, CnnFrags F) {

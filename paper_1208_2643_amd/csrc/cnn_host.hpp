@@ -84,6 +84,7 @@ struct CnnNet {
         A(&fr.w4, 9 * CNN_CH);
         A(&fr.x2, CNN_NFRAG32 * 64 * 8);
         A(&fr.x3, CNN_NFRAG32 * 64 * 8);
+        A(&fr.x4, 9 * 64 * 8);
         if (train) {
             for (int l = 1; l <= 3; ++l) { A(&a[l], act); A(&z[l], act); }
             A(&dz[0], act);
@@ -121,6 +122,7 @@ struct CnnNet {
         hipLaunchKernelGGL(k_cnn_prepare, dim3((total + 255) / 256), dim3(256), 0, s, theta, fr);
         hipLaunchKernelGGL(k_cnn_prepare32, dim3(2 * CNN_NFRAG32 * 64 * 8 / 256), dim3(256), 0, s,
                            theta, fr);
+        hipLaunchKernelGGL(k_cnn_prepare_out32, dim3(9 * 64 * 8 / 256), dim3(256), 0, s, theta, fr);
     }
 
     int load(const float* blob, hipStream_t s) {
@@ -166,14 +168,14 @@ struct CnnNet {
         c.zout = training ? z[3] : nullptr;
         conv32(c, s);
         CnnOutArgs o{};
-        o.m = m; o.n = n; o.in = a[3]; o.smp = d_smp; o.sc = sc; o.w4 = fr.w4;
+        o.m = m; o.n = n; o.in = a[3]; o.smp = d_smp; o.sc = sc; o.w4frag = fr.x4;
         o.b4 = theta + CNN_B4; o.gd = gd; o.part = part;
         o.gscale = 2.0 / ((double)B * (double)NP);
         if (training) {
-            hipLaunchKernelGGL((k_cnn_out<true>), tg, blk, 0, s, o);
+            hipLaunchKernelGGL((k_cnn_out32<true>), tg, blk, 0, s, o);
             hipLaunchKernelGGL((k_partials_sum<256>), dim3(1), blk, 0, s, part, nblk_out, B, sums);
         } else {
-            hipLaunchKernelGGL((k_cnn_out<false>), tg, blk, 0, s, o);
+            hipLaunchKernelGGL((k_cnn_out32<false>), tg, blk, 0, s, o);
             hipLaunchKernelGGL((k_partials_sum<256>), dim3(1), blk, 0, s, part, nblk_out, B, sums);
             if (shift)
                 hipLaunchKernelGGL(k_cnn_shift, dim3((unsigned)((NP + 255) / 256), B), blk, 0, s,
