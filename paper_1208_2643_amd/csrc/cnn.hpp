@@ -19,12 +19,15 @@
 // b3, W4 [3][3][32], b4).  A convolution is a GEMM per tap with the output
 // channels as M (two 16-row tiles), 16 pixels of a tile row as N and the input
 // channels as K; its weight operand is kept in registers as per-lane fragments
-// prepared from the FP32 master weights (k_cnn_prepare).  Layer 1 gathers its
-// 27 taps x channels, each input split into a BF16 hi and lo part, into one
-// K = 64 operand (im2col in LDS).
+// prepared from the FP32 master weights (k_cnn_prepare32 and its siblings).
+// Layer 1 gathers its 27 taps x channels, each input split into a BF16 hi and
+// lo part, into one K = 64 operand (im2col in LDS).  The forward layers and
+// the backward data pass run on v_mfma_f32_16x16x32_bf16; the weight
+// gradients (GEMMs over pixels) on v_mfma_f32_16x16x16bf16_1k.
 //
-// MFMA v_mfma_f32_16x16x16bf16_1k operand layout (lane l, g = l / 16,
-// c = l % 16): A[m = c][k = 4g + i], B[k = 4g + i][n = c], D[m = 4g + i][n = c].
+// Operand layouts (lane l, g = l / 16, c = l % 16): K = 32: A[m = c][k = 8g +
+// i], B[k = 8g + i][n = c]; K = 16: A[m = c][k = 4g + i], B[k = 4g + i][n = c];
+// both D[m = 4g + i][n = c].
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -40,8 +43,6 @@ constexpr int CNN_CH = 32;
 constexpr int CNN_TILE = 16;
 constexpr int CNN_HALO = 18;
 constexpr int CNN_PX = 36;           // LDS stride of one pixel (32 channels + 4 pad)
-constexpr int CNN_NFRAG1 = 8;        // layer 1: K = 64 (4 chunks) x 2 M tiles
-constexpr int CNN_NFRAG = 36;        // 9 taps x 2 K chunks x 2 M tiles
 constexpr int CNN_NFRAG32 = 18;      // K = 32 instruction: 9 taps x 2 M tiles
 // parameter offsets in the FP32 vector (blob order, no header)
 constexpr int CNN_CIN = 3;
@@ -153,7 +154,6 @@ __device__ __forceinline__ void cnn_load_inputs(const CnnSample& S, double in_sc
 // im2col value k of tile pixel (ty, tx): k = part * 27 + tap * 3 + channel for
 // the hi (part 0) and lo (part 1) inputs, 0 for k >= 54.
 constexpr int CNN_K1 = 64;        // layer-1 K (54 used), 4 chunks of 16
-constexpr int CNN_PX1 = 68;       // LDS stride of one im2col pixel
 __device__ __forceinline__ uint16_t cnn_im2col(const uint16_t (*xs)[CNN_HALO * CNN_HALO], int k,
                                                int ty, int tx) {
     if (k >= 2 * CNN_K1H) return 0;
@@ -178,109 +178,11 @@ struct CnnConvArgs {
 enum { CNN_FWD = 0, CNN_BWD = 1 };
 
 // One 3x3 convolution layer with 32 output channels on a 16 x 16 tile of one
-// sample.  FWD: out = gelu(conv(in) + b) (and z = conv(in) + b when zout is set).
-// BWD (transposed, flipped weights): out = conv(in) * gelu'(zprev).
-// Grid (m / 16, n / 16, samples), 256 threads; wave w computes tile rows
-// 4w ... 4w + 3.
-template <bool IM2COL, int MODE>
-__global__ void __launch_bounds__(256) k_cnn_conv(CnnConvArgs A) {
-    constexpr int NFR = IM2COL ? CNN_NFRAG1 : CNN_NFRAG;
-    constexpr int LDS_N = IM2COL ? CNN_TILE * CNN_TILE * CNN_PX1 : CNN_HALO * CNN_HALO * CNN_PX;
-    __shared__ __align__(16) uint16_t lds[LDS_N];
-    __shared__ uint16_t xs[IM2COL ? 6 : 1][IM2COL ? CNN_HALO * CNN_HALO : 1];
-    const int m = A.m, n = A.n;
-    const size_t NP = (size_t)m * n;
-    const int s = blockIdx.z;
-    const int x0 = blockIdx.x * CNN_TILE, y0 = blockIdx.y * CNN_TILE;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 4, c16 = lane & 15;
-    cnn_v4s af[NFR];
-#pragma unroll
-    for (int f = 0; f < NFR; ++f) af[f] = *(const cnn_v4s*)(A.wfrag + ((size_t)f * 64 + lane) * 4);
-    if constexpr (IM2COL) {
-        const CnnSample S = A.smp[s];
-        cnn_load_inputs(S, A.in_scale, A.dt, A.sc[4 * s + 0], x0, y0, m, n, xs);
-        __syncthreads();
-        {
-            const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
-#pragma unroll
-            for (int k = 0; k < CNN_K1; ++k) lds[t * CNN_PX1 + k] = cnn_im2col(xs, k, ty, tx);
-        }
-    } else {
-        cnn_load_halo(A.in, (size_t)s * NP, x0, y0, m, n, lds);
-    }
-    __syncthreads();
-    cnn_v4f acc[4][2];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) acc[r][mt] = cnn_v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = wave * 4 + r;
-        if constexpr (IM2COL) {
-#pragma unroll
-            for (int kc = 0; kc < CNN_K1 / 16; ++kc) {
-                const cnn_v4s b = *(const cnn_v4s*)(lds + (row * CNN_TILE + c16) * CNN_PX1 + kc * 16 + 4 * g);
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt)
-                    acc[r][mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[kc * 2 + mt], b,
-                                                                          acc[r][mt], 0, 0, 0);
-            }
-        } else {
-#pragma unroll
-            for (int tap = 0; tap < 9; ++tap) {
-                const int ky = tap / 3, kx = tap - 3 * (tap / 3);
-#pragma unroll
-                for (int kc = 0; kc < 2; ++kc) {
-                    const cnn_v4s b = *(const cnn_v4s*)(lds + ((row + ky) * CNN_HALO + c16 + kx) * CNN_PX +
-                                                        kc * 16 + 4 * g);
-#pragma unroll
-                    for (int mt = 0; mt < 2; ++mt)
-                        acc[r][mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
-                            af[(tap * 2 + kc) * 2 + mt], b, acc[r][mt], 0, 0, 0);
-                }
-            }
-        }
-    }
-    // epilogue: lane holds channels mt * 16 + 4g .. + 3 of pixel (row, c16)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = wave * 4 + r;
-        const size_t q = (size_t)s * NP + (size_t)(y0 + row) * m + x0 + c16;
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-            const int co = mt * 16 + 4 * g;
-            uint16_t o[4];
-            if constexpr (MODE == CNN_FWD) {
-                uint16_t zb[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float z = acc[r][mt][i] + A.bias[co + i];
-                    zb[i] = bf16_bits(z);
-                    o[i] = bf16_bits(gelu_f(z));
-                }
-                if (A.zout)
-                    *(uint2*)(A.zout + q * CNN_CH + co) =
-                        make_uint2((uint32_t)zb[0] | ((uint32_t)zb[1] << 16),
-                                   (uint32_t)zb[2] | ((uint32_t)zb[3] << 16));
-            } else {
-                const uint2 zp = *(const uint2*)(A.zprev + q * CNN_CH + co);
-                const uint16_t zv[4] = {(uint16_t)(zp.x & 0xffff), (uint16_t)(zp.x >> 16),
-                                        (uint16_t)(zp.y & 0xffff), (uint16_t)(zp.y >> 16)};
-#pragma unroll
-                for (int i = 0; i < 4; ++i) o[i] = bf16_bits(acc[r][mt][i] * gelu_grad_f(bf16_val(zv[i])));
-            }
-            *(uint2*)(A.out + q * CNN_CH + co) = make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16),
-                                                           (uint32_t)o[2] | ((uint32_t)o[3] << 16));
-        }
-    }
-}
-
-// Forward 32 -> 32 convolution on the K = 32 instruction
-// (v_mfma_f32_16x16x32_bf16: A[m = l % 16][k = 8 (l / 16) + i],
-// B[k = 8 (l / 16) + i][n = l % 16], D as for the K = 16 one), same result as
-// k_cnn_conv<false, CNN_FWD> up to the order of the FP32 additions.  The halo
+// sample, on the K = 32 instruction (v_mfma_f32_16x16x32_bf16:
+// A[m = l % 16][k = 8 (l / 16) + i], B[k = 8 (l / 16) + i][n = l % 16],
+// D[m = 4 (l / 16) + i][n = l % 16]).  FWD: out = gelu(conv(in) + b) (and
+// z = conv(in) + b when zout is set).  BWD (transposed, flipped weights):
+// out = conv(in) * gelu'(zprev).  The halo
 // tile's LDS pixel stride is CNN_PX32, so every lane reads the 8 channels of
 // its B operand as one 16-byte access.  Grid (m / 16, n / 16, samples), 256
 // threads; wave w computes rows 4w ... 4w + 3, the nine taps outside and the
@@ -288,6 +190,7 @@ __global__ void __launch_bounds__(256) k_cnn_conv(CnnConvArgs A) {
 constexpr int CNN_PX32 = 40;
 typedef __bf16 cnn_v8b __attribute__((ext_vector_type(8)));
 
+template <int MODE>
 __global__ void __launch_bounds__(256, 3) k_cnn_conv32(CnnConvArgs A) {
     constexpr int RW = 4;                      // rows per wave (8 measured slower)
     constexpr int TH = 4 * RW;                 // tile rows (four waves of RW rows)
@@ -351,6 +254,87 @@ __global__ void __launch_bounds__(256, 3) k_cnn_conv32(CnnConvArgs A) {
     for (int r = 0; r < RW; ++r) {
         const int row = wave * RW + r;
         const size_t q = base + (size_t)(y0 + row) * m + x0 + c16;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const int co = mt * 16 + 4 * g;
+            uint16_t o[4];
+            if constexpr (MODE == CNN_FWD) {
+                uint16_t zb[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float z = acc[r][mt][i] + A.bias[co + i];
+                    zb[i] = bf16_bits(z);
+                    o[i] = bf16_bits(gelu_f(z));
+                }
+                if (A.zout)
+                    *(uint2*)(A.zout + q * CNN_CH + co) =
+                        make_uint2((uint32_t)zb[0] | ((uint32_t)zb[1] << 16),
+                                   (uint32_t)zb[2] | ((uint32_t)zb[3] << 16));
+            } else {
+                const uint2 zp = *(const uint2*)(A.zprev + q * CNN_CH + co);
+                const uint16_t zv[4] = {(uint16_t)(zp.x & 0xffff), (uint16_t)(zp.x >> 16),
+                                        (uint16_t)(zp.y & 0xffff), (uint16_t)(zp.y >> 16)};
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    o[i] = bf16_bits(acc[r][mt][i] * gelu_grad_f(bf16_val(zv[i])));
+            }
+            *(uint2*)(A.out + q * CNN_CH + co) =
+                make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16),
+                           (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+        }
+    }
+}
+
+// First layer (3 inputs as BF16 hi and lo parts -> 32 channels) on the K = 32
+// instruction: the 27 taps x inputs of both parts (k = part * 27 + tap * 3 +
+// input, zero from 54 to 63) are gathered into an im2col row per pixel (LDS
+// pixel stride CNN_PX1_32, so a lane's 8 consecutive k are one 16-byte
+// access) and contracted in two K = 32 chunks.
+constexpr int CNN_PX1_32 = 72;
+__global__ void __launch_bounds__(256) k_cnn_conv1_32(CnnConvArgs A) {
+    __shared__ __align__(16) uint16_t lds[CNN_TILE * CNN_TILE * CNN_PX1_32];
+    __shared__ uint16_t xs[6][CNN_HALO * CNN_HALO];
+    const int m = A.m, n = A.n;
+    const size_t NP = (size_t)m * n;
+    const int s = blockIdx.z;
+    const size_t base = (size_t)s * NP;
+    const int x0 = blockIdx.x * CNN_TILE, y0 = blockIdx.y * CNN_TILE;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int g = lane >> 4, c16 = lane & 15;
+    cnn_v8b wf[4];  // (kc, mt) = (f >> 1, f & 1)
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+        wf[f] = __builtin_bit_cast(cnn_v8b, *(const uint4*)(A.wfrag + ((size_t)f * 64 + lane) * 8));
+    const CnnSample S = A.smp[s];
+    cnn_load_inputs(S, A.in_scale, A.dt, A.sc[4 * s + 0], x0, y0, m, n, xs);
+    __syncthreads();
+    {
+        const int ty = t >> 4, tx = t & 15;
+#pragma unroll
+        for (int k = 0; k < CNN_K1; ++k) lds[t * CNN_PX1_32 + k] = cnn_im2col(xs, k, ty, tx);
+    }
+    __syncthreads();
+    cnn_v4f acc[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        acc[r][0] = cnn_v4f{0.f, 0.f, 0.f, 0.f};
+        acc[r][1] = cnn_v4f{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const cnn_v8b b = __builtin_bit_cast(
+                cnn_v8b,
+                *(const uint4*)(lds + ((wave * 4 + r) * CNN_TILE + c16) * CNN_PX1_32 + kc * 32 + 8 * g));
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+                acc[r][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[kc * 2 + mt], b, acc[r][mt],
+                                                                     0, 0, 0);
+        }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const size_t q = base + (size_t)(y0 + wave * 4 + r) * m + x0 + c16;
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
             const int co = mt * 16 + 4 * g;
@@ -761,31 +745,47 @@ __global__ void __launch_bounds__(256) k_cnn_adam(float* theta, const float* __r
 //   f2, f3: layers 2, 3 forward, [tap][kc][mt][lane][4], A[co][ci] = W[tap][ci][co];
 //   r2, r3: backward data, A[co'][ci'] = W[8 - tap][co'][ci'] (flipped taps, swapped channels);
 //   w4: output-layer weights rounded to BF16 (as floats).
+// Weight operands for the K = 32 instruction, prepared from the FP32 master
+// weights after every change (load, Adam step).
 struct CnnFrags {
-    uint16_t* f1;
-    uint16_t* f2;
-    uint16_t* f3;
-    uint16_t* r2;
-    uint16_t* r3;
-    float* w4;
-    uint16_t* x2;   // layers 2, 3 forward for the K = 32 instruction (k_cnn_conv32)
+    uint16_t* x1;   // layer 1 (k_cnn_conv1_32): 2 K chunks x 2 M tiles
+    uint16_t* x2;   // layers 2, 3 forward (k_cnn_conv32<CNN_FWD>): 9 taps x 2 M tiles
     uint16_t* x3;
-    uint16_t* x4;   // output layer, K = 32 (k_cnn_out32): 9 fragments, row 0 only
+    uint16_t* r2;   // layers 2, 3 backward data (k_cnn_conv32<CNN_BWD>): flipped, transposed
+    uint16_t* r3;
+    uint16_t* x4;   // output layer (k_cnn_out32): 9 fragments, row 0 only
+    float* w4;      // output layer, BF16-rounded FP32 values (k_cnn_out_bwd)
 };
 
-// Weight fragments of layers 2 and 3 for v_mfma_f32_16x16x32_bf16: fragment
-// f = tap * 2 + mt, lane l, element i holds W[tap][ci = 8 (l / 16) + i][co =
-// 16 mt + l % 16] at ((f * 64 + l) * 8 + i).
+// Weight fragments of layers 2 and 3: fragment f = tap * 2 + mt, lane l,
+// element i at ((f * 64 + l) * 8 + i) holds, with a = 16 mt + l % 16 and
+// b = 8 (l / 16) + i, forward W[tap][ci = b][co = a]; backward data the
+// flipped, transposed W[8 - tap][ci = a][co = b].
 __global__ void __launch_bounds__(256) k_cnn_prepare32(const float* __restrict__ th, CnnFrags F) {
     const int e = blockIdx.x * 256 + threadIdx.x;
     constexpr int NX = CNN_NFRAG32 * 64 * 8;
-    if (e >= 2 * NX) return;
-    const int which = e / NX, r = e - which * NX;
+    if (e >= 4 * NX) return;
+    const int which = e / NX, r = e - which * NX;   // x2, x3, r2, r3
     const int f = r >> 9, lane = (r >> 3) & 63, i = r & 7;
     const int tap = f >> 1, mt = f & 1;
-    const int co = mt * 16 + (lane & 15), ci = 8 * (lane >> 4) + i;
-    const int base = which ? CNN_W3 : CNN_W2;
-    (which ? F.x3 : F.x2)[r] = bf16_bits(th[base + (tap * CNN_CH + ci) * CNN_CH + co]);
+    const int a = mt * 16 + (lane & 15), b = 8 * (lane >> 4) + i;
+    const int base = (which & 1) ? CNN_W3 : CNN_W2;
+    uint16_t* dst = which == 0 ? F.x2 : which == 1 ? F.x3 : which == 2 ? F.r2 : F.r3;
+    const float v = which < 2 ? th[base + (tap * CNN_CH + b) * CNN_CH + a]
+                              : th[base + ((8 - tap) * CNN_CH + a) * CNN_CH + b];
+    dst[r] = bf16_bits(v);
+}
+
+// Layer-1 fragments for k_cnn_conv1_32: fragment f = kc * 2 + mt, lane l,
+// element i holds W1 at k = 32 kc + 8 (l / 16) + i (both BF16 parts of an
+// input share its weight; zero for k >= 54), co = 16 mt + l % 16.
+__global__ void __launch_bounds__(256) k_cnn_prepare1_32(const float* __restrict__ th, CnnFrags F) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= 4 * 64 * 8) return;
+    const int f = e >> 9, lane = (e >> 3) & 63, i = e & 7;
+    const int kc = f >> 1, mt = f & 1;
+    const int co = mt * 16 + (lane & 15), k = kc * 32 + 8 * (lane >> 4) + i;
+    F.x1[e] = k < 2 * CNN_K1H ? bf16_bits(th[CNN_W1 + (k % CNN_K1H) * CNN_CH + co]) : (uint16_t)0;
 }
 
 // Output-layer fragments for k_cnn_out32: fragment tap, lane l, element i holds
@@ -798,33 +798,10 @@ __global__ void __launch_bounds__(256) k_cnn_prepare_out32(const float* __restri
     F.x4[e] = (lane & 15) == 0 ? bf16_bits(th[CNN_W4 + tap * CNN_CH + ci]) : (uint16_t)0;
 }
 
+// Output-layer weights rounded to BF16 (kept as FP32 values) for k_cnn_out_bwd.
 __global__ void __launch_bounds__(256) k_cnn_prepare(const float* __restrict__ th, CnnFrags F) {
     const int e = blockIdx.x * 256 + threadIdx.x;
-    constexpr int N1 = CNN_NFRAG1 * 256, N2 = CNN_NFRAG * 256;
-    if (e < N1) {
-        const int f = e >> 8, lane = (e >> 2) & 63, i = e & 3;
-        const int kc = f >> 1, mt = f & 1;
-        const int co = mt * 16 + (lane & 15), k = kc * 16 + 4 * (lane >> 4) + i;
-        F.f1[e] = k < 2 * CNN_K1H ? bf16_bits(th[CNN_W1 + (k % CNN_K1H) * CNN_CH + co]) : (uint16_t)0;
-        return;
-    }
-    int r = e - N1;
-    if (r < 4 * N2) {
-        const int which = r / N2;
-        r -= which * N2;
-        const int f = r >> 8, lane = (r >> 2) & 63, i = r & 3;
-        const int tap = f >> 2, kc = (f >> 1) & 1, mt = f & 1;
-        const int a = mt * 16 + (lane & 15), b = kc * 16 + 4 * (lane >> 4) + i;
-        const int base = (which & 1) ? CNN_W3 : CNN_W2;
-        uint16_t* dst = which == 0 ? F.f2 : which == 1 ? F.f3 : which == 2 ? F.r2 : F.r3;
-        // forward: co = a, ci = b; backward: co' = a (an input channel of W), ci' = b
-        const float v = which < 2 ? th[base + (tap * CNN_CH + b) * CNN_CH + a]
-                                  : th[base + ((8 - tap) * CNN_CH + a) * CNN_CH + b];
-        dst[r] = bf16_bits(v);
-        return;
-    }
-    r -= 4 * N2;
-    if (r < 9 * CNN_CH) F.w4[r] = bf16_val(bf16_bits(th[CNN_W4 + r]));
+    if (e < 9 * CNN_CH) F.w4[e] = bf16_val(bf16_bits(th[CNN_W4 + e]));
 }
 
 // Candidates of the step's initial guess, the learned one in copy 0 and the

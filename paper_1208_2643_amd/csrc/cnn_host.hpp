@@ -76,15 +76,13 @@ struct CnnNet {
         int rc = MPFC_OK;
         auto A = [&](auto** p, size_t cnt) { if (!rc) rc = dalloc(p, cnt); };
         A(&theta, CNN_NPARAM);
-        A(&fr.f1, CNN_NFRAG1 * 256);
-        A(&fr.f2, CNN_NFRAG * 256);
-        A(&fr.f3, CNN_NFRAG * 256);
-        A(&fr.r2, CNN_NFRAG * 256);
-        A(&fr.r3, CNN_NFRAG * 256);
-        A(&fr.w4, 9 * CNN_CH);
+        A(&fr.x1, 4 * 64 * 8);
         A(&fr.x2, CNN_NFRAG32 * 64 * 8);
         A(&fr.x3, CNN_NFRAG32 * 64 * 8);
+        A(&fr.r2, CNN_NFRAG32 * 64 * 8);
+        A(&fr.r3, CNN_NFRAG32 * 64 * 8);
         A(&fr.x4, 9 * 64 * 8);
+        A(&fr.w4, 9 * CNN_CH);
         if (train) {
             for (int l = 1; l <= 3; ++l) { A(&a[l], act); A(&z[l], act); }
             A(&dz[0], act);
@@ -118,11 +116,11 @@ struct CnnNet {
     }
 
     void prepare(hipStream_t s) {
-        const int total = CNN_NFRAG1 * 256 + 4 * CNN_NFRAG * 256 + 9 * CNN_CH;
-        hipLaunchKernelGGL(k_cnn_prepare, dim3((total + 255) / 256), dim3(256), 0, s, theta, fr);
-        hipLaunchKernelGGL(k_cnn_prepare32, dim3(2 * CNN_NFRAG32 * 64 * 8 / 256), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_cnn_prepare, dim3((9 * CNN_CH + 255) / 256), dim3(256), 0, s, theta, fr);
+        hipLaunchKernelGGL(k_cnn_prepare32, dim3(4 * CNN_NFRAG32 * 64 * 8 / 256), dim3(256), 0, s,
                            theta, fr);
         hipLaunchKernelGGL(k_cnn_prepare_out32, dim3(9 * 64 * 8 / 256), dim3(256), 0, s, theta, fr);
+        hipLaunchKernelGGL(k_cnn_prepare1_32, dim3(4 * 64 * 8 / 256), dim3(256), 0, s, theta, fr);
     }
 
     int load(const float* blob, hipStream_t s) {
@@ -144,7 +142,8 @@ struct CnnNet {
 
     // A forward 32 -> 32 layer on the K = 32 instruction.
     void conv32(const CnnConvArgs& c, hipStream_t s) {
-        hipLaunchKernelGGL(k_cnn_conv32, dim3(m / CNN_TILE, n / CNN_TILE, B), dim3(256), 0, s, c);
+        hipLaunchKernelGGL((k_cnn_conv32<CNN_FWD>), dim3(m / CNN_TILE, n / CNN_TILE, B), dim3(256), 0,
+                           s, c);
     }
 
     // Scales, three hidden layers and the output layer.  Inference writes the
@@ -159,8 +158,8 @@ struct CnnNet {
                            out_scale, sc);
         CnnConvArgs c{};
         c.m = m; c.n = n; c.smp = d_smp; c.sc = sc; c.in_scale = in_scale; c.dt = dt;
-        c.wfrag = fr.f1; c.bias = theta + CNN_B1; c.out = a[1]; c.zout = training ? z[1] : nullptr;
-        hipLaunchKernelGGL((k_cnn_conv<true, CNN_FWD>), tg, blk, 0, s, c);
+        c.wfrag = fr.x1; c.bias = theta + CNN_B1; c.out = a[1]; c.zout = training ? z[1] : nullptr;
+        hipLaunchKernelGGL(k_cnn_conv1_32, tg, blk, 0, s, c);
         c.in = a[1]; c.wfrag = fr.x2; c.bias = theta + CNN_B2; c.out = a[2];
         c.zout = training ? z[2] : nullptr;
         conv32(c, s);
@@ -205,12 +204,12 @@ struct CnnNet {
         reduce(CNN_SEG, CNN_W3, s);
         CnnConvArgs c{};
         c.m = m; c.n = n; c.in = dz[0]; c.wfrag = fr.r3; c.zprev = z[2]; c.out = dz[1];
-        hipLaunchKernelGGL((k_cnn_conv<false, CNN_BWD>), tg, blk, 0, s, c);
+        hipLaunchKernelGGL((k_cnn_conv32<CNN_BWD>), tg, blk, 0, s, c);
         wg.in = a[1]; wg.dz = dz[1];
         hipLaunchKernelGGL((k_cnn_wgrad<false>), dim3(nblk_w), blk, 0, s, wg);
         reduce(CNN_SEG, CNN_W2, s);
         c.in = dz[1]; c.wfrag = fr.r2; c.zprev = z[1]; c.out = dz[0];
-        hipLaunchKernelGGL((k_cnn_conv<false, CNN_BWD>), tg, blk, 0, s, c);
+        hipLaunchKernelGGL((k_cnn_conv32<CNN_BWD>), tg, blk, 0, s, c);
         wg.dz = dz[0];
         hipLaunchKernelGGL((k_cnn_wgrad<true>), dim3(nblk_w), blk, 0, s, wg);
         reduce(CNN_SEG1, CNN_W1, s);
