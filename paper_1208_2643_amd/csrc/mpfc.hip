@@ -547,13 +547,13 @@ void defect(mpfc_ctx* C, int from, int add, hipStream_t s) {
     F.base = nullptr;
     const int to = from ^ 1;
     const int max_norms = C->o.max_cycles + 1;
-    auto kern = C->p.scheme == 1 ? k_defect<1, NT> : k_defect<2, NT>;
-    // one thread per cell (the partial sums hold one value per 256 cells):
-    // a grid-stride loop of a few cells per thread waits on each cell's loads
-    // in turn
-    const unsigned nb = (unsigned)((total + NT - 1) / NT);
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(NT), 0, s, F, level_op(C, F0), F0.g, C->st, C->part,
-                       FF.e[0][0], FF.e[0][1], FF.e[0][2], add, F0.u[to][0], F0.u[to][1],
+    // one 32 x 8 tile per workgroup (the partial sums hold one value per 256
+    // cells), its values and their ring staged in LDS
+    auto kern = C->p.scheme == 1 ? k_defect_tile<1> : k_defect_tile<2>;
+    const dim3 grid((F0.m + DT_X - 1) / DT_X, (F0.n + DT_Y - 1) / DT_Y);
+    const unsigned nb = grid.x * grid.y;
+    hipLaunchKernelGGL(kern, grid, dim3(DT_X * DT_Y), 0, s, F, level_op(C, F0), F0.g, C->st,
+                       C->part, FF.e[0][0], FF.e[0][1], FF.e[0][2], add, F0.u[to][0], F0.u[to][1],
                        F0.u[to][2], FF.f[0], FF.f[1], FF.f[2], FF.pb);
     hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)nb, C->st,
                        C->hist, F0.h * F0.h, C->o.tol, max_norms, C->o.diverge);

@@ -71,29 +71,82 @@ __device__ __forceinline__ double defect_cell(const Fields<double>& F, const Lev
     return a * a + b * b + c * c;
 }
 
-// Whole finest grid, one thread per cell; per-block sums of r^2 into part[]
-// (summed by k_norm_finalize).  The correction e is cleared by the next
-// outer iteration, not here (neighbours still read it).
-template <int SCHEME, int NT>
-__global__ void __launch_bounds__(NT) k_defect(Fields<double> F, LevelOp<double> op, Grid g,
-                                               const CycleState* st, double* part,
-                                               const float* __restrict__ e0,
-                                               const float* __restrict__ e1,
-                                               const float* __restrict__ e2, int add,
-                                               double* un0, double* un1, double* un2,
-                                               float* r0, float* r1, float* r2, float* pbase) {
+// The same on a 32 x 8 tile per workgroup (one cell per thread): u + e of the
+// tile and a ring of one cell (the neighbour rule of wrapx / wrapy) is formed
+// once into LDS, so each cell's value is loaded from memory once instead of
+// by its five stencils.  Same arithmetic and order per cell as defect_cell;
+// per-block sums of r^2 into part[] (blockIdx.y * gridDim.x + blockIdx.x),
+// summed by k_norm_finalize.  The correction e is cleared by the next outer
+// iteration, not here (other workgroups still read it for their ring).
+constexpr int DT_X = 32, DT_Y = 8;
+template <int SCHEME>
+__global__ void __launch_bounds__(DT_X * DT_Y) k_defect_tile(Fields<double> F, LevelOp<double> op,
+                                                            Grid g, const CycleState* st,
+                                                            double* part,
+                                                            const float* __restrict__ e0,
+                                                            const float* __restrict__ e1,
+                                                            const float* __restrict__ e2, int add,
+                                                            double* un0, double* un1, double* un2,
+                                                            float* r0, float* r1, float* r2,
+                                                            float* pbase) {
+    constexpr int NT = DT_X * DT_Y, LX = DT_X + 2, LY = DT_Y + 2, NL = LX * LY;
     if (stopped(st)) return;
+    __shared__ double U[3][LY][LX];
     __shared__ double red[NT / 64];
+    const int t = threadIdx.x;
+    const int x0 = blockIdx.x * DT_X, y0 = blockIdx.y * DT_Y;
+    // tile + ring: every load issued before the LDS stores (indices clamped)
+    constexpr int NR = (NL + NT - 1) / NT;
+    double v[NR][3];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int c = min(t + k * NT, NL - 1);
+        const int ly = c / LX, lx = c - ly * LX;
+        const int gi = wrapx(min(max(x0 + lx - 1, -1), g.m), g);
+        const int gj = wrapy(min(max(y0 + ly - 1, -1), g.n), g);
+        const size_t q = at(gi, gj, g);
+        v[k][0] = add ? F.phi[q] + (double)e0[q] : F.phi[q];
+        v[k][1] = add ? F.mu[q] + (double)e1[q] : F.mu[q];
+        v[k][2] = add ? F.ka[q] + (double)e2[q] : F.ka[q];
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int c = t + k * NT;
+        if (c < NL) {
+            const int ly = c / LX, lx = c - ly * LX;
+            U[0][ly][lx] = v[k][0];
+            U[1][ly][lx] = v[k][1];
+            U[2][ly][lx] = v[k][2];
+        }
+    }
+    __syncthreads();
+    const int tx = t % DT_X, ty = t / DT_X;
+    const int i = x0 + tx, j = y0 + ty;
     double acc = 0.0;
-    const size_t total = (size_t)g.m * g.n;
-    for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
-        int i, j;
-        cell_of(q, g, i, j);
-        acc += defect_cell<SCHEME>(F, op, g, e0, e1, e2, add, un0, un1, un2, r0, r1, r2, pbase, i, j);
+    if (i < g.m && j < g.n) {
+        const size_t q = at(i, j, g);
+        const int lx = tx + 1, ly = ty + 1;
+        const double x = U[0][ly][lx], y = U[1][ly][lx], z = U[2][ly][lx];
+        // neighbours in defect_cell's order: east, west, north, south
+        const double sx = ((U[0][ly][lx + 1] + U[0][ly][lx - 1]) + U[0][ly + 1][lx]) + U[0][ly - 1][lx];
+        const double sy = ((U[1][ly][lx + 1] + U[1][ly][lx - 1]) + U[1][ly + 1][lx]) + U[1][ly - 1][lx];
+        const double sz = ((U[2][ly][lx + 1] + U[2][ly][lx - 1]) + U[2][ly + 1][lx]) + U[2][ly - 1][lx];
+        const double xk = SCHEME == 2 ? F.phik[q] : 0.0;
+        const double lphi = (sx - 4.0 * x) * op.ih2;
+        const double lmu = (sy - 4.0 * y) * op.ih2;
+        const double lka = (sz - 4.0 * z) * op.ih2;
+        const double a = F.f1[q] - (x - op.c * lmu);
+        const double b = F.f2[q] - (y - nl_value<double, SCHEME, false>(x, 0.0, xk) - op.al * x - lka);
+        const double c = F.f3[q] - (z - op.e * lphi);
+        un0[q] = x; un1[q] = y; un2[q] = z;
+        r0[q] = (float)a; r1[q] = (float)b; r2[q] = (float)c;
+        pbase[q] = (float)x;
+        acc = a * a + b * b + c * c;
     }
     const double bs = block_sum<NT>(acc, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+    if (t == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = bs;
 }
+
 
 template <typename TI, typename TO>
 __global__ void __launch_bounds__(256) k_convert(const TI* __restrict__ a, TO* b, size_t n) {
