@@ -1230,6 +1230,33 @@ int step_prologue(mpfc_ctx* C, hipStream_t s) {
     const int gmode = C->o.guess == MPFC_GUESS_PREV ? 0 : 1;
     const double* pin = C->pinned ? F0.pin : nullptr;
     const double* phihat = C->pinned ? C->phihat : nullptr;
+    // Without the learned guess, on sides that are multiples of 32 (x) and 8
+    // (y): the whole set-up in one tiled pass (with the first norm's sums
+    // unless mixed precision forms its own first defect).
+    if (!learned && F0.m % SU_X == 0 && F0.n % SU_Y == 0) {
+        const dim3 grid(F0.m / SU_X, F0.n / SU_Y);
+        const unsigned nb = grid.x * grid.y;
+        const bool mixed = C->o.precision == MPFC_MIXED;
+        auto kern = C->p.scheme == 1 ? (mixed ? k_setup_tile<1, false> : k_setup_tile<1, true>)
+                                     : (mixed ? k_setup_tile<2, false> : k_setup_tile<2, true>);
+        hipLaunchKernelGGL(kern, grid, dim3(SU_X * SU_Y), 0, s, g0, level_op(C, F0), C->d,
+                           C->alpha, gmode, (const StepIO*)C->io, F0.f[0], F0.f[1], F0.f[2],
+                           C->phik, pin, phihat, F0.u[0][0], F0.u[0][2], F0.u[0][1], C->st,
+                           C->part);
+        if (!mixed) {
+            hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)nb,
+                               C->st, C->hist, F0.h * F0.h, C->o.tol, C->o.max_cycles + 1,
+                               C->o.diverge);
+        } else {
+            const auto& FF = C->FL[0];
+            if (C->p.scheme == 2)
+                hipLaunchKernelGGL((k_convert<double, float>), grid1(total), dim3(256), 0, s,
+                                   C->phik, FF.xk, total);
+            defect(C, 0, 0, s);
+        }
+        HIP_TRY(hipGetLastError());
+        return MPFC_OK;
+    }
     // Source, guess and kappa in one pass (the caller's arrays from C->io: this
     // part is captured once and replayed); with the learned guess the
     // extrapolated candidate goes to copy 1 and the network's to copy 0.

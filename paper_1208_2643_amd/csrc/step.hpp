@@ -299,6 +299,114 @@ __global__ void __launch_bounds__(256) k_setup(Grid g, double ih2, double d, dou
     ka[q] = S3[q] + e * (ns - 4.0 * x) * ih2;
 }
 
+// The step's whole set-up on a 32 x 8 tile per workgroup: the source S, the
+// guess, kappa and mu (k_setup, then k_complete_mu) and, with NORM, the
+// per-block sums of r1^2 of the completed guess (k_resnorm_guess).  phi^k and
+// phi^{k-1} of the tile and a ring of three cells (the neighbour rule of
+// wrapx / wrapy; reflected rings of a Neumann axis give the mirrored cells'
+// values, so kappa and mu there are the mirrored cells' too) are staged in
+// LDS; the guess is formed on all of it, kappa on the tile and two rings, mu
+// on the tile and one ring.  Same arithmetic and order per cell as those
+// kernels.  Sides must be multiples of 32 (x) and 8 (y), at least 32 x 8.
+// Workgroup (0, 0) also resets the cycle state.
+constexpr int SU_X = 32, SU_Y = 8, SU_H = 3;
+template <int SCHEME, bool NORM>
+__global__ void __launch_bounds__(SU_X * SU_Y) k_setup_tile(
+    Grid g, LevelOp<double> op, double d, double alpha, int mode, const StepIO* __restrict__ io,
+    double* S1, double* S2, double* S3, double* phik_copy, const double* __restrict__ pin,
+    const double* __restrict__ phihat, double* phi0, double* ka, double* mu, CycleState* st,
+    double* part) {
+    constexpr int NT = SU_X * SU_Y, LX = SU_X + 2 * SU_H, LY = SU_Y + 2 * SU_H;
+    __shared__ double PK[LY][LX], PM[LY][LX], G0[LY][LX], K[LY][LX], MU[LY][LX];
+    __shared__ double red[NT / 64];
+    const int t = threadIdx.x;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
+        st->acc = 0.0; st->blocks = 0u; st->count = 0;
+        st->status = ST_RUNNING; st->done = 0; st->pad0 = st->pad1 = 0;
+    }
+    const int xb = blockIdx.x * SU_X - SU_H, yb = blockIdx.y * SU_Y - SU_H;
+    const double* __restrict__ phik = io->phi_n;
+    const double* __restrict__ phikm1 = io->phi_nm1;
+    const double ih2 = op.ih2;
+    // phi^k, phi^{k-1} and the guess on the tile and three rings
+    {
+        constexpr int NL = LX * LY, NR = (NL + NT - 1) / NT;
+        double vk[NR], vm[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int c = min(t + r * NT, NL - 1);
+            const int ly = c / LX, lx = c - ly * LX;
+            const size_t q = at(wrapx(xb + lx, g), wrapy(yb + ly, g), g);
+            vk[r] = phik[q];
+            vm[r] = phikm1[q];
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int c = t + r * NT;
+            if (c < NL) {
+                const int ly = c / LX, lx = c - ly * LX;
+                PK[ly][lx] = vk[r];
+                PM[ly][lx] = vm[r];
+                G0[ly][lx] = guess_value(mode, vk[r], vm[r]);
+            }
+        }
+    }
+    __syncthreads();
+    auto ns = [&](const double (&A)[LY][LX], int lx, int ly) {
+        return (A[ly][lx + 1] + A[ly][lx - 1]) + (A[ly + 1][lx] + A[ly - 1][lx]);
+    };
+    // kappa = S3 + e Lap phi0 on the tile and two rings
+    for (int c = t; c < (LX - 2) * (LY - 2); c += NT) {
+        const int ly = 1 + c / (LX - 2), lx = 1 + c % (LX - 2);
+        const double lk = (ns(PK, lx, ly) - 4.0 * PK[ly][lx]) * ih2;
+        const double s3 = SCHEME == 1 ? 0.0 : 0.5 * lk;
+        K[ly][lx] = s3 + op.e * (ns(G0, lx, ly) - 4.0 * G0[ly][lx]) * ih2;
+    }
+    __syncthreads();
+    // S2 of a cell (source_cell's arithmetic)
+    auto s2_at = [&](int lx, int ly, size_t q) {
+        const double pk = PK[ly][lx];
+        const double lk = (ns(PK, lx, ly) - 4.0 * pk) * ih2;
+        if constexpr (SCHEME == 1) {
+            return 2.0 * lk;
+        } else {
+            const double lkm1 = (ns(PM, lx, ly) - 4.0 * PM[ly][lx]) * ih2;
+            double v = 0.5 * alpha * pk + (3.0 * lk - lkm1);
+            if (pin) v += pin[q] * (pk - 2.0 * phihat[q]);
+            return v;
+        }
+    };
+    // mu = S2 + g(phi0) + al phi0 + Lap kappa on the tile and one ring
+    for (int c = t; c < (LX - 4) * (LY - 4); c += NT) {
+        const int ly = 2 + c / (LX - 4), lx = 2 + c % (LX - 4);
+        const size_t q = at(wrapx(xb + lx, g), wrapy(yb + ly, g), g);
+        const double x = G0[ly][lx];
+        const double xk = SCHEME == 2 ? PK[ly][lx] : 0.0;
+        const double alq = op.al + (pin ? pin[q] : 0.0);
+        MU[ly][lx] = s2_at(lx, ly, q) + nl_value<double, SCHEME, false>(x, 0.0, xk) + alq * x +
+                     (ns(K, lx, ly) - 4.0 * K[ly][lx]) * ih2;
+    }
+    __syncthreads();
+    // the tile: S, phi^k copy, guess, kappa, mu and the first residual component
+    const int tx = t % SU_X, ty = t / SU_X, lx = tx + SU_H, ly = ty + SU_H;
+    const size_t q = at(blockIdx.x * SU_X + tx, blockIdx.y * SU_Y + ty, g);
+    const double pk = PK[ly][lx];
+    const double s1 = pk + d * io->psi[q];
+    S1[q] = s1;
+    S2[q] = s2_at(lx, ly, q);
+    S3[q] = SCHEME == 1 ? 0.0 : 0.5 * ((ns(PK, lx, ly) - 4.0 * pk) * ih2);
+    if (phik_copy) phik_copy[q] = pk;
+    phi0[q] = G0[ly][lx];
+    ka[q] = K[ly][lx];
+    mu[q] = MU[ly][lx];
+    if constexpr (NORM) {
+        const double lmu = (ns(MU, lx, ly) - 4.0 * MU[ly][lx]) * ih2;
+        const double r1 = s1 - (G0[ly][lx] - op.c * lmu);
+        const double bs = block_sum<NT>(r1 * r1, red);
+        if (t == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = bs;
+    }
+}
+
 // Residual norm of a guess completed by k_setup and k_complete_mu: N^(2) = S^(2)
 // and N^(3) = S^(3) hold by construction (up to rounding), so only
 // r1 = S1 - (phi - c Lap mu) is summed (per-block sums of r1^2 into part[];
