@@ -1230,23 +1230,34 @@ int step_prologue(mpfc_ctx* C, hipStream_t s) {
     const int gmode = C->o.guess == MPFC_GUESS_PREV ? 0 : 1;
     const double* pin = C->pinned ? F0.pin : nullptr;
     const double* phihat = C->pinned ? C->phihat : nullptr;
-    // Without the learned guess, on sides that are multiples of 32 (x) and 8
-    // (y): the whole set-up in one tiled pass (with the first norm's sums
-    // unless mixed precision forms its own first defect).
-    if (!learned && F0.m % SU_X == 0 && F0.n % SU_Y == 0) {
+    // On sides that are multiples of 32 (x) and 8 (y): the whole set-up of the
+    // extrapolated (or previous-step) guess in one tiled pass, with the first
+    // norm's sums unless mixed precision forms its own first defect or the
+    // learned guess is compared with it (then it goes to copy 1, and the
+    // network's candidate to copy 0; both paths complete that guess with the
+    // same arithmetic, so a network that falls back reproduces the run
+    // without it bit for bit).
+    if (F0.m % SU_X == 0 && F0.n % SU_Y == 0) {
         const dim3 grid(F0.m / SU_X, F0.n / SU_Y);
         const unsigned nb = grid.x * grid.y;
         const bool mixed = C->o.precision == MPFC_MIXED;
-        auto kern = C->p.scheme == 1 ? (mixed ? k_setup_tile<1, false> : k_setup_tile<1, true>)
-                                     : (mixed ? k_setup_tile<2, false> : k_setup_tile<2, true>);
+        const bool norm = !mixed && !learned;
+        const int ce = learned ? 1 : 0;
+        auto kern = C->p.scheme == 1 ? (norm ? k_setup_tile<1, true> : k_setup_tile<1, false>)
+                                     : (norm ? k_setup_tile<2, true> : k_setup_tile<2, false>);
         hipLaunchKernelGGL(kern, grid, dim3(SU_X * SU_Y), 0, s, g0, level_op(C, F0), C->d,
                            C->alpha, gmode, (const StepIO*)C->io, F0.f[0], F0.f[1], F0.f[2],
-                           C->phik, pin, phihat, F0.u[0][0], F0.u[0][2], F0.u[0][1], C->st,
+                           C->phik, pin, phihat, F0.u[ce][0], F0.u[ce][2], F0.u[ce][1], C->st,
                            C->part);
+        if (learned) {
+            int rc = cnn_candidate(C, (const StepIO*)C->io, s);  // into copy 0, completed
+            if (rc) return rc;
+            cnn_choose(C, s);  // leaves the kept guess's sum in part[0]
+        }
         if (!mixed) {
-            hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part, (int)nb,
-                               C->st, C->hist, F0.h * F0.h, C->o.tol, C->o.max_cycles + 1,
-                               C->o.diverge);
+            hipLaunchKernelGGL((k_norm_finalize<NT>), dim3(1), dim3(NT), 0, s, C->part,
+                               learned ? 1 : (int)nb, C->st, C->hist, F0.h * F0.h, C->o.tol,
+                               C->o.max_cycles + 1, C->o.diverge);
         } else {
             const auto& FF = C->FL[0];
             if (C->p.scheme == 2)
