@@ -171,7 +171,8 @@ int mpfc_create(mpfc_ctx **out, int m, int n, const mpfc_params *p, const mpfc_o
  *              d_phi_nm1)
  *   d_phi_np1  phi^{k+1} (written; must not alias the inputs)
  *   d_mu, d_kappa  optional outputs (NULL to skip): mu^{k+1} (mu^{k+1/2} for
- *              scheme 2) and kappa
+ *              scheme 2) and kappa; distinct arrays that alias none of the
+ *              above (else MPFC_EINVAL)
  *   h_info     optional report (NULL to skip).
  * Returns after the final residual readback (the outputs are complete on the
  * context's stream).  On MPFC_ENOTCONVERGED / ENONFINITE / EDIVERGED the

@@ -1332,20 +1332,27 @@ void enqueue_wrapup(mpfc_ctx* C, hipStream_t s, bool warm, int npoisson) {
     const size_t total = (size_t)C->m * C->n;
     const int mixed = C->o.precision == MPFC_MIXED;
     const StepIO* io = C->io;
+    WrapFields wf;
+    for (int c = 0; c < 2; ++c) {
+        wf.phi[c] = F0.u[c][0];
+        wf.mu[c] = F0.u[c][1];
+        wf.kappa[c] = F0.u[c][2];
+    }
     if (!C->o.energy) {
         if (C->p.scheme == 1)
             hipLaunchKernelGGL((k_wrap_psi<1>), grid1(total), dim3(256), 0, s, io, C->st, mixed,
-                               F0.u[0][0], F0.u[1][0], total, C->p.dt);
+                               wf, total, C->p.dt);
         else
             hipLaunchKernelGGL((k_wrap_psi<2>), grid1(total), dim3(256), 0, s, io, C->st, mixed,
-                               F0.u[0][0], F0.u[1][0], total, C->p.dt);
+                               wf, total, C->p.dt);
         return;
     }
     const unsigned rb = red_blocks(total);
-    // psi^{k+1}, phi^{k+1} and the sums of psi^{k+1} and mu (acc[8], acc[9])
+    // psi^{k+1}, phi^{k+1}, the optional mu and kappa outputs, and the sums
+    // of psi^{k+1} and mu (acc[8], acc[9])
     auto k1 = C->p.scheme == 1 ? k_wrap_psi_sums<1, NT> : k_wrap_psi_sums<2, NT>;
-    hipLaunchKernelGGL(k1, dim3(rb), dim3(NT), 0, s, io, C->st, mixed, F0.u[0][0], F0.u[1][0],
-                       F0.u[0][1], F0.u[1][1], warm ? 1 : 0, total, C->p.dt, C->part, C->pst);
+    hipLaunchKernelGGL(k1, dim3(rb), dim3(NT), 0, s, io, C->st, mixed, wf, warm ? 1 : 0, total,
+                       C->p.dt, C->part, C->pst);
     hipLaunchKernelGGL((k_wrap_partials<NT>), dim3(1), dim3(NT), 0, s, C->st, C->part, (int)rb, 2,
                        C->acc + 8);
     if (!warm) {
@@ -1372,7 +1379,9 @@ void enqueue_wrapup(mpfc_ctx* C, hipStream_t s, bool warm, int npoisson) {
         hipLaunchKernelGGL((k_p_finalize<NT>), dim3(1), dim3(NT), 0, s, C->acc + 11, 1, C->pst,
                            C->phist, C->acc + 10, kPoissonRel, kPoissonStall, kPoissonMax);
     for (int k = 0; k < npoisson; ++k) vcycle_poisson(C, s);
-    enqueue_energy_terms(C, s, warm);
+    // A warm start with no cycle behind it keeps the sums above (the host runs
+    // cycles and the sums again if it fails its test): nothing to enqueue.
+    if (!warm || npoisson > 0) enqueue_energy_terms(C, s, warm);
 }
 
 // Energy sums of phi^{k+1} with the Poisson cycles' w into acc[0..7], when
@@ -1646,6 +1655,11 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
         return fail(MPFC_EINVAL, "phi_np1 must not alias an input");
     if (psi == phi_n || psi == phi_nm1)
         return fail(MPFC_EINVAL, "psi (updated in place) must not alias phi_n or phi_nm1");
+    for (const double* o : {(const double*)mu_out, (const double*)ka_out})
+        if (o && (o == phi_n || o == phi_nm1 || o == psi || o == phi_np1))
+            return fail(MPFC_EINVAL, "mu and kappa outputs must not alias the other arrays");
+    if (mu_out && mu_out == ka_out)
+        return fail(MPFC_EINVAL, "mu and kappa outputs must be distinct arrays");
     if (!phi_nm1) phi_nm1 = phi_n;
     if (C->o.guess == MPFC_GUESS_CNN && !C->cnn)
         return fail(MPFC_EINVAL, "guess mode MPFC_GUESS_CNN needs a network (mpfc_cnn_load)");
@@ -1655,7 +1669,8 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     const bool mixed = C->o.precision == MPFC_MIXED;
     const bool learned = C->o.guess == MPFC_GUESS_CNN;
     // The caller's arrays, for the captured set-up and wrap-up.
-    hipLaunchKernelGGL(k_set_io, dim3(1), dim3(64), 0, s, C->io, phi_n, phi_nm1, psi, phi_np1);
+    hipLaunchKernelGGL(k_set_io, dim3(1), dim3(64), 0, s, C->io, phi_n, phi_nm1, psi, phi_np1,
+                       mu_out, ka_out);
     int rc = run_unit(C, graph_key(GK_PROLOGUE), [&](hipStream_t cs) {
         (void)step_prologue(C, cs);
     });
@@ -1736,13 +1751,6 @@ int mpfc_step(mpfc_ctx* C, const double* phi_n, const double* phi_nm1, double* p
     const int nouter = fin.count - 1;
     const int ncyc = mixed ? inner_cycles_run(C, nouter) : nouter;
     C->pred_units = nouter > 0 ? nouter : 1;
-    const int cur = mixed ? 1 ^ (nouter & 1) : 0;
-    if (mu_out)
-        HIP_TRY(hipMemcpyAsync(mu_out, F0.u[cur][1], total * sizeof(double),
-                               hipMemcpyDeviceToDevice, s));
-    if (ka_out)
-        HIP_TRY(hipMemcpyAsync(ka_out, F0.u[cur][2], total * sizeof(double),
-                               hipMemcpyDeviceToDevice, s));
     const int st_rc = status_code(fin.status);
     if (info) {
         info->n_cycles = ncyc;

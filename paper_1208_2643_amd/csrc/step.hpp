@@ -200,6 +200,8 @@ struct StepIO {
     const double* phi_nm1;  // phi^{k-1}
     double* psi;            // psi^k on entry, psi^{k+1} after the wrap-up
     double* phi_np1;        // phi^{k+1}
+    double* mu;             // optional mu^{k+1} output (null: not asked for)
+    double* kappa;          // optional kappa^{k+1} output (null: not asked for)
 };
 
 template <int SCHEME>
@@ -255,12 +257,14 @@ __device__ __forceinline__ void complete_kappa_cell(const Grid& g, double ih2, d
 }
 
 __global__ void k_set_io(StepIO* io, const double* phi_n, const double* phi_nm1, double* psi,
-                         double* phi_np1) {
+                         double* phi_np1, double* mu, double* kappa) {
     if (threadIdx.x == 0) {
         io->phi_n = phi_n;
         io->phi_nm1 = phi_nm1;
         io->psi = psi;
         io->phi_np1 = phi_np1;
+        io->mu = mu;
+        io->kappa = kappa;
     }
 }
 

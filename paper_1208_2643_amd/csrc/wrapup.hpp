@@ -27,34 +27,45 @@ __device__ __forceinline__ int final_copy(const CycleState* st, int mixed) {
     return mixed ? 1 ^ ((st->count - 1) & 1) : 0;
 }
 
-// psi^{k+1} in place on the caller's psi and phi^{k+1} into the caller's array
-// (steps without energies).
+// Level-0 arrays of the two FP64 copies of the iterate (copy 1 exists with
+// mixed precision and with the learned guess; null otherwise).
+struct WrapFields {
+    const double* phi[2];
+    const double* mu[2];
+    const double* kappa[2];
+};
+
+// The caller's optional mu and kappa outputs of cell q from the final copy c.
+__device__ __forceinline__ void wrap_outputs(const StepIO* __restrict__ io, const WrapFields& f,
+                                             int c, size_t q) {
+    if (io->mu) io->mu[q] = f.mu[c][q];
+    if (io->kappa) io->kappa[q] = f.kappa[c][q];
+}
+
+// psi^{k+1} in place on the caller's psi, phi^{k+1} and (when asked for) mu,
+// kappa into the caller's arrays (steps without energies).
 template <int SCHEME>
 __global__ void __launch_bounds__(256) k_wrap_psi(const StepIO* __restrict__ io,
-                                                  const CycleState* st, int mixed,
-                                                  const double* __restrict__ phi0,
-                                                  const double* __restrict__ phi1, size_t total,
-                                                  double s) {
+                                                  const CycleState* st, int mixed, WrapFields f,
+                                                  size_t total, double s) {
     if (wrapup_off(st)) return;
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= total) return;
-    const double* phi = final_copy(st, mixed) ? phi1 : phi0;
-    psi_cell<SCHEME>(s, phi, io->phi_n, io->psi, io->phi_np1, q);
+    const int c = final_copy(st, mixed);
+    psi_cell<SCHEME>(s, f.phi[c], io->phi_n, io->psi, io->phi_np1, q);
+    wrap_outputs(io, f, c, q);
 }
 
-// psi^{k+1} in place on the caller's psi, phi^{k+1} into the caller's array,
-// and per-block sums of psi^{k+1} and (advance) of the step's mu into
-// part[blk * 2 + 0/1].  Block 0 resets the Poisson cycle state, or, while the
-// wrap-up is off, marks it stopped so that the Poisson cycles skip too.
+// psi^{k+1} in place on the caller's psi, phi^{k+1} and (when asked for) mu,
+// kappa into the caller's arrays, and per-block sums of psi^{k+1} and
+// (advance) of the step's mu into part[blk * 2 + 0/1].  Block 0 resets the
+// Poisson cycle state, or, while the wrap-up is off, marks it stopped so that
+// the Poisson cycles skip too.
 template <int SCHEME, int NT>
 __global__ void __launch_bounds__(NT) k_wrap_psi_sums(const StepIO* __restrict__ io,
                                                       const CycleState* st, int mixed,
-                                                      const double* __restrict__ phi0,
-                                                      const double* __restrict__ phi1,
-                                                      const double* __restrict__ mu0,
-                                                      const double* __restrict__ mu1, int advance,
-                                                      size_t total, double s, double* part,
-                                                      CycleState* pst) {
+                                                      WrapFields f, int advance, size_t total,
+                                                      double s, double* part, CycleState* pst) {
     __shared__ double red[NT / 64];
     const bool off = wrapup_off(st);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -67,11 +78,14 @@ __global__ void __launch_bounds__(NT) k_wrap_psi_sums(const StepIO* __restrict__
     }
     if (off) return;
     const int fc = final_copy(st, mixed);
-    const double* __restrict__ phi = fc ? phi1 : phi0;
-    const double* __restrict__ mu = advance ? (fc ? mu1 : mu0) : nullptr;
+    const double* __restrict__ phi = f.phi[fc];
+    const double* __restrict__ mu = f.mu[fc];
+    const double* __restrict__ ka = f.kappa[fc];
     const double* __restrict__ phik = io->phi_n;
     double* __restrict__ psi = io->psi;
     double* __restrict__ out = io->phi_np1;
+    double* __restrict__ mu_out = io->mu;
+    double* __restrict__ ka_out = io->kappa;
     double sx = 0.0, sy = 0.0;
     for (size_t q = (size_t)blockIdx.x * NT + threadIdx.x; q < total; q += (size_t)gridDim.x * NT) {
         const double x = phi[q];
@@ -79,7 +93,12 @@ __global__ void __launch_bounds__(NT) k_wrap_psi_sums(const StepIO* __restrict__
         psi[q] = v;
         out[q] = x;
         sx += v;
-        if (mu) sy += mu[q];
+        if (advance || mu_out) {
+            const double y = mu[q];
+            if (advance) sy += y;
+            if (mu_out) mu_out[q] = y;
+        }
+        if (ka_out) ka_out[q] = ka[q];
     }
     const double tx = block_sum<NT>(sx, red);
     __syncthreads();

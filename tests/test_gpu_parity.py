@@ -440,6 +440,47 @@ def test_one_cycle_iterate_matches_oracle(precision):
         assert info.history[1] < 0.1 * info.history[0]
 
 
+@pytest.mark.parametrize("precision,energy", [(0, 1), (0, 0), (1, 1), (1, 0)])
+def test_mu_kappa_outputs_match_oracle(precision, energy):
+    """The optional mu and kappa outputs, written by the step's wrap-up from the
+    copy of the iterate that holds the result (with mixed precision either of
+    the two), equal the oracle's converged mu and kappa over three steps: the
+    first with a cold -1 norm solve, the later ones warm-started."""
+    N = 128
+    po, pg = both(2, h=math.pi / 4, dt=0.05)
+    phi = I.crystallites(N, N, math.pi / 4, radius_cells=N / 8, seed=4)
+    prev, psi = phi.copy(), np.zeros_like(phi)
+    st = api.Stepper(N, N, pg, tol=1e-10, precision=precision, energy=energy, max_cycles=60)
+    phi_d, prev_d, psi_d = dev(phi), dev(prev), dev(psi)
+    mu = torch.empty_like(psi_d)
+    ka = torch.empty_like(psi_d)
+    outer = set()
+    for _ in range(3):
+        mu.fill_(float("nan"))
+        ka.fill_(float("nan"))
+        nxt, info = st.step(phi_d, prev_d, psi_d, mu=mu, kappa=ka)
+        r = O.step(po, phi, prev, psi, guess=1, tol=1e-12, max_cycles=300, energy=False)
+        assert info.status == 0 and r.cycles >= 0
+        assert rel_l2(host(mu), r.mu) <= 1e-8
+        assert rel_l2(host(ka), r.kappa) <= 1e-8
+        outer.add(info.outer_iters)
+        prev, phi, psi = phi, r.phi, r.psi
+        prev_d, phi_d = phi_d, nxt
+    if precision == 1:
+        assert max(outer) >= 1
+
+
+def test_mu_kappa_outputs_must_not_alias():
+    _, pg = both(2, h=math.pi / 4, dt=0.05)
+    phi0 = dev(I.noise(32, 32, mean=0.1, amp=0.1, seed=82))
+    st = api.Stepper(32, 32, pg, energy=0)
+    psi = torch.zeros_like(phi0)
+    out = torch.empty_like(phi0)
+    for mu, ka in ((psi, None), (None, phi0), (out, None), (out2 := torch.empty_like(phi0), out2)):
+        with pytest.raises(L.MpfcError):
+            st.step(phi0, phi0, psi, phi_np1=out, mu=mu, kappa=ka)
+
+
 @pytest.mark.parametrize("shape", [0, 1, 2, 3])
 def test_tile_shape_invariance(shape, monkeypatch):
     """Every tile shape gives the same iterate after a fixed number of
