@@ -226,10 +226,13 @@ int pick_shape(int H) {
 }
 
 // Tuned choice from the measured times: the first shape (in table order)
-// within 5 % of the fastest, so that near-ties do not flip between runs.
+// within 5 % of the fastest, so that near-ties do not flip between runs.  The
+// window is taken on |best|, so the fastest shape always qualifies, also when
+// a time with the preceding launch's time subtracted comes out at or below 0.
 int pick_tuned(const float* t, float best, int H) {
     for (int k = 0; k < kNumShapes; ++k)
-        if (H <= kShapes[k].hmax && t[k] <= 1.05f * best) return k;
+        if (H <= kShapes[k].hmax && t[k] < 1e30f && t[k] <= best + 0.05f * std::fabs(best))
+            return k;
     return pick_shape(H);
 }
 
@@ -830,16 +833,19 @@ constexpr int kTuneReps = 8;
 template <class Fn, class Pre>
 int tune_one(mpfc_ctx* C, Level& lv, int kind, int H, Fn&& launch, Pre&& pre, bool has_pre) {
     float t[kNumShapes];
-    float best = 1e30f;
     for (int k = 0; k < kNumShapes; ++k) t[k] = 1e30f;
-    float t_pre = 0.f;
-    if (has_pre) {
-        int rc = time_in_graph(C->cap_stream, C->stream, kTuneReps, pre, t_pre);
-        if (rc) return rc;
-    }
-    // two interleaved rounds, each shape's faster one counts (the launches of
-    // the small levels take a few microseconds and vary from run to run)
-    for (int round = 0; round < 2; ++round)
+    float t_pre = has_pre ? 1e30f : 0.f;
+    // two interleaved rounds; each shape's faster one counts, and so does the
+    // faster of the two timings of `pre` (the launches of the small levels
+    // take a few microseconds, and a stall of the host between the timed
+    // graph launches only ever adds time)
+    for (int round = 0; round < 2; ++round) {
+        if (has_pre) {
+            float ms = 0.f;
+            int rc = time_in_graph(C->cap_stream, C->stream, kTuneReps, pre, ms);
+            if (rc) return rc;
+            t_pre = ms < t_pre ? ms : t_pre;
+        }
         for (int k = 0; k < kNumShapes; ++k) {
             if (H > kShapes[k].hmax || (C->gen && !gen_shape(k))) continue;
             lv.shape[kind] = k;
@@ -848,8 +854,13 @@ int tune_one(mpfc_ctx* C, Level& lv, int kind, int H, Fn&& launch, Pre&& pre, bo
                                              [&](hipStream_t s) { pre(s); launch(s); }, ms)
                              : time_in_graph(C->cap_stream, C->stream, kTuneReps, launch, ms);
             if (rc) return rc;
-            ms -= t_pre;
             t[k] = ms < t[k] ? ms : t[k];
+        }
+    }
+    float best = 1e30f;
+    for (int k = 0; k < kNumShapes; ++k)
+        if (t[k] < 1e30f) {
+            t[k] -= t_pre;
             best = t[k] < best ? t[k] : best;
         }
     lv.shape[kind] = pick_tuned(t, best, H);
