@@ -1382,13 +1382,15 @@ void enqueue_wrapup(mpfc_ctx* C, hipStream_t s, bool warm, int npoisson) {
                        1.0 / (F0.h * F0.h), C->acc + 8, F0.pf, warm ? F0.w[0] : nullptr, C->part,
                        (const double*)(C->pinned ? F0.pin : nullptr),
                        (const double*)(C->pinned ? C->phihat : nullptr));
-    hipLaunchKernelGGL((k_wrap_partials<NT>), dim3(1), dim3(NT), 0, s, C->st, C->part, (int)rb, 12,
-                       C->acc);
     // the warm start's residual is the first norm of the Poisson solve: it
     // may already meet the test, and the cycles behind it then exit at once
     if (warm)
-        hipLaunchKernelGGL((k_p_finalize<NT>), dim3(1), dim3(NT), 0, s, C->acc + 11, 1, C->pst,
-                           C->phist, C->acc + 10, kPoissonRel, kPoissonStall, kPoissonMax);
+        hipLaunchKernelGGL((k_wrap_partials_pnorm<NT>), dim3(1), dim3(NT), 0, s, C->st, C->part,
+                           (int)rb, C->acc, C->pst, C->phist, kPoissonRel, kPoissonStall,
+                           kPoissonMax);
+    else
+        hipLaunchKernelGGL((k_wrap_partials<NT>), dim3(1), dim3(NT), 0, s, C->st, C->part, (int)rb,
+                           12, C->acc);
     for (int k = 0; k < npoisson; ++k) vcycle_poisson(C, s);
     // A warm start with no cycle behind it keeps the sums above (the host runs
     // cycles and the sums again if it fails its test): nothing to enqueue.

@@ -27,8 +27,8 @@ __global__ void __launch_bounds__(256) k_fill(T* a, size_t n, T v) {
 // fixed stride, reading consecutive addresses with its neighbours; then
 // thread k adds the NT / nvals thread sums of value k in order.
 template <int NT>
-__device__ __forceinline__ void partials_sum_body(const double* __restrict__ part, int nparts,
-                                                  int nvals, double* out) {
+__device__ __forceinline__ double partials_sum_body(const double* __restrict__ part, int nparts,
+                                                    int nvals, double* out) {
     __shared__ double red[NT];
     const int t = threadIdx.x, per = NT / nvals;
     double s = 0.0;
@@ -48,11 +48,12 @@ __device__ __forceinline__ void partials_sum_body(const double* __restrict__ par
     }
     red[t] = s;
     __syncthreads();
+    double tot = 0.0;
     if (t < nvals) {
-        double tot = 0.0;
         for (int r = 0; r < per; ++r) tot += red[r * nvals + t];
         out[t] = tot;
     }
+    return tot;  // value t for threads t < nvals
 }
 
 template <int NT>
@@ -77,6 +78,26 @@ __global__ void __launch_bounds__(256) k_w_advance(double* w, const double* __re
     w[q] = a * w[q] - b * (mu[q] - mean);
 }
 
+// Norm bookkeeping of the Poisson cycles and the stop decision for one norm
+// (one thread): `tot` the squared residual sum, `bsq` = ||b||^2.
+__device__ inline void p_decide(CycleState* st, double* hist, double tot, double bsq, double rel,
+                                double stall, int max_norms) {
+    const double nr = sqrt(tot);
+    const double bn = sqrt(bsq);
+    const int k = st->count;
+    const double prev = k > 0 ? hist[k - 1] : 1e300;
+    hist[k] = nr;
+    st->acc = nr;
+    st->count = k + 1;
+    int status = ST_RUNNING;
+    if (!(nr == nr)) status = ST_NONFINITE;
+    else if (bn == 0.0 || nr <= rel * bn || (nr <= stall * bn && nr > 0.5 * prev))
+        status = ST_CONVERGED;
+    else if (k + 1 >= max_norms) status = ST_MAXCYC;
+    st->status = status;
+    st->done = status != ST_RUNNING;
+}
+
 // Norm bookkeeping of the Poisson cycles with the stop decision on the device:
 // converged when ||r|| <= rel ||b|| (||b||^2 = bsq[0]), or when the residual has
 // reached the operator's rounding floor (||r|| <= stall ||b|| and the last cycle
@@ -91,22 +112,7 @@ __global__ void __launch_bounds__(NT) k_p_finalize(const double* __restrict__ pa
     double s = 0.0;
     for (int b = threadIdx.x; b < nparts; b += NT) s += part[b];
     const double tot = block_sum<NT>(s, red);
-    if (threadIdx.x == 0) {
-        const double nr = sqrt(tot);
-        const double bn = sqrt(bsq[0]);
-        const int k = st->count;
-        const double prev = k > 0 ? hist[k - 1] : 1e300;
-        hist[k] = nr;
-        st->acc = nr;
-        st->count = k + 1;
-        int status = ST_RUNNING;
-        if (!(nr == nr)) status = ST_NONFINITE;
-        else if (bn == 0.0 || nr <= rel * bn || (nr <= stall * bn && nr > 0.5 * prev))
-            status = ST_CONVERGED;
-        else if (k + 1 >= max_norms) status = ST_MAXCYC;
-        st->status = status;
-        st->done = status != ST_RUNNING;
-    }
+    if (threadIdx.x == 0) p_decide(st, hist, tot, bsq[0], rel, stall, max_norms);
 }
 
 // Finest-grid Poisson residual sum of squares (b + Lap_h w)^2 for grids small

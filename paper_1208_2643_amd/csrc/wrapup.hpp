@@ -117,6 +117,26 @@ __global__ void __launch_bounds__(NT) k_wrap_partials(const CycleState* st,
     partials_sum_body<NT>(part, nparts, nvals, out);
 }
 
+// k_wrap_partials for the twelve sums of k_wrap_rhs_terms followed, for a
+// warm start, by the Poisson state's first norm and stop decision from the
+// warm start's residual sum (value 11) and ||b||^2 (value 10), as
+// k_p_finalize would take them from acc[11] and acc[10].
+template <int NT>
+__global__ void __launch_bounds__(NT) k_wrap_partials_pnorm(const CycleState* st,
+                                                            const double* __restrict__ part,
+                                                            int nparts, double* out,
+                                                            CycleState* pst, double* phist,
+                                                            double rel, double stall,
+                                                            int max_norms) {
+    if (wrapup_off(st)) return;
+    __shared__ double r[2];
+    const double v = partials_sum_body<NT>(part, nparts, 12, out);
+    if (threadIdx.x == 10) r[0] = v;
+    if (threadIdx.x == 11) r[1] = v;
+    __syncthreads();
+    if (threadIdx.x == 0 && !stopped(pst)) p_decide(pst, phist, r[1], r[0], rel, stall, max_norms);
+}
+
 // Cold start of the Poisson solution (first step of a context).
 __global__ void __launch_bounds__(256) k_wrap_w_zero(const CycleState* st, double* w,
                                                      size_t total) {
